@@ -1,0 +1,173 @@
+"""End-to-end pins of the oracle compressor (Method section, Algorithm 1):
+the per-point bound |x - x_hat| <= eps holds in FP64, special cases reduce to
+trivial streams, and the truncation search returns what an exhaustive
+evaluation of every truncation point gives."""
+import numpy as np
+import pytest
+
+from paper_2510_22265_amd import synth
+
+
+def _check(ref, x, eps_rel, **kw):
+    s = ref.compress(x, eps_rel, **kw)
+    y = ref.decompress(s, *x.shape)
+    rng_ = float(x.max()) - float(x.min())
+    err = np.abs(x.astype(np.float64) - y.astype(np.float64)).max()
+    assert err <= eps_rel * rng_, (err, eps_rel * rng_)
+    return s, y
+
+
+@pytest.mark.parametrize("var", ["t", "u", "v", "q"])
+@pytest.mark.parametrize("eps", [1e-3, 1e-2, 1e-1])
+def test_bound_holds_era5_like(ref, var, eps):
+    x = synth.field(var, 91, 180, cfg=1, level=3)
+    s, _ = _check(ref, x, eps)
+    assert len(s) < x.nbytes
+
+
+def test_plain_field_bound_and_ratio(ref):
+    x = synth.plain_field()
+    s, tr = ref.compress(x, 0.01, trace=True)
+    y = ref.decompress(s, *x.shape)
+    assert np.abs(x.astype(np.float64) - y).max() <= 0.01 * (float(x.max()) - float(x.min()))
+    assert tr["mode"] == 2
+    # the base section plus header meets the ratio r = 30
+    assert 48 + tr["base_bytes"] <= (4 * x.size) // 30
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 2), (3, 3), (5, 64), (33, 17), (64, 64), (100, 3)])
+def test_odd_shapes(ref, shape):
+    rng = np.random.default_rng(sum(shape))
+    x = (rng.standard_normal(shape) * 3 + 10).astype(np.float32)
+    if x.size == 1:
+        s = ref.compress(x, 0.01)
+        assert len(s) == 48
+        assert (ref.decompress(s, *shape) == x).all()
+        return
+    for eps in (0.002, 0.05):
+        _check(ref, x, eps)
+
+
+@pytest.mark.parametrize("cb", [(2, 2), (4, 6), (6, 6), (5, 3)])
+@pytest.mark.parametrize("tile", [1, 3])
+def test_params(ref, cb, tile):
+    x = synth.field("u", 61, 97, cfg=1, level=1)
+    _check(ref, x, 0.01, cbl2w=cb[0], cbl2h=cb[1], tile=tile, levels=4, base_ratio=12.0)
+
+
+def test_absolute_bound(ref):
+    x = synth.field("t", 45, 90, cfg=1)
+    s = ref.compress(x, 0.25, bound_mode=1)
+    y = ref.decompress(s, *x.shape)
+    assert np.abs(x.astype(np.float64) - y).max() <= 0.25
+
+
+def test_constant_field(ref):
+    x = np.full((37, 41), 273.15, np.float32)
+    s = ref.compress(x, 0.01)
+    assert len(s) == 48 and s[:4] == b"EBCC" and s[5] == 0
+    assert (ref.decompress(s, 37, 41) == x).all()
+
+
+def test_tiny_bound_gives_raw(ref):
+    x = synth.field("t", 20, 30)
+    s = ref.compress(x, 1e-13)
+    assert s[5] == 1 and len(s) == 48 + 4 * x.size
+    assert (ref.decompress(s, 20, 30) == x).all()
+
+
+def test_fp32_resolution_limit_gives_raw_or_exact(ref):
+    """A bound below what FP32 can represent near the data is met exactly
+    (raw) rather than violated."""
+    x = (1e4 + np.random.default_rng(1).standard_normal((24, 24))).astype(np.float32)
+    s = ref.compress(x, 2e-9)
+    y = ref.decompress(s, 24, 24)
+    assert np.abs(x.astype(np.float64) - y).max() <= 2e-9 * (float(x.max()) - float(x.min()))
+
+
+def test_error_paths(ref):
+    x = synth.field("v", 16, 16)
+    rc, _, _ = ref.compress_rc(np.array([[1.0, np.nan]], np.float32), 0.01)
+    assert rc == ref.EINVAL
+    rc, _, _ = ref.compress_rc(np.array([[1.0, np.inf]], np.float32), 0.01)
+    assert rc == ref.EINVAL
+    assert ref.compress_rc(x, 0.0)[0] == ref.EINVAL
+    assert ref.compress_rc(x, 0.01, base_ratio=0.5)[0] == ref.EINVAL
+    rc, _, need = ref.compress_rc(x, 0.01, cap=10)
+    assert rc == ref.ENOSPC and need > 10
+    rc, s, n = ref.compress_rc(x, 0.01, cap=need)
+    assert rc == 0 and n == need
+    s = ref.compress(x, 0.01)
+    bad = bytearray(s)
+    bad[60] ^= 0x10
+    assert ref.decompress_rc(bytes(bad), 16, 16) == ref.ECORRUPT
+    assert ref.decompress_rc(s[:-1], 16, 16) == ref.ECORRUPT
+    assert ref.decompress_rc(b"XBCC" + s[4:], 16, 16) == ref.ECORRUPT
+    assert ref.decompress_rc(s, 16, 17) == ref.EINVAL
+
+
+def test_deterministic(ref):
+    x = synth.field("q", 50, 70)
+    assert ref.compress(x, 0.003) == ref.compress(x, 0.003)
+
+
+def test_checksum_definition(ref):
+    b = bytes(range(1, 12))
+    w = np.frombuffer(b + b"\0", "<u4")
+    exp = int(sum(int(v) * (2 * k + 1) for k, v in enumerate(w)) % 2 ** 32)
+    assert ref.checksum(b) == exp
+
+
+def _feasible_all(ref, x, tr, eps, L, tile):
+    """Exhaustive: feasibility of every plane truncation of the residual."""
+    ny, nx = x.shape
+    cres, abase = tr["cres"], tr["abase"]
+    e_r = tr["e_r"]
+    sh = np.float32(2.0 ** (-e_r))
+    qr = np.minimum(np.abs(cres) * sh, np.float32(2 ** 23 - 1)).astype(np.uint32)
+    neg = (cres < 0).astype(np.uint8)
+    nmax = int(qr.max()).bit_length() - 1
+    assert nmax == tr["n_max"]
+    xmin = np.float32(x.min())
+    rng_f = np.float32(float(x.max()) - float(x.min()))
+    out = {}
+    for k in range(0, nmax + 2):
+        if k == 0:
+            r = np.zeros_like(abase)
+        else:
+            ns = nmax - k + 1
+            sec = ref.spiht_encode(qr, neg, L, tile, ns)
+            rc, m, ng = ref.spiht_decode(sec, ny, nx, L, tile, ns)
+            mag = np.where(m > 0, (2.0 * m.astype(np.float64) + 2.0 ** ns) * 2.0 ** (e_r - 1), 0).astype(np.float32)
+            r = ref.dwt(np.where(ng == 1, -mag, mag), L, inverse=True)
+        xh = xmin + (((abase + r) + np.float32(0.5)) * rng_f)
+        out[k] = bool(np.abs(x.astype(np.float64) - xh.astype(np.float64)).max() <= eps)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_plane_search_bruteforce_8x8(ref, seed):
+    """8x8 fields, 3 levels, random bounds: every truncation point is
+    evaluated; the stream's truncation equals the bisection over those
+    outcomes, it is feasible, and one plane fewer is not."""
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal((8, 8)) * rng.uniform(0.1, 10) + rng.uniform(-5, 5)).astype(np.float32)
+    eps_rel = float(10 ** rng.uniform(-3.5, -1))
+    s, tr = ref.compress(x, eps_rel, levels=3, tile=1, base_ratio=float(rng.uniform(2, 40)), trace=True)
+    eps = eps_rel * (float(x.max()) - float(x.min()))
+    y = ref.decompress(s, 8, 8)
+    assert np.abs(x.astype(np.float64) - y).max() <= eps
+    if tr["mode"] != 2 or tr["resid_bytes"] == 0:
+        return
+    feas = _feasible_all(ref, x, tr, eps, 3, 1)
+    K = tr["n_max"] + 1
+    assert not feas[0] and feas[K]
+    lo, hi = 0, K
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if feas[mid]:
+            hi = mid
+        else:
+            lo = mid
+    assert tr["n_s"] == tr["n_max"] - hi + 1
+    assert feas[hi] and not feas[hi - 1]

@@ -1,0 +1,148 @@
+"""Pins of the oracle's MQ coder (T.800 Annex C) and EBCOT tier-1 block
+coder (T.800 Annex D)."""
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "t800_contexts.txt")
+
+
+def _match(spec, val):
+    if spec in ("x", "-"):
+        return True
+    if spec.startswith(">="):
+        return val >= int(spec[2:])
+    return val == int(spec)
+
+
+def test_zc_table_matches_t800(ref):
+    rows = [l.split() for l in open(GOLDEN) if l.startswith("zc ")]
+    cls_of = {0: "LLLH", 2: "LLLH", 1: "HL", 3: "HH"}
+    for orient in range(4):
+        for h in range(3):
+            for v in range(3):
+                for d in range(5):
+                    got = ref.zc_ctx(orient, h, v, d)
+                    cl = cls_of[orient]
+                    hv = h + v
+                    exp = None
+                    for _, c, H, V, D, ctx in rows:
+                        if c != cl:
+                            continue
+                        hval = hv if cl == "HH" else h
+                        if _match(H, hval) and _match(V, v) and _match(D, d):
+                            exp = int(ctx)
+                            break
+                    assert got == exp, (orient, h, v, d)
+
+
+def test_sc_table_matches_t800(ref):
+    for line in open(GOLDEN):
+        if line.startswith("sc "):
+            _, hc, vc, ctx, xr = line.split()
+            assert ref.sc_ctx(int(hc), int(vc)) == (int(ctx), int(xr))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_mq_roundtrip(ref, seed):
+    rng = np.random.default_rng(seed)
+    n = 20000 if seed else 100000
+    cx = rng.integers(0, 19, n).astype(np.uint8)
+    p = rng.uniform(0.001, 0.999, 19)
+    bits = (rng.random(n) < p[cx]).astype(np.uint8)
+    s = ref.mq_encode(cx, bits)
+    assert (ref.mq_decode(s, cx) == bits).all()
+
+
+@pytest.mark.parametrize("p", [0.02, 0.1, 0.3, 0.5])
+def test_mq_rate_near_entropy(ref, p):
+    """A single adaptive context on iid Bernoulli(p) codes within a few
+    percent of the binary entropy."""
+    rng = np.random.default_rng(7)
+    n = 200000
+    bits = (rng.random(n) < p).astype(np.uint8)
+    cx = np.ones(n, np.uint8)               # context 1 starts at state 0
+    s = ref.mq_encode(cx, bits)
+    H = -(p * np.log2(p) + (1 - p) * np.log2(1 - p))
+    assert len(s) * 8 <= n * H * 1.06 + 64
+    assert len(s) * 8 >= n * H * 0.97
+
+
+def test_mq_uniform_context_costs_one_bit(ref):
+    rng = np.random.default_rng(8)
+    n = 80000
+    bits = rng.integers(0, 2, n).astype(np.uint8)
+    s = ref.mq_encode(np.full(n, 18, np.uint8), bits)
+    assert abs(len(s) * 8 - n) <= 0.01 * n + 32
+
+
+def _block(rng, h, w):
+    dens = rng.uniform(0.05, 1.0)
+    q = (rng.geometric(rng.uniform(0.05, 0.9), size=(h, w)) - 1) * (rng.random((h, w)) < dens)
+    if rng.random() < 0.3:
+        q = q << int(rng.integers(0, 12))
+    q = np.minimum(q, (1 << 23) - 1).astype(np.uint32)
+    neg = rng.integers(0, 2, size=(h, w)).astype(np.uint8)
+    return q, neg
+
+
+def _e2(q, m, pk):
+    q = q.astype(np.int64)
+    m = m.astype(np.int64)
+    e = np.where(m > 0, 2 * q + 1 - (2 * m + (np.int64(1) << pk.astype(np.int64))), 2 * q + 1)
+    return e * e
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_t1_block_properties(ref, seed):
+    rng = np.random.default_rng(100 + seed)
+    h, w = [(32, 32), (4, 4), (1, 1), (3, 17), (32, 7), (5, 32), (64, 64), (13, 9)][seed % 8]
+    orient = seed % 4
+    q, neg = _block(rng, h, w)
+    cw, R, D = ref.t1_encode(q, neg, orient)
+    P = int(q.max()).bit_length()
+    n = len(R) - 1
+    assert n == (3 * P - 2 if P else 0)
+    # all passes: lossless magnitudes and signs
+    m, ng, pk = ref.t1_decode(cw, h, w, orient, P, n)
+    assert (m == q).all() and ((ng == neg) | (q == 0)).all()
+    assert R[0] == 0 and D[0] == 0
+    ks = range(n + 1) if n <= 25 else sorted(set(rng.integers(0, n + 1, 12)) | {0, 1, n})
+    for k in ks:
+        cwk, _, _ = ref.t1_encode(q, neg, orient, keep=k)
+        assert len(cwk) == R[k]                    # flushed length = R_k
+        mk, ngk, pkk = ref.t1_decode(cwk, h, w, orient, P, k)
+        sig = mk > 0
+        sh = pkk.astype(np.uint32)
+        # known bits are q's bits at and above the lowest known plane
+        assert ((mk >> sh) == (q >> sh))[sig].all()
+        assert ((mk & ((np.uint32(1) << sh) - 1)) == 0)[sig].all()
+        # the bits known after k passes follow the pass order: plane p is
+        # fully known once its cleanup pass (index 3(P-1-p)) is kept
+        p_full = P - 1 - k // 3 if k % 3 == 1 else P - 1 - (k + 2) // 3 + 1 if k else P
+        if k and k % 3 == 1:
+            assert (mk == ((q >> np.uint32(p_full)) << np.uint32(p_full)) * (q >= (1 << p_full))).all()
+        # distortion bookkeeping: D_k = sum of error-square reductions
+        red = (_e2(q, np.zeros_like(q), pkk) - _e2(q, mk, pkk))[q > 0].sum()
+        assert red == D[k]
+        # prefix: the full codeword decoded for k passes agrees
+        mf, nf, pf = ref.t1_decode(cw, h, w, orient, P, k)
+        assert (mf == mk).all() and (pf[sig] == pkk[sig]).all()
+
+
+def test_t1_empty_block(ref):
+    q = np.zeros((32, 32), np.uint32)
+    cw, R, D = ref.t1_encode(q, np.zeros_like(q, dtype=np.uint8), 0)
+    assert cw == b"" and list(R) == [0] and list(D) == [0]
+
+
+def test_t1_single_coefficient(ref):
+    q = np.zeros((8, 8), np.uint32)
+    q[3, 5] = 1
+    neg = np.zeros((8, 8), np.uint8)
+    neg[3, 5] = 1
+    cw, R, D = ref.t1_encode(q, neg, 3)
+    assert len(R) == 2 and D[1] == 9 - 0   # e^2: (2*1+1)^2 -> (3 - 3)^2
+    m, ng, pk = ref.t1_decode(cw, 8, 8, 3, 1, 1)
+    assert m[3, 5] == 1 and ng[3, 5] == 1 and m.sum() == 1
