@@ -1,0 +1,126 @@
+/*
+ * ebcc.h — C ABI of the EBCC GPU library (libebcc.so, HIP for gfx950).
+ *
+ * EBCC is the two-layer error-bounded compressor of arXiv 2510.22265: a
+ * JPEG2000-style base layer (9/7 lifting DWT, dead-zone quantisation, EBCOT
+ * tier-1 with the MQ coder, rate allocation to a base compression ratio r)
+ * and a residual layer (DWT of input minus decoded base, SPIHT bit-plane
+ * coding truncated at the first plane where every point meets the bound).
+ * The operation is the problem statement of the paper's Algorithm 1 (EBCC
+ * Compression Process): input a 2-D array, a max error target eps and a base
+ * ratio; output a byte sequence that decodes with max|x - x_hat| <= eps.
+ * Fields are float32 only (Implementation Details) and 2-D after flattening
+ * (Method section, first paragraph).
+ *
+ * Conventions for every entry point:
+ *  - Pointers prefixed d_ are device pointers (HBM of the current HIP
+ *    device); h_ are host pointers.  The caller owns every buffer passed in.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it; entry points that return a size or a status read it back and
+ *    therefore synchronise that stream before returning.
+ *  - The library keeps per-device scratch workspaces and per-shape plans
+ *    between calls (grown on demand, freed by ebcc_release).  Calls on
+ *    different streams are safe to make from different host threads.
+ *  - Return values are ebcc_status codes (0 = success, negative = error);
+ *    ebcc_last_error() gives a human-readable detail for the calling thread.
+ *  - Output streams are byte-identical to the CPU oracle's for the same
+ *    input and parameters (the stream format is described with the design
+ *    notes of this repository).
+ */
+#ifndef EBCC_H
+#define EBCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EBCC_OK = 0,
+  EBCC_EINVAL = -1,    /* bad argument, non-finite input, dims mismatch */
+  EBCC_ENOSPC = -2,    /* output capacity too small; *out_len = size needed */
+  EBCC_ECORRUPT = -3,  /* stream fails magic/version/length/checksum checks */
+  EBCC_ENOMEM = -4,    /* device allocation failed */
+  EBCC_EHIP = -5,      /* a HIP runtime call failed (see ebcc_last_error) */
+  EBCC_ENOTIMPL = -6   /* a parameter value this build does not implement */
+} ebcc_status;
+
+enum { EBCC_BOUND_REL = 0, EBCC_BOUND_ABS = 1 };
+
+/* Stream modes (byte 5 of the 48-byte header). */
+enum { EBCC_MODE_CONST = 0, EBCC_MODE_RAW = 1, EBCC_MODE_CODED = 2 };
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(ebcc_params), for ABI versioning */
+  uint32_t bound_mode;    /* EBCC_BOUND_REL: err_bound is a fraction of (max - min)
+                             (range-relative, Benchmarks section); EBCC_BOUND_ABS: absolute */
+  double err_bound;       /* > 0 and finite */
+  double base_ratio;      /* r >= 1: header + base section <= floor(4 * ny * nx / r) bytes */
+  double q;               /* 0: fixed base ratio (implemented).  Other values select the
+                             q-quantile feedback search of Algorithm 1: EBCC_ENOTIMPL. */
+  uint32_t levels;        /* DWT levels (default 5), clamped to floor(log2(min(ny, nx))) */
+  uint32_t cblk_log2w;    /* code-block width  = 2^cblk_log2w, 2..6 (default 5) */
+  uint32_t cblk_log2h;    /* code-block height = 2^cblk_log2h, 2..6 (default 5); w*h <= 4096 */
+  uint32_t spiht_tile;    /* SPIHT tile side in coarsest-LL roots, 1..64 (default 2) */
+} ebcc_params;
+
+/* Fill p with the defaults: range-relative 1% bound, r = 30, 5 levels,
+ * 32x32 code-blocks, 2x2-root SPIHT tiles, q = 0. */
+void ebcc_params_default(ebcc_params* p);
+
+/* Largest stream ebcc_compress can produce for an ny x nx field (a coded
+ * stream never exceeds the raw one): 48 + 4 * ny * nx bytes. */
+size_t ebcc_compress_bound(size_t ny, size_t nx);
+
+/* Compress one float32 field.
+ *   d_x      [ny][nx] row-major float32, device.  1 <= ny, nx <= 2^24,
+ *            ny * nx < 2^31.  All values must be finite (else EBCC_EINVAL).
+ *   p        parameters (host); NULL = defaults.
+ *   d_out    device buffer of out_cap bytes receiving the stream.
+ *   out_len  host: stream length on success, or the size needed on ENOSPC.
+ * Synchronises `stream` (the truncation search reads back a few scalars and
+ * the final length). */
+int ebcc_compress(const float* d_x, size_t ny, size_t nx, const ebcc_params* p,
+                  uint8_t* d_out, size_t out_cap, size_t* out_len, void* stream);
+
+/* Decompress one stream (device bytes d_in[0..in_len)) into d_x [ny][nx]
+ * float32.  ny, nx must match the stream header (else EBCC_EINVAL).  Corrupt
+ * streams return EBCC_ECORRUPT (the output is then unspecified).
+ * Synchronises `stream`. */
+int ebcc_decompress(const uint8_t* d_in, size_t in_len, float* d_x, size_t ny, size_t nx,
+                    void* stream);
+
+/* Header fields of a stream, read from host memory (the first 48 bytes). */
+int ebcc_stream_info(const uint8_t* h_hdr, size_t len, size_t* ny, size_t* nx, int* mode);
+
+/* Free the calling process's cached plans and workspaces on the current
+ * device (the next call re-creates them). */
+void ebcc_release(void);
+
+const char* ebcc_status_str(int status);
+/* Detail of the last error raised on the calling host thread ("" if none). */
+const char* ebcc_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Stage trace (for stage-by-stage comparison with the CPU oracle).
+ * Runs ebcc_compress and copies intermediate device results into the given
+ * device buffers (any may be NULL):
+ *   d_coef  [ny*nx] f32  forward DWT of the normalised field
+ *   d_abase [ny*nx] f32  base-layer reconstruction (normalised domain)
+ *   d_cres  [ny*nx] f32  forward DWT of the residual
+ *   d_kb    [nblocks] u8 coding passes kept per code-block
+ *   d_pb    [nblocks] u8 magnitude bit-planes per code-block
+ *   h_info  [11] i32 (host): mode, levels, e0, e_r, n_max, n_s, nblocks,
+ *           ntiles, base_bytes, resid_bytes, feasibility checks
+ * ------------------------------------------------------------------------- */
+int ebcc_compress_trace(const float* d_x, size_t ny, size_t nx, const ebcc_params* p,
+                        uint8_t* d_out, size_t out_cap, size_t* out_len, void* stream,
+                        float* d_coef, float* d_abase, float* d_cres, uint8_t* d_kb,
+                        uint8_t* d_pb, int32_t* h_info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EBCC_H */

@@ -857,6 +857,15 @@ static void smax_build(const sgeom_t* g, const uint32_t* q, smax_t* s) {
 }
 static void smax_free(smax_t* s) { free(s->sub); free(s->maxD); free(s->maxL); }
 
+/* Number of coefficients in the tree rooted at n (n included). */
+static long tree_size(const sgeom_t* g, node_t n) {
+  node_t o[9];
+  int k = offspring(g, n, o);
+  long s = 1;
+  for (int c = 0; c < k; c++) s += tree_size(g, o[c]);
+  return s;
+}
+
 typedef struct { uint8_t* buf; long nbits, cap; } bitw_t;
 static void bw_put(bitw_t* w, int bit) {
   if ((w->nbits >> 3) >= w->cap) {
@@ -889,8 +898,9 @@ static void spiht_tile(const sgeom_t* g, long ty, long tx, int n_top, int n_bot,
   long i0 = ty * g->T, j0 = tx * g->T;
   long i1 = i0 + g->T < g->hL ? i0 + g->T : g->hL, j1 = j0 + g->T < g->wL ? j0 + g->T : g->wL;
   /* capacity: every coefficient of the tile's trees */
-  long ncoef = (i1 - i0) * (j1 - j0) << (2 * g->L);
-  ncoef += 64;
+  long ncoef = 0;
+  for (long i = i0; i < i1; i++)
+    for (long j = j0; j < j1; j++) ncoef += tree_size(g, (node_t){0, i, j});
   lip_t* lip = (lip_t*)malloc(sizeof(lip_t) * (size_t)ncoef);
   lis_t* lis = (lis_t*)malloc(sizeof(lis_t) * (size_t)ncoef * 2);
   node_t* lsp = (node_t*)malloc(sizeof(node_t) * (size_t)ncoef);
@@ -1202,7 +1212,7 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
   if (out_len) *out_len = 0;
   if (ny < 1 || nx < 1 || ny > (1L << 24) || nx > (1L << 24) || ny * nx > (1L << 31) - 1) return REF_EINVAL;
   if (!(err_bound > 0) || !isfinite(err_bound) || !(base_ratio >= 1.0) || !isfinite(base_ratio)) return REF_EINVAL;
-  if (levels < 0 || levels > MAX_LEVELS || cbl2w < 2 || cbl2h < 2 || cbl2w + cbl2h > 12 || tile < 1 || tile > 64)
+  if (levels < 0 || levels > MAX_LEVELS || cbl2w < 2 || cbl2h < 2 || cbl2w > 6 || cbl2h > 6 || tile < 1 || tile > 64)
     return REF_EINVAL;
   long N = ny * nx;
   float xmin = x[0], xmax = x[0];
@@ -1211,6 +1221,8 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
     if (x[i] < xmin) xmin = x[i];
     if (x[i] > xmax) xmax = x[i];
   }
+  if (xmin == 0.0f) xmin = 0.0f;                          /* +0 for a zero extreme */
+  if (xmax == 0.0f) xmax = 0.0f;
   double range_d = (double)xmax - (double)xmin;
   double eps = bound_mode == 0 ? err_bound * range_d : err_bound;
   int cbl = cbl2w | (cbl2h << 4);
@@ -1415,7 +1427,7 @@ EXPORT int ebcc_ref_decompress(const uint8_t* in, size_t len, float* x, size_t n
   if (mode == MODE_RAW) { if (bb != 4 * (uint32_t)N) return REF_ECORRUPT; memcpy(x, in + HDR_BYTES, 4 * (size_t)N); return REF_OK; }
   int L = in[6], cbl2w = in[7] & 15, cbl2h = in[7] >> 4, T = (int)get_u16(in + 32);
   int e0 = (int8_t)in[28], er = (int8_t)in[29], ns = (int8_t)in[31];
-  if (L != levels_eff(ny, nx, L) || cbl2w < 2 || cbl2h < 2 || cbl2w + cbl2h > 12 || T < 1) return REF_ECORRUPT;
+  if (L != levels_eff(ny, nx, L) || cbl2w < 2 || cbl2h < 2 || cbl2w > 6 || cbl2h > 6 || T < 1) return REF_ECORRUPT;
   layout_t ly; layout_init(&ly, ny, nx, L, cbl2w, cbl2h, T);
   int rc = REF_OK;
   const uint8_t* p = in + HDR_BYTES;

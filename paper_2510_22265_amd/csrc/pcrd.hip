@@ -1,0 +1,130 @@
+// Rate allocation of the base layer: post-compression rate-distortion
+// optimisation (PCRD, Taubman 2000) meeting the base compression ratio r of
+// the paper's enc_base(A, r, eps) (Algorithm 1).
+//
+// One workgroup per field:
+//  1. one thread per code-block builds the upper convex hull of its
+//     (R_k, D_k) pass points (strictly decreasing slopes; passes that do not
+//     add distortion reduction or whose length exceeds 65535 are skipped);
+//  2. the segments are ordered by the composite key (slope descending,
+//     block ascending, segment ascending); segments are accepted in that
+//     order until the first one that would overflow the byte budget.  The
+//     first non-fitting segment is found by a radix select over the 104-bit
+//     key (8-bit digits, LDS histograms of segment lengths), so no sort is
+//     materialised;
+//  3. one thread per block keeps the segments whose key is above the
+//     threshold and writes k_b and the codeword length R_{k_b}.
+#include "common.h"
+
+namespace ebcc {
+
+constexpr int kPcrdThreads = 1024;
+
+__device__ __forceinline__ double seg_slope(int64_t dD, int64_t dR) {
+  return dR <= 0 ? __longlong_as_double(0x7ff0000000000000ll) : (double)dD / (double)dR;
+}
+
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ u128 seg_key(uint64_t slope_bits, int b, int j) {
+  return ((u128)slope_bits << 40) | ((u128)(0xFFFFFFFFu - (uint32_t)b) << 8) | (u128)(0xFFu - (uint32_t)j);
+}
+
+__global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const uint8_t* __restrict__ pb, const int32_t* __restrict__ R,
+                                                       const int64_t* __restrict__ D, int nblk, int64_t budget,
+                                                       uint8_t* __restrict__ kb, uint8_t* __restrict__ hk,
+                                                       uint64_t* __restrict__ keys, int32_t* __restrict__ dr,
+                                                       uint8_t* __restrict__ nhv, int32_t* __restrict__ len_out) {
+  __shared__ unsigned long long hist[256];
+  __shared__ int s_choice;
+  __shared__ int s_allfit;
+  __shared__ unsigned long long s_acc;
+  int tid = threadIdx.x;
+  // 1. hulls
+  for (int b = tid; b < nblk; b += kPcrdThreads) {
+    int P = pb[b];
+    int n = P ? 3 * P - 2 : 0;
+    const int32_t* r = R + (size_t)b * kPassStride;
+    const int64_t* d = D + (size_t)b * kPassStride;
+    uint8_t* h = hk + (size_t)b * kPassStride;
+    int nh = 0;
+    h[nh++] = 0;
+    for (int k = 1; k <= n; k++) {
+      int32_t rk = r[k];
+      if (rk > kSegRMax) continue;
+      int64_t dk = d[k];
+      if (dk <= d[h[nh - 1]]) continue;
+      while (nh >= 2) {
+        int a = h[nh - 2], c = h[nh - 1];
+        double sac = seg_slope(d[c] - d[a], (int64_t)r[c] - r[a]);
+        double sck = seg_slope(dk - d[c], (int64_t)rk - r[c]);
+        if (sck >= sac) nh--; else break;
+      }
+      h[nh++] = (uint8_t)k;
+    }
+    nhv[b] = (uint8_t)nh;
+    for (int j = 1; j < nh; j++) {
+      int a = h[j - 1], c = h[j];
+      keys[(size_t)b * kPassStride + j] = (uint64_t)__double_as_longlong(seg_slope(d[c] - d[a], (int64_t)r[c] - r[a]));
+      dr[(size_t)b * kPassStride + j] = r[c] - r[a];
+    }
+  }
+  __syncthreads();
+  // 2. radix select of the first segment that does not fit
+  u128 prefix = 0;
+  unsigned long long acc = 0;
+  bool allfit = false;
+  for (int dgt = 0; dgt < 13; dgt++) {
+    for (int i = tid; i < 256; i += kPcrdThreads) hist[i] = 0;
+    __syncthreads();
+    int sh = 104 - 8 * (dgt + 1);
+    for (int b = tid; b < nblk; b += kPcrdThreads) {
+      int nh = nhv[b];
+      for (int j = 1; j < nh; j++) {
+        u128 key = seg_key(keys[(size_t)b * kPassStride + j], b, j);
+        if (dgt > 0 && (key >> (sh + 8)) != prefix) continue;
+        int dg = (int)((key >> sh) & 0xFF);
+        atomicAdd(&hist[dg], (unsigned long long)dr[(size_t)b * kPassStride + j]);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int choice = -1;
+      unsigned long long a = acc;
+      for (int t = 255; t >= 0; t--) {
+        if (a + hist[t] > (unsigned long long)budget) { choice = t; break; }
+        a += hist[t];
+      }
+      s_choice = choice;
+      s_acc = a;
+      s_allfit = choice < 0;
+    }
+    __syncthreads();
+    if (s_allfit) { allfit = true; break; }
+    prefix = (prefix << 8) | (u128)s_choice;
+    acc = s_acc;
+    __syncthreads();
+  }
+  // 3. kept passes per block: every segment with key above the threshold
+  for (int b = tid; b < nblk; b += kPcrdThreads) {
+    int nh = nhv[b];
+    int k = 0;
+    for (int j = 1; j < nh; j++) {
+      u128 key = seg_key(keys[(size_t)b * kPassStride + j], b, j);
+      if (allfit || key > prefix) k = hk[(size_t)b * kPassStride + j];
+      else break;
+    }
+    kb[b] = (uint8_t)k;
+    len_out[b] = k ? R[(size_t)b * kPassStride + k] : 0;
+  }
+}
+
+void pcrd(const uint8_t* pb, const int32_t* R, const int64_t* D, int nblk, int64_t budget, uint8_t* kb,
+          uint8_t* hk_scratch, uint64_t* key_scratch, int32_t* dr_scratch, uint8_t* nh_scratch, int32_t* len_out,
+          hipStream_t st) {
+  if (nblk <= 0) return;
+  k_pcrd<<<1, kPcrdThreads, 0, st>>>(pb, R, D, nblk, budget < 0 ? 0 : budget, kb, hk_scratch, key_scratch,
+                                     dr_scratch, nh_scratch, len_out);
+}
+
+}  // namespace ebcc

@@ -1,0 +1,331 @@
+// Residual layer of EBCC: SPIHT bit-plane coding (Said & Pearlman 1996, as
+// cited in the paper's Method section) of the quantised wavelet coefficients
+// of the residual, coded independently per tile of coarsest-LL roots.
+//
+// Spatial-orientation trees: an LL root has the three co-located
+// coefficients of the coarsest HL, LH and HH bands as offspring; a detail
+// coefficient (i, j) at level l >= 2 has the 2x2 group (2i.., 2j..) of its
+// orientation one level finer, and when the finer band has one more row
+// (column) than twice the coarser band, the parents of the last row (column)
+// also take that row (column); level-1 coefficients are leaves.
+//
+//  * k_maxima: per band, coarse-to-fine dependency order reversed (level 2
+//    first), one thread per node: the maximum magnitude over the node's
+//    descendants (maxD), over its grand-descendants and below (maxL), and
+//    over its subtree including itself (sub).
+//  * k_spiht_encode / k_spiht_decode: one lane per tile; the three lists
+//    (LIP, LSP, LIS) are FIFO arrays in the tile's slice of a global scratch
+//    (removal = clearing an "alive" bit), bits are packed MSB-first.
+#include "common.h"
+
+namespace ebcc {
+
+// List entry: j | i << 24 | band << 48 | typeB << 56 | alive << 57.
+__device__ __forceinline__ uint64_t mk_node(int band, int i, int j) {
+  return (uint64_t)(uint32_t)j | ((uint64_t)(uint32_t)i << 24) | ((uint64_t)band << 48);
+}
+__device__ __forceinline__ int nd_j(uint64_t n) { return (int)(n & 0xFFFFFF); }
+__device__ __forceinline__ int nd_i(uint64_t n) { return (int)((n >> 24) & 0xFFFFFF); }
+__device__ __forceinline__ int nd_band(uint64_t n) { return (int)((n >> 48) & 0xFF); }
+constexpr uint64_t kTypeB = 1ull << 56, kAlive = 1ull << 57;
+
+__device__ __forceinline__ int nd_pos(const Band* B, int nx, uint64_t n) {
+  const Band& b = B[nd_band(n)];
+  return (b.y0 + nd_i(n)) * nx + b.x0 + nd_j(n);
+}
+
+// Offspring of (band, i, j) in row-major order; returns the count (<= 9).
+__device__ __forceinline__ int offspring(const Band* B, int L, int band, int i, int j, uint64_t* o) {
+  int k = 0;
+  if (band == 0) {
+    if (L == 0) return 0;
+    for (int c = 1; c <= 3; c++)
+      if (i < B[c].h && j < B[c].w) o[k++] = mk_node(c, i, j);
+    return k;
+  }
+  const Band& pb = B[band];
+  if (pb.level == 1) return 0;
+  int cb = band + 3;
+  const Band& ch = B[cb];
+  int r1 = (i == pb.h - 1) ? ch.h : 2 * i + 2;
+  int c1 = (j == pb.w - 1) ? ch.w : 2 * j + 2;
+  if (r1 > ch.h) r1 = ch.h;
+  if (c1 > ch.w) c1 = ch.w;
+  for (int r = 2 * i; r < r1; r++)
+    for (int c = 2 * j; c < c1; c++) o[k++] = mk_node(cb, r, c);
+  return k;
+}
+// Level of a node's offspring (roots: the coarsest detail level).
+__device__ __forceinline__ int child_level(const Band* B, int L, int band) { return band == 0 ? L : B[band].level - 1; }
+
+__global__ __launch_bounds__(256) void k_maxima(const uint32_t* __restrict__ qr, int nx, const Band* __restrict__ bands,
+                                                int L, int band, uint32_t* __restrict__ sub, uint32_t* __restrict__ maxd,
+                                                uint32_t* __restrict__ maxl) {
+  const Band& bd = bands[band];
+  int n = bd.h * bd.w;
+  int cl = child_level(bands, L, band);
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < n; t += gridDim.x * 256) {
+    int i = t / bd.w, j = t - i * bd.w;
+    uint64_t o[9];
+    int no = offspring(bands, L, band, i, j, o);
+    uint32_t md = 0, ml = 0;
+    for (int c = 0; c < no; c++) {
+      int pc = nd_pos(bands, nx, o[c]);
+      uint32_t s, d;
+      if (cl == 1) { s = qr[pc] & 0x7FFFFFu; d = 0; }
+      else { s = sub[pc]; d = maxd[pc]; }
+      md = s > md ? s : md;
+      ml = d > ml ? d : ml;
+    }
+    int p = (bd.y0 + i) * nx + bd.x0 + j;
+    uint32_t self = qr[p] & 0x7FFFFFu;
+    sub[p] = self > md ? self : md;
+    maxd[p] = md;
+    maxl[p] = ml;
+  }
+}
+
+void spiht_maxima(const uint32_t* qr, int nx, const Band* bands_dev, const Band* bands_host, int nb, int L,
+                  uint32_t* sub, uint32_t* maxd, uint32_t* maxl, hipStream_t st) {
+  // finer parents first: levels 2 .. L, then the LL roots
+  for (int l = 2; l <= L; l++)
+    for (int o = 0; o < 3; o++) {
+      int band = 1 + 3 * (L - l) + o;
+      int n = bands_host[band].h * bands_host[band].w;
+      int g = (n + 255) / 256;
+      if (g > 2048) g = 2048;
+      if (n > 0) k_maxima<<<g, 256, 0, st>>>(qr, nx, bands_dev, L, band, sub, maxd, maxl);
+    }
+  int n = bands_host[0].h * bands_host[0].w;
+  int g = (n + 255) / 256;
+  if (g > 2048) g = 2048;
+  k_maxima<<<g, 256, 0, st>>>(qr, nx, bands_dev, L, 0, sub, maxd, maxl);
+}
+
+struct BitW {
+  uint8_t* out;
+  int64_t pos, cap;
+  uint32_t acc;
+  int n;
+  __device__ void put(int b) {
+    acc = (acc << 1) | (uint32_t)b;
+    if (++n == 8) {
+      if (pos < cap) out[pos] = (uint8_t)acc;
+      pos++;
+      acc = 0; n = 0;
+    }
+  }
+  __device__ void flush() {
+    if (n) {
+      if (pos < cap) out[pos] = (uint8_t)(acc << (8 - n));
+      pos++;
+      acc = 0; n = 0;
+    }
+  }
+};
+
+__global__ __launch_bounds__(64) void k_spiht_encode(const uint32_t* __restrict__ qr, const uint32_t* __restrict__ sub,
+                                                     const uint32_t* __restrict__ maxd, const uint32_t* __restrict__ maxl,
+                                                     int nx, const Band* __restrict__ bands_g, int nb, int L,
+                                                     const TileD* __restrict__ tiles, int ntiles, int n_s,
+                                                     uint64_t* __restrict__ lists, uint8_t* __restrict__ slots,
+                                                     const int64_t* __restrict__ slot_off, uint32_t* __restrict__ tlen,
+                                                     uint32_t* __restrict__ tent) {
+  __shared__ Band B[kMaxBands];
+  for (int i = threadIdx.x; i < nb; i += 64) B[i] = bands_g[i];
+  __syncthreads();
+  int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= ntiles) return;
+  TileD td = tiles[t];
+  uint32_t mx = 0;
+  for (int i = td.i0; i < td.i1; i++)
+    for (int j = td.j0; j < td.j1; j++) {
+      uint32_t s = sub[i * nx + j];
+      mx = s > mx ? s : mx;
+    }
+  int ntop = mx ? 31 - __builtin_clz(mx) : -1;
+  if (ntop < n_s) { tlen[t] = 0; tent[t] = 0; return; }
+  int nc = td.ncoef;
+  uint64_t* lip = lists + 4 * td.off;
+  uint64_t* lsp = lip + nc;
+  uint64_t* lis = lsp + nc;
+  int nlip = 0, nlsp = 0, nlis = 0;
+  uint64_t o[9];
+  for (int i = td.i0; i < td.i1; i++)
+    for (int j = td.j0; j < td.j1; j++) {
+      uint64_t n = mk_node(0, i, j);
+      lip[nlip++] = n | kAlive;
+      if (offspring(B, L, 0, i, j, o) > 0) lis[nlis++] = n | kAlive;
+    }
+  int64_t so = slot_off[t];
+  BitW w{slots + so, 0, slot_off[t + 1] - so, 0u, 0};
+  for (int pl = ntop; pl >= n_s; pl--) {
+    uint32_t thr = 1u << pl;
+    int lsp_prev = nlsp;
+    for (int k = 0; k < nlip; k++) {
+      uint64_t e = lip[k];
+      if (!(e & kAlive)) continue;
+      uint32_t v = qr[nd_pos(B, nx, e)];
+      int s = (v & 0x7FFFFFu) >= thr;
+      w.put(s);
+      if (s) {
+        w.put((int)(v >> 31));
+        lsp[nlsp++] = e & ~kAlive;
+        lip[k] = e & ~kAlive;
+      }
+    }
+    for (int k = 0; k < nlis; k++) {
+      uint64_t e = lis[k];
+      if (!(e & kAlive)) continue;
+      int band = nd_band(e), i = nd_i(e), j = nd_j(e);
+      int p = nd_pos(B, nx, e);
+      int no = offspring(B, L, band, i, j, o);
+      if (!(e & kTypeB)) {
+        int s = maxd[p] >= thr;
+        w.put(s);
+        if (!s) continue;
+        for (int c = 0; c < no; c++) {
+          uint32_t v = qr[nd_pos(B, nx, o[c])];
+          int sc = (v & 0x7FFFFFu) >= thr;
+          w.put(sc);
+          if (sc) {
+            w.put((int)(v >> 31));
+            lsp[nlsp++] = o[c];
+          } else {
+            lip[nlip++] = o[c] | kAlive;
+          }
+        }
+        lis[k] = e & ~kAlive;
+        if (no > 0 && child_level(B, L, band) >= 2) lis[nlis++] = (e & ~kAlive) | kTypeB | kAlive;
+      } else {
+        int s = maxl[p] >= thr;
+        w.put(s);
+        if (!s) continue;
+        for (int c = 0; c < no; c++) lis[nlis++] = o[c] | kAlive;
+        lis[k] = e & ~kAlive;
+      }
+    }
+    for (int k = 0; k < lsp_prev; k++) {
+      uint32_t v = qr[nd_pos(B, nx, lsp[k])];
+      w.put((int)((v >> pl) & 1u));
+    }
+  }
+  w.flush();
+  tlen[t] = (uint32_t)w.pos;
+  tent[t] = (uint32_t)w.pos | ((uint32_t)(ntop + 1) << 26);
+}
+
+void spiht_encode(const uint32_t* qr, const uint32_t* sub, const uint32_t* maxd, const uint32_t* maxl, int nx,
+                  const Band* bands, int nb, int L, const TileD* tiles, int ntiles, int n_s, uint64_t* lists,
+                  uint8_t* slots, const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st) {
+  if (ntiles <= 0) return;
+  k_spiht_encode<<<(ntiles + 63) / 64, 64, 0, st>>>(qr, sub, maxd, maxl, nx, bands, nb, L, tiles, ntiles, n_s,
+                                                    lists, slots, slot_off, tlen, tent);
+}
+
+struct BitR {
+  const uint8_t* in;
+  int64_t len, pos;
+  __device__ int get() {
+    int64_t by = pos >> 3;
+    int b = (by < len) ? (in[by] >> (7 - (pos & 7))) & 1 : 0;
+    pos++;
+    return b;
+  }
+};
+
+// sec: residual section (tile table then payloads); toff[t]: offset of tile
+// t's payload after the table.  mags: N-sized scratch (magnitude | sign << 31).
+__global__ __launch_bounds__(64) void k_spiht_decode(const uint8_t* __restrict__ sec, int64_t sec_len,
+                                                     const int64_t* __restrict__ toff, int nx,
+                                                     const Band* __restrict__ bands_g, int nb, int L,
+                                                     const TileD* __restrict__ tiles, int ntiles, int n_s, int e_r,
+                                                     uint64_t* __restrict__ lists, uint32_t* __restrict__ mags,
+                                                     float* __restrict__ chat, int* __restrict__ flag) {
+  __shared__ Band B[kMaxBands];
+  for (int i = threadIdx.x; i < nb; i += 64) B[i] = bands_g[i];
+  __syncthreads();
+  int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= ntiles) return;
+  TileD td = tiles[t];
+  uint32_t ent = (uint32_t)sec[4 * t] | ((uint32_t)sec[4 * t + 1] << 8) | ((uint32_t)sec[4 * t + 2] << 16) |
+                 ((uint32_t)sec[4 * t + 3] << 24);
+  int64_t len = ent & 0x3FFFFFF;
+  int ntop = (int)(ent >> 26) - 1;
+  int64_t pbase = 4 * (int64_t)ntiles;      // payloads follow the tile table
+  int64_t o0 = toff[t];
+  if (o0 < 0 || pbase + o0 + len > sec_len || (ntop >= kQBits)) { atomicOr(flag, 1); return; }
+  if (ntop < n_s) return;
+  int nc = td.ncoef;
+  uint64_t* lip = lists + 4 * td.off;
+  uint64_t* lsp = lip + nc;
+  uint64_t* lis = lsp + nc;
+  int nlip = 0, nlsp = 0, nlis = 0;
+  uint64_t o[9];
+  for (int i = td.i0; i < td.i1; i++)
+    for (int j = td.j0; j < td.j1; j++) {
+      uint64_t n = mk_node(0, i, j);
+      lip[nlip++] = n | kAlive;
+      if (offspring(B, L, 0, i, j, o) > 0) lis[nlis++] = n | kAlive;
+    }
+  BitR r{sec + pbase + o0, len, 0};
+  for (int pl = ntop; pl >= n_s; pl--) {
+    uint32_t thr = 1u << pl;
+    int lsp_prev = nlsp;
+    for (int k = 0; k < nlip; k++) {
+      uint64_t e = lip[k];
+      if (!(e & kAlive)) continue;
+      if (r.get()) {
+        int sg = r.get();
+        mags[nd_pos(B, nx, e)] = thr | ((uint32_t)sg << 31);
+        lsp[nlsp++] = e & ~kAlive;
+        lip[k] = e & ~kAlive;
+      }
+    }
+    for (int k = 0; k < nlis; k++) {
+      uint64_t e = lis[k];
+      if (!(e & kAlive)) continue;
+      int band = nd_band(e), i = nd_i(e), j = nd_j(e);
+      int no = offspring(B, L, band, i, j, o);
+      if (!(e & kTypeB)) {
+        if (!r.get()) continue;
+        for (int c = 0; c < no; c++) {
+          if (r.get()) {
+            int sg = r.get();
+            mags[nd_pos(B, nx, o[c])] = thr | ((uint32_t)sg << 31);
+            lsp[nlsp++] = o[c];
+          } else {
+            lip[nlip++] = o[c] | kAlive;
+          }
+        }
+        lis[k] = e & ~kAlive;
+        if (no > 0 && child_level(B, L, band) >= 2) lis[nlis++] = (e & ~kAlive) | kTypeB | kAlive;
+      } else {
+        if (!r.get()) continue;
+        for (int c = 0; c < no; c++) lis[nlis++] = o[c] | kAlive;
+        lis[k] = e & ~kAlive;
+      }
+    }
+    for (int k = 0; k < lsp_prev; k++) {
+      int p = nd_pos(B, nx, lsp[k]);
+      if (r.get()) mags[p] |= thr;
+    }
+  }
+  for (int k = 0; k < nlsp; k++) {
+    int p = nd_pos(B, nx, lsp[k]);
+    uint32_t v = mags[p];
+    uint32_t m = v & 0x7FFFFFu;
+    float f = ldexpf((float)(2u * m + (1u << n_s)), e_r - 1);
+    chat[p] = (v >> 31) ? -f : f;
+  }
+}
+
+void spiht_decode(const uint8_t* sec, int64_t sec_len, const int64_t* toff, int nx, const Band* bands, int nb, int L,
+                  const TileD* tiles, int ntiles, int n_s, int e_r, uint64_t* lists, uint32_t* mags, float* chat,
+                  int* flag, hipStream_t st) {
+  if (ntiles <= 0) return;
+  k_spiht_decode<<<(ntiles + 63) / 64, 64, 0, st>>>(sec, sec_len, toff, nx, bands, nb, L, tiles, ntiles, n_s, e_r,
+                                                    lists, mags, chat, flag);
+}
+
+}  // namespace ebcc

@@ -1,0 +1,746 @@
+// Base layer of EBCC: dead-zone quantisation, EBCOT tier-1 coding passes and
+// the MQ arithmetic coder (JPEG2000 Part 1, Annexes C and D, default mode
+// switches), as used by the paper's JPEG2000 base compression layer.
+//
+// Layout of the work:
+//  * k_quant_planes: one wavefront per code-block.  Quantises the block and
+//    builds, with ballots, one bit mask per (bit-plane, row) and per row of
+//    signs, plus the block's number of magnitude planes P_b.
+//  * k_t1_encode: one lane per code-block.  Coding-pass state (significance,
+//    visited-in-this-plane, refined, sign, current plane's magnitudes) is kept
+//    as one bit mask per block row in LDS, so the scan jumps from candidate
+//    column to candidate column instead of visiting every sample.  The MQ
+//    coder's registers live in VGPRs, its 19 context states in LDS.  At every
+//    pass end the coder is flushed on a copy to obtain the exact terminated
+//    length R_k and the bytes termination would write.
+//  * k_virtual_decode: one wavefront per block, lanes over samples.  Gives the
+//    base reconstruction for the kept passes in closed form (what the decoder
+//    recovers), from q, P_b, k_b and a per-sample "became significant in a
+//    significance-propagation pass" bit recorded by the encoder.
+//  * k_t1_decode: one lane per block; the decoder for decompression.
+#include "common.h"
+
+namespace ebcc {
+
+// MQ probability-estimation table (T.800 Table C.2), packed as
+// Qe | NMPS << 16 | NLPS << 22 | SWITCH << 28.
+#define MQE(q, nm, nl, sw) ((uint32_t)(q) | ((uint32_t)(nm) << 16) | ((uint32_t)(nl) << 22) | ((uint32_t)(sw) << 28))
+__constant__ uint32_t c_mqt[47] = {
+    MQE(0x5601, 1, 1, 1),   MQE(0x3401, 2, 6, 0),   MQE(0x1801, 3, 9, 0),   MQE(0x0AC1, 4, 12, 0),
+    MQE(0x0521, 5, 29, 0),  MQE(0x0221, 38, 33, 0), MQE(0x5601, 7, 6, 1),   MQE(0x5401, 8, 14, 0),
+    MQE(0x4801, 9, 14, 0),  MQE(0x3801, 10, 14, 0), MQE(0x3001, 11, 17, 0), MQE(0x2401, 12, 18, 0),
+    MQE(0x1C01, 13, 20, 0), MQE(0x1601, 29, 21, 0), MQE(0x5601, 15, 14, 1), MQE(0x5401, 16, 14, 0),
+    MQE(0x5101, 17, 15, 0), MQE(0x4801, 18, 16, 0), MQE(0x3801, 19, 17, 0), MQE(0x3401, 20, 18, 0),
+    MQE(0x3001, 21, 19, 0), MQE(0x2801, 22, 19, 0), MQE(0x2401, 23, 20, 0), MQE(0x2201, 24, 21, 0),
+    MQE(0x1C01, 25, 22, 0), MQE(0x1801, 26, 23, 0), MQE(0x1601, 27, 24, 0), MQE(0x1401, 28, 25, 0),
+    MQE(0x1201, 29, 26, 0), MQE(0x1101, 30, 27, 0), MQE(0x0AC1, 31, 28, 0), MQE(0x09C1, 32, 29, 0),
+    MQE(0x08A1, 33, 30, 0), MQE(0x0521, 34, 31, 0), MQE(0x0441, 35, 32, 0), MQE(0x02A1, 36, 33, 0),
+    MQE(0x0221, 37, 34, 0), MQE(0x0141, 38, 35, 0), MQE(0x0111, 39, 36, 0), MQE(0x0085, 40, 37, 0),
+    MQE(0x0049, 41, 38, 0), MQE(0x0025, 42, 39, 0), MQE(0x0015, 43, 40, 0), MQE(0x0009, 44, 41, 0),
+    MQE(0x0005, 45, 42, 0), MQE(0x0001, 45, 43, 0), MQE(0x5601, 46, 46, 0)};
+#undef MQE
+
+constexpr int kNCtx = 19;
+constexpr int CX_RL = 17, CX_UNI = 18, CX_MR = 14, CX_SC = 9;
+
+// Zero-coding context label from neighbour significance counts (T.800 D.1).
+__device__ __forceinline__ int zc_ctx(int o, int h, int v, int d) {
+  if (o == ORI_HH) {
+    int hv = h + v;
+    if (d >= 3) return 8;
+    if (d == 2) return hv ? 7 : 6;
+    if (d == 1) return hv >= 2 ? 5 : (hv ? 4 : 3);
+    return hv >= 2 ? 2 : hv;
+  }
+  if (o == ORI_HL) { int t = h; h = v; v = t; }
+  if (h == 2) return 8;
+  if (h == 1) return v ? 7 : (d ? 6 : 5);
+  if (v) return 2 + v;                 // v = 2 -> 4, v = 1 -> 3
+  return d >= 2 ? 2 : d;
+}
+// Sign-coding context (9..13) and XOR bit from clamped contributions.
+__device__ __forceinline__ int sc_ctx(int hc, int vc, int* xr) {
+  // hc = 0: 9 (vc = 0) or 10, XOR when vc < 0; hc = +-1: 12 + hc*vc, XOR when hc < 0
+  int c, x;
+  if (hc == 0) { c = vc ? 10 : 9; x = vc < 0; }
+  else { c = 12 + hc * vc; x = hc < 0; }
+  *xr = x;
+  return c;
+}
+
+template <typename M> struct MaskBits { static constexpr int value = 8 * sizeof(M); };
+template <typename M>
+__device__ __forceinline__ int bt(M r, int x) {
+  return (x >= 0 && x < MaskBits<M>::value) ? (int)((r >> x) & 1) : 0;
+}
+template <typename M> __device__ __forceinline__ int ctzm(M v);
+template <> __device__ __forceinline__ int ctzm<uint32_t>(uint32_t v) { return __builtin_ctz(v); }
+template <> __device__ __forceinline__ int ctzm<uint64_t>(uint64_t v) { return __builtin_ctzll(v); }
+template <typename M>
+__device__ __forceinline__ M nb3(int x) {   // bits x-1, x, x+1
+  M m = (M)1 << x;
+  if (x > 0) m |= (M)1 << (x - 1);
+  if (x + 1 < MaskBits<M>::value) m |= (M)1 << (x + 1);
+  return m;
+}
+
+// ------------------------------------------------------------------------
+// Quantisation and bit-plane masks (one wavefront per code-block).
+// planes: [nblk][kQBits][cbh] masks; signs: [nblk][cbh]; pb: [nblk].
+// ------------------------------------------------------------------------
+template <typename M>
+__global__ __launch_bounds__(256) void k_quant_planes(const float* __restrict__ coef, int nx, const Blk* __restrict__ blk,
+                                                      int nblk, int e0, int cbw, int cbh, M* __restrict__ planes,
+                                                      M* __restrict__ signs, uint8_t* __restrict__ pb) {
+  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int b = blockIdx.x * 4 + wave;
+  if (b >= nblk) return;
+  Blk k = blk[b];
+  int sh = k.gain - e0;
+  uint32_t mx = 0;
+  for (int i = lane; i < k.w * k.h; i += 64) {
+    int y = i / k.w, x = i - y * k.w;
+    uint32_t q = quantq(coef[(k.y0 + y) * nx + k.x0 + x], sh);
+    mx = q > mx ? q : mx;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    uint32_t t = __shfl_xor(mx, o);
+    mx = t > mx ? t : mx;
+  }
+  int P = mx ? 32 - __builtin_clz(mx) : 0;
+  if (lane == 0) pb[b] = (uint8_t)P;
+  // rows per ballot: 64 / cbw (cbw is a power of two <= 64)
+  int rpb = 64 / cbw;
+  int r = lane / cbw, x = lane - r * cbw;
+  M* pl = planes + (size_t)b * kQBits * cbh;
+  M* sg = signs + (size_t)b * cbh;
+  uint64_t wm = (cbw == 64) ? ~0ull : ((1ull << cbw) - 1ull);
+  for (int y0 = 0; y0 < k.h; y0 += rpb) {
+    int y = y0 + r;
+    bool valid = (x < k.w) && (y < k.h);
+    float c = valid ? coef[(k.y0 + y) * nx + k.x0 + x] : 0.0f;
+    uint32_t q = valid ? quantq(c, sh) : 0u;
+    uint64_t bs = __ballot(valid && c < 0.0f);
+    for (int p = 0; p < P; p++) {
+      uint64_t bp = __ballot((q >> p) & 1u);
+      // lane p keeps plane p's rows; the rows of this ballot go out one by one
+      for (int rr = 0; rr < rpb; rr++) {
+        if (y0 + rr >= k.h) break;
+        M row = (M)((bp >> (rr * cbw)) & wm);
+        if (lane == p) pl[(size_t)p * cbh + y0 + rr] = row;
+      }
+    }
+    for (int rr = 0; rr < rpb; rr++) {
+      if (y0 + rr >= k.h) break;
+      if (lane == 63) sg[y0 + rr] = (M)((bs >> (rr * cbw)) & wm);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// MQ encoder in registers.  B is the byte at index BP (not yet written: it
+// may still receive a carry); BP = -1 is the dummy byte before the output.
+// ------------------------------------------------------------------------
+struct MQEnc {
+  uint32_t C, A, B;
+  int CT, BP;
+  uint8_t* out;
+};
+__device__ __forceinline__ void mq_emit(MQEnc& e, uint32_t nb) {
+  if (e.BP >= 0 && e.BP < kCwCap) e.out[e.BP] = (uint8_t)e.B;
+  e.BP++;
+  e.B = nb;
+}
+__device__ __forceinline__ void mq_byteout(MQEnc& e) {
+  if (e.B == 0xFF) {
+    mq_emit(e, e.C >> 20); e.C &= 0xFFFFF; e.CT = 7;
+  } else if (e.C < 0x8000000u) {
+    mq_emit(e, e.C >> 19); e.C &= 0x7FFFF; e.CT = 8;
+  } else {
+    e.B += 1;
+    if (e.B == 0xFF) {
+      e.C &= 0x7FFFFFF;
+      mq_emit(e, e.C >> 20); e.C &= 0xFFFFF; e.CT = 7;
+    } else {
+      mq_emit(e, (e.C >> 19) & 0xFF); e.C &= 0x7FFFF; e.CT = 8;
+    }
+  }
+}
+__device__ __forceinline__ void mq_renorm(MQEnc& e) {
+  // shift until A >= 0x8000, emitting a byte whenever CT reaches 0
+  int n = __builtin_clz(e.A) - 16;
+  while (n > 0) {
+    int s = n < e.CT ? n : e.CT;
+    e.A <<= s; e.C <<= s; e.CT -= s; n -= s;
+    if (e.CT == 0) mq_byteout(e);
+  }
+}
+// cs: context state (index | MPS << 7)
+__device__ __forceinline__ void mq_encode(MQEnc& e, uint8_t* cs_ptr, int d) {
+  uint32_t cs = *cs_ptr;
+  uint32_t ent = c_mqt[cs & 0x7f];
+  uint32_t qe = ent & 0xFFFF;
+  uint32_t mps = cs >> 7;
+  e.A -= qe;
+  if ((uint32_t)d == mps) {
+    if ((e.A & 0x8000) == 0) {
+      if (e.A < qe) e.A = qe; else e.C += qe;
+      *cs_ptr = (uint8_t)((cs & 0x80) | ((ent >> 16) & 0x3f));
+      mq_renorm(e);
+    } else {
+      e.C += qe;
+    }
+  } else {
+    if (e.A < qe) e.C += qe; else e.A = qe;
+    uint32_t m = (ent >> 28) ? (mps ^ 1u) : mps;
+    *cs_ptr = (uint8_t)((m << 7) | ((ent >> 22) & 0x3f));
+    mq_renorm(e);
+  }
+}
+// Terminate a copy of the coder: returns the codeword length and the bytes
+// written at positions BP, BP+1, BP+2 (packed little-endian in *tail).
+__device__ __forceinline__ int mq_flush_copy(const MQEnc& e, uint32_t* tail) {
+  uint32_t C = e.C, tempc = C + e.A;
+  C |= 0xFFFF;
+  if (C >= tempc) C -= 0x8000;
+  uint32_t tb[3] = {e.B, 0u, 0u};
+  int bp = 0, CT = e.CT;
+  for (int r = 0; r < 2; r++) {
+    C <<= CT;
+    uint32_t B = tb[bp];
+    if (B == 0xFF) {
+      bp++; tb[bp] = (C >> 20) & 0xFF; C &= 0xFFFFF; CT = 7;
+    } else if (C < 0x8000000u) {
+      bp++; tb[bp] = (C >> 19) & 0xFF; C &= 0x7FFFF; CT = 8;
+    } else {
+      B += 1; tb[bp] = B & 0xFF;
+      if (B == 0xFF) {
+        C &= 0x7FFFFFF; bp++; tb[bp] = (C >> 20) & 0xFF; C &= 0xFFFFF; CT = 7;
+      } else {
+        bp++; tb[bp] = (C >> 19) & 0xFF; C &= 0x7FFFF; CT = 8;
+      }
+    }
+  }
+  *tail = tb[0] | (tb[1] << 8) | (tb[2] << 16);
+  return e.BP + 3 - (tb[2] == 0xFF ? 1 : 0);
+}
+
+// Squared-error reductions (units of (step/2)^2) when a sample of magnitude q
+// becomes significant at plane p, or is refined at plane p.
+__device__ __forceinline__ int64_t sig_delta(uint32_t q, int p) {
+  int64_t e0 = 2 * (int64_t)q + 1;
+  int64_t m = (int64_t)((q >> p) << p);
+  int64_t e1 = e0 - (2 * m + ((int64_t)1 << p));
+  return e0 * e0 - e1 * e1;
+}
+__device__ __forceinline__ int64_t ref_delta(uint32_t q, int p) {
+  int64_t e = 2 * (int64_t)q + 1;
+  int64_t m0 = (int64_t)((q >> (p + 1)) << (p + 1));
+  int64_t m1 = (int64_t)((q >> p) << p);
+  int64_t a = e - (2 * m0 + ((int64_t)1 << (p + 1)));
+  int64_t b = e - (2 * m1 + ((int64_t)1 << p));
+  return a * a - b * b;
+}
+
+template <typename M, int ROWS, int LANES>
+struct T1Shared {
+  M sig[ROWS][LANES], vis[ROWS][LANES], ref[ROWS][LANES], neg[ROWS][LANES], mag[ROWS][LANES], aux[ROWS][LANES];
+  uint8_t ctx[kNCtx][LANES];
+};
+
+template <typename M, int ROWS, int LANES>
+struct T1Lane {
+  T1Shared<M, ROWS, LANES>& S;
+  int lane, h, w, orient;
+  __device__ M row(M (*a)[LANES], int y) const { return (y >= 0 && y < h) ? a[y][lane] : (M)0; }
+  __device__ void counts(int y, int x, int& H, int& V, int& D) const {
+    M up = row(S.sig, y - 1), mid = S.sig[y][lane], dn = row(S.sig, y + 1);
+    H = bt(mid, x - 1) + bt(mid, x + 1);
+    V = bt(up, x) + bt(dn, x);
+    D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
+  }
+  __device__ int sgn(int y, int x) const {   // sign contribution of a neighbour
+    if (y < 0 || y >= h || !bt(S.sig[y][lane], x)) return 0;
+    return bt(S.neg[y][lane], x) ? -1 : 1;
+  }
+  __device__ int sign_ctx(int y, int x, int* xr) const {
+    int hc = sgn(y, x - 1) + sgn(y, x + 1);
+    int vc = sgn(y - 1, x) + sgn(y + 1, x);
+    hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
+    vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
+    return sc_ctx(hc, vc, xr);
+  }
+  // columns of stripe y0 (rn rows) holding a sample with sig = 0 and at
+  // least one significant neighbour, restricted to columns >= x
+  __device__ M spp_cands(int y0, int rn, int x) const {
+    M c = 0;
+    for (int r = 0; r < rn; r++) {
+      M mid = S.sig[y0 + r][lane];
+      M nb = row(S.sig, y0 + r - 1) | mid | row(S.sig, y0 + r + 1);
+      nb = nb | (nb << 1) | (nb >> 1);
+      c |= ~mid & nb;
+    }
+    M wm = (w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << w) - 1);
+    return c & wm & (~(M)0 << x);
+  }
+  __device__ bool run_ok(int y0, int x) const {
+    for (int r = 0; r < 4; r++)
+      if (bt(S.sig[y0 + r][lane] | S.vis[y0 + r][lane], x)) return false;
+    M nbm = nb3<M>(x);
+    for (int y = y0 - 1; y <= y0 + 4; y++)
+      if (row(S.sig, y) & nbm) return false;
+    return true;
+  }
+};
+
+// ------------------------------------------------------------------------
+// Tier-1 encoder: one lane per code-block.
+// ------------------------------------------------------------------------
+template <typename M, int ROWS, int LANES>
+__global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ coef, int nx, const Blk* __restrict__ blk,
+                                                     int nblk, int e0, int cbh, const M* __restrict__ planes,
+                                                     const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
+                                                     uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
+                                                     int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
+                                                     uint32_t* __restrict__ tailt, M* __restrict__ sppf) {
+  __shared__ T1Shared<M, ROWS, LANES> S;
+  int lane = threadIdx.x;
+  int b = blockIdx.x * LANES + lane;
+  if (b >= nblk) return;
+  Blk k = blk[b];
+  int P = pbv[b];
+  int32_t* R = Rt + (size_t)b * kPassStride;
+  int64_t* Dd = Dt + (size_t)b * kPassStride;
+  int32_t* BPk = bpt + (size_t)b * kPassStride;
+  uint32_t* TL = tailt + (size_t)b * kPassStride;
+  R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0;
+  M* spo = sppf + (size_t)b * cbh;
+  if (P == 0) {
+    for (int y = 0; y < k.h; y++) spo[y] = 0;
+    return;
+  }
+  T1Lane<M, ROWS, LANES> T{S, lane, k.h, k.w, k.orient};
+  for (int y = 0; y < k.h; y++) {
+    S.sig[y][lane] = 0; S.vis[y][lane] = 0; S.ref[y][lane] = 0; S.aux[y][lane] = 0;
+    S.neg[y][lane] = signs[(size_t)b * cbh + y];
+  }
+  for (int c = 0; c < kNCtx; c++) S.ctx[c][lane] = 0;
+  S.ctx[0][lane] = 4; S.ctx[CX_RL][lane] = 3; S.ctx[CX_UNI][lane] = 46;
+  MQEnc e;
+  e.C = 0; e.A = 0x8000; e.B = 0; e.CT = 12; e.BP = -1; e.out = cw + (size_t)b * kCwCap;
+  const int sh = k.gain - e0;
+  const float* cb = coef + (size_t)k.y0 * nx + k.x0;
+  auto qat = [&](int y, int x) { return quantq(cb[y * nx + x], sh); };
+  auto code_sign = [&](int y, int x) {
+    int xr;
+    int cx = T.sign_ctx(y, x, &xr);
+    mq_encode(e, &S.ctx[cx][lane], bt(S.neg[y][lane], x) ^ xr);
+  };
+  int npass = 3 * P - 2, kk = 0;
+  bool stop = false;
+  int64_t Dcum = 0;
+  for (int p = P - 1; p >= 0 && !stop; p--) {
+    const M* pl = planes + ((size_t)b * kQBits + p) * cbh;
+    for (int y = 0; y < k.h; y++) S.mag[y][lane] = pl[y];
+    for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
+      int64_t dd = 0;
+      for (int y0 = 0; y0 < k.h && !stop; y0 += 4) {
+        int rn = k.h - y0 < 4 ? k.h - y0 : 4;
+        if (ty == 0) {                         // significance propagation
+          int x = 0;
+          while (x < k.w) {
+            M c = T.spp_cands(y0, rn, x);
+            if (!c) break;
+            x = ctzm(c);
+            for (int r = 0; r < rn; r++) {
+              int y = y0 + r;
+              M mid = S.sig[y][lane];
+              if (bt(mid, x)) continue;
+              int H, V, D;
+              T.counts(y, x, H, V, D);
+              if (H + V + D == 0) continue;
+              int bit = bt(S.mag[y][lane], x);
+              mq_encode(e, &S.ctx[zc_ctx(k.orient, H, V, D)][lane], bit);
+              S.vis[y][lane] |= (M)1 << x;
+              if (bit) {
+                code_sign(y, x);
+                S.sig[y][lane] = mid | ((M)1 << x);
+                S.aux[y][lane] |= (M)1 << x;
+                dd += sig_delta(qat(y, x), p);
+              }
+            }
+            x++;
+          }
+        } else if (ty == 1) {                  // magnitude refinement
+          M mk = 0;
+          for (int r = 0; r < rn; r++) mk |= S.sig[y0 + r][lane] & ~S.vis[y0 + r][lane];
+          while (mk) {
+            int x = ctzm(mk);
+            mk &= mk - 1;
+            for (int r = 0; r < rn; r++) {
+              int y = y0 + r;
+              if (!bt(S.sig[y][lane] & ~S.vis[y][lane], x)) continue;
+              int cx;
+              if (bt(S.ref[y][lane], x)) cx = CX_MR + 2;
+              else { int H, V, D; T.counts(y, x, H, V, D); cx = (H + V + D) ? CX_MR + 1 : CX_MR; }
+              mq_encode(e, &S.ctx[cx][lane], bt(S.mag[y][lane], x));
+              S.ref[y][lane] |= (M)1 << x;
+              dd += ref_delta(qat(y, x), p);
+            }
+          }
+        } else {                               // cleanup
+          M u = 0;
+          for (int r = 0; r < rn; r++) u |= ~(S.sig[y0 + r][lane] | S.vis[y0 + r][lane]);
+          M wm = (k.w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << k.w) - 1);
+          u &= wm;
+          while (u) {
+            int x = ctzm(u);
+            u &= u - 1;
+            int r = 0;
+            if (rn == 4 && T.run_ok(y0, x)) {
+              int rr = -1;
+              for (int t = 0; t < 4; t++)
+                if (bt(S.mag[y0 + t][lane], x)) { rr = t; break; }
+              mq_encode(e, &S.ctx[CX_RL][lane], rr >= 0);
+              if (rr < 0) continue;
+              mq_encode(e, &S.ctx[CX_UNI][lane], (rr >> 1) & 1);
+              mq_encode(e, &S.ctx[CX_UNI][lane], rr & 1);
+              int y = y0 + rr;
+              code_sign(y, x);
+              S.sig[y][lane] |= (M)1 << x;
+              dd += sig_delta(qat(y, x), p);
+              r = rr + 1;
+            }
+            for (; r < rn; r++) {
+              int y = y0 + r;
+              if (bt(S.sig[y][lane] | S.vis[y][lane], x)) continue;
+              int H, V, D;
+              T.counts(y, x, H, V, D);
+              int bit = bt(S.mag[y][lane], x);
+              mq_encode(e, &S.ctx[zc_ctx(k.orient, H, V, D)][lane], bit);
+              if (bit) {
+                code_sign(y, x);
+                S.sig[y][lane] |= (M)1 << x;
+                dd += sig_delta(qat(y, x), p);
+              }
+            }
+          }
+        }
+        if (e.BP >= 65536) stop = true;       // every later pass exceeds the length limit
+      }
+      if (ty == 2)
+        for (int y = 0; y < k.h; y++) S.vis[y][lane] = 0;
+      if (stop) break;
+      kk++;
+      Dcum += dd;
+      uint32_t tail;
+      R[kk] = mq_flush_copy(e, &tail);
+      Dd[kk] = Dcum;
+      BPk[kk] = e.BP;
+      TL[kk] = tail;
+    }
+  }
+  for (int j = kk + 1; j <= npass; j++) { R[j] = kRInf; Dd[j] = Dcum; BPk[j] = 0; TL[j] = 0; }
+  for (int y = 0; y < k.h; y++) spo[y] = S.aux[y][lane];
+}
+
+// ------------------------------------------------------------------------
+// Closed-form base reconstruction for the kept passes (one wave per block).
+// ------------------------------------------------------------------------
+template <typename M>
+__global__ __launch_bounds__(256) void k_virtual_decode(const float* __restrict__ coef, int nx, const Blk* __restrict__ blk,
+                                                        int nblk, int e0, int cbh, const uint8_t* __restrict__ pbv,
+                                                        const uint8_t* __restrict__ kbv, const M* __restrict__ sppf,
+                                                        float* __restrict__ yhat) {
+  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int b = blockIdx.x * 4 + wave;
+  if (b >= nblk) return;
+  Blk k = blk[b];
+  int P = pbv[b], kb = kbv[b];
+  int sh = k.gain - e0, e = e0 - k.gain;
+  for (int i = lane; i < k.w * k.h; i += 64) {
+    int y = i / k.w, x = i - y * k.w;
+    int idx = (k.y0 + y) * nx + k.x0 + x;
+    float c = coef[idx];
+    uint32_t q = quantq(c, sh);
+    float v = 0.0f;
+    if (q && kb) {
+      int ps = 31 - __builtin_clz(q);
+      int sp;                                   // pass index that makes it significant
+      if (ps == P - 1) sp = 0;
+      else sp = 3 * (P - 2 - ps) + (bt(sppf[(size_t)b * cbh + y], x) ? 1 : 3);
+      if (sp < kb) {
+        int pk = ps;
+        while (pk > 0 && 3 * (P - 2 - (pk - 1)) + 2 < kb) pk--;
+        uint32_t m = (q >> pk) << pk;
+        v = dequant(m, pk, c < 0.0f, e);
+      }
+    }
+    yhat[idx] = v;
+  }
+}
+
+// ------------------------------------------------------------------------
+// MQ decoder (bytes past the codeword read as 0xFF).
+// ------------------------------------------------------------------------
+struct MQDec {
+  uint32_t C, A;
+  int CT, BP, len;
+  const uint8_t* buf;
+};
+__device__ __forceinline__ uint32_t mq_rd(const MQDec& d, int i) { return (i >= 0 && i < d.len) ? d.buf[i] : 0xFFu; }
+__device__ __forceinline__ void mq_bytein(MQDec& d) {
+  if (mq_rd(d, d.BP) == 0xFF) {
+    if (mq_rd(d, d.BP + 1) > 0x8F) { d.C += 0xFF00; d.CT = 8; }
+    else { d.BP++; d.C += mq_rd(d, d.BP) << 9; d.CT = 7; }
+  } else {
+    d.BP++; d.C += mq_rd(d, d.BP) << 8; d.CT = 8;
+  }
+}
+__device__ __forceinline__ void mq_dinit(MQDec& d, const uint8_t* buf, int len) {
+  d.buf = buf; d.len = len; d.BP = 0;
+  d.C = mq_rd(d, 0) << 16;
+  mq_bytein(d);
+  d.C <<= 7; d.CT -= 7; d.A = 0x8000;
+}
+__device__ __forceinline__ void mq_renormd(MQDec& d) {
+  do {
+    if (d.CT == 0) mq_bytein(d);
+    d.A <<= 1; d.C <<= 1; d.CT--;
+  } while ((d.A & 0x8000) == 0);
+}
+__device__ __forceinline__ int mq_decode(MQDec& d, uint8_t* cs_ptr) {
+  uint32_t cs = *cs_ptr;
+  uint32_t ent = c_mqt[cs & 0x7f];
+  uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
+  uint32_t nm = (ent >> 16) & 0x3f, nl = (ent >> 22) & 0x3f, sw = ent >> 28;
+  int D;
+  d.A -= qe;
+  if ((d.C >> 16) < qe) {
+    if (d.A < qe) { D = (int)mps; cs = (mps << 7) | nm; }
+    else { D = (int)(mps ^ 1u); uint32_t m = sw ? (mps ^ 1u) : mps; cs = (m << 7) | nl; }
+    d.A = qe;
+    *cs_ptr = (uint8_t)cs;
+    mq_renormd(d);
+  } else {
+    d.C -= qe << 16;
+    if ((d.A & 0x8000) == 0) {
+      if (d.A < qe) { D = (int)(mps ^ 1u); uint32_t m = sw ? (mps ^ 1u) : mps; cs = (m << 7) | nl; }
+      else { D = (int)mps; cs = (mps << 7) | nm; }
+      *cs_ptr = (uint8_t)cs;
+      mq_renormd(d);
+    } else {
+      D = (int)mps;
+    }
+  }
+  return D;
+}
+
+// ------------------------------------------------------------------------
+// Tier-1 decoder: one lane per code-block.  `table` holds the 4-byte block
+// entries (P_b | k_b << 8 | len << 16), `off` the payload offsets within
+// `sec` (the whole base section).  Writes the dequantised coefficients of
+// every sample of the block into yhat; the magnitudes being decoded are kept
+// in yhat's storage as integers until the block is finished.
+// ------------------------------------------------------------------------
+template <typename M, int ROWS, int LANES>
+__global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__ sec, int64_t sec_len,
+                                                     const uint32_t* __restrict__ table, const int64_t* __restrict__ off,
+                                                     int nx, const Blk* __restrict__ blk, int nblk, int e0,
+                                                     float* __restrict__ yhat, int* __restrict__ flag) {
+  __shared__ T1Shared<M, ROWS, LANES> S;     // aux = coded in the current plane
+  int lane = threadIdx.x;
+  int b = blockIdx.x * LANES + lane;
+  if (b >= nblk) return;
+  Blk k = blk[b];
+  uint32_t ent = table[b];
+  int P = ent & 0xFF, kb = (ent >> 8) & 0xFF, len = (int)(ent >> 16);
+  int64_t o = off[b];
+  float* yb = yhat + (size_t)k.y0 * nx + k.x0;
+  uint32_t* mb = reinterpret_cast<uint32_t*>(yb);
+  bool bad = P > kQBits || kb > (P ? 3 * P - 2 : 0) || o < 0 || o + len > sec_len;
+  if (bad) atomicOr(flag, 1);
+  if (bad || P == 0 || kb == 0) {
+    for (int y = 0; y < k.h; y++)
+      for (int x = 0; x < k.w; x++) yb[y * nx + x] = 0.0f;
+    return;
+  }
+  T1Lane<M, ROWS, LANES> T{S, lane, k.h, k.w, k.orient};
+  for (int y = 0; y < k.h; y++) {
+    S.sig[y][lane] = 0; S.vis[y][lane] = 0; S.ref[y][lane] = 0; S.neg[y][lane] = 0; S.aux[y][lane] = 0;
+  }
+  for (int c = 0; c < kNCtx; c++) S.ctx[c][lane] = 0;
+  S.ctx[0][lane] = 4; S.ctx[CX_RL][lane] = 3; S.ctx[CX_UNI][lane] = 46;
+  MQDec d;
+  mq_dinit(d, sec + o, len);
+  auto dec_sign = [&](int y, int x) {
+    int xr;
+    int cx = T.sign_ctx(y, x, &xr);
+    int s = mq_decode(d, &S.ctx[cx][lane]) ^ xr;
+    if (s) S.neg[y][lane] |= (M)1 << x;
+  };
+  int done = 0, plast = P - 1;
+  for (int p = P - 1; p >= 0 && done < kb; p--) {
+    plast = p;
+    for (int y = 0; y < k.h; y++) S.aux[y][lane] = 0;
+    for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < kb; ty++) {
+      for (int y0 = 0; y0 < k.h; y0 += 4) {
+        int rn = k.h - y0 < 4 ? k.h - y0 : 4;
+        if (ty == 0) {
+          int x = 0;
+          while (x < k.w) {
+            M c = T.spp_cands(y0, rn, x);
+            if (!c) break;
+            x = ctzm(c);
+            for (int r = 0; r < rn; r++) {
+              int y = y0 + r;
+              M mid = S.sig[y][lane];
+              if (bt(mid, x)) continue;
+              int H, V, D;
+              T.counts(y, x, H, V, D);
+              if (H + V + D == 0) continue;
+              int bit = mq_decode(d, &S.ctx[zc_ctx(k.orient, H, V, D)][lane]);
+              S.vis[y][lane] |= (M)1 << x;
+              if (bit) {
+                dec_sign(y, x);
+                S.sig[y][lane] = mid | ((M)1 << x);
+                S.aux[y][lane] |= (M)1 << x;
+                mb[y * nx + x] = 1u << p;
+              }
+            }
+            x++;
+          }
+        } else if (ty == 1) {
+          M mk = 0;
+          for (int r = 0; r < rn; r++) mk |= S.sig[y0 + r][lane] & ~S.vis[y0 + r][lane];
+          while (mk) {
+            int x = ctzm(mk);
+            mk &= mk - 1;
+            for (int r = 0; r < rn; r++) {
+              int y = y0 + r;
+              if (!bt(S.sig[y][lane] & ~S.vis[y][lane], x)) continue;
+              int cx;
+              if (bt(S.ref[y][lane], x)) cx = CX_MR + 2;
+              else { int H, V, D; T.counts(y, x, H, V, D); cx = (H + V + D) ? CX_MR + 1 : CX_MR; }
+              int bit = mq_decode(d, &S.ctx[cx][lane]);
+              if (bit) mb[y * nx + x] |= 1u << p;
+              S.ref[y][lane] |= (M)1 << x;
+              S.aux[y][lane] |= (M)1 << x;
+            }
+          }
+        } else {
+          M u = 0;
+          for (int r = 0; r < rn; r++) u |= ~(S.sig[y0 + r][lane] | S.vis[y0 + r][lane]);
+          M wm = (k.w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << k.w) - 1);
+          u &= wm;
+          while (u) {
+            int x = ctzm(u);
+            u &= u - 1;
+            int r = 0;
+            if (rn == 4 && T.run_ok(y0, x)) {
+              if (!mq_decode(d, &S.ctx[CX_RL][lane])) continue;
+              int b1 = mq_decode(d, &S.ctx[CX_UNI][lane]);
+              int b0 = mq_decode(d, &S.ctx[CX_UNI][lane]);
+              int rr = 2 * b1 + b0;
+              int y = y0 + rr;
+              dec_sign(y, x);
+              S.sig[y][lane] |= (M)1 << x;
+              S.aux[y][lane] |= (M)1 << x;
+              mb[y * nx + x] = 1u << p;
+              r = rr + 1;
+            }
+            for (; r < rn; r++) {
+              int y = y0 + r;
+              if (bt(S.sig[y][lane] | S.vis[y][lane], x)) continue;
+              int H, V, D;
+              T.counts(y, x, H, V, D);
+              int bit = mq_decode(d, &S.ctx[zc_ctx(k.orient, H, V, D)][lane]);
+              if (bit) {
+                dec_sign(y, x);
+                S.sig[y][lane] |= (M)1 << x;
+                S.aux[y][lane] |= (M)1 << x;
+                mb[y * nx + x] = 1u << p;
+              }
+            }
+          }
+        }
+      }
+      if (ty == 2)
+        for (int y = 0; y < k.h; y++) S.vis[y][lane] = 0;
+      done++;
+    }
+  }
+  const int e = e0 - k.gain;
+  for (int y = 0; y < k.h; y++) {
+    M sg = S.sig[y][lane], cur = S.aux[y][lane], ng = S.neg[y][lane];
+    for (int x = 0; x < k.w; x++) {
+      float v = 0.0f;
+      if (bt(sg, x)) {
+        int pk = bt(cur, x) ? plast : plast + 1;
+        v = dequant(mb[y * nx + x], pk, bt(ng, x), e);
+      }
+      yb[y * nx + x] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// Launchers: mask width follows the code-block width, LDS rows its height.
+// ------------------------------------------------------------------------
+#define T1_DISPATCH(CBW, CBH, MACRO)                               \
+  do {                                                             \
+    if ((CBW) <= 32) {                                             \
+      if ((CBH) <= 16) MACRO(uint32_t, 16, 64);                    \
+      else if ((CBH) <= 32) MACRO(uint32_t, 32, 64);               \
+      else MACRO(uint32_t, 64, 32);                                \
+    } else {                                                       \
+      if ((CBH) <= 16) MACRO(uint64_t, 16, 64);                    \
+      else if ((CBH) <= 32) MACRO(uint64_t, 32, 32);               \
+      else MACRO(uint64_t, 64, 16);                                \
+    }                                                              \
+  } while (0)
+
+void quant_planes(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, void* planes,
+                  void* signs, uint8_t* pb, hipStream_t st) {
+  if (nblk <= 0) return;
+  int g = (nblk + 3) / 4;
+  if (cbw <= 32)
+    k_quant_planes<uint32_t><<<g, 256, 0, st>>>(coef, nx, blk, nblk, e0, cbw, cbh, (uint32_t*)planes,
+                                                 (uint32_t*)signs, pb);
+  else
+    k_quant_planes<uint64_t><<<g, 256, 0, st>>>(coef, nx, blk, nblk, e0, cbw, cbh, (uint64_t*)planes,
+                                                 (uint64_t*)signs, pb);
+}
+
+void t1_encode(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, const void* planes,
+               const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
+               uint32_t* tail, void* sppf, hipStream_t st) {
+  if (nblk <= 0) return;
+#define ENC(MT, RW, LN)                                                                                        \
+  k_t1_encode<MT, RW, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(coef, nx, blk, nblk, e0, cbh, (const MT*)planes, \
+                                                               (const MT*)signs, pb, cw, R, D, bp, tail,       \
+                                                               (MT*)sppf)
+  T1_DISPATCH(cbw, cbh, ENC);
+#undef ENC
+}
+
+void virtual_decode(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, const uint8_t* pb,
+                    const uint8_t* kb, const void* sppf, float* yhat, hipStream_t st) {
+  if (nblk <= 0) return;
+  int g = (nblk + 3) / 4;
+  if (cbw <= 32)
+    k_virtual_decode<uint32_t><<<g, 256, 0, st>>>(coef, nx, blk, nblk, e0, cbh, pb, kb, (const uint32_t*)sppf, yhat);
+  else
+    k_virtual_decode<uint64_t><<<g, 256, 0, st>>>(coef, nx, blk, nblk, e0, cbh, pb, kb, (const uint64_t*)sppf, yhat);
+}
+
+void t1_decode(const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off, int nx, const Blk* blk,
+               int nblk, int e0, int cbw, int cbh, float* yhat, int* flag, hipStream_t st) {
+  if (nblk <= 0) return;
+#define DEC(MT, RW, LN) \
+  k_t1_decode<MT, RW, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(sec, sec_len, table, off, nx, blk, nblk, e0, yhat, flag)
+  T1_DISPATCH(cbw, cbh, DEC);
+#undef DEC
+}
+
+}  // namespace ebcc

@@ -1,0 +1,169 @@
+"""ctypes binding of libebcc.so (the C ABI in include/ebcc.h).
+
+Argument marshalling only: every step of compression and decompression runs
+in the library's HIP kernels.  Tensors are PyTorch CUDA (HIP) tensors; the
+current torch stream is passed to the library.  There is no CPU fallback: if
+the library is missing, loading fails with an error.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libebcc.so")
+
+OK, EINVAL, ENOSPC, ECORRUPT, ENOMEM, EHIP, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6
+BOUND_REL, BOUND_ABS = 0, 1
+MODE_CONST, MODE_RAW, MODE_CODED = 0, 1, 2
+HDR_BYTES = 48
+
+SYMBOLS = ("ebcc_params_default", "ebcc_compress_bound", "ebcc_compress", "ebcc_decompress", "ebcc_stream_info",
+           "ebcc_release", "ebcc_status_str", "ebcc_last_error", "ebcc_compress_trace")
+
+
+class Params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("bound_mode", C.c_uint32), ("err_bound", C.c_double),
+                ("base_ratio", C.c_double), ("q", C.c_double), ("levels", C.c_uint32), ("cblk_log2w", C.c_uint32),
+                ("cblk_log2h", C.c_uint32), ("spiht_tile", C.c_uint32)]
+
+
+class EbccError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libebcc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (__graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P, S = C.c_void_p, C.c_size_t
+        L.ebcc_params_default.argtypes = [C.POINTER(Params)]
+        L.ebcc_params_default.restype = None
+        L.ebcc_compress_bound.argtypes = [S, S]
+        L.ebcc_compress_bound.restype = S
+        L.ebcc_compress.argtypes = [P, S, S, C.POINTER(Params), P, S, C.POINTER(S), P]
+        L.ebcc_compress_trace.argtypes = [P, S, S, C.POINTER(Params), P, S, C.POINTER(S), P, P, P, P, P, P, P]
+        L.ebcc_decompress.argtypes = [P, S, P, S, S, P]
+        L.ebcc_stream_info.argtypes = [P, S, C.POINTER(S), C.POINTER(S), C.POINTER(C.c_int)]
+        L.ebcc_release.argtypes = []
+        L.ebcc_release.restype = None
+        L.ebcc_status_str.argtypes = [C.c_int]
+        L.ebcc_status_str.restype = C.c_char_p
+        L.ebcc_last_error.argtypes = []
+        L.ebcc_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def params(err_bound=0.01, base_ratio=30.0, bound_mode=BOUND_REL, levels=5, cblk_log2w=5, cblk_log2h=5,
+           spiht_tile=2, q=0.0):
+    p = Params()
+    lib().ebcc_params_default(C.byref(p))
+    p.err_bound, p.base_ratio, p.bound_mode = float(err_bound), float(base_ratio), int(bound_mode)
+    p.levels, p.cblk_log2w, p.cblk_log2h, p.spiht_tile, p.q = levels, cblk_log2w, cblk_log2h, spiht_tile, float(q)
+    return p
+
+
+def _check(rc):
+    if rc != OK:
+        raise EbccError(rc, lib().ebcc_last_error().decode() or lib().ebcc_status_str(rc).decode())
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(x):
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.dim() == 2):
+        raise TypeError("expected a 2-D float32 tensor on the GPU")
+    return x.contiguous()
+
+
+def compress_bound(ny, nx):
+    return lib().ebcc_compress_bound(ny, nx)
+
+
+def compress_into(x, out, p, stream=None):
+    """Compress x into the uint8 device tensor `out`; returns (rc, length)."""
+    n = C.c_size_t(0)
+    rc = lib().ebcc_compress(C.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], C.byref(p), C.c_void_p(out.data_ptr()),
+                             out.numel(), C.byref(n), _stream_ptr(stream))
+    return rc, n.value
+
+
+def compress(x, err_bound=0.01, base_ratio=30.0, out=None, stream=None, **kw):
+    """Compress a 2-D float32 CUDA tensor; returns a uint8 CUDA tensor (a view
+    of `out` when given)."""
+    x = _dev_f32(x)
+    p = params(err_bound, base_ratio, **kw)
+    if out is None:
+        out = torch.empty(compress_bound(*x.shape), dtype=torch.uint8, device=x.device)
+    rc, n = compress_into(x, out, p, stream)
+    _check(rc)
+    return out[:n]
+
+
+def compress_trace(x, err_bound=0.01, base_ratio=30.0, stream=None, **kw):
+    """Compress and also return intermediate results for stage comparison."""
+    x = _dev_f32(x)
+    p = params(err_bound, base_ratio, **kw)
+    out = torch.empty(compress_bound(*x.shape), dtype=torch.uint8, device=x.device)
+    coef = torch.zeros_like(x)
+    abase = torch.zeros_like(x)
+    cres = torch.zeros_like(x)
+    nblk_cap = x.numel() + 64
+    kb = torch.zeros(nblk_cap, dtype=torch.uint8, device=x.device)
+    pb = torch.zeros(nblk_cap, dtype=torch.uint8, device=x.device)
+    info = (C.c_int32 * 11)()
+    n = C.c_size_t(0)
+    rc = lib().ebcc_compress_trace(C.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], C.byref(p),
+                                   C.c_void_p(out.data_ptr()), out.numel(), C.byref(n), _stream_ptr(stream),
+                                   C.c_void_p(coef.data_ptr()), C.c_void_p(abase.data_ptr()),
+                                   C.c_void_p(cres.data_ptr()), C.c_void_p(kb.data_ptr()), C.c_void_p(pb.data_ptr()),
+                                   info)
+    _check(rc)
+    torch.cuda.synchronize()
+    f = list(info)
+    nb = f[6]
+    d = dict(coef=coef, abase=abase, cres=cres, kb=kb[:nb], pb=pb[:nb])
+    keys = ("mode", "L", "e0", "e_r", "n_max", "n_s", "nblocks", "ntiles", "base_bytes", "resid_bytes", "checks")
+    d.update(zip(keys, f))
+    return out[: n.value], d
+
+
+def decompress_into(stream_bytes, out, stream=None):
+    return lib().ebcc_decompress(C.c_void_p(stream_bytes.data_ptr()), stream_bytes.numel(), C.c_void_p(out.data_ptr()),
+                                 out.shape[0], out.shape[1], _stream_ptr(stream))
+
+
+def decompress(stream_bytes, ny, nx, out=None, stream=None):
+    """Decompress a uint8 CUDA tensor holding one stream into a float32
+    CUDA tensor of shape (ny, nx)."""
+    if not (isinstance(stream_bytes, torch.Tensor) and stream_bytes.is_cuda and stream_bytes.dtype == torch.uint8):
+        raise TypeError("expected a uint8 tensor on the GPU")
+    stream_bytes = stream_bytes.contiguous()
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.float32, device=stream_bytes.device)
+    _check(decompress_into(stream_bytes, out, stream))
+    return out
+
+
+def stream_info(header_bytes):
+    """(ny, nx, mode) from the first 48 bytes of a stream (host bytes)."""
+    b = (C.c_uint8 * len(header_bytes)).from_buffer_copy(bytes(header_bytes))
+    ny, nx, mode = C.c_size_t(), C.c_size_t(), C.c_int()
+    _check(lib().ebcc_stream_info(b, len(header_bytes), C.byref(ny), C.byref(nx), C.byref(mode)))
+    return ny.value, nx.value, mode.value
+
+
+def release():
+    lib().ebcc_release()

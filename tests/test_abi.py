@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every entry point include/ebcc.h
+declares (no GPU needed: nothing is called that touches a device)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ebcc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ebcc_[a-z_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_2510_22265_amd import ebcc
+    if not os.path.exists(ebcc.LIB_PATH):
+        from paper_2510_22265_amd import build
+        build.build()
+    return ebcc
+
+
+def test_exports_every_declared_symbol():
+    ebcc = _lib()
+    lib = ctypes.CDLL(ebcc.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(ebcc.SYMBOLS)
+
+
+def test_host_only_entry_points():
+    ebcc = _lib()
+    L = ebcc.lib()
+    p = ebcc.Params()
+    L.ebcc_params_default(ctypes.byref(p))
+    assert p.struct_size == ctypes.sizeof(ebcc.Params)
+    assert (p.err_bound, p.base_ratio, p.levels, p.cblk_log2w, p.cblk_log2h, p.spiht_tile) == (0.01, 30.0, 5, 5, 5, 2)
+    assert L.ebcc_compress_bound(181, 360) == 48 + 4 * 181 * 360
+    assert L.ebcc_status_str(-3) == b"corrupt stream"
+    hdr = bytearray(48)
+    hdr[:4] = b"EBCC"
+    hdr[4] = 1
+    hdr[5] = 2
+    hdr[8:12] = (721).to_bytes(4, "little")
+    hdr[12:16] = (1440).to_bytes(4, "little")
+    assert ebcc.stream_info(bytes(hdr)) == (721, 1440, 2)
+    bad = bytes(b"XBCC" + hdr[4:])
+    try:
+        ebcc.stream_info(bad)
+        assert False
+    except ebcc.EbccError as e:
+        assert e.code == ebcc.ECORRUPT
+
+
+def test_params_struct_matches_header():
+    """Field order and size of ebcc_params in the binding and the header."""
+    src = open(os.path.join(ROOT, "include", "ebcc.h")).read()
+    body = src[src.index("typedef struct {"): src.index("} ebcc_params;")]
+    fields = re.findall(r"^\s*(?:uint32_t|double)\s+(\w+);", body, flags=re.M)
+    from paper_2510_22265_amd import ebcc
+    assert fields == [f for f, _ in ebcc.Params._fields_]

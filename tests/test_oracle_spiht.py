@@ -12,7 +12,8 @@ def _field(rng, ny, nx, p=0.3, dens=0.5):
 
 @pytest.mark.parametrize("shape,L,T", [((8, 8), 3, 1), ((6, 6), 2, 1), ((13, 7), 2, 2), ((1, 1), 0, 1),
                                         ((1, 17), 0, 3), ((2, 2), 1, 1), ((91, 180), 5, 2), ((45, 46), 4, 1),
-                                        ((33, 66), 5, 2), ((70, 6), 2, 3)])
+                                        ((33, 66), 5, 2), ((70, 6), 2, 3), ((70, 130), 6, 1), ((6, 6), 2, 2),
+                                        ((45, 90), 5, 1)])
 def test_all_planes_lossless(ref, shape, L, T):
     rng = np.random.default_rng(sum(shape) * 7 + L)
     L = ref.levels_eff(*shape, L)
