@@ -120,6 +120,21 @@ int ebcc_compress_trace(const float* d_x, size_t ny, size_t nx, const ebcc_param
                         float* d_coef, float* d_abase, float* d_cres, uint8_t* d_kb,
                         uint8_t* d_pb, int32_t* h_info);
 
+/* ---------------------------------------------------------------------------
+ * Stage profiling.  When enabled, every call records HIP events on its
+ * stream at stage boundaries (base DWT, tier-1 encode, rate allocation, ...)
+ * and adds each stage's device time to process-wide accumulators; enabled
+ * calls synchronise their stream once more before returning.
+ *   ebcc_profile_enable(on)   enable/disable and reset the accumulators
+ *   ebcc_profile_read(ms, calls, n)  copy up to n stage totals (milliseconds,
+ *                             number of timed occurrences); returns the
+ *                             number of stages
+ *   ebcc_profile_stage_name(i)  the stage's name (static string)
+ * ------------------------------------------------------------------------- */
+void ebcc_profile_enable(int on);
+int ebcc_profile_read(double* ms, long* calls, int n);
+const char* ebcc_profile_stage_name(int i);
+
 #ifdef __cplusplus
 }
 #endif

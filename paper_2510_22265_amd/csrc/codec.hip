@@ -35,6 +35,60 @@ static int fail(int code, const std::string& msg) {
   } while (0)
 
 // ---------------------------------------------------------------------------
+// Stage profiling: HIP events recorded on the caller's stream at stage
+// boundaries; the time since the previous boundary is added to the stage
+// that just ended.  Off unless enabled (then every call synchronises once
+// more at its end to read the events).
+// ---------------------------------------------------------------------------
+enum Stage {
+  S_SCALARS, S_DWT, S_QUANT, S_T1ENC, S_PCRD, S_BASEREC, S_RESID, S_SEARCH, S_SPIHT, S_PACK,
+  S_D_PARSE, S_D_T1, S_D_IDWT_BASE, S_D_SPIHT, S_D_FINAL, S_COUNT
+};
+static const char* kStageNames[S_COUNT] = {
+    "scalars", "dwt_fwd", "quant_planes", "t1_encode", "pcrd", "base_recon", "resid_dwt_quant",
+    "plane_search", "spiht_encode", "pack", "dec_parse", "t1_decode", "dec_idwt_base", "spiht_decode",
+    "dec_final"};
+static int g_prof = 0;
+static double g_stage_ms[S_COUNT];
+static long g_stage_calls[S_COUNT];
+static std::mutex g_prof_mu;
+
+struct Prof {
+  hipStream_t st;
+  bool on;
+  hipEvent_t prev = nullptr;
+  std::vector<std::pair<int, hipEvent_t>> marks;
+  hipEvent_t first = nullptr;
+  explicit Prof(hipStream_t s) : st(s), on(g_prof != 0) {
+    if (!on) return;
+    if (hipEventCreate(&first) != hipSuccess || hipEventRecord(first, st) != hipSuccess) on = false;
+  }
+  void mark(int stage) {
+    if (!on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    marks.push_back(std::make_pair(stage, e));
+  }
+  ~Prof() {
+    if (!on) return;
+    (void)hipStreamSynchronize(st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t a = first;
+    for (auto& m : marks) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, a, m.second) == hipSuccess) {
+        g_stage_ms[m.first] += ms;
+        g_stage_calls[m.first] += 1;
+      }
+      a = m.second;
+    }
+    for (auto& m : marks) (void)hipEventDestroy(m.second);
+    (void)hipEventDestroy(first);
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned f2o(float f) {
@@ -554,12 +608,14 @@ static int compress_impl(const float* x, size_t ny_, size_t nx_, const ebcc_para
   rc = get_ws(*pl, st, &B);
   if (rc) return rc;
   int32_t info[11] = {0};
+  Prof prof(st);
 
   // ---- scalars: min, max, range, eps, exponents ----
   k_init_fp<<<1, 1, 0, st>>>(B.fp, B.flags, 8);
   k_minmax<<<grid_for(N), 256, 0, st>>>(x, (int)N, B.fp);
   k_params<<<1, 1, 0, st>>>(B.fp, pp->err_bound, (int)pp->bound_mode);
   HIPCHK(hipGetLastError());
+  prof.mark(S_SCALARS);
   FieldParams fp;
   if ((rc = d2h(&fp, B.fp, 1, st))) return rc;
   if (fp.mode < 0) return fail(EBCC_EINVAL, "input contains non-finite values");
@@ -582,22 +638,28 @@ static int compress_impl(const float* x, size_t ny_, size_t nx_, const ebcc_para
 
   // ---- base layer: DWT of the normalised field, tier-1, PCRD at ratio r ----
   dwt_forward(x, B.coef, B.tmp, ny, nx, L, PRO_NORM, io, st);
+  prof.mark(S_DWT);
   quant_planes(B.coef, nx, pl->d_blks, pl->nblk, e0, pl->cbw, pl->cbh, B.planes, B.signs, B.pb, st);
+  prof.mark(S_QUANT);
   t1_encode(B.coef, nx, pl->d_blks, pl->nblk, e0, pl->cbw, pl->cbh, B.planes, B.signs, B.pb, B.cw, B.R, B.D, B.bpt,
             B.tail, B.sppf, st);
+  prof.mark(S_T1ENC);
   int64_t total_budget = (int64_t)std::floor((double)(4.0 * (double)N) / pp->base_ratio);
   int64_t budget = total_budget - kHdr - 4 * (int64_t)pl->nblk;
   if (budget < 0) budget = 0;
   pcrd(B.pb, B.R, B.D, pl->nblk, budget, B.kb, B.hk, B.keys, B.dr, B.nh, B.len, st);
+  prof.mark(S_PCRD);
   // ---- A_base = dec_base(e_base) (closed form), residual, its DWT ----
   virtual_decode(B.coef, nx, pl->d_blks, pl->nblk, e0, pl->cbw, pl->cbh, B.pb, B.kb, B.sppf, B.yhat, st);
   dwt_inverse(B.yhat, B.tmp, B.abase, ny, nx, L, EPI_STORE, io, st);
   pointwise(nullptr, nullptr, (int)N, 3, EPI_CHECK, io, st);   // does the base alone meet the bound?
+  prof.mark(S_BASEREC);
   dwt_forward(x, B.cres, B.tmp, ny, nx, L, PRO_NORM_MINUS, io, st);
   int er = elog - 6;
   k_zero_int<<<1, 64, 0, st>>>((int*)B.u32s, 8);
   k_quant_res<<<grid_for(N), 256, 0, st>>>(B.cres, (int)N, er, B.qr, &B.u32s[0]);
   HIPCHK(hipGetLastError());
+  prof.mark(S_RESID);
   int hflag[2];
   unsigned qmax;
   if ((rc = d2h(hflag, B.flags, 1, st))) return rc;
@@ -644,11 +706,13 @@ static int compress_impl(const float* x, size_t ny_, size_t nx_, const ebcc_para
     }
     if (!found) mode = MODE_RAW;
   }
+  prof.mark(S_SEARCH);
   if (mode == MODE_CODED && resid) {
     spiht_maxima(B.qr, nx, pl->d_bands, pl->bands.data(), pl->nb, L, B.sub, B.maxd, B.maxl, st);
     spiht_encode(B.qr, B.sub, B.maxd, B.maxl, nx, pl->d_bands, pl->nb, L, pl->d_tiles, pl->ntiles, ns, B.lists,
                  B.slots, pl->d_slot_off, B.tlen, B.tent, st);
   }
+  prof.mark(S_SPIHT);
   // ---- sizes ----
   k_block_entries<<<grid_for(pl->nblk), 256, 0, st>>>(B.pb, B.kb, B.len, pl->nblk, B.bent);
   k_scan<<<1, 1024, 0, st>>>(B.bent, pl->nblk, 16, 0xFFFFu, B.boff, &B.totals[0]);
@@ -684,6 +748,7 @@ static int compress_impl(const float* x, size_t ny_, size_t nx_, const ebcc_para
   k_header<<<1, 1, 0, st>>>(out, B.fp, MODE_CODED, L, cbl, ny, nx, er_out, nmax, ns, T, (uint32_t)base_bytes,
                             (uint32_t)resid_bytes, &B.u32s[1]);
   HIPCHK(hipGetLastError());
+  prof.mark(S_PACK);
   if (tr) {
     if (tr->coef) HIPCHK(hipMemcpyAsync(tr->coef, B.coef, 4 * N, hipMemcpyDeviceToDevice, st));
     if (tr->abase) HIPCHK(hipMemcpyAsync(tr->abase, B.abase, 4 * N, hipMemcpyDeviceToDevice, st));
@@ -732,6 +797,7 @@ static int decompress_impl(const uint8_t* in, size_t in_len, float* x, size_t ny
   if (rc) return rc;
   Bufs B;
   if ((rc = get_ws(*pl, st, &B))) return rc;
+  Prof prof(st);
   k_set_decode_params<<<1, 1, 0, st>>>(B.fp, xmin, range_f, B.flags, 8);
   k_zero_int<<<1, 64, 0, st>>>((int*)B.u32s, 8);
   k_checksum<<<grid_for((in_len + 3) / 4), 256, 0, st>>>(in, nullptr, (int64_t)in_len, &B.u32s[1]);
@@ -746,10 +812,13 @@ static int decompress_impl(const uint8_t* in, size_t in_len, float* x, size_t ny
     k_read_table<<<grid_for(pl->nblk), 256, 0, st>>>(bsec, pl->nblk, B.bent);
     k_scan<<<1, 1024, 0, st>>>(B.bent, pl->nblk, 16, 0xFFFFu, B.boff, &B.totals[0]);
     k_check_tables<<<1, 64, 0, st>>>(bsec, pl->nblk, (int64_t)bb, &B.totals[0], &B.flags[1]);
+    prof.mark(S_D_PARSE);
     t1_decode(bsec + 4 * (size_t)pl->nblk, (int64_t)bb - 4 * (int64_t)pl->nblk, B.bent, B.boff, nx, pl->d_blks,
               pl->nblk, e0, pl->cbw, pl->cbh, B.yhat, &B.flags[1], st);
+    prof.mark(S_D_T1);
     if (rb) {
       dwt_inverse(B.yhat, B.tmp, B.abase, ny, nx, L, EPI_STORE, io, st);
+      prof.mark(S_D_IDWT_BASE);
       if ((int64_t)rb < 4 * (int64_t)pl->ntiles) return fail(EBCC_ECORRUPT, "residual section shorter than its table");
       const uint8_t* rsec = bsec + bb;
       k_read_table<<<grid_for(pl->ntiles), 256, 0, st>>>(rsec, pl->ntiles, B.tent);
@@ -759,10 +828,14 @@ static int decompress_impl(const uint8_t* in, size_t in_len, float* x, size_t ny
       // payload offsets relative to the residual section start
       spiht_decode(rsec, (int64_t)rb, B.toff, nx, pl->d_bands, pl->nb, L, pl->d_tiles, pl->ntiles, ns, er, B.lists,
                    B.qr, B.chat, &B.flags[1], st);
+      prof.mark(S_D_SPIHT);
       dwt_inverse(B.chat, B.tmp, nullptr, ny, nx, L, EPI_FINAL, io, st);
+      prof.mark(S_D_FINAL);
     } else {
       dwt_inverse(B.yhat, B.tmp, B.abase, ny, nx, L, EPI_STORE, io, st);
+      prof.mark(S_D_IDWT_BASE);
       pointwise(nullptr, nullptr, (int)N, 3, EPI_FINAL, io, st);
+      prof.mark(S_D_FINAL);
     }
   }
   HIPCHK(hipGetLastError());
@@ -845,5 +918,22 @@ const char* ebcc_status_str(int s) {
 }
 
 const char* ebcc_last_error(void) { return g_err.c_str(); }
+
+void ebcc_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof = on ? 1 : 0;
+  for (int i = 0; i < S_COUNT; i++) { g_stage_ms[i] = 0.0; g_stage_calls[i] = 0; }
+}
+
+int ebcc_profile_read(double* ms, long* calls, int n) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int i = 0; i < n && i < S_COUNT; i++) {
+    if (ms) ms[i] = g_stage_ms[i];
+    if (calls) calls[i] = g_stage_calls[i];
+  }
+  return S_COUNT;
+}
+
+const char* ebcc_profile_stage_name(int i) { return (i >= 0 && i < S_COUNT) ? kStageNames[i] : ""; }
 
 }  // extern "C"

@@ -19,7 +19,8 @@ MODE_CONST, MODE_RAW, MODE_CODED = 0, 1, 2
 HDR_BYTES = 48
 
 SYMBOLS = ("ebcc_params_default", "ebcc_compress_bound", "ebcc_compress", "ebcc_decompress", "ebcc_stream_info",
-           "ebcc_release", "ebcc_status_str", "ebcc_last_error", "ebcc_compress_trace")
+           "ebcc_release", "ebcc_status_str", "ebcc_last_error", "ebcc_compress_trace", "ebcc_profile_enable",
+           "ebcc_profile_read", "ebcc_profile_stage_name")
 
 
 class Params(C.Structure):
@@ -59,6 +60,11 @@ def lib():
         L.ebcc_status_str.restype = C.c_char_p
         L.ebcc_last_error.argtypes = []
         L.ebcc_last_error.restype = C.c_char_p
+        L.ebcc_profile_enable.argtypes = [C.c_int]
+        L.ebcc_profile_enable.restype = None
+        L.ebcc_profile_read.argtypes = [P, P, C.c_int]
+        L.ebcc_profile_stage_name.argtypes = [C.c_int]
+        L.ebcc_profile_stage_name.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -167,3 +173,17 @@ def stream_info(header_bytes):
 
 def release():
     lib().ebcc_release()
+
+
+def profile_enable(on=True):
+    lib().ebcc_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """{stage name: (total device ms, occurrences)} since profile_enable."""
+    L = lib()
+    n = L.ebcc_profile_read(None, None, 0)
+    ms = (C.c_double * n)()
+    calls = (C.c_long * n)()
+    L.ebcc_profile_read(ms, calls, n)
+    return {L.ebcc_profile_stage_name(i).decode(): (ms[i], calls[i]) for i in range(n)}
