@@ -102,6 +102,14 @@ void spiht_maxima(const uint32_t* qr, int nx, const Band* bands_dev, const Band*
   k_maxima<<<g, 256, 0, st>>>(qr, nx, bands_dev, L, 0, sub, maxd, maxl);
 }
 
+// Tiles per wavefront: one per wavefront for a lone field (latency), up to
+// 64 for large batches (throughput).
+static int pick_tile_lanes(int items) {
+  int l = 1;
+  while (l < 64 && items / l > 8192) l *= 4;
+  return l;
+}
+
 struct BitW {
   uint8_t* out;
   int64_t pos, cap;
@@ -124,7 +132,8 @@ struct BitW {
   }
 };
 
-__global__ __launch_bounds__(64) void k_spiht_encode(const uint32_t* __restrict__ qr, const uint32_t* __restrict__ sub,
+template <int LANES>
+__global__ __launch_bounds__(LANES) void k_spiht_encode(const uint32_t* __restrict__ qr, const uint32_t* __restrict__ sub,
                                                      const uint32_t* __restrict__ maxd, const uint32_t* __restrict__ maxl,
                                                      int nx, const Band* __restrict__ bands_g, int nb, int L,
                                                      const TileD* __restrict__ tiles, int ntiles, int n_s,
@@ -132,9 +141,9 @@ __global__ __launch_bounds__(64) void k_spiht_encode(const uint32_t* __restrict_
                                                      const int64_t* __restrict__ slot_off, uint32_t* __restrict__ tlen,
                                                      uint32_t* __restrict__ tent) {
   __shared__ Band B[kMaxBands];
-  for (int i = threadIdx.x; i < nb; i += 64) B[i] = bands_g[i];
+  for (int i = threadIdx.x; i < nb; i += LANES) B[i] = bands_g[i];
   __syncthreads();
-  int t = blockIdx.x * 64 + threadIdx.x;
+  int t = blockIdx.x * LANES + threadIdx.x;
   if (t >= ntiles) return;
   TileD td = tiles[t];
   uint32_t mx = 0;
@@ -219,8 +228,12 @@ void spiht_encode(const uint32_t* qr, const uint32_t* sub, const uint32_t* maxd,
                   const Band* bands, int nb, int L, const TileD* tiles, int ntiles, int n_s, uint64_t* lists,
                   uint8_t* slots, const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st) {
   if (ntiles <= 0) return;
-  k_spiht_encode<<<(ntiles + 63) / 64, 64, 0, st>>>(qr, sub, maxd, maxl, nx, bands, nb, L, tiles, ntiles, n_s,
-                                                    lists, slots, slot_off, tlen, tent);
+  int ln = pick_tile_lanes(ntiles);
+#define ENC_L(LN) k_spiht_encode<LN><<<(ntiles + LN - 1) / LN, LN, 0, st>>>(qr, sub, maxd, maxl, nx, bands, nb, L, \
+                                                                        tiles, ntiles, n_s, lists, slots, slot_off, \
+                                                                        tlen, tent)
+  if (ln == 1) ENC_L(1); else if (ln == 4) ENC_L(4); else if (ln == 16) ENC_L(16); else ENC_L(64);
+#undef ENC_L
 }
 
 struct BitR {
@@ -236,16 +249,17 @@ struct BitR {
 
 // sec: residual section (tile table then payloads); toff[t]: offset of tile
 // t's payload after the table.  mags: N-sized scratch (magnitude | sign << 31).
-__global__ __launch_bounds__(64) void k_spiht_decode(const uint8_t* __restrict__ sec, int64_t sec_len,
+template <int LANES>
+__global__ __launch_bounds__(LANES) void k_spiht_decode(const uint8_t* __restrict__ sec, int64_t sec_len,
                                                      const int64_t* __restrict__ toff, int nx,
                                                      const Band* __restrict__ bands_g, int nb, int L,
                                                      const TileD* __restrict__ tiles, int ntiles, int n_s, int e_r,
                                                      uint64_t* __restrict__ lists, uint32_t* __restrict__ mags,
                                                      float* __restrict__ chat, int* __restrict__ flag) {
   __shared__ Band B[kMaxBands];
-  for (int i = threadIdx.x; i < nb; i += 64) B[i] = bands_g[i];
+  for (int i = threadIdx.x; i < nb; i += LANES) B[i] = bands_g[i];
   __syncthreads();
-  int t = blockIdx.x * 64 + threadIdx.x;
+  int t = blockIdx.x * LANES + threadIdx.x;
   if (t >= ntiles) return;
   TileD td = tiles[t];
   uint32_t ent = (uint32_t)sec[4 * t] | ((uint32_t)sec[4 * t + 1] << 8) | ((uint32_t)sec[4 * t + 2] << 16) |
@@ -324,8 +338,12 @@ void spiht_decode(const uint8_t* sec, int64_t sec_len, const int64_t* toff, int 
                   const TileD* tiles, int ntiles, int n_s, int e_r, uint64_t* lists, uint32_t* mags, float* chat,
                   int* flag, hipStream_t st) {
   if (ntiles <= 0) return;
-  k_spiht_decode<<<(ntiles + 63) / 64, 64, 0, st>>>(sec, sec_len, toff, nx, bands, nb, L, tiles, ntiles, n_s, e_r,
-                                                    lists, mags, chat, flag);
+  int ln = pick_tile_lanes(ntiles);
+#define DEC_L(LN) k_spiht_decode<LN><<<(ntiles + LN - 1) / LN, LN, 0, st>>>(sec, sec_len, toff, nx, bands, nb, L, \
+                                                                        tiles, ntiles, n_s, e_r, lists, mags, chat, \
+                                                                        flag)
+  if (ln == 1) DEC_L(1); else if (ln == 4) DEC_L(4); else if (ln == 16) DEC_L(16); else DEC_L(64);
+#undef DEC_L
 }
 
 }  // namespace ebcc

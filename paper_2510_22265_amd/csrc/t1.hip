@@ -176,9 +176,9 @@ __device__ __forceinline__ void mq_renorm(MQEnc& e) {
   }
 }
 // cs: context state (index | MPS << 7)
-__device__ __forceinline__ void mq_encode(MQEnc& e, uint8_t* cs_ptr, int d) {
+__device__ __forceinline__ void mq_encode(MQEnc& e, uint8_t* cs_ptr, int d, const uint32_t* tab) {
   uint32_t cs = *cs_ptr;
-  uint32_t ent = c_mqt[cs & 0x7f];
+  uint32_t ent = tab[cs & 0x7f];
   uint32_t qe = ent & 0xFFFF;
   uint32_t mps = cs >> 7;
   e.A -= qe;
@@ -246,6 +246,7 @@ template <typename M, int ROWS, int LANES>
 struct T1Shared {
   M sig[ROWS][LANES], vis[ROWS][LANES], ref[ROWS][LANES], neg[ROWS][LANES], mag[ROWS][LANES], aux[ROWS][LANES];
   uint8_t ctx[kNCtx][LANES];
+  uint32_t mqt[47];
 };
 
 template <typename M, int ROWS, int LANES>
@@ -305,6 +306,8 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ c
                                                      uint32_t* __restrict__ tailt, M* __restrict__ sppf) {
   __shared__ T1Shared<M, ROWS, LANES> S;
   int lane = threadIdx.x;
+  for (int i = lane; i < 47; i += LANES) S.mqt[i] = c_mqt[i];
+  __syncthreads();
   int b = blockIdx.x * LANES + lane;
   if (b >= nblk) return;
   Blk k = blk[b];
@@ -331,10 +334,11 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ c
   const int sh = k.gain - e0;
   const float* cb = coef + (size_t)k.y0 * nx + k.x0;
   auto qat = [&](int y, int x) { return quantq(cb[y * nx + x], sh); };
+  auto mq_enc = [&](uint8_t* cs, int bit) { mq_encode(e, cs, bit, S.mqt); };
   auto code_sign = [&](int y, int x) {
     int xr;
     int cx = T.sign_ctx(y, x, &xr);
-    mq_encode(e, &S.ctx[cx][lane], bt(S.neg[y][lane], x) ^ xr);
+    mq_enc(&S.ctx[cx][lane], bt(S.neg[y][lane], x) ^ xr);
   };
   int npass = 3 * P - 2, kk = 0;
   bool stop = false;
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ c
               T.counts(y, x, H, V, D);
               if (H + V + D == 0) continue;
               int bit = bt(S.mag[y][lane], x);
-              mq_encode(e, &S.ctx[zc_ctx(k.orient, H, V, D)][lane], bit);
+              mq_enc(&S.ctx[zc_ctx(k.orient, H, V, D)][lane], bit);
               S.vis[y][lane] |= (M)1 << x;
               if (bit) {
                 code_sign(y, x);
@@ -383,7 +387,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ c
               int cx;
               if (bt(S.ref[y][lane], x)) cx = CX_MR + 2;
               else { int H, V, D; T.counts(y, x, H, V, D); cx = (H + V + D) ? CX_MR + 1 : CX_MR; }
-              mq_encode(e, &S.ctx[cx][lane], bt(S.mag[y][lane], x));
+              mq_enc(&S.ctx[cx][lane], bt(S.mag[y][lane], x));
               S.ref[y][lane] |= (M)1 << x;
               dd += ref_delta(qat(y, x), p);
             }
@@ -401,10 +405,10 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ c
               int rr = -1;
               for (int t = 0; t < 4; t++)
                 if (bt(S.mag[y0 + t][lane], x)) { rr = t; break; }
-              mq_encode(e, &S.ctx[CX_RL][lane], rr >= 0);
+              mq_enc(&S.ctx[CX_RL][lane], rr >= 0);
               if (rr < 0) continue;
-              mq_encode(e, &S.ctx[CX_UNI][lane], (rr >> 1) & 1);
-              mq_encode(e, &S.ctx[CX_UNI][lane], rr & 1);
+              mq_enc(&S.ctx[CX_UNI][lane], (rr >> 1) & 1);
+              mq_enc(&S.ctx[CX_UNI][lane], rr & 1);
               int y = y0 + rr;
               code_sign(y, x);
               S.sig[y][lane] |= (M)1 << x;
@@ -417,7 +421,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ c
               int H, V, D;
               T.counts(y, x, H, V, D);
               int bit = bt(S.mag[y][lane], x);
-              mq_encode(e, &S.ctx[zc_ctx(k.orient, H, V, D)][lane], bit);
+              mq_enc(&S.ctx[zc_ctx(k.orient, H, V, D)][lane], bit);
               if (bit) {
                 code_sign(y, x);
                 S.sig[y][lane] |= (M)1 << x;
@@ -483,23 +487,32 @@ __global__ __launch_bounds__(256) void k_virtual_decode(const float* __restrict_
 // ------------------------------------------------------------------------
 // MQ decoder (bytes past the codeword read as 0xFF).
 // ------------------------------------------------------------------------
+// The byte at BP (cur) and the one after it (nxt) are held in registers; the
+// load of the following byte is issued as soon as BP advances.
 struct MQDec {
-  uint32_t C, A;
+  uint32_t C, A, cur, nxt;
   int CT, BP, len;
   const uint8_t* buf;
 };
 __device__ __forceinline__ uint32_t mq_rd(const MQDec& d, int i) { return (i >= 0 && i < d.len) ? d.buf[i] : 0xFFu; }
+__device__ __forceinline__ void mq_adv(MQDec& d) {
+  d.BP++;
+  d.cur = d.nxt;
+  d.nxt = mq_rd(d, d.BP + 1);
+}
 __device__ __forceinline__ void mq_bytein(MQDec& d) {
-  if (mq_rd(d, d.BP) == 0xFF) {
-    if (mq_rd(d, d.BP + 1) > 0x8F) { d.C += 0xFF00; d.CT = 8; }
-    else { d.BP++; d.C += mq_rd(d, d.BP) << 9; d.CT = 7; }
+  if (d.cur == 0xFF) {
+    if (d.nxt > 0x8F) { d.C += 0xFF00; d.CT = 8; }
+    else { mq_adv(d); d.C += d.cur << 9; d.CT = 7; }
   } else {
-    d.BP++; d.C += mq_rd(d, d.BP) << 8; d.CT = 8;
+    mq_adv(d); d.C += d.cur << 8; d.CT = 8;
   }
 }
 __device__ __forceinline__ void mq_dinit(MQDec& d, const uint8_t* buf, int len) {
   d.buf = buf; d.len = len; d.BP = 0;
-  d.C = mq_rd(d, 0) << 16;
+  d.cur = mq_rd(d, 0);
+  d.nxt = mq_rd(d, 1);
+  d.C = d.cur << 16;
   mq_bytein(d);
   d.C <<= 7; d.CT -= 7; d.A = 0x8000;
 }
@@ -509,9 +522,9 @@ __device__ __forceinline__ void mq_renormd(MQDec& d) {
     d.A <<= 1; d.C <<= 1; d.CT--;
   } while ((d.A & 0x8000) == 0);
 }
-__device__ __forceinline__ int mq_decode(MQDec& d, uint8_t* cs_ptr) {
+__device__ __forceinline__ int mq_decode(MQDec& d, uint8_t* cs_ptr, const uint32_t* tab) {
   uint32_t cs = *cs_ptr;
-  uint32_t ent = c_mqt[cs & 0x7f];
+  uint32_t ent = tab[cs & 0x7f];
   uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
   uint32_t nm = (ent >> 16) & 0x3f, nl = (ent >> 22) & 0x3f, sw = ent >> 28;
   int D;
@@ -550,6 +563,8 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__
                                                      float* __restrict__ yhat, int* __restrict__ flag) {
   __shared__ T1Shared<M, ROWS, LANES> S;     // aux = coded in the current plane
   int lane = threadIdx.x;
+  for (int i = lane; i < 47; i += LANES) S.mqt[i] = c_mqt[i];
+  __syncthreads();
   int b = blockIdx.x * LANES + lane;
   if (b >= nblk) return;
   Blk k = blk[b];
@@ -573,10 +588,11 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__
   S.ctx[0][lane] = 4; S.ctx[CX_RL][lane] = 3; S.ctx[CX_UNI][lane] = 46;
   MQDec d;
   mq_dinit(d, sec + o, len);
+  auto mq_dec = [&](uint8_t* cs) { return mq_decode(d, cs, S.mqt); };
   auto dec_sign = [&](int y, int x) {
     int xr;
     int cx = T.sign_ctx(y, x, &xr);
-    int s = mq_decode(d, &S.ctx[cx][lane]) ^ xr;
+    int s = mq_dec(&S.ctx[cx][lane]) ^ xr;
     if (s) S.neg[y][lane] |= (M)1 << x;
   };
   int done = 0, plast = P - 1;
@@ -599,7 +615,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__
               int H, V, D;
               T.counts(y, x, H, V, D);
               if (H + V + D == 0) continue;
-              int bit = mq_decode(d, &S.ctx[zc_ctx(k.orient, H, V, D)][lane]);
+              int bit = mq_dec(&S.ctx[zc_ctx(k.orient, H, V, D)][lane]);
               S.vis[y][lane] |= (M)1 << x;
               if (bit) {
                 dec_sign(y, x);
@@ -622,7 +638,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__
               int cx;
               if (bt(S.ref[y][lane], x)) cx = CX_MR + 2;
               else { int H, V, D; T.counts(y, x, H, V, D); cx = (H + V + D) ? CX_MR + 1 : CX_MR; }
-              int bit = mq_decode(d, &S.ctx[cx][lane]);
+              int bit = mq_dec(&S.ctx[cx][lane]);
               if (bit) mb[y * nx + x] |= 1u << p;
               S.ref[y][lane] |= (M)1 << x;
               S.aux[y][lane] |= (M)1 << x;
@@ -638,9 +654,9 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__
             u &= u - 1;
             int r = 0;
             if (rn == 4 && T.run_ok(y0, x)) {
-              if (!mq_decode(d, &S.ctx[CX_RL][lane])) continue;
-              int b1 = mq_decode(d, &S.ctx[CX_UNI][lane]);
-              int b0 = mq_decode(d, &S.ctx[CX_UNI][lane]);
+              if (!mq_dec(&S.ctx[CX_RL][lane])) continue;
+              int b1 = mq_dec(&S.ctx[CX_UNI][lane]);
+              int b0 = mq_dec(&S.ctx[CX_UNI][lane]);
               int rr = 2 * b1 + b0;
               int y = y0 + rr;
               dec_sign(y, x);
@@ -654,7 +670,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__
               if (bt(S.sig[y][lane] | S.vis[y][lane], x)) continue;
               int H, V, D;
               T.counts(y, x, H, V, D);
-              int bit = mq_decode(d, &S.ctx[zc_ctx(k.orient, H, V, D)][lane]);
+              int bit = mq_dec(&S.ctx[zc_ctx(k.orient, H, V, D)][lane]);
               if (bit) {
                 dec_sign(y, x);
                 S.sig[y][lane] |= (M)1 << x;
@@ -685,20 +701,64 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__
 }
 
 // ------------------------------------------------------------------------
-// Launchers: mask width follows the code-block width, LDS rows its height.
+// Launchers: mask width follows the code-block width, LDS rows its height,
+// and the blocks per wavefront (lanes) the amount of work: a lone field's
+// blocks are spread one per wavefront (no divergence, the whole chip busy),
+// large batches pack up to 64 blocks per wavefront for throughput.
 // ------------------------------------------------------------------------
+static int pick_lanes(int items, int lanes_max) {
+  const int resident = 8192;   // wavefronts the chip keeps in flight comfortably
+  int l = 1;
+  while (l < lanes_max && items / l > resident) l *= 4;
+  return l > lanes_max ? lanes_max : l;
+}
+template <typename M, int ROWS>
+constexpr int t1_lanes_max() {
+  return (6 * ROWS * (int)sizeof(M) * 64 <= 49152) ? 64 : (6 * ROWS * (int)sizeof(M) * 16 <= 49152 ? 16 : 4);
+}
+
 #define T1_DISPATCH(CBW, CBH, MACRO)                               \
   do {                                                             \
     if ((CBW) <= 32) {                                             \
-      if ((CBH) <= 16) MACRO(uint32_t, 16, 64);                    \
-      else if ((CBH) <= 32) MACRO(uint32_t, 32, 64);               \
-      else MACRO(uint32_t, 64, 32);                                \
+      if ((CBH) <= 16) MACRO(uint32_t, 16);                        \
+      else if ((CBH) <= 32) MACRO(uint32_t, 32);                   \
+      else MACRO(uint32_t, 64);                                    \
     } else {                                                       \
-      if ((CBH) <= 16) MACRO(uint64_t, 16, 64);                    \
-      else if ((CBH) <= 32) MACRO(uint64_t, 32, 32);               \
-      else MACRO(uint64_t, 64, 16);                                \
+      if ((CBH) <= 16) MACRO(uint64_t, 16);                        \
+      else if ((CBH) <= 32) MACRO(uint64_t, 32);                   \
+      else MACRO(uint64_t, 64);                                    \
     }                                                              \
   } while (0)
+
+template <typename M, int ROWS>
+static void launch_encode(int nblk, const float* coef, int nx, const Blk* blk, int e0, int cbh, const void* planes,
+                          const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
+                          uint32_t* tail, void* sppf, hipStream_t st) {
+  constexpr int LM = t1_lanes_max<M, ROWS>();
+  int ln = pick_lanes(nblk, LM);
+#define ENC_L(LN)                                                                                                    \
+  k_t1_encode<M, ROWS, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(coef, nx, blk, nblk, e0, cbh, (const M*)planes,       \
+                                                               (const M*)signs, pb, cw, R, D, bp, tail, (M*)sppf)
+  if (ln == 1) ENC_L(1);
+  else if (ln == 4) ENC_L(4);
+  else if (ln == 16 || LM == 16) ENC_L((LM >= 16 ? 16 : 4));
+  else ENC_L((LM >= 64 ? 64 : 4));
+#undef ENC_L
+}
+
+template <typename M, int ROWS>
+static void launch_decode(int nblk, const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off,
+                          int nx, const Blk* blk, int e0, float* yhat, int* flag, hipStream_t st) {
+  constexpr int LM = t1_lanes_max<M, ROWS>();
+  int ln = pick_lanes(nblk, LM);
+#define DEC_L(LN) \
+  k_t1_decode<M, ROWS, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(sec, sec_len, table, off, nx, blk, nblk, e0, yhat, flag)
+  if (ln == 1) DEC_L(1);
+  else if (ln == 4) DEC_L(4);
+  else if (ln == 16 || LM == 16) DEC_L((LM >= 16 ? 16 : 4));
+  else DEC_L((LM >= 64 ? 64 : 4));
+#undef DEC_L
+}
 
 void quant_planes(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, void* planes,
                   void* signs, uint8_t* pb, hipStream_t st) {
@@ -716,10 +776,7 @@ void t1_encode(const float* coef, int nx, const Blk* blk, int nblk, int e0, int 
                const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
                uint32_t* tail, void* sppf, hipStream_t st) {
   if (nblk <= 0) return;
-#define ENC(MT, RW, LN)                                                                                        \
-  k_t1_encode<MT, RW, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(coef, nx, blk, nblk, e0, cbh, (const MT*)planes, \
-                                                               (const MT*)signs, pb, cw, R, D, bp, tail,       \
-                                                               (MT*)sppf)
+#define ENC(MT, RW) launch_encode<MT, RW>(nblk, coef, nx, blk, e0, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st)
   T1_DISPATCH(cbw, cbh, ENC);
 #undef ENC
 }
@@ -737,8 +794,7 @@ void virtual_decode(const float* coef, int nx, const Blk* blk, int nblk, int e0,
 void t1_decode(const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off, int nx, const Blk* blk,
                int nblk, int e0, int cbw, int cbh, float* yhat, int* flag, hipStream_t st) {
   if (nblk <= 0) return;
-#define DEC(MT, RW, LN) \
-  k_t1_decode<MT, RW, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(sec, sec_len, table, off, nx, blk, nblk, e0, yhat, flag)
+#define DEC(MT, RW) launch_decode<MT, RW>(nblk, sec, sec_len, table, off, nx, blk, e0, yhat, flag, st)
   T1_DISPATCH(cbw, cbh, DEC);
 #undef DEC
 }
