@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libebcc.so")
-SOURCES = ["dwt.hip", "t1.hip", "pcrd.hip", "spiht.hip", "codec.hip"]
+SOURCES = ["dwt.hip", "t1.hip", "t1wave.hip", "pcrd.hip", "spiht.hip", "spihtwave.hip", "codec.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Bit-exactness with the CPU reference needs IEEE FP32 without contraction,

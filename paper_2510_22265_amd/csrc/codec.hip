@@ -9,6 +9,7 @@
 #include "ebcc.h"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -348,6 +349,8 @@ struct Plan {
   TileD* d_tiles = nullptr;
   int64_t* d_slot_off = nullptr;
   int nblk = 0, ntiles = 0, nb = 0;
+  int max_tile_coef = 0, max_tile_parents = 0;
+  int spiht_cap = 0;   // LDS capacity class of the per-tile SPIHT kernels (0: global-memory kernels)
   ~Plan() {
     if (d_bands) (void)hipFree(d_bands);
     if (d_blks) (void)hipFree(d_blks);
@@ -393,14 +396,14 @@ static int build_plan(Plan& p) {
       TileD t;
       t.i0 = a * T; t.i1 = std::min(hL, t.i0 + T);
       t.j0 = c * T; t.j1 = std::min(wL, t.j0 + T);
-      int64_t n = (int64_t)(t.i1 - t.i0) * (t.j1 - t.j0);
+      int64_t n = (int64_t)(t.i1 - t.i0) * (t.j1 - t.j0), n1 = 0;
       for (int o = 0; o < 3 && L > 0; o++) {
         const Band& top = p.bands[1 + o];
         int r0 = t.i0, r1 = std::min(t.i1, top.h), c0 = t.j0, c1 = std::min(t.j1, top.w);
         for (int l = L;; l--) {
           if (r0 >= r1 || c0 >= c1) break;
           n += (int64_t)(r1 - r0) * (c1 - c0);
-          if (l == 1) break;
+          if (l == 1) { n1 += (int64_t)(r1 - r0) * (c1 - c0); break; }
           const Band& pb = p.bands[1 + 3 * (L - l) + o];
           const Band& cb = p.bands[1 + 3 * (L - l + 1) + o];
           int nr0 = 2 * r0, nr1 = (r1 == pb.h) ? cb.h : std::min(2 * r1, cb.h);
@@ -410,6 +413,8 @@ static int build_plan(Plan& p) {
       }
       t.off = off;
       t.ncoef = (int)n;
+      p.max_tile_coef = std::max(p.max_tile_coef, (int)n);
+      p.max_tile_parents = std::max(p.max_tile_parents, (int)(L > 0 ? n - n1 : 0));
       t.pad = 0;
       off += n;
       soff += 12 * n + 16;
@@ -417,6 +422,7 @@ static int build_plan(Plan& p) {
       p.slot_off.push_back(soff);
     }
   p.ntiles = (int)p.tiles.size();
+  p.spiht_cap = spiht_lds_cap(std::max(p.max_tile_coef, 2 * p.max_tile_parents));
   if (off != (int64_t)ny * nx) return fail(EBCC_EINVAL, "internal: SPIHT trees do not cover the field");
   HIPCHK(hipMalloc(&p.d_bands, sizeof(Band) * p.bands.size()));
   HIPCHK(hipMemcpy(p.d_bands, p.bands.data(), sizeof(Band) * p.bands.size(), hipMemcpyHostToDevice));
@@ -427,6 +433,14 @@ static int build_plan(Plan& p) {
   HIPCHK(hipMalloc(&p.d_slot_off, sizeof(int64_t) * p.slot_off.size()));
   HIPCHK(hipMemcpy(p.d_slot_off, p.slot_off.data(), sizeof(int64_t) * p.slot_off.size(), hipMemcpyHostToDevice));
   return EBCC_OK;
+}
+
+// SPIHT kernel family for a plan: LDS per tile when the tiles fit (the
+// environment variable EBCC_SPIHT_KERNEL=global forces the global-memory
+// kernels, for testing both families).
+static int spiht_cap_for(const Plan* p) {
+  const char* e = getenv("EBCC_SPIHT_KERNEL");
+  return (e && e[0] == 'g') ? 0 : p->spiht_cap;
 }
 
 static std::mutex g_mu;
@@ -485,6 +499,7 @@ struct Bufs {
   int64_t *D, *boff, *toff;
   uint64_t *keys, *lists;
   uint32_t *tail, *tlen, *tent, *bent;
+  int* misfit;
 };
 
 static size_t layout(const Plan& p, Bufs* b, char* base) {
@@ -511,6 +526,7 @@ static size_t layout(const Plan& p, Bufs* b, char* base) {
   b->boff = c.take<int64_t>(nb); b->bent = c.take<uint32_t>(nb);
   b->cw = c.take<uint8_t>(nb * (size_t)kCwCap);
   b->tlen = c.take<uint32_t>(nt); b->tent = c.take<uint32_t>(nt); b->toff = c.take<int64_t>(nt);
+  b->misfit = c.take<int>(nt);
   b->lists = c.take<uint64_t>(4 * N);
   b->slots = c.take<uint8_t>((size_t)p.slot_off.back());
   return c.used + 256;
@@ -709,8 +725,12 @@ static int compress_impl(const float* x, size_t ny_, size_t nx_, const ebcc_para
   prof.mark(S_SEARCH);
   if (mode == MODE_CODED && resid) {
     spiht_maxima(B.qr, nx, pl->d_bands, pl->bands.data(), pl->nb, L, B.sub, B.maxd, B.maxl, st);
-    spiht_encode(B.qr, B.sub, B.maxd, B.maxl, nx, pl->d_bands, pl->nb, L, pl->d_tiles, pl->ntiles, ns, B.lists,
-                 B.slots, pl->d_slot_off, B.tlen, B.tent, st);
+    if (spiht_cap_for(pl))
+      spiht_encode_lds(spiht_cap_for(pl), B.qr, B.sub, B.maxd, B.maxl, nx, pl->d_bands, pl->nb, L, pl->d_tiles,
+                       pl->ntiles, ns, B.slots, pl->d_slot_off, B.tlen, B.tent, B.misfit, st);
+    else
+      spiht_encode(B.qr, B.sub, B.maxd, B.maxl, nx, pl->d_bands, pl->nb, L, pl->d_tiles, pl->ntiles, ns, B.lists,
+                   B.slots, pl->d_slot_off, B.tlen, B.tent, st);
   }
   prof.mark(S_SPIHT);
   // ---- sizes ----
@@ -826,8 +846,12 @@ static int decompress_impl(const uint8_t* in, size_t in_len, float* x, size_t ny
       k_check_tables<<<1, 64, 0, st>>>(rsec, pl->ntiles, (int64_t)rb, &B.totals[1], &B.flags[1]);
       k_fill<<<grid_for(N), 256, 0, st>>>(B.chat, (int)N, 0.0f);
       // payload offsets relative to the residual section start
-      spiht_decode(rsec, (int64_t)rb, B.toff, nx, pl->d_bands, pl->nb, L, pl->d_tiles, pl->ntiles, ns, er, B.lists,
-                   B.qr, B.chat, &B.flags[1], st);
+      if (spiht_cap_for(pl))
+        spiht_decode_lds(spiht_cap_for(pl), rsec, (int64_t)rb, B.toff, nx, pl->d_bands, pl->nb, L, pl->d_tiles,
+                         pl->ntiles, ns, er, B.chat, &B.flags[1], B.misfit, st);
+      else
+        spiht_decode(rsec, (int64_t)rb, B.toff, nx, pl->d_bands, pl->nb, L, pl->d_tiles, pl->ntiles, ns, er,
+                     B.lists, B.qr, B.chat, &B.flags[1], st);
       prof.mark(S_D_SPIHT);
       dwt_inverse(B.chat, B.tmp, nullptr, ny, nx, L, EPI_FINAL, io, st);
       prof.mark(S_D_FINAL);

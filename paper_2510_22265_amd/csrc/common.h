@@ -98,6 +98,16 @@ void t1_decode(const uint8_t* sec, int64_t sec_len, const uint32_t* table, const
                int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, float* yhat, int* flag,
                hipStream_t st);
 
+// t1wave.hip: one wavefront per code-block (few blocks in flight)
+void t1_encode_wave(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh,
+                    const void* planes, const void* signs, const uint8_t* pb, uint8_t* cw,
+                    int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail, void* sppf, hipStream_t st);
+void t1_decode_wave(const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off,
+                    int nx, const Blk* blk, int nblk, int e0, int cbw, float* yhat, int* flag,
+                    hipStream_t st);
+// Tier-1 kernel choice: 0 = by work size, 1 = wave per block, 2 = lane per block.
+int t1_variant();
+
 // pcrd.hip
 void pcrd(const uint8_t* pb, const int32_t* R, const int64_t* D, int nblk, int64_t budget,
           uint8_t* kb, uint8_t* hk_scratch, uint64_t* key_scratch, int32_t* dr_scratch,
@@ -113,6 +123,16 @@ void spiht_maxima(const uint32_t* qr, int nx, const Band* bands_dev, const Band*
 void spiht_encode(const uint32_t* qr, const uint32_t* sub, const uint32_t* maxd, const uint32_t* maxl, int nx,
                   const Band* bands, int nb, int L, const TileD* tiles, int ntiles, int n_s, uint64_t* lists,
                   uint8_t* slots, const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st);
+// spihtwave.hip: one wavefront per tile with the tile in LDS.  spiht_lds_cap
+// gives the LDS capacity class for the largest tile (0 = does not fit).
+int spiht_lds_cap(int max_tile_coef);
+void spiht_encode_lds(int cap, const uint32_t* qr, const uint32_t* sub, const uint32_t* maxd, const uint32_t* maxl,
+                      int nx, const Band* bands, int nb, int L, const TileD* tiles, int ntiles, int n_s,
+                      uint8_t* slots, const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit,
+                      hipStream_t st);
+void spiht_decode_lds(int cap, const uint8_t* sec, int64_t sec_len, const int64_t* toff, int nx, const Band* bands,
+                      int nb, int L, const TileD* tiles, int ntiles, int n_s, int e_r, float* chat, int* flag,
+                      int* misfit, hipStream_t st);
 // Decode the residual section: `sec` starts at the tile table.  Uses `mags`
 // (ny*nx scratch) for the magnitude|sign of significant coefficients and
 // writes their dequantised values into chat (which must be zero elsewhere).

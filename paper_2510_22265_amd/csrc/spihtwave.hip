@@ -1,0 +1,568 @@
+// SPIHT (Said & Pearlman 1996) per tile with one wavefront per tile and the
+// tile's coefficients and lists in LDS.
+//
+// Encoder: every list pass is processed 64 entries at a time.  Each lane takes
+// one entry, computes the bits it emits and the entries it appends to each
+// list; wavefront prefix sums place the bits in the output and the appended
+// entries at the list tails, and removed entries are compacted in place.
+// Entries appended to the LIS tail are reached by later chunks of the same
+// pass, so the result is exactly the sequential algorithm's.
+//
+// Decoder: the bits decide what happens, so the LIS pass runs as
+// wave-uniform code; the LIP pass skips runs of zero bits (insignificant
+// entries) with one count-leading-zeros per run, and the refinement bits,
+// whose positions are known, are read by all lanes at once.
+//
+// Tile-local coordinates: the tile's trees cover one rectangle per band;
+// rectangles are numbered in band order, so a coefficient's local index is
+// the rectangle's offset plus its raster index inside it.  LL roots come
+// first, level-1 coefficients (which have no children) last.
+#include "common.h"
+
+namespace ebcc {
+
+constexpr int kSpihtBig = 4608;     // coefficients per tile the LDS kernels accept
+constexpr int kSpihtSmall = 1280;
+
+struct TileGeom {
+  int r0[kMaxBands], c0[kMaxBands], hr[kMaxBands], wr[kMaxBands], off[kMaxBands + 1];
+  int ncoef, nparents;
+};
+
+// Rectangles of the tile's trees (computed by lane 0).
+__device__ void tile_geom(TileGeom& g, const Band* B, int nb, int L, const TileD& td) {
+  g.r0[0] = td.i0; g.c0[0] = td.j0; g.hr[0] = td.i1 - td.i0; g.wr[0] = td.j1 - td.j0;
+  for (int o = 1; o <= 3 && L > 0; o++) {
+    int r1 = td.i1 < B[o].h ? td.i1 : B[o].h, c1 = td.j1 < B[o].w ? td.j1 : B[o].w;
+    g.r0[o] = td.i0; g.c0[o] = td.j0;
+    g.hr[o] = r1 > td.i0 ? r1 - td.i0 : 0;
+    g.wr[o] = c1 > td.j0 ? c1 - td.j0 : 0;
+  }
+  for (int b = 4; b < nb; b++) {
+    int pb = b - 3;
+    if (g.hr[pb] == 0 || g.wr[pb] == 0) { g.r0[b] = g.c0[b] = 0; g.hr[b] = g.wr[b] = 0; continue; }
+    int pr0 = g.r0[pb], pr1 = pr0 + g.hr[pb], pc0 = g.c0[pb], pc1 = pc0 + g.wr[pb];
+    int r0 = 2 * pr0, r1 = (pr1 == B[pb].h) ? B[b].h : (2 * pr1 < B[b].h ? 2 * pr1 : B[b].h);
+    int c0 = 2 * pc0, c1 = (pc1 == B[pb].w) ? B[b].w : (2 * pc1 < B[b].w ? 2 * pc1 : B[b].w);
+    g.r0[b] = r0; g.c0[b] = c0;
+    g.hr[b] = r1 > r0 ? r1 - r0 : 0;
+    g.wr[b] = c1 > c0 ? c1 - c0 : 0;
+  }
+  int o = 0;
+  for (int b = 0; b < nb; b++) { g.off[b] = o; o += g.hr[b] * g.wr[b]; }
+  g.off[nb] = o;
+  g.ncoef = o;
+  g.nparents = L >= 1 ? g.off[1 + 3 * (L - 1)] : 0;
+}
+
+__device__ __forceinline__ int band_of(const TileGeom& g, int nb, int local) {
+  int b = nb - 1;
+  while (b > 0 && local < g.off[b]) b--;
+  return b;
+}
+
+// Offspring (local indices, row-major) of the node with local index `loc`.
+__device__ __forceinline__ int offspring_local(const TileGeom& g, const Band* B, int nb, int L, int loc, int* ch,
+                                               int* clevel) {
+  int b = band_of(g, nb, loc);
+  int rel = loc - g.off[b];
+  int li = rel / g.wr[b], lj = rel - li * g.wr[b];
+  int i = g.r0[b] + li, j = g.c0[b] + lj;
+  int k = 0;
+  if (b == 0) {
+    *clevel = L;
+    if (L == 0) return 0;
+    for (int c = 1; c <= 3; c++)
+      if (i < B[c].h && j < B[c].w) ch[k++] = g.off[c] + (i - g.r0[c]) * g.wr[c] + (j - g.c0[c]);
+    return k;
+  }
+  *clevel = B[b].level - 1;
+  if (B[b].level == 1) return 0;
+  int cb = b + 3;
+  int r1 = (i == B[b].h - 1) ? B[cb].h : 2 * i + 2;
+  int c1 = (j == B[b].w - 1) ? B[cb].w : 2 * j + 2;
+  if (r1 > B[cb].h) r1 = B[cb].h;
+  if (c1 > B[cb].w) c1 = B[cb].w;
+  for (int r = 2 * i; r < r1; r++)
+    for (int c = 2 * j; c < c1; c++) ch[k++] = g.off[cb] + (r - g.r0[cb]) * g.wr[cb] + (c - g.c0[cb]);
+  return k;
+}
+
+__device__ __forceinline__ int wscan_excl(int v, int lane, int* total) {
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(x, o);
+    if (lane >= o) x += t;
+  }
+  *total = __shfl(x, 63);
+  return x - v;
+}
+
+// OR nb (<= 32) bits of v (MSB first) at bit offset rel of the window; the
+// window's words hold stream bits big-endian (bit 31 first).
+__device__ __forceinline__ void put_bits(uint32_t* bw, int rel, int nb, uint32_t v) {
+  if (nb <= 0) return;
+  int w = rel >> 5, b = rel & 31;
+  if (b + nb <= 32) {
+    atomicOr(&bw[w], v << (32 - b - nb));
+  } else {
+    int n1 = 32 - b, n2 = nb - n1;
+    atomicOr(&bw[w], v >> n2);
+    atomicOr(&bw[w + 1], v << (32 - n2));
+  }
+}
+__device__ __forceinline__ uint32_t bswap32(uint32_t v) {
+  return (v >> 24) | ((v >> 8) & 0xFF00u) | ((v << 8) & 0xFF0000u) | (v << 24);
+}
+__device__ __forceinline__ int blen(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
+
+template <int CAP>
+struct SpihtLds {
+  Band B[kMaxBands];
+  TileGeom g;
+  uint32_t qv[CAP];          // magnitude | sign << 31 (decoder: decoded magnitude)
+  uint8_t mdl[CAP / 2];      // bit length of the max over descendants
+  uint8_t mll[CAP / 2];      // bit length of the max over grand-descendants
+  uint16_t lip[CAP], lsp[CAP];
+  uint16_t lis[CAP];         // local index | typeB << 15
+  uint32_t bw[72];           // encoder output window (2048 bits + slack)
+  int ntop, ok;
+};
+
+// Load the tile's geometry and coefficients; returns false when it does not fit.
+template <int CAP>
+__device__ bool spiht_setup(SpihtLds<CAP>& S, const Band* bands_g, int nb, int L, const TileD& td, int lane) {
+  for (int i = lane; i < nb; i += 64) S.B[i] = bands_g[i];
+  __syncthreads();
+  if (lane == 0) {
+    tile_geom(S.g, S.B, nb, L, td);
+    S.ok = S.g.ncoef <= CAP && 2 * S.g.nparents <= CAP;
+  }
+  __syncthreads();
+  return S.ok;
+}
+
+template <int CAP>
+__global__ __launch_bounds__(64) void k_spiht_encode_lds(const uint32_t* __restrict__ qr, const uint32_t* __restrict__ sub,
+                                                         const uint32_t* __restrict__ maxd,
+                                                         const uint32_t* __restrict__ maxl, int nx,
+                                                         const Band* __restrict__ bands_g, int nb, int L,
+                                                         const TileD* __restrict__ tiles, int ntiles, int n_s,
+                                                         uint8_t* __restrict__ slots,
+                                                         const int64_t* __restrict__ slot_off,
+                                                         uint32_t* __restrict__ tlen, uint32_t* __restrict__ tent,
+                                                         int* __restrict__ misfit) {
+  __shared__ SpihtLds<CAP> S;
+  const int lane = threadIdx.x;
+  const int t = blockIdx.x;
+  const TileD td = tiles[t];
+  if (!spiht_setup<CAP>(S, bands_g, nb, L, td, lane)) {
+    if (lane == 0) misfit[t] = 1;
+    return;
+  }
+  if (lane == 0) misfit[t] = 0;
+  const TileGeom& g = S.g;
+  // coefficients and descendant maxima into LDS; the tile's top plane
+  uint32_t mx = 0;
+  for (int b = 0; b < nb; b++) {
+    int n = g.hr[b] * g.wr[b];
+    for (int r = lane; r < n; r += 64) {
+      int li = r / g.wr[b], lj = r - li * g.wr[b];
+      int p = (S.B[b].y0 + g.r0[b] + li) * nx + S.B[b].x0 + g.c0[b] + lj;
+      int loc = g.off[b] + r;
+      S.qv[loc] = qr[p];
+      if (loc < g.nparents) {
+        S.mdl[loc] = (uint8_t)blen(maxd[p]);
+        S.mll[loc] = (uint8_t)blen(maxl[p]);
+      }
+      if (b == 0) { uint32_t s = sub[p]; mx = s > mx ? s : mx; }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) { uint32_t v = __shfl_xor(mx, o); mx = v > mx ? v : mx; }
+  const int ntop = mx ? 31 - __builtin_clz(mx) : -1;
+  if (ntop < n_s) {
+    if (lane == 0) { tlen[t] = 0; tent[t] = 0; }
+    return;
+  }
+  // initial lists: LIP = roots, LIS = roots with offspring (type A)
+  const int nroots = g.hr[0] * g.wr[0];
+  int nlis = 0;
+  for (int r0 = 0; r0 < nroots; r0 += 64) {
+    int r = r0 + lane;
+    int ch[9], cl;
+    int has = 0;
+    if (r < nroots) {
+      S.lip[r] = (uint16_t)r;
+      has = offspring_local(g, S.B, nb, L, r, ch, &cl) > 0;
+    }
+    int tot;
+    int pre = wscan_excl(has, lane, &tot);
+    if (has) S.lis[nlis + pre] = (uint16_t)r;
+    nlis += tot;
+  }
+  for (int i = lane; i < 72; i += 64) S.bw[i] = 0;
+  __syncthreads();
+  int nlip = nroots, nlsp = 0;
+  int64_t bitpos = 0, wbase = 0;       // bits emitted; stream bit index of bw[0]
+  uint8_t* out = slots + slot_off[t];
+  const int64_t cap_bytes = slot_off[t + 1] - slot_off[t];
+  auto flush = [&](bool final) {
+    __syncthreads();
+    int nfull = (int)((bitpos - wbase) >> 5);
+    int nw = final ? (int)((bitpos - wbase + 31) >> 5) : nfull;
+    uint32_t* o32 = reinterpret_cast<uint32_t*>(out + (wbase >> 3));
+    for (int i = lane; i < nw; i += 64)
+      if ((wbase >> 3) + 4 * (int64_t)i + 4 <= cap_bytes) o32[i] = bswap32(S.bw[i]);
+    if (!final && nfull > 0) {
+      uint32_t part = S.bw[nfull];
+      __syncthreads();
+      for (int i = lane; i < 72; i += 64) S.bw[i] = (i == 0) ? part : 0u;
+      wbase += 32 * (int64_t)nfull;
+    }
+    __syncthreads();
+  };
+  for (int pl = ntop; pl >= n_s; pl--) {
+    const uint32_t thr = 1u << pl;
+    const int lsp_prev = nlsp;
+    // sorting pass, LIP
+    int surv = 0;
+    for (int h0 = 0; h0 < nlip; h0 += 64) {
+      int k = h0 + lane;
+      bool act = k < nlip;
+      int e = act ? S.lip[k] : 0;
+      uint32_t q = act ? S.qv[e] : 0u;
+      int s = act && (q & 0x7FFFFFu) >= thr;
+      int nbits = act ? (s ? 2 : 1) : 0;
+      uint32_t v = s ? (2u | (q >> 31)) : 0u;
+      int tb, ts, tl;
+      int pb = wscan_excl(nbits, lane, &tb);
+      int ps = wscan_excl(s, lane, &ts);
+      int pk = wscan_excl(act && !s, lane, &tl);
+      __syncthreads();
+      put_bits(S.bw, (int)(bitpos - wbase) + pb, nbits, v);
+      if (s) S.lsp[nlsp + ps] = (uint16_t)e;
+      if (act && !s) S.lip[surv + pk] = (uint16_t)e;
+      bitpos += tb; nlsp += ts; surv += tl;
+      flush(false);
+    }
+    nlip = surv;
+    // sorting pass, LIS (grows while it is processed)
+    int head = 0, kept = 0;
+    while (head < nlis) {
+      int k = head + lane;
+      bool act = k < nlis;
+      int e = act ? S.lis[k] : 0;
+      int loc = e & 0x7FFF, typeB = e >> 15;
+      int ch[9], cl = 0, no = 0;
+      if (act) no = offspring_local(g, S.B, nb, L, loc, ch, &cl);
+      int s = 0, nbits = 0, nlsp_a = 0, nlip_a = 0, nlis_a = 0;
+      uint32_t v = 0;
+      if (act) {
+        if (!typeB) {
+          s = S.mdl[loc] > pl;
+          v = (uint32_t)s; nbits = 1;
+          if (s) {
+#pragma unroll
+            for (int c = 0; c < 9; c++)
+              if (c < no) {
+                uint32_t q = S.qv[ch[c]];
+                int sc = (q & 0x7FFFFFu) >= thr;
+                v = (v << 1) | (uint32_t)sc; nbits++;
+                if (sc) { v = (v << 1) | (q >> 31); nbits++; nlsp_a++; }
+                else nlip_a++;
+              }
+            nlis_a = (no > 0 && cl >= 2) ? 1 : 0;
+          }
+        } else {
+          s = S.mll[loc] > pl;
+          v = (uint32_t)s; nbits = 1;
+          if (s) nlis_a = no;
+        }
+      }
+      int keep = act && !s;
+      int tb, tk, tsp, tip, tis;
+      int pb = wscan_excl(nbits, lane, &tb);
+      int pk = wscan_excl(keep, lane, &tk);
+      int psp = wscan_excl(nlsp_a, lane, &tsp);
+      int pip = wscan_excl(nlip_a, lane, &tip);
+      int pis = wscan_excl(nlis_a, lane, &tis);
+      __syncthreads();
+      put_bits(S.bw, (int)(bitpos - wbase) + pb, nbits, v);
+      if (keep) S.lis[kept + pk] = (uint16_t)e;
+      if (act && s) {
+        if (!typeB) {
+          int a = 0, b = 0;
+#pragma unroll
+          for (int c = 0; c < 9; c++)
+            if (c < no) {
+              int sc = (S.qv[ch[c]] & 0x7FFFFFu) >= thr;
+              if (sc) S.lsp[nlsp + psp + (a++)] = (uint16_t)ch[c];
+              else S.lip[nlip + pip + (b++)] = (uint16_t)ch[c];
+            }
+          if (nlis_a) S.lis[nlis + pis] = (uint16_t)(loc | 0x8000);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 9; c++)
+            if (c < no) S.lis[nlis + pis + c] = (uint16_t)ch[c];
+        }
+      }
+      bitpos += tb; kept += tk; nlsp += tsp; nlip += tip;
+      head += 64 < nlis - head ? 64 : nlis - head;
+      nlis += tis;
+      flush(false);
+    }
+    nlis = kept;
+    // refinement pass
+    for (int h0 = 0; h0 < lsp_prev; h0 += 64) {
+      int k = h0 + lane;
+      bool act = k < lsp_prev;
+      int n = lsp_prev - h0 < 64 ? lsp_prev - h0 : 64;
+      uint32_t bit = act ? (S.qv[S.lsp[k]] >> pl) & 1u : 0u;
+      __syncthreads();
+      if (act) put_bits(S.bw, (int)(bitpos - wbase) + lane, 1, bit);
+      bitpos += n;
+      flush(false);
+    }
+  }
+  flush(true);
+  if (lane == 0) {
+    uint32_t bytes = (uint32_t)((bitpos + 7) >> 3);
+    tlen[t] = bytes;
+    tent[t] = bytes | ((uint32_t)(ntop + 1) << 26);
+  }
+}
+
+// Uniform reader of a tile payload (bytes past its end read as 0).
+struct BitRU {
+  const uint8_t* buf;
+  int64_t len, pos;        // pos: next bit to consume
+  uint64_t win;            // next bits, MSB first
+  int wn;                  // valid bits in win
+  int64_t bytepos;         // next byte to load into win
+  uint64_t wa;
+  uint32_t word;
+  __device__ uint32_t byte_at(int64_t i) {
+    if (i < 0 || i >= len) return 0u;
+    uint64_t a = (uint64_t)(buf + i);
+    uint64_t w = a & ~(uint64_t)3;
+    if (w != wa) { word = *reinterpret_cast<const uint32_t*>(w); wa = w; }
+    return (word >> (8 * (uint32_t)(a & 3))) & 0xFFu;
+  }
+  __device__ void init(const uint8_t* b, int64_t n) {
+    buf = b; len = n; pos = 0; win = 0; wn = 0; bytepos = 0; wa = ~(uint64_t)0; word = 0;
+    refill();
+  }
+  __device__ void refill() {
+    while (wn <= 56) {
+      win |= (uint64_t)byte_at(bytepos) << (56 - wn);
+      bytepos++;
+      wn += 8;
+    }
+  }
+  __device__ int get() {
+    int b = (int)(win >> 63);
+    win <<= 1; wn--; pos++;
+    if (wn <= 56) refill();
+    return b;
+  }
+  // leading zeros among the next bits (at most 57)
+  __device__ int zeros() {
+    int z = win ? __builtin_clzll(win) : 64;
+    return z < wn ? z : wn;
+  }
+  __device__ void skip(int n) {
+    while (n > 0) {
+      int s = n < 32 ? n : 32;
+      win <<= s; wn -= s; pos += s; n -= s;
+      if (wn <= 56) refill();
+    }
+  }
+  // jump to an absolute bit position >= pos
+  __device__ void seek(int64_t p) {
+    pos = p; win = 0; wn = 0;
+    bytepos = p >> 3;
+    refill();
+    int drop = (int)(p & 7);
+    win <<= drop; wn -= drop;
+    if (wn <= 56) refill();
+  }
+};
+
+template <int CAP>
+__global__ __launch_bounds__(64) void k_spiht_decode_lds(const uint8_t* __restrict__ sec, int64_t sec_len,
+                                                         const int64_t* __restrict__ toff, int nx,
+                                                         const Band* __restrict__ bands_g, int nb, int L,
+                                                         const TileD* __restrict__ tiles, int ntiles, int n_s,
+                                                         int e_r, float* __restrict__ chat, int* __restrict__ flag,
+                                                         int* __restrict__ misfit) {
+  __shared__ SpihtLds<CAP> S;
+  const int lane = threadIdx.x;
+  const int t = blockIdx.x;
+  const TileD td = tiles[t];
+  if (!spiht_setup<CAP>(S, bands_g, nb, L, td, lane)) {
+    if (lane == 0) misfit[t] = 1;
+    return;
+  }
+  if (lane == 0) misfit[t] = 0;
+  const TileGeom& g = S.g;
+  const uint32_t ent = (uint32_t)sec[4 * t] | ((uint32_t)sec[4 * t + 1] << 8) | ((uint32_t)sec[4 * t + 2] << 16) |
+                       ((uint32_t)sec[4 * t + 3] << 24);
+  const int64_t len = ent & 0x3FFFFFF;
+  const int ntop = (int)(ent >> 26) - 1;
+  const int64_t pbase = 4 * (int64_t)ntiles;
+  const int64_t o0 = toff[t];
+  if (o0 < 0 || pbase + o0 + len > sec_len || ntop >= kQBits) {
+    if (lane == 0) atomicOr(flag, 1);
+    return;
+  }
+  if (ntop < n_s) return;
+  const uint8_t* pay = sec + pbase + o0;
+  for (int i = lane; i < g.ncoef; i += 64) S.qv[i] = 0;
+  const int nroots = g.hr[0] * g.wr[0];
+  int nlis = 0;
+  for (int r0 = 0; r0 < nroots; r0 += 64) {
+    int r = r0 + lane;
+    int ch[9], cl;
+    int has = 0;
+    if (r < nroots) {
+      S.lip[r] = (uint16_t)r;
+      has = offspring_local(g, S.B, nb, L, r, ch, &cl) > 0;
+    }
+    int tot;
+    int pre = wscan_excl(has, lane, &tot);
+    if (has) S.lis[nlis + pre] = (uint16_t)r;
+    nlis += tot;
+  }
+  __syncthreads();
+  int nlip = nroots, nlsp = 0;
+  BitRU rd;
+  rd.init(pay, len);
+  for (int pl = ntop; pl >= n_s; pl--) {
+    const uint32_t thr = 1u << pl;
+    const int lsp_prev = nlsp;
+    // LIP: runs of zeros leave entries in place; a one makes the entry significant
+    int k = 0, surv = 0;
+    while (k < nlip) {
+      int z = rd.zeros();
+      if (z > nlip - k) z = nlip - k;
+      if (z > 0) {
+        // survivors k .. k+z-1 move down to surv .. (ascending chunks are safe)
+        if (surv != k)
+          for (int c = 0; c < z; c += 64) {
+            int i = c + lane;
+            uint16_t v = i < z ? S.lip[k + i] : 0;
+            __syncthreads();
+            if (i < z) S.lip[surv + i] = v;
+            __syncthreads();
+          }
+        rd.skip(z);
+        k += z; surv += z;
+        continue;
+      }
+      // entry k: significant (its token is 1 and a sign bit)
+      rd.get();
+      int sg = rd.get();
+      int e = S.lip[k];
+      if (lane == 0) { S.qv[e] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)e; }
+      __syncthreads();
+      nlsp++;
+      k++;
+    }
+    nlip = surv;
+    // LIS
+    int head = 0, kept = 0;
+    while (head < nlis) {
+      int e = S.lis[head];
+      int loc = e & 0x7FFF, typeB = e >> 15;
+      int ch[9], cl = 0;
+      int no = offspring_local(g, S.B, nb, L, loc, ch, &cl);
+      int s = rd.get();
+      if (!s) {
+        if (lane == 0) S.lis[kept] = (uint16_t)e;
+        kept++;
+      } else if (!typeB) {
+        for (int c = 0; c < no; c++) {
+          if (rd.get()) {
+            int sg = rd.get();
+            if (lane == 0) { S.qv[ch[c]] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)ch[c]; }
+            nlsp++;
+          } else {
+            if (lane == 0) S.lip[nlip] = (uint16_t)ch[c];
+            nlip++;
+          }
+        }
+        if (no > 0 && cl >= 2) {
+          if (lane == 0) S.lis[nlis] = (uint16_t)(loc | 0x8000);
+          nlis++;
+        }
+      } else {
+        for (int c = 0; c < no; c++) {
+          if (lane == 0) S.lis[nlis + c] = (uint16_t)ch[c];
+        }
+        nlis += no;
+      }
+      __syncthreads();
+      head++;
+    }
+    nlis = kept;
+    // refinement: the next lsp_prev bits, read by all lanes
+    const int64_t p0 = rd.pos;
+    for (int h0 = 0; h0 < lsp_prev; h0 += 64) {
+      int kk = h0 + lane;
+      if (kk < lsp_prev) {
+        int64_t bp = p0 + kk;
+        int64_t by = bp >> 3;
+        uint32_t b = by < len ? (pay[by] >> (7 - (bp & 7))) & 1u : 0u;
+        if (b) S.qv[S.lsp[kk]] |= thr;
+      }
+    }
+    __syncthreads();
+    rd.seek(p0 + lsp_prev);
+  }
+  // dequantised significant coefficients
+  for (int b = 0; b < nb; b++) {
+    int n = g.hr[b] * g.wr[b];
+    for (int r = lane; r < n; r += 64) {
+      uint32_t v = S.qv[g.off[b] + r];
+      if (!v) continue;
+      int li = r / g.wr[b], lj = r - li * g.wr[b];
+      int p = (S.B[b].y0 + g.r0[b] + li) * nx + S.B[b].x0 + g.c0[b] + lj;
+      uint32_t m = v & 0x7FFFFFu;
+      float f = ldexpf((float)(2u * m + (1u << n_s)), e_r - 1);
+      chat[p] = (v >> 31) ? -f : f;
+    }
+  }
+}
+
+int spiht_lds_cap(int max_tile_coef) {
+  if (max_tile_coef <= kSpihtSmall) return kSpihtSmall;
+  if (max_tile_coef <= kSpihtBig) return kSpihtBig;
+  return 0;
+}
+
+void spiht_encode_lds(int cap, const uint32_t* qr, const uint32_t* sub, const uint32_t* maxd, const uint32_t* maxl,
+                      int nx, const Band* bands, int nb, int L, const TileD* tiles, int ntiles, int n_s,
+                      uint8_t* slots, const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit,
+                      hipStream_t st) {
+  if (ntiles <= 0) return;
+  if (cap == kSpihtSmall)
+    k_spiht_encode_lds<kSpihtSmall><<<ntiles, 64, 0, st>>>(qr, sub, maxd, maxl, nx, bands, nb, L, tiles, ntiles, n_s,
+                                                            slots, slot_off, tlen, tent, misfit);
+  else
+    k_spiht_encode_lds<kSpihtBig><<<ntiles, 64, 0, st>>>(qr, sub, maxd, maxl, nx, bands, nb, L, tiles, ntiles, n_s,
+                                                          slots, slot_off, tlen, tent, misfit);
+}
+
+void spiht_decode_lds(int cap, const uint8_t* sec, int64_t sec_len, const int64_t* toff, int nx, const Band* bands,
+                      int nb, int L, const TileD* tiles, int ntiles, int n_s, int e_r, float* chat, int* flag,
+                      int* misfit, hipStream_t st) {
+  if (ntiles <= 0) return;
+  if (cap == kSpihtSmall)
+    k_spiht_decode_lds<kSpihtSmall><<<ntiles, 64, 0, st>>>(sec, sec_len, toff, nx, bands, nb, L, tiles, ntiles, n_s,
+                                                            e_r, chat, flag, misfit);
+  else
+    k_spiht_decode_lds<kSpihtBig><<<ntiles, 64, 0, st>>>(sec, sec_len, toff, nx, bands, nb, L, tiles, ntiles, n_s,
+                                                          e_r, chat, flag, misfit);
+}
+
+}  // namespace ebcc

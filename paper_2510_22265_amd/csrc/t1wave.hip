@@ -1,0 +1,672 @@
+// Tier-1 coding (JPEG2000 Part 1 Annexes C and D) with one wavefront per
+// code-block, for the latency-bound case of few blocks in flight (one field).
+//
+// The coding passes are inherently sequential per block, so the wavefront
+// runs them as wave-uniform code: the scan position, the MQ registers and
+// the current stripe's rows are uniform values (SGPRs, scalar ALU), while
+// the vector registers act as a register file for the block: lane y holds
+// row y's bit masks (significant, visited in this plane, refined, sign,
+// magnitude bit of the current plane).  A stripe's six rows (the four rows
+// plus one above and one below) are read into scalars with readlane when
+// the stripe starts and written back when it ends.  The 19 context states
+// live in one VGPR (lane = context) and the 47-entry probability table in
+// another (lane = state), both read with readlane.  The per-pass distortion
+// reductions are summed in parallel across rows at the pass end.
+#include "common.h"
+#include "t1_common.h"
+
+namespace ebcc {
+
+template <typename M> __device__ __forceinline__ M rdl(M v, int l);
+template <> __device__ __forceinline__ uint32_t rdl<uint32_t>(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+template <> __device__ __forceinline__ uint64_t rdl<uint64_t>(uint64_t v, int l) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ uint32_t rdl32(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+
+// Wave-uniform MQ encoder; lane 0 stores the finished bytes.
+struct MQW {
+  uint32_t C, A, B;
+  int CT, BP;
+};
+__device__ __forceinline__ void mqw_emit(MQW& e, uint32_t nb, uint8_t* out, int lane) {
+  if (lane == 0 && e.BP >= 0 && e.BP < kCwCap) out[e.BP] = (uint8_t)e.B;
+  e.BP++;
+  e.B = nb;
+}
+__device__ __forceinline__ void mqw_byteout(MQW& e, uint8_t* out, int lane) {
+  if (e.B == 0xFF) {
+    mqw_emit(e, e.C >> 20, out, lane); e.C &= 0xFFFFF; e.CT = 7;
+  } else if (e.C < 0x8000000u) {
+    mqw_emit(e, e.C >> 19, out, lane); e.C &= 0x7FFFF; e.CT = 8;
+  } else {
+    e.B += 1;
+    if (e.B == 0xFF) {
+      e.C &= 0x7FFFFFF;
+      mqw_emit(e, e.C >> 20, out, lane); e.C &= 0xFFFFF; e.CT = 7;
+    } else {
+      mqw_emit(e, (e.C >> 19) & 0xFF, out, lane); e.C &= 0x7FFFF; e.CT = 8;
+    }
+  }
+}
+__device__ __forceinline__ void mqw_renorm(MQW& e, uint8_t* out, int lane) {
+  int n = __builtin_clz(e.A) - 16;
+  while (n > 0) {
+    int s = n < e.CT ? n : e.CT;
+    e.A <<= s; e.C <<= s; e.CT -= s; n -= s;
+    if (e.CT == 0) mqw_byteout(e, out, lane);
+  }
+}
+// ctxv: lane c holds context c's state (index | MPS << 7); tabv: lane i holds
+// table entry i.
+__device__ __forceinline__ void mqw_encode(MQW& e, uint32_t& ctxv, uint32_t tabv, int cx, int d, uint8_t* out, int lane) {
+  uint32_t cs = rdl32(ctxv, cx);
+  uint32_t ent = rdl32(tabv, (int)(cs & 0x7f));
+  uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
+  e.A -= qe;
+  if ((uint32_t)d == mps) {
+    if ((e.A & 0x8000) == 0) {
+      if (e.A < qe) e.A = qe; else e.C += qe;
+      uint32_t ncs = (cs & 0x80) | ((ent >> 16) & 0x3f);
+      if (lane == cx) ctxv = ncs;
+      mqw_renorm(e, out, lane);
+    } else {
+      e.C += qe;
+    }
+  } else {
+    if (e.A < qe) e.C += qe; else e.A = qe;
+    uint32_t m = (ent >> 28) ? (mps ^ 1u) : mps;
+    uint32_t ncs = (m << 7) | ((ent >> 22) & 0x3f);
+    if (lane == cx) ctxv = ncs;
+    mqw_renorm(e, out, lane);
+  }
+}
+__device__ __forceinline__ int mqw_flush_copy(const MQW& e, uint32_t* tail) {
+  uint32_t C = e.C, tempc = C + e.A;
+  C |= 0xFFFF;
+  if (C >= tempc) C -= 0x8000;
+  uint32_t t0 = e.B, t1 = 0, t2 = 0;
+  int CT = e.CT;
+  // first BYTEOUT: byte 0 is the pending byte B
+  C <<= CT;
+  if (t0 == 0xFF) { t1 = (C >> 20) & 0xFF; C &= 0xFFFFF; CT = 7; }
+  else if (C < 0x8000000u) { t1 = (C >> 19) & 0xFF; C &= 0x7FFFF; CT = 8; }
+  else {
+    t0 = (t0 + 1) & 0x1FF;
+    if (t0 == 0xFF) { C &= 0x7FFFFFF; t1 = (C >> 20) & 0xFF; C &= 0xFFFFF; CT = 7; }
+    else { t0 &= 0xFF; t1 = (C >> 19) & 0xFF; C &= 0x7FFFF; CT = 8; }
+  }
+  // second BYTEOUT: the pending byte is t1
+  C <<= CT;
+  if (t1 == 0xFF) { t2 = (C >> 20) & 0xFF; }
+  else if (C < 0x8000000u) { t2 = (C >> 19) & 0xFF; }
+  else {
+    t1 += 1;
+    if (t1 == 0xFF) { C &= 0x7FFFFFF; t2 = (C >> 20) & 0xFF; }
+    else { t1 &= 0xFF; t2 = (C >> 19) & 0xFF; }
+  }
+  *tail = (t0 & 0xFF) | ((t1 & 0xFF) << 8) | ((t2 & 0xFF) << 16);
+  return e.BP + 3 - (t2 == 0xFF ? 1 : 0);
+}
+
+template <typename M>
+__device__ __forceinline__ M wmask_of(int w) {
+  return (w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << w) - 1);
+}
+template <typename M>
+__device__ __forceinline__ int sgn3(M s, M n, int x) {
+  return bt(s, x) ? (bt(n, x) ? -1 : 1) : 0;
+}
+
+// Row r' in [-1, 4] of the current stripe's significance / sign rows.
+#define SR(rr) ((rr) < 0 ? sA : ((rr) > 3 ? sC : sB[(rr)]))
+#define NR(rr) ((rr) < 0 ? nA : ((rr) > 3 ? nC : nB[(rr)]))
+
+template <typename M>
+__global__ __launch_bounds__(64) void k_t1_encode_wave(const float* __restrict__ coef, int nx, const Blk* __restrict__ blk,
+                                                       int nblk, int e0, int cbh, const M* __restrict__ planes,
+                                                       const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
+                                                       uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
+                                                       int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
+                                                       uint32_t* __restrict__ tailt, M* __restrict__ sppf) {
+  __shared__ uint32_t qs[64 * 64];   // quantised magnitudes [y][x], pitch 64
+  const int lane = threadIdx.x;
+  const int b = blockIdx.x;
+  const Blk k = blk[b];
+  const int P = pbv[b];
+  const int h = k.h, w = k.w;
+  int32_t* R = Rt + (size_t)b * kPassStride;
+  int64_t* Dd = Dt + (size_t)b * kPassStride;
+  int32_t* BPk = bpt + (size_t)b * kPassStride;
+  uint32_t* TL = tailt + (size_t)b * kPassStride;
+  M* spo = sppf + (size_t)b * cbh;
+  if (lane == 0) { R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0; }
+  if (P == 0) {
+    if (lane < h) spo[lane] = 0;
+    return;
+  }
+  const int sh = k.gain - e0;
+  for (int i = lane; i < w * h; i += 64) {
+    int y = i / w, x = i - y * w;
+    qs[y * 64 + x] = quantq(coef[(size_t)(k.y0 + y) * nx + k.x0 + x], sh);
+  }
+  __syncthreads();
+  uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
+  uint32_t ctxv = lane == 0 ? 4u : (lane == CX_RL ? 3u : (lane == CX_UNI ? 46u : 0u));
+  M sig = 0, vis = 0, ref = 0, spp = 0, nsig = 0, mag = 0;
+  M neg = lane < h ? signs[(size_t)b * cbh + lane] : (M)0;
+  const M wm = wmask_of<M>(w);
+  uint8_t* out = cw + (size_t)b * kCwCap;
+  MQW e;
+  e.C = 0; e.A = 0x8000; e.B = 0; e.CT = 12; e.BP = -1;
+  const int orient = k.orient;
+  int npass = 3 * P - 2, kk = 0;
+  bool stop = false;
+  int64_t Dcum = 0;
+  auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
+
+  for (int p = P - 1; p >= 0 && !stop; p--) {
+    mag = lane < h ? planes[((size_t)b * kQBits + p) * cbh + lane] : (M)0;
+    for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
+      nsig = 0;
+      M refd = sig & ~vis;          // MRP refines every sample significant before this plane
+      for (int y0 = 0; y0 < h && !stop; y0 += 4) {
+        const int rn = h - y0 < 4 ? h - y0 : 4;
+        M sA = rowv(sig, y0 - 1), sC = rowv(sig, y0 + 4);
+        M sB[4], vB[4], fB[4], gB[4], nB[4], nsB[4], spB[4];
+        M nA = 0, nC = 0;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          int y = y0 + r;
+          bool in = r < rn;
+          sB[r] = in ? rdl<M>(sig, y) : (M)0;
+          vB[r] = in ? rdl<M>(vis, y) : (M)0;
+          fB[r] = (in && ty == 1) ? rdl<M>(ref, y) : (M)0;
+          gB[r] = in ? rdl<M>(mag, y) : (M)0;
+          nB[r] = (in && ty != 1) ? rdl<M>(neg, y) : (M)0;
+          nsB[r] = 0; spB[r] = 0;
+        }
+        if (ty != 1) { nA = rowv(neg, y0 - 1); nC = rowv(neg, y0 + 4); }
+        auto code_sign = [&](int r, int x) {
+          int hc = sgn3(SR(r), NR(r), x - 1) + sgn3(SR(r), NR(r), x + 1);
+          int vc = 0;
+          // r is a compile-time constant in every caller (unrolled loops)
+          if (r == 0) vc = sgn3(sA, nA, x) + sgn3(sB[1], nB[1], x);
+          else if (r == 1) vc = sgn3(sB[0], nB[0], x) + sgn3(sB[2], nB[2], x);
+          else if (r == 2) vc = sgn3(sB[1], nB[1], x) + sgn3(sB[3], nB[3], x);
+          else vc = sgn3(sB[2], nB[2], x) + sgn3(sC, nC, x);
+          hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
+          vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
+          int xr;
+          int cx = sc_ctx(hc, vc, &xr);
+          mqw_encode(e, ctxv, tabv, cx, bt(nB[r], x) ^ xr, out, lane);
+        };
+        if (ty == 0) {                                   // significance propagation
+          int x = 0;
+          while (x < w) {
+            M c = 0;
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+              if (r < rn) {
+                M nb = SR(r - 1) | SR(r) | SR(r + 1);
+                nb = nb | (nb << 1) | (nb >> 1);
+                c |= ~SR(r) & nb;
+              }
+            c &= wm & (~(M)0 << x);
+            if (!c) break;
+            x = ctzm(c);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r >= rn) continue;
+              M mid = sB[r];
+              if (bt(mid, x)) continue;
+              M up = SR(r - 1), dn = SR(r + 1);
+              int H = bt(mid, x - 1) + bt(mid, x + 1);
+              int V = bt(up, x) + bt(dn, x);
+              int D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
+              if (H + V + D == 0) continue;
+              int bit = bt(gB[r], x);
+              mqw_encode(e, ctxv, tabv, zc_ctx(orient, H, V, D), bit, out, lane);
+              vB[r] |= (M)1 << x;
+              if (bit) {
+                code_sign(r, x);
+                sB[r] = mid | ((M)1 << x);
+                nsB[r] |= (M)1 << x;
+                spB[r] |= (M)1 << x;
+              }
+            }
+            x++;
+          }
+        } else if (ty == 1) {                            // magnitude refinement
+          M mk = 0;
+#pragma unroll
+          for (int r = 0; r < 4; r++) mk |= sB[r] & ~vB[r];
+          while (mk) {
+            int x = ctzm(mk);
+            mk &= mk - 1;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r >= rn || !bt(sB[r] & ~vB[r], x)) continue;
+              int cx;
+              if (bt(fB[r], x)) cx = CX_MR + 2;
+              else {
+                M up = SR(r - 1), dn = SR(r + 1), mid = sB[r];
+                int t = bt(mid, x - 1) + bt(mid, x + 1) + bt(up, x) + bt(dn, x) + bt(up, x - 1) + bt(up, x + 1) +
+                        bt(dn, x - 1) + bt(dn, x + 1);
+                cx = t ? CX_MR + 1 : CX_MR;
+              }
+              mqw_encode(e, ctxv, tabv, cx, bt(gB[r], x), out, lane);
+              fB[r] |= (M)1 << x;
+            }
+          }
+        } else {                                         // cleanup
+          M u = 0;
+#pragma unroll
+          for (int r = 0; r < 4; r++)
+            if (r < rn) u |= ~(sB[r] | vB[r]);
+          u &= wm;
+          while (u) {
+            int x = ctzm(u);
+            u &= u - 1;
+            int rstart = 0;
+            if (rn == 4) {
+              bool run = true;
+#pragma unroll
+              for (int r = 0; r < 4; r++)
+                if (bt(sB[r] | vB[r], x)) run = false;
+              if (run) {
+                M nbm = nb3<M>(x);
+                if ((sA | sB[0] | sB[1] | sB[2] | sB[3] | sC) & nbm) run = false;
+              }
+              if (run) {
+                int rr = -1;
+#pragma unroll
+                for (int r = 3; r >= 0; r--)
+                  if (bt(gB[r], x)) rr = r;
+                mqw_encode(e, ctxv, tabv, CX_RL, rr >= 0, out, lane);
+                if (rr < 0) continue;
+                mqw_encode(e, ctxv, tabv, CX_UNI, (rr >> 1) & 1, out, lane);
+                mqw_encode(e, ctxv, tabv, CX_UNI, rr & 1, out, lane);
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                  if (r == rr) {
+                    code_sign(r, x);
+                    sB[r] |= (M)1 << x;
+                    nsB[r] |= (M)1 << x;
+                  }
+                rstart = rr + 1;
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r < rstart || r >= rn) continue;
+              if (bt(sB[r] | vB[r], x)) continue;
+              M up = SR(r - 1), dn = SR(r + 1), mid = sB[r];
+              int H = bt(mid, x - 1) + bt(mid, x + 1);
+              int V = bt(up, x) + bt(dn, x);
+              int D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
+              int bit = bt(gB[r], x);
+              mqw_encode(e, ctxv, tabv, zc_ctx(orient, H, V, D), bit, out, lane);
+              if (bit) {
+                code_sign(r, x);
+                sB[r] |= (M)1 << x;
+                nsB[r] |= (M)1 << x;
+              }
+            }
+          }
+        }
+        // write the stripe's rows back to the row registers
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          if (r < rn && lane == y0 + r) {
+            sig = sB[r]; vis = vB[r];
+            if (ty == 1) ref = fB[r];
+            nsig |= nsB[r];
+            spp |= spB[r];
+          }
+        if (e.BP >= 65536) stop = true;                  // every later pass exceeds the length limit
+      }
+      if (stop) break;
+      // distortion reduction of this pass, summed over rows in parallel
+      M chg = (ty == 1) ? refd : nsig;
+      int64_t dd = 0;
+      while (chg) {
+        int x = ctzm(chg);
+        chg &= chg - 1;
+        uint32_t q = qs[lane * 64 + x];
+        dd += (ty == 1) ? ref_delta(q, p) : sig_delta(q, p);
+      }
+      for (int o = 32; o > 0; o >>= 1) dd += __shfl_xor(dd, o);
+      if (ty == 2) vis = 0;
+      kk++;
+      Dcum += dd;
+      uint32_t tail;
+      int rk = mqw_flush_copy(e, &tail);
+      if (lane == 0) { R[kk] = rk; Dd[kk] = Dcum; BPk[kk] = e.BP; TL[kk] = tail; }
+    }
+  }
+  if (lane == 0)
+    for (int j = kk + 1; j <= npass; j++) { R[j] = kRInf; Dd[j] = Dcum; BPk[j] = 0; TL[j] = 0; }
+  if (lane < h) spo[lane] = spp;
+}
+
+// ------------------------------------------------------------------------
+// Wave-uniform MQ decoder: bytes are read through a uniform 4-byte window;
+// bytes past the codeword read as 0xFF.
+// ------------------------------------------------------------------------
+struct MQWD {
+  uint32_t C, A, cur, nxt;
+  int CT, BP, len;
+  const uint8_t* buf;
+  uint64_t wa;
+  uint32_t word;
+};
+__device__ __forceinline__ uint32_t mqwd_rd(MQWD& d, int i) {
+  if (i < 0 || i >= d.len) return 0xFFu;
+  uint64_t a = (uint64_t)(d.buf + i);
+  uint64_t wa = a & ~(uint64_t)3;
+  if (wa != d.wa) {
+    d.word = *reinterpret_cast<const uint32_t*>(wa);
+    d.wa = wa;
+  }
+  return (d.word >> (8 * (uint32_t)(a & 3))) & 0xFFu;
+}
+__device__ __forceinline__ void mqwd_adv(MQWD& d) {
+  d.BP++;
+  d.cur = d.nxt;
+  d.nxt = mqwd_rd(d, d.BP + 1);
+}
+__device__ __forceinline__ void mqwd_bytein(MQWD& d) {
+  if (d.cur == 0xFF) {
+    if (d.nxt > 0x8F) { d.C += 0xFF00; d.CT = 8; }
+    else { mqwd_adv(d); d.C += d.cur << 9; d.CT = 7; }
+  } else {
+    mqwd_adv(d); d.C += d.cur << 8; d.CT = 8;
+  }
+}
+__device__ __forceinline__ void mqwd_init(MQWD& d, const uint8_t* buf, int len) {
+  d.buf = buf; d.len = len; d.BP = 0; d.wa = ~(uint64_t)0; d.word = 0;
+  d.cur = mqwd_rd(d, 0);
+  d.nxt = mqwd_rd(d, 1);
+  d.C = d.cur << 16;
+  mqwd_bytein(d);
+  d.C <<= 7; d.CT -= 7; d.A = 0x8000;
+}
+__device__ __forceinline__ void mqwd_renorm(MQWD& d) {
+  do {
+    if (d.CT == 0) mqwd_bytein(d);
+    d.A <<= 1; d.C <<= 1; d.CT--;
+  } while ((d.A & 0x8000) == 0);
+}
+__device__ __forceinline__ int mqwd_decode(MQWD& d, uint32_t& ctxv, uint32_t tabv, int cx, int lane) {
+  uint32_t cs = rdl32(ctxv, cx);
+  uint32_t ent = rdl32(tabv, (int)(cs & 0x7f));
+  uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
+  uint32_t nm = (ent >> 16) & 0x3f, nl = (ent >> 22) & 0x3f, sw = ent >> 28;
+  int D;
+  uint32_t ncs = cs;
+  d.A -= qe;
+  if ((d.C >> 16) < qe) {
+    if (d.A < qe) { D = (int)mps; ncs = (mps << 7) | nm; }
+    else { D = (int)(mps ^ 1u); ncs = ((sw ? (mps ^ 1u) : mps) << 7) | nl; }
+    d.A = qe;
+    if (lane == cx) ctxv = ncs;
+    mqwd_renorm(d);
+  } else {
+    d.C -= qe << 16;
+    if ((d.A & 0x8000) == 0) {
+      if (d.A < qe) { D = (int)(mps ^ 1u); ncs = ((sw ? (mps ^ 1u) : mps) << 7) | nl; }
+      else { D = (int)mps; ncs = (mps << 7) | nm; }
+      if (lane == cx) ctxv = ncs;
+      mqwd_renorm(d);
+    } else {
+      D = (int)mps;
+    }
+  }
+  return D;
+}
+
+template <typename M>
+__global__ __launch_bounds__(64) void k_t1_decode_wave(const uint8_t* __restrict__ sec, int64_t sec_len,
+                                                       const uint32_t* __restrict__ table,
+                                                       const int64_t* __restrict__ off, int nx,
+                                                       const Blk* __restrict__ blk, int nblk, int e0,
+                                                       float* __restrict__ yhat, int* __restrict__ flag) {
+  __shared__ uint32_t qm[64 * 64];   // decoded magnitudes [y][x], pitch 64
+  const int lane = threadIdx.x;
+  const int b = blockIdx.x;
+  const Blk k = blk[b];
+  const int h = k.h, w = k.w;
+  const uint32_t ent = table[b];
+  const int P = ent & 0xFF, kb = (ent >> 8) & 0xFF, len = (int)(ent >> 16);
+  const int64_t o = off[b];
+  float* yb = yhat + (size_t)k.y0 * nx + k.x0;
+  const bool bad = P > kQBits || kb > (P ? 3 * P - 2 : 0) || o < 0 || o + len > sec_len;
+  if (bad && lane == 0) atomicOr(flag, 1);
+  if (bad || P == 0 || kb == 0) {
+    for (int i = lane; i < w * h; i += 64) {
+      int y = i / w, x = i - y * w;
+      yb[(size_t)y * nx + x] = 0.0f;
+    }
+    return;
+  }
+  for (int i = lane; i < 64 * 64; i += 64) qm[i] = 0;
+  __syncthreads();
+  uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
+  uint32_t ctxv = lane == 0 ? 4u : (lane == CX_RL ? 3u : (lane == CX_UNI ? 46u : 0u));
+  M sig = 0, vis = 0, ref = 0, neg = 0, cur = 0, magp = 0;
+  const M wm = wmask_of<M>(w);
+  const int orient = k.orient;
+  MQWD d;
+  mqwd_init(d, sec + o, len);
+  auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
+  int done = 0, plast = P - 1;
+  for (int p = P - 1; p >= 0 && done < kb; p--) {
+    plast = p;
+    cur = 0;
+    magp = 0;
+    for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < kb; ty++) {
+      for (int y0 = 0; y0 < h; y0 += 4) {
+        const int rn = h - y0 < 4 ? h - y0 : 4;
+        M sA = rowv(sig, y0 - 1), sC = rowv(sig, y0 + 4);
+        M nA = rowv(neg, y0 - 1), nC = rowv(neg, y0 + 4);
+        M sB[4], vB[4], fB[4], nB[4], cB[4], mB[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          int y = y0 + r;
+          bool in = r < rn;
+          sB[r] = in ? rdl<M>(sig, y) : (M)0;
+          vB[r] = in ? rdl<M>(vis, y) : (M)0;
+          fB[r] = (in && ty == 1) ? rdl<M>(ref, y) : (M)0;
+          nB[r] = in ? rdl<M>(neg, y) : (M)0;
+          cB[r] = 0; mB[r] = 0;
+        }
+        auto dec_sign = [&](int r, int x) {
+          int hc = sgn3(SR(r), NR(r), x - 1) + sgn3(SR(r), NR(r), x + 1);
+          int vc = 0;
+          if (r == 0) vc = sgn3(sA, nA, x) + sgn3(sB[1], nB[1], x);
+          else if (r == 1) vc = sgn3(sB[0], nB[0], x) + sgn3(sB[2], nB[2], x);
+          else if (r == 2) vc = sgn3(sB[1], nB[1], x) + sgn3(sB[3], nB[3], x);
+          else vc = sgn3(sB[2], nB[2], x) + sgn3(sC, nC, x);
+          hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
+          vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
+          int xr;
+          int cx = sc_ctx(hc, vc, &xr);
+          int s = mqwd_decode(d, ctxv, tabv, cx, lane) ^ xr;
+          if (s) nB[r] |= (M)1 << x;
+        };
+        if (ty == 0) {
+          int x = 0;
+          while (x < w) {
+            M c = 0;
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+              if (r < rn) {
+                M nb = SR(r - 1) | SR(r) | SR(r + 1);
+                nb = nb | (nb << 1) | (nb >> 1);
+                c |= ~SR(r) & nb;
+              }
+            c &= wm & (~(M)0 << x);
+            if (!c) break;
+            x = ctzm(c);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r >= rn) continue;
+              M mid = sB[r];
+              if (bt(mid, x)) continue;
+              M up = SR(r - 1), dn = SR(r + 1);
+              int H = bt(mid, x - 1) + bt(mid, x + 1);
+              int V = bt(up, x) + bt(dn, x);
+              int D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
+              if (H + V + D == 0) continue;
+              int bit = mqwd_decode(d, ctxv, tabv, zc_ctx(orient, H, V, D), lane);
+              vB[r] |= (M)1 << x;
+              if (bit) {
+                dec_sign(r, x);
+                sB[r] = mid | ((M)1 << x);
+                cB[r] |= (M)1 << x;
+                mB[r] |= (M)1 << x;
+              }
+            }
+            x++;
+          }
+        } else if (ty == 1) {
+          M mk = 0;
+#pragma unroll
+          for (int r = 0; r < 4; r++) mk |= sB[r] & ~vB[r];
+          while (mk) {
+            int x = ctzm(mk);
+            mk &= mk - 1;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r >= rn || !bt(sB[r] & ~vB[r], x)) continue;
+              int cx;
+              if (bt(fB[r], x)) cx = CX_MR + 2;
+              else {
+                M up = SR(r - 1), dn = SR(r + 1), mid = sB[r];
+                int t = bt(mid, x - 1) + bt(mid, x + 1) + bt(up, x) + bt(dn, x) + bt(up, x - 1) + bt(up, x + 1) +
+                        bt(dn, x - 1) + bt(dn, x + 1);
+                cx = t ? CX_MR + 1 : CX_MR;
+              }
+              int bit = mqwd_decode(d, ctxv, tabv, cx, lane);
+              if (bit) mB[r] |= (M)1 << x;
+              fB[r] |= (M)1 << x;
+              cB[r] |= (M)1 << x;
+            }
+          }
+        } else {
+          M u = 0;
+#pragma unroll
+          for (int r = 0; r < 4; r++)
+            if (r < rn) u |= ~(sB[r] | vB[r]);
+          u &= wm;
+          while (u) {
+            int x = ctzm(u);
+            u &= u - 1;
+            int rstart = 0;
+            if (rn == 4) {
+              bool run = true;
+#pragma unroll
+              for (int r = 0; r < 4; r++)
+                if (bt(sB[r] | vB[r], x)) run = false;
+              if (run) {
+                M nbm = nb3<M>(x);
+                if ((sA | sB[0] | sB[1] | sB[2] | sB[3] | sC) & nbm) run = false;
+              }
+              if (run) {
+                if (!mqwd_decode(d, ctxv, tabv, CX_RL, lane)) continue;
+                int b1 = mqwd_decode(d, ctxv, tabv, CX_UNI, lane);
+                int b0 = mqwd_decode(d, ctxv, tabv, CX_UNI, lane);
+                int rr = 2 * b1 + b0;
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                  if (r == rr) {
+                    dec_sign(r, x);
+                    sB[r] |= (M)1 << x;
+                    cB[r] |= (M)1 << x;
+                    mB[r] |= (M)1 << x;
+                  }
+                rstart = rr + 1;
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r < rstart || r >= rn) continue;
+              if (bt(sB[r] | vB[r], x)) continue;
+              M up = SR(r - 1), dn = SR(r + 1), mid = sB[r];
+              int H = bt(mid, x - 1) + bt(mid, x + 1);
+              int V = bt(up, x) + bt(dn, x);
+              int D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
+              int bit = mqwd_decode(d, ctxv, tabv, zc_ctx(orient, H, V, D), lane);
+              if (bit) {
+                dec_sign(r, x);
+                sB[r] |= (M)1 << x;
+                cB[r] |= (M)1 << x;
+                mB[r] |= (M)1 << x;
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          if (r < rn && lane == y0 + r) {
+            sig = sB[r]; vis = vB[r]; neg = nB[r];
+            if (ty == 1) ref = fB[r];
+            cur |= cB[r];
+            magp |= mB[r];
+          }
+      }
+      if (ty == 2) vis = 0;
+      done++;
+    }
+    // this plane's decoded bits into the magnitudes of the row
+    M mm = magp;
+    while (mm) {
+      int x = ctzm(mm);
+      mm &= mm - 1;
+      qm[lane * 64 + x] |= 1u << p;
+    }
+  }
+  __syncthreads();
+  const int e = e0 - k.gain;
+  if (lane < h) {
+    for (int x = 0; x < w; x++) {
+      float v = 0.0f;
+      if (bt(sig, x)) {
+        int pk = bt(cur, x) ? plast : plast + 1;
+        v = dequant(qm[lane * 64 + x], pk, bt(neg, x), e);
+      }
+      yb[(size_t)lane * nx + x] = v;
+    }
+  }
+}
+
+#undef SR
+#undef NR
+
+void t1_encode_wave(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, const void* planes,
+                    const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
+                    uint32_t* tail, void* sppf, hipStream_t st) {
+  if (nblk <= 0) return;
+  if (cbw <= 32)
+    k_t1_encode_wave<uint32_t><<<nblk, 64, 0, st>>>(coef, nx, blk, nblk, e0, cbh, (const uint32_t*)planes,
+                                                     (const uint32_t*)signs, pb, cw, R, D, bp, tail, (uint32_t*)sppf);
+  else
+    k_t1_encode_wave<uint64_t><<<nblk, 64, 0, st>>>(coef, nx, blk, nblk, e0, cbh, (const uint64_t*)planes,
+                                                     (const uint64_t*)signs, pb, cw, R, D, bp, tail, (uint64_t*)sppf);
+}
+
+void t1_decode_wave(const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off, int nx,
+                    const Blk* blk, int nblk, int e0, int cbw, float* yhat, int* flag, hipStream_t st) {
+  if (nblk <= 0) return;
+  if (cbw <= 32)
+    k_t1_decode_wave<uint32_t><<<nblk, 64, 0, st>>>(sec, sec_len, table, off, nx, blk, nblk, e0, yhat, flag);
+  else
+    k_t1_decode_wave<uint64_t><<<nblk, 64, 0, st>>>(sec, sec_len, table, off, nx, blk, nblk, e0, yhat, flag);
+}
+
+}  // namespace ebcc

@@ -164,3 +164,24 @@ def test_deterministic(gpu):
 def test_full_size_era5_stack_fields(gpu, ref, var, eps):
     """721x1440 fields (the ERA5-shaped stack's grid), three bounds."""
     _roundtrip(gpu, ref, synth.field(var, 721, 1440, cfg=1, level=17), eps)
+
+
+@pytest.mark.parametrize("variant", ["lane", "wave"])
+@pytest.mark.parametrize("cb", [(5, 5), (6, 6), (2, 3), (6, 4)])
+def test_tier1_kernel_variants(gpu, ref, variant, cb, monkeypatch):
+    """Both tier-1 kernel families (wave per block for few blocks, lanes per
+    block for large batches) produce the oracle's stream and decode."""
+    monkeypatch.setenv("EBCC_T1_KERNEL", variant)
+    x = synth.field("u", 181, 360, cfg=1, level=11)
+    _roundtrip(gpu, ref, x, 0.002, cbl2w=cb[0], cbl2h=cb[1])
+
+
+@pytest.mark.parametrize("variant", ["global", "lds"])
+@pytest.mark.parametrize("shape,levels,tile", [((181, 360), 5, 1), ((181, 360), 5, 2), ((97, 203), 3, 3),
+                                                ((70, 130), 6, 1), ((33, 17), 2, 2)])
+def test_spiht_kernel_variants(gpu, ref, variant, shape, levels, tile, monkeypatch):
+    """Both SPIHT kernel families (tile in LDS, lists in global memory)
+    produce the oracle's stream and decode."""
+    monkeypatch.setenv("EBCC_SPIHT_KERNEL", variant)
+    x = synth.field("v", *shape, cfg=1, level=13)
+    _roundtrip(gpu, ref, x, 0.002, levels=levels, tile=tile)
