@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
 """EBCC compress/decompress throughput on one MI355X.
 
-Workload (default): the ERA5-shaped stack, plain per-field path: 148 float32
-fields of 721x1440 (37 levels x {temperature-, u-, v-, humidity-like}),
-range-relative bound 1% (the headline bound), base ratio r = 30, 5 DWT
-levels, 32x32 code-blocks, 2x2-root SPIHT tiles.  Inputs are synthetic
-(seeded generators standing in for ERA5) and resident in HBM before timing.
+Headline workload (`value`): the ERA5-shaped stack, plain per-field path:
+148 float32 fields of 721x1440 (37 levels x {temperature-, u-, v-,
+humidity-like}), range-relative bound 1%, base ratio r = 30, 5 DWT levels,
+32x32 code-blocks, 2x2-root SPIHT tiles.  One step = compress every field,
+then decompress every stream, one field per call on one stream.  value = fp32
+bytes of the stack / step time (GB/s, decimal): round-trip throughput.
 
-One step = compress every field, then decompress every stream, one field at
-a time on one stream.  value = fp32 bytes of the stack / step time (GB/s,
-decimal), i.e. round-trip throughput; compress and decompress rates,
-compression ratio, per-call p50/p99 latency, the stage breakdown, the
-roofline of the dominant kernel and the CPU oracle baseline are printed in
-the same JSON line.
+Beside it, in the same JSON line:
+  batched   the uneven batch (256 fields drawn from 91x180 .. 721x1440,
+            per-field bounds log-uniform in [0.1%, 10%] of range) through
+            ebcc_compress_batch / ebcc_decompress_batch, the same fields
+            through the per-field loop, and the speedup; also the headline
+            stack through the batched entry points;
+  roofline  the dominant kernel of the headline path (its HIP-event time
+            per launch, algorithmic bytes per launch);
+  cpu_baseline  the CPU oracle on a bounded sample of the headline fields.
+Inputs are synthetic (seeded generators standing in for ERA5) and resident
+in HBM before timing; verification (bound, compression ratio) is outside the
+timed region.
 """
 import argparse
 import json
@@ -26,31 +33,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
-# Integer/ALU peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s.
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
-def _gen(args):
+def _gen(spec):
     from paper_2510_22265_amd import synth
-    var, ny, nx, level = args
-    return synth.field(var, ny, nx, cfg=1, level=level)
+    kind, a = spec
+    if kind == "stack":
+        var, ny, nx, level = a
+        return synth.field(var, ny, nx, cfg=1, level=level)
+    return synth.batch_field(a)
 
 
-def make_fields(nfields, ny, nx):
+def generate(specs):
     from multiprocessing import Pool
-    specs = []
-    for lev in range(37):
-        for v in ("t", "u", "v", "q"):
-            specs.append((v, ny, nx, lev))
-    specs = specs[:nfields]
     procs = min(16, os.cpu_count() or 1)
     with Pool(procs) as p:
-        fields = p.map(_gen, specs)
-    return specs, fields
+        return p.map(_gen, specs, chunksize=4)
 
 
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def verify(xs_h, recs, eps):
+    """Count bound violations (FP64) and the largest range-relative error."""
+    viol, max_rel = 0, 0.0
+    for x, y, e in zip(xs_h, recs, eps):
+        rng_ = float(x.max()) - float(x.min())
+        err = float(np.abs(x.astype(np.float64) - y.cpu().numpy().astype(np.float64)).max())
+        if err > e * rng_:
+            viol += 1
+        if rng_ > 0:
+            max_rel = max(max_rel, err / rng_)
+    return viol, max_rel
 
 
 def main():
@@ -63,6 +82,7 @@ def main():
     ap.add_argument("--nx", type=int, default=1440)
     ap.add_argument("--eps", type=float, default=0.01)
     ap.add_argument("--ratio", type=float, default=30.0)
+    ap.add_argument("--batch-fields", type=int, default=256, help="fields of the uneven batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -72,84 +92,76 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2510_22265_amd import ebcc
+    from paper_2510_22265_amd import ebcc, synth
     if not os.path.exists(ebcc.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
     ebcc.lib()
     dev = torch.device("cuda:0")
-    print(f"bench: generating {args.fields} fields of {args.ny}x{args.nx}", file=sys.stderr, flush=True)
-    specs, fields_h = make_fields(args.fields, args.ny, args.nx)
-    xs = [torch.from_numpy(f).to(dev) for f in fields_h]
+    stream = torch.cuda.current_stream()
+
+    # ---------------- inputs ----------------
+    stack_specs = [("stack", (v, args.ny, args.nx, lev)) for lev in range(37) for v in synth.VARS][: args.fields]
+    bspecs = synth.batch_specs(n=args.batch_fields) if args.batch_fields else []
+    log(f"generating {len(stack_specs)} fields of {args.ny}x{args.nx} and an uneven batch of {len(bspecs)}")
+    fields_h = generate(stack_specs + [("batch", s) for s in bspecs])
+    stack_h, batch_h = fields_h[: len(stack_specs)], fields_h[len(stack_specs):]
+    xs = [torch.from_numpy(f).to(dev) for f in stack_h]
     p = ebcc.params(args.eps, args.ratio)
     cap = ebcc.compress_bound(args.ny, args.nx)
     outs = [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in xs]
     recs = [torch.empty((args.ny, args.nx), dtype=torch.float32, device=dev) for _ in xs]
     lens = [0] * len(xs)
-    stream = torch.cuda.current_stream()
-    nbytes = sum(f.nbytes for f in fields_h)
+    nbytes = sum(f.nbytes for f in stack_h)
 
-    def step(lat_c=None, lat_d=None):
+    def per_field_step(xs_, outs_, recs_, lens_, p_list, lat_c=None, lat_d=None):
         t0 = time.perf_counter()
-        for i, x in enumerate(xs):
+        for i, x in enumerate(xs_):
             a = time.perf_counter()
-            rc, n = ebcc.compress_into(x, outs[i], p, stream)
+            rc, n = ebcc.compress_into(x, outs_[i], p_list[i], stream)
             if rc != 0:
-                raise RuntimeError(f"compress failed on field {specs[i]}: {rc} {ebcc.lib().ebcc_last_error()}")
-            lens[i] = n
+                raise RuntimeError(f"compress failed on field {i}: {rc} {ebcc.lib().ebcc_last_error()}")
+            lens_[i] = n
             if lat_c is not None:
                 lat_c.append(time.perf_counter() - a)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for i in range(len(xs)):
+        for i in range(len(xs_)):
             a = time.perf_counter()
-            rc = ebcc.decompress_into(outs[i][: lens[i]], recs[i], stream)
+            rc = ebcc.decompress_into(outs_[i][: lens_[i]], recs_[i], stream)
             if rc != 0:
-                raise RuntimeError(f"decompress failed on field {specs[i]}: {rc}")
+                raise RuntimeError(f"decompress failed on field {i}: {rc}")
             if lat_d is not None:
                 lat_d.append(time.perf_counter() - a)
         torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        return t1 - t0, t2 - t1
+        return t1 - t0, time.perf_counter() - t1
 
+    # ---------------- headline: per-field path over the stack ----------------
+    plist = [p] * len(xs)
     for w in range(args.warmup):
-        step()
-        print(f"bench: warmup step {w} done", file=sys.stderr, flush=True)
+        per_field_step(xs, outs, recs, lens, plist)
+        log(f"warmup step {w} done")
     lat_c, lat_d = [], []
     ebcc.profile_enable(True)
     torch.cuda.synchronize()
     tc = td = 0.0
     t_start = time.perf_counter()
     for s in range(args.steps):
-        a, b = step(lat_c, lat_d)
+        a, b = per_field_step(xs, outs, recs, lens, plist, lat_c, lat_d)
         tc += a
         td += b
-        print(f"bench: step {s}: compress {a * 1e3:.1f} ms, decompress {b * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        log(f"step {s}: compress {a * 1e3:.1f} ms, decompress {b * 1e3:.1f} ms")
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     prof = ebcc.profile_read()
     ebcc.profile_enable(False)
-
-    # verification outside the timed region: bound and compression ratio
-    viol = 0
-    max_rel = 0.0
-    for i, x in enumerate(xs):
-        xd = x.double()
-        rng_ = float(fields_h[i].max()) - float(fields_h[i].min())
-        err = float((xd - recs[i].double()).abs().max())
-        if err > args.eps * rng_:
-            viol += 1
-        if rng_ > 0:
-            max_rel = max(max_rel, err / rng_)
+    viol, max_rel = verify(stack_h, recs, [args.eps] * len(xs))
     stream_bytes = sum(lens)
-    cr = nbytes / stream_bytes
-
     steps = args.steps
     value = nbytes * steps / t_total / 1e9
-    comp_gbps = nbytes * steps / tc / 1e9
-    dec_gbps = nbytes * steps / td / 1e9
 
-    # roofline of the dominant stage (a single kernel: tier-1 encode)
+    # roofline of the dominant kernel (each timed stage is one kernel launch
+    # per call for tier-1; HIP events on the library's stream)
     stages = {k: v for k, v in prof.items() if v[1] > 0}
     dom = max(stages, key=lambda k: stages[k][0]) if stages else None
     roof = None
@@ -157,17 +169,113 @@ def main():
         ms, calls = stages[dom]
         avg_s = ms / calls / 1e3
         N = args.ny * args.nx
-        # algorithmic bytes of one launch of the dominant kernel
-        if dom == "t1_encode":
-            # reads the field's quantised bit-plane masks and coefficients and
-            # writes the codewords: ~4 B/sample in + codeword bytes out
-            algo = 4.0 * N + stream_bytes / len(xs)
+        if dom in ("t1_encode", "t1_decode"):
+            # algorithmic bytes of one launch: the field's coefficients (4 B
+            # per sample) and the base-layer codewords of one stream
+            algo = 4.0 * N + stream_bytes / len(xs) / 2
         else:
             algo = 8.0 * N
         ach = algo / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBPS, "traffic": None, "avg_launch_ms": ms / calls}
+                "frac": ach / HBM_PEAK_GBPS, "traffic": None, "avg_launch_ms": ms / calls,
+                "algo_bytes_per_launch": algo}
 
+    # ---------------- batched execution ----------------
+    batched = None
+    if bspecs:
+        bx = [torch.from_numpy(f).to(dev) for f in batch_h]
+        beps = [s[3] for s in bspecs]
+        bbytes = sum(f.nbytes for f in batch_h)
+        bargs = ebcc.BatchArgs(bx, err_bounds=beps)
+        bout = torch.empty(bargs.bound(), dtype=torch.uint8, device=dev)
+
+        def batch_compress():
+            rc = ebcc.compress_batch_into(bargs, bout, p, stream)
+            if rc != 0:
+                raise RuntimeError(f"batched compress failed: {rc} {ebcc.lib().ebcc_last_error()}")
+
+        batch_compress()
+        bstreams = [bout[bargs.offsets[i]: bargs.offsets[i] + bargs.lengths[i]] for i in range(bargs.n)]
+        brecs = [torch.empty(f.shape, dtype=torch.float32, device=dev) for f in batch_h]
+        dargs = ebcc.DecodeArgs(bstreams, brecs)
+
+        def batch_decompress():
+            rc = ebcc.decompress_batch_into(dargs, stream)
+            if rc != 0:
+                raise RuntimeError(f"batched decompress failed: {rc}")
+
+        batch_decompress()
+        torch.cuda.synchronize()
+        bc = bd = 0.0
+        blat = []
+        for s in range(steps):
+            a = time.perf_counter()
+            batch_compress()
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            batch_decompress()
+            torch.cuda.synchronize()
+            c = time.perf_counter()
+            bc += b - a
+            bd += c - b
+            blat.append(c - a)
+            log(f"batched step {s}: compress {(b - a) * 1e3:.1f} ms, decompress {(c - b) * 1e3:.1f} ms")
+        bviol, bmax = verify(batch_h, brecs, beps)
+        bsbytes = sum(bargs.lengths[i] for i in range(bargs.n))
+        # the same fields and bounds through the per-field loop (one step)
+        bplist = [ebcc.params(e, args.ratio) for e in beps]
+        bouts = [torch.empty(ebcc.compress_bound(*f.shape), dtype=torch.uint8, device=dev) for f in batch_h]
+        blens = [0] * len(bx)
+        per_field_step(bx, bouts, brecs, blens, bplist)
+        pc, pd = per_field_step(bx, bouts, brecs, blens, bplist)
+        same = all(torch.equal(bouts[i][: blens[i]], bstreams[i]) for i in range(len(bx)))
+        # stage breakdown of one batched call (profiled separately, not timed)
+        ebcc.profile_enable(True)
+        batch_compress()
+        batch_decompress()
+        torch.cuda.synchronize()
+        bprof = {k: v[0] for k, v in ebcc.profile_read().items() if v[1] > 0}
+        ebcc.profile_enable(False)
+        # the headline stack through the batched entry points
+        sargs = ebcc.BatchArgs(xs, err_bounds=[args.eps] * len(xs))
+        sout = torch.empty(sargs.bound(), dtype=torch.uint8, device=dev)
+        assert ebcc.compress_batch_into(sargs, sout, p, stream) == 0
+        sstreams = [sout[sargs.offsets[i]: sargs.offsets[i] + sargs.lengths[i]] for i in range(sargs.n)]
+        sdargs = ebcc.DecodeArgs(sstreams, recs)
+        assert ebcc.decompress_batch_into(sdargs, stream) == 0
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for s in range(steps):
+            assert ebcc.compress_batch_into(sargs, sout, p, stream) == 0
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        for s in range(steps):
+            assert ebcc.decompress_batch_into(sdargs, stream) == 0
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        sviol, _ = verify(stack_h, recs, [args.eps] * len(xs))
+        stack_same = all(torch.equal(sstreams[i], outs[i][: lens[i]]) for i in range(len(xs)))
+        batched = {
+            "workload": f"uneven batch: {len(bx)} fields from {{91x180, 181x360, 361x720, 721x1440}}, "
+                        f"eps_rel log-uniform [1e-3, 1e-1], r {args.ratio}",
+            "fields": len(bx), "MB": bbytes / 1e6,
+            "GBps": bbytes * steps / (bc + bd) / 1e9,
+            "compress_GBps": bbytes * steps / bc / 1e9, "decompress_GBps": bbytes * steps / bd / 1e9,
+            "per_field_GBps": bbytes / (pc + pd) / 1e9,
+            "per_field_compress_GBps": bbytes / pc / 1e9, "per_field_decompress_GBps": bbytes / pd / 1e9,
+            "speedup_vs_per_field": (pc + pd) / ((bc + bd) / steps),
+            "streams_identical_to_per_field": bool(same),
+            "CR": bbytes / bsbytes, "violations": bviol, "max_err_rel": bmax,
+            "batch_ms_p50": pct(blat, 50) * 1e3, "batch_ms_p99": pct(blat, 99) * 1e3,
+            "stages_ms_per_batch": bprof,
+            "stack_GBps": nbytes * steps / (c - a) / 1e9,
+            "stack_compress_GBps": nbytes * steps / (b - a) / 1e9,
+            "stack_decompress_GBps": nbytes * steps / (c - b) / 1e9,
+            "stack_speedup_vs_per_field": (t_total / steps) / ((c - a) / steps),
+            "stack_streams_identical": bool(stack_same), "stack_violations": sviol,
+        }
+
+    # ---------------- CPU oracle baseline ----------------
     cpu = None
     if not args.no_cpu:
         from oracle import ref
@@ -175,14 +283,14 @@ def main():
         t0 = time.perf_counter()
         done = 0
         sb = 0
-        while done < len(fields_h) and time.perf_counter() - t0 < args.cpu_seconds:
-            s = ref.compress(fields_h[done], args.eps, base_ratio=args.ratio)
+        while done < len(stack_h) and time.perf_counter() - t0 < args.cpu_seconds:
+            s = ref.compress(stack_h[done], args.eps, base_ratio=args.ratio)
             ref.decompress(s, args.ny, args.nx)
-            sb += fields_h[done].nbytes
+            sb += stack_h[done].nbytes
             done += 1
         el = time.perf_counter() - t0
         cpu = {"value": sb / el / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} of {len(fields_h)} fields ({args.ny}x{args.nx}), compress + decompress, "
+               "sample": f"{done} of {len(stack_h)} fields ({args.ny}x{args.nx}), compress + decompress, "
                          f"single thread, {el:.1f} s"}
 
     out = {
@@ -193,11 +301,12 @@ def main():
         "config": {"workload": f"ERA5-shaped stack, plain per-field path: {len(xs)} fields {args.ny}x{args.nx} "
                                f"(37 levels x t,u,v,q), eps_rel {args.eps}, r {args.ratio}, L 5, 32x32 blocks",
                    "fields": len(xs), "ny": args.ny, "nx": args.nx, "eps_rel": args.eps, "base_ratio": args.ratio},
-        "compress_GBps": comp_gbps, "decompress_GBps": dec_gbps, "CR": cr, "violations": viol,
-        "max_err_rel": max_rel,
+        "compress_GBps": nbytes * steps / tc / 1e9, "decompress_GBps": nbytes * steps / td / 1e9,
+        "CR": nbytes / stream_bytes, "violations": viol, "max_err_rel": max_rel,
         "compress_ms_p50": pct(lat_c, 50) * 1e3, "compress_ms_p99": pct(lat_c, 99) * 1e3,
         "decompress_ms_p50": pct(lat_d, 50) * 1e3, "decompress_ms_p99": pct(lat_d, 99) * 1e3,
         "stages_ms_per_step": {k: v[0] / steps for k, v in stages.items()},
+        "batched": batched,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -92,6 +92,47 @@ int ebcc_compress(const float* d_x, size_t ny, size_t nx, const ebcc_params* p,
 int ebcc_decompress(const uint8_t* d_in, size_t in_len, float* d_x, size_t ny, size_t nx,
                     void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched execution.  A climate dataset is many 2-D fields of uneven sizes
+ * (the paper compresses each variable/level slice independently; Benchmarks
+ * section), and one small field does not fill the GPU.  These entry points
+ * run every stage of the pipeline once over all fields of the batch: one
+ * launch per stage covers every field's code-blocks, SPIHT tiles and DWT
+ * tiles, and the per-field truncation searches of Algorithm 1 advance in
+ * lockstep (one launch and one read-back per search round for the batch).
+ * Each field's stream is byte-identical to what ebcc_compress /
+ * ebcc_decompress produce for it alone.  Large batches are processed in
+ * chunks of at most 2^26 samples or 4096 fields.
+ * ------------------------------------------------------------------------- */
+
+/* Compress n fields.
+ *   d_x[i]        device pointer of field i, [ny[i]][nx[i]] float32 (host
+ *                 arrays d_x, ny, nx of n entries).
+ *   err_bounds    host [n]: per-field error bound (same bound_mode), or NULL
+ *                 for p->err_bound for every field.
+ *   p             shared parameters (host); NULL = defaults.
+ *   d_out         device buffer of out_cap bytes; the streams are written
+ *                 back to back in field order.
+ *   h_offsets, h_lengths  host [n]: byte offset in d_out and length of each
+ *                 stream.
+ * out_cap >= sum of ebcc_compress_bound(ny[i], nx[i]) always suffices; a
+ * smaller buffer may fail with EBCC_ENOSPC after earlier chunks were
+ * written.  Errors of one field (non-finite input, bad size) fail the call.
+ * Synchronises `stream`. */
+int ebcc_compress_batch(int n, const float* const* d_x, const size_t* ny, const size_t* nx,
+                        const double* err_bounds, const ebcc_params* p, uint8_t* d_out,
+                        size_t out_cap, uint64_t* h_offsets, uint64_t* h_lengths, void* stream);
+
+/* Decompress n streams: d_in[i] (device, in_len[i] bytes) into d_x[i]
+ * [ny[i]][nx[i]] float32.  h_status (host [n], may be NULL) receives each
+ * stream's status; a stream that is corrupt or does not match its size is
+ * reported there and the others are still decoded.  Streams decoded in one
+ * chunk must share the code-block size (EBCC_EINVAL for the odd ones
+ * otherwise).  Returns the first error, or EBCC_OK.  Synchronises `stream`. */
+int ebcc_decompress_batch(int n, const uint8_t* const* d_in, const size_t* in_len,
+                          float* const* d_x, const size_t* ny, const size_t* nx, int* h_status,
+                          void* stream);
+
 /* Header fields of a stream, read from host memory (the first 48 bytes). */
 int ebcc_stream_info(const uint8_t* h_hdr, size_t len, size_t* ny, size_t* nx, int* mode);
 

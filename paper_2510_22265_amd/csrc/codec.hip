@@ -89,8 +89,10 @@ struct Prof {
   }
 };
 
+
 // ---------------------------------------------------------------------------
-// Small kernels
+// Small kernels (every one takes the call's field table; field = blockIdx.y
+// or one thread per field)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned f2o(float f) {
   unsigned u = __float_as_uint(f);
@@ -100,14 +102,21 @@ __device__ __forceinline__ float o2f(unsigned u) {
   return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
 }
 
-__global__ void k_init_fp(FieldParams* fp, int* flags, int nflags) {
-  fp->xmin_bits = 0xFFFFFFFFu;
-  fp->xmax_bits = 0u;
-  fp->nonfinite = 0;
-  for (int i = 0; i < nflags; i++) flags[i] = 0;
+__global__ void k_init_fields(const FieldDev* __restrict__ F, int nf) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  const FieldDev& f = F[i];
+  f.fp->xmin_bits = 0xFFFFFFFFu;
+  f.fp->xmax_bits = 0u;
+  f.fp->nonfinite = 0;
+  for (int k = 0; k < 8; k++) { f.flags[k] = 0; f.u32s[k] = 0; f.totals[k] = 0; }
 }
 
-__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int n, FieldParams* fp) {
+__global__ __launch_bounds__(256) void k_minmax(const FieldDev* __restrict__ F) {
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active) return;
+  const int n = f.ny * f.nx;
+  const float* x = f.buf[BUF_X];
   unsigned mn = 0xFFFFFFFFu, mx = 0u;
   int nf = 0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
@@ -125,22 +134,25 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int
     nf |= c;
   }
   if ((threadIdx.x & 63) == 0) {
-    atomicMin(&fp->xmin_bits, mn);
-    atomicMax(&fp->xmax_bits, mx);
-    if (nf) atomicOr(&fp->nonfinite, 1);
+    atomicMin(&f.fp->xmin_bits, mn);
+    atomicMax(&f.fp->xmax_bits, mx);
+    if (nf) atomicOr(&f.fp->nonfinite, 1);
   }
 }
 
 // Field scalars (range, bound, quantiser exponents) from min and max.
 // eps is range-relative (Benchmarks section) or absolute.
-__global__ void k_params(FieldParams* fp, double err, int bound_mode) {
+__global__ void k_params(const FieldDev* __restrict__ F, int nfields) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfields || !F[i].active) return;
+  FieldParams* fp = F[i].fp;
   float xmin = o2f(fp->xmin_bits), xmax = o2f(fp->xmax_bits);
   if (xmin == 0.0f) xmin = 0.0f;   // +0 for a zero extreme
   if (xmax == 0.0f) xmax = 0.0f;
   fp->xmin = xmin;
   fp->xmax = xmax;
   double range_d = (double)xmax - (double)xmin;
-  double eps = bound_mode == EBCC_BOUND_REL ? err * range_d : err;
+  double eps = F[i].bound_mode == EBCC_BOUND_REL ? F[i].err * range_d : F[i].err;
   fp->range_d = range_d;
   fp->eps = eps;
   fp->range_f = 0.0f;
@@ -163,25 +175,42 @@ __global__ void k_params(FieldParams* fp, double err, int bound_mode) {
   fp->inv_f = (float)(1.0 / range_d);
 }
 
-__global__ void k_set_decode_params(FieldParams* fp, float xmin, float range_f, int* flags, int nflags) {
-  fp->xmin = xmin;
-  fp->range_f = range_f;
-  fp->inv_f = 0.0f;
-  fp->eps = 0.0;
-  for (int i = 0; i < nflags; i++) flags[i] = 0;
+// Decoder: header scalars into the field's parameters; flags cleared.
+__global__ void k_set_decode(const FieldDev* __restrict__ F, int nfields, const float* __restrict__ xr) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfields) return;
+  const FieldDev& f = F[i];
+  f.fp->xmin = xr[2 * i];
+  f.fp->range_f = xr[2 * i + 1];
+  f.fp->inv_f = 0.0f;
+  f.fp->eps = 0.0;
+  for (int k = 0; k < 8; k++) { f.flags[k] = 0; f.u32s[k] = 0; f.totals[k] = 0; }
 }
 
-__global__ void k_zero_int(int* p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+__global__ void k_zero_slot(const FieldDev* __restrict__ F, int nfields, int which) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfields || !F[i].active) return;
+  if (which == 0) F[i].flags[0] = 0;
+  else F[i].u32s[0] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, int n, float v) {
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
+// Fill buf[which] with v (which = BUF_XOUT and v = NaN: fill with xmin).
+__global__ __launch_bounds__(256) void k_fill(const FieldDev* __restrict__ F, int which, float v) {
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active) return;
+  const int n = f.ny * f.nx;
+  float val = (v != v) ? f.fp->xmin : v;
+  float* p = f.buf[which];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = val;
 }
 
 // Residual quantisation q_r = floor(|c| * 2^-e_r) (capped), sign in bit 31.
-__global__ __launch_bounds__(256) void k_quant_res(const float* __restrict__ c, int n, int er, uint32_t* __restrict__ qr,
-                                                   unsigned* __restrict__ qmax) {
+__global__ __launch_bounds__(256) void k_quant_res(const FieldDev* __restrict__ F) {
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active) return;
+  const int n = f.ny * f.nx, er = f.er;
+  const float* c = f.buf[BUF_CRES];
+  uint32_t* qr = f.qr;
   unsigned mx = 0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     float v = c[i];
@@ -193,13 +222,17 @@ __global__ __launch_bounds__(256) void k_quant_res(const float* __restrict__ c, 
     unsigned a = __shfl_xor(mx, off);
     mx = a > mx ? a : mx;
   }
-  if ((threadIdx.x & 63) == 0) atomicMax(qmax, mx);
+  if ((threadIdx.x & 63) == 0) atomicMax(&f.u32s[0], mx);
 }
 
 // Residual coefficients kept by truncation at the end of plane n_s, midpoint
 // reconstructed: what the SPIHT decoder recovers from planes n_max .. n_s.
-__global__ __launch_bounds__(256) void k_dequant_res(const uint32_t* __restrict__ qr, int n, int ns, int er,
-                                                     float* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_dequant_res(const FieldDev* __restrict__ F) {
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active) return;
+  const int n = f.ny * f.nx, ns = f.ns, er = f.er;
+  const uint32_t* qr = f.qr;
+  float* out = f.buf[BUF_CHAT];
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     uint32_t v = qr[i], q = v & 0x7FFFFFu;
     uint32_t m = (q >> ns) << ns;
@@ -207,16 +240,34 @@ __global__ __launch_bounds__(256) void k_dequant_res(const uint32_t* __restrict_
   }
 }
 
-// Exclusive scan of n 32-bit lengths (len = (v >> shift) & mask) in one
-// workgroup; off[i] = sum of the lengths before i; *total = sum of all.
-__global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ v, int n, int shift, uint32_t mask,
-                                               int64_t* __restrict__ off, int64_t* __restrict__ total) {
+// Small per-field results gathered for one device-to-host copy:
+// violation flag, corruption flag, residual max, checksum, base and residual
+// payload bytes, parameters mode.
+__global__ void k_collect(const FieldDev* __restrict__ F, int nfields, int64_t* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfields) return;
+  const FieldDev& f = F[i];
+  int64_t* o = out + 8 * i;
+  o[0] = f.flags[0]; o[1] = f.flags[1]; o[2] = f.u32s[0]; o[3] = f.u32s[1];
+  o[4] = f.totals[0]; o[5] = f.totals[1]; o[6] = 0; o[7] = 0;
+}
+
+// Exclusive scan of a field's 32-bit lengths (len = (v >> shift) & mask);
+// which = 0: its code-blocks (total -> totals[0]), 1: its tiles (totals[1]).
+__global__ __launch_bounds__(1024) void k_scan(const FieldDev* __restrict__ F, const uint32_t* __restrict__ v_g,
+                                               int which, int shift, uint32_t mask, int64_t* __restrict__ off_g) {
+  const FieldDev& f = F[blockIdx.x];
+  if (!f.active) return;
   __shared__ int64_t part[1024];
+  const int b0 = which ? f.tile0 : f.blk0;
+  const int n = which ? f.ntiles : f.nblk;
+  const uint32_t* v = v_g + b0;
+  int64_t* off = off_g + b0;
   int tid = threadIdx.x;
   int per = (n + 1023) / 1024;
-  int b0 = tid * per, b1 = b0 + per < n ? b0 + per : n;
+  int i0 = tid * per, i1 = i0 + per < n ? i0 + per : n;
   int64_t s = 0;
-  for (int i = b0; i < b1; i++) s += (int64_t)((v[i] >> shift) & mask);
+  for (int i = i0; i < i1; i++) s += (int64_t)((v[i] >> shift) & mask);
   part[tid] = s;
   __syncthreads();
   for (int d = 1; d < 1024; d <<= 1) {
@@ -226,11 +277,11 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ v, i
     __syncthreads();
   }
   int64_t run = part[tid] - s;
-  for (int i = b0; i < b1; i++) {
+  for (int i = i0; i < i1; i++) {
     off[i] = run;
     run += (int64_t)((v[i] >> shift) & mask);
   }
-  if (tid == 1023) *total = part[1023];
+  if (tid == 1023) f.totals[which] = part[1023];
 }
 
 // Block table entries (P_b | k_b << 8 | len << 16) of the coded stream.
@@ -241,53 +292,90 @@ __global__ __launch_bounds__(256) void k_block_entries(const uint8_t* __restrict
     ent[b] = (uint32_t)pb[b] | ((uint32_t)kb[b] << 8) | ((uint32_t)len[b] << 16);
 }
 
-__global__ __launch_bounds__(256) void k_put_table(const uint32_t* __restrict__ ent, int n, uint8_t* __restrict__ out) {
-  for (int b = blockIdx.x * 256 + threadIdx.x; b < n; b += gridDim.x * 256) {
-    uint32_t v = ent[b];
-    out[4 * b] = (uint8_t)v;
-    out[4 * b + 1] = (uint8_t)(v >> 8);
-    out[4 * b + 2] = (uint8_t)(v >> 16);
-    out[4 * b + 3] = (uint8_t)(v >> 24);
+__device__ __forceinline__ void put32(uint8_t* p, uint32_t v) {
+  p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); p[2] = (uint8_t)(v >> 16); p[3] = (uint8_t)(v >> 24);
+}
+__device__ __forceinline__ uint32_t get32(const uint8_t* p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+// Block table of each field's stream.
+__global__ __launch_bounds__(256) void k_put_blocks(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                    const uint32_t* __restrict__ ent, int nblk) {
+  for (int b = blockIdx.x * 256 + threadIdx.x; b < nblk; b += gridDim.x * 256) {
+    const FieldDev& f = F[blk[b].field];
+    if (!f.active) continue;
+    put32(f.out + kHdr + 4 * (size_t)(b - f.blk0), ent[b]);
   }
 }
 
 // Terminated codewords: bytes before the termination point from the
 // encoder's buffer, then the bytes the termination of pass k_b writes.
-__global__ __launch_bounds__(256) void k_gather_cw(const uint8_t* __restrict__ cw, const uint8_t* __restrict__ kb,
+__global__ __launch_bounds__(256) void k_gather_cw(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                   const uint8_t* __restrict__ cw, const uint8_t* __restrict__ kb,
                                                    const int32_t* __restrict__ len, const int32_t* __restrict__ bpt,
-                                                   const uint32_t* __restrict__ tailt, const int64_t* __restrict__ off,
-                                                   int nblk, uint8_t* __restrict__ out) {
+                                                   const uint32_t* __restrict__ tailt,
+                                                   const int64_t* __restrict__ off, int nblk) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int b = blockIdx.x * 4 + wave; b < nblk; b += gridDim.x * 4) {
+    const FieldDev& f = F[blk[b].field];
     int k = kb[b], n = len[b];
-    if (!k) continue;
+    if (!f.active || !k) continue;
     int bp = bpt[(size_t)b * kPassStride + k];
     uint32_t tl = tailt[(size_t)b * kPassStride + k];
     const uint8_t* src = cw + (size_t)b * kCwCap;
-    uint8_t* dst = out + off[b];
+    uint8_t* dst = f.out + kHdr + 4 * (size_t)f.nblk + off[b];
     for (int j = lane; j < n; j += 64) dst[j] = j < bp ? src[j] : (uint8_t)(tl >> (8 * (j - bp)));
   }
 }
 
-__global__ __launch_bounds__(256) void k_gather_tiles(const uint8_t* __restrict__ slots, const int64_t* __restrict__ slot_off,
-                                                      const uint32_t* __restrict__ tlen, const int64_t* __restrict__ off,
-                                                      int nt, uint8_t* __restrict__ out) {
+// Tile table and tile payloads of each field with a residual section.
+__global__ __launch_bounds__(256) void k_put_tiles(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
+                                                   const uint32_t* __restrict__ tent, int nt) {
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < nt; t += gridDim.x * 256) {
+    const FieldDev& f = F[tiles[t].field];
+    if (!f.active || f.rb == 0) continue;
+    put32(f.out + kHdr + f.bb + 4 * (size_t)(t - f.tile0), tent[t]);
+  }
+}
+__global__ __launch_bounds__(256) void k_gather_tiles(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
+                                                      const uint8_t* __restrict__ slots,
+                                                      const int64_t* __restrict__ slot_off,
+                                                      const uint32_t* __restrict__ tlen,
+                                                      const int64_t* __restrict__ off, int nt) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int t = blockIdx.x * 4 + wave; t < nt; t += gridDim.x * 4) {
+    const FieldDev& f = F[tiles[t].field];
+    if (!f.active || f.rb == 0) continue;
     int64_t cap = slot_off[t + 1] - slot_off[t];
     int n = (int)((int64_t)tlen[t] < cap ? (int64_t)tlen[t] : cap);
     const uint8_t* src = slots + slot_off[t];
-    uint8_t* dst = out + off[t];
+    uint8_t* dst = f.out + kHdr + f.bb + 4 * (size_t)f.ntiles + off[t];
     for (int j = lane; j < n; j += 64) dst[j] = src[j];
   }
 }
 
+// Raw streams: the field's samples after the header.
+__global__ __launch_bounds__(256) void k_copy_raw(const FieldDev* __restrict__ F, int to_stream) {
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active) return;
+  const int n = f.ny * f.nx;
+  uint32_t* s = reinterpret_cast<uint32_t*>(f.out + kHdr);
+  float* x = f.buf[to_stream ? BUF_X : BUF_XOUT];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    if (to_stream) put32(f.out + kHdr + 4 * (size_t)i, __float_as_uint(x[i]));
+    else x[i] = __uint_as_float(get32(f.out + kHdr + 4 * (size_t)i));
+  }
+  (void)s;
+}
+
 // Stream checksum: sum over the little-endian 32-bit words w_k of the bytes
 // after the header (zero padded) of w_k * (2k + 1), modulo 2^32.
-__global__ __launch_bounds__(256) void k_checksum(const uint8_t* __restrict__ p, const int64_t* __restrict__ total_dev,
-                                                  int64_t total_host, unsigned* __restrict__ sum) {
-  int64_t n = (total_dev ? *total_dev : total_host) - kHdr;
-  const uint8_t* q = p + kHdr;
+__global__ __launch_bounds__(256) void k_checksum(const FieldDev* __restrict__ F) {
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active) return;
+  int64_t n = f.len - kHdr;
+  const uint8_t* q = f.out + kHdr;
   int64_t nw = (n + 3) / 4;
   unsigned s = 0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nw; k += (int64_t)gridDim.x * 256) {
@@ -297,43 +385,56 @@ __global__ __launch_bounds__(256) void k_checksum(const uint8_t* __restrict__ p,
     s += w * (uint32_t)(2 * k + 1);
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if ((threadIdx.x & 63) == 0) atomicAdd(sum, s);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&f.u32s[1], s);
 }
 
-__device__ __forceinline__ void put32(uint8_t* p, uint32_t v) {
-  p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); p[2] = (uint8_t)(v >> 16); p[3] = (uint8_t)(v >> 24);
-}
-__global__ void k_header(uint8_t* o, const FieldParams* fp, int mode, int L, int cbl, int ny, int nx, int er, int nmax,
-                         int ns, int T, uint32_t bb, uint32_t rb, const unsigned* csum) {
-  for (int i = 0; i < kHdr; i++) o[i] = 0;
+__global__ void k_header(const FieldDev* __restrict__ F, int nfields) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfields || !F[i].active) return;
+  const FieldDev& f = F[i];
+  uint8_t* o = f.out;
+  const int mode = f.mode;
+  for (int k = 0; k < kHdr; k++) o[k] = 0;
   o[0] = 'E'; o[1] = 'B'; o[2] = 'C'; o[3] = 'C';
-  o[4] = 1; o[5] = (uint8_t)mode; o[6] = (uint8_t)L; o[7] = (uint8_t)cbl;
-  put32(o + 8, (uint32_t)ny);
-  put32(o + 12, (uint32_t)nx);
-  put32(o + 16, __float_as_uint(fp->xmin));
-  put32(o + 20, __float_as_uint(mode == MODE_CONST ? 0.0f : fp->range_f));
-  put32(o + 24, __float_as_uint(mode == MODE_CONST ? 0.0f : fp->inv_f));
-  o[28] = (uint8_t)(int8_t)(mode == MODE_CODED ? fp->e0 : 0);
-  o[29] = (uint8_t)(int8_t)er;
-  o[30] = (uint8_t)(int8_t)nmax;
-  o[31] = (uint8_t)(int8_t)ns;
-  o[32] = (uint8_t)T; o[33] = (uint8_t)(T >> 8);
-  put32(o + 36, bb);
-  put32(o + 40, rb);
-  put32(o + 44, *csum);
+  o[4] = 1; o[5] = (uint8_t)mode; o[6] = (uint8_t)(mode == MODE_CODED ? f.L : 0); o[7] = (uint8_t)f.cbl;
+  put32(o + 8, (uint32_t)f.ny);
+  put32(o + 12, (uint32_t)f.nx);
+  put32(o + 16, __float_as_uint(f.fp->xmin));
+  put32(o + 20, __float_as_uint(mode == MODE_CONST ? 0.0f : f.fp->range_f));
+  put32(o + 24, __float_as_uint(mode == MODE_CONST ? 0.0f : f.fp->inv_f));
+  o[28] = (uint8_t)(int8_t)(mode == MODE_CODED ? f.e0 : 0);
+  o[29] = (uint8_t)(int8_t)(mode == MODE_CODED && f.rb ? f.er : 0);
+  o[30] = (uint8_t)(int8_t)(mode == MODE_CODED && f.rb ? f.nmax : -1);
+  o[31] = (uint8_t)(int8_t)(mode == MODE_CODED && f.rb ? f.ns : 0);
+  o[32] = (uint8_t)f.T; o[33] = (uint8_t)(f.T >> 8);
+  put32(o + 36, f.bb);
+  put32(o + 40, f.rb);
+  put32(o + 44, f.u32s[1]);
 }
 
-// Decoder: offsets and validity of the base block table and the tile table.
-__global__ __launch_bounds__(256) void k_check_tables(const uint8_t* __restrict__ in, int nblk, int64_t bb,
-                                                      const int64_t* __restrict__ btot, int* __restrict__ flag) {
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    if (*btot != bb - 4 * (int64_t)nblk) atomicOr(flag, 1);
+// Decoder: table entries and consistency of the block and tile tables.
+__global__ __launch_bounds__(256) void k_read_blocks(const FieldDev* __restrict__ F, const Blk* __restrict__ blk, int nblk,
+                                                     uint32_t* __restrict__ ent) {
+  for (int b = blockIdx.x * 256 + threadIdx.x; b < nblk; b += gridDim.x * 256) {
+    const FieldDev& f = F[blk[b].field];
+    ent[b] = f.active ? get32(f.out + kHdr + 4 * (size_t)(b - f.blk0)) : 0u;
+  }
 }
-__global__ __launch_bounds__(256) void k_read_table(const uint8_t* __restrict__ tab, int n, uint32_t* __restrict__ ent) {
-  for (int b = blockIdx.x * 256 + threadIdx.x; b < n; b += gridDim.x * 256)
-    ent[b] = (uint32_t)tab[4 * b] | ((uint32_t)tab[4 * b + 1] << 8) | ((uint32_t)tab[4 * b + 2] << 16) |
-             ((uint32_t)tab[4 * b + 3] << 24);
+__global__ __launch_bounds__(256) void k_read_tiles(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
+                                                    int nt, uint32_t* __restrict__ ent) {
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < nt; t += gridDim.x * 256) {
+    const FieldDev& f = F[tiles[t].field];
+    ent[t] = (f.active && f.rb) ? get32(f.out + kHdr + f.bb + 4 * (size_t)(t - f.tile0)) : 0u;
+  }
 }
+__global__ void k_check_tables(const FieldDev* __restrict__ F, int nfields) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfields || !F[i].active) return;
+  const FieldDev& f = F[i];
+  if (f.totals[0] != (int64_t)f.bb - 4 * (int64_t)f.nblk) f.flags[1] = 1;
+  if (f.rb && f.totals[1] != (int64_t)f.rb - 4 * (int64_t)f.ntiles) f.flags[1] = 1;
+}
+
 
 // ---------------------------------------------------------------------------
 // Plans: per-shape geometry on the host and on the device.
@@ -384,7 +485,7 @@ static int build_plan(Plan& p) {
   for (const Band& b : p.bands)
     for (int by = 0; by < b.h; by += p.cbh)
       for (int bx = 0; bx < b.w; bx += p.cbw)
-        p.blks.push_back(Blk{b.y0 + by, b.x0 + bx, std::min(p.cbw, b.w - bx), std::min(p.cbh, b.h - by), b.orient, b.gain});
+        p.blks.push_back(Blk{b.y0 + by, b.x0 + bx, std::min(p.cbw, b.w - bx), std::min(p.cbh, b.h - by), b.orient, b.gain, 0});
   p.nblk = (int)p.blks.size();
   // SPIHT tiles: T x T LL roots and the rectangles their trees cover per band
   int hL = h[L], wL = w[L], T = p.T;
@@ -415,7 +516,7 @@ static int build_plan(Plan& p) {
       t.ncoef = (int)n;
       p.max_tile_coef = std::max(p.max_tile_coef, (int)n);
       p.max_tile_parents = std::max(p.max_tile_parents, (int)(L > 0 ? n - n1 : 0));
-      t.pad = 0;
+      t.field = 0;
       off += n;
       soff += 12 * n + 16;
       p.tiles.push_back(t);
@@ -464,13 +565,26 @@ static int get_plan(int ny, int nx, int L, int cbl2w, int cbl2h, int T, Plan** o
   return EBCC_OK;
 }
 
+
 // ---------------------------------------------------------------------------
 // Workspaces: one device allocation per (device, stream), carved per call.
 // ---------------------------------------------------------------------------
+// Host-to-device copies of a call go through the workspace's pinned staging
+// buffer (the host source of an asynchronous copy must outlive it); the
+// event recorded at the end of each call guards the buffer's reuse.
 struct WS {
   void* base = nullptr;
   size_t cap = 0;
-  ~WS() { if (base) (void)hipFree(base); }
+  uint8_t* pin = nullptr;
+  size_t pin_cap = 0;
+  hipEvent_t ev = nullptr;
+  bool ev_live = false;
+  ~WS() {
+    if (ev_live) (void)hipEventSynchronize(ev);
+    if (base) (void)hipFree(base);
+    if (pin) (void)hipHostFree(pin);
+    if (ev) (void)hipEventDestroy(ev);
+  }
 };
 typedef std::pair<int, hipStream_t> WSKey;
 static std::map<WSKey, std::unique_ptr<WS>> g_ws;
@@ -486,59 +600,34 @@ struct Carve {
   }
 };
 
-struct Bufs {
-  FieldParams* fp;
-  int* flags;            // [0] check violation, [1] decode corruption
-  unsigned* u32s;        // [0] qmax, [1] checksum
-  int64_t* totals;       // [0] base payload, [1] resid payload, [2] stream total
-  float *coef, *tmp, *yhat, *abase, *cres, *chat;
-  uint32_t *qr, *sub, *maxd, *maxl;
-  void *planes, *signs, *sppf;
-  uint8_t *pb, *kb, *hk, *nh, *cw, *slots;
-  int32_t *R, *bpt, *dr, *len;
-  int64_t *D, *boff, *toff;
-  uint64_t *keys, *lists;
-  uint32_t *tail, *tlen, *tent, *bent;
-  int* misfit;
-};
-
-static size_t layout(const Plan& p, Bufs* b, char* base) {
-  Carve c{base, 0};
-  size_t N = (size_t)p.ny * p.nx;
-  size_t ms = p.cbw <= 32 ? 4 : 8;
-  size_t nb = p.nblk, nt = p.ntiles;
-  b->fp = c.take<FieldParams>(1);
-  b->flags = c.take<int>(8);
-  b->u32s = c.take<unsigned>(8);
-  b->totals = c.take<int64_t>(8);
-  b->coef = c.take<float>(N); b->tmp = c.take<float>(N); b->yhat = c.take<float>(N);
-  b->abase = c.take<float>(N); b->cres = c.take<float>(N); b->chat = c.take<float>(N);
-  b->qr = c.take<uint32_t>(N); b->sub = c.take<uint32_t>(N); b->maxd = c.take<uint32_t>(N); b->maxl = c.take<uint32_t>(N);
-  b->planes = c.take<char>(nb * kQBits * p.cbh * ms);
-  b->signs = c.take<char>(nb * p.cbh * ms);
-  b->sppf = c.take<char>(nb * p.cbh * ms);
-  b->pb = c.take<uint8_t>(nb); b->kb = c.take<uint8_t>(nb); b->nh = c.take<uint8_t>(nb);
-  b->hk = c.take<uint8_t>(nb * kPassStride);
-  b->R = c.take<int32_t>(nb * kPassStride); b->bpt = c.take<int32_t>(nb * kPassStride);
-  b->dr = c.take<int32_t>(nb * kPassStride); b->len = c.take<int32_t>(nb);
-  b->D = c.take<int64_t>(nb * kPassStride); b->keys = c.take<uint64_t>(nb * kPassStride);
-  b->tail = c.take<uint32_t>(nb * kPassStride);
-  b->boff = c.take<int64_t>(nb); b->bent = c.take<uint32_t>(nb);
-  b->cw = c.take<uint8_t>(nb * (size_t)kCwCap);
-  b->tlen = c.take<uint32_t>(nt); b->tent = c.take<uint32_t>(nt); b->toff = c.take<int64_t>(nt);
-  b->misfit = c.take<int>(nt);
-  b->lists = c.take<uint64_t>(4 * N);
-  b->slots = c.take<uint8_t>((size_t)p.slot_off.back());
-  return c.used + 256;
-}
-
-static int get_ws(const Plan& p, hipStream_t st, Bufs* b) {
+static int get_ws(hipStream_t st, WS** out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  size_t need = layout(p, b, nullptr);
   std::lock_guard<std::mutex> lk(g_mu);
   std::unique_ptr<WS>& w = g_ws[WSKey(dev, st)];
-  if (!w) w.reset(new WS());
+  if (!w) {
+    w.reset(new WS());
+    HIPCHK(hipEventCreateWithFlags(&w->ev, hipEventDisableTiming));
+  }
+  // the previous call's staged copies must have left the pinned buffer
+  if (w->ev_live) HIPCHK(hipEventSynchronize(w->ev));
+  w->ev_live = false;
+  *out = w.get();
+  return EBCC_OK;
+}
+
+static int grow_ws(WS* w, size_t need, size_t pin_need, hipStream_t st, char** base) {
+  if (w->pin_cap < pin_need) {
+    if (w->pin) HIPCHK(hipHostFree(w->pin));
+    w->pin = nullptr;
+    w->pin_cap = 0;
+    size_t alloc = std::max<size_t>(pin_need, 1 << 20);
+    if (hipHostMalloc((void**)&w->pin, alloc, hipHostMallocDefault) != hipSuccess) {
+      w->pin = nullptr;
+      return fail(EBCC_ENOMEM, "pinned staging allocation failed");
+    }
+    w->pin_cap = alloc;
+  }
   if (w->cap < need) {
     if (w->base) {
       HIPCHK(hipStreamSynchronize(st));
@@ -546,32 +635,34 @@ static int get_ws(const Plan& p, hipStream_t st, Bufs* b) {
       w->base = nullptr;
       w->cap = 0;
     }
-    hipError_t e = hipMalloc(&w->base, need);
+    size_t alloc = need + need / 8;
+    hipError_t e = hipMalloc(&w->base, alloc);
     if (e != hipSuccess) { w->base = nullptr; return fail(EBCC_ENOMEM, "workspace allocation failed"); }
-    w->cap = need;
+    w->cap = alloc;
   }
-  layout(p, b, (char*)w->base);
+  *base = (char*)w->base;
   return EBCC_OK;
 }
+
+// LDS capacity class shared by the tiles of a call: the largest class, or
+// 0 (global-memory kernels) as soon as one field's tiles do not fit.
+static int merge_cap(int a, int b) { return (a == 0 || b == 0) ? 0 : std::max(a, b); }
+
+// Batches are processed in chunks of at most this many samples or fields.
+constexpr size_t kChunkSamples = size_t(1) << 26;
+constexpr int kChunkFields = 4096;
 
 static int grid_for(size_t n) {
   size_t g = (n + 255) / 256;
-  if (g > 4096) g = 4096;
+  if (g > 2048) g = 2048;
   return g < 1 ? 1 : (int)g;
 }
 
-template <typename T>
-static int d2h(T* h, const T* d, size_t n, hipStream_t st) {
-  HIPCHK(hipMemcpyAsync(h, d, sizeof(T) * n, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return EBCC_OK;
-}
-
-static int check_params(size_t ny, size_t nx, const ebcc_params* p) {
+static int check_params(size_t ny, size_t nx, const ebcc_params* p, double err) {
   if (ny < 1 || nx < 1 || ny > (1u << 24) || nx > (1u << 24) || ny * nx > 0x7FFFFFFFull)
     return fail(EBCC_EINVAL, "field dimensions out of range");
   if (p->struct_size != sizeof(ebcc_params)) return fail(EBCC_EINVAL, "ebcc_params.struct_size mismatch");
-  if (!(p->err_bound > 0) || !std::isfinite(p->err_bound)) return fail(EBCC_EINVAL, "err_bound must be > 0 and finite");
+  if (!(err > 0) || !std::isfinite(err)) return fail(EBCC_EINVAL, "err_bound must be > 0 and finite");
   if (p->bound_mode > 1) return fail(EBCC_EINVAL, "bad bound_mode");
   if (!(p->base_ratio >= 1.0) || !std::isfinite(p->base_ratio)) return fail(EBCC_EINVAL, "base_ratio must be >= 1");
   if (p->levels > (unsigned)kMaxLevels) return fail(EBCC_EINVAL, "levels out of range");
@@ -588,199 +679,450 @@ struct Trace {
   int32_t* info;
 };
 
-// RAW stream: header + the input bytes.
-static int emit_raw(const float* x, size_t N, const Plan* pl, int cbl, int ny, int nx, int T, const Bufs& B, uint8_t* out,
-                    size_t cap, size_t* out_len, hipStream_t st) {
-  size_t total = kHdr + 4 * N;
-  *out_len = total;
-  if (total > cap) return fail(EBCC_ENOSPC, "output capacity too small");
-  (void)pl;
-  HIPCHK(hipMemcpyAsync(out + kHdr, x, 4 * N, hipMemcpyDeviceToDevice, st));
-  k_zero_int<<<1, 64, 0, st>>>((int*)B.u32s, 8);
-  k_checksum<<<grid_for(N), 256, 0, st>>>(out, nullptr, (int64_t)total, &B.u32s[1]);
-  k_header<<<1, 1, 0, st>>>(out, B.fp, MODE_RAW, 0, cbl, ny, nx, 0, -1, 0, T, (uint32_t)(4 * N), 0u, &B.u32s[1]);
-  HIPCHK(hipGetLastError());
+// One call over nf fields: the field table (host copy and device copy), the
+// concatenated code-blocks and tiles of the coded fields, and the carved
+// workspace.
+struct Call {
+  int nf = 0;
+  hipStream_t st = nullptr;
+  WS* ws = nullptr;
+  size_t pin_used = 0;
+  FieldParams* d_fp = nullptr;   // the fields' scalars, contiguous
+  std::vector<FieldDev> Fh;
+  std::vector<Plan*> plans;
+  FieldDev* F = nullptr;
+  // items of the coded fields
+  int nblk = 0, ntiles = 0;
+  const Blk* d_blk = nullptr;
+  const TileD* d_tiles = nullptr;
+  const int64_t* d_slot_off = nullptr;
+  bool need_lists = false;
+  int spiht_cap = 0, cbw = 32, cbh = 32;
+  // per-item arrays
+  void *planes, *signs, *sppf;
+  uint8_t *pb, *kb, *hk, *nh, *cw, *slots;
+  int32_t *R, *bpt, *dr, *len;
+  int64_t *D, *boff, *toff, *collect;
+  uint64_t *keys, *lists;
+  uint32_t *tail, *tlen, *tent, *bent;
+  int* misfit;
+  Blk* d_blk_own;
+  TileD* d_tiles_own;
+  int64_t* d_slot_own;
+
+  ~Call() {
+    if (ws && hipEventRecord(ws->ev, st) == hipSuccess) ws->ev_live = true;
+  }
+  // Asynchronous host-to-device copy through the pinned staging buffer.
+  int stage(void* dst, const void* src, size_t n) {
+    if (!n) return EBCC_OK;
+    size_t a = (pin_used + 255) & ~(size_t)255;
+    if (a + n > ws->pin_cap) {
+      HIPCHK(hipStreamSynchronize(st));
+      a = 0;
+    }
+    memcpy(ws->pin + a, src, n);
+    HIPCHK(hipMemcpyAsync(dst, ws->pin + a, n, hipMemcpyHostToDevice, st));
+    pin_used = a + n;
+    return EBCC_OK;
+  }
+  // Device-to-host copy and synchronisation (the staging buffer is free again).
+  template <typename T> int fetch(T* h, const T* d, size_t n) {
+    HIPCHK(hipMemcpyAsync(h, d, sizeof(T) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    pin_used = 0;
+    return EBCC_OK;
+  }
+  int upload() { return stage(F, Fh.data(), sizeof(FieldDev) * nf); }   // field table host -> device
+  int set_active(const std::vector<int>& act) {
+    for (int i = 0; i < nf; i++) Fh[i].active = act[i];
+    return upload();
+  }
+  int collect_host(std::vector<int64_t>& v) {
+    k_collect<<<(nf + 63) / 64, 64, 0, st>>>(F, nf, collect);
+    HIPCHK(hipGetLastError());
+    v.resize(8 * (size_t)nf);
+    return fetch(v.data(), collect, v.size());
+  }
+};
+
+// Lay out (base == nullptr: measure) the workspace of a call; every coded
+// field gets its buffers, items get their tables.
+static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
+  Carve cv{base, 0};
+  c.F = cv.take<FieldDev>(c.nf);
+  c.d_fp = cv.take<FieldParams>(c.nf);
+  int* flags = cv.take<int>(8 * (size_t)c.nf);
+  unsigned* u32s = cv.take<unsigned>(8 * (size_t)c.nf);
+  int64_t* totals = cv.take<int64_t>(8 * (size_t)c.nf);
+  for (int i = 0; i < c.nf; i++) {
+    FieldDev& f = c.Fh[i];
+    size_t N = (size_t)f.ny * f.nx;
+    f.fp = c.d_fp ? c.d_fp + i : nullptr;
+    f.flags = flags ? flags + 8 * i : nullptr;
+    f.u32s = u32s ? u32s + 8 * i : nullptr;
+    f.totals = totals ? totals + 8 * i : nullptr;
+    size_t nbuf = coded[i] ? N : 0;
+    for (int b = BUF_COEF; b <= BUF_CHAT; b++) f.buf[b] = cv.take<float>(nbuf);
+    f.qr = cv.take<uint32_t>(nbuf);
+    f.sub = cv.take<uint32_t>(nbuf);
+    f.maxd = cv.take<uint32_t>(nbuf);
+    f.maxl = cv.take<uint32_t>(nbuf);
+  }
+  size_t nb = c.nblk, nt = c.ntiles;
+  size_t ms = c.cbw <= 32 ? 4 : 8;
+  c.planes = cv.take<char>(nb * kQBits * c.cbh * ms);
+  c.signs = cv.take<char>(nb * c.cbh * ms);
+  c.sppf = cv.take<char>(nb * c.cbh * ms);
+  c.pb = cv.take<uint8_t>(nb); c.kb = cv.take<uint8_t>(nb); c.nh = cv.take<uint8_t>(nb);
+  c.hk = cv.take<uint8_t>(nb * kPassStride);
+  c.R = cv.take<int32_t>(nb * kPassStride); c.bpt = cv.take<int32_t>(nb * kPassStride);
+  c.dr = cv.take<int32_t>(nb * kPassStride); c.len = cv.take<int32_t>(nb);
+  c.D = cv.take<int64_t>(nb * kPassStride); c.keys = cv.take<uint64_t>(nb * kPassStride);
+  c.tail = cv.take<uint32_t>(nb * kPassStride);
+  c.boff = cv.take<int64_t>(nb); c.bent = cv.take<uint32_t>(nb);
+  c.cw = cv.take<uint8_t>(nb * (size_t)kCwCap);
+  c.tlen = cv.take<uint32_t>(nt); c.tent = cv.take<uint32_t>(nt); c.toff = cv.take<int64_t>(nt);
+  c.misfit = cv.take<int>(nt);
+  c.collect = cv.take<int64_t>(8 * (size_t)c.nf);
+  c.d_blk_own = cv.take<Blk>(nb);
+  c.d_tiles_own = cv.take<TileD>(nt);
+  c.d_slot_own = cv.take<int64_t>(nt + 1);
+  int64_t lists = 0, slots = 0;
+  for (int i = 0; i < c.nf; i++)
+    if (coded[i]) { lists += (int64_t)c.Fh[i].ny * c.Fh[i].nx; slots += c.plans[i]->slot_off.back(); }
+  c.lists = cv.take<uint64_t>(c.need_lists ? 4 * (size_t)lists : 0);
+  c.slots = cv.take<uint8_t>((size_t)slots);
+  return cv.used + 256;
+}
+
+// Largest single staged copy of a call, doubled (the staging buffer then
+// holds at least two copies before it has to wait).
+static size_t pin_need(const Call& c) {
+  size_t m = sizeof(FieldDev) * (size_t)c.nf;
+  m = std::max(m, sizeof(Blk) * (size_t)c.nblk);
+  m = std::max(m, sizeof(TileD) * (size_t)c.ntiles);
+  m = std::max(m, sizeof(int64_t) * ((size_t)c.ntiles + 1));
+  m = std::max(m, 2 * sizeof(float) * (size_t)c.nf);
+  return 2 * m + 4096;
+}
+
+// Concatenate the coded fields' blocks and tiles (a single field reuses its
+// plan's device tables).
+static int build_items(Call& c, const std::vector<int>& coded) {
+  int nb = 0, nt = 0;
+  std::vector<int> ci;
+  for (int i = 0; i < c.nf; i++)
+    if (coded[i]) ci.push_back(i);
+  for (int i : ci) {
+    c.Fh[i].blk0 = nb; c.Fh[i].nblk = c.plans[i]->nblk; nb += c.plans[i]->nblk;
+    c.Fh[i].tile0 = nt; c.Fh[i].ntiles = c.plans[i]->ntiles; nt += c.plans[i]->ntiles;
+  }
+  c.nblk = nb;
+  c.ntiles = nt;
   return EBCC_OK;
 }
 
-static int compress_impl(const float* x, size_t ny_, size_t nx_, const ebcc_params* pp, uint8_t* out, size_t cap,
-                         size_t* out_len, hipStream_t st, const Trace* tr) {
+static int upload_items(Call& c, const std::vector<int>& coded) {
+  std::vector<int> ci;
+  for (int i = 0; i < c.nf; i++)
+    if (coded[i]) ci.push_back(i);
+  if (ci.size() == 1 && ci[0] == 0) {
+    c.d_blk = c.plans[0]->d_blks;
+    c.d_tiles = c.plans[0]->d_tiles;
+    c.d_slot_off = c.plans[0]->d_slot_off;
+    return EBCC_OK;
+  }
+  std::vector<Blk> blks;
+  std::vector<TileD> tiles;
+  std::vector<int64_t> soff;
+  blks.reserve(c.nblk);
+  tiles.reserve(c.ntiles);
+  soff.reserve(c.ntiles + 1);
+  int64_t lo = 0, so = 0;
+  soff.push_back(0);
+  for (int i : ci) {
+    const Plan* p = c.plans[i];
+    for (Blk b : p->blks) { b.field = i; blks.push_back(b); }
+    for (size_t t = 0; t < p->tiles.size(); t++) {
+      TileD d = p->tiles[t];
+      d.field = i;
+      d.off += lo;
+      tiles.push_back(d);
+      soff.push_back(so + p->slot_off[t + 1]);
+    }
+    lo += (int64_t)p->ny * p->nx;
+    so += p->slot_off.back();
+  }
+  int rc;
+  if ((rc = c.stage(c.d_blk_own, blks.data(), sizeof(Blk) * blks.size()))) return rc;
+  if ((rc = c.stage(c.d_tiles_own, tiles.data(), sizeof(TileD) * tiles.size()))) return rc;
+  if ((rc = c.stage(c.d_slot_own, soff.data(), sizeof(int64_t) * soff.size()))) return rc;
+  c.d_blk = c.d_blk_own;
+  c.d_tiles = c.d_tiles_own;
+  c.d_slot_off = c.d_slot_own;
+  return EBCC_OK;
+}
+
+struct FieldIn {
+  const float* x;
+  size_t ny, nx;
+  double err;
+};
+
+// Compress nf fields; stream i goes to out + off[i] (compacted in field
+// order); lens[i] receives its length.  On ENOSPC *need holds the total.
+static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, uint8_t* out, size_t cap,
+                         std::vector<uint64_t>& offs, std::vector<uint64_t>& lens, size_t* need, hipStream_t st,
+                         const Trace* tr) {
   ebcc_params dflt;
   if (!pp) { ebcc_params_default(&dflt); pp = &dflt; }
-  if (!out_len) return fail(EBCC_EINVAL, "out_len is NULL");
-  *out_len = 0;
-  int rc = check_params(ny_, nx_, pp);
-  if (rc) return rc;
-  if (!x || !out) return fail(EBCC_EINVAL, "NULL buffer");
-  int ny = (int)ny_, nx = (int)nx_;
-  size_t N = (size_t)ny * nx;
-  int L = levels_eff(ny, nx, (int)pp->levels);
-  int cbl = (int)(pp->cblk_log2w | (pp->cblk_log2h << 4));
-  int T = (int)pp->spiht_tile;
-  Plan* pl;
-  rc = get_plan(ny, nx, L, pp->cblk_log2w, pp->cblk_log2h, T, &pl);
-  if (rc) return rc;
-  Bufs B;
-  rc = get_ws(*pl, st, &B);
-  if (rc) return rc;
-  int32_t info[11] = {0};
+  const int nf = (int)in.size();
+  *need = 0;
+  offs.assign(nf, 0);
+  lens.assign(nf, 0);
+  if (nf == 0) return EBCC_OK;
+  if (!out) return fail(EBCC_EINVAL, "NULL output buffer");
+  int rc;
+  for (int i = 0; i < nf; i++) {
+    if ((rc = check_params(in[i].ny, in[i].nx, pp, in[i].err))) return rc;
+    if (!in[i].x) return fail(EBCC_EINVAL, "NULL input buffer");
+  }
+  Call c;
+  c.nf = nf;
+  c.st = st;
+  c.Fh.assign(nf, FieldDev());
+  c.plans.assign(nf, nullptr);
+  c.cbw = 1 << pp->cblk_log2w;
+  c.cbh = 1 << pp->cblk_log2h;
+  const int cbl = (int)(pp->cblk_log2w | (pp->cblk_log2h << 4)), T = (int)pp->spiht_tile;
+  for (int i = 0; i < nf; i++) {
+    FieldDev& f = c.Fh[i];
+    memset(&f, 0, sizeof(f));
+    f.ny = (int)in[i].ny; f.nx = (int)in[i].nx;
+    f.L = levels_eff(f.ny, f.nx, (int)pp->levels);
+    f.buf[BUF_X] = const_cast<float*>(in[i].x);
+    f.err = in[i].err; f.bound_mode = (int)pp->bound_mode;
+    f.cbl = cbl; f.T = T; f.active = 1;
+    if ((rc = get_plan(f.ny, f.nx, f.L, pp->cblk_log2w, pp->cblk_log2h, T, &c.plans[i]))) return rc;
+    f.bands = c.plans[i]->d_bands;
+    f.nb = c.plans[i]->nb;
+  }
+  // every field is laid out as coded (the mode is known only on the device)
+  std::vector<int> coded(nf, 1);
+  build_items(c, coded);
+  c.spiht_cap = 1;
+  for (int i = 0; i < nf; i++) c.spiht_cap = merge_cap(c.spiht_cap, spiht_cap_for(c.plans[i]));
+  c.need_lists = c.spiht_cap == 0;
+  size_t need_ws = layout_call(c, nullptr, coded);
+  char* base;
+  if ((rc = get_ws(st, &c.ws))) return rc;
+  if ((rc = grow_ws(c.ws, need_ws, pin_need(c), st, &base))) return rc;
+  layout_call(c, base, coded);
   Prof prof(st);
 
-  // ---- scalars: min, max, range, eps, exponents ----
-  k_init_fp<<<1, 1, 0, st>>>(B.fp, B.flags, 8);
-  k_minmax<<<grid_for(N), 256, 0, st>>>(x, (int)N, B.fp);
-  k_params<<<1, 1, 0, st>>>(B.fp, pp->err_bound, (int)pp->bound_mode);
+  // ---- scalars of every field: min, max, range, eps, exponents ----
+  if ((rc = c.upload())) return rc;
+  k_init_fields<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
+  size_t maxN = 0;
+  for (auto& f : c.Fh) maxN = std::max(maxN, (size_t)f.ny * f.nx);
+  k_minmax<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+  k_params<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
   HIPCHK(hipGetLastError());
   prof.mark(S_SCALARS);
-  FieldParams fp;
-  if ((rc = d2h(&fp, B.fp, 1, st))) return rc;
-  if (fp.mode < 0) return fail(EBCC_EINVAL, "input contains non-finite values");
-  if (fp.mode == MODE_CONST) {
-    *out_len = kHdr;
-    if (cap < (size_t)kHdr) return fail(EBCC_ENOSPC, "output capacity too small");
-    k_zero_int<<<1, 64, 0, st>>>((int*)B.u32s, 8);
-    k_header<<<1, 1, 0, st>>>(out, B.fp, MODE_CONST, 0, cbl, ny, nx, 0, -1, 0, T, 0u, 0u, &B.u32s[1]);
-    HIPCHK(hipGetLastError());
-    if (tr && tr->info) { info[0] = MODE_CONST; memcpy(tr->info, info, sizeof(info)); }
-    return EBCC_OK;
+  std::vector<FieldParams> fps(nf);
+  if ((rc = c.fetch(fps.data(), c.d_fp, nf))) return rc;
+  std::vector<int> mode(nf);
+  for (int i = 0; i < nf; i++) {
+    if (fps[i].mode < 0) return fail(EBCC_EINVAL, "input field " + std::to_string(i) + " contains non-finite values");
+    mode[i] = fps[i].mode;
+    c.Fh[i].e0 = fps[i].e0;
   }
-  if (fp.mode == MODE_RAW) {
-    rc = emit_raw(x, N, pl, cbl, ny, nx, T, B, out, cap, out_len, st);
-    if (tr && tr->info) { info[0] = MODE_RAW; memcpy(tr->info, info, sizeof(info)); }
-    return rc;
+  // coded fields take part in the pipeline
+  std::vector<int> act(nf), resid(nf, 0), nmax(nf, -1), checks(nf, 0);
+  for (int i = 0; i < nf; i++) {
+    act[i] = mode[i] == MODE_CODED;
+    checks[i] = act[i];
+    int64_t tb = (int64_t)std::floor((double)(4.0 * (double)in[i].ny * (double)in[i].nx) / pp->base_ratio);
+    c.Fh[i].budget = std::max<int64_t>(0, tb - kHdr - 4 * (int64_t)c.plans[i]->nblk);
+    c.Fh[i].er = fps[i].elog - 6;
   }
-  const int e0 = fp.e0, elog = fp.elog;
-  DwtIO io{x, B.abase, nullptr, &B.flags[0], B.fp};
-
-  // ---- base layer: DWT of the normalised field, tier-1, PCRD at ratio r ----
-  dwt_forward(x, B.coef, B.tmp, ny, nx, L, PRO_NORM, io, st);
-  prof.mark(S_DWT);
-  quant_planes(B.coef, nx, pl->d_blks, pl->nblk, e0, pl->cbw, pl->cbh, B.planes, B.signs, B.pb, st);
-  prof.mark(S_QUANT);
-  t1_encode(B.coef, nx, pl->d_blks, pl->nblk, e0, pl->cbw, pl->cbh, B.planes, B.signs, B.pb, B.cw, B.R, B.D, B.bpt,
-            B.tail, B.sppf, st);
-  prof.mark(S_T1ENC);
-  int64_t total_budget = (int64_t)std::floor((double)(4.0 * (double)N) / pp->base_ratio);
-  int64_t budget = total_budget - kHdr - 4 * (int64_t)pl->nblk;
-  if (budget < 0) budget = 0;
-  pcrd(B.pb, B.R, B.D, pl->nblk, budget, B.kb, B.hk, B.keys, B.dr, B.nh, B.len, st);
-  prof.mark(S_PCRD);
-  // ---- A_base = dec_base(e_base) (closed form), residual, its DWT ----
-  virtual_decode(B.coef, nx, pl->d_blks, pl->nblk, e0, pl->cbw, pl->cbh, B.pb, B.kb, B.sppf, B.yhat, st);
-  dwt_inverse(B.yhat, B.tmp, B.abase, ny, nx, L, EPI_STORE, io, st);
-  pointwise(nullptr, nullptr, (int)N, 3, EPI_CHECK, io, st);   // does the base alone meet the bound?
-  prof.mark(S_BASEREC);
-  dwt_forward(x, B.cres, B.tmp, ny, nx, L, PRO_NORM_MINUS, io, st);
-  int er = elog - 6;
-  k_zero_int<<<1, 64, 0, st>>>((int*)B.u32s, 8);
-  k_quant_res<<<grid_for(N), 256, 0, st>>>(B.cres, (int)N, er, B.qr, &B.u32s[0]);
-  HIPCHK(hipGetLastError());
-  prof.mark(S_RESID);
-  int hflag[2];
-  unsigned qmax;
-  if ((rc = d2h(hflag, B.flags, 1, st))) return rc;
-  if ((rc = d2h(&qmax, B.u32s, 1, st))) return rc;
-  int checks = 1;
-  int mode = MODE_CODED, nmax = -1, ns = 0, er_out = 0;
-  bool resid = hflag[0] != 0;
-  auto feasible = [&](int k, int nm, int e_r, bool* ok) -> int {
-    int s = nm - k + 1;
-    k_zero_int<<<1, 64, 0, st>>>(B.flags, 1);
-    k_dequant_res<<<grid_for(N), 256, 0, st>>>(B.qr, (int)N, s, e_r, B.chat);
-    dwt_inverse(B.chat, B.tmp, nullptr, ny, nx, L, EPI_CHECK, io, st);
+  if ((rc = upload_items(c, coded))) return rc;
+  bool any = false;
+  for (int v : act) any |= v != 0;
+  if (any) {
+    if ((rc = c.set_active(act))) return rc;
+    // ---- base layer: DWT of the normalised field, tier-1, PCRD at ratio r ----
+    dwt_forward(c.F, c.Fh.data(), nf, BUF_X, BUF_COEF, PRO_NORM, st);
+    prof.mark(S_DWT);
+    quant_planes(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, st);
+    prof.mark(S_QUANT);
+    t1_encode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, c.cw, c.R, c.D, c.bpt, c.tail, c.sppf, st);
+    prof.mark(S_T1ENC);
+    pcrd(c.F, nf, c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
+    prof.mark(S_PCRD);
+    // ---- A_base = dec_base(e_base) (closed form), residual, its DWT ----
+    virtual_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.pb, c.kb, c.sppf, st);
+    dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, st);
+    pointwise(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, 3, EPI_CHECK, 0, st);   // does the base alone meet the bound?
+    prof.mark(S_BASEREC);
+    dwt_forward(c.F, c.Fh.data(), nf, BUF_X, BUF_CRES, PRO_NORM_MINUS, st);
+    k_quant_res<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
     HIPCHK(hipGetLastError());
-    int f;
-    int r = d2h(&f, B.flags, 1, st);
-    if (r) return r;
-    checks++;
-    *ok = f == 0;
-    return EBCC_OK;
-  };
-  if (resid) {
-    bool found = false;
-    for (int att = 0; att < 5 && !found; att++) {
-      int e_r = elog - 6 - att;
-      if (att > 0) {
-        k_zero_int<<<1, 64, 0, st>>>((int*)B.u32s, 1);
-        k_quant_res<<<grid_for(N), 256, 0, st>>>(B.cres, (int)N, e_r, B.qr, &B.u32s[0]);
-        if ((rc = d2h(&qmax, B.u32s, 1, st))) return rc;
+    prof.mark(S_RESID);
+    std::vector<int64_t> col;
+    if ((rc = c.collect_host(col))) return rc;
+    // ---- truncation search, all fields in lockstep: one launch + one sync per round ----
+    enum { NONE = 0, CHECK_ALL, BISECT, REQUANT, FOUND, FAIL };
+    std::vector<int> state(nf, NONE), att(nf, 0), lo(nf, 0), hi(nf, 0), mid(nf, 0);
+    auto start_attempt = [&](int i) {
+      int q = (int)col[8 * i + 2];
+      int nm = q ? 31 - __builtin_clz((unsigned)q) : -1;
+      if (nm < 0) {
+        if (++att[i] >= 5) { state[i] = FAIL; return; }
+        state[i] = REQUANT;
+        c.Fh[i].er = fps[i].elog - 6 - att[i];
+        return;
       }
-      int nm = qmax ? 31 - __builtin_clz(qmax) : -1;
-      if (nm < 0) continue;
-      int K = nm + 1;
-      bool ok;
-      if ((rc = feasible(K, nm, e_r, &ok))) return rc;
-      if (!ok) continue;
-      int lo = 0, hi = K;
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if ((rc = feasible(mid, nm, e_r, &ok))) return rc;
-        if (ok) hi = mid; else lo = mid;
+      nmax[i] = nm;
+      state[i] = CHECK_ALL;
+      mid[i] = nm + 1;
+    };
+    for (int i = 0; i < nf; i++)
+      if (act[i] && col[8 * i + 0]) { resid[i] = 1; start_attempt(i); }
+    for (int round = 0; round < 256; round++) {
+      std::vector<int> rq(nf, 0), ck(nf, 0);
+      bool anyrq = false, anyck = false;
+      for (int i = 0; i < nf; i++) {
+        if (state[i] == REQUANT) { rq[i] = 1; anyrq = true; }
+        if (state[i] == CHECK_ALL || state[i] == BISECT) {
+          ck[i] = 1; anyck = true;
+          c.Fh[i].ns = nmax[i] - mid[i] + 1;
+        }
       }
-      found = true;
-      nmax = nm; ns = nm - hi + 1; er_out = e_r;
+      if (!anyrq && !anyck) break;
+      if (anyrq) {
+        if ((rc = c.set_active(rq))) return rc;
+        k_zero_slot<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, 1);
+        k_quant_res<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+      }
+      if (anyck) {
+        if ((rc = c.set_active(ck))) return rc;
+        k_zero_slot<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, 0);
+        k_dequant_res<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+        dwt_inverse(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, EPI_CHECK, st);
+      }
+      HIPCHK(hipGetLastError());
+      if ((rc = c.collect_host(col))) return rc;
+      for (int i = 0; i < nf; i++) {
+        if (rq[i]) { start_attempt(i); continue; }
+        if (!ck[i]) continue;
+        checks[i]++;
+        bool ok = col[8 * i + 0] == 0;
+        if (state[i] == CHECK_ALL) {
+          if (!ok) {
+            if (++att[i] >= 5) { state[i] = FAIL; continue; }
+            state[i] = REQUANT;
+            c.Fh[i].er = fps[i].elog - 6 - att[i];
+            continue;
+          }
+          lo[i] = 0; hi[i] = nmax[i] + 1;
+          state[i] = BISECT;
+        } else {
+          if (ok) hi[i] = mid[i]; else lo[i] = mid[i];
+        }
+        if (hi[i] - lo[i] > 1) mid[i] = (lo[i] + hi[i]) >> 1;
+        else { state[i] = FOUND; c.Fh[i].ns = nmax[i] - hi[i] + 1; }
+      }
     }
-    if (!found) mode = MODE_RAW;
+    prof.mark(S_SEARCH);
+    std::vector<int> sp(nf, 0);
+    bool anysp = false;
+    for (int i = 0; i < nf; i++) {
+      if (state[i] == FAIL) { mode[i] = MODE_RAW; act[i] = 0; }
+      if (state[i] == FOUND) { sp[i] = 1; anysp = true; }
+      c.Fh[i].nmax = nmax[i];
+      if (state[i] != FOUND) resid[i] = 0;
+    }
+    if (anysp) {
+      if ((rc = c.set_active(sp))) return rc;
+      spiht_maxima(c.F, c.Fh.data(), nf, st);
+      if (c.spiht_cap)
+        spiht_encode_lds(c.spiht_cap, c.F, c.d_tiles, c.ntiles, c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, st);
+      else
+        spiht_encode(c.F, c.d_tiles, c.ntiles, c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, st);
+      k_scan<<<nf, 1024, 0, st>>>(c.F, c.tlen, 1, 0, 0xFFFFFFFFu, c.toff);
+    }
+    prof.mark(S_SPIHT);
+    // ---- sizes ----
+    if ((rc = c.set_active(act))) return rc;
+    k_block_entries<<<grid_for(c.nblk), 256, 0, st>>>(c.pb, c.kb, c.len, c.nblk, c.bent);
+    k_scan<<<nf, 1024, 0, st>>>(c.F, c.bent, 0, 16, 0xFFFFu, c.boff);
+    HIPCHK(hipGetLastError());
+    if ((rc = c.collect_host(col))) return rc;
+    for (int i = 0; i < nf; i++) {
+      if (!act[i]) continue;
+      FieldDev& f = c.Fh[i];
+      f.bb = (uint32_t)(4 * (int64_t)f.nblk + col[8 * i + 4]);
+      f.rb = resid[i] ? (uint32_t)(4 * (int64_t)f.ntiles + col[8 * i + 5]) : 0u;
+      if ((int64_t)f.bb + f.rb > 4 * (int64_t)f.ny * f.nx) { mode[i] = MODE_RAW; act[i] = 0; resid[i] = 0; }
+    }
   }
-  prof.mark(S_SEARCH);
-  if (mode == MODE_CODED && resid) {
-    spiht_maxima(B.qr, nx, pl->d_bands, pl->bands.data(), pl->nb, L, B.sub, B.maxd, B.maxl, st);
-    if (spiht_cap_for(pl))
-      spiht_encode_lds(spiht_cap_for(pl), B.qr, B.sub, B.maxd, B.maxl, nx, pl->d_bands, pl->nb, L, pl->d_tiles,
-                       pl->ntiles, ns, B.slots, pl->d_slot_off, B.tlen, B.tent, B.misfit, st);
-    else
-      spiht_encode(B.qr, B.sub, B.maxd, B.maxl, nx, pl->d_bands, pl->nb, L, pl->d_tiles, pl->ntiles, ns, B.lists,
-                   B.slots, pl->d_slot_off, B.tlen, B.tent, st);
+  // ---- stream lengths and places ----
+  uint64_t total = 0;
+  for (int i = 0; i < nf; i++) {
+    FieldDev& f = c.Fh[i];
+    size_t N = (size_t)f.ny * f.nx;
+    f.mode = mode[i];
+    if (mode[i] == MODE_CONST) { f.len = kHdr; f.bb = 0; f.rb = 0; }
+    else if (mode[i] == MODE_RAW) { f.len = kHdr + 4 * (int64_t)N; f.bb = (uint32_t)(4 * N); f.rb = 0; }
+    else f.len = kHdr + (int64_t)f.bb + f.rb;
+    offs[i] = total;
+    lens[i] = (uint64_t)f.len;
+    total += (uint64_t)f.len;
   }
-  prof.mark(S_SPIHT);
-  // ---- sizes ----
-  k_block_entries<<<grid_for(pl->nblk), 256, 0, st>>>(B.pb, B.kb, B.len, pl->nblk, B.bent);
-  k_scan<<<1, 1024, 0, st>>>(B.bent, pl->nblk, 16, 0xFFFFu, B.boff, &B.totals[0]);
-  if (mode == MODE_CODED && resid) k_scan<<<1, 1024, 0, st>>>(B.tlen, pl->ntiles, 0, 0xFFFFFFFFu, B.toff, &B.totals[1]);
-  HIPCHK(hipGetLastError());
-  int64_t tot[2] = {0, 0};
-  if ((rc = d2h(tot, B.totals, 2, st))) return rc;
-  int64_t base_bytes = 4 * (int64_t)pl->nblk + tot[0];
-  int64_t resid_bytes = (mode == MODE_CODED && resid) ? 4 * (int64_t)pl->ntiles + tot[1] : 0;
-  if (mode == MODE_CODED && base_bytes + resid_bytes > 4 * (int64_t)N) mode = MODE_RAW;
-  if (mode == MODE_RAW) {
-    rc = emit_raw(x, N, pl, cbl, ny, nx, T, B, out, cap, out_len, st);
-    if (tr && tr->info) { info[0] = MODE_RAW; info[10] = checks; memcpy(tr->info, info, sizeof(info)); }
-    return rc;
-  }
-  size_t total = kHdr + (size_t)base_bytes + (size_t)resid_bytes;
-  *out_len = total;
+  *need = total;
   if (total > cap) return fail(EBCC_ENOSPC, "output capacity too small");
-  // ---- pack: header, block table, codewords, tile table, tile payloads ----
-  uint8_t* bsec = out + kHdr;
-  k_put_table<<<grid_for(pl->nblk), 256, 0, st>>>(B.bent, pl->nblk, bsec);
-  k_gather_cw<<<grid_for(pl->nblk), 256, 0, st>>>(B.cw, B.kb, B.len, B.bpt, B.tail, B.boff, pl->nblk,
-                                                  bsec + 4 * (size_t)pl->nblk);
-  if (resid) {
-    uint8_t* rsec = bsec + base_bytes;
-    k_put_table<<<grid_for(pl->ntiles), 256, 0, st>>>(B.tent, pl->ntiles, rsec);
-    k_gather_tiles<<<grid_for(pl->ntiles), 256, 0, st>>>(B.slots, pl->d_slot_off, B.tlen, B.toff, pl->ntiles,
-                                                         rsec + 4 * (size_t)pl->ntiles);
+  for (int i = 0; i < nf; i++) c.Fh[i].out = out + offs[i];
+  // ---- pack: tables, codewords, tile tables and payloads, raw data, checksum, header ----
+  if ((rc = c.set_active(act))) return rc;
+  if (any) {
+    k_put_blocks<<<grid_for(c.nblk), 256, 0, st>>>(c.F, c.d_blk, c.bent, c.nblk);
+    k_gather_cw<<<grid_for(c.nblk), 256, 0, st>>>(c.F, c.d_blk, c.cw, c.kb, c.len, c.bpt, c.tail, c.boff, c.nblk);
+    k_put_tiles<<<grid_for(c.ntiles), 256, 0, st>>>(c.F, c.d_tiles, c.tent, c.ntiles);
+    k_gather_tiles<<<grid_for(c.ntiles), 256, 0, st>>>(c.F, c.d_tiles, c.slots, c.d_slot_off, c.tlen, c.toff, c.ntiles);
   }
-  k_zero_int<<<1, 64, 0, st>>>((int*)B.u32s, 8);
-  k_checksum<<<grid_for((total + 3) / 4), 256, 0, st>>>(out, nullptr, (int64_t)total, &B.u32s[1]);
-  if (!resid) { nmax = -1; ns = 0; er_out = 0; }
-  k_header<<<1, 1, 0, st>>>(out, B.fp, MODE_CODED, L, cbl, ny, nx, er_out, nmax, ns, T, (uint32_t)base_bytes,
-                            (uint32_t)resid_bytes, &B.u32s[1]);
+  std::vector<int> rawm(nf, 0);
+  bool anyraw = false;
+  for (int i = 0; i < nf; i++)
+    if (mode[i] == MODE_RAW) { rawm[i] = 1; anyraw = true; }
+  if (anyraw) {
+    if ((rc = c.set_active(rawm))) return rc;
+    k_copy_raw<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, 1);
+  }
+  std::vector<int> all(nf, 1);
+  if ((rc = c.set_active(all))) return rc;
+  k_checksum<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+  k_header<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
   HIPCHK(hipGetLastError());
   prof.mark(S_PACK);
-  if (tr) {
-    if (tr->coef) HIPCHK(hipMemcpyAsync(tr->coef, B.coef, 4 * N, hipMemcpyDeviceToDevice, st));
-    if (tr->abase) HIPCHK(hipMemcpyAsync(tr->abase, B.abase, 4 * N, hipMemcpyDeviceToDevice, st));
-    if (tr->cres) HIPCHK(hipMemcpyAsync(tr->cres, B.cres, 4 * N, hipMemcpyDeviceToDevice, st));
-    if (tr->kb) HIPCHK(hipMemcpyAsync(tr->kb, B.kb, pl->nblk, hipMemcpyDeviceToDevice, st));
-    if (tr->pb) HIPCHK(hipMemcpyAsync(tr->pb, B.pb, pl->nblk, hipMemcpyDeviceToDevice, st));
-    if (tr->info) {
-      info[0] = MODE_CODED; info[1] = L; info[2] = e0; info[3] = er_out; info[4] = nmax; info[5] = ns;
-      info[6] = pl->nblk; info[7] = pl->ntiles; info[8] = (int32_t)base_bytes; info[9] = (int32_t)resid_bytes;
-      info[10] = checks;
-      memcpy(tr->info, info, sizeof(info));
+  if (tr && nf == 1) {
+    const FieldDev& f = c.Fh[0];
+    size_t N = (size_t)f.ny * f.nx;
+    int32_t info[11] = {0};
+    info[0] = mode[0];
+    if (mode[0] == MODE_CODED) {
+      if (tr->coef) HIPCHK(hipMemcpyAsync(tr->coef, f.buf[BUF_COEF], 4 * N, hipMemcpyDeviceToDevice, st));
+      if (tr->abase) HIPCHK(hipMemcpyAsync(tr->abase, f.buf[BUF_ABASE], 4 * N, hipMemcpyDeviceToDevice, st));
+      if (tr->cres) HIPCHK(hipMemcpyAsync(tr->cres, f.buf[BUF_CRES], 4 * N, hipMemcpyDeviceToDevice, st));
+      if (tr->kb) HIPCHK(hipMemcpyAsync(tr->kb, c.kb, f.nblk, hipMemcpyDeviceToDevice, st));
+      if (tr->pb) HIPCHK(hipMemcpyAsync(tr->pb, c.pb, f.nblk, hipMemcpyDeviceToDevice, st));
+      info[1] = f.L; info[2] = f.e0;
+      info[3] = resid[0] ? f.er : 0; info[4] = resid[0] ? nmax[0] : -1; info[5] = resid[0] ? f.ns : 0;
+      info[6] = f.nblk; info[7] = f.ntiles; info[8] = (int32_t)f.bb; info[9] = (int32_t)f.rb;
     }
+    info[10] = checks[0];
+    if (tr->info) memcpy(tr->info, info, sizeof(info));
     HIPCHK(hipStreamSynchronize(st));
   }
   return EBCC_OK;
@@ -788,88 +1130,170 @@ static int compress_impl(const float* x, size_t ny_, size_t nx_, const ebcc_para
 
 static uint32_t rd32(const uint8_t* p) { return p[0] | (p[1] << 8) | (p[2] << 16) | ((uint32_t)p[3] << 24); }
 
-static int decompress_impl(const uint8_t* in, size_t in_len, float* x, size_t ny_, size_t nx_, hipStream_t st) {
-  if (!in || !x) return fail(EBCC_EINVAL, "NULL buffer");
-  if (in_len < (size_t)kHdr) return fail(EBCC_ECORRUPT, "stream shorter than its header");
-  uint8_t h[kHdr];
-  HIPCHK(hipMemcpyAsync(h, in, kHdr, hipMemcpyDeviceToHost, st));
+struct StreamIn {
+  const uint8_t* in;
+  size_t len;
+  float* x;
+  size_t ny, nx;
+};
+
+// Decompress nf streams; status per stream in st_out (the first error is
+// returned).  A stream whose header cannot be used is reported and skipped;
+// the others are still decoded.
+static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st_out, hipStream_t st) {
+  const int nf = (int)in.size();
+  st_out.assign(nf, EBCC_OK);
+  if (nf == 0) return EBCC_OK;
+  std::vector<uint8_t> hdr(kHdr * (size_t)nf);
+  for (int i = 0; i < nf; i++) {
+    if (!in[i].in || !in[i].x) return fail(EBCC_EINVAL, "NULL buffer");
+    if (in[i].len >= (size_t)kHdr)
+      HIPCHK(hipMemcpyAsync(hdr.data() + kHdr * (size_t)i, in[i].in, kHdr, hipMemcpyDeviceToHost, st));
+  }
   HIPCHK(hipStreamSynchronize(st));
-  size_t hny, hnx;
-  int mode;
-  if (ebcc_stream_info(h, kHdr, &hny, &hnx, &mode) != EBCC_OK) return fail(EBCC_ECORRUPT, "bad stream header");
-  if (hny != ny_ || hnx != nx_ || ny_ < 1 || nx_ < 1) return fail(EBCC_EINVAL, "dimensions do not match the stream");
-  int ny = (int)ny_, nx = (int)nx_;
-  size_t N = (size_t)ny * nx;
-  uint32_t bb = rd32(h + 36), rb = rd32(h + 40), csum = rd32(h + 44);
-  if ((size_t)kHdr + bb + rb != in_len) return fail(EBCC_ECORRUPT, "stream length does not match its header");
-  float xmin, range_f;
-  memcpy(&xmin, h + 16, 4);
-  memcpy(&range_f, h + 20, 4);
-  int L = h[6], cbl2w = h[7] & 15, cbl2h = h[7] >> 4, T = h[32] | (h[33] << 8);
-  int e0 = (int8_t)h[28], er = (int8_t)h[29], ns = (int8_t)h[31];
-  if (mode == MODE_RAW && bb != 4 * N) return fail(EBCC_ECORRUPT, "raw stream of the wrong size");
-  if (mode == MODE_CODED && (L != levels_eff(ny, nx, L) || cbl2w < 2 || cbl2w > 6 || cbl2h < 2 || cbl2h > 6 || T < 1 ||
-                             T > 64 || ns < 0 || ns >= kQBits))
-    return fail(EBCC_ECORRUPT, "bad coding parameters in the header");
-  Plan* pl;
-  int rc = get_plan(ny, nx, mode == MODE_CODED ? L : 0, mode == MODE_CODED ? cbl2w : 2, mode == MODE_CODED ? cbl2h : 2,
-                    mode == MODE_CODED ? T : 1, &pl);
-  if (rc) return rc;
-  Bufs B;
-  if ((rc = get_ws(*pl, st, &B))) return rc;
+  Call c;
+  c.nf = nf;
+  c.st = st;
+  c.Fh.assign(nf, FieldDev());
+  c.plans.assign(nf, nullptr);
+  std::vector<int> mode(nf, MODE_CONST), coded(nf, 0), good(nf, 0);
+  std::vector<float> xr(2 * (size_t)nf, 0.0f);
+  int rc, cbl2w = -1, cbl2h = -1;
+  int first = EBCC_OK;
+  auto bad = [&](int i, int code, const char* msg) {
+    st_out[i] = code;
+    if (first == EBCC_OK) first = fail(code, std::string(msg) + " (stream " + std::to_string(i) + ")");
+  };
+  for (int i = 0; i < nf; i++) {
+    FieldDev& f = c.Fh[i];
+    memset(&f, 0, sizeof(f));
+    if (in[i].len < (size_t)kHdr) { bad(i, EBCC_ECORRUPT, "stream shorter than its header"); continue; }
+    const uint8_t* h = hdr.data() + kHdr * (size_t)i;
+    size_t hny, hnx;
+    if (ebcc_stream_info(h, kHdr, &hny, &hnx, &mode[i]) != EBCC_OK) { bad(i, EBCC_ECORRUPT, "bad stream header"); continue; }
+    if (hny != in[i].ny || hnx != in[i].nx || hny < 1 || hnx < 1 || hny * hnx > 0x7FFFFFFFull) {
+      bad(i, EBCC_EINVAL, "dimensions do not match the stream");
+      continue;
+    }
+    f.ny = (int)hny; f.nx = (int)hnx;
+    size_t N = hny * hnx;
+    f.bb = rd32(h + 36); f.rb = rd32(h + 40);
+    f.len = (int64_t)in[i].len;
+    if ((size_t)kHdr + f.bb + f.rb != in[i].len) { bad(i, EBCC_ECORRUPT, "stream length does not match its header"); continue; }
+    if (mode[i] == MODE_RAW && f.bb != 4 * N) { bad(i, EBCC_ECORRUPT, "raw stream of the wrong size"); continue; }
+    memcpy(&xr[2 * i], h + 16, 4);
+    memcpy(&xr[2 * i + 1], h + 20, 4);
+    f.out = const_cast<uint8_t*>(in[i].in);
+    f.mode = mode[i];
+    if (mode[i] == MODE_CODED) {
+      int L = h[6], w2 = h[7] & 15, h2 = h[7] >> 4, T = h[32] | (h[33] << 8);
+      f.e0 = (int8_t)h[28]; f.er = (int8_t)h[29]; f.ns = (int8_t)h[31];
+      if (L != levels_eff(f.ny, f.nx, L) || w2 < 2 || w2 > 6 || h2 < 2 || h2 > 6 || T < 1 || T > 64 || f.ns < 0 ||
+          f.ns >= kQBits) {
+        bad(i, EBCC_ECORRUPT, "bad coding parameters in the header");
+        continue;
+      }
+      if (cbl2w >= 0 && (w2 != cbl2w || h2 != cbl2h)) {
+        bad(i, EBCC_EINVAL, "streams decoded together must share the code-block size");
+        continue;
+      }
+      f.L = L; f.T = T;
+      if ((rc = get_plan(f.ny, f.nx, L, w2, h2, T, &c.plans[i]))) return rc;
+      if ((int64_t)f.bb < 4 * (int64_t)c.plans[i]->nblk) { bad(i, EBCC_ECORRUPT, "base section shorter than its table"); continue; }
+      if (f.rb && (int64_t)f.rb < 4 * (int64_t)c.plans[i]->ntiles) {
+        bad(i, EBCC_ECORRUPT, "residual section shorter than its table");
+        continue;
+      }
+      cbl2w = w2; cbl2h = h2;
+      f.bands = c.plans[i]->d_bands;
+      f.nb = c.plans[i]->nb;
+      coded[i] = 1;
+    }
+    good[i] = 1;
+  }
+  if (cbl2w >= 0) { c.cbw = 1 << cbl2w; c.cbh = 1 << cbl2h; }
+  build_items(c, coded);
+  c.spiht_cap = 1;
+  bool anycoded = false;
+  for (int i = 0; i < nf; i++)
+    if (coded[i]) { anycoded = true; c.spiht_cap = merge_cap(c.spiht_cap, spiht_cap_for(c.plans[i])); }
+  if (!anycoded) c.spiht_cap = 0;
+  c.need_lists = anycoded && c.spiht_cap == 0;
+  size_t need_ws = layout_call(c, nullptr, coded);
+  char* base;
+  if ((rc = get_ws(st, &c.ws))) return rc;
+  if ((rc = grow_ws(c.ws, need_ws, pin_need(c), st, &base))) return rc;
+  layout_call(c, base, coded);
+  for (int i = 0; i < nf; i++) {
+    c.Fh[i].buf[BUF_XOUT] = in[i].x;
+    c.Fh[i].active = good[i];
+  }
   Prof prof(st);
-  k_set_decode_params<<<1, 1, 0, st>>>(B.fp, xmin, range_f, B.flags, 8);
-  k_zero_int<<<1, 64, 0, st>>>((int*)B.u32s, 8);
-  k_checksum<<<grid_for((in_len + 3) / 4), 256, 0, st>>>(in, nullptr, (int64_t)in_len, &B.u32s[1]);
-  if (mode == MODE_CONST) {
-    k_fill<<<grid_for(N), 256, 0, st>>>(x, (int)N, xmin);
-  } else if (mode == MODE_RAW) {
-    HIPCHK(hipMemcpyAsync(x, in + kHdr, 4 * N, hipMemcpyDeviceToDevice, st));
-  } else {
-    if ((int64_t)bb < 4 * (int64_t)pl->nblk) return fail(EBCC_ECORRUPT, "base section shorter than its table");
-    const uint8_t* bsec = in + kHdr;
-    DwtIO io{nullptr, B.abase, x, &B.flags[0], B.fp};
-    k_read_table<<<grid_for(pl->nblk), 256, 0, st>>>(bsec, pl->nblk, B.bent);
-    k_scan<<<1, 1024, 0, st>>>(B.bent, pl->nblk, 16, 0xFFFFu, B.boff, &B.totals[0]);
-    k_check_tables<<<1, 64, 0, st>>>(bsec, pl->nblk, (int64_t)bb, &B.totals[0], &B.flags[1]);
-    prof.mark(S_D_PARSE);
-    t1_decode(bsec + 4 * (size_t)pl->nblk, (int64_t)bb - 4 * (int64_t)pl->nblk, B.bent, B.boff, nx, pl->d_blks,
-              pl->nblk, e0, pl->cbw, pl->cbh, B.yhat, &B.flags[1], st);
-    prof.mark(S_D_T1);
-    if (rb) {
-      dwt_inverse(B.yhat, B.tmp, B.abase, ny, nx, L, EPI_STORE, io, st);
-      prof.mark(S_D_IDWT_BASE);
-      if ((int64_t)rb < 4 * (int64_t)pl->ntiles) return fail(EBCC_ECORRUPT, "residual section shorter than its table");
-      const uint8_t* rsec = bsec + bb;
-      k_read_table<<<grid_for(pl->ntiles), 256, 0, st>>>(rsec, pl->ntiles, B.tent);
-      k_scan<<<1, 1024, 0, st>>>(B.tent, pl->ntiles, 0, 0x3FFFFFFu, B.toff, &B.totals[1]);
-      k_check_tables<<<1, 64, 0, st>>>(rsec, pl->ntiles, (int64_t)rb, &B.totals[1], &B.flags[1]);
-      k_fill<<<grid_for(N), 256, 0, st>>>(B.chat, (int)N, 0.0f);
-      // payload offsets relative to the residual section start
-      if (spiht_cap_for(pl))
-        spiht_decode_lds(spiht_cap_for(pl), rsec, (int64_t)rb, B.toff, nx, pl->d_bands, pl->nb, L, pl->d_tiles,
-                         pl->ntiles, ns, er, B.chat, &B.flags[1], B.misfit, st);
-      else
-        spiht_decode(rsec, (int64_t)rb, B.toff, nx, pl->d_bands, pl->nb, L, pl->d_tiles, pl->ntiles, ns, er,
-                     B.lists, B.qr, B.chat, &B.flags[1], st);
-      prof.mark(S_D_SPIHT);
-      dwt_inverse(B.chat, B.tmp, nullptr, ny, nx, L, EPI_FINAL, io, st);
-      prof.mark(S_D_FINAL);
-    } else {
-      dwt_inverse(B.yhat, B.tmp, B.abase, ny, nx, L, EPI_STORE, io, st);
-      prof.mark(S_D_IDWT_BASE);
-      pointwise(nullptr, nullptr, (int)N, 3, EPI_FINAL, io, st);
-      prof.mark(S_D_FINAL);
+  if ((rc = upload_items(c, coded))) return rc;
+  float* d_xr = reinterpret_cast<float*>(c.collect);   // reuse: 2 floats per field fit 8 int64 per field
+  if ((rc = c.stage(d_xr, xr.data(), sizeof(float) * xr.size()))) return rc;
+  std::vector<int> all(good);
+  if ((rc = c.set_active(all))) return rc;
+  k_set_decode<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, d_xr);
+  size_t maxN = 0;
+  for (auto& f : c.Fh) maxN = std::max(maxN, (size_t)f.ny * f.nx);
+  k_checksum<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+  std::vector<int> cm(nf, 0), rm(nf, 0), cd(nf, 0), cr(nf, 0), cn(nf, 0);
+  bool anyc = false, anyr = false, anyres = false, anynores = false;
+  for (int i = 0; i < nf; i++) {
+    if (!good[i]) continue;
+    if (mode[i] == MODE_CONST) { cm[i] = 1; anyc = true; }
+    if (mode[i] == MODE_RAW) { rm[i] = 1; anyr = true; }
+    if (coded[i]) {
+      cd[i] = 1;
+      if (c.Fh[i].rb) { cr[i] = 1; anyres = true; } else { cn[i] = 1; anynores = true; }
     }
   }
+  if (anyc) {
+    if ((rc = c.set_active(cm))) return rc;
+    k_fill<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, BUF_XOUT, __builtin_nanf(""));
+  }
+  if (anyr) {
+    if ((rc = c.set_active(rm))) return rc;
+    k_copy_raw<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, 0);
+  }
+  if (anycoded) {
+    if ((rc = c.set_active(cd))) return rc;
+    k_read_blocks<<<grid_for(c.nblk), 256, 0, st>>>(c.F, c.d_blk, c.nblk, c.bent);
+    k_scan<<<nf, 1024, 0, st>>>(c.F, c.bent, 0, 16, 0xFFFFu, c.boff);
+    k_read_tiles<<<grid_for(c.ntiles), 256, 0, st>>>(c.F, c.d_tiles, c.ntiles, c.tent);
+    k_scan<<<nf, 1024, 0, st>>>(c.F, c.tent, 1, 0, 0x3FFFFFFu, c.toff);
+    k_check_tables<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
+    prof.mark(S_D_PARSE);
+    t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, st);
+    prof.mark(S_D_T1);
+    dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, st);
+    prof.mark(S_D_IDWT_BASE);
+    if (anyres) {
+      if ((rc = c.set_active(cr))) return rc;
+      k_fill<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, BUF_CHAT, 0.0f);
+      if (c.spiht_cap) spiht_decode_lds(c.spiht_cap, c.F, c.d_tiles, c.ntiles, c.toff, c.misfit, st);
+      else spiht_decode(c.F, c.d_tiles, c.ntiles, c.toff, c.lists, st);
+      prof.mark(S_D_SPIHT);
+      dwt_inverse(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, EPI_FINAL, st);
+    }
+    if (anynores) {
+      if ((rc = c.set_active(cn))) return rc;
+      pointwise(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, 3, EPI_FINAL, 0, st);
+    }
+    prof.mark(S_D_FINAL);
+  }
   HIPCHK(hipGetLastError());
-  int fl[2];
-  unsigned cs[2];
-  if ((rc = d2h(fl, B.flags, 2, st))) return rc;
-  if ((rc = d2h(cs, B.u32s, 2, st))) return rc;
-  if (fl[1]) return fail(EBCC_ECORRUPT, "inconsistent block or tile tables");
-  if (cs[1] != csum) return fail(EBCC_ECORRUPT, "checksum mismatch");
-  return EBCC_OK;
+  if ((rc = c.set_active(all))) return rc;
+  std::vector<int64_t> col;
+  if ((rc = c.collect_host(col))) return rc;
+  for (int i = 0; i < nf; i++) {
+    if (!good[i]) continue;
+    uint32_t csum = rd32(hdr.data() + kHdr * (size_t)i + 44);
+    if (col[8 * i + 1]) bad(i, EBCC_ECORRUPT, "inconsistent block or tile tables");
+    else if ((uint32_t)col[8 * i + 3] != csum) bad(i, EBCC_ECORRUPT, "checksum mismatch");
+  }
+  return first;
 }
 
 }  // namespace ebcc
@@ -897,20 +1321,101 @@ size_t ebcc_compress_bound(size_t ny, size_t nx) { return (size_t)kHdr + 4 * ny 
 int ebcc_compress(const float* d_x, size_t ny, size_t nx, const ebcc_params* p, uint8_t* d_out, size_t out_cap,
                   size_t* out_len, void* stream) {
   g_err.clear();
-  return compress_impl(d_x, ny, nx, p, d_out, out_cap, out_len, (hipStream_t)stream, nullptr);
+  if (!out_len) return fail(EBCC_EINVAL, "out_len is NULL");
+  *out_len = 0;
+  std::vector<FieldIn> in(1, FieldIn{d_x, ny, nx, p ? p->err_bound : 0.01});
+  std::vector<uint64_t> offs, lens;
+  size_t need = 0;
+  int rc = compress_call(in, p, d_out, out_cap, offs, lens, &need, (hipStream_t)stream, nullptr);
+  *out_len = rc == EBCC_ENOSPC ? need : (rc == EBCC_OK ? (size_t)lens[0] : 0);
+  return rc;
 }
 
 int ebcc_compress_trace(const float* d_x, size_t ny, size_t nx, const ebcc_params* p, uint8_t* d_out, size_t out_cap,
                         size_t* out_len, void* stream, float* d_coef, float* d_abase, float* d_cres, uint8_t* d_kb,
                         uint8_t* d_pb, int32_t* h_info) {
   g_err.clear();
+  if (!out_len) return fail(EBCC_EINVAL, "out_len is NULL");
+  *out_len = 0;
   Trace tr{d_coef, d_abase, d_cres, d_kb, d_pb, h_info};
-  return compress_impl(d_x, ny, nx, p, d_out, out_cap, out_len, (hipStream_t)stream, &tr);
+  std::vector<FieldIn> in(1, FieldIn{d_x, ny, nx, p ? p->err_bound : 0.01});
+  std::vector<uint64_t> offs, lens;
+  size_t need = 0;
+  int rc = compress_call(in, p, d_out, out_cap, offs, lens, &need, (hipStream_t)stream, &tr);
+  *out_len = rc == EBCC_ENOSPC ? need : (rc == EBCC_OK ? (size_t)lens[0] : 0);
+  return rc;
+}
+
+int ebcc_compress_batch(int n, const float* const* d_x, const size_t* ny, const size_t* nx, const double* err_bounds,
+                        const ebcc_params* p, uint8_t* d_out, size_t out_cap, uint64_t* h_offsets,
+                        uint64_t* h_lengths, void* stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!d_x || !ny || !nx || !h_offsets || !h_lengths)))
+    return fail(EBCC_EINVAL, "bad batch arguments");
+  for (int i = 0; i < n; i++) { h_offsets[i] = 0; h_lengths[i] = 0; }
+  size_t done = 0;
+  int i = 0;
+  while (i < n) {
+    // one chunk: consecutive fields up to kChunkSamples samples (at least one)
+    std::vector<FieldIn> in;
+    size_t samples = 0;
+    int j = i;
+    while (j < n && (in.empty() || samples + ny[j] * nx[j] <= kChunkSamples) && (int)in.size() < kChunkFields) {
+      in.push_back(FieldIn{d_x[j], ny[j], nx[j], err_bounds ? err_bounds[j] : (p ? p->err_bound : 0.01)});
+      samples += ny[j] * nx[j];
+      j++;
+    }
+    std::vector<uint64_t> offs, lens;
+    size_t need = 0;
+    if (done > out_cap) return fail(EBCC_ENOSPC, "output capacity too small");
+    int rc = compress_call(in, p, d_out + done, out_cap - done, offs, lens, &need, (hipStream_t)stream, nullptr);
+    if (rc) return rc;
+    for (int k = i; k < j; k++) {
+      h_offsets[k] = done + offs[k - i];
+      h_lengths[k] = lens[k - i];
+    }
+    done += need;
+    i = j;
+  }
+  return EBCC_OK;
 }
 
 int ebcc_decompress(const uint8_t* d_in, size_t in_len, float* d_x, size_t ny, size_t nx, void* stream) {
   g_err.clear();
-  return decompress_impl(d_in, in_len, d_x, ny, nx, (hipStream_t)stream);
+  std::vector<StreamIn> in(1, StreamIn{d_in, in_len, d_x, ny, nx});
+  std::vector<int> st;
+  return decompress_call(in, st, (hipStream_t)stream);
+}
+
+int ebcc_decompress_batch(int n, const uint8_t* const* d_in, const size_t* in_len, float* const* d_x,
+                          const size_t* ny, const size_t* nx, int* h_status, void* stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!d_in || !in_len || !d_x || !ny || !nx)))
+    return fail(EBCC_EINVAL, "bad batch arguments");
+  int first = EBCC_OK;
+  std::string first_msg;
+  int i = 0;
+  while (i < n) {
+    std::vector<StreamIn> in;
+    size_t samples = 0;
+    int j = i;
+    while (j < n && (in.empty() || samples + ny[j] * nx[j] <= kChunkSamples) && (int)in.size() < kChunkFields) {
+      in.push_back(StreamIn{d_in[j], in_len[j], d_x[j], ny[j], nx[j]});
+      samples += ny[j] * nx[j];
+      j++;
+    }
+    std::vector<int> st;
+    int rc = decompress_call(in, st, (hipStream_t)stream);
+    bool per_stream = false;
+    for (int v : st) per_stream |= v != EBCC_OK;
+    if (rc && !per_stream) st.assign(j - i, rc);   // a failure of the whole chunk
+    for (int k = i; k < j; k++)
+      if (h_status) h_status[k] = st.empty() ? rc : st[k - i];
+    if (rc && first == EBCC_OK) { first = rc; first_msg = g_err; }
+    i = j;
+  }
+  if (first) g_err = first_msg;
+  return first;
 }
 
 int ebcc_stream_info(const uint8_t* h, size_t len, size_t* ny, size_t* nx, int* mode) {

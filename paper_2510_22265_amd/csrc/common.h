@@ -25,19 +25,21 @@ struct Band {
   int gain;            // g_b: log2 of the subband's synthesis gain, rounded
 };
 
-// A code-block: position in the Mallat array, size, subband class and gain.
+// A code-block: position in the Mallat array, size, subband class, gain and
+// the field (index into the call's field table) it belongs to.
 struct Blk {
   int y0, x0;
   int w, h;
   int orient, gain;
+  int field;
 };
 
-// A SPIHT tile: LL root rectangle and the offset of its list storage.
+// A SPIHT tile: LL root rectangle, the offset of its list storage, its field.
 struct TileD {
   int i0, j0, i1, j1;  // LL roots [i0, i1) x [j0, j1)
   int64_t off;         // start of this tile's slice in the per-coefficient scratch
   int ncoef;           // coefficients in the tile's trees
-  int pad;
+  int field;
 };
 
 // Scalars of one field, produced on the device from the input.
@@ -62,82 +64,91 @@ __device__ __forceinline__ float dequant(uint32_t m, int p, int neg, int e) {
   return neg ? -v : v;
 }
 
+// Per-field table entry seen by every kernel: the field's device buffers,
+// shape and coding state.  One call (a single field or a batch) passes an
+// array of these; work items (code-blocks, tiles, DWT tiles) carry their
+// field's index.
+enum { BUF_X = 0, BUF_COEF, BUF_TMP, BUF_YHAT, BUF_ABASE, BUF_CRES, BUF_CHAT, BUF_XOUT, NBUF };
+struct FieldDev {
+  float* buf[NBUF];    // BUF_X is the caller's input (read only)
+  FieldParams* fp;
+  int* flags;          // [0] bound violated, [1] stream inconsistent
+  unsigned* u32s;      // [0] residual magnitude max, [1] checksum
+  int64_t* totals;     // [0] base payload bytes, [1] residual payload bytes
+  uint32_t *qr, *sub, *maxd, *maxl;
+  const Band* bands;   // the field's subband table
+  uint8_t* out;        // compressed stream (output of compress, input of decompress)
+  int ny, nx, L, nb;
+  int blk0, nblk, tile0, ntiles;
+  int active, ns, er, e0;
+  int64_t budget;      // rate-allocation payload budget
+  double err;          // requested bound (range-relative or absolute)
+  int bound_mode, mode, nmax, cbl, T;
+  uint32_t bb, rb;     // base and residual section bytes (header fields)
+  int64_t len;         // stream length
+};
+
 // Device kernels' launch wrappers (all asynchronous on `st`).
 // dwt.hip
 enum { PRO_COPY = 0, PRO_NORM = 1, PRO_NORM_MINUS = 2 };
 enum { EPI_STORE = 0, EPI_FINAL = 1, EPI_CHECK = 2 };
-struct DwtIO {
-  const float* x;            // original field (prologue/epilogue)
-  const float* abase;        // base reconstruction (prologue NORM_MINUS, epilogues)
-  float* xout;               // EPI_FINAL output
-  int* flag;                 // EPI_CHECK violation flag
-  const FieldParams* fp;     // xmin, inv_f, range_f, eps
-};
-// Forward multi-level DWT. Level 1 reads `src` through the prologue; the
-// result (Mallat layout) is left in `a`.  `tmp` is an ny*nx scratch.
-void dwt_forward(const float* src, float* a, float* tmp, int ny, int nx, int L, int prologue,
-                 const DwtIO& io, hipStream_t st);
-// Inverse multi-level DWT of `a` (destroyed).  The last level writes the
-// result through the epilogue into `out` (EPI_STORE), io.xout (EPI_FINAL),
-// or only checks it (EPI_CHECK).
-void dwt_inverse(float* a, float* tmp, float* out, int ny, int nx, int L, int epilogue,
-                 const DwtIO& io, hipStream_t st);
-// Elementwise forms used when L = 0 and for the base-only check.
-void pointwise(const float* src, float* dst, int n, int prologue, int epilogue, const DwtIO& io,
-               hipStream_t st);
+// Forward multi-level DWT of every active field (F device table, Fh its host
+// copy): level 1 reads buf[src] through the prologue, the Mallat result is
+// left in buf[dst]; buf[BUF_TMP] is scratch.
+void dwt_forward(const FieldDev* F, const FieldDev* Fh, int nf, int src, int dst, int prologue, hipStream_t st);
+// Inverse multi-level DWT of buf[a] (destroyed); the last level goes through
+// the epilogue into buf[out] (EPI_STORE), buf[BUF_XOUT] (EPI_FINAL), or only
+// checks the bound (EPI_CHECK, flags[0]).
+void dwt_inverse(const FieldDev* F, const FieldDev* Fh, int nf, int a, int out, int epilogue, hipStream_t st);
+// Elementwise prologue (PRO_*, or 3 = zero) and epilogue over whole fields.
+void pointwise(const FieldDev* F, const FieldDev* Fh, int nf, int src, int dst, int prologue, int epilogue,
+               int lzero_only, hipStream_t st);
 
-// t1.hip
-void quant_planes(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh,
-                  void* planes, void* signs, uint8_t* pb, hipStream_t st);
-void t1_encode(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh,
-               const void* planes, const void* signs, const uint8_t* pb, uint8_t* cw,
-               int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail, void* sppf, hipStream_t st);
-void virtual_decode(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh,
-                    const uint8_t* pb, const uint8_t* kb, const void* sppf, float* yhat, hipStream_t st);
-void t1_decode(const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off,
-               int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, float* yhat, int* flag,
-               hipStream_t st);
-
-// t1wave.hip: one wavefront per code-block (few blocks in flight)
-void t1_encode_wave(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh,
-                    const void* planes, const void* signs, const uint8_t* pb, uint8_t* cw,
-                    int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail, void* sppf, hipStream_t st);
-void t1_decode_wave(const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off,
-                    int nx, const Blk* blk, int nblk, int e0, int cbw, float* yhat, int* flag,
-                    hipStream_t st);
+// t1.hip / t1wave.hip: code-blocks of every field in one launch; per-block
+// tables are indexed by the block's position in the call's block array.
+void quant_planes(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, void* planes, void* signs,
+                  uint8_t* pb, hipStream_t st);
+void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
+               const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
+               uint32_t* tail, void* sppf, hipStream_t st);
+void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,
+                    const uint8_t* kb, const void* sppf, hipStream_t st);
+// table: per-block entries (P | k << 8 | len << 16); off: payload offsets
+// within each field's base payload (which starts at out + 48 + 4 nblk).
+void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
+               const int64_t* off, hipStream_t st);
+void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
+                    const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
+                    uint32_t* tail, void* sppf, hipStream_t st);
+void t1_decode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, const uint32_t* table,
+                    const int64_t* off, hipStream_t st);
 // Tier-1 kernel choice: 0 = by work size, 1 = wave per block, 2 = lane per block.
 int t1_variant();
 
-// pcrd.hip
-void pcrd(const uint8_t* pb, const int32_t* R, const int64_t* D, int nblk, int64_t budget,
-          uint8_t* kb, uint8_t* hk_scratch, uint64_t* key_scratch, int32_t* dr_scratch,
-          uint8_t* nh_scratch, int32_t* len_out, hipStream_t st);
+// pcrd.hip: one workgroup per field; kb/len per block.
+void pcrd(const FieldDev* F, int nf, const uint8_t* pb, const int32_t* R, const int64_t* D, uint8_t* kb,
+          uint8_t* hk_scratch, uint64_t* key_scratch, int32_t* dr_scratch, uint8_t* nh_scratch, int32_t* len_out,
+          hipStream_t st);
 
-// spiht.hip
-// qr: per-coefficient residual magnitude (bits 0..22) and sign (bit 31).
-void spiht_maxima(const uint32_t* qr, int nx, const Band* bands_dev, const Band* bands_host, int nb, int L,
-                  uint32_t* sub, uint32_t* maxd, uint32_t* maxl, hipStream_t st);
-// Encode every tile for planes n_t .. n_s into its slot of `slots`
-// (slot_off[t] .. ); tlen[t] receives the byte length and tent[t] the tile
+// spiht.hip: tiles of every field in one launch (global-memory lists).
+// FieldDev.qr: residual magnitude (bits 0..22) and sign (bit 31).
+void spiht_maxima(const FieldDev* F, const FieldDev* Fh, int nf, hipStream_t st);
+// Encode every tile for planes n_t .. F.ns into its slot of `slots`
+// (slot_off[t] ..); tlen[t] receives the byte length and tent[t] the tile
 // table entry.
-void spiht_encode(const uint32_t* qr, const uint32_t* sub, const uint32_t* maxd, const uint32_t* maxl, int nx,
-                  const Band* bands, int nb, int L, const TileD* tiles, int ntiles, int n_s, uint64_t* lists,
-                  uint8_t* slots, const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st);
+void spiht_encode(const FieldDev* F, const TileD* tiles, int ntiles, uint64_t* lists, uint8_t* slots,
+                  const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st);
+// Decode residual sections (each field's starts at out + 48 + bb): writes the
+// dequantised significant coefficients into buf[BUF_CHAT] (zero elsewhere);
+// toff: payload offsets after each field's tile table.
+void spiht_decode(const FieldDev* F, const TileD* tiles, int ntiles, const int64_t* toff, uint64_t* lists,
+                  hipStream_t st);
 // spihtwave.hip: one wavefront per tile with the tile in LDS.  spiht_lds_cap
 // gives the LDS capacity class for the largest tile (0 = does not fit).
 int spiht_lds_cap(int max_tile_coef);
-void spiht_encode_lds(int cap, const uint32_t* qr, const uint32_t* sub, const uint32_t* maxd, const uint32_t* maxl,
-                      int nx, const Band* bands, int nb, int L, const TileD* tiles, int ntiles, int n_s,
-                      uint8_t* slots, const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit,
+void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, int ntiles, uint8_t* slots,
+                      const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit, hipStream_t st);
+void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, int ntiles, const int64_t* toff, int* misfit,
                       hipStream_t st);
-void spiht_decode_lds(int cap, const uint8_t* sec, int64_t sec_len, const int64_t* toff, int nx, const Band* bands,
-                      int nb, int L, const TileD* tiles, int ntiles, int n_s, int e_r, float* chat, int* flag,
-                      int* misfit, hipStream_t st);
-// Decode the residual section: `sec` starts at the tile table.  Uses `mags`
-// (ny*nx scratch) for the magnitude|sign of significant coefficients and
-// writes their dequantised values into chat (which must be zero elsewhere).
-void spiht_decode(const uint8_t* sec, int64_t sec_len, const int64_t* toff, int nx, const Band* bands, int nb,
-                  int L, const TileD* tiles, int ntiles, int n_s, int e_r, uint64_t* lists, uint32_t* mags,
-                  float* chat, int* flag, hipStream_t st);
 
 }  // namespace ebcc

@@ -14,6 +14,8 @@
 // exactly, also in FP32.
 #include "common.h"
 
+#include <algorithm>
+
 namespace ebcc {
 
 // Nearest binary32 values of the 9/7 lifting factors and of K, 1/K.
@@ -49,27 +51,36 @@ __device__ __forceinline__ Scal load_scal(const FieldParams* fp) {
   return s;
 }
 
+// Size of the region level l (1-based) transforms: ceil(n / 2^(l-1)).
+__device__ __forceinline__ int lvl_size(int n, int l) {
+  for (int i = 1; i < l; i++) n = (n + 1) >> 1;
+  return n;
+}
+
 // Prologue: the value of the level-1 input at flat index idx.
 template <int PRO>
-__device__ __forceinline__ float prologue(const float* __restrict__ src, int idx, const DwtIO& io, const Scal& sc) {
+__device__ __forceinline__ float prologue(const float* __restrict__ src, int idx, const FieldDev& f, const Scal& sc) {
   if (PRO == PRO_COPY) return src[idx];
   float t = src[idx] - sc.xmin;
   t = t * sc.inv;
   t = t - 0.5f;
   if (PRO == PRO_NORM) return t;
-  return t - io.abase[idx];
+  return t - f.buf[BUF_ABASE][idx];
 }
 
 // Epilogue: reconstruction x_hat = xmin + ((abase + v + 0.5) * range).
 template <int EPI>
-__device__ __forceinline__ void epilogue(float* __restrict__ out, int idx, float v, const DwtIO& io, const Scal& sc) {
+__device__ __forceinline__ void epilogue(float* __restrict__ out, int idx, float v, const FieldDev& f, const Scal& sc) {
   if (EPI == EPI_STORE) { out[idx] = v; return; }
-  float a = io.abase[idx] + v;
+  float a = f.buf[BUF_ABASE][idx] + v;
   a = a + 0.5f;
   a = a * sc.range;
   float xh = sc.xmin + a;
-  if (EPI == EPI_FINAL) { io.xout[idx] = xh; return; }
-  if (fabs((double)io.x[idx] - (double)xh) > sc.eps) atomicOr(io.flag, 1);
+  if (EPI == EPI_FINAL) { f.buf[BUF_XOUT][idx] = xh; return; }
+  // one atomic per wavefront that sees a violation
+  const bool bad = fabs((double)f.buf[BUF_X][idx] - (double)xh) > sc.eps;
+  const unsigned long long m = __ballot(bad);
+  if (bad && (int)__lane_id() == __builtin_ctzll(m)) atomicOr(&f.flags[0], 1);
 }
 
 // One lifting step along the first LDS index (rows) of a column tile.
@@ -85,20 +96,26 @@ __device__ __forceinline__ void lift_rows(float (*s)[kColTileC + 1], int nrows, 
   __syncthreads();
 }
 
-// Forward vertical pass on region H x W (stride nx): src -> dst deinterleaved.
+// Forward vertical pass of level l on every active field (blockIdx.z):
+// buf[src] (level 1: through the prologue) -> buf[BUF_TMP], deinterleaved.
 template <int PRO>
-__global__ __launch_bounds__(256) void k_fwd_cols(const float* __restrict__ src, float* __restrict__ dst,
-                                                  int nx, int H, int W, DwtIO io) {
+__global__ __launch_bounds__(256) void k_fwd_cols(const FieldDev* __restrict__ F, int l, int src, int dst) {
+  const FieldDev& f = F[blockIdx.z];
+  if (!f.active || l > f.L) return;
+  const int nx = f.nx, H = lvl_size(f.ny, l), W = lvl_size(f.nx, l);
+  int c0 = blockIdx.x * kColTileC, r0 = blockIdx.y * kColTileR;
+  if (c0 >= W || r0 >= H) return;
+  const float* sp = f.buf[l == 1 ? src : dst];
+  float* dp = f.buf[BUF_TMP];
   __shared__ float s[kColTileR + 2 * kHalo][kColTileC + 1];
   const int NR = kColTileR + 2 * kHalo;
-  int c0 = blockIdx.x * kColTileC, r0 = blockIdx.y * kColTileR;
   int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   int col = c0 + tx;
   Scal sc = {};
-  if (PRO != PRO_COPY) sc = load_scal(io.fp);
+  if (PRO != PRO_COPY) sc = load_scal(f.fp);
   for (int r = ty; r < NR; r += 4) {
     int g = mirror(r0 - kHalo + r, H);
-    s[r][tx] = (col < W) ? prologue<PRO>(src, g * nx + col, io, sc) : 0.0f;
+    s[r][tx] = (col < W) ? prologue<PRO>(sp, g * nx + col, f, sc) : 0.0f;
   }
   __syncthreads();
   lift_rows<false>(s, NR, 1, 1, L97_A, tx, ty);
@@ -112,29 +129,35 @@ __global__ __launch_bounds__(256) void k_fwd_cols(const float* __restrict__ src,
       float v = s[r][tx];
       v = (g & 1) ? v * L97_K : v * L97_IK;
       int orow = (g & 1) ? nl + (g >> 1) : (g >> 1);
-      dst[orow * nx + col] = v;
+      dp[orow * nx + col] = v;
     }
   }
 }
 
-// Inverse vertical pass: deinterleaved src -> interleaved dst (via epilogue).
+// Inverse vertical pass of level l: buf[BUF_TMP] (deinterleaved) -> level 1:
+// the epilogue into buf[out]; other levels: buf[a].
 template <int EPI>
-__global__ __launch_bounds__(256) void k_inv_cols(const float* __restrict__ src, float* __restrict__ dst,
-                                                  int nx, int H, int W, DwtIO io) {
+__global__ __launch_bounds__(256) void k_inv_cols(const FieldDev* __restrict__ F, int l, int a, int out) {
+  const FieldDev& f = F[blockIdx.z];
+  if (!f.active || l > f.L) return;
+  const int nx = f.nx, H = lvl_size(f.ny, l), W = lvl_size(f.nx, l);
+  int c0 = blockIdx.x * kColTileC, r0 = blockIdx.y * kColTileR;
+  if (c0 >= W || r0 >= H) return;
+  const float* sp = f.buf[BUF_TMP];
+  float* dp = f.buf[l == 1 ? out : a];
   __shared__ float s[kColTileR + 2 * kHalo][kColTileC + 1];
   const int NR = kColTileR + 2 * kHalo;
-  int c0 = blockIdx.x * kColTileC, r0 = blockIdx.y * kColTileR;
   int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   int col = c0 + tx;
   int nl = (H + 1) >> 1;
   Scal sc = {};
-  if (EPI != EPI_STORE) sc = load_scal(io.fp);
+  if (EPI != EPI_STORE) sc = load_scal(f.fp);
   for (int r = ty; r < NR; r += 4) {
     int g = mirror(r0 - kHalo + r, H);
     float v = 0.0f;
     if (col < W) {
       int srow = (g & 1) ? nl + (g >> 1) : (g >> 1);
-      v = src[srow * nx + col];
+      v = sp[srow * nx + col];
       v = (g & 1) ? v * L97_IK : v * L97_K;
     }
     s[r][tx] = v;
@@ -146,7 +169,10 @@ __global__ __launch_bounds__(256) void k_inv_cols(const float* __restrict__ src,
   lift_rows<true>(s, NR, 4, 1, L97_A, tx, ty);
   for (int r = kHalo + ty; r < kColTileR + kHalo; r += 4) {
     int g = r0 - kHalo + r;
-    if (g < H && col < W) epilogue<EPI>(dst, g * nx + col, s[r][tx], io, sc);
+    if (g < H && col < W) {
+      if (l == 1) epilogue<EPI>(dp, g * nx + col, s[r][tx], f, sc);
+      else dp[g * nx + col] = s[r][tx];
+    }
   }
 }
 
@@ -165,12 +191,17 @@ __device__ __forceinline__ void lift_cols(float (*s)[kRowTileC + 2 * kHalo + 1],
   __syncthreads();
 }
 
-// Forward horizontal pass on region H x W: src -> dst deinterleaved.
-__global__ __launch_bounds__(256) void k_fwd_rows(const float* __restrict__ src, float* __restrict__ dst,
-                                                  int nx, int H, int W) {
+// Forward horizontal pass of level l: buf[BUF_TMP] -> buf[dst] deinterleaved.
+__global__ __launch_bounds__(256) void k_fwd_rows(const FieldDev* __restrict__ F, int l, int dst) {
+  const FieldDev& f = F[blockIdx.z];
+  if (!f.active || l > f.L) return;
+  const int nx = f.nx, H = lvl_size(f.ny, l), W = lvl_size(f.nx, l);
+  int c0 = blockIdx.x * kRowTileC, r0 = blockIdx.y * kRowTileR;
+  if (c0 >= W || r0 >= H) return;
+  const float* src = f.buf[BUF_TMP];
+  float* dp = f.buf[dst];
   __shared__ float s[kRowTileR][kRowTileC + 2 * kHalo + 1];
   const int NC = kRowTileC + 2 * kHalo;
-  int c0 = blockIdx.x * kRowTileC, r0 = blockIdx.y * kRowTileR;
   int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int rr = 0; rr < kRowTileR; rr++) {
     int row = r0 + rr;
@@ -194,18 +225,23 @@ __global__ __launch_bounds__(256) void k_fwd_rows(const float* __restrict__ src,
         float v = s[rr][cc];
         v = (g & 1) ? v * L97_K : v * L97_IK;
         int ocol = (g & 1) ? nl + (g >> 1) : (g >> 1);
-        dst[row * nx + ocol] = v;
+        dp[row * nx + ocol] = v;
       }
     }
   }
 }
 
-// Inverse horizontal pass: deinterleaved src -> interleaved dst.
-__global__ __launch_bounds__(256) void k_inv_rows(const float* __restrict__ src, float* __restrict__ dst,
-                                                  int nx, int H, int W) {
+// Inverse horizontal pass of level l: buf[a] (deinterleaved) -> buf[BUF_TMP].
+__global__ __launch_bounds__(256) void k_inv_rows(const FieldDev* __restrict__ F, int l, int a) {
+  const FieldDev& f = F[blockIdx.z];
+  if (!f.active || l > f.L) return;
+  const int nx = f.nx, H = lvl_size(f.ny, l), W = lvl_size(f.nx, l);
+  int c0 = blockIdx.x * kRowTileC, r0 = blockIdx.y * kRowTileR;
+  if (c0 >= W || r0 >= H) return;
+  const float* src = f.buf[a];
+  float* dp = f.buf[BUF_TMP];
   __shared__ float s[kRowTileR][kRowTileC + 2 * kHalo + 1];
   const int NC = kRowTileC + 2 * kHalo;
-  int c0 = blockIdx.x * kRowTileC, r0 = blockIdx.y * kRowTileR;
   int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   int nl = (W + 1) >> 1;
   for (int rr = 0; rr < kRowTileR; rr++) {
@@ -231,74 +267,98 @@ __global__ __launch_bounds__(256) void k_inv_rows(const float* __restrict__ src,
     if (row >= H) break;
     for (int cc = kHalo + threadIdx.x; cc < kRowTileC + kHalo; cc += 256) {
       int g = c0 - kHalo + cc;
-      if (g < W) dst[row * nx + g] = s[rr][cc];
+      if (g < W) dp[row * nx + g] = s[rr][cc];
     }
   }
 }
 
-// Elementwise prologue/epilogue (levels = 0, base-only check, plain copies).
-// PRO value 3 means "the residual is zero".
+// Elementwise prologue/epilogue over whole fields (blockIdx.y = field).
+// PRO value 3 means "the value is zero" (no residual).  lzero: only fields
+// without transform levels take part.
 template <int PRO, int EPI>
-__global__ __launch_bounds__(256) void k_pointwise(const float* __restrict__ src, float* __restrict__ dst, int n, DwtIO io) {
-  Scal sc = load_scal(io.fp);
+__global__ __launch_bounds__(256) void k_pointwise(const FieldDev* __restrict__ F, int src, int dst, int lzero) {
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active || (lzero && f.L != 0)) return;
+  const int n = f.ny * f.nx;
+  Scal sc = load_scal(f.fp);
+  const float* sp = f.buf[src];
+  float* dp = f.buf[dst];
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    float v = (PRO == 3) ? 0.0f : prologue<(PRO == 3 ? 0 : PRO)>(src, i, io, sc);
-    epilogue<EPI>(dst, i, v, io, sc);
+    float v = (PRO == 3) ? 0.0f : prologue<(PRO == 3 ? 0 : PRO)>(sp, i, f, sc);
+    epilogue<EPI>(dp, i, v, f, sc);
   }
 }
 
-static void sizes(int ny, int nx, int L, int* h, int* w) {
-  h[0] = ny; w[0] = nx;
-  for (int l = 1; l <= L; l++) { h[l] = (h[l - 1] + 1) / 2; w[l] = (w[l - 1] + 1) / 2; }
+struct Grid2 { int gx, gy; };
+static Grid2 level_grid(const FieldDev* Fh, int nf, int l, int tc, int tr) {
+  Grid2 g{0, 0};
+  for (int i = 0; i < nf; i++) {
+    if (!Fh[i].active || l > Fh[i].L) continue;
+    int H = Fh[i].ny, W = Fh[i].nx;
+    for (int k = 1; k < l; k++) { H = (H + 1) / 2; W = (W + 1) / 2; }
+    g.gx = std::max(g.gx, (W + tc - 1) / tc);
+    g.gy = std::max(g.gy, (H + tr - 1) / tr);
+  }
+  return g;
+}
+static int max_L(const FieldDev* Fh, int nf) {
+  int m = 0;
+  for (int i = 0; i < nf; i++)
+    if (Fh[i].active) m = std::max(m, Fh[i].L);
+  return m;
+}
+static bool any_lzero(const FieldDev* Fh, int nf) {
+  for (int i = 0; i < nf; i++)
+    if (Fh[i].active && Fh[i].L == 0) return true;
+  return false;
+}
+static int max_n(const FieldDev* Fh, int nf) {
+  int m = 0;
+  for (int i = 0; i < nf; i++)
+    if (Fh[i].active) m = std::max(m, Fh[i].ny * Fh[i].nx);
+  return m;
 }
 
-void dwt_forward(const float* src, float* a, float* tmp, int ny, int nx, int L, int prologue, const DwtIO& io,
-                 hipStream_t st) {
-  int h[kMaxLevels + 1], w[kMaxLevels + 1];
-  sizes(ny, nx, L, h, w);
-  if (L == 0) {
-    pointwise(src, a, ny * nx, prologue, EPI_STORE, io, st);
-    return;
-  }
-  for (int l = 1; l <= L; l++) {
-    int H = h[l - 1], W = w[l - 1];
-    dim3 gc((W + kColTileC - 1) / kColTileC, (H + kColTileR - 1) / kColTileR);
-    const float* s = (l == 1) ? src : a;
-    int pro = (l == 1) ? prologue : PRO_COPY;
-    if (pro == PRO_NORM) k_fwd_cols<PRO_NORM><<<gc, 256, 0, st>>>(s, tmp, nx, H, W, io);
-    else if (pro == PRO_NORM_MINUS) k_fwd_cols<PRO_NORM_MINUS><<<gc, 256, 0, st>>>(s, tmp, nx, H, W, io);
-    else k_fwd_cols<PRO_COPY><<<gc, 256, 0, st>>>(s, tmp, nx, H, W, io);
-    dim3 gr((W + kRowTileC - 1) / kRowTileC, (H + kRowTileR - 1) / kRowTileR);
-    k_fwd_rows<<<gr, 256, 0, st>>>(tmp, a, nx, H, W);
+void dwt_forward(const FieldDev* F, const FieldDev* Fh, int nf, int src, int dst, int pro, hipStream_t st) {
+  if (any_lzero(Fh, nf)) pointwise(F, Fh, nf, src, dst, pro, EPI_STORE, 1, st);
+  int Lm = max_L(Fh, nf);
+  for (int l = 1; l <= Lm; l++) {
+    Grid2 c = level_grid(Fh, nf, l, kColTileC, kColTileR);
+    if (c.gx == 0) continue;
+    dim3 gc(c.gx, c.gy, nf);
+    int p = (l == 1) ? pro : PRO_COPY;
+    if (p == PRO_NORM) k_fwd_cols<PRO_NORM><<<gc, 256, 0, st>>>(F, l, src, dst);
+    else if (p == PRO_NORM_MINUS) k_fwd_cols<PRO_NORM_MINUS><<<gc, 256, 0, st>>>(F, l, src, dst);
+    else k_fwd_cols<PRO_COPY><<<gc, 256, 0, st>>>(F, l, src, dst);
+    Grid2 r = level_grid(Fh, nf, l, kRowTileC, kRowTileR);
+    k_fwd_rows<<<dim3(r.gx, r.gy, nf), 256, 0, st>>>(F, l, dst);
   }
 }
 
-void dwt_inverse(float* a, float* tmp, float* out, int ny, int nx, int L, int epi, const DwtIO& io,
-                 hipStream_t st) {
-  int h[kMaxLevels + 1], w[kMaxLevels + 1];
-  sizes(ny, nx, L, h, w);
-  if (L == 0) {
-    pointwise(a, out, ny * nx, PRO_COPY, epi, io, st);
-    return;
-  }
-  for (int l = L; l >= 1; l--) {
-    int H = h[l - 1], W = w[l - 1];
-    dim3 gr((W + kRowTileC - 1) / kRowTileC, (H + kRowTileR - 1) / kRowTileR);
-    k_inv_rows<<<gr, 256, 0, st>>>(a, tmp, nx, H, W);
-    dim3 gc((W + kColTileC - 1) / kColTileC, (H + kColTileR - 1) / kColTileR);
+void dwt_inverse(const FieldDev* F, const FieldDev* Fh, int nf, int a, int out, int epi, hipStream_t st) {
+  if (any_lzero(Fh, nf)) pointwise(F, Fh, nf, a, out, PRO_COPY, epi, 1, st);
+  int Lm = max_L(Fh, nf);
+  for (int l = Lm; l >= 1; l--) {
+    Grid2 r = level_grid(Fh, nf, l, kRowTileC, kRowTileR);
+    if (r.gx == 0) continue;
+    k_inv_rows<<<dim3(r.gx, r.gy, nf), 256, 0, st>>>(F, l, a);
+    Grid2 c = level_grid(Fh, nf, l, kColTileC, kColTileR);
+    dim3 gc(c.gx, c.gy, nf);
     int e = (l == 1) ? epi : EPI_STORE;
-    float* d = (l == 1) ? out : a;
-    if (e == EPI_FINAL) k_inv_cols<EPI_FINAL><<<gc, 256, 0, st>>>(tmp, d, nx, H, W, io);
-    else if (e == EPI_CHECK) k_inv_cols<EPI_CHECK><<<gc, 256, 0, st>>>(tmp, d, nx, H, W, io);
-    else k_inv_cols<EPI_STORE><<<gc, 256, 0, st>>>(tmp, d, nx, H, W, io);
+    if (e == EPI_FINAL) k_inv_cols<EPI_FINAL><<<gc, 256, 0, st>>>(F, l, a, out);
+    else if (e == EPI_CHECK) k_inv_cols<EPI_CHECK><<<gc, 256, 0, st>>>(F, l, a, out);
+    else k_inv_cols<EPI_STORE><<<gc, 256, 0, st>>>(F, l, a, out);
   }
 }
 
-void pointwise(const float* src, float* dst, int n, int pro, int epi, const DwtIO& io, hipStream_t st) {
+void pointwise(const FieldDev* F, const FieldDev* Fh, int nf, int src, int dst, int pro, int epi, int lzero,
+               hipStream_t st) {
+  int n = max_n(Fh, nf);
   int blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 2048) blocks = 2048;
   if (blocks < 1) blocks = 1;
-#define PW(P, E) k_pointwise<P, E><<<blocks, 256, 0, st>>>(src, dst, n, io)
+  dim3 g(blocks, nf);
+#define PW(P, E) k_pointwise<P, E><<<g, 256, 0, st>>>(F, src, dst, lzero)
   if (pro == 3) {
     if (epi == EPI_FINAL) PW(3, EPI_FINAL); else if (epi == EPI_CHECK) PW(3, EPI_CHECK); else PW(3, EPI_STORE);
   } else if (pro == PRO_NORM) {

@@ -30,15 +30,30 @@ __device__ __forceinline__ u128 seg_key(uint64_t slope_bits, int b, int j) {
   return ((u128)slope_bits << 40) | ((u128)(0xFFFFFFFFu - (uint32_t)b) << 8) | (u128)(0xFFu - (uint32_t)j);
 }
 
-__global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const uint8_t* __restrict__ pb, const int32_t* __restrict__ R,
-                                                       const int64_t* __restrict__ D, int nblk, int64_t budget,
-                                                       uint8_t* __restrict__ kb, uint8_t* __restrict__ hk,
-                                                       uint64_t* __restrict__ keys, int32_t* __restrict__ dr,
-                                                       uint8_t* __restrict__ nhv, int32_t* __restrict__ len_out) {
+__global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restrict__ F, const uint8_t* __restrict__ pb_g,
+                                                       const int32_t* __restrict__ R_g, const int64_t* __restrict__ D_g,
+                                                       uint8_t* __restrict__ kb_g, uint8_t* __restrict__ hk_g,
+                                                       uint64_t* __restrict__ keys_g, int32_t* __restrict__ dr_g,
+                                                       uint8_t* __restrict__ nhv_g, int32_t* __restrict__ len_g) {
   __shared__ unsigned long long hist[256];
   __shared__ int s_choice;
   __shared__ int s_allfit;
   __shared__ unsigned long long s_acc;
+  const FieldDev& f = F[blockIdx.x];
+  if (!f.active) return;
+  // this field's blocks: [blk0, blk0 + nblk) of the call's block arrays
+  const size_t b0 = (size_t)f.blk0;
+  const int nblk = f.nblk;
+  const int64_t budget = f.budget < 0 ? 0 : f.budget;
+  const uint8_t* pb = pb_g + b0;
+  const int32_t* R = R_g + b0 * kPassStride;
+  const int64_t* D = D_g + b0 * kPassStride;
+  uint8_t* kb = kb_g + b0;
+  uint8_t* hk = hk_g + b0 * kPassStride;
+  uint64_t* keys = keys_g + b0 * kPassStride;
+  int32_t* dr = dr_g + b0 * kPassStride;
+  uint8_t* nhv = nhv_g + b0;
+  int32_t* len_out = len_g + b0;
   int tid = threadIdx.x;
   // 1. hulls
   for (int b = tid; b < nblk; b += kPcrdThreads) {
@@ -119,12 +134,11 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const uint8_t* __restrict
   }
 }
 
-void pcrd(const uint8_t* pb, const int32_t* R, const int64_t* D, int nblk, int64_t budget, uint8_t* kb,
+void pcrd(const FieldDev* F, int nf, const uint8_t* pb, const int32_t* R, const int64_t* D, uint8_t* kb,
           uint8_t* hk_scratch, uint64_t* key_scratch, int32_t* dr_scratch, uint8_t* nh_scratch, int32_t* len_out,
           hipStream_t st) {
-  if (nblk <= 0) return;
-  k_pcrd<<<1, kPcrdThreads, 0, st>>>(pb, R, D, nblk, budget < 0 ? 0 : budget, kb, hk_scratch, key_scratch,
-                                     dr_scratch, nh_scratch, len_out);
+  if (nf <= 0) return;
+  k_pcrd<<<nf, kPcrdThreads, 0, st>>>(F, pb, R, D, kb, hk_scratch, key_scratch, dr_scratch, nh_scratch, len_out);
 }
 
 }  // namespace ebcc

@@ -18,6 +18,8 @@
 //    (removal = clearing an "alive" bit), bits are packed MSB-first.
 #include "common.h"
 
+#include <algorithm>
+
 namespace ebcc {
 
 // List entry: j | i << 24 | band << 48 | typeB << 56 | alive << 57.
@@ -58,19 +60,28 @@ __device__ __forceinline__ int offspring(const Band* B, int L, int band, int i, 
 // Level of a node's offspring (roots: the coarsest detail level).
 __device__ __forceinline__ int child_level(const Band* B, int L, int band) { return band == 0 ? L : B[band].level - 1; }
 
-__global__ __launch_bounds__(256) void k_maxima(const uint32_t* __restrict__ qr, int nx, const Band* __restrict__ bands,
-                                                int L, int band, uint32_t* __restrict__ sub, uint32_t* __restrict__ maxd,
-                                                uint32_t* __restrict__ maxl) {
-  const Band& bd = bands[band];
+// Band index of (level, orientation 0..2) in a field with L levels; level 0
+// denotes the LL roots.
+__device__ __forceinline__ int band_index(int L, int lvl, int o) { return lvl == 0 ? 0 : 1 + 3 * (L - lvl) + o; }
+
+__global__ __launch_bounds__(256) void k_maxima(const FieldDev* __restrict__ F, int lvl, int o) {
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active || lvl > f.L || (lvl == 1)) return;
+  const int L = f.L, nx = f.nx;
+  const Band* bands = f.bands;
+  const int band = band_index(L, lvl, o);
+  const Band bd = bands[band];
   int n = bd.h * bd.w;
   int cl = child_level(bands, L, band);
+  const uint32_t* qr = f.qr;
+  uint32_t *sub = f.sub, *maxd = f.maxd, *maxl = f.maxl;
   for (int t = blockIdx.x * 256 + threadIdx.x; t < n; t += gridDim.x * 256) {
     int i = t / bd.w, j = t - i * bd.w;
-    uint64_t o[9];
-    int no = offspring(bands, L, band, i, j, o);
+    uint64_t oo[9];
+    int no = offspring(bands, L, band, i, j, oo);
     uint32_t md = 0, ml = 0;
     for (int c = 0; c < no; c++) {
-      int pc = nd_pos(bands, nx, o[c]);
+      int pc = nd_pos(bands, nx, oo[c]);
       uint32_t s, d;
       if (cl == 1) { s = qr[pc] & 0x7FFFFFu; d = 0; }
       else { s = sub[pc]; d = maxd[pc]; }
@@ -85,21 +96,40 @@ __global__ __launch_bounds__(256) void k_maxima(const uint32_t* __restrict__ qr,
   }
 }
 
-void spiht_maxima(const uint32_t* qr, int nx, const Band* bands_dev, const Band* bands_host, int nb, int L,
-                  uint32_t* sub, uint32_t* maxd, uint32_t* maxl, hipStream_t st) {
+// Largest band of (level, orientation) over the active fields (host side).
+static int max_band_size(const FieldDev* Fh, int nf, int lvl, int o) {
+  int m = 0;
+  for (int i = 0; i < nf; i++) {
+    const FieldDev& f = Fh[i];
+    if (!f.active || lvl > f.L) continue;
+    int h = f.ny, w = f.nx;
+    int hp = h, wp = w;
+    int lv = lvl == 0 ? f.L : lvl;
+    for (int k = 1; k <= lv; k++) { hp = h; wp = w; h = (h + 1) / 2; w = (w + 1) / 2; }
+    int bh, bw;
+    if (lvl == 0) { bh = h; bw = w; }
+    else if (o == 0) { bh = h; bw = wp - w; }
+    else if (o == 1) { bh = hp - h; bw = w; }
+    else { bh = hp - h; bw = wp - w; }
+    m = std::max(m, bh * bw);
+  }
+  return m;
+}
+
+void spiht_maxima(const FieldDev* F, const FieldDev* Fh, int nf, hipStream_t st) {
+  int Lm = 0;
+  for (int i = 0; i < nf; i++)
+    if (Fh[i].active) Lm = std::max(Lm, Fh[i].L);
   // finer parents first: levels 2 .. L, then the LL roots
-  for (int l = 2; l <= L; l++)
+  for (int l = 2; l <= Lm; l++)
     for (int o = 0; o < 3; o++) {
-      int band = 1 + 3 * (L - l) + o;
-      int n = bands_host[band].h * bands_host[band].w;
-      int g = (n + 255) / 256;
-      if (g > 2048) g = 2048;
-      if (n > 0) k_maxima<<<g, 256, 0, st>>>(qr, nx, bands_dev, L, band, sub, maxd, maxl);
+      int n = max_band_size(Fh, nf, l, o);
+      int g = std::min(2048, std::max(1, (n + 255) / 256));
+      if (n > 0) k_maxima<<<dim3(g, nf), 256, 0, st>>>(F, l, o);
     }
-  int n = bands_host[0].h * bands_host[0].w;
-  int g = (n + 255) / 256;
-  if (g > 2048) g = 2048;
-  k_maxima<<<g, 256, 0, st>>>(qr, nx, bands_dev, L, 0, sub, maxd, maxl);
+  int n = max_band_size(Fh, nf, 0, 0);
+  int g = std::min(2048, std::max(1, (n + 255) / 256));
+  k_maxima<<<dim3(g, nf), 256, 0, st>>>(F, 0, 0);
 }
 
 // Tiles per wavefront: one per wavefront for a lone field (latency), up to
@@ -133,19 +163,19 @@ struct BitW {
 };
 
 template <int LANES>
-__global__ __launch_bounds__(LANES) void k_spiht_encode(const uint32_t* __restrict__ qr, const uint32_t* __restrict__ sub,
-                                                     const uint32_t* __restrict__ maxd, const uint32_t* __restrict__ maxl,
-                                                     int nx, const Band* __restrict__ bands_g, int nb, int L,
-                                                     const TileD* __restrict__ tiles, int ntiles, int n_s,
-                                                     uint64_t* __restrict__ lists, uint8_t* __restrict__ slots,
-                                                     const int64_t* __restrict__ slot_off, uint32_t* __restrict__ tlen,
-                                                     uint32_t* __restrict__ tent) {
-  __shared__ Band B[kMaxBands];
-  for (int i = threadIdx.x; i < nb; i += LANES) B[i] = bands_g[i];
-  __syncthreads();
+__global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
+                                                        int ntiles, uint64_t* __restrict__ lists,
+                                                        uint8_t* __restrict__ slots,
+                                                        const int64_t* __restrict__ slot_off,
+                                                        uint32_t* __restrict__ tlen, uint32_t* __restrict__ tent) {
   int t = blockIdx.x * LANES + threadIdx.x;
   if (t >= ntiles) return;
   TileD td = tiles[t];
+  const FieldDev& f = F[td.field];
+  if (!f.active) return;
+  const Band* B = f.bands;
+  const int nx = f.nx, L = f.L, n_s = f.ns;
+  const uint32_t *qr = f.qr, *sub = f.sub, *maxd = f.maxd, *maxl = f.maxl;
   uint32_t mx = 0;
   for (int i = td.i0; i < td.i1; i++)
     for (int j = td.j0; j < td.j1; j++) {
@@ -224,13 +254,11 @@ __global__ __launch_bounds__(LANES) void k_spiht_encode(const uint32_t* __restri
   tent[t] = (uint32_t)w.pos | ((uint32_t)(ntop + 1) << 26);
 }
 
-void spiht_encode(const uint32_t* qr, const uint32_t* sub, const uint32_t* maxd, const uint32_t* maxl, int nx,
-                  const Band* bands, int nb, int L, const TileD* tiles, int ntiles, int n_s, uint64_t* lists,
-                  uint8_t* slots, const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st) {
+void spiht_encode(const FieldDev* F, const TileD* tiles, int ntiles, uint64_t* lists, uint8_t* slots,
+                  const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st) {
   if (ntiles <= 0) return;
   int ln = pick_tile_lanes(ntiles);
-#define ENC_L(LN) k_spiht_encode<LN><<<(ntiles + LN - 1) / LN, LN, 0, st>>>(qr, sub, maxd, maxl, nx, bands, nb, L, \
-                                                                        tiles, ntiles, n_s, lists, slots, slot_off, \
+#define ENC_L(LN) k_spiht_encode<LN><<<(ntiles + LN - 1) / LN, LN, 0, st>>>(F, tiles, ntiles, lists, slots, slot_off, \
                                                                         tlen, tent)
   if (ln == 1) ENC_L(1); else if (ln == 4) ENC_L(4); else if (ln == 16) ENC_L(16); else ENC_L(64);
 #undef ENC_L
@@ -250,23 +278,27 @@ struct BitR {
 // sec: residual section (tile table then payloads); toff[t]: offset of tile
 // t's payload after the table.  mags: N-sized scratch (magnitude | sign << 31).
 template <int LANES>
-__global__ __launch_bounds__(LANES) void k_spiht_decode(const uint8_t* __restrict__ sec, int64_t sec_len,
-                                                     const int64_t* __restrict__ toff, int nx,
-                                                     const Band* __restrict__ bands_g, int nb, int L,
-                                                     const TileD* __restrict__ tiles, int ntiles, int n_s, int e_r,
-                                                     uint64_t* __restrict__ lists, uint32_t* __restrict__ mags,
-                                                     float* __restrict__ chat, int* __restrict__ flag) {
-  __shared__ Band B[kMaxBands];
-  for (int i = threadIdx.x; i < nb; i += LANES) B[i] = bands_g[i];
-  __syncthreads();
+__global__ __launch_bounds__(LANES) void k_spiht_decode(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
+                                                        int ntiles, const int64_t* __restrict__ toff,
+                                                        uint64_t* __restrict__ lists) {
   int t = blockIdx.x * LANES + threadIdx.x;
   if (t >= ntiles) return;
   TileD td = tiles[t];
-  uint32_t ent = (uint32_t)sec[4 * t] | ((uint32_t)sec[4 * t + 1] << 8) | ((uint32_t)sec[4 * t + 2] << 16) |
-                 ((uint32_t)sec[4 * t + 3] << 24);
+  const FieldDev& f = F[td.field];
+  if (!f.active) return;
+  const Band* B = f.bands;
+  const int nx = f.nx, L = f.L, n_s = f.ns, e_r = f.er;
+  const uint8_t* sec = f.out + kHdr + f.bb;
+  const int64_t sec_len = f.rb;
+  uint32_t* mags = f.qr;
+  float* chat = f.buf[BUF_CHAT];
+  int* flag = &f.flags[1];
+  const int tl = t - f.tile0;
+  uint32_t ent = (uint32_t)sec[4 * tl] | ((uint32_t)sec[4 * tl + 1] << 8) | ((uint32_t)sec[4 * tl + 2] << 16) |
+                 ((uint32_t)sec[4 * tl + 3] << 24);
   int64_t len = ent & 0x3FFFFFF;
   int ntop = (int)(ent >> 26) - 1;
-  int64_t pbase = 4 * (int64_t)ntiles;      // payloads follow the tile table
+  int64_t pbase = 4 * (int64_t)f.ntiles;      // payloads follow the tile table
   int64_t o0 = toff[t];
   if (o0 < 0 || pbase + o0 + len > sec_len || (ntop >= kQBits)) { atomicOr(flag, 1); return; }
   if (ntop < n_s) return;
@@ -334,14 +366,11 @@ __global__ __launch_bounds__(LANES) void k_spiht_decode(const uint8_t* __restric
   }
 }
 
-void spiht_decode(const uint8_t* sec, int64_t sec_len, const int64_t* toff, int nx, const Band* bands, int nb, int L,
-                  const TileD* tiles, int ntiles, int n_s, int e_r, uint64_t* lists, uint32_t* mags, float* chat,
-                  int* flag, hipStream_t st) {
+void spiht_decode(const FieldDev* F, const TileD* tiles, int ntiles, const int64_t* toff, uint64_t* lists,
+                  hipStream_t st) {
   if (ntiles <= 0) return;
   int ln = pick_tile_lanes(ntiles);
-#define DEC_L(LN) k_spiht_decode<LN><<<(ntiles + LN - 1) / LN, LN, 0, st>>>(sec, sec_len, toff, nx, bands, nb, L, \
-                                                                        tiles, ntiles, n_s, e_r, lists, mags, chat, \
-                                                                        flag)
+#define DEC_L(LN) k_spiht_decode<LN><<<(ntiles + LN - 1) / LN, LN, 0, st>>>(F, tiles, ntiles, toff, lists)
   if (ln == 1) DEC_L(1); else if (ln == 4) DEC_L(4); else if (ln == 16) DEC_L(16); else DEC_L(64);
 #undef DEC_L
 }

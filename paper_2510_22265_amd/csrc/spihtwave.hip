@@ -143,12 +143,8 @@ __device__ bool spiht_setup(SpihtLds<CAP>& S, const Band* bands_g, int nb, int L
 }
 
 template <int CAP>
-__global__ __launch_bounds__(64) void k_spiht_encode_lds(const uint32_t* __restrict__ qr, const uint32_t* __restrict__ sub,
-                                                         const uint32_t* __restrict__ maxd,
-                                                         const uint32_t* __restrict__ maxl, int nx,
-                                                         const Band* __restrict__ bands_g, int nb, int L,
-                                                         const TileD* __restrict__ tiles, int ntiles, int n_s,
-                                                         uint8_t* __restrict__ slots,
+__global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
+                                                         int ntiles, uint8_t* __restrict__ slots,
                                                          const int64_t* __restrict__ slot_off,
                                                          uint32_t* __restrict__ tlen, uint32_t* __restrict__ tent,
                                                          int* __restrict__ misfit) {
@@ -156,6 +152,11 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const uint32_t* __restr
   const int lane = threadIdx.x;
   const int t = blockIdx.x;
   const TileD td = tiles[t];
+  const FieldDev& f = F[td.field];
+  if (!f.active) return;
+  const uint32_t *qr = f.qr, *sub = f.sub, *maxd = f.maxd, *maxl = f.maxl;
+  const Band* bands_g = f.bands;
+  const int nx = f.nx, nb = f.nb, L = f.L, n_s = f.ns;
   if (!spiht_setup<CAP>(S, bands_g, nb, L, td, lane)) {
     if (lane == 0) misfit[t] = 1;
     return;
@@ -389,27 +390,33 @@ struct BitRU {
 };
 
 template <int CAP>
-__global__ __launch_bounds__(64) void k_spiht_decode_lds(const uint8_t* __restrict__ sec, int64_t sec_len,
-                                                         const int64_t* __restrict__ toff, int nx,
-                                                         const Band* __restrict__ bands_g, int nb, int L,
-                                                         const TileD* __restrict__ tiles, int ntiles, int n_s,
-                                                         int e_r, float* __restrict__ chat, int* __restrict__ flag,
+__global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
+                                                         int ntiles, const int64_t* __restrict__ toff,
                                                          int* __restrict__ misfit) {
   __shared__ SpihtLds<CAP> S;
   const int lane = threadIdx.x;
   const int t = blockIdx.x;
   const TileD td = tiles[t];
+  const FieldDev& f = F[td.field];
+  if (!f.active) return;
+  const uint8_t* __restrict__ sec = f.out + kHdr + f.bb;
+  const int64_t sec_len = f.rb;
+  const Band* bands_g = f.bands;
+  const int nx = f.nx, nb = f.nb, L = f.L, n_s = f.ns, e_r = f.er;
+  float* chat = f.buf[BUF_CHAT];
+  int* flag = &f.flags[1];
+  const int tl = t - f.tile0;
   if (!spiht_setup<CAP>(S, bands_g, nb, L, td, lane)) {
     if (lane == 0) misfit[t] = 1;
     return;
   }
   if (lane == 0) misfit[t] = 0;
   const TileGeom& g = S.g;
-  const uint32_t ent = (uint32_t)sec[4 * t] | ((uint32_t)sec[4 * t + 1] << 8) | ((uint32_t)sec[4 * t + 2] << 16) |
-                       ((uint32_t)sec[4 * t + 3] << 24);
+  const uint32_t ent = (uint32_t)sec[4 * tl] | ((uint32_t)sec[4 * tl + 1] << 8) | ((uint32_t)sec[4 * tl + 2] << 16) |
+                       ((uint32_t)sec[4 * tl + 3] << 24);
   const int64_t len = ent & 0x3FFFFFF;
   const int ntop = (int)(ent >> 26) - 1;
-  const int64_t pbase = 4 * (int64_t)ntiles;
+  const int64_t pbase = 4 * (int64_t)f.ntiles;
   const int64_t o0 = toff[t];
   if (o0 < 0 || pbase + o0 + len > sec_len || ntop >= kQBits) {
     if (lane == 0) atomicOr(flag, 1);
@@ -540,29 +547,22 @@ int spiht_lds_cap(int max_tile_coef) {
   return 0;
 }
 
-void spiht_encode_lds(int cap, const uint32_t* qr, const uint32_t* sub, const uint32_t* maxd, const uint32_t* maxl,
-                      int nx, const Band* bands, int nb, int L, const TileD* tiles, int ntiles, int n_s,
-                      uint8_t* slots, const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit,
+void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, int ntiles, uint8_t* slots,
+                      const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit, hipStream_t st) {
+  if (ntiles <= 0) return;
+  if (cap == kSpihtSmall)
+    k_spiht_encode_lds<kSpihtSmall><<<ntiles, 64, 0, st>>>(F, tiles, ntiles, slots, slot_off, tlen, tent, misfit);
+  else
+    k_spiht_encode_lds<kSpihtBig><<<ntiles, 64, 0, st>>>(F, tiles, ntiles, slots, slot_off, tlen, tent, misfit);
+}
+
+void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, int ntiles, const int64_t* toff, int* misfit,
                       hipStream_t st) {
   if (ntiles <= 0) return;
   if (cap == kSpihtSmall)
-    k_spiht_encode_lds<kSpihtSmall><<<ntiles, 64, 0, st>>>(qr, sub, maxd, maxl, nx, bands, nb, L, tiles, ntiles, n_s,
-                                                            slots, slot_off, tlen, tent, misfit);
+    k_spiht_decode_lds<kSpihtSmall><<<ntiles, 64, 0, st>>>(F, tiles, ntiles, toff, misfit);
   else
-    k_spiht_encode_lds<kSpihtBig><<<ntiles, 64, 0, st>>>(qr, sub, maxd, maxl, nx, bands, nb, L, tiles, ntiles, n_s,
-                                                          slots, slot_off, tlen, tent, misfit);
-}
-
-void spiht_decode_lds(int cap, const uint8_t* sec, int64_t sec_len, const int64_t* toff, int nx, const Band* bands,
-                      int nb, int L, const TileD* tiles, int ntiles, int n_s, int e_r, float* chat, int* flag,
-                      int* misfit, hipStream_t st) {
-  if (ntiles <= 0) return;
-  if (cap == kSpihtSmall)
-    k_spiht_decode_lds<kSpihtSmall><<<ntiles, 64, 0, st>>>(sec, sec_len, toff, nx, bands, nb, L, tiles, ntiles, n_s,
-                                                            e_r, chat, flag, misfit);
-  else
-    k_spiht_decode_lds<kSpihtBig><<<ntiles, 64, 0, st>>>(sec, sec_len, toff, nx, bands, nb, L, tiles, ntiles, n_s,
-                                                          e_r, chat, flag, misfit);
+    k_spiht_decode_lds<kSpihtBig><<<ntiles, 64, 0, st>>>(F, tiles, ntiles, toff, misfit);
 }
 
 }  // namespace ebcc

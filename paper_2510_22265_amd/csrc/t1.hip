@@ -30,13 +30,16 @@ namespace ebcc {
 // planes: [nblk][kQBits][cbh] masks; signs: [nblk][cbh]; pb: [nblk].
 // ------------------------------------------------------------------------
 template <typename M>
-__global__ __launch_bounds__(256) void k_quant_planes(const float* __restrict__ coef, int nx, const Blk* __restrict__ blk,
-                                                      int nblk, int e0, int cbw, int cbh, M* __restrict__ planes,
+__global__ __launch_bounds__(256) void k_quant_planes(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                      int nblk, int cbw, int cbh, M* __restrict__ planes,
                                                       M* __restrict__ signs, uint8_t* __restrict__ pb) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int b = blockIdx.x * 4 + wave;
   if (b >= nblk) return;
   Blk k = blk[b];
+  if (!F[k.field].active) return;
+  const float* coef = F[k.field].buf[BUF_COEF];
+  const int nx = F[k.field].nx, e0 = F[k.field].e0;
   int sh = k.gain - e0;
   uint32_t mx = 0;
   for (int i = lane; i < k.w * k.h; i += 64) {
@@ -222,8 +225,8 @@ struct T1Lane {
 // Tier-1 encoder: one lane per code-block.
 // ------------------------------------------------------------------------
 template <typename M, int ROWS, int LANES>
-__global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ coef, int nx, const Blk* __restrict__ blk,
-                                                     int nblk, int e0, int cbh, const M* __restrict__ planes,
+__global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                     int nblk, int cbh, const M* __restrict__ planes,
                                                      const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
                                                      uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
                                                      int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
@@ -235,6 +238,9 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ c
   int b = blockIdx.x * LANES + lane;
   if (b >= nblk) return;
   Blk k = blk[b];
+  if (!F[k.field].active) return;
+  const float* coef = F[k.field].buf[BUF_COEF];
+  const int nx = F[k.field].nx, e0 = F[k.field].e0;
   int P = pbv[b];
   int32_t* R = Rt + (size_t)b * kPassStride;
   int64_t* Dd = Dt + (size_t)b * kPassStride;
@@ -376,14 +382,17 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const float* __restrict__ c
 // Closed-form base reconstruction for the kept passes (one wave per block).
 // ------------------------------------------------------------------------
 template <typename M>
-__global__ __launch_bounds__(256) void k_virtual_decode(const float* __restrict__ coef, int nx, const Blk* __restrict__ blk,
-                                                        int nblk, int e0, int cbh, const uint8_t* __restrict__ pbv,
-                                                        const uint8_t* __restrict__ kbv, const M* __restrict__ sppf,
-                                                        float* __restrict__ yhat) {
+__global__ __launch_bounds__(256) void k_virtual_decode(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                        int nblk, int cbh, const uint8_t* __restrict__ pbv,
+                                                        const uint8_t* __restrict__ kbv, const M* __restrict__ sppf) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int b = blockIdx.x * 4 + wave;
   if (b >= nblk) return;
   Blk k = blk[b];
+  if (!F[k.field].active) return;
+  const float* coef = F[k.field].buf[BUF_COEF];
+  float* yhat = F[k.field].buf[BUF_YHAT];
+  const int nx = F[k.field].nx, e0 = F[k.field].e0;
   int P = pbv[b], kb = kbv[b];
   int sh = k.gain - e0, e = e0 - k.gain;
   for (int i = lane; i < k.w * k.h; i += 64) {
@@ -481,10 +490,9 @@ __device__ __forceinline__ int mq_decode(MQDec& d, uint8_t* cs_ptr, const uint32
 // in yhat's storage as integers until the block is finished.
 // ------------------------------------------------------------------------
 template <typename M, int ROWS, int LANES>
-__global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__ sec, int64_t sec_len,
-                                                     const uint32_t* __restrict__ table, const int64_t* __restrict__ off,
-                                                     int nx, const Blk* __restrict__ blk, int nblk, int e0,
-                                                     float* __restrict__ yhat, int* __restrict__ flag) {
+__global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                     int nblk, const uint32_t* __restrict__ table,
+                                                     const int64_t* __restrict__ off) {
   __shared__ T1Shared<M, ROWS, LANES> S;     // aux = coded in the current plane
   int lane = threadIdx.x;
   for (int i = lane; i < 47; i += LANES) S.mqt[i] = c_mqt[i];
@@ -492,6 +500,13 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const uint8_t* __restrict__
   int b = blockIdx.x * LANES + lane;
   if (b >= nblk) return;
   Blk k = blk[b];
+  const FieldDev& f = F[k.field];
+  if (!f.active) return;
+  const uint8_t* sec = f.out + kHdr + 4 * (size_t)f.nblk;
+  const int64_t sec_len = (int64_t)f.bb - 4 * (int64_t)f.nblk;
+  const int nx = f.nx, e0 = f.e0;
+  float* yhat = f.buf[BUF_YHAT];
+  int* flag = &f.flags[1];
   uint32_t ent = table[b];
   int P = ent & 0xFF, kb = (ent >> 8) & 0xFF, len = (int)(ent >> 16);
   int64_t o = off[b];
@@ -655,13 +670,13 @@ constexpr int t1_lanes_max() {
   } while (0)
 
 template <typename M, int ROWS>
-static void launch_encode(int nblk, const float* coef, int nx, const Blk* blk, int e0, int cbh, const void* planes,
-                          const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
-                          uint32_t* tail, void* sppf, hipStream_t st) {
+static void launch_encode(int nblk, const FieldDev* F, const Blk* blk, int cbh, const void* planes, const void* signs,
+                          const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail,
+                          void* sppf, hipStream_t st) {
   constexpr int LM = t1_lanes_max<M, ROWS>();
   int ln = pick_lanes(nblk, LM);
-#define ENC_L(LN)                                                                                                    \
-  k_t1_encode<M, ROWS, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(coef, nx, blk, nblk, e0, cbh, (const M*)planes,       \
+#define ENC_L(LN)                                                                                                  \
+  k_t1_encode<M, ROWS, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(F, blk, nblk, cbh, (const M*)planes,               \
                                                                (const M*)signs, pb, cw, R, D, bp, tail, (M*)sppf)
   if (ln == 1) ENC_L(1);
   else if (ln == 4) ENC_L(4);
@@ -671,12 +686,11 @@ static void launch_encode(int nblk, const float* coef, int nx, const Blk* blk, i
 }
 
 template <typename M, int ROWS>
-static void launch_decode(int nblk, const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off,
-                          int nx, const Blk* blk, int e0, float* yhat, int* flag, hipStream_t st) {
+static void launch_decode(int nblk, const FieldDev* F, const Blk* blk, const uint32_t* table, const int64_t* off,
+                          hipStream_t st) {
   constexpr int LM = t1_lanes_max<M, ROWS>();
   int ln = pick_lanes(nblk, LM);
-#define DEC_L(LN) \
-  k_t1_decode<M, ROWS, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(sec, sec_len, table, off, nx, blk, nblk, e0, yhat, flag)
+#define DEC_L(LN) k_t1_decode<M, ROWS, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(F, blk, nblk, table, off)
   if (ln == 1) DEC_L(1);
   else if (ln == 4) DEC_L(4);
   else if (ln == 16 || LM == 16) DEC_L((LM >= 16 ? 16 : 4));
@@ -684,16 +698,14 @@ static void launch_decode(int nblk, const uint8_t* sec, int64_t sec_len, const u
 #undef DEC_L
 }
 
-void quant_planes(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, void* planes,
-                  void* signs, uint8_t* pb, hipStream_t st) {
+void quant_planes(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, void* planes, void* signs,
+                  uint8_t* pb, hipStream_t st) {
   if (nblk <= 0) return;
   int g = (nblk + 3) / 4;
   if (cbw <= 32)
-    k_quant_planes<uint32_t><<<g, 256, 0, st>>>(coef, nx, blk, nblk, e0, cbw, cbh, (uint32_t*)planes,
-                                                 (uint32_t*)signs, pb);
+    k_quant_planes<uint32_t><<<g, 256, 0, st>>>(F, blk, nblk, cbw, cbh, (uint32_t*)planes, (uint32_t*)signs, pb);
   else
-    k_quant_planes<uint64_t><<<g, 256, 0, st>>>(coef, nx, blk, nblk, e0, cbw, cbh, (uint64_t*)planes,
-                                                 (uint64_t*)signs, pb);
+    k_quant_planes<uint64_t><<<g, 256, 0, st>>>(F, blk, nblk, cbw, cbh, (uint64_t*)planes, (uint64_t*)signs, pb);
 }
 
 // Up to this many blocks in flight the wave-per-block coder is used (latency);
@@ -709,37 +721,37 @@ static bool use_wave(int nblk) {
   return v == 1 || (v == 0 && nblk <= kWaveBlocksMax);
 }
 
-void t1_encode(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, const void* planes,
-               const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
-               uint32_t* tail, void* sppf, hipStream_t st) {
+void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes, const void* signs,
+               const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail, void* sppf,
+               hipStream_t st) {
   if (nblk <= 0) return;
   if (use_wave(nblk)) {
-    t1_encode_wave(coef, nx, blk, nblk, e0, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st);
+    t1_encode_wave(F, blk, nblk, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st);
     return;
   }
-#define ENC(MT, RW) launch_encode<MT, RW>(nblk, coef, nx, blk, e0, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st)
+#define ENC(MT, RW) launch_encode<MT, RW>(nblk, F, blk, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st)
   T1_DISPATCH(cbw, cbh, ENC);
 #undef ENC
 }
 
-void virtual_decode(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, const uint8_t* pb,
-                    const uint8_t* kb, const void* sppf, float* yhat, hipStream_t st) {
+void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,
+                    const uint8_t* kb, const void* sppf, hipStream_t st) {
   if (nblk <= 0) return;
   int g = (nblk + 3) / 4;
   if (cbw <= 32)
-    k_virtual_decode<uint32_t><<<g, 256, 0, st>>>(coef, nx, blk, nblk, e0, cbh, pb, kb, (const uint32_t*)sppf, yhat);
+    k_virtual_decode<uint32_t><<<g, 256, 0, st>>>(F, blk, nblk, cbh, pb, kb, (const uint32_t*)sppf);
   else
-    k_virtual_decode<uint64_t><<<g, 256, 0, st>>>(coef, nx, blk, nblk, e0, cbh, pb, kb, (const uint64_t*)sppf, yhat);
+    k_virtual_decode<uint64_t><<<g, 256, 0, st>>>(F, blk, nblk, cbh, pb, kb, (const uint64_t*)sppf);
 }
 
-void t1_decode(const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off, int nx, const Blk* blk,
-               int nblk, int e0, int cbw, int cbh, float* yhat, int* flag, hipStream_t st) {
+void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
+               const int64_t* off, hipStream_t st) {
   if (nblk <= 0) return;
   if (use_wave(nblk)) {
-    t1_decode_wave(sec, sec_len, table, off, nx, blk, nblk, e0, cbw, yhat, flag, st);
+    t1_decode_wave(F, blk, nblk, cbw, table, off, st);
     return;
   }
-#define DEC(MT, RW) launch_decode<MT, RW>(nblk, sec, sec_len, table, off, nx, blk, e0, yhat, flag, st)
+#define DEC(MT, RW) launch_decode<MT, RW>(nblk, F, blk, table, off, st)
   T1_DISPATCH(cbw, cbh, DEC);
 #undef DEC
 }

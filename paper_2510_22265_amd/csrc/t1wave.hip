@@ -127,8 +127,8 @@ __device__ __forceinline__ int sgn3(M s, M n, int x) {
 #define NR(rr) ((rr) < 0 ? nA : ((rr) > 3 ? nC : nB[(rr)]))
 
 template <typename M>
-__global__ __launch_bounds__(64) void k_t1_encode_wave(const float* __restrict__ coef, int nx, const Blk* __restrict__ blk,
-                                                       int nblk, int e0, int cbh, const M* __restrict__ planes,
+__global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                       int nblk, int cbh, const M* __restrict__ planes,
                                                        const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
                                                        uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
                                                        int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
@@ -137,6 +137,9 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const float* __restrict__
   const int lane = threadIdx.x;
   const int b = blockIdx.x;
   const Blk k = blk[b];
+  if (!F[k.field].active) return;
+  const float* coef = F[k.field].buf[BUF_COEF];
+  const int nx = F[k.field].nx, e0 = F[k.field].e0;
   const int P = pbv[b];
   const int h = k.h, w = k.w;
   int32_t* R = Rt + (size_t)b * kPassStride;
@@ -431,15 +434,20 @@ __device__ __forceinline__ int mqwd_decode(MQWD& d, uint32_t& ctxv, uint32_t tab
 }
 
 template <typename M>
-__global__ __launch_bounds__(64) void k_t1_decode_wave(const uint8_t* __restrict__ sec, int64_t sec_len,
-                                                       const uint32_t* __restrict__ table,
-                                                       const int64_t* __restrict__ off, int nx,
-                                                       const Blk* __restrict__ blk, int nblk, int e0,
-                                                       float* __restrict__ yhat, int* __restrict__ flag) {
+__global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                       int nblk, const uint32_t* __restrict__ table,
+                                                       const int64_t* __restrict__ off) {
   __shared__ uint32_t qm[64 * 64];   // decoded magnitudes [y][x], pitch 64
   const int lane = threadIdx.x;
   const int b = blockIdx.x;
   const Blk k = blk[b];
+  const FieldDev& f = F[k.field];
+  if (!f.active) return;
+  const uint8_t* __restrict__ sec = f.out + kHdr + 4 * (size_t)f.nblk;
+  const int64_t sec_len = (int64_t)f.bb - 4 * (int64_t)f.nblk;
+  const int nx = f.nx, e0 = f.e0;
+  float* yhat = f.buf[BUF_YHAT];
+  int* flag = &f.flags[1];
   const int h = k.h, w = k.w;
   const uint32_t ent = table[b];
   const int P = ent & 0xFF, kb = (ent >> 8) & 0xFF, len = (int)(ent >> 16);
@@ -648,25 +656,25 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const uint8_t* __restrict
 #undef SR
 #undef NR
 
-void t1_encode_wave(const float* coef, int nx, const Blk* blk, int nblk, int e0, int cbw, int cbh, const void* planes,
+void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
                     const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
                     uint32_t* tail, void* sppf, hipStream_t st) {
   if (nblk <= 0) return;
   if (cbw <= 32)
-    k_t1_encode_wave<uint32_t><<<nblk, 64, 0, st>>>(coef, nx, blk, nblk, e0, cbh, (const uint32_t*)planes,
-                                                     (const uint32_t*)signs, pb, cw, R, D, bp, tail, (uint32_t*)sppf);
+    k_t1_encode_wave<uint32_t><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes, (const uint32_t*)signs,
+                                                     pb, cw, R, D, bp, tail, (uint32_t*)sppf);
   else
-    k_t1_encode_wave<uint64_t><<<nblk, 64, 0, st>>>(coef, nx, blk, nblk, e0, cbh, (const uint64_t*)planes,
-                                                     (const uint64_t*)signs, pb, cw, R, D, bp, tail, (uint64_t*)sppf);
+    k_t1_encode_wave<uint64_t><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint64_t*)planes, (const uint64_t*)signs,
+                                                     pb, cw, R, D, bp, tail, (uint64_t*)sppf);
 }
 
-void t1_decode_wave(const uint8_t* sec, int64_t sec_len, const uint32_t* table, const int64_t* off, int nx,
-                    const Blk* blk, int nblk, int e0, int cbw, float* yhat, int* flag, hipStream_t st) {
+void t1_decode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, const uint32_t* table, const int64_t* off,
+                    hipStream_t st) {
   if (nblk <= 0) return;
   if (cbw <= 32)
-    k_t1_decode_wave<uint32_t><<<nblk, 64, 0, st>>>(sec, sec_len, table, off, nx, blk, nblk, e0, yhat, flag);
+    k_t1_decode_wave<uint32_t><<<nblk, 64, 0, st>>>(F, blk, nblk, table, off);
   else
-    k_t1_decode_wave<uint64_t><<<nblk, 64, 0, st>>>(sec, sec_len, table, off, nx, blk, nblk, e0, yhat, flag);
+    k_t1_decode_wave<uint64_t><<<nblk, 64, 0, st>>>(F, blk, nblk, table, off);
 }
 
 }  // namespace ebcc

@@ -20,7 +20,7 @@ HDR_BYTES = 48
 
 SYMBOLS = ("ebcc_params_default", "ebcc_compress_bound", "ebcc_compress", "ebcc_decompress", "ebcc_stream_info",
            "ebcc_release", "ebcc_status_str", "ebcc_last_error", "ebcc_compress_trace", "ebcc_profile_enable",
-           "ebcc_profile_read", "ebcc_profile_stage_name")
+           "ebcc_profile_read", "ebcc_profile_stage_name", "ebcc_compress_batch", "ebcc_decompress_batch")
 
 
 class Params(C.Structure):
@@ -53,6 +53,8 @@ def lib():
         L.ebcc_compress.argtypes = [P, S, S, C.POINTER(Params), P, S, C.POINTER(S), P]
         L.ebcc_compress_trace.argtypes = [P, S, S, C.POINTER(Params), P, S, C.POINTER(S), P, P, P, P, P, P, P]
         L.ebcc_decompress.argtypes = [P, S, P, S, S, P]
+        L.ebcc_compress_batch.argtypes = [C.c_int, P, P, P, P, C.POINTER(Params), P, S, P, P, P]
+        L.ebcc_decompress_batch.argtypes = [C.c_int, P, P, P, P, P, P, P]
         L.ebcc_stream_info.argtypes = [P, S, C.POINTER(S), C.POINTER(S), C.POINTER(C.c_int)]
         L.ebcc_release.argtypes = []
         L.ebcc_release.restype = None
@@ -161,6 +163,84 @@ def decompress(stream_bytes, ny, nx, out=None, stream=None):
         out = torch.empty((ny, nx), dtype=torch.float32, device=stream_bytes.device)
     _check(decompress_into(stream_bytes, out, stream))
     return out
+
+
+def _arr(ctype, vals):
+    return (ctype * max(1, len(vals)))(*vals)
+
+
+class BatchArgs:
+    """Host argument arrays of a batched call, built once for a fixed set of
+    device tensors (so a serving loop or a timed loop marshals nothing)."""
+
+    def __init__(self, xs, outs=None, err_bounds=None):
+        self.n = len(xs)
+        self.xs = xs
+        self.d_x = _arr(C.c_void_p, [x.data_ptr() for x in xs])
+        self.ny = _arr(C.c_size_t, [x.shape[0] for x in xs])
+        self.nx = _arr(C.c_size_t, [x.shape[1] for x in xs])
+        self.err = None if err_bounds is None else _arr(C.c_double, [float(e) for e in err_bounds])
+        self.offsets = (C.c_uint64 * max(1, self.n))()
+        self.lengths = (C.c_uint64 * max(1, self.n))()
+        self.status = (C.c_int * max(1, self.n))()
+
+    def bound(self):
+        return sum(compress_bound(x.shape[0], x.shape[1]) for x in self.xs)
+
+
+def compress_batch_into(args, out, p, stream=None):
+    """Compress args.xs into `out` (uint8 device tensor); returns rc.  Offsets
+    and lengths are left in args.offsets / args.lengths."""
+    return lib().ebcc_compress_batch(args.n, args.d_x, args.ny, args.nx, args.err, C.byref(p),
+                                     C.c_void_p(out.data_ptr()), out.numel(), args.offsets, args.lengths,
+                                     _stream_ptr(stream))
+
+
+def compress_batch(xs, err_bounds=None, err_bound=0.01, base_ratio=30.0, stream=None, **kw):
+    """Compress a list of 2-D float32 CUDA tensors in one batched call;
+    returns a list of uint8 CUDA tensors (views of one buffer)."""
+    xs = [_dev_f32(x) for x in xs]
+    args = BatchArgs(xs, err_bounds=err_bounds)
+    p = params(err_bound, base_ratio, **kw)
+    dev = xs[0].device if xs else torch.device("cuda")
+    out = torch.empty(max(1, args.bound()), dtype=torch.uint8, device=dev)
+    _check(compress_batch_into(args, out, p, stream))
+    return [out[args.offsets[i]: args.offsets[i] + args.lengths[i]] for i in range(args.n)]
+
+
+class DecodeArgs:
+    """Host argument arrays of a batched decompression (streams -> outputs)."""
+
+    def __init__(self, streams, outs):
+        self.n = len(streams)
+        self.keep = (streams, outs)
+        self.d_in = _arr(C.c_void_p, [s.data_ptr() for s in streams])
+        self.in_len = _arr(C.c_size_t, [s.numel() for s in streams])
+        self.d_x = _arr(C.c_void_p, [o.data_ptr() for o in outs])
+        self.ny = _arr(C.c_size_t, [o.shape[0] for o in outs])
+        self.nx = _arr(C.c_size_t, [o.shape[1] for o in outs])
+        self.status = (C.c_int * max(1, self.n))()
+
+
+def decompress_batch_into(args, stream=None):
+    """Decompress; returns rc (per-stream statuses in args.status)."""
+    return lib().ebcc_decompress_batch(args.n, args.d_in, args.in_len, args.d_x, args.ny, args.nx, args.status,
+                                       _stream_ptr(stream))
+
+
+def decompress_batch(streams, shapes, stream=None, check=True):
+    """Decompress a list of uint8 CUDA tensors (one stream each) into float32
+    CUDA tensors of the given (ny, nx) shapes.  With check=False returns
+    (outputs, statuses) instead of raising on the first bad stream."""
+    streams = [s.contiguous() for s in streams]
+    dev = streams[0].device if streams else torch.device("cuda")
+    outs = [torch.empty(tuple(sh), dtype=torch.float32, device=dev) for sh in shapes]
+    args = DecodeArgs(streams, outs)
+    rc = decompress_batch_into(args, stream)
+    if check:
+        _check(rc)
+        return outs
+    return outs, [args.status[i] for i in range(args.n)]
 
 
 def stream_info(header_bytes):

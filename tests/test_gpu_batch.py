@@ -1,0 +1,190 @@
+"""Batched execution on the GPU: many fields of uneven sizes in one call.
+
+Every field's stream from ebcc_compress_batch must be byte-identical to the
+oracle's stream for that field alone (and so to the single-field GPU call),
+and ebcc_decompress_batch must decode each stream bit-identically to the
+oracle.  A stream that cannot be decoded is reported in its own status slot
+while the others of the batch still decode."""
+import numpy as np
+import pytest
+
+from paper_2510_22265_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_22265_amd import ebcc
+    ebcc.lib()
+    return ebcc
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _host(t):
+    return t.cpu().numpy()
+
+
+def _mixed_fields():
+    """Shapes from 1x1 to 181x360, three field kinds, a constant field, a
+    field whose bound is below FP32 resolution (raw), ragged sizes."""
+    fs = [
+        (synth.field("t", 91, 180, cfg=1), 0.01),
+        (np.full((37, 41), 273.15, np.float32), 0.01),
+        (synth.field("q", 181, 360, cfg=1, level=9), 0.003),
+        (synth.field("t", 20, 30), 1e-13),
+        (synth.field("u", 33, 17, cfg=1), 0.05),
+        (synth.field("v", 1, 1), 0.01),
+        (synth.field("v", 2, 2), 0.01),
+        (synth.field("u", 5, 64), 0.001),
+        (synth.field("v", 129, 255, cfg=3, level=2), 0.02),
+        (synth.field("q", 1, 7), 0.1),
+        (synth.field("t", 64, 64, cfg=5), 0.001),
+    ]
+    return [x for x, _ in fs], [e for _, e in fs]
+
+
+def _check_batch(gpu, ref, xs, eps, **kw):
+    streams = gpu.compress_batch([_dev(x) for x in xs], err_bounds=eps, **kw)
+    oracle_kw = {{"cblk_log2w": "cbl2w", "cblk_log2h": "cbl2h", "spiht_tile": "tile"}.get(k, k): v
+                 for k, v in kw.items()}
+    refs = []
+    for i, (x, e) in enumerate(zip(xs, eps)):
+        s_ref = ref.compress(x, e, **oracle_kw)
+        s_gpu = _host(streams[i]).tobytes()
+        assert s_gpu == s_ref, f"field {i} {x.shape}: stream differs from the oracle's"
+        refs.append(s_ref)
+    ys = gpu.decompress_batch([_dev(np.frombuffer(s, np.uint8).copy()) for s in refs], [x.shape for x in xs])
+    for i, (x, s) in enumerate(zip(xs, refs)):
+        y_ref = ref.decompress(s, *x.shape)
+        assert np.array_equal(_host(ys[i]).view(np.uint32), y_ref.view(np.uint32)), f"field {i}"
+    return refs
+
+
+def test_batch_mixed_matches_oracle(gpu, ref):
+    xs, eps = _mixed_fields()
+    _check_batch(gpu, ref, xs, eps)
+
+
+def test_batch_order_and_repeats(gpu, ref):
+    """The same field twice and in another order: identical streams."""
+    xs, eps = _mixed_fields()
+    order = [4, 2, 2, 0, 10, 7, 1, 3, 8, 6, 5, 9, 0]
+    _check_batch(gpu, ref, [xs[i] for i in order], [eps[i] for i in order])
+
+
+@pytest.mark.parametrize("kw", [dict(levels=2), dict(cblk_log2w=6, cblk_log2h=4), dict(spiht_tile=1),
+                                dict(base_ratio=4.0), dict(levels=0), dict(bound_mode=1)])
+def test_batch_parameters(gpu, ref, kw):
+    xs, eps = _mixed_fields()
+    if kw.get("bound_mode") == 1:
+        eps = [e * float(x.max() - x.min() + 1.0) for x, e in zip(xs, eps)]
+    _check_batch(gpu, ref, xs, eps, **kw)
+
+
+@pytest.mark.parametrize("t1", ["lane", "wave"])
+@pytest.mark.parametrize("spiht", ["global", "lds"])
+def test_batch_kernel_variants(gpu, ref, t1, spiht, monkeypatch):
+    monkeypatch.setenv("EBCC_T1_KERNEL", t1)
+    monkeypatch.setenv("EBCC_SPIHT_KERNEL", spiht)
+    xs, eps = _mixed_fields()
+    _check_batch(gpu, ref, xs, eps)
+
+
+def test_batch_uneven_mix_equals_solo(gpu):
+    """The uneven mix of grids from 91x180 to 721x1440 with log-uniform
+    bounds: batched streams equal the single-field calls' streams, and every
+    decoded point meets its bound."""
+    specs = synth.batch_specs(n=24)
+    xs = [synth.batch_field(s) for s in specs]
+    eps = [s[3] for s in specs]
+    dx = [_dev(x) for x in xs]
+    streams = gpu.compress_batch(dx, err_bounds=eps)
+    for i, x in enumerate(dx):
+        solo = _host(gpu.compress(x, eps[i])).tobytes()
+        assert _host(streams[i]).tobytes() == solo, f"field {i} {tuple(x.shape)}"
+    ys = gpu.decompress_batch(streams, [x.shape for x in xs])
+    for i, x in enumerate(xs):
+        y = _host(ys[i])
+        solo = _host(gpu.decompress(streams[i], *x.shape))
+        assert np.array_equal(y.view(np.uint32), solo.view(np.uint32))
+        rng_ = float(x.max()) - float(x.min())
+        assert np.abs(x.astype(np.float64) - y.astype(np.float64)).max() <= eps[i] * rng_
+
+
+def test_batch_chunking(gpu, ref):
+    """More fields than one chunk holds (4096): every stream still matches."""
+    g = np.random.default_rng(7)
+    xs = [g.standard_normal((3 + i % 5, 2 + i % 7)).astype(np.float32) for i in range(4100)]
+    eps = [0.01] * len(xs)
+    streams = gpu.compress_batch([_dev(x) for x in xs], err_bounds=eps)
+    for i in list(range(0, 4100, 97)) + [4095, 4096, 4099]:
+        assert _host(streams[i]).tobytes() == ref.compress(xs[i], 0.01), f"field {i}"
+    ys = gpu.decompress_batch(streams, [x.shape for x in xs])
+    for i in list(range(0, 4100, 97)) + [4095, 4096, 4099]:
+        y_ref = ref.decompress(_host(streams[i]).tobytes(), *xs[i].shape)
+        assert np.array_equal(_host(ys[i]).view(np.uint32), y_ref.view(np.uint32))
+
+
+def test_batch_bad_stream_isolated(gpu):
+    import torch
+    xs, eps = _mixed_fields()
+    streams = [s.clone() for s in gpu.compress_batch([_dev(x) for x in xs], err_bounds=eps)]
+    good = gpu.decompress_batch(streams, [x.shape for x in xs])
+    bad = [s.clone() for s in streams]
+    bad[2][60] ^= 0x10                       # payload bit flip: checksum
+    bad[4] = bad[4][:-1].clone()             # truncated
+    shapes = [x.shape for x in xs]
+    shapes[8] = (shapes[8][0], shapes[8][1] + 1)   # wrong size
+    outs, st = gpu.decompress_batch(bad, shapes, check=False)
+    assert st[2] == gpu.ECORRUPT and st[4] == gpu.ECORRUPT and st[8] == gpu.EINVAL
+    for i in range(len(xs)):
+        if i in (2, 4, 8):
+            continue
+        assert st[i] == gpu.OK
+        assert torch.equal(outs[i].view(torch.int32), good[i].view(torch.int32))
+
+
+def test_batch_mixed_code_block_sizes_decode(gpu):
+    """Streams with another code-block size than the first coded stream of a
+    decode batch are refused one by one; the rest decode."""
+    xs, eps = _mixed_fields()
+    a = gpu.compress(_dev(xs[0]), eps[0])
+    b = gpu.compress(_dev(xs[2]), eps[2], cblk_log2w=6, cblk_log2h=6)
+    c = gpu.compress(_dev(xs[8]), eps[8])
+    outs, st = gpu.decompress_batch([a, b, c], [xs[0].shape, xs[2].shape, xs[8].shape], check=False)
+    assert st == [gpu.OK, gpu.EINVAL, gpu.OK]
+    assert np.array_equal(_host(outs[0]), _host(gpu.decompress(a, *xs[0].shape)))
+    assert np.array_equal(_host(outs[2]), _host(gpu.decompress(c, *xs[8].shape)))
+
+
+def test_batch_errors(gpu):
+    import torch
+    xs, eps = _mixed_fields()
+    dx = [_dev(x) for x in xs]
+    dx[3] = dx[3].clone()
+    dx[3][1, 1] = float("inf")
+    with pytest.raises(gpu.EbccError) as e:
+        gpu.compress_batch(dx, err_bounds=eps)
+    assert e.value.code == gpu.EINVAL
+    args = gpu.BatchArgs([_dev(x) for x in xs], err_bounds=eps)
+    small = torch.empty(100, dtype=torch.uint8, device="cuda")
+    assert gpu.compress_batch_into(args, small, gpu.params()) == gpu.ENOSPC
+    assert gpu.compress_batch([]) == []
+    assert gpu.decompress_batch([], []) == []
+
+
+@pytest.mark.parametrize("cb", [(2, 2), (5, 5)])
+def test_batch_many_blocks(gpu, ref, cb):
+    """Enough code-blocks that the lanes-per-block tier-1 kernels run with
+    16 and 64 blocks per wavefront (4x4 blocks on three 721x1440 fields)."""
+    xs = [synth.field(v, 721, 1440, cfg=1, level=5) for v in ("t", "u", "q")]
+    eps = [0.01, 0.002, 0.05]
+    _check_batch(gpu, ref, xs, eps, cblk_log2w=cb[0], cblk_log2h=cb[1])
