@@ -4,7 +4,7 @@
 Headline workload (`value`): the ERA5-shaped stack, plain per-field path:
 148 float32 fields of 721x1440 (37 levels x {temperature-, u-, v-,
 humidity-like}), range-relative bound 1%, base ratio r = 30, 5 DWT levels,
-32x32 code-blocks, 2x2-root SPIHT tiles.  One step = compress every field,
+32x32 code-blocks, one-root SPIHT tiles.  One step = compress every field,
 then decompress every stream, one field per call on one stream.  value = fp32
 bytes of the stack / step time (GB/s, decimal): round-trip throughput.
 
@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--nx", type=int, default=1440)
     ap.add_argument("--eps", type=float, default=0.01)
     ap.add_argument("--ratio", type=float, default=30.0)
+    ap.add_argument("--tile", type=int, default=None, help="SPIHT tile side (default: the library's)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuned batched run")
     ap.add_argument("--batch-fields", type=int, default=256, help="fields of the uneven batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -107,7 +109,9 @@ def main():
     fields_h = generate(stack_specs + [("batch", s) for s in bspecs])
     stack_h, batch_h = fields_h[: len(stack_specs)], fields_h[len(stack_specs):]
     xs = [torch.from_numpy(f).to(dev) for f in stack_h]
-    p = ebcc.params(args.eps, args.ratio)
+    fmt = {} if args.tile is None else {"spiht_tile": args.tile}
+    p = ebcc.params(args.eps, args.ratio, **fmt)
+    tile = p.spiht_tile
     cap = ebcc.compress_bound(args.ny, args.nx)
     outs = [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in xs]
     recs = [torch.empty((args.ny, args.nx), dtype=torch.float32, device=dev) for _ in xs]
@@ -223,7 +227,7 @@ def main():
         bviol, bmax = verify(batch_h, brecs, beps)
         bsbytes = sum(bargs.lengths[i] for i in range(bargs.n))
         # the same fields and bounds through the per-field loop (one step)
-        bplist = [ebcc.params(e, args.ratio) for e in beps]
+        bplist = [ebcc.params(e, args.ratio, **fmt) for e in beps]
         bouts = [torch.empty(ebcc.compress_bound(*f.shape), dtype=torch.uint8, device=dev) for f in batch_h]
         blens = [0] * len(bx)
         per_field_step(bx, bouts, brecs, blens, bplist)
@@ -255,6 +259,42 @@ def main():
         c = time.perf_counter()
         sviol, _ = verify(stack_h, recs, [args.eps] * len(xs))
         stack_same = all(torch.equal(sstreams[i], outs[i][: lens[i]]) for i in range(len(xs)))
+        # autotuned batched run: format and kernel choices measured on the batch
+        tuned = None
+        if not args.no_tune:
+            from paper_2510_22265_amd import autotune
+            t0 = time.perf_counter()
+            res = autotune.tune(bx, beps, base_ratio=args.ratio, stream=stream)
+            t_tune = time.perf_counter() - t0
+            old = ebcc.set_tuning(**res["tuning"])
+            tp = ebcc.params(args.eps, args.ratio, **res["params"])
+            targs = ebcc.BatchArgs(bx, err_bounds=beps)
+            tout = torch.empty(targs.bound(), dtype=torch.uint8, device=dev)
+            assert ebcc.compress_batch_into(targs, tout, tp, stream) == 0
+            tstreams = [tout[targs.offsets[i]: targs.offsets[i] + targs.lengths[i]] for i in range(targs.n)]
+            tdargs = ebcc.DecodeArgs(tstreams, brecs)
+            assert ebcc.decompress_batch_into(tdargs, stream) == 0
+            torch.cuda.synchronize()
+            tc_ = td_ = 0.0
+            for s in range(steps):
+                a = time.perf_counter()
+                assert ebcc.compress_batch_into(targs, tout, tp, stream) == 0
+                torch.cuda.synchronize()
+                b = time.perf_counter()
+                assert ebcc.decompress_batch_into(tdargs, stream) == 0
+                torch.cuda.synchronize()
+                c = time.perf_counter()
+                tc_ += b - a
+                td_ += c - b
+                log(f"tuned batched step {s}: compress {(b - a) * 1e3:.1f} ms, decompress {(c - b) * 1e3:.1f} ms")
+            tviol, _ = verify(batch_h, brecs, beps)
+            ebcc.set_tuning(**old)
+            tsb = sum(targs.lengths[i] for i in range(targs.n))
+            tuned = {"params": res["params"], "tuning": res["tuning"], "tune_seconds": t_tune,
+                     "candidates": len(res["table"]),
+                     "GBps": bbytes * steps / (tc_ + td_) / 1e9, "compress_GBps": bbytes * steps / tc_ / 1e9,
+                     "decompress_GBps": bbytes * steps / td_ / 1e9, "CR": bbytes / tsb, "violations": tviol,
+                     "speedup_vs_per_field": (pc + pd) / ((tc_ + td_) / steps)}
         batched = {
             "workload": f"uneven batch: {len(bx)} fields from {{91x180, 181x360, 361x720, 721x1440}}, "
                         f"eps_rel log-uniform [1e-3, 1e-1], r {args.ratio}",
@@ -273,6 +313,7 @@ def main():
             "stack_decompress_GBps": nbytes * steps / (c - b) / 1e9,
             "stack_speedup_vs_per_field": (t_total / steps) / ((c - a) / steps),
             "stack_streams_identical": bool(stack_same), "stack_violations": sviol,
+            "tuned": tuned,
         }
 
     # ---------------- CPU oracle baseline ----------------
@@ -299,7 +340,8 @@ def main():
         "ms_per_step": t_total / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"ERA5-shaped stack, plain per-field path: {len(xs)} fields {args.ny}x{args.nx} "
-                               f"(37 levels x t,u,v,q), eps_rel {args.eps}, r {args.ratio}, L 5, 32x32 blocks",
+                               f"(37 levels x t,u,v,q), eps_rel {args.eps}, r {args.ratio}, L 5, 32x32 blocks, "
+                               f"{tile}x{tile}-root SPIHT tiles",
                    "fields": len(xs), "ny": args.ny, "nx": args.nx, "eps_rel": args.eps, "base_ratio": args.ratio},
         "compress_GBps": nbytes * steps / tc / 1e9, "decompress_GBps": nbytes * steps / td / 1e9,
         "CR": nbytes / stream_bytes, "violations": viol, "max_err_rel": max_rel,

@@ -63,11 +63,11 @@ typedef struct {
   uint32_t levels;        /* DWT levels (default 5), clamped to floor(log2(min(ny, nx))) */
   uint32_t cblk_log2w;    /* code-block width  = 2^cblk_log2w, 2..6 (default 5) */
   uint32_t cblk_log2h;    /* code-block height = 2^cblk_log2h, 2..6 (default 5); w*h <= 4096 */
-  uint32_t spiht_tile;    /* SPIHT tile side in coarsest-LL roots, 1..64 (default 2) */
+  uint32_t spiht_tile;    /* SPIHT tile side in coarsest-LL roots, 1..64 (default 1) */
 } ebcc_params;
 
 /* Fill p with the defaults: range-relative 1% bound, r = 30, 5 levels,
- * 32x32 code-blocks, 2x2-root SPIHT tiles, q = 0. */
+ * 32x32 code-blocks, one-root SPIHT tiles, q = 0. */
 void ebcc_params_default(ebcc_params* p);
 
 /* Largest stream ebcc_compress can produce for an ny x nx field (a coded
@@ -175,6 +175,32 @@ int ebcc_compress_trace(const float* d_x, size_t ny, size_t nx, const ebcc_param
 void ebcc_profile_enable(int on);
 int ebcc_profile_read(double* ms, long* calls, int n);
 const char* ebcc_profile_stage_name(int i);
+
+/* ---------------------------------------------------------------------------
+ * Kernel tuning (process-wide).  These choices never change a stream: every
+ * kernel variant produces the same bytes; they only trade latency for
+ * throughput.  The autotuner of the Python package measures them (with the
+ * code-block size and SPIHT tile, which do change the stream) on a sample of
+ * the caller's fields.
+ *   t1_encoder, t1_decoder  0 = by work size, 1 = one wavefront per
+ *                           code-block (latency), 2 = several code-blocks per
+ *                           wavefront, one per lane (throughput)
+ *   t1_wave_max             by work size: the encoder keeps one wavefront per
+ *                           code-block up to this many code-blocks per call
+ *   spiht                   0 = SPIHT tiles in LDS (by capacity class, the
+ *                           largest tiles with global-memory lists), 1 =
+ *                           global-memory lists for every tile
+ * ebcc_tuning_set returns EBCC_EINVAL for out-of-range values.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  uint32_t struct_size;   /* sizeof(ebcc_tuning) */
+  int32_t t1_encoder;
+  int32_t t1_decoder;
+  int32_t t1_wave_max;
+  int32_t spiht;
+} ebcc_tuning;
+int ebcc_tuning_get(ebcc_tuning* t);
+int ebcc_tuning_set(const ebcc_tuning* t);
 
 #ifdef __cplusplus
 }

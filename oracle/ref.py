@@ -97,7 +97,7 @@ def n_blocks(ny, nx, levels=5, cbl2w=5, cbl2h=5):
     return n
 
 
-def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=2, trace=False):
+def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, trace=False):
     """Compress a 2-D float32 field.  Returns bytes (and a dict of
     intermediate results when ``trace`` is true)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
@@ -129,7 +129,7 @@ def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl
     return s
 
 
-def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=2, cap=None):
+def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, cap=None):
     """Raw status-code form for error-path tests: returns (rc, bytes or None, out_len)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     ny, nx = x.shape if x.ndim == 2 else (x.size, 1)

@@ -451,12 +451,16 @@ struct Plan {
   int64_t* d_slot_off = nullptr;
   int nblk = 0, ntiles = 0, nb = 0;
   int max_tile_coef = 0, max_tile_parents = 0;
-  int spiht_cap = 0;   // LDS capacity class of the per-tile SPIHT kernels (0: global-memory kernels)
+  // tile indices grouped by SPIHT kernel class: LDS small, LDS big, global
+  std::vector<int> tix;
+  int ncls[3] = {0, 0, 0};
+  int* d_tix = nullptr;
   ~Plan() {
     if (d_bands) (void)hipFree(d_bands);
     if (d_blks) (void)hipFree(d_blks);
     if (d_tiles) (void)hipFree(d_tiles);
     if (d_slot_off) (void)hipFree(d_slot_off);
+    if (d_tix) (void)hipFree(d_tix);
   }
 };
 
@@ -490,6 +494,7 @@ static int build_plan(Plan& p) {
   // SPIHT tiles: T x T LL roots and the rectangles their trees cover per band
   int hL = h[L], wL = w[L], T = p.T;
   int ty = (hL + T - 1) / T, tx = (wL + T - 1) / T;
+  std::vector<int> tcls;
   int64_t off = 0, soff = 0;
   p.slot_off.push_back(0);
   for (int a = 0; a < ty; a++)
@@ -516,6 +521,8 @@ static int build_plan(Plan& p) {
       t.ncoef = (int)n;
       p.max_tile_coef = std::max(p.max_tile_coef, (int)n);
       p.max_tile_parents = std::max(p.max_tile_parents, (int)(L > 0 ? n - n1 : 0));
+      int64_t need = std::max<int64_t>(n, 2 * (L > 0 ? n - n1 : 0));
+      tcls.push_back(need <= kSpihtSmall ? 0 : (need <= kSpihtBig ? 1 : 2));
       t.field = 0;
       off += n;
       soff += 12 * n + 16;
@@ -523,7 +530,9 @@ static int build_plan(Plan& p) {
       p.slot_off.push_back(soff);
     }
   p.ntiles = (int)p.tiles.size();
-  p.spiht_cap = spiht_lds_cap(std::max(p.max_tile_coef, 2 * p.max_tile_parents));
+  for (int k = 0; k < 3; k++)
+    for (int t = 0; t < p.ntiles; t++)
+      if (tcls[t] == k) { p.tix.push_back(t); p.ncls[k]++; }
   if (off != (int64_t)ny * nx) return fail(EBCC_EINVAL, "internal: SPIHT trees do not cover the field");
   HIPCHK(hipMalloc(&p.d_bands, sizeof(Band) * p.bands.size()));
   HIPCHK(hipMemcpy(p.d_bands, p.bands.data(), sizeof(Band) * p.bands.size(), hipMemcpyHostToDevice));
@@ -531,17 +540,28 @@ static int build_plan(Plan& p) {
   if (p.nblk) HIPCHK(hipMemcpy(p.d_blks, p.blks.data(), sizeof(Blk) * p.blks.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&p.d_tiles, sizeof(TileD) * p.tiles.size()));
   HIPCHK(hipMemcpy(p.d_tiles, p.tiles.data(), sizeof(TileD) * p.tiles.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&p.d_tix, sizeof(int) * p.tix.size()));
+  HIPCHK(hipMemcpy(p.d_tix, p.tix.data(), sizeof(int) * p.tix.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&p.d_slot_off, sizeof(int64_t) * p.slot_off.size()));
   HIPCHK(hipMemcpy(p.d_slot_off, p.slot_off.data(), sizeof(int64_t) * p.slot_off.size(), hipMemcpyHostToDevice));
   return EBCC_OK;
 }
 
-// SPIHT kernel family for a plan: LDS per tile when the tiles fit (the
-// environment variable EBCC_SPIHT_KERNEL=global forces the global-memory
-// kernels, for testing both families).
-static int spiht_cap_for(const Plan* p) {
+// SPIHT kernels: tiles that fit run with the tile in LDS, the others with
+// global-memory lists; the environment variable EBCC_SPIHT_KERNEL=global
+// sends every tile to the global-memory kernels (to test both families).
+static std::mutex g_tune_mu;
+static Tuning g_tuning = {0, 0, 32768, 0};
+
+Tuning tuning() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tuning;
+}
+
+static bool spiht_forced_global() {
   const char* e = getenv("EBCC_SPIHT_KERNEL");
-  return (e && e[0] == 'g') ? 0 : p->spiht_cap;
+  if (e && e[0]) return e[0] == 'g';
+  return tuning().spiht == 1;
 }
 
 static std::mutex g_mu;
@@ -579,11 +599,18 @@ struct WS {
   size_t pin_cap = 0;
   hipEvent_t ev = nullptr;
   bool ev_live = false;
+  // second stream for independent launches of one call (SPIHT tile
+  // classes), ordered against the caller's stream with two events
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~WS() {
     if (ev_live) (void)hipEventSynchronize(ev);
     if (base) (void)hipFree(base);
     if (pin) (void)hipHostFree(pin);
     if (ev) (void)hipEventDestroy(ev);
+    if (aux) (void)hipStreamDestroy(aux);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
   }
 };
 typedef std::pair<int, hipStream_t> WSKey;
@@ -608,6 +635,9 @@ static int get_ws(hipStream_t st, WS** out) {
   if (!w) {
     w.reset(new WS());
     HIPCHK(hipEventCreateWithFlags(&w->ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking));
   }
   // the previous call's staged copies must have left the pinned buffer
   if (w->ev_live) HIPCHK(hipEventSynchronize(w->ev));
@@ -643,10 +673,6 @@ static int grow_ws(WS* w, size_t need, size_t pin_need, hipStream_t st, char** b
   *base = (char*)w->base;
   return EBCC_OK;
 }
-
-// LDS capacity class shared by the tiles of a call: the largest class, or
-// 0 (global-memory kernels) as soon as one field's tiles do not fit.
-static int merge_cap(int a, int b) { return (a == 0 || b == 0) ? 0 : std::max(a, b); }
 
 // Batches are processed in chunks of at most this many samples or fields.
 constexpr size_t kChunkSamples = size_t(1) << 26;
@@ -696,8 +722,10 @@ struct Call {
   const Blk* d_blk = nullptr;
   const TileD* d_tiles = nullptr;
   const int64_t* d_slot_off = nullptr;
-  bool need_lists = false;
-  int spiht_cap = 0, cbw = 32, cbh = 32;
+  bool need_lists = false, forced_global = false;
+  int cbw = 32, cbh = 32;
+  const int* d_tix = nullptr;   // tile indices by class (see Plan::tix)
+  int ncls[3] = {0, 0, 0};
   // per-item arrays
   void *planes, *signs, *sppf;
   uint8_t *pb, *kb, *hk, *nh, *cw, *slots;
@@ -709,6 +737,7 @@ struct Call {
   Blk* d_blk_own;
   TileD* d_tiles_own;
   int64_t* d_slot_own;
+  int* d_tix_own;
 
   ~Call() {
     if (ws && hipEventRecord(ws->ev, st) == hipSuccess) ws->ev_live = true;
@@ -734,6 +763,18 @@ struct Call {
     return EBCC_OK;
   }
   int upload() { return stage(F, Fh.data(), sizeof(FieldDev) * nf); }   // field table host -> device
+  // Work launched on ws->aux between fork() and join() runs concurrently with
+  // the caller's stream and is complete, for that stream, after join().
+  int fork() {
+    HIPCHK(hipEventRecord(ws->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(ws->aux, ws->ev_fork, 0));
+    return EBCC_OK;
+  }
+  int join() {
+    HIPCHK(hipEventRecord(ws->ev_join, ws->aux));
+    HIPCHK(hipStreamWaitEvent(st, ws->ev_join, 0));
+    return EBCC_OK;
+  }
   int set_active(const std::vector<int>& act) {
     for (int i = 0; i < nf; i++) Fh[i].active = act[i];
     return upload();
@@ -788,6 +829,7 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
   c.d_blk_own = cv.take<Blk>(nb);
   c.d_tiles_own = cv.take<TileD>(nt);
   c.d_slot_own = cv.take<int64_t>(nt + 1);
+  c.d_tix_own = cv.take<int>(nt);
   int64_t lists = 0, slots = 0;
   for (int i = 0; i < c.nf; i++)
     if (coded[i]) { lists += (int64_t)c.Fh[i].ny * c.Fh[i].nx; slots += c.plans[i]->slot_off.back(); }
@@ -803,6 +845,7 @@ static size_t pin_need(const Call& c) {
   m = std::max(m, sizeof(Blk) * (size_t)c.nblk);
   m = std::max(m, sizeof(TileD) * (size_t)c.ntiles);
   m = std::max(m, sizeof(int64_t) * ((size_t)c.ntiles + 1));
+  m = std::max(m, sizeof(int) * (size_t)c.ntiles);
   m = std::max(m, 2 * sizeof(float) * (size_t)c.nf);
   return 2 * m + 4096;
 }
@@ -831,6 +874,8 @@ static int upload_items(Call& c, const std::vector<int>& coded) {
     c.d_blk = c.plans[0]->d_blks;
     c.d_tiles = c.plans[0]->d_tiles;
     c.d_slot_off = c.plans[0]->d_slot_off;
+    c.d_tix = c.plans[0]->d_tix;
+    for (int k = 0; k < 3; k++) c.ncls[k] = c.plans[0]->ncls[k];
     return EBCC_OK;
   }
   std::vector<Blk> blks;
@@ -854,7 +899,21 @@ static int upload_items(Call& c, const std::vector<int>& coded) {
     lo += (int64_t)p->ny * p->nx;
     so += p->slot_off.back();
   }
+  std::vector<int> tix;
+  tix.reserve(c.ntiles);
+  for (int k = 0; k < 3; k++) {
+    c.ncls[k] = 0;
+    for (int i : ci) {
+      const Plan* p = c.plans[i];
+      int base = c.Fh[i].tile0, o = 0;
+      for (int q = 0; q < k; q++) o += p->ncls[q];
+      for (int q = 0; q < p->ncls[k]; q++) tix.push_back(base + p->tix[o + q]);
+      c.ncls[k] += p->ncls[k];
+    }
+  }
   int rc;
+  if ((rc = c.stage(c.d_tix_own, tix.data(), sizeof(int) * tix.size()))) return rc;
+  c.d_tix = c.d_tix_own;
   if ((rc = c.stage(c.d_blk_own, blks.data(), sizeof(Blk) * blks.size()))) return rc;
   if ((rc = c.stage(c.d_tiles_own, tiles.data(), sizeof(TileD) * tiles.size()))) return rc;
   if ((rc = c.stage(c.d_slot_own, soff.data(), sizeof(int64_t) * soff.size()))) return rc;
@@ -911,9 +970,9 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   // every field is laid out as coded (the mode is known only on the device)
   std::vector<int> coded(nf, 1);
   build_items(c, coded);
-  c.spiht_cap = 1;
-  for (int i = 0; i < nf; i++) c.spiht_cap = merge_cap(c.spiht_cap, spiht_cap_for(c.plans[i]));
-  c.need_lists = c.spiht_cap == 0;
+  c.forced_global = spiht_forced_global();
+  c.need_lists = c.forced_global;
+  for (int i = 0; i < nf; i++) c.need_lists |= c.plans[i]->ncls[2] > 0;
   size_t need_ws = layout_call(c, nullptr, coded);
   char* base;
   if ((rc = get_ws(st, &c.ws))) return rc;
@@ -1047,10 +1106,18 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     if (anysp) {
       if ((rc = c.set_active(sp))) return rc;
       spiht_maxima(c.F, c.Fh.data(), nf, st);
-      if (c.spiht_cap)
-        spiht_encode_lds(c.spiht_cap, c.F, c.d_tiles, c.ntiles, c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, st);
-      else
-        spiht_encode(c.F, c.d_tiles, c.ntiles, c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, st);
+      if (c.forced_global) {
+        spiht_encode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, st);
+      } else {
+        // the classes run concurrently: big and global tiles on the second stream
+        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1];
+        hipStream_t sa = c.ws->aux;
+        if ((rc = c.fork())) return rc;
+        spiht_encode(c.F, c.d_tiles, t2, c.ncls[2], c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, sa);
+        spiht_encode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, sa);
+        spiht_encode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, st);
+        if ((rc = c.join())) return rc;
+      }
       k_scan<<<nf, 1024, 0, st>>>(c.F, c.tlen, 1, 0, 0xFFFFFFFFu, c.toff);
     }
     prof.mark(S_SPIHT);
@@ -1213,12 +1280,10 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
   }
   if (cbl2w >= 0) { c.cbw = 1 << cbl2w; c.cbh = 1 << cbl2h; }
   build_items(c, coded);
-  c.spiht_cap = 1;
   bool anycoded = false;
+  c.forced_global = spiht_forced_global();
   for (int i = 0; i < nf; i++)
-    if (coded[i]) { anycoded = true; c.spiht_cap = merge_cap(c.spiht_cap, spiht_cap_for(c.plans[i])); }
-  if (!anycoded) c.spiht_cap = 0;
-  c.need_lists = anycoded && c.spiht_cap == 0;
+    if (coded[i]) { anycoded = true; c.need_lists |= c.forced_global || c.plans[i]->ncls[2] > 0; }
   size_t need_ws = layout_call(c, nullptr, coded);
   char* base;
   if ((rc = get_ws(st, &c.ws))) return rc;
@@ -1272,8 +1337,17 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
     if (anyres) {
       if ((rc = c.set_active(cr))) return rc;
       k_fill<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, BUF_CHAT, 0.0f);
-      if (c.spiht_cap) spiht_decode_lds(c.spiht_cap, c.F, c.d_tiles, c.ntiles, c.toff, c.misfit, st);
-      else spiht_decode(c.F, c.d_tiles, c.ntiles, c.toff, c.lists, st);
+      if (c.forced_global) {
+        spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, st);
+      } else {
+        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1];
+        hipStream_t sa = c.ws->aux;
+        if ((rc = c.fork())) return rc;
+        spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sa);
+        spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sa);
+        spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, st);
+        if ((rc = c.join())) return rc;
+      }
       prof.mark(S_D_SPIHT);
       dwt_inverse(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, EPI_FINAL, st);
     }
@@ -1313,7 +1387,7 @@ void ebcc_params_default(ebcc_params* p) {
   p->levels = 5;
   p->cblk_log2w = 5;
   p->cblk_log2h = 5;
-  p->spiht_tile = 2;
+  p->spiht_tile = 1;
 }
 
 size_t ebcc_compress_bound(size_t ny, size_t nx) { return (size_t)kHdr + 4 * ny * nx; }
@@ -1461,6 +1535,27 @@ int ebcc_profile_read(double* ms, long* calls, int n) {
     if (calls) calls[i] = g_stage_calls[i];
   }
   return S_COUNT;
+}
+
+int ebcc_tuning_get(ebcc_tuning* t) {
+  if (!t) return fail(EBCC_EINVAL, "NULL tuning");
+  Tuning v = tuning();
+  t->struct_size = sizeof(ebcc_tuning);
+  t->t1_encoder = v.t1_encoder;
+  t->t1_decoder = v.t1_decoder;
+  t->t1_wave_max = v.t1_wave_max;
+  t->spiht = v.spiht;
+  return EBCC_OK;
+}
+
+int ebcc_tuning_set(const ebcc_tuning* t) {
+  if (!t || t->struct_size != sizeof(ebcc_tuning)) return fail(EBCC_EINVAL, "bad ebcc_tuning");
+  if (t->t1_encoder < 0 || t->t1_encoder > 2 || t->t1_decoder < 0 || t->t1_decoder > 2 || t->t1_wave_max < 0 ||
+      t->spiht < 0 || t->spiht > 1)
+    return fail(EBCC_EINVAL, "tuning value out of range");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuning = Tuning{t->t1_encoder, t->t1_decoder, t->t1_wave_max, t->spiht};
+  return EBCC_OK;
 }
 
 const char* ebcc_profile_stage_name(int i) { return (i >= 0 && i < S_COUNT) ? kStageNames[i] : ""; }

@@ -122,8 +122,15 @@ void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
                     uint32_t* tail, void* sppf, hipStream_t st);
 void t1_decode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, const uint32_t* table,
                     const int64_t* off, hipStream_t st);
-// Tier-1 kernel choice: 0 = by work size, 1 = wave per block, 2 = lane per block.
-int t1_variant();
+// Kernel choices (process-wide, set through the C ABI; the environment
+// variables EBCC_T1_KERNEL=wave|lane and EBCC_SPIHT_KERNEL=global override).
+struct Tuning {
+  int t1_encoder;    // 0 by work size, 1 wave per code-block, 2 lanes per code-block
+  int t1_decoder;    // same
+  int t1_wave_max;   // by work size: the encoder uses a wave per block up to this many blocks
+  int spiht;         // 0 LDS kernels by capacity class, 1 global-memory lists for every tile
+};
+Tuning tuning();
 
 // pcrd.hip: one workgroup per field; kb/len per block.
 void pcrd(const FieldDev* F, int nf, const uint8_t* pb, const int32_t* R, const int64_t* D, uint8_t* kb,
@@ -136,19 +143,22 @@ void spiht_maxima(const FieldDev* F, const FieldDev* Fh, int nf, hipStream_t st)
 // Encode every tile for planes n_t .. F.ns into its slot of `slots`
 // (slot_off[t] ..); tlen[t] receives the byte length and tent[t] the tile
 // table entry.
-void spiht_encode(const FieldDev* F, const TileD* tiles, int ntiles, uint64_t* lists, uint8_t* slots,
+void spiht_encode(const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint64_t* lists, uint8_t* slots,
                   const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st);
 // Decode residual sections (each field's starts at out + 48 + bb): writes the
 // dequantised significant coefficients into buf[BUF_CHAT] (zero elsewhere);
 // toff: payload offsets after each field's tile table.
-void spiht_decode(const FieldDev* F, const TileD* tiles, int ntiles, const int64_t* toff, uint64_t* lists,
-                  hipStream_t st);
-// spihtwave.hip: one wavefront per tile with the tile in LDS.  spiht_lds_cap
-// gives the LDS capacity class for the largest tile (0 = does not fit).
-int spiht_lds_cap(int max_tile_coef);
-void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, int ntiles, uint8_t* slots,
+void spiht_decode(const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
+                  uint64_t* lists, hipStream_t st);
+// spihtwave.hip: one wavefront per tile with the tile in LDS, in two capacity
+// classes (coefficients of the tile's trees, and twice its parents, must fit).
+constexpr int kSpihtSmall = 1280;
+constexpr int kSpihtBig = 4608;
+// Each SPIHT launch covers the tiles tix[0 .. ntix) of the call's tile array
+// (tiles are launched in capacity classes).
+void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint8_t* slots,
                       const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit, hipStream_t st);
-void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, int ntiles, const int64_t* toff, int* misfit,
-                      hipStream_t st);
+void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
+                      int* misfit, hipStream_t st);
 
 }  // namespace ebcc

@@ -164,12 +164,14 @@ struct BitW {
 
 template <int LANES>
 __global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
-                                                        int ntiles, uint64_t* __restrict__ lists,
+                                                        const int* __restrict__ tix, int ntix,
+                                                        uint64_t* __restrict__ lists,
                                                         uint8_t* __restrict__ slots,
                                                         const int64_t* __restrict__ slot_off,
                                                         uint32_t* __restrict__ tlen, uint32_t* __restrict__ tent) {
-  int t = blockIdx.x * LANES + threadIdx.x;
-  if (t >= ntiles) return;
+  const int q = blockIdx.x * LANES + threadIdx.x;
+  if (q >= ntix) return;
+  const int t = tix[q];
   TileD td = tiles[t];
   const FieldDev& f = F[td.field];
   if (!f.active) return;
@@ -254,12 +256,12 @@ __global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restri
   tent[t] = (uint32_t)w.pos | ((uint32_t)(ntop + 1) << 26);
 }
 
-void spiht_encode(const FieldDev* F, const TileD* tiles, int ntiles, uint64_t* lists, uint8_t* slots,
+void spiht_encode(const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint64_t* lists, uint8_t* slots,
                   const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st) {
-  if (ntiles <= 0) return;
-  int ln = pick_tile_lanes(ntiles);
-#define ENC_L(LN) k_spiht_encode<LN><<<(ntiles + LN - 1) / LN, LN, 0, st>>>(F, tiles, ntiles, lists, slots, slot_off, \
-                                                                        tlen, tent)
+  if (ntix <= 0) return;
+  int ln = pick_tile_lanes(ntix);
+#define ENC_L(LN) k_spiht_encode<LN><<<(ntix + LN - 1) / LN, LN, 0, st>>>(F, tiles, tix, ntix, lists, slots, slot_off, \
+                                                                      tlen, tent)
   if (ln == 1) ENC_L(1); else if (ln == 4) ENC_L(4); else if (ln == 16) ENC_L(16); else ENC_L(64);
 #undef ENC_L
 }
@@ -279,10 +281,12 @@ struct BitR {
 // t's payload after the table.  mags: N-sized scratch (magnitude | sign << 31).
 template <int LANES>
 __global__ __launch_bounds__(LANES) void k_spiht_decode(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
-                                                        int ntiles, const int64_t* __restrict__ toff,
+                                                        const int* __restrict__ tix, int ntix,
+                                                        const int64_t* __restrict__ toff,
                                                         uint64_t* __restrict__ lists) {
-  int t = blockIdx.x * LANES + threadIdx.x;
-  if (t >= ntiles) return;
+  const int q = blockIdx.x * LANES + threadIdx.x;
+  if (q >= ntix) return;
+  const int t = tix[q];
   TileD td = tiles[t];
   const FieldDev& f = F[td.field];
   if (!f.active) return;
@@ -366,11 +370,11 @@ __global__ __launch_bounds__(LANES) void k_spiht_decode(const FieldDev* __restri
   }
 }
 
-void spiht_decode(const FieldDev* F, const TileD* tiles, int ntiles, const int64_t* toff, uint64_t* lists,
-                  hipStream_t st) {
-  if (ntiles <= 0) return;
-  int ln = pick_tile_lanes(ntiles);
-#define DEC_L(LN) k_spiht_decode<LN><<<(ntiles + LN - 1) / LN, LN, 0, st>>>(F, tiles, ntiles, toff, lists)
+void spiht_decode(const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
+                  uint64_t* lists, hipStream_t st) {
+  if (ntix <= 0) return;
+  int ln = pick_tile_lanes(ntix);
+#define DEC_L(LN) k_spiht_decode<LN><<<(ntix + LN - 1) / LN, LN, 0, st>>>(F, tiles, tix, ntix, toff, lists)
   if (ln == 1) DEC_L(1); else if (ln == 4) DEC_L(4); else if (ln == 16) DEC_L(16); else DEC_L(64);
 #undef DEC_L
 }

@@ -21,8 +21,6 @@
 
 namespace ebcc {
 
-constexpr int kSpihtBig = 4608;     // coefficients per tile the LDS kernels accept
-constexpr int kSpihtSmall = 1280;
 
 struct TileGeom {
   int r0[kMaxBands], c0[kMaxBands], hr[kMaxBands], wr[kMaxBands], off[kMaxBands + 1];
@@ -144,13 +142,13 @@ __device__ bool spiht_setup(SpihtLds<CAP>& S, const Band* bands_g, int nb, int L
 
 template <int CAP>
 __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
-                                                         int ntiles, uint8_t* __restrict__ slots,
+                                                         const int* __restrict__ tix, uint8_t* __restrict__ slots,
                                                          const int64_t* __restrict__ slot_off,
                                                          uint32_t* __restrict__ tlen, uint32_t* __restrict__ tent,
                                                          int* __restrict__ misfit) {
   __shared__ SpihtLds<CAP> S;
   const int lane = threadIdx.x;
-  const int t = blockIdx.x;
+  const int t = tix[blockIdx.x];
   const TileD td = tiles[t];
   const FieldDev& f = F[td.field];
   if (!f.active) return;
@@ -391,11 +389,11 @@ struct BitRU {
 
 template <int CAP>
 __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
-                                                         int ntiles, const int64_t* __restrict__ toff,
+                                                         const int* __restrict__ tix, const int64_t* __restrict__ toff,
                                                          int* __restrict__ misfit) {
   __shared__ SpihtLds<CAP> S;
   const int lane = threadIdx.x;
-  const int t = blockIdx.x;
+  const int t = tix[blockIdx.x];
   const TileD td = tiles[t];
   const FieldDev& f = F[td.field];
   if (!f.active) return;
@@ -541,28 +539,22 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
   }
 }
 
-int spiht_lds_cap(int max_tile_coef) {
-  if (max_tile_coef <= kSpihtSmall) return kSpihtSmall;
-  if (max_tile_coef <= kSpihtBig) return kSpihtBig;
-  return 0;
-}
-
-void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, int ntiles, uint8_t* slots,
+void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint8_t* slots,
                       const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit, hipStream_t st) {
-  if (ntiles <= 0) return;
+  if (ntix <= 0) return;
   if (cap == kSpihtSmall)
-    k_spiht_encode_lds<kSpihtSmall><<<ntiles, 64, 0, st>>>(F, tiles, ntiles, slots, slot_off, tlen, tent, misfit);
+    k_spiht_encode_lds<kSpihtSmall><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, misfit);
   else
-    k_spiht_encode_lds<kSpihtBig><<<ntiles, 64, 0, st>>>(F, tiles, ntiles, slots, slot_off, tlen, tent, misfit);
+    k_spiht_encode_lds<kSpihtBig><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, misfit);
 }
 
-void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, int ntiles, const int64_t* toff, int* misfit,
-                      hipStream_t st) {
-  if (ntiles <= 0) return;
+void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
+                      int* misfit, hipStream_t st) {
+  if (ntix <= 0) return;
   if (cap == kSpihtSmall)
-    k_spiht_decode_lds<kSpihtSmall><<<ntiles, 64, 0, st>>>(F, tiles, ntiles, toff, misfit);
+    k_spiht_decode_lds<kSpihtSmall><<<ntix, 64, 0, st>>>(F, tiles, tix, toff, misfit);
   else
-    k_spiht_decode_lds<kSpihtBig><<<ntiles, 64, 0, st>>>(F, tiles, ntiles, toff, misfit);
+    k_spiht_decode_lds<kSpihtBig><<<ntix, 64, 0, st>>>(F, tiles, tix, toff, misfit);
 }
 
 }  // namespace ebcc

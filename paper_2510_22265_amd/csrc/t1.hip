@@ -708,24 +708,23 @@ void quant_planes(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh,
     k_quant_planes<uint64_t><<<g, 256, 0, st>>>(F, blk, nblk, cbw, cbh, (uint64_t*)planes, (uint64_t*)signs, pb);
 }
 
-// Up to this many blocks in flight the wave-per-block coder is used (latency);
-// beyond it, lanes per block (throughput).
-constexpr int kWaveBlocksMax = 32768;
-
-int t1_variant() {
+// By work size: the encoder uses a wave per block up to Tuning::t1_wave_max
+// blocks (latency) and lanes per block beyond (throughput); the
+// wave-per-block decoder was the faster one at every batch size measured.
+static bool use_wave(int nblk, bool decode) {
   const char* e = getenv("EBCC_T1_KERNEL");
-  return (e && e[0] == 'w') ? 1 : ((e && e[0] == 'l') ? 2 : 0);
-}
-static bool use_wave(int nblk) {
-  int v = t1_variant();
-  return v == 1 || (v == 0 && nblk <= kWaveBlocksMax);
+  if (e && e[0] == 'w') return true;
+  if (e && e[0] == 'l') return false;
+  Tuning t = tuning();
+  int v = decode ? t.t1_decoder : t.t1_encoder;
+  return v == 1 || (v == 0 && (decode || nblk <= t.t1_wave_max));
 }
 
 void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes, const void* signs,
                const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail, void* sppf,
                hipStream_t st) {
   if (nblk <= 0) return;
-  if (use_wave(nblk)) {
+  if (use_wave(nblk, false)) {
     t1_encode_wave(F, blk, nblk, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st);
     return;
   }
@@ -747,7 +746,7 @@ void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
 void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
                const int64_t* off, hipStream_t st) {
   if (nblk <= 0) return;
-  if (use_wave(nblk)) {
+  if (use_wave(nblk, true)) {
     t1_decode_wave(F, blk, nblk, cbw, table, off, st);
     return;
   }

@@ -20,13 +20,19 @@ HDR_BYTES = 48
 
 SYMBOLS = ("ebcc_params_default", "ebcc_compress_bound", "ebcc_compress", "ebcc_decompress", "ebcc_stream_info",
            "ebcc_release", "ebcc_status_str", "ebcc_last_error", "ebcc_compress_trace", "ebcc_profile_enable",
-           "ebcc_profile_read", "ebcc_profile_stage_name", "ebcc_compress_batch", "ebcc_decompress_batch")
+           "ebcc_profile_read", "ebcc_profile_stage_name", "ebcc_compress_batch", "ebcc_decompress_batch",
+           "ebcc_tuning_get", "ebcc_tuning_set")
 
 
 class Params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("bound_mode", C.c_uint32), ("err_bound", C.c_double),
                 ("base_ratio", C.c_double), ("q", C.c_double), ("levels", C.c_uint32), ("cblk_log2w", C.c_uint32),
                 ("cblk_log2h", C.c_uint32), ("spiht_tile", C.c_uint32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("t1_encoder", C.c_int32), ("t1_decoder", C.c_int32),
+                ("t1_wave_max", C.c_int32), ("spiht", C.c_int32)]
 
 
 class EbccError(RuntimeError):
@@ -56,6 +62,8 @@ def lib():
         L.ebcc_compress_batch.argtypes = [C.c_int, P, P, P, P, C.POINTER(Params), P, S, P, P, P]
         L.ebcc_decompress_batch.argtypes = [C.c_int, P, P, P, P, P, P, P]
         L.ebcc_stream_info.argtypes = [P, S, C.POINTER(S), C.POINTER(S), C.POINTER(C.c_int)]
+        L.ebcc_tuning_get.argtypes = [C.POINTER(Tuning)]
+        L.ebcc_tuning_set.argtypes = [C.POINTER(Tuning)]
         L.ebcc_release.argtypes = []
         L.ebcc_release.restype = None
         L.ebcc_status_str.argtypes = [C.c_int]
@@ -72,7 +80,7 @@ def lib():
 
 
 def params(err_bound=0.01, base_ratio=30.0, bound_mode=BOUND_REL, levels=5, cblk_log2w=5, cblk_log2h=5,
-           spiht_tile=2, q=0.0):
+           spiht_tile=1, q=0.0):
     p = Params()
     lib().ebcc_params_default(C.byref(p))
     p.err_bound, p.base_ratio, p.bound_mode = float(err_bound), float(base_ratio), int(bound_mode)
@@ -249,6 +257,25 @@ def stream_info(header_bytes):
     ny, nx, mode = C.c_size_t(), C.c_size_t(), C.c_int()
     _check(lib().ebcc_stream_info(b, len(header_bytes), C.byref(ny), C.byref(nx), C.byref(mode)))
     return ny.value, nx.value, mode.value
+
+
+def get_tuning():
+    """Current kernel choices as a dict (see ebcc_tuning in include/ebcc.h)."""
+    t = Tuning()
+    _check(lib().ebcc_tuning_get(C.byref(t)))
+    return {k: getattr(t, k) for k, _ in Tuning._fields_ if k != "struct_size"}
+
+
+def set_tuning(**kw):
+    """Change kernel choices (t1_encoder, t1_decoder, t1_wave_max, spiht);
+    returns the previous ones."""
+    old = get_tuning()
+    t = Tuning()
+    t.struct_size = C.sizeof(Tuning)
+    for k, v in {**old, **kw}.items():
+        setattr(t, k, int(v))
+    _check(lib().ebcc_tuning_set(C.byref(t)))
+    return old
 
 
 def release():

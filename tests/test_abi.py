@@ -37,7 +37,7 @@ def test_host_only_entry_points():
     p = ebcc.Params()
     L.ebcc_params_default(ctypes.byref(p))
     assert p.struct_size == ctypes.sizeof(ebcc.Params)
-    assert (p.err_bound, p.base_ratio, p.levels, p.cblk_log2w, p.cblk_log2h, p.spiht_tile) == (0.01, 30.0, 5, 5, 5, 2)
+    assert (p.err_bound, p.base_ratio, p.levels, p.cblk_log2w, p.cblk_log2h, p.spiht_tile) == (0.01, 30.0, 5, 5, 5, 1)
     assert L.ebcc_compress_bound(181, 360) == 48 + 4 * 181 * 360
     assert L.ebcc_status_str(-3) == b"corrupt stream"
     hdr = bytearray(48)
@@ -62,3 +62,26 @@ def test_params_struct_matches_header():
     fields = re.findall(r"^\s*(?:uint32_t|double)\s+(\w+);", body, flags=re.M)
     from paper_2510_22265_amd import ebcc
     assert fields == [f for f, _ in ebcc.Params._fields_]
+
+
+def test_tuning_struct_and_round_trip():
+    """ebcc_tuning: field order matches the header; set/get round-trips and
+    out-of-range values are refused (host-only entry points)."""
+    src = open(os.path.join(ROOT, "include", "ebcc.h")).read()
+    body = src[src.rindex("typedef struct {"): src.index("} ebcc_tuning;")]
+    fields = re.findall(r"^\s*(?:uint32_t|int32_t)\s+(\w+);", body, flags=re.M)
+    ebcc = _lib()
+    assert fields == [f for f, _ in ebcc.Tuning._fields_]
+    old = ebcc.get_tuning()
+    assert old == {"t1_encoder": 0, "t1_decoder": 0, "t1_wave_max": 32768, "spiht": 0}
+    try:
+        ebcc.set_tuning(t1_encoder=2, t1_wave_max=100, spiht=1)
+        assert ebcc.get_tuning() == {"t1_encoder": 2, "t1_decoder": 0, "t1_wave_max": 100, "spiht": 1}
+        try:
+            ebcc.set_tuning(spiht=5)
+            assert False
+        except ebcc.EbccError as e:
+            assert e.code == ebcc.EINVAL
+    finally:
+        ebcc.set_tuning(**old)
+    assert ebcc.get_tuning() == old

@@ -80,7 +80,7 @@ def test_batch_order_and_repeats(gpu, ref):
     _check_batch(gpu, ref, [xs[i] for i in order], [eps[i] for i in order])
 
 
-@pytest.mark.parametrize("kw", [dict(levels=2), dict(cblk_log2w=6, cblk_log2h=4), dict(spiht_tile=1),
+@pytest.mark.parametrize("kw", [dict(levels=2), dict(cblk_log2w=6, cblk_log2h=4), dict(spiht_tile=2),
                                 dict(base_ratio=4.0), dict(levels=0), dict(bound_mode=1)])
 def test_batch_parameters(gpu, ref, kw):
     xs, eps = _mixed_fields()
@@ -188,3 +188,35 @@ def test_batch_many_blocks(gpu, ref, cb):
     xs = [synth.field(v, 721, 1440, cfg=1, level=5) for v in ("t", "u", "q")]
     eps = [0.01, 0.002, 0.05]
     _check_batch(gpu, ref, xs, eps, cblk_log2w=cb[0], cblk_log2h=cb[1])
+
+
+@pytest.mark.parametrize("tun", [dict(t1_encoder=2, t1_decoder=2), dict(t1_encoder=1, t1_decoder=1, spiht=1),
+                                 dict(t1_encoder=0, t1_decoder=0, t1_wave_max=0)])
+def test_batch_tuning_api(gpu, ref, tun):
+    """Kernel choices set through ebcc_tuning_set never change the streams."""
+    old = gpu.set_tuning(**tun)
+    try:
+        xs, eps = _mixed_fields()
+        _check_batch(gpu, ref, xs, eps)
+    finally:
+        gpu.set_tuning(**old)
+
+
+def test_autotune_picks_a_measured_candidate(gpu):
+    """The autotuner returns one of its measured candidates, respects the
+    compression-ratio constraint, and leaves the tuning unchanged."""
+    from paper_2510_22265_amd import autotune
+    specs = synth.batch_specs(n=12)
+    xs = [_dev(synth.batch_field(s)) for s in specs]
+    eps = [s[3] for s in specs]
+    before = gpu.get_tuning()
+    res = autotune.tune(xs, eps, formats=((5, 5, 1), (5, 5, 2), (5, 4, 1)), kernels=autotune.KERNELS[:3])
+    assert gpu.get_tuning() == before
+    assert res["CR"] >= 0.99 * res["CR_default"]
+    picked = [r for r in res["table"] if r["GBps"] == res["GBps"]]
+    assert picked and all(picked[0][k] == v for k, v in {**res["params"], **res["tuning"]}.items())
+    streams = gpu.compress_batch(xs, err_bounds=eps, **res["params"])
+    for i, x in enumerate(xs):
+        y = _host(gpu.decompress(streams[i], *x.shape)).astype(np.float64)
+        xh = _host(x).astype(np.float64)
+        assert np.abs(xh - y).max() <= eps[i] * (xh.max() - xh.min())
