@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--ratio", type=float, default=30.0)
     ap.add_argument("--tile", type=int, default=None, help="SPIHT tile side (default: the library's)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuned batched run")
+    ap.add_argument("--serve-rates", default="200,1000,5000", help="Poisson arrival rates (req/s); empty: skip")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per rate")
     ap.add_argument("--batch-fields", type=int, default=256, help="fields of the uneven batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -315,6 +317,42 @@ def main():
             "stack_streams_identical": bool(stack_same), "stack_violations": sviol,
             "tuned": tuned,
         }
+
+    # ---------------- serving loop: Poisson arrivals, continuous batching ----------------
+    serving = None
+    rates = [float(r) for r in args.serve_rates.split(",") if r.strip()] if bspecs else []
+    if rates:
+        from paper_2510_22265_amd import serve
+        import random
+        # half the requests compress a field of the uneven mix, half decompress one of its streams
+        sstreams_c = [s.clone() for s in bstreams]
+        serving = {"workload": f"Poisson arrivals of compress/decompress requests (1:1) on the uneven "
+                               f"{len(bx)}-field mix, HBM admission budget 64 GB, 2 lanes",
+                   "budget_GB": 64, "lanes": 2}
+        for rate in rates:
+            rnd = random.Random(int(rate))
+
+            def make(k):
+                i = rnd.randrange(len(bx))
+                if rnd.random() < 0.5:
+                    return serve.Request(serve.COMPRESS, bx[i], eps=beps[i], tag=i)
+                return serve.Request(serve.DECOMPRESS, sstreams_c[i], shape=tuple(bx[i].shape), tag=i)
+
+            srv = serve.Server(hbm_budget=64 * 10**9, lanes=2, params=fmt, base_ratio=args.ratio).start()
+            reqs, wall = serve.poisson_run(srv, make, rate=rate, duration=args.serve_seconds, seed=int(rate),
+                                           max_requests=int(rate * args.serve_seconds * 2) + 10)
+            srv.stop()
+            st = serve.summarize(reqs, wall)
+            st["mean_batch"] = float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0
+            st["peak_GB_admitted"] = srv.peak_in_use / 1e9
+            bad = 0
+            for r in reqs:   # results in the mix against the same request alone (a sample)
+                if r.kind == serve.COMPRESS and r.tag % 16 == 0 and r.status == 0:
+                    bad += int(not torch.equal(r.result, bstreams[r.tag]))
+            st["mix_vs_solo_mismatches"] = bad
+            serving[f"{int(rate)}_per_s"] = st
+            log(f"serving at {rate:.0f} req/s: {st}")
+        batched["serving"] = serving
 
     # ---------------- CPU oracle baseline ----------------
     cpu = None
