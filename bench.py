@@ -89,6 +89,10 @@ def main():
     ap.add_argument("--batch-fields", type=int, default=256, help="fields of the uneven batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the batched uneven mix (for kernel profiles); prints its own JSON line")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run a plain elementwise copy of MIB MiB three times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the path shards by field with no exchange between GPUs, "
@@ -103,6 +107,16 @@ def main():
     ebcc.lib()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)      # reads 4 B and writes 4 B per element
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "elementwise copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "launches": 3}), flush=True)
+        return
 
     # ---------------- inputs ----------------
     stack_specs = [("stack", (v, args.ny, args.nx, lev)) for lev in range(37) for v in synth.VARS][: args.fields]
@@ -141,6 +155,33 @@ def main():
                 lat_d.append(time.perf_counter() - a)
         torch.cuda.synchronize()
         return t1 - t0, time.perf_counter() - t1
+
+    if args.batch_only:
+        bx = [torch.from_numpy(f).to(dev) for f in batch_h]
+        beps = [s[3] for s in bspecs]
+        bbytes = sum(f.nbytes for f in batch_h)
+        bargs = ebcc.BatchArgs(bx, err_bounds=beps)
+        bout = torch.empty(bargs.bound(), dtype=torch.uint8, device=dev)
+        assert ebcc.compress_batch_into(bargs, bout, p, stream) == 0
+        bstreams = [bout[bargs.offsets[i]: bargs.offsets[i] + bargs.lengths[i]] for i in range(bargs.n)]
+        brecs = [torch.empty(f.shape, dtype=torch.float32, device=dev) for f in batch_h]
+        dargs = ebcc.DecodeArgs(bstreams, brecs)
+        for w in range(args.warmup):
+            assert ebcc.compress_batch_into(bargs, bout, p, stream) == 0
+            assert ebcc.decompress_batch_into(dargs, stream) == 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            assert ebcc.compress_batch_into(bargs, bout, p, stream) == 0
+            assert ebcc.decompress_batch_into(dargs, stream) == 0
+            log(f"batched step {s} done")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        viol, _ = verify(batch_h, brecs, beps)
+        print(json.dumps({"workload": f"uneven batch of {len(bx)} fields, batched entry points only",
+                          "GBps": bbytes * args.steps / dt / 1e9, "steps": args.steps, "violations": viol}),
+              flush=True)
+        return
 
     # ---------------- headline: per-field path over the stack ----------------
     plist = [p] * len(xs)

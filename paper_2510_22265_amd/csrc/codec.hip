@@ -112,13 +112,42 @@ __global__ void k_init_fields(const FieldDev* __restrict__ F, int nf) {
   for (int k = 0; k < 8; k++) { f.flags[k] = 0; f.u32s[k] = 0; f.totals[k] = 0; }
 }
 
+// Block-wide reductions of 256 threads (the result is valid in thread 0);
+// full-field sweeps make one atomic update per block.
+__device__ __forceinline__ unsigned block_min(unsigned v, unsigned* sh) {
+  for (int off = 32; off > 0; off >>= 1) { unsigned a = __shfl_xor(v, off); v = a < v ? a : v; }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 1; k < 4; k++) v = sh[k] < v ? sh[k] : v;
+  return v;
+}
+__device__ __forceinline__ unsigned block_max(unsigned v, unsigned* sh) {
+  for (int off = 32; off > 0; off >>= 1) { unsigned a = __shfl_xor(v, off); v = a > v ? a : v; }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 1; k < 4; k++) v = sh[k] > v ? sh[k] : v;
+  return v;
+}
+__device__ __forceinline__ unsigned block_sum(unsigned v, unsigned* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) v = sh[0] + sh[1] + sh[2] + sh[3];
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_minmax(const FieldDev* __restrict__ F) {
+  __shared__ unsigned sh[4];
   const FieldDev& f = F[blockIdx.y];
   if (!f.active) return;
   const int n = f.ny * f.nx;
   const float* x = f.buf[BUF_X];
-  unsigned mn = 0xFFFFFFFFu, mx = 0u;
-  int nf = 0;
+  unsigned mn = 0xFFFFFFFFu, mx = 0u, nf = 0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     float v = x[i];
     if (!__builtin_isfinite(v)) { nf = 1; continue; }
@@ -126,14 +155,10 @@ __global__ __launch_bounds__(256) void k_minmax(const FieldDev* __restrict__ F) 
     mn = o < mn ? o : mn;
     mx = o > mx ? o : mx;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    unsigned a = __shfl_xor(mn, off), b = __shfl_xor(mx, off);
-    int c = __shfl_xor(nf, off);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-    nf |= c;
-  }
-  if ((threadIdx.x & 63) == 0) {
+  mn = block_min(mn, sh);
+  mx = block_max(mx, sh);
+  nf = block_max(nf, sh);
+  if (threadIdx.x == 0) {
     atomicMin(&f.fp->xmin_bits, mn);
     atomicMax(&f.fp->xmax_bits, mx);
     if (nf) atomicOr(&f.fp->nonfinite, 1);
@@ -206,6 +231,7 @@ __global__ __launch_bounds__(256) void k_fill(const FieldDev* __restrict__ F, in
 
 // Residual quantisation q_r = floor(|c| * 2^-e_r) (capped), sign in bit 31.
 __global__ __launch_bounds__(256) void k_quant_res(const FieldDev* __restrict__ F) {
+  __shared__ unsigned sh[4];
   const FieldDev& f = F[blockIdx.y];
   if (!f.active) return;
   const int n = f.ny * f.nx, er = f.er;
@@ -218,11 +244,8 @@ __global__ __launch_bounds__(256) void k_quant_res(const FieldDev* __restrict__ 
     qr[i] = q | (v < 0.0f ? 0x80000000u : 0u);
     mx = q > mx ? q : mx;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    unsigned a = __shfl_xor(mx, off);
-    mx = a > mx ? a : mx;
-  }
-  if ((threadIdx.x & 63) == 0) atomicMax(&f.u32s[0], mx);
+  mx = block_max(mx, sh);
+  if (threadIdx.x == 0 && mx) atomicMax(&f.u32s[0], mx);
 }
 
 // Residual coefficients kept by truncation at the end of plane n_s, midpoint
@@ -372,6 +395,7 @@ __global__ __launch_bounds__(256) void k_copy_raw(const FieldDev* __restrict__ F
 // Stream checksum: sum over the little-endian 32-bit words w_k of the bytes
 // after the header (zero padded) of w_k * (2k + 1), modulo 2^32.
 __global__ __launch_bounds__(256) void k_checksum(const FieldDev* __restrict__ F) {
+  __shared__ unsigned sh[4];
   const FieldDev& f = F[blockIdx.y];
   if (!f.active) return;
   int64_t n = f.len - kHdr;
@@ -384,8 +408,8 @@ __global__ __launch_bounds__(256) void k_checksum(const FieldDev* __restrict__ F
       if (4 * k + b < n) w |= (uint32_t)q[4 * k + b] << (8 * b);
     s += w * (uint32_t)(2 * k + 1);
   }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if ((threadIdx.x & 63) == 0) atomicAdd(&f.u32s[1], s);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) atomicAdd(&f.u32s[1], s);
 }
 
 __global__ void k_header(const FieldDev* __restrict__ F, int nfields) {
@@ -677,6 +701,14 @@ static int grow_ws(WS* w, size_t need, size_t pin_need, hipStream_t st, char** b
 // Batches are processed in chunks of at most this many samples or fields.
 constexpr size_t kChunkSamples = size_t(1) << 26;
 constexpr int kChunkFields = 4096;
+
+// Full-field sweeps that reduce: about 16 elements per thread, at most 1024
+// blocks per field.
+static int grid_sweep(size_t n) {
+  size_t g = (n + 4095) / 4096;
+  if (g > 1024) g = 1024;
+  return g < 1 ? 1 : (int)g;
+}
 
 static int grid_for(size_t n) {
   size_t g = (n + 255) / 256;
@@ -985,7 +1017,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   k_init_fields<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
   size_t maxN = 0;
   for (auto& f : c.Fh) maxN = std::max(maxN, (size_t)f.ny * f.nx);
-  k_minmax<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+  k_minmax<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
   k_params<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
   HIPCHK(hipGetLastError());
   prof.mark(S_SCALARS);
@@ -1026,7 +1058,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     pointwise(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, 3, EPI_CHECK, 0, st);   // does the base alone meet the bound?
     prof.mark(S_BASEREC);
     dwt_forward(c.F, c.Fh.data(), nf, BUF_X, BUF_CRES, PRO_NORM_MINUS, st);
-    k_quant_res<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+    k_quant_res<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
     HIPCHK(hipGetLastError());
     prof.mark(S_RESID);
     std::vector<int64_t> col;
@@ -1063,7 +1095,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
       if (anyrq) {
         if ((rc = c.set_active(rq))) return rc;
         k_zero_slot<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, 1);
-        k_quant_res<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+        k_quant_res<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
       }
       if (anyck) {
         if ((rc = c.set_active(ck))) return rc;
@@ -1169,7 +1201,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   }
   std::vector<int> all(nf, 1);
   if ((rc = c.set_active(all))) return rc;
-  k_checksum<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+  k_checksum<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
   k_header<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
   HIPCHK(hipGetLastError());
   prof.mark(S_PACK);
@@ -1302,7 +1334,7 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
   k_set_decode<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, d_xr);
   size_t maxN = 0;
   for (auto& f : c.Fh) maxN = std::max(maxN, (size_t)f.ny * f.nx);
-  k_checksum<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
+  k_checksum<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
   std::vector<int> cm(nf, 0), rm(nf, 0), cd(nf, 0), cr(nf, 0), cn(nf, 0);
   bool anyc = false, anyr = false, anyres = false, anynores = false;
   for (int i = 0; i < nf; i++) {
