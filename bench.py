@@ -34,6 +34,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 
+# HBM bytes per launch of the headline path's dominant kernel on one
+# 721x1440 field at eps_rel 1%, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# WRITE_SIZE; profiles/kernels_era5_721x1440_per_field.md), each scaled by
+# what the counter reads for a plain elementwise copy of 1 GiB (FETCH_SIZE
+# x2.0, WRITE_SIZE x1.0).  Valid only while the kernel's source is the one
+# measured (checked by hash); otherwise traffic is reported as null.
+MEASURED_TRAFFIC = {
+    "t1_encode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
+                  "sha256": "7a43aa6c07d9b488498cbf9d8f102696f63a434745eb1dae3220f07c4a6c2438",
+                  "ny": 721, "nx": 1440, "eps": 0.01,
+                  "bytes": (2.0 * (4540.1 + 4316.9) / 2 + 1.0 * (974.0 + 1231.7) / 2) * 1024},
+}
+
+
+def measured_traffic(kernel, ny, nx, eps):
+    import hashlib
+    m = MEASURED_TRAFFIC.get(kernel)
+    if not m or (m["ny"], m["nx"], m["eps"]) != (ny, nx, eps):
+        return None
+    with open(os.path.join(ROOT, m["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != m["sha256"]:
+            return None
+    return m["bytes"]
+
 
 def _gen(spec):
     from paper_2510_22265_amd import synth
@@ -83,6 +107,7 @@ def main():
     ap.add_argument("--eps", type=float, default=0.01)
     ap.add_argument("--ratio", type=float, default=30.0)
     ap.add_argument("--tile", type=int, default=None, help="SPIHT tile side (default: the library's)")
+    ap.add_argument("--cblk", default=None, help="code-block log2 sizes w,h (default: the library's)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuned batched run")
     ap.add_argument("--serve-rates", default="200,1000,5000", help="Poisson arrival rates (req/s); empty: skip")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per rate")
@@ -126,6 +151,8 @@ def main():
     stack_h, batch_h = fields_h[: len(stack_specs)], fields_h[len(stack_specs):]
     xs = [torch.from_numpy(f).to(dev) for f in stack_h]
     fmt = {} if args.tile is None else {"spiht_tile": args.tile}
+    if args.cblk:
+        fmt["cblk_log2w"], fmt["cblk_log2h"] = (int(v) for v in args.cblk.split(","))
     p = ebcc.params(args.eps, args.ratio, **fmt)
     tile = p.spiht_tile
     cap = ebcc.compress_bound(args.ny, args.nx)
@@ -224,8 +251,8 @@ def main():
             algo = 8.0 * N
         ach = algo / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBPS, "traffic": None, "avg_launch_ms": ms / calls,
-                "algo_bytes_per_launch": algo}
+                "frac": ach / HBM_PEAK_GBPS, "traffic": measured_traffic(dom, args.ny, args.nx, args.eps),
+                "avg_launch_ms": ms / calls, "algo_bytes_per_launch": algo}
 
     # ---------------- batched execution ----------------
     batched = None
@@ -419,7 +446,8 @@ def main():
         "ms_per_step": t_total / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"ERA5-shaped stack, plain per-field path: {len(xs)} fields {args.ny}x{args.nx} "
-                               f"(37 levels x t,u,v,q), eps_rel {args.eps}, r {args.ratio}, L 5, 32x32 blocks, "
+                               f"(37 levels x t,u,v,q), eps_rel {args.eps}, r {args.ratio}, L 5, "
+                               f"{1 << p.cblk_log2w}x{1 << p.cblk_log2h} blocks, "
                                f"{tile}x{tile}-root SPIHT tiles",
                    "fields": len(xs), "ny": args.ny, "nx": args.nx, "eps_rel": args.eps, "base_ratio": args.ratio},
         "compress_GBps": nbytes * steps / tc / 1e9, "decompress_GBps": nbytes * steps / td / 1e9,

@@ -1362,25 +1362,31 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
     k_scan<<<nf, 1024, 0, st>>>(c.F, c.tent, 1, 0, 0x3FFFFFFu, c.toff);
     k_check_tables<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
     prof.mark(S_D_PARSE);
+    if (anyres) {
+      // The residual layer decodes independently of the base layer: SPIHT
+      // runs on the second stream while tier-1 decoding and the base
+      // inverse DWT run on the caller's (the SPIHT kernels skip fields
+      // without a residual section).
+      k_fill<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, BUF_CHAT, 0.0f);
+      hipStream_t sa = c.ws->aux;
+      if ((rc = c.fork())) return rc;
+      if (c.forced_global) {
+        spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, sa);
+      } else {
+        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1];
+        spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sa);
+        spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sa);
+        spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, sa);
+      }
+    }
     t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, st);
     prof.mark(S_D_T1);
     dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, st);
     prof.mark(S_D_IDWT_BASE);
     if (anyres) {
-      if ((rc = c.set_active(cr))) return rc;
-      k_fill<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, BUF_CHAT, 0.0f);
-      if (c.forced_global) {
-        spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, st);
-      } else {
-        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1];
-        hipStream_t sa = c.ws->aux;
-        if ((rc = c.fork())) return rc;
-        spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sa);
-        spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sa);
-        spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, st);
-        if ((rc = c.join())) return rc;
-      }
+      if ((rc = c.join())) return rc;
       prof.mark(S_D_SPIHT);
+      if ((rc = c.set_active(cr))) return rc;
       dwt_inverse(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, EPI_FINAL, st);
     }
     if (anynores) {

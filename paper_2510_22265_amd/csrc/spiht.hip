@@ -289,7 +289,7 @@ __global__ __launch_bounds__(LANES) void k_spiht_decode(const FieldDev* __restri
   const int t = tix[q];
   TileD td = tiles[t];
   const FieldDev& f = F[td.field];
-  if (!f.active) return;
+  if (!f.active || f.rb == 0) return;
   const Band* B = f.bands;
   const int nx = f.nx, L = f.L, n_s = f.ns, e_r = f.er;
   const uint8_t* sec = f.out + kHdr + f.bb;

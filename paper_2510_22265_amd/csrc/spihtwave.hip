@@ -396,7 +396,7 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
   const int t = tix[blockIdx.x];
   const TileD td = tiles[t];
   const FieldDev& f = F[td.field];
-  if (!f.active) return;
+  if (!f.active || f.rb == 0) return;
   const uint8_t* __restrict__ sec = f.out + kHdr + f.bb;
   const int64_t sec_len = f.rb;
   const Band* bands_g = f.bands;
