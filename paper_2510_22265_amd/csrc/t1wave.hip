@@ -122,6 +122,28 @@ __device__ __forceinline__ int sgn3(M s, M n, int x) {
   return bt(s, x) ? (bt(n, x) ? -1 : 1) : 0;
 }
 
+// Lane y: the columns of row y with at least one significant neighbour among
+// the eight (rows y-1, y, y+1).  Significance does not change during a
+// magnitude refinement pass, so its contexts are fixed at the pass start
+// and computed here for all rows at once.
+template <typename M> __device__ __forceinline__ M shfl_row(M v, int src);
+template <> __device__ __forceinline__ uint32_t shfl_row<uint32_t>(uint32_t v, int src) {
+  return (uint32_t)__shfl((int)v, src);
+}
+template <> __device__ __forceinline__ uint64_t shfl_row<uint64_t>(uint64_t v, int src) {
+  uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src), hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+template <typename M>
+__device__ __forceinline__ M neighbour_mask(M sig, int lane) {
+  M up = shfl_row<M>(sig, lane > 0 ? lane - 1 : 0);
+  M dn = shfl_row<M>(sig, lane < 63 ? lane + 1 : 63);
+  if (lane == 0) up = 0;
+  if (lane == 63) dn = 0;
+  M v = up | dn;
+  return (sig << 1) | (sig >> 1) | v | (v << 1) | (v >> 1);
+}
+
 // Row r' in [-1, 4] of the current stripe's significance / sign rows.
 #define SR(rr) ((rr) < 0 ? sA : ((rr) > 3 ? sC : sB[(rr)]))
 #define NR(rr) ((rr) < 0 ? nA : ((rr) > 3 ? nC : nB[(rr)]))
@@ -177,6 +199,7 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
       nsig = 0;
       M refd = sig & ~vis;          // MRP refines every sample significant before this plane
+      const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
       for (int y0 = 0; y0 < h && !stop; y0 += 4) {
         const int rn = h - y0 < 4 ? h - y0 : 4;
         M sA = rowv(sig, y0 - 1), sC = rowv(sig, y0 + 4);
@@ -190,7 +213,9 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
           vB[r] = in ? rdl<M>(vis, y) : (M)0;
           fB[r] = (in && ty == 1) ? rdl<M>(ref, y) : (M)0;
           gB[r] = in ? rdl<M>(mag, y) : (M)0;
-          nB[r] = (in && ty != 1) ? rdl<M>(neg, y) : (M)0;
+          // sign rows; in a refinement pass (no sign coding) the rows'
+          // neighbour-significance masks instead
+          nB[r] = in ? rdl<M>(ty == 1 ? nbm8 : neg, y) : (M)0;
           nsB[r] = 0; spB[r] = 0;
         }
         if (ty != 1) { nA = rowv(neg, y0 - 1); nC = rowv(neg, y0 + 4); }
@@ -254,14 +279,7 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
 #pragma unroll
             for (int r = 0; r < 4; r++) {
               if (r >= rn || !bt(sB[r] & ~vB[r], x)) continue;
-              int cx;
-              if (bt(fB[r], x)) cx = CX_MR + 2;
-              else {
-                M up = SR(r - 1), dn = SR(r + 1), mid = sB[r];
-                int t = bt(mid, x - 1) + bt(mid, x + 1) + bt(up, x) + bt(dn, x) + bt(up, x - 1) + bt(up, x + 1) +
-                        bt(dn, x - 1) + bt(dn, x + 1);
-                cx = t ? CX_MR + 1 : CX_MR;
-              }
+              const int cx = bt(fB[r], x) ? CX_MR + 2 : (bt(nB[r], x) ? CX_MR + 1 : CX_MR);
               mqw_encode(e, ctxv, tabv, cx, bt(gB[r], x), out, lane);
               fB[r] |= (M)1 << x;
             }
@@ -478,6 +496,7 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
     cur = 0;
     magp = 0;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < kb; ty++) {
+      const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
       for (int y0 = 0; y0 < h; y0 += 4) {
         const int rn = h - y0 < 4 ? h - y0 : 4;
         M sA = rowv(sig, y0 - 1), sC = rowv(sig, y0 + 4);
@@ -490,7 +509,9 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
           sB[r] = in ? rdl<M>(sig, y) : (M)0;
           vB[r] = in ? rdl<M>(vis, y) : (M)0;
           fB[r] = (in && ty == 1) ? rdl<M>(ref, y) : (M)0;
-          nB[r] = in ? rdl<M>(neg, y) : (M)0;
+          // decoded signs; in a refinement pass (no sign decoding) the
+          // rows' neighbour-significance masks instead
+          nB[r] = in ? rdl<M>(ty == 1 ? nbm8 : neg, y) : (M)0;
           cB[r] = 0; mB[r] = 0;
         }
         auto dec_sign = [&](int r, int x) {
@@ -552,14 +573,7 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
 #pragma unroll
             for (int r = 0; r < 4; r++) {
               if (r >= rn || !bt(sB[r] & ~vB[r], x)) continue;
-              int cx;
-              if (bt(fB[r], x)) cx = CX_MR + 2;
-              else {
-                M up = SR(r - 1), dn = SR(r + 1), mid = sB[r];
-                int t = bt(mid, x - 1) + bt(mid, x + 1) + bt(up, x) + bt(dn, x) + bt(up, x - 1) + bt(up, x + 1) +
-                        bt(dn, x - 1) + bt(dn, x + 1);
-                cx = t ? CX_MR + 1 : CX_MR;
-              }
+              const int cx = bt(fB[r], x) ? CX_MR + 2 : (bt(nB[r], x) ? CX_MR + 1 : CX_MR);
               int bit = mqwd_decode(d, ctxv, tabv, cx, lane);
               if (bit) mB[r] |= (M)1 << x;
               fB[r] |= (M)1 << x;
@@ -622,7 +636,8 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
 #pragma unroll
         for (int r = 0; r < 4; r++)
           if (r < rn && lane == y0 + r) {
-            sig = sB[r]; vis = vB[r]; neg = nB[r];
+            sig = sB[r]; vis = vB[r];
+            if (ty != 1) neg = nB[r];
             if (ty == 1) ref = fB[r];
             cur |= cB[r];
             magp |= mB[r];
