@@ -144,6 +144,24 @@ __device__ __forceinline__ M neighbour_mask(M sig, int lane) {
   return (sig << 1) | (sig >> 1) | v | (v << 1) | (v >> 1);
 }
 
+// Bits x-1, x, x+1 of a row mask as bits 0, 1, 2 (0 outside the row), and
+// the neighbourhood counts of T.800 Table D.1 from three such fields.
+template <typename M>
+__device__ __forceinline__ uint32_t f3(M m, int x) {
+  return x > 0 ? (uint32_t)(m >> (x - 1)) & 7u : (uint32_t)(m << 1) & 7u;
+}
+template <typename M>
+__device__ __forceinline__ int btu(M m, int x) { return (int)((m >> x) & 1); }   // 0 <= x < bits
+struct HVD { int h, v, d; bool any; };
+__device__ __forceinline__ HVD hvd(uint32_t u3, uint32_t m3, uint32_t d3) {
+  HVD r;
+  r.h = __builtin_popcount(m3 & 5u);
+  r.v = (int)((u3 >> 1) & 1u) + (int)((d3 >> 1) & 1u);
+  r.d = __builtin_popcount(u3 & 5u) + __builtin_popcount(d3 & 5u);
+  r.any = ((u3 | d3 | (m3 & 5u)) != 0u);
+  return r;
+}
+
 // Row r' in [-1, 4] of the current stripe's significance / sign rows.
 #define SR(rr) ((rr) < 0 ? sA : ((rr) > 3 ? sC : sB[(rr)]))
 #define NR(rr) ((rr) < 0 ? nA : ((rr) > 3 ? nC : nB[(rr)]))
@@ -231,43 +249,43 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
           vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
           int xr;
           int cx = sc_ctx(hc, vc, &xr);
-          mqw_encode(e, ctxv, tabv, cx, bt(nB[r], x) ^ xr, out, lane);
+          mqw_encode(e, ctxv, tabv, cx, btu(nB[r], x) ^ xr, out, lane);
         };
         if (ty == 0) {                                   // significance propagation
-          int x = 0;
-          while (x < w) {
-            M c = 0;
+          // candidate columns at the stripe start; a sample that becomes
+          // significant in column x can only add column x + 1
+          M c = 0;
 #pragma unroll
-            for (int r = 0; r < 4; r++)
-              if (r < rn) {
-                M nb = SR(r - 1) | SR(r) | SR(r + 1);
-                nb = nb | (nb << 1) | (nb >> 1);
-                c |= ~SR(r) & nb;
-              }
-            c &= wm & (~(M)0 << x);
-            if (!c) break;
-            x = ctzm(c);
+          for (int r = 0; r < 4; r++)
+            if (r < rn) {
+              M nb = SR(r - 1) | SR(r) | SR(r + 1);
+              nb = nb | (nb << 1) | (nb >> 1);
+              c |= ~SR(r) & nb;
+            }
+          c &= wm;
+          while (c) {
+            const int x = ctzm(c);
+            c &= c - 1;
+            bool grew = false;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
               if (r >= rn) continue;
               M mid = sB[r];
-              if (bt(mid, x)) continue;
-              M up = SR(r - 1), dn = SR(r + 1);
-              int H = bt(mid, x - 1) + bt(mid, x + 1);
-              int V = bt(up, x) + bt(dn, x);
-              int D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
-              if (H + V + D == 0) continue;
-              int bit = bt(gB[r], x);
-              mqw_encode(e, ctxv, tabv, zc_ctx(orient, H, V, D), bit, out, lane);
+              if (btu(mid, x)) continue;
+              const HVD n = hvd(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
+              if (!n.any) continue;
+              int bit = btu(gB[r], x);
+              mqw_encode(e, ctxv, tabv, zc_ctx(orient, n.h, n.v, n.d), bit, out, lane);
               vB[r] |= (M)1 << x;
               if (bit) {
                 code_sign(r, x);
                 sB[r] = mid | ((M)1 << x);
                 nsB[r] |= (M)1 << x;
                 spB[r] |= (M)1 << x;
+                grew = true;
               }
             }
-            x++;
+            if (grew && x + 1 < w) c |= (M)1 << (x + 1);
           }
         } else if (ty == 1) {                            // magnitude refinement
           M mk = 0;
@@ -278,9 +296,9 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
             mk &= mk - 1;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-              if (r >= rn || !bt(sB[r] & ~vB[r], x)) continue;
-              const int cx = bt(fB[r], x) ? CX_MR + 2 : (bt(nB[r], x) ? CX_MR + 1 : CX_MR);
-              mqw_encode(e, ctxv, tabv, cx, bt(gB[r], x), out, lane);
+              if (r >= rn || !btu(sB[r] & ~vB[r], x)) continue;
+              const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nB[r], x) ? CX_MR + 1 : CX_MR);
+              mqw_encode(e, ctxv, tabv, cx, btu(gB[r], x), out, lane);
               fB[r] |= (M)1 << x;
             }
           }
@@ -298,7 +316,7 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
               bool run = true;
 #pragma unroll
               for (int r = 0; r < 4; r++)
-                if (bt(sB[r] | vB[r], x)) run = false;
+                if (btu(sB[r] | vB[r], x)) run = false;
               if (run) {
                 M nbm = nb3<M>(x);
                 if ((sA | sB[0] | sB[1] | sB[2] | sB[3] | sC) & nbm) run = false;
@@ -307,7 +325,7 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
                 int rr = -1;
 #pragma unroll
                 for (int r = 3; r >= 0; r--)
-                  if (bt(gB[r], x)) rr = r;
+                  if (btu(gB[r], x)) rr = r;
                 mqw_encode(e, ctxv, tabv, CX_RL, rr >= 0, out, lane);
                 if (rr < 0) continue;
                 mqw_encode(e, ctxv, tabv, CX_UNI, (rr >> 1) & 1, out, lane);
@@ -325,13 +343,10 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
 #pragma unroll
             for (int r = 0; r < 4; r++) {
               if (r < rstart || r >= rn) continue;
-              if (bt(sB[r] | vB[r], x)) continue;
-              M up = SR(r - 1), dn = SR(r + 1), mid = sB[r];
-              int H = bt(mid, x - 1) + bt(mid, x + 1);
-              int V = bt(up, x) + bt(dn, x);
-              int D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
-              int bit = bt(gB[r], x);
-              mqw_encode(e, ctxv, tabv, zc_ctx(orient, H, V, D), bit, out, lane);
+              if (btu(sB[r] | vB[r], x)) continue;
+              const HVD n = hvd(f3(SR(r - 1), x), f3(sB[r], x), f3(SR(r + 1), x));
+              int bit = btu(gB[r], x);
+              mqw_encode(e, ctxv, tabv, zc_ctx(orient, n.h, n.v, n.d), bit, out, lane);
               if (bit) {
                 code_sign(r, x);
                 sB[r] |= (M)1 << x;
@@ -529,39 +544,39 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
           if (s) nB[r] |= (M)1 << x;
         };
         if (ty == 0) {
-          int x = 0;
-          while (x < w) {
-            M c = 0;
+          // candidate columns at the stripe start; a sample that becomes
+          // significant in column x can only add column x + 1
+          M c = 0;
 #pragma unroll
-            for (int r = 0; r < 4; r++)
-              if (r < rn) {
-                M nb = SR(r - 1) | SR(r) | SR(r + 1);
-                nb = nb | (nb << 1) | (nb >> 1);
-                c |= ~SR(r) & nb;
-              }
-            c &= wm & (~(M)0 << x);
-            if (!c) break;
-            x = ctzm(c);
+          for (int r = 0; r < 4; r++)
+            if (r < rn) {
+              M nb = SR(r - 1) | SR(r) | SR(r + 1);
+              nb = nb | (nb << 1) | (nb >> 1);
+              c |= ~SR(r) & nb;
+            }
+          c &= wm;
+          while (c) {
+            const int x = ctzm(c);
+            c &= c - 1;
+            bool grew = false;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
               if (r >= rn) continue;
               M mid = sB[r];
-              if (bt(mid, x)) continue;
-              M up = SR(r - 1), dn = SR(r + 1);
-              int H = bt(mid, x - 1) + bt(mid, x + 1);
-              int V = bt(up, x) + bt(dn, x);
-              int D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
-              if (H + V + D == 0) continue;
-              int bit = mqwd_decode(d, ctxv, tabv, zc_ctx(orient, H, V, D), lane);
+              if (btu(mid, x)) continue;
+              const HVD n = hvd(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
+              if (!n.any) continue;
+              int bit = mqwd_decode(d, ctxv, tabv, zc_ctx(orient, n.h, n.v, n.d), lane);
               vB[r] |= (M)1 << x;
               if (bit) {
                 dec_sign(r, x);
                 sB[r] = mid | ((M)1 << x);
                 cB[r] |= (M)1 << x;
                 mB[r] |= (M)1 << x;
+                grew = true;
               }
             }
-            x++;
+            if (grew && x + 1 < w) c |= (M)1 << (x + 1);
           }
         } else if (ty == 1) {
           M mk = 0;
@@ -572,8 +587,8 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
             mk &= mk - 1;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-              if (r >= rn || !bt(sB[r] & ~vB[r], x)) continue;
-              const int cx = bt(fB[r], x) ? CX_MR + 2 : (bt(nB[r], x) ? CX_MR + 1 : CX_MR);
+              if (r >= rn || !btu(sB[r] & ~vB[r], x)) continue;
+              const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nB[r], x) ? CX_MR + 1 : CX_MR);
               int bit = mqwd_decode(d, ctxv, tabv, cx, lane);
               if (bit) mB[r] |= (M)1 << x;
               fB[r] |= (M)1 << x;
@@ -594,7 +609,7 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
               bool run = true;
 #pragma unroll
               for (int r = 0; r < 4; r++)
-                if (bt(sB[r] | vB[r], x)) run = false;
+                if (btu(sB[r] | vB[r], x)) run = false;
               if (run) {
                 M nbm = nb3<M>(x);
                 if ((sA | sB[0] | sB[1] | sB[2] | sB[3] | sC) & nbm) run = false;
@@ -618,12 +633,9 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
 #pragma unroll
             for (int r = 0; r < 4; r++) {
               if (r < rstart || r >= rn) continue;
-              if (bt(sB[r] | vB[r], x)) continue;
-              M up = SR(r - 1), dn = SR(r + 1), mid = sB[r];
-              int H = bt(mid, x - 1) + bt(mid, x + 1);
-              int V = bt(up, x) + bt(dn, x);
-              int D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
-              int bit = mqwd_decode(d, ctxv, tabv, zc_ctx(orient, H, V, D), lane);
+              if (btu(sB[r] | vB[r], x)) continue;
+              const HVD n = hvd(f3(SR(r - 1), x), f3(sB[r], x), f3(SR(r + 1), x));
+              int bit = mqwd_decode(d, ctxv, tabv, zc_ctx(orient, n.h, n.v, n.d), lane);
               if (bit) {
                 dec_sign(r, x);
                 sB[r] |= (M)1 << x;
