@@ -42,9 +42,9 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 # measured (checked by hash); otherwise traffic is reported as null.
 MEASURED_TRAFFIC = {
     "t1_encode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
-                  "sha256": "7a43aa6c07d9b488498cbf9d8f102696f63a434745eb1dae3220f07c4a6c2438",
+                  "sha256": "1bec147a73172eac890a04b479db0e0a424dfb03bff96a9bf01915babd006f9a",
                   "ny": 721, "nx": 1440, "eps": 0.01,
-                  "bytes": (2.0 * (4540.1 + 4316.9) / 2 + 1.0 * (974.0 + 1231.7) / 2) * 1024},
+                  "bytes": (2.0 * (4530.3 + 4312.4) / 2 + 1.0 * (978.3 + 1231.4) / 2) * 1024},
 }
 
 
