@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -770,6 +771,14 @@ struct Call {
   TileD* d_tiles_own;
   int64_t* d_slot_own;
   int* d_tix_own;
+  // truncation-search candidates: a table of candidate entries (a field with
+  // one truncation point each), their violation flags and, when the search
+  // evaluates two bisection levels per round, three extra pairs of
+  // residual/scratch planes per field
+  int spec_depth = 1;
+  FieldDev* Fc = nullptr;
+  int* cand_flags = nullptr;
+  std::vector<float*> cand_buf;   // per field: 6 planes (3 x CHAT, TMP) or none
 
   ~Call() {
     if (ws && hipEventRecord(ws->ev, st) == hipSuccess) ws->ev_live = true;
@@ -858,6 +867,11 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
   c.tlen = cv.take<uint32_t>(nt); c.tent = cv.take<uint32_t>(nt); c.toff = cv.take<int64_t>(nt);
   c.misfit = cv.take<int>(nt);
   c.collect = cv.take<int64_t>(8 * (size_t)c.nf);
+  c.Fc = cv.take<FieldDev>(4 * (size_t)c.nf);
+  c.cand_flags = cv.take<int>(8 * 4 * (size_t)c.nf);
+  c.cand_buf.assign(c.nf, nullptr);
+  for (int i = 0; i < c.nf; i++)
+    if (c.spec_depth > 1 && coded[i]) c.cand_buf[i] = cv.take<float>(6 * (size_t)c.Fh[i].ny * c.Fh[i].nx);
   c.d_blk_own = cv.take<Blk>(nb);
   c.d_tiles_own = cv.take<TileD>(nt);
   c.d_slot_own = cv.take<int64_t>(nt + 1);
@@ -1002,6 +1016,13 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   // every field is laid out as coded (the mode is known only on the device)
   std::vector<int> coded(nf, 1);
   build_items(c, coded);
+  // small calls evaluate two bisection levels per search round (fewer
+  // read-backs); large batches one (the device is busy anyway)
+  {
+    size_t tot = 0;
+    for (auto& f : c.Fh) tot += (size_t)f.ny * f.nx;
+    c.spec_depth = tot <= ((size_t)1 << 24) ? 2 : 1;
+  }
   c.forced_global = spiht_forced_global();
   c.need_lists = c.forced_global;
   for (int i = 0; i < nf; i++) c.need_lists |= c.plans[i]->ncls[2] > 0;
@@ -1065,7 +1086,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     if ((rc = c.collect_host(col))) return rc;
     // ---- truncation search, all fields in lockstep: one launch + one sync per round ----
     enum { NONE = 0, CHECK_ALL, BISECT, REQUANT, FOUND, FAIL };
-    std::vector<int> state(nf, NONE), att(nf, 0), lo(nf, 0), hi(nf, 0), mid(nf, 0);
+    std::vector<int> state(nf, NONE), att(nf, 0), lo(nf, 0), hi(nf, 0);
     auto start_attempt = [&](int i) {
       int q = (int)col[8 * i + 2];
       int nm = q ? 31 - __builtin_clz((unsigned)q) : -1;
@@ -1077,41 +1098,84 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
       }
       nmax[i] = nm;
       state[i] = CHECK_ALL;
-      mid[i] = nm + 1;
     };
     for (int i = 0; i < nf; i++)
       if (act[i] && col[8 * i + 0]) { resid[i] = 1; start_attempt(i); }
+    // Candidates of a round: the bisection of Algorithm 1's residual loop,
+    // spec_depth levels of its decision tree at once (all are evaluated;
+    // the decisions then follow the tree, so the result is the sequential
+    // bisection's); a field's first round also checks "all planes".
+    struct Cand { int field, k, slot; };
+    std::vector<FieldDev> Fch;
     for (int round = 0; round < 256; round++) {
-      std::vector<int> rq(nf, 0), ck(nf, 0);
-      bool anyrq = false, anyck = false;
+      std::vector<int> rq(nf, 0);
+      std::vector<Cand> cands;
+      std::vector<int> nslot(nf, 0);
+      bool anyrq = false;
+      std::function<void(int, int, int, int)> tree = [&](int i, int l, int h, int depth) {
+        if (depth == 0 || h - l <= 1) return;
+        int m = (l + h) >> 1;
+        cands.push_back(Cand{i, m, nslot[i]++});
+        tree(i, l, m, depth - 1);
+        tree(i, m, h, depth - 1);
+      };
       for (int i = 0; i < nf; i++) {
         if (state[i] == REQUANT) { rq[i] = 1; anyrq = true; }
-        if (state[i] == CHECK_ALL || state[i] == BISECT) {
-          ck[i] = 1; anyck = true;
-          c.Fh[i].ns = nmax[i] - mid[i] + 1;
+        if (state[i] == CHECK_ALL) {
+          cands.push_back(Cand{i, nmax[i] + 1, nslot[i]++});
+          if (c.spec_depth > 1) tree(i, 0, nmax[i] + 1, c.spec_depth);
+        } else if (state[i] == BISECT) {
+          tree(i, lo[i], hi[i], c.spec_depth);
         }
       }
-      if (!anyrq && !anyck) break;
+      if (!anyrq && cands.empty()) break;
       if (anyrq) {
         if ((rc = c.set_active(rq))) return rc;
         k_zero_slot<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, 1);
         k_quant_res<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
+        k_collect<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, c.collect);
       }
-      if (anyck) {
-        if ((rc = c.set_active(ck))) return rc;
-        k_zero_slot<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, 0);
-        k_dequant_res<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F);
-        dwt_inverse(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, EPI_CHECK, st);
+      const int nc = (int)cands.size();
+      if (nc) {
+        Fch.resize(nc);
+        size_t cmax = 0;
+        for (int j = 0; j < nc; j++) {
+          const Cand& q = cands[j];
+          FieldDev f = c.Fh[q.field];
+          f.active = 1;
+          f.ns = nmax[q.field] - q.k + 1;
+          f.flags = c.cand_flags + 8 * j;
+          if (q.slot > 0) {
+            size_t N = (size_t)f.ny * f.nx;
+            f.buf[BUF_CHAT] = c.cand_buf[q.field] + (size_t)(2 * (q.slot - 1)) * N;
+            f.buf[BUF_TMP] = c.cand_buf[q.field] + (size_t)(2 * (q.slot - 1) + 1) * N;
+          }
+          Fch[j] = f;
+          cmax = std::max(cmax, (size_t)f.ny * f.nx);
+        }
+        if ((rc = c.stage(c.Fc, Fch.data(), sizeof(FieldDev) * nc))) return rc;
+        k_zero_slot<<<(nc + 63) / 64, 64, 0, st>>>(c.Fc, nc, 0);
+        k_dequant_res<<<dim3(grid_for(cmax), nc), 256, 0, st>>>(c.Fc);
+        dwt_inverse(c.Fc, Fch.data(), nc, BUF_CHAT, BUF_CHAT, EPI_CHECK, st);
       }
       HIPCHK(hipGetLastError());
-      if ((rc = c.collect_host(col))) return rc;
+      std::vector<int> cf(8 * (size_t)std::max(nc, 1));
+      if (anyrq) {
+        col.resize(8 * (size_t)nf);
+        HIPCHK(hipMemcpyAsync(col.data(), c.collect, sizeof(int64_t) * col.size(), hipMemcpyDeviceToHost, st));
+      }
+      if ((rc = c.fetch(cf.data(), c.cand_flags, 8 * (size_t)std::max(nc, 1)))) return rc;
+      // results per field: truncation point -> bound met
+      std::vector<std::map<int, bool>> res(nf);
+      for (int j = 0; j < nc; j++) {
+        res[cands[j].field][cands[j].k] = cf[8 * j] == 0;
+        checks[cands[j].field]++;
+      }
       for (int i = 0; i < nf; i++) {
         if (rq[i]) { start_attempt(i); continue; }
-        if (!ck[i]) continue;
-        checks[i]++;
-        bool ok = col[8 * i + 0] == 0;
+        if (state[i] != CHECK_ALL && state[i] != BISECT) continue;
         if (state[i] == CHECK_ALL) {
-          if (!ok) {
+          if (!res[i][nmax[i] + 1]) {
             if (++att[i] >= 5) { state[i] = FAIL; continue; }
             state[i] = REQUANT;
             c.Fh[i].er = fps[i].elog - 6 - att[i];
@@ -1119,11 +1183,14 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
           }
           lo[i] = 0; hi[i] = nmax[i] + 1;
           state[i] = BISECT;
-        } else {
-          if (ok) hi[i] = mid[i]; else lo[i] = mid[i];
         }
-        if (hi[i] - lo[i] > 1) mid[i] = (lo[i] + hi[i]) >> 1;
-        else { state[i] = FOUND; c.Fh[i].ns = nmax[i] - hi[i] + 1; }
+        while (hi[i] - lo[i] > 1) {
+          int m = (lo[i] + hi[i]) >> 1;
+          auto it = res[i].find(m);
+          if (it == res[i].end()) break;
+          if (it->second) hi[i] = m; else lo[i] = m;
+        }
+        if (hi[i] - lo[i] <= 1) { state[i] = FOUND; c.Fh[i].ns = nmax[i] - hi[i] + 1; }
       }
     }
     prof.mark(S_SEARCH);

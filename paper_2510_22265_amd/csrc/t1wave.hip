@@ -144,6 +144,10 @@ __device__ __forceinline__ M neighbour_mask(M sig, int lane) {
   return (sig << 1) | (sig >> 1) | v | (v << 1) | (v >> 1);
 }
 
+__device__ __forceinline__ uint64_t lane_ptr(uint32_t pv, int i) {
+  return (uint64_t)rdl32(pv, 2 * i) | ((uint64_t)rdl32(pv, 2 * i + 1) << 32);
+}
+
 // Bits x-1, x, x+1 of a row mask as bits 0, 1, 2 (0 outside the row), and
 // the neighbourhood counts of T.800 Table D.1 from three such fields.
 template <typename M>
@@ -187,6 +191,18 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
   int32_t* BPk = bpt + (size_t)b * kPassStride;
   uint32_t* TL = tailt + (size_t)b * kPassStride;
   M* spo = sppf + (size_t)b * cbh;
+  // per-block table pointers used once per pass live in lanes of one vector
+  // register (lane 2i / 2i+1: low / high half of pointer i)
+  uint32_t pv = 0;
+  {
+    const uint64_t pp[5] = {(uint64_t)R, (uint64_t)Dd, (uint64_t)BPk, (uint64_t)TL,
+                            (uint64_t)(planes + (size_t)b * kQBits * cbh)};
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+      if (lane == 2 * i) pv = (uint32_t)pp[i];
+      if (lane == 2 * i + 1) pv = (uint32_t)(pp[i] >> 32);
+    }
+  }
   if (lane == 0) { R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0; }
   if (P == 0) {
     if (lane < h) spo[lane] = 0;
@@ -213,7 +229,7 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
   auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
 
   for (int p = P - 1; p >= 0 && !stop; p--) {
-    mag = lane < h ? planes[((size_t)b * kQBits + p) * cbh + lane] : (M)0;
+    mag = lane < h ? ((const M*)lane_ptr(pv, 4))[(size_t)p * cbh + lane] : (M)0;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
       nsig = 0;
       M refd = sig & ~vis;          // MRP refines every sample significant before this plane
@@ -382,7 +398,13 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
       Dcum += dd;
       uint32_t tail;
       int rk = mqw_flush_copy(e, &tail);
-      if (lane == 0) { R[kk] = rk; Dd[kk] = Dcum; BPk[kk] = e.BP; TL[kk] = tail; }
+      if (lane == 0) {
+        int32_t* Rp = (int32_t*)lane_ptr(pv, 0);
+        int64_t* Dp = (int64_t*)lane_ptr(pv, 1);
+        int32_t* Bp = (int32_t*)lane_ptr(pv, 2);
+        uint32_t* Tp = (uint32_t*)lane_ptr(pv, 3);
+        Rp[kk] = rk; Dp[kk] = Dcum; Bp[kk] = e.BP; Tp[kk] = tail;
+      }
     }
   }
   if (lane == 0)
