@@ -1254,9 +1254,9 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   if ((rc = c.set_active(act))) return rc;
   if (any) {
     k_put_blocks<<<grid_for(c.nblk), 256, 0, st>>>(c.F, c.d_blk, c.bent, c.nblk);
-    k_gather_cw<<<grid_for(c.nblk), 256, 0, st>>>(c.F, c.d_blk, c.cw, c.kb, c.len, c.bpt, c.tail, c.boff, c.nblk);
+    k_gather_cw<<<std::max(1, (c.nblk + 3) / 4), 256, 0, st>>>(c.F, c.d_blk, c.cw, c.kb, c.len, c.bpt, c.tail, c.boff, c.nblk);
     k_put_tiles<<<grid_for(c.ntiles), 256, 0, st>>>(c.F, c.d_tiles, c.tent, c.ntiles);
-    k_gather_tiles<<<grid_for(c.ntiles), 256, 0, st>>>(c.F, c.d_tiles, c.slots, c.d_slot_off, c.tlen, c.toff, c.ntiles);
+    k_gather_tiles<<<std::max(1, (c.ntiles + 3) / 4), 256, 0, st>>>(c.F, c.d_tiles, c.slots, c.d_slot_off, c.tlen, c.toff, c.ntiles);
   }
   std::vector<int> rawm(nf, 0);
   bool anyraw = false;

@@ -77,10 +77,11 @@ __device__ __forceinline__ void epilogue(float* __restrict__ out, int idx, float
   a = a * sc.range;
   float xh = sc.xmin + a;
   if (EPI == EPI_FINAL) { f.buf[BUF_XOUT][idx] = xh; return; }
-  // one atomic per wavefront that sees a violation
+  // one atomic per wavefront that sees a violation, skipped once the flag
+  // is known to be set
   const bool bad = fabs((double)f.buf[BUF_X][idx] - (double)xh) > sc.eps;
   const unsigned long long m = __ballot(bad);
-  if (bad && (int)__lane_id() == __builtin_ctzll(m)) atomicOr(&f.flags[0], 1);
+  if (bad && (int)__lane_id() == __builtin_ctzll(m) && *(volatile const int*)f.flags == 0) atomicOr(&f.flags[0], 1);
 }
 
 // One lifting step along the first LDS index (rows) of a column tile.
@@ -140,6 +141,15 @@ template <int EPI>
 __global__ __launch_bounds__(256) void k_inv_cols(const FieldDev* __restrict__ F, int l, int a, int out) {
   const FieldDev& f = F[blockIdx.z];
   if (!f.active || l > f.L) return;
+  // a bound check only answers "is any sample violated": once the flag is
+  // set the rest of the pass is moot (the flag only goes from 0 to 1).  One
+  // thread reads it so that the whole workgroup takes the same branch.
+  if (EPI == EPI_CHECK && l == 1) {
+    __shared__ int s_done;
+    if (threadIdx.x == 0) s_done = *(volatile const int*)f.flags;
+    __syncthreads();
+    if (s_done) return;
+  }
   const int nx = f.nx, H = lvl_size(f.ny, l), W = lvl_size(f.nx, l);
   int c0 = blockIdx.x * kColTileC, r0 = blockIdx.y * kColTileR;
   if (c0 >= W || r0 >= H) return;
@@ -279,6 +289,7 @@ template <int PRO, int EPI>
 __global__ __launch_bounds__(256) void k_pointwise(const FieldDev* __restrict__ F, int src, int dst, int lzero) {
   const FieldDev& f = F[blockIdx.y];
   if (!f.active || (lzero && f.L != 0)) return;
+  if (EPI == EPI_CHECK && *(volatile const int*)f.flags) return;   // violation already found
   const int n = f.ny * f.nx;
   Scal sc = load_scal(f.fp);
   const float* sp = f.buf[src];

@@ -11,7 +11,8 @@
 //     order until the first one that would overflow the byte budget.  The
 //     first non-fitting segment is found by a radix select over the 104-bit
 //     key (8-bit digits, LDS histograms of segment lengths), so no sort is
-//     materialised;
+//     materialised; after two digits the few segments still in play move
+//     to LDS;
 //  3. one thread per block keeps the segments whose key is above the
 //     threshold and writes k_b and the codeword length R_{k_b}.
 #include "common.h"
@@ -19,6 +20,7 @@
 namespace ebcc {
 
 constexpr int kPcrdThreads = 1024;
+constexpr int kPcrdCand = 2048;    // LDS candidates after the first two digits
 
 __device__ __forceinline__ double seg_slope(int64_t dD, int64_t dR) {
   return dR <= 0 ? __longlong_as_double(0x7ff0000000000000ll) : (double)dD / (double)dR;
@@ -36,6 +38,9 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
                                                        uint64_t* __restrict__ keys_g, int32_t* __restrict__ dr_g,
                                                        uint8_t* __restrict__ nhv_g, int32_t* __restrict__ len_g) {
   __shared__ unsigned long long hist[256];
+  __shared__ uint64_t c_hi[kPcrdCand], c_lo[kPcrdCand];
+  __shared__ uint32_t c_dr[kPcrdCand];
+  __shared__ int s_cnt;
   __shared__ int s_choice;
   __shared__ int s_allfit;
   __shared__ unsigned long long s_acc;
@@ -85,21 +90,35 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
     }
   }
   __syncthreads();
-  // 2. radix select of the first segment that does not fit
+  // 2. radix select of the first segment that does not fit.  The first two
+  // digits scan every segment in global memory; the segments that still
+  // match the selected prefix are then copied to LDS (when they fit) and the
+  // remaining digits scan only those.
   u128 prefix = 0;
   unsigned long long acc = 0;
   bool allfit = false;
+  int ncand = -1;   // LDS candidate count (-1: not compacted)
   for (int dgt = 0; dgt < 13; dgt++) {
     for (int i = tid; i < 256; i += kPcrdThreads) hist[i] = 0;
+    if (tid == 0) s_cnt = 0;
     __syncthreads();
     int sh = 104 - 8 * (dgt + 1);
-    for (int b = tid; b < nblk; b += kPcrdThreads) {
-      int nh = nhv[b];
-      for (int j = 1; j < nh; j++) {
-        u128 key = seg_key(keys[(size_t)b * kPassStride + j], b, j);
+    if (ncand < 0) {
+      for (int b = tid; b < nblk; b += kPcrdThreads) {
+        int nh = nhv[b];
+        for (int j = 1; j < nh; j++) {
+          u128 key = seg_key(keys[(size_t)b * kPassStride + j], b, j);
+          if (dgt > 0 && (key >> (sh + 8)) != prefix) continue;
+          int dg = (int)((key >> sh) & 0xFF);
+          atomicAdd(&hist[dg], (unsigned long long)dr[(size_t)b * kPassStride + j]);
+        }
+      }
+    } else {
+      for (int q = tid; q < ncand; q += kPcrdThreads) {
+        u128 key = ((u128)c_hi[q] << 40) | (u128)c_lo[q];
         if (dgt > 0 && (key >> (sh + 8)) != prefix) continue;
         int dg = (int)((key >> sh) & 0xFF);
-        atomicAdd(&hist[dg], (unsigned long long)dr[(size_t)b * kPassStride + j]);
+        atomicAdd(&hist[dg], (unsigned long long)c_dr[q]);
       }
     }
     __syncthreads();
@@ -118,6 +137,24 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
     if (s_allfit) { allfit = true; break; }
     prefix = (prefix << 8) | (u128)s_choice;
     acc = s_acc;
+    if (dgt == 1 && ncand < 0) {
+      // compact the segments that match the 16-bit prefix into LDS
+      for (int b = tid; b < nblk; b += kPcrdThreads) {
+        int nh = nhv[b];
+        for (int j = 1; j < nh; j++) {
+          u128 key = seg_key(keys[(size_t)b * kPassStride + j], b, j);
+          if ((key >> sh) != prefix) continue;
+          int q = atomicAdd(&s_cnt, 1);
+          if (q < kPcrdCand) {
+            c_hi[q] = (uint64_t)(key >> 40);
+            c_lo[q] = (uint64_t)(key & (((u128)1 << 40) - 1));
+            c_dr[q] = (uint32_t)dr[(size_t)b * kPassStride + j];
+          }
+        }
+      }
+      __syncthreads();
+      if (s_cnt <= kPcrdCand) ncand = s_cnt;
+    }
     __syncthreads();
   }
   // 3. kept passes per block: every segment with key above the threshold
