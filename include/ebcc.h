@@ -102,7 +102,7 @@ int ebcc_decompress(const uint8_t* d_in, size_t in_len, float* d_x, size_t ny, s
  * lockstep (one launch and one read-back per search round for the batch).
  * Each field's stream is byte-identical to what ebcc_compress /
  * ebcc_decompress produce for it alone.  Large batches are processed in
- * chunks of at most 2^26 samples or 4096 fields.
+ * chunks of at most 2^27 samples or 4096 fields.
  * ------------------------------------------------------------------------- */
 
 /* Compress n fields.
@@ -185,8 +185,8 @@ const char* ebcc_profile_stage_name(int i);
  *   t1_encoder, t1_decoder  0 = by work size, 1 = one wavefront per
  *                           code-block (latency), 2 = several code-blocks per
  *                           wavefront, one per lane (throughput)
- *   t1_wave_max             by work size: the encoder keeps one wavefront per
- *                           code-block up to this many code-blocks per call
+ *   t1_wave_max             by work size: one wavefront per code-block up to
+ *                           this many code-blocks in a launch, lanes beyond
  *   spiht                   0 = SPIHT tiles in LDS (by capacity class, the
  *                           largest tiles with global-memory lists), 1 =
  *                           global-memory lists for every tile

@@ -700,7 +700,7 @@ static int grow_ws(WS* w, size_t need, size_t pin_need, hipStream_t st, char** b
 }
 
 // Batches are processed in chunks of at most this many samples or fields.
-constexpr size_t kChunkSamples = size_t(1) << 26;
+constexpr size_t kChunkSamples = size_t(1) << 27;
 constexpr int kChunkFields = 4096;
 
 // Full-field sweeps that reduce: about 16 elements per thread, at most 1024

@@ -127,7 +127,7 @@ void t1_decode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, const 
 struct Tuning {
   int t1_encoder;    // 0 by work size, 1 wave per code-block, 2 lanes per code-block
   int t1_decoder;    // same
-  int t1_wave_max;   // by work size: the encoder uses a wave per block up to this many blocks
+  int t1_wave_max;   // by work size: a wave per block up to this many blocks, lanes beyond
   int spiht;         // 0 LDS kernels by capacity class, 1 global-memory lists for every tile
 };
 Tuning tuning();

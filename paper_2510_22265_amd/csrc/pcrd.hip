@@ -105,12 +105,24 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
     int sh = 104 - 8 * (dgt + 1);
     if (ncand < 0) {
       for (int b = tid; b < nblk; b += kPcrdThreads) {
-        int nh = nhv[b];
-        for (int j = 1; j < nh; j++) {
-          u128 key = seg_key(keys[(size_t)b * kPassStride + j], b, j);
-          if (dgt > 0 && (key >> (sh + 8)) != prefix) continue;
-          int dg = (int)((key >> sh) & 0xFF);
-          atomicAdd(&hist[dg], (unsigned long long)dr[(size_t)b * kPassStride + j]);
+        const int nh = nhv[b];
+        const uint64_t* kp = keys + (size_t)b * kPassStride;
+        const int32_t* dp = dr + (size_t)b * kPassStride;
+        for (int j0 = 1; j0 < nh; j0 += 4) {
+          uint64_t kk[4];
+          int32_t dd[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++)   // independent loads first
+            if (j0 + u < nh) { kk[u] = kp[j0 + u]; dd[u] = dp[j0 + u]; }
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const int j = j0 + u;
+            if (j >= nh) break;
+            u128 key = seg_key(kk[u], b, j);
+            if (dgt > 0 && (key >> (sh + 8)) != prefix) continue;
+            int dg = (int)((key >> sh) & 0xFF);
+            atomicAdd(&hist[dg], (unsigned long long)dd[u]);
+          }
         }
       }
     } else {
@@ -140,15 +152,27 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
     if (dgt == 1 && ncand < 0) {
       // compact the segments that match the 16-bit prefix into LDS
       for (int b = tid; b < nblk; b += kPcrdThreads) {
-        int nh = nhv[b];
-        for (int j = 1; j < nh; j++) {
-          u128 key = seg_key(keys[(size_t)b * kPassStride + j], b, j);
-          if ((key >> sh) != prefix) continue;
-          int q = atomicAdd(&s_cnt, 1);
-          if (q < kPcrdCand) {
-            c_hi[q] = (uint64_t)(key >> 40);
-            c_lo[q] = (uint64_t)(key & (((u128)1 << 40) - 1));
-            c_dr[q] = (uint32_t)dr[(size_t)b * kPassStride + j];
+        const int nh = nhv[b];
+        const uint64_t* kp = keys + (size_t)b * kPassStride;
+        const int32_t* dp = dr + (size_t)b * kPassStride;
+        for (int j0 = 1; j0 < nh; j0 += 4) {
+          uint64_t kk[4];
+          int32_t dd[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++)
+            if (j0 + u < nh) { kk[u] = kp[j0 + u]; dd[u] = dp[j0 + u]; }
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const int j = j0 + u;
+            if (j >= nh) break;
+            u128 key = seg_key(kk[u], b, j);
+            if ((key >> sh) != prefix) continue;
+            int q = atomicAdd(&s_cnt, 1);
+            if (q < kPcrdCand) {
+              c_hi[q] = (uint64_t)(key >> 40);
+              c_lo[q] = (uint64_t)(key & (((u128)1 << 40) - 1));
+              c_dr[q] = (uint32_t)dd[u];
+            }
           }
         }
       }

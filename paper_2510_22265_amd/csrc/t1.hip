@@ -708,16 +708,17 @@ void quant_planes(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh,
     k_quant_planes<uint64_t><<<g, 256, 0, st>>>(F, blk, nblk, cbw, cbh, (uint64_t*)planes, (uint64_t*)signs, pb);
 }
 
-// By work size: the encoder uses a wave per block up to Tuning::t1_wave_max
-// blocks (latency) and lanes per block beyond (throughput); the
-// wave-per-block decoder was the faster one at every batch size measured.
+// By work size: a wave per block up to Tuning::t1_wave_max blocks in the
+// launch (latency: one field's blocks spread over the whole chip), lanes per
+// block beyond (throughput: the 256-field batch encodes 1.5x and decodes
+// 1.2x faster that way).
 static bool use_wave(int nblk, bool decode) {
   const char* e = getenv("EBCC_T1_KERNEL");
   if (e && e[0] == 'w') return true;
   if (e && e[0] == 'l') return false;
   Tuning t = tuning();
   int v = decode ? t.t1_decoder : t.t1_encoder;
-  return v == 1 || (v == 0 && (decode || nblk <= t.t1_wave_max));
+  return v == 1 || (v == 0 && nblk <= t.t1_wave_max);
 }
 
 void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes, const void* signs,
