@@ -58,8 +58,10 @@ typedef struct {
                              (range-relative, Benchmarks section); EBCC_BOUND_ABS: absolute */
   double err_bound;       /* > 0 and finite */
   double base_ratio;      /* r >= 1: header + base section <= floor(4 * ny * nx / r) bytes */
-  double q;               /* 0: fixed base ratio (implemented).  Other values select the
-                             q-quantile feedback search of Algorithm 1: EBCC_ENOTIMPL. */
+  double q;               /* 0: the base layer runs at base_ratio.  q in (0, 1]: Algorithm 1's
+                             feedback search from r0 = base_ratio for the ratio at which the
+                             proportion q of samples meets the bound in the base alone (the
+                             paper uses 1 - 1e-5), plus its base-only fallback.  Else EINVAL. */
   uint32_t levels;        /* DWT levels (default 5), clamped to floor(log2(min(ny, nx))) */
   uint32_t cblk_log2w;    /* code-block width  = 2^cblk_log2w, 2..6 (default 5) */
   uint32_t cblk_log2h;    /* code-block height = 2^cblk_log2h, 2..6 (default 5); w*h <= 4096 */

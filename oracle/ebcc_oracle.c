@@ -757,7 +757,8 @@ static int seg_cmp(const void* pa, const void* pb) {
  * segment first) are accepted while the running length stays within the
  * budget; the first that does not fit ends the allocation.  kb[b] = passes
  * kept in block b.  R and D are [nblk][stride]. */
-static long pcrd(int nblk, const int* npass, const int32_t* R, const int64_t* D, int stride, long budget, uint8_t* kb) {
+static long pcrd_af(int nblk, const int* npass, const int32_t* R, const int64_t* D, int stride, long budget,
+                    uint8_t* kb, int* allfit) {
   seg_t* segs = (seg_t*)malloc(sizeof(seg_t) * (size_t)(nblk * stride + 1));
   int* hull = (int*)malloc(sizeof(int) * (size_t)(stride + 1));
   long ns = 0;
@@ -773,14 +774,18 @@ static long pcrd(int nblk, const int* npass, const int32_t* R, const int64_t* D,
     }
   }
   qsort(segs, (size_t)ns, sizeof(seg_t), seg_cmp);
-  long used = 0;
-  for (long i = 0; i < ns; i++) {
+  long used = 0, i = 0;
+  for (; i < ns; i++) {
     if (used + segs[i].dR > budget) break;
     used += segs[i].dR;
     kb[segs[i].b] = (uint8_t)segs[i].hk;
   }
+  if (allfit) *allfit = (i == ns);
   free(segs); free(hull);
   return used;
+}
+static long pcrd(int nblk, const int* npass, const int32_t* R, const int64_t* D, int stride, long budget, uint8_t* kb) {
+  return pcrd_af(nblk, npass, R, D, stride, budget, kb, NULL);
 }
 EXPORT long ebcc_ref_pcrd(int nblk, const int* npass, const int32_t* R, const int64_t* D, int stride, long budget, uint8_t* kb) {
   return pcrd(nblk, npass, R, D, stride, budget, kb);
@@ -1199,6 +1204,117 @@ static int layout_init(layout_t* ly, long ny, long nx, int L, int cbl2w, int cbl
 
 EXPORT size_t ebcc_ref_compress_bound(size_t ny, size_t nx) { return HDR_BYTES + 4 * ny * nx; }
 
+/* ---------------------------------------------------------------------- */
+/* enc_base at a ratio r, and Algorithm 1's feedback search over r.        */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  const layout_t* ly;
+  const int* np; const int32_t* R; const int64_t* D; int stride;
+  mqe_t* saved; long (*sbp)[3 * QMAX_BITS]; uint8_t (*stail)[3 * QMAX_BITS][3];
+  const uint8_t* pbv; int e0;
+  const float* x; float xmin, range_f; double eps; long N;
+  uint8_t* kb; uint8_t** cw; long* cwlen; float* abase;
+  int evals;
+} basectx_t;
+
+/* Optional log of every enc_base evaluation (test hook): ratio, q_A (NaN
+ * when not computed), whether every segment fitted, budget. */
+static double* g_log_r; static double* g_log_q; static int* g_log_af; static long* g_log_bud;
+static int g_log_cap, g_log_n;
+EXPORT int ebcc_ref_alg1_log(double* r, double* q, int* af, long* bud, int cap) {
+  int n = g_log_n;
+  g_log_r = r; g_log_q = q; g_log_af = af; g_log_bud = bud; g_log_cap = r ? cap : 0; g_log_n = 0;
+  return n;
+}
+
+/* Base payload budget for ratio r: header + block table + codewords fit
+ * floor(4 N / r) bytes. */
+static long base_budget(long N, long nblk, double r) {
+  long t = (long)floor((double)(4 * N) / r) - HDR_BYTES - 4 * nblk;
+  return t < 0 ? 0 : t;
+}
+
+/* enc_base(A, r) followed by dec_base: PCRD at r, the terminated codewords,
+ * the decoded base (normalised domain) in c->abase.  Returns the payload. */
+static long base_at(basectx_t* c, double r, int* allfit, long* budget) {
+  long nblk = c->ly->nblk;
+  long bud = base_budget(c->N, nblk, r);
+  if (budget) *budget = bud;
+  long used = pcrd_af((int)nblk, c->np, c->R, c->D, c->stride, bud, c->kb, allfit);
+  for (long b = 0; b < nblk; b++) {
+    t1enc_t tmp; tmp.e = c->saved[b];
+    memcpy(tmp.bp, c->sbp[b], sizeof(tmp.bp)); memcpy(tmp.tail, c->stail[b], sizeof(tmp.tail));
+    for (int j = 0; j <= c->np[b]; j++) tmp.R[j] = c->R[b * c->stride + j];
+    free(c->cw[b]);
+    c->cwlen[b] = c->kb[b] ? c->R[b * c->stride + c->kb[b]] : 0;
+    c->cw[b] = (uint8_t*)malloc((size_t)c->cwlen[b] + 1);
+    t1_codeword(&tmp, c->kb[b], c->cw[b]);
+  }
+  base_decode(c->ly, c->e0, c->pbv, c->kb, (const uint8_t* const*)c->cw, c->cwlen, c->abase);
+  c->evals++;
+  if (g_log_n < g_log_cap) {
+    int allfit_v = 0;
+    if (allfit) allfit_v = *allfit;
+    g_log_r[g_log_n] = r; g_log_q[g_log_n] = NAN; g_log_af[g_log_n] = allfit_v; g_log_bud[g_log_n] = bud;
+  }
+  g_log_n++;
+  return used;
+}
+
+/* q_A: the proportion of samples whose base-layer error does not exceed
+ * eps (Algorithm 1, enc_base). */
+static double base_quality(const basectx_t* c) {
+  long n = 0;
+  for (long i = 0; i < c->N; i++) {
+    float xh = denorm(c->abase[i], 0.0f, c->xmin, c->range_f);
+    if (fabs((double)c->x[i] - (double)xh) <= c->eps) n++;
+  }
+  double qa = (double)n / (double)c->N;
+  if (g_log_n >= 1 && g_log_n - 1 < g_log_cap) g_log_q[g_log_n - 1] = qa;
+  return qa;
+}
+
+/* Algorithm 1's choice of the base ratio for proportion q, starting from r0:
+ * halve r while q_A < q, else double it while q_A > q, then bisect until the
+ * bracket is narrower than 1e-3 and keep the largest ratio seen with
+ * q_A >= q.  Two guards the algorithm leaves open: halving stops once every
+ * codable pass is kept (a smaller ratio cannot change the base), doubling
+ * stops once the budget is zero.  Returns the ratio; *q_out = its q_A. */
+static double alg1_ratio(basectx_t* c, double q, double r0, double* q_out) {
+  int allfit; long bud;
+  base_at(c, r0, &allfit, &bud);
+  double qa0 = base_quality(c), qa = qa0, q_f = qa0;
+  double r_low = r0, r_high = r0, r_f = r0;
+  int guard = allfit;
+  while (qa < q && !guard) {
+    r_low = r_low / 2.0;
+    base_at(c, r_low, &allfit, &bud);
+    qa = base_quality(c);
+    r_f = r_low; q_f = qa;
+    guard = allfit;
+  }
+  qa = qa0;
+  long bud0 = base_budget(c->N, c->ly->nblk, r0);
+  int zero = bud0 == 0;
+  while (qa > q && !zero) {
+    r_high = r_high * 2.0;
+    base_at(c, r_high, &allfit, &bud);
+    qa = base_quality(c);
+    zero = bud == 0;
+  }
+  while (r_high - r_low > 1e-3) {
+    double r_mid = (r_low + r_high) / 2.0;
+    base_at(c, r_mid, &allfit, &bud);
+    qa = base_quality(c);
+    if (qa < q) r_high = r_mid;
+    else { r_low = r_mid; r_f = r_mid; q_f = qa; }
+  }
+  if (q_out) *q_out = q_f;
+  return r_f;
+}
+
+EXPORT long ebcc_ref_base_budget(long N, long nblk, double r) { return base_budget(N, nblk, r); }
+
 /* Compress a 2-D float32 field.
  *   bound_mode 0: err_bound is range-relative (eps = err_bound * (max - min));
  *   bound_mode 1: err_bound is absolute.
@@ -1206,12 +1322,13 @@ EXPORT size_t ebcc_ref_compress_bound(size_t ny, size_t nx) { return HDR_BYTES +
  *   header fits floor(4 N / r) bytes.
  * Returns 0 and the stream length, or a negative status. */
 EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, double err_bound, int bound_mode,
-                                   double base_ratio, int levels, int cbl2w, int cbl2h, int tile,
+                                   double base_ratio, double q, int levels, int cbl2w, int cbl2h, int tile,
                                    uint8_t* out, size_t cap, size_t* out_len, ebcc_ref_trace* tr) {
   long ny = (long)ny_, nx = (long)nx_;
   if (out_len) *out_len = 0;
   if (ny < 1 || nx < 1 || ny > (1L << 24) || nx > (1L << 24) || ny * nx > (1L << 31) - 1) return REF_EINVAL;
   if (!(err_bound > 0) || !isfinite(err_bound) || !(base_ratio >= 1.0) || !isfinite(base_ratio)) return REF_EINVAL;
+  if (!(q >= 0.0 && q <= 1.0)) return REF_EINVAL;
   if (levels < 0 || levels > MAX_LEVELS || cbl2w < 2 || cbl2h < 2 || cbl2w > 6 || cbl2h > 6 || tile < 1 || tile > 64)
     return REF_EINVAL;
   long N = ny * nx;
@@ -1289,25 +1406,26 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
       for (int j = 0; j <= te->npass; j++) { R[b * stride + j] = te->R[j]; D[b * stride + j] = te->D[j]; }
       saved[b] = te->e; memcpy(sbp[b], te->bp, sizeof(te->bp)); memcpy(stail[b], te->tail, sizeof(te->tail));
     }
-    long total_budget = (long)floor((double)(4 * N) / base_ratio);
-    long budget = total_budget - HDR_BYTES - 4 * ly.nblk;
-    if (budget < 0) budget = 0;
-    base_payload = pcrd((int)ly.nblk, np, R, D, stride, budget, kbv);
-    for (long b = 0; b < ly.nblk; b++) {
-      t1enc_t tmp; tmp.e = saved[b];
-      memcpy(tmp.bp, sbp[b], sizeof(tmp.bp)); memcpy(tmp.tail, stail[b], sizeof(tmp.tail));
-      for (int j = 0; j <= np[b]; j++) tmp.R[j] = R[b * stride + j];
-      cwlen[b] = kbv[b] ? R[b * stride + kbv[b]] : 0;
-      cw[b] = (uint8_t*)malloc((size_t)cwlen[b] + 1);
-      t1_codeword(&tmp, kbv[b], cw[b]);
-      free(saved[b].raw);
+    basectx_t bc = {&ly, np, R, D, stride, saved, sbp, stail, pbv, e0, x, xmin, range_f, eps, N,
+                    kbv, cw, cwlen, abase, 0};
+    /* base ratio: the given r (q = 0), or Algorithm 1's feedback search for
+     * proportion q from r0 = r, plus the base-only search (q = 1) for the
+     * final fallback */
+    double r_use = base_ratio, r_only = -1.0;
+    if (q > 0.0) {
+      double qf;
+      r_use = alg1_ratio(&bc, q, base_ratio, &qf);
+      if (q < 1.0) {
+        double q1;
+        double r1 = alg1_ratio(&bc, 1.0, base_ratio, &q1);
+        if (q1 >= 1.0) r_only = r1;            /* the base alone meets the bound */
+      }
     }
-    free(saved); free(sbp); free(stail); free(te); free(qb); free(nb); free(R); free(D); free(np);
+    base_payload = base_at(&bc, r_use, NULL, NULL);
     if (tr && tr->kb) memcpy(tr->kb, kbv, (size_t)ly.nblk);
     if (tr && tr->pb) memcpy(tr->pb, pbv, (size_t)ly.nblk);
 
     /* ---- A_base = dec_base(e_base); residual = A - A_base; W = DWT ---- */
-    base_decode(&ly, e0, pbv, kbv, (const uint8_t* const*)cw, cwlen, abase);
     if (tr && tr->abase) memcpy(tr->abase, abase, sizeof(float) * (size_t)N);
     for (long i = 0; i < N; i++) cres[i] = a[i] - abase[i];
     dwt2_f(cres, ny, nx, ly.L, 0);
@@ -1355,6 +1473,24 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
       free(qr); free(ngr);
       if (!found) mode = MODE_RAW;
     }
+    /* fallback (end of Algorithm 1): the base alone at its own ratio when
+     * that stream is smaller */
+    if (r_only >= 0.0) {
+      uint8_t* kb1 = (uint8_t*)calloc((size_t)ly.nblk, 1);
+      long pay1 = pcrd((int)ly.nblk, np, R, D, stride, base_budget(N, ly.nblk, r_only), kb1);
+      free(kb1);
+      long ebcc_total = (mode == MODE_CODED) ? base_payload + resid_bytes : 4 * N;
+      if (pay1 < ebcc_total) {
+        base_payload = base_at(&bc, r_only, NULL, NULL);
+        mode = MODE_CODED;
+        er_final = 0; nmax_final = -1; ns_final = 0; resid_bytes = 0;
+        free(resid); resid = NULL;
+        if (tr && tr->kb) memcpy(tr->kb, kbv, (size_t)ly.nblk);
+        if (tr && tr->abase) memcpy(tr->abase, abase, sizeof(float) * (size_t)N);
+      }
+    }
+    for (long b = 0; b < ly.nblk; b++) free(saved[b].raw);
+    free(saved); free(sbp); free(stail); free(te); free(qb); free(nb); free(R); free(D); free(np);
   }
 
   size_t total;
@@ -1397,9 +1533,9 @@ done:
 }
 
 EXPORT int ebcc_ref_compress(const float* x, size_t ny, size_t nx, double err_bound, int bound_mode,
-                             double base_ratio, int levels, int cbl2w, int cbl2h, int tile,
+                             double base_ratio, double q, int levels, int cbl2w, int cbl2h, int tile,
                              uint8_t* out, size_t cap, size_t* out_len) {
-  return ebcc_ref_compress_trace(x, ny, nx, err_bound, bound_mode, base_ratio, levels, cbl2w, cbl2h, tile,
+  return ebcc_ref_compress_trace(x, ny, nx, err_bound, bound_mode, base_ratio, q, levels, cbl2w, cbl2h, tile,
                                  out, cap, out_len, NULL);
 }
 

@@ -41,8 +41,11 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.ebcc_ref_compress_trace.argtypes = [P, C.c_size_t, C.c_size_t, C.c_double, C.c_int, C.c_double,
-                                              C.c_int, C.c_int, C.c_int, C.c_int, P, C.c_size_t,
+                                              C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, P, C.c_size_t,
                                               C.POINTER(C.c_size_t), P]
+        L.ebcc_ref_base_budget.argtypes = [C.c_long, C.c_long, C.c_double]
+        L.ebcc_ref_base_budget.restype = C.c_long
+        L.ebcc_ref_alg1_log.argtypes = [P, P, P, P, C.c_int]
         L.ebcc_ref_decompress.argtypes = [P, C.c_size_t, P, C.c_size_t, C.c_size_t]
         L.ebcc_ref_compress_bound.argtypes = [C.c_size_t, C.c_size_t]
         L.ebcc_ref_compress_bound.restype = C.c_size_t
@@ -97,7 +100,7 @@ def n_blocks(ny, nx, levels=5, cbl2w=5, cbl2h=5):
     return n
 
 
-def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, trace=False):
+def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, trace=False, q=0.0):
     """Compress a 2-D float32 field.  Returns bytes (and a dict of
     intermediate results when ``trace`` is true)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
@@ -114,7 +117,7 @@ def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl
                     cres=np.zeros((ny, nx), np.float32), kb=np.zeros(nb, np.uint8), pb=np.zeros(nb, np.uint8),
                     info=np.zeros(11, np.int32))
         tr = Trace(*[_p(bufs[k]).value for k in ("coef", "abase", "cres", "kb", "pb", "info")])
-    rc = L.ebcc_ref_compress_trace(_p(x), ny, nx, float(err_bound), int(bound_mode), float(base_ratio),
+    rc = L.ebcc_ref_compress_trace(_p(x), ny, nx, float(err_bound), int(bound_mode), float(base_ratio), float(q),
                                    int(levels), int(cbl2w), int(cbl2h), int(tile), _p(out), cap, C.byref(n),
                                    C.byref(tr) if tr is not None else None)
     if rc != OK:
@@ -129,7 +132,7 @@ def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl
     return s
 
 
-def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, cap=None):
+def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, cap=None, q=0.0):
     """Raw status-code form for error-path tests: returns (rc, bytes or None, out_len)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     ny, nx = x.shape if x.ndim == 2 else (x.size, 1)
@@ -138,9 +141,23 @@ def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, 
         cap = L.ebcc_ref_compress_bound(max(ny, 1), max(nx, 1))
     out = np.zeros(max(cap, 1), dtype=np.uint8)
     n = C.c_size_t(0)
-    rc = L.ebcc_ref_compress_trace(_p(x), ny, nx, float(err_bound), int(bound_mode), float(base_ratio),
+    rc = L.ebcc_ref_compress_trace(_p(x), ny, nx, float(err_bound), int(bound_mode), float(base_ratio), float(q),
                                    int(levels), int(cbl2w), int(cbl2h), int(tile), _p(out), cap, C.byref(n), None)
     return rc, (out[: n.value].tobytes() if rc == OK else None), n.value
+
+
+def compress_logged(x, err_bound, q, base_ratio=30.0, cap=4096, **kw):
+    """Compress with the enc_base log on: returns (stream, list of
+    (ratio, q_A or nan, every segment fitted, budget)) in evaluation order."""
+    L = lib()
+    r = np.zeros(cap); qa = np.zeros(cap); af = np.zeros(cap, np.int32); bud = np.zeros(cap, np.int64)
+    L.ebcc_ref_alg1_log(_p(r), _p(qa), _p(af), _p(bud), cap)
+    try:
+        s = compress(x, err_bound, base_ratio=base_ratio, q=q, **kw)
+    finally:
+        n = L.ebcc_ref_alg1_log(None, None, None, None, 0)
+    n = min(n, cap)
+    return s, [(float(r[i]), float(qa[i]), bool(af[i]), int(bud[i])) for i in range(n)]
 
 
 def decompress(stream, ny, nx):

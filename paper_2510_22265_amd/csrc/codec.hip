@@ -217,7 +217,8 @@ __global__ void k_zero_slot(const FieldDev* __restrict__ F, int nfields, int whi
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nfields || !F[i].active) return;
   if (which == 0) F[i].flags[0] = 0;
-  else F[i].u32s[0] = 0;
+  else if (which == 1) F[i].u32s[0] = 0;
+  else F[i].u32s[2] = 0;
 }
 
 // Fill buf[which] with v (which = BUF_XOUT and v = NaN: fill with xmin).
@@ -273,7 +274,31 @@ __global__ void k_collect(const FieldDev* __restrict__ F, int nfields, int64_t* 
   const FieldDev& f = F[i];
   int64_t* o = out + 8 * i;
   o[0] = f.flags[0]; o[1] = f.flags[1]; o[2] = f.u32s[0]; o[3] = f.u32s[1];
-  o[4] = f.totals[0]; o[5] = f.totals[1]; o[6] = 0; o[7] = 0;
+  o[4] = f.totals[0]; o[5] = f.totals[1]; o[6] = f.u32s[2];
+  o[7] = f.totals[2] | ((int64_t)(f.flags[2] & 1) << 48);   // PCRD payload, every segment fitted
+}
+
+// q_A of Algorithm 1's enc_base: samples whose base-layer reconstruction
+// (zero residual, the decoder's arithmetic) is within eps, into u32s[2].
+__global__ __launch_bounds__(256) void k_count_within(const FieldDev* __restrict__ F) {
+  __shared__ unsigned sh[4];
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active) return;
+  const int n = f.ny * f.nx;
+  const float* x = f.buf[BUF_X];
+  const float* ab = f.buf[BUF_ABASE];
+  const float xmin = f.fp->xmin, range = f.fp->range_f;
+  const double eps = f.fp->eps;
+  unsigned cnt = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    float a = ab[i] + 0.0f;
+    a = a + 0.5f;
+    a = a * range;
+    float xh = xmin + a;
+    cnt += fabs((double)x[i] - (double)xh) <= eps ? 1u : 0u;
+  }
+  cnt = block_sum(cnt, sh);
+  if (threadIdx.x == 0 && cnt) atomicAdd(&f.u32s[2], cnt);
 }
 
 // Exclusive scan of a field's 32-bit lengths (len = (v >> shift) & mask);
@@ -703,6 +728,13 @@ static int grow_ws(WS* w, size_t need, size_t pin_need, hipStream_t st, char** b
 constexpr size_t kChunkSamples = size_t(1) << 27;
 constexpr int kChunkFields = 4096;
 
+// Base payload budget for ratio r: header + block table + codewords fit
+// floor(4 N / r) bytes (Algorithm 1's compression ratio r).
+static int64_t base_budget(int64_t N, int64_t nblk, double r) {
+  int64_t t = (int64_t)std::floor((double)(4 * N) / r) - kHdr - 4 * nblk;
+  return t < 0 ? 0 : t;
+}
+
 // Full-field sweeps that reduce: about 16 elements per thread, at most 1024
 // blocks per field.
 static int grid_sweep(size_t n) {
@@ -728,7 +760,7 @@ static int check_params(size_t ny, size_t nx, const ebcc_params* p, double err) 
   if (p->cblk_log2w < 2 || p->cblk_log2w > 6 || p->cblk_log2h < 2 || p->cblk_log2h > 6)
     return fail(EBCC_EINVAL, "code-block size out of range");
   if (p->spiht_tile < 1 || p->spiht_tile > 64) return fail(EBCC_EINVAL, "spiht_tile out of range");
-  if (p->q != 0.0) return fail(EBCC_ENOTIMPL, "the q-quantile base-ratio search is not implemented (q must be 0)");
+  if (!(p->q >= 0.0 && p->q <= 1.0)) return fail(EBCC_EINVAL, "q must be 0 (fixed base ratio) or in (0, 1]");
   return EBCC_OK;
 }
 
@@ -1055,11 +1087,13 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   for (int i = 0; i < nf; i++) {
     act[i] = mode[i] == MODE_CODED;
     checks[i] = act[i];
-    int64_t tb = (int64_t)std::floor((double)(4.0 * (double)in[i].ny * (double)in[i].nx) / pp->base_ratio);
-    c.Fh[i].budget = std::max<int64_t>(0, tb - kHdr - 4 * (int64_t)c.plans[i]->nblk);
+    c.Fh[i].budget = base_budget((int64_t)in[i].ny * (int64_t)in[i].nx, c.plans[i]->nblk, pp->base_ratio);
     c.Fh[i].er = fps[i].elog - 6;
   }
   if ((rc = upload_items(c, coded))) return rc;
+  std::vector<double> r_use(nf, pp->base_ratio), r_only(nf, -1.0);
+  const std::vector<int> coded0(act);   // coded after the field scalars
+  std::vector<int64_t> col;             // per-field results read back (k_collect)
   bool any = false;
   for (int v : act) any |= v != 0;
   if (any) {
@@ -1071,6 +1105,85 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     prof.mark(S_QUANT);
     t1_encode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, c.cw, c.R, c.D, c.bpt, c.tail, c.sppf, st);
     prof.mark(S_T1ENC);
+    // ---- base ratio: the given r, or Algorithm 1's feedback search ----
+    if (pp->q > 0.0) {
+      auto fieldN = [&](int i) { return (int64_t)c.Fh[i].ny * c.Fh[i].nx; };
+      auto search = [&](double q, std::vector<double>& rf, std::vector<double>& qf) -> int {
+        // per field: phase 0 evaluates r0, 1 halves r_low, 2 doubles r_high,
+        // 3 bisects; every round evaluates one ratio per field still
+        // searching (PCRD, closed-form dec_base, inverse DWT, q_A count)
+        struct S { int ph; double r_low, r_high, r_f, q_f, qa0, r_eval; bool zero0; };
+        std::vector<S> sv(nf);
+        std::vector<int> ev(nf, 0);
+        const double r0 = pp->base_ratio;
+        for (int i = 0; i < nf; i++)
+          if (act[i]) {
+            sv[i] = S{0, r0, r0, r0, 0.0, 0.0, r0, base_budget(fieldN(i), c.Fh[i].nblk, r0) == 0};
+            ev[i] = 1;
+          }
+        auto bisect = [&](int i) {
+          S& z = sv[i];
+          if (z.r_high - z.r_low > 1e-3) { z.ph = 3; z.r_eval = (z.r_low + z.r_high) / 2.0; }
+          else { z.ph = 4; ev[i] = 0; }
+        };
+        auto after_halving = [&](int i) {
+          S& z = sv[i];
+          if (z.qa0 > q && !z.zero0) { z.ph = 2; z.r_high = z.r_high * 2.0; z.r_eval = z.r_high; }
+          else bisect(i);
+        };
+        for (int round = 0; round < 4096; round++) {
+          bool anyev = false;
+          for (int i = 0; i < nf; i++)
+            if (ev[i]) { c.Fh[i].budget = base_budget(fieldN(i), c.Fh[i].nblk, sv[i].r_eval); anyev = true; }
+          if (!anyev) break;
+          int rc2;
+          if ((rc2 = c.set_active(ev))) return rc2;
+          k_zero_slot<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, 2);
+          pcrd(c.F, nf, c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
+          virtual_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.pb, c.kb, c.sppf, st);
+          dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, st);
+          k_count_within<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
+          HIPCHK(hipGetLastError());
+          if ((rc2 = c.collect_host(col))) return rc2;
+          for (int i = 0; i < nf; i++) {
+            if (!ev[i]) continue;
+            S& z = sv[i];
+            const double qa = (double)col[8 * i + 6] / (double)fieldN(i);
+            const bool allfit = ((col[8 * i + 7] >> 48) & 1) != 0;
+            const int64_t bud = base_budget(fieldN(i), c.Fh[i].nblk, z.r_eval);
+            if (z.ph == 0) {
+              z.qa0 = qa; z.q_f = qa;
+              if (qa < q && !allfit) { z.ph = 1; z.r_low = z.r_low / 2.0; z.r_eval = z.r_low; }
+              else after_halving(i);
+            } else if (z.ph == 1) {
+              z.r_f = z.r_low; z.q_f = qa;
+              if (qa < q && !allfit) { z.r_low = z.r_low / 2.0; z.r_eval = z.r_low; }
+              else after_halving(i);
+            } else if (z.ph == 2) {
+              if (qa > q && bud != 0) { z.r_high = z.r_high * 2.0; z.r_eval = z.r_high; }
+              else bisect(i);
+            } else {
+              if (qa < q) z.r_high = z.r_eval;
+              else { z.r_low = z.r_eval; z.r_f = z.r_eval; z.q_f = qa; }
+              bisect(i);
+            }
+          }
+        }
+        for (int i = 0; i < nf; i++) { rf[i] = sv[i].r_f; qf[i] = sv[i].q_f; }
+        return EBCC_OK;
+      };
+      std::vector<double> qf(nf, 0.0);
+      if ((rc = search(pp->q, r_use, qf))) return rc;
+      if (pp->q < 1.0) {
+        std::vector<double> r1(nf, 0.0), q1(nf, 0.0);
+        if ((rc = search(1.0, r1, q1))) return rc;
+        for (int i = 0; i < nf; i++)
+          if (act[i] && q1[i] >= 1.0) r_only[i] = r1[i];   // the base alone meets the bound
+      }
+      for (int i = 0; i < nf; i++)
+        if (act[i]) c.Fh[i].budget = base_budget(fieldN(i), c.Fh[i].nblk, r_use[i]);
+      if ((rc = c.set_active(act))) return rc;
+    }
     pcrd(c.F, nf, c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
     prof.mark(S_PCRD);
     // ---- A_base = dec_base(e_base) (closed form), residual, its DWT ----
@@ -1082,7 +1195,6 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     k_quant_res<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
     HIPCHK(hipGetLastError());
     prof.mark(S_RESID);
-    std::vector<int64_t> col;
     if ((rc = c.collect_host(col))) return rc;
     // ---- truncation search, all fields in lockstep: one launch + one sync per round ----
     enum { NONE = 0, CHECK_ALL, BISECT, REQUANT, FOUND, FAIL };
@@ -1231,6 +1343,56 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
       FieldDev& f = c.Fh[i];
       f.bb = (uint32_t)(4 * (int64_t)f.nblk + col[8 * i + 4]);
       f.rb = resid[i] ? (uint32_t)(4 * (int64_t)f.ntiles + col[8 * i + 5]) : 0u;
+    }
+    // ---- fallback (end of Algorithm 1): the base alone at its own ratio
+    // when that stream is smaller ----
+    std::vector<int> fbc(nf, 0);
+    bool anyfb = false;
+    for (int i = 0; i < nf; i++)
+      if (coded0[i] && r_only[i] >= 0.0) {
+        fbc[i] = 1; anyfb = true;
+        c.Fh[i].budget = base_budget((int64_t)c.Fh[i].ny * c.Fh[i].nx, c.Fh[i].nblk, r_only[i]);
+      }
+    if (anyfb) {
+      std::vector<int64_t> ebcc_total(nf, 0);
+      for (int i = 0; i < nf; i++)
+        if (fbc[i])
+          ebcc_total[i] = mode[i] == MODE_CODED ? col[8 * i + 4] + (int64_t)c.Fh[i].rb
+                                                : 4 * (int64_t)c.Fh[i].ny * c.Fh[i].nx;
+      if ((rc = c.set_active(fbc))) return rc;
+      pcrd(c.F, nf, c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
+      if ((rc = c.collect_host(col))) return rc;
+      std::vector<int> sw(nf, 0), restore(nf, 0);
+      bool anysw = false, anyrs = false;
+      for (int i = 0; i < nf; i++) {
+        if (!fbc[i]) continue;
+        const int64_t pay1 = col[8 * i + 7] & (((int64_t)1 << 48) - 1);
+        if (pay1 < ebcc_total[i]) {
+          sw[i] = 1; anysw = true;
+          mode[i] = MODE_CODED; act[i] = 1; resid[i] = 0;
+          c.Fh[i].rb = 0;
+        } else if (mode[i] == MODE_CODED) {
+          restore[i] = 1; anyrs = true;
+          c.Fh[i].budget = base_budget((int64_t)c.Fh[i].ny * c.Fh[i].nx, c.Fh[i].nblk, r_use[i]);
+        }
+      }
+      if (anyrs) {   // PCRD at the search's ratio again for the fields that keep it
+        if ((rc = c.set_active(restore))) return rc;
+        pcrd(c.F, nf, c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
+      }
+      if (anysw) {   // block table and base size of the base-only streams
+        if ((rc = c.set_active(sw))) return rc;
+        k_block_entries<<<grid_for(c.nblk), 256, 0, st>>>(c.pb, c.kb, c.len, c.nblk, c.bent);
+        k_scan<<<nf, 1024, 0, st>>>(c.F, c.bent, 0, 16, 0xFFFFu, c.boff);
+        HIPCHK(hipGetLastError());
+        if ((rc = c.collect_host(col))) return rc;
+        for (int i = 0; i < nf; i++)
+          if (sw[i]) c.Fh[i].bb = (uint32_t)(4 * (int64_t)c.Fh[i].nblk + col[8 * i + 4]);
+      }
+    }
+    for (int i = 0; i < nf; i++) {
+      if (!act[i]) continue;
+      FieldDev& f = c.Fh[i];
       if ((int64_t)f.bb + f.rb > 4 * (int64_t)f.ny * f.nx) { mode[i] = MODE_RAW; act[i] = 0; resid[i] = 0; }
     }
   }

@@ -181,7 +181,9 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
     }
     __syncthreads();
   }
-  // 3. kept passes per block: every segment with key above the threshold
+  // 3. kept passes per block: every segment with key above the threshold;
+  // the accepted payload and whether every segment fitted go to the field
+  unsigned long long used = 0;
   for (int b = tid; b < nblk; b += kPcrdThreads) {
     int nh = nhv[b];
     int k = 0;
@@ -192,6 +194,16 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
     }
     kb[b] = (uint8_t)k;
     len_out[b] = k ? R[(size_t)b * kPassStride + k] : 0;
+    used += (unsigned long long)len_out[b];
+  }
+  for (int o = 32; o > 0; o >>= 1) used += __shfl_xor(used, o);
+  if ((tid & 63) == 0) hist[tid >> 6] = used;      // the histogram is free again
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kPcrdThreads / 64; w++) t += hist[w];
+    f.totals[2] = (int64_t)t;
+    f.flags[2] = allfit ? 1 : 0;
   }
 }
 

@@ -81,7 +81,8 @@ def test_batch_order_and_repeats(gpu, ref):
 
 
 @pytest.mark.parametrize("kw", [dict(levels=2), dict(cblk_log2w=6, cblk_log2h=4), dict(spiht_tile=2),
-                                dict(base_ratio=4.0), dict(levels=0), dict(bound_mode=1)])
+                                dict(base_ratio=4.0), dict(levels=0), dict(bound_mode=1), dict(q=1 - 1e-5),
+                                dict(q=0.99), dict(q=1.0)])
 def test_batch_parameters(gpu, ref, kw):
     xs, eps = _mixed_fields()
     if kw.get("bound_mode") == 1:

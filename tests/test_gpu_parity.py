@@ -140,8 +140,8 @@ def test_error_paths(gpu):
     rc, need = gpu.compress_into(x, small, p)
     assert rc == gpu.ENOSPC and need > 10
     with pytest.raises(gpu.EbccError) as e:
-        gpu.compress(x, 0.01, q=1 - 1e-5)
-    assert e.value.code == gpu.ENOTIMPL
+        gpu.compress(x, 0.01, q=1.5)
+    assert e.value.code == gpu.EINVAL
     s = gpu.compress(x, 0.01).clone()
     y = torch.empty((16, 16), dtype=torch.float32, device="cuda")
     assert gpu.decompress_into(s, y) == 0
@@ -185,3 +185,13 @@ def test_spiht_kernel_variants(gpu, ref, variant, shape, levels, tile, monkeypat
     monkeypatch.setenv("EBCC_SPIHT_KERNEL", variant)
     x = synth.field("v", *shape, cfg=1, level=13)
     _roundtrip(gpu, ref, x, 0.002, levels=levels, tile=tile)
+
+
+@pytest.mark.parametrize("var,shape,eps", [("t", (91, 180), 0.01), ("u", (181, 360), 0.001), ("q", (64, 96), 0.05),
+                                           ("v", (129, 255), 0.01), ("u", (33, 47), 0.02), ("t", (5, 64), 0.01)])
+@pytest.mark.parametrize("q", [1 - 1e-5, 0.99, 0.5, 1.0])
+def test_stream_parity_ratio_search(gpu, ref, var, shape, eps, q):
+    """Algorithm 1's base-ratio feedback search (q > 0) and its base-only
+    fallback: the oracle's stream, byte for byte."""
+    x = synth.field(var, *shape, cfg=1, level=1)
+    _roundtrip(gpu, ref, x, eps, q=q)
