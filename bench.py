@@ -68,6 +68,12 @@ def _gen(spec):
     return synth.batch_field(a)
 
 
+def _gen_km(a):
+    from paper_2510_22265_amd import synth
+    var, level = a
+    return synth.vortex_field(1801, 3600, var=var, level=level, cfg=4)
+
+
 def generate(specs):
     from multiprocessing import Pool
     procs = min(16, os.cpu_count() or 1)
@@ -111,6 +117,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuned batched run")
     ap.add_argument("--serve-rates", default="200,1000,5000", help="Poisson arrival rates (req/s); empty: skip")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per rate")
+    ap.add_argument("--q", type=float, default=1 - 1e-5, help="proportion q of the ratio-search run (0: skip)")
+    ap.add_argument("--km-fields", type=int, default=8, help="km-scale 1801x3600 vortex fields (0: skip)")
     ap.add_argument("--batch-fields", type=int, default=256, help="fields of the uneven batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -422,6 +430,70 @@ def main():
             log(f"serving at {rate:.0f} req/s: {st}")
         batched["serving"] = serving
 
+    # ---------------- Algorithm 1's ratio search on the stack (batched) ----------------
+    ratio_search = None
+    if args.q > 0:
+        qargs = ebcc.BatchArgs(xs, err_bounds=[args.eps] * len(xs))
+        qout = torch.empty(qargs.bound(), dtype=torch.uint8, device=dev)
+        pq = ebcc.params(args.eps, args.ratio, q=args.q, **fmt)
+        assert ebcc.compress_batch_into(qargs, qout, pq, stream) == 0
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        assert ebcc.compress_batch_into(qargs, qout, pq, stream) == 0
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        qstreams = [qout[qargs.offsets[i]: qargs.offsets[i] + qargs.lengths[i]] for i in range(qargs.n)]
+        qd = ebcc.DecodeArgs(qstreams, recs)
+        assert ebcc.decompress_batch_into(qd, stream) == 0
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        qviol, qmax = verify(stack_h, recs, [args.eps] * len(xs))
+        qsb = sum(qargs.lengths[i] for i in range(qargs.n))
+        ratio_search = {"workload": f"the stack through the batched entry points with Algorithm 1's base-ratio "
+                                    f"search, q = {args.q}, r0 = {args.ratio}",
+                        "q": args.q, "compress_GBps": nbytes / (b - a) / 1e9, "decompress_GBps": nbytes / (c - b) / 1e9,
+                        "CR": nbytes / qsb, "CR_fixed_ratio": nbytes / stream_bytes, "violations": qviol,
+                        "max_err_rel": qmax}
+        log(f"ratio search: {ratio_search}")
+
+    # ---------------- km-scale stress fields (batched) ----------------
+    km = None
+    if args.km_fields:
+        kspecs = [("km", (v, lev)) for lev in range((args.km_fields + 1) // 2) for v in ("u", "v")][: args.km_fields]
+        from multiprocessing import Pool
+        with Pool(min(16, os.cpu_count() or 1)) as pool:
+            kh = pool.map(_gen_km, [k[1] for k in kspecs])
+        kx = [torch.from_numpy(f).to(dev) for f in kh]
+        kbytes = sum(f.nbytes for f in kh)
+        kargs = ebcc.BatchArgs(kx, err_bounds=[0.001] * len(kx))
+        kout = torch.empty(kargs.bound(), dtype=torch.uint8, device=dev)
+        pk = ebcc.params(0.001, args.ratio, levels=6, **fmt)
+        assert ebcc.compress_batch_into(kargs, kout, pk, stream) == 0
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        assert ebcc.compress_batch_into(kargs, kout, pk, stream) == 0
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        kst = [kout[kargs.offsets[i]: kargs.offsets[i] + kargs.lengths[i]] for i in range(kargs.n)]
+        krec = [torch.empty(f.shape, dtype=torch.float32, device=dev) for f in kh]
+        kd = ebcc.DecodeArgs(kst, krec)
+        assert ebcc.decompress_batch_into(kd, stream) == 0
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        kviol, kmax = verify(kh, krec, [0.001] * len(kx))
+        ext_err = 0.0
+        for f, y in zip(kh, krec):   # error at the vortex cores (top 0.01% of |x|)
+            a64 = np.abs(f.astype(np.float64))
+            m = a64 >= np.quantile(a64, 0.9999)
+            e = np.abs(f.astype(np.float64) - y.cpu().numpy().astype(np.float64))[m].max()
+            ext_err = max(ext_err, e / (float(f.max()) - float(f.min())))
+        km = {"workload": f"{len(kx)} km-scale 1801x3600 fields (8 Rankine vortices each), bound 0.1% of range, "
+                          f"6 levels, batched", "MB": kbytes / 1e6,
+              "compress_GBps": kbytes / (b - a) / 1e9, "decompress_GBps": kbytes / (c - b) / 1e9,
+              "CR": kbytes / sum(kargs.lengths[i] for i in range(kargs.n)), "violations": kviol,
+              "max_err_rel": kmax, "max_err_rel_at_extremes": ext_err}
+        log(f"km-scale: {km}")
+
     # ---------------- CPU oracle baseline ----------------
     cpu = None
     if not args.no_cpu:
@@ -456,6 +528,8 @@ def main():
         "decompress_ms_p50": pct(lat_d, 50) * 1e3, "decompress_ms_p99": pct(lat_d, 99) * 1e3,
         "stages_ms_per_step": {k: v[0] / steps for k, v in stages.items()},
         "batched": batched,
+        "ratio_search": ratio_search,
+        "km_scale": km,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -221,3 +221,41 @@ def test_autotune_picks_a_measured_candidate(gpu):
         y = _host(gpu.decompress(streams[i], *x.shape)).astype(np.float64)
         xh = _host(x).astype(np.float64)
         assert np.abs(xh - y).max() <= eps[i] * (xh.max() - xh.min())
+
+
+def test_nd_chunks_round_trip(gpu):
+    """A (T, P, H, W) array in chunks: every chunk is a field of one batched
+    call (its stream equals the flattened chunk compressed alone) and the
+    decoded array meets each chunk's range-relative bound."""
+    import torch
+    from paper_2510_22265_amd import nd
+    T, P, H, W = 3, 4, 46, 90
+    x = np.stack([np.stack([synth.field(v, H, W, cfg=7, level=4 * t + p) for p, v in enumerate("tuvq")])
+                  for t in range(T)]).astype(np.float32)
+    chunk = (2, 3, 46, 90)
+    blob = nd.compress_nd(_dev(x), chunk, err_bound=0.005)
+    y = _host(nd.decompress_nd(blob))
+    shape, ch, table, start = nd.parse_nd(blob)
+    assert shape == x.shape and ch == chunk
+    for (origin, ext), (o, n) in zip(nd.chunk_grid(x.shape, chunk), table):
+        sl = tuple(slice(a, a + e) for a, e in zip(origin, ext))
+        xc = x[sl].reshape(nd.flat_shape(ext))
+        solo = _host(gpu.compress(_dev(xc), 0.005)).tobytes()
+        assert blob[start + o: start + o + n] == solo
+        err = np.abs(x[sl].astype(np.float64) - y[sl].astype(np.float64)).max()
+        assert err <= 0.005 * (float(xc.max()) - float(xc.min()))
+
+
+def test_km_scale_vortex_field_matches_oracle(gpu, ref):
+    """Km-scale stress field (1801x3600, 8 Rankine vortices, 6 levels, bound
+    0.1% of range): the oracle's stream, and no violation at the extremes."""
+    x = synth.vortex_field(1801, 3600, var="u", level=0, cfg=4)
+    s_ref = ref.compress(x, 0.001, levels=6)
+    s_gpu = _host(gpu.compress_batch([_dev(x)], err_bounds=[0.001], levels=6)[0]).tobytes()
+    assert s_gpu == s_ref
+    y = _host(gpu.decompress(_dev(np.frombuffer(s_ref, np.uint8).copy()), *x.shape)).astype(np.float64)
+    eps = 0.001 * (float(x.max()) - float(x.min()))
+    err = np.abs(x.astype(np.float64) - y)
+    assert err.max() <= eps
+    ext = np.abs(x) >= np.quantile(np.abs(x), 0.9999)       # the vortex cores
+    assert err[ext].max() <= eps
