@@ -192,6 +192,8 @@ const char* ebcc_profile_stage_name(int i);
  *   spiht                   0 = SPIHT tiles in LDS (by capacity class, the
  *                           largest tiles with global-memory lists), 1 =
  *                           global-memory lists for every tile
+ *   t1_lanes                lanes-per-block coders: code-blocks per
+ *                           wavefront, 0 = by work size, or 1, 4, 16, 64
  * ebcc_tuning_set returns EBCC_EINVAL for out-of-range values.
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -200,6 +202,7 @@ typedef struct {
   int32_t t1_decoder;
   int32_t t1_wave_max;
   int32_t spiht;
+  int32_t t1_lanes;
 } ebcc_tuning;
 int ebcc_tuning_get(ebcc_tuning* t);
 int ebcc_tuning_set(const ebcc_tuning* t);

@@ -601,7 +601,7 @@ static int build_plan(Plan& p) {
 // global-memory lists; the environment variable EBCC_SPIHT_KERNEL=global
 // sends every tile to the global-memory kernels (to test both families).
 static std::mutex g_tune_mu;
-static Tuning g_tuning = {0, 0, 32768, 0};
+static Tuning g_tuning = {0, 0, 32768, 0, 0};
 
 Tuning tuning() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1812,16 +1812,18 @@ int ebcc_tuning_get(ebcc_tuning* t) {
   t->t1_decoder = v.t1_decoder;
   t->t1_wave_max = v.t1_wave_max;
   t->spiht = v.spiht;
+  t->t1_lanes = v.t1_lanes;
   return EBCC_OK;
 }
 
 int ebcc_tuning_set(const ebcc_tuning* t) {
   if (!t || t->struct_size != sizeof(ebcc_tuning)) return fail(EBCC_EINVAL, "bad ebcc_tuning");
   if (t->t1_encoder < 0 || t->t1_encoder > 2 || t->t1_decoder < 0 || t->t1_decoder > 2 || t->t1_wave_max < 0 ||
-      t->spiht < 0 || t->spiht > 1)
+      t->spiht < 0 || t->spiht > 1 ||
+      !(t->t1_lanes == 0 || t->t1_lanes == 1 || t->t1_lanes == 4 || t->t1_lanes == 16 || t->t1_lanes == 64))
     return fail(EBCC_EINVAL, "tuning value out of range");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuning = Tuning{t->t1_encoder, t->t1_decoder, t->t1_wave_max, t->spiht};
+  g_tuning = Tuning{t->t1_encoder, t->t1_decoder, t->t1_wave_max, t->spiht, t->t1_lanes};
   return EBCC_OK;
 }
 

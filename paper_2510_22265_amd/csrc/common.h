@@ -129,6 +129,7 @@ struct Tuning {
   int t1_decoder;    // same
   int t1_wave_max;   // by work size: a wave per block up to this many blocks, lanes beyond
   int spiht;         // 0 LDS kernels by capacity class, 1 global-memory lists for every tile
+  int t1_lanes;      // lanes-per-block kernels: blocks per wavefront (0 by work size, 1, 4, 16, 64)
 };
 Tuning tuning();
 

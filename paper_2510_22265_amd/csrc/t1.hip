@@ -646,6 +646,8 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
 // large batches pack up to 64 blocks per wavefront for throughput.
 // ------------------------------------------------------------------------
 static int pick_lanes(int items, int lanes_max) {
+  const int forced = tuning().t1_lanes;
+  if (forced > 0) return forced > lanes_max ? lanes_max : forced;
   const int resident = 8192;   // wavefronts the chip keeps in flight comfortably
   int l = 1;
   while (l < lanes_max && items / l > resident) l *= 4;

@@ -73,15 +73,16 @@ def test_tuning_struct_and_round_trip():
     ebcc = _lib()
     assert fields == [f for f, _ in ebcc.Tuning._fields_]
     old = ebcc.get_tuning()
-    assert old == {"t1_encoder": 0, "t1_decoder": 0, "t1_wave_max": 32768, "spiht": 0}
+    assert old == {"t1_encoder": 0, "t1_decoder": 0, "t1_wave_max": 32768, "spiht": 0, "t1_lanes": 0}
     try:
-        ebcc.set_tuning(t1_encoder=2, t1_wave_max=100, spiht=1)
-        assert ebcc.get_tuning() == {"t1_encoder": 2, "t1_decoder": 0, "t1_wave_max": 100, "spiht": 1}
-        try:
-            ebcc.set_tuning(spiht=5)
-            assert False
-        except ebcc.EbccError as e:
-            assert e.code == ebcc.EINVAL
+        ebcc.set_tuning(t1_encoder=2, t1_wave_max=100, spiht=1, t1_lanes=64)
+        assert ebcc.get_tuning() == {"t1_encoder": 2, "t1_decoder": 0, "t1_wave_max": 100, "spiht": 1, "t1_lanes": 64}
+        for bad in (dict(spiht=5), dict(t1_lanes=8)):
+            try:
+                ebcc.set_tuning(**bad)
+                assert False
+            except ebcc.EbccError as e:
+                assert e.code == ebcc.EINVAL
     finally:
         ebcc.set_tuning(**old)
     assert ebcc.get_tuning() == old
