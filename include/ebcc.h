@@ -194,6 +194,10 @@ const char* ebcc_profile_stage_name(int i);
  *                           global-memory lists for every tile
  *   t1_lanes                lanes-per-block coders: code-blocks per
  *                           wavefront, 0 = by work size, or 1, 4, 16, 64
+ *   t1_split                percent (0..100, default 20) of a lanes-per-block
+ *                           encoder launch's code-blocks given to the
+ *                           wave-per-block coder on a second stream (scalar
+ *                           and vector units then work at the same time)
  * ebcc_tuning_set returns EBCC_EINVAL for out-of-range values.
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -203,6 +207,7 @@ typedef struct {
   int32_t t1_wave_max;
   int32_t spiht;
   int32_t t1_lanes;
+  int32_t t1_split;
 } ebcc_tuning;
 int ebcc_tuning_get(ebcc_tuning* t);
 int ebcc_tuning_set(const ebcc_tuning* t);

@@ -601,7 +601,7 @@ static int build_plan(Plan& p) {
 // global-memory lists; the environment variable EBCC_SPIHT_KERNEL=global
 // sends every tile to the global-memory kernels (to test both families).
 static std::mutex g_tune_mu;
-static Tuning g_tuning = {0, 0, 32768, 0, 0};
+static Tuning g_tuning = {0, 0, 32768, 0, 0, 20};
 
 Tuning tuning() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1103,7 +1103,9 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     prof.mark(S_DWT);
     quant_planes(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, st);
     prof.mark(S_QUANT);
-    t1_encode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, c.cw, c.R, c.D, c.bpt, c.tail, c.sppf, st);
+    const T1Split t1s{c.ws->aux, c.ws->ev_fork, c.ws->ev_join};
+    t1_encode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, c.cw, c.R, c.D, c.bpt, c.tail, c.sppf, st,
+              &t1s);
     prof.mark(S_T1ENC);
     // ---- base ratio: the given r, or Algorithm 1's feedback search ----
     if (pp->q > 0.0) {
@@ -1608,6 +1610,7 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
         spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, sa);
       }
     }
+    // (no scalar/vector split here: the second stream is busy with SPIHT)
     t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, st);
     prof.mark(S_D_T1);
     dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, st);
@@ -1813,6 +1816,7 @@ int ebcc_tuning_get(ebcc_tuning* t) {
   t->t1_wave_max = v.t1_wave_max;
   t->spiht = v.spiht;
   t->t1_lanes = v.t1_lanes;
+  t->t1_split = v.t1_split;
   return EBCC_OK;
 }
 
@@ -1820,10 +1824,11 @@ int ebcc_tuning_set(const ebcc_tuning* t) {
   if (!t || t->struct_size != sizeof(ebcc_tuning)) return fail(EBCC_EINVAL, "bad ebcc_tuning");
   if (t->t1_encoder < 0 || t->t1_encoder > 2 || t->t1_decoder < 0 || t->t1_decoder > 2 || t->t1_wave_max < 0 ||
       t->spiht < 0 || t->spiht > 1 ||
-      !(t->t1_lanes == 0 || t->t1_lanes == 1 || t->t1_lanes == 4 || t->t1_lanes == 16 || t->t1_lanes == 64))
+      !(t->t1_lanes == 0 || t->t1_lanes == 1 || t->t1_lanes == 4 || t->t1_lanes == 16 || t->t1_lanes == 64) ||
+      t->t1_split < 0 || t->t1_split > 100)
     return fail(EBCC_EINVAL, "tuning value out of range");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuning = Tuning{t->t1_encoder, t->t1_decoder, t->t1_wave_max, t->spiht, t->t1_lanes};
+  g_tuning = Tuning{t->t1_encoder, t->t1_decoder, t->t1_wave_max, t->spiht, t->t1_lanes, t->t1_split};
   return EBCC_OK;
 }
 

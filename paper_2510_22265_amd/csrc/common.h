@@ -108,15 +108,21 @@ void pointwise(const FieldDev* F, const FieldDev* Fh, int nf, int src, int dst, 
 // tables are indexed by the block's position in the call's block array.
 void quant_planes(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, void* planes, void* signs,
                   uint8_t* pb, hipStream_t st);
+// Optional second stream (and the two events ordering it against the first)
+// for the wave-per-block share of a lanes-per-block launch.
+struct T1Split {
+  hipStream_t aux;
+  hipEvent_t ev_fork, ev_join;
+};
 void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
                const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
-               uint32_t* tail, void* sppf, hipStream_t st);
+               uint32_t* tail, void* sppf, hipStream_t st, const T1Split* sp = nullptr);
 void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,
                     const uint8_t* kb, const void* sppf, hipStream_t st);
 // table: per-block entries (P | k << 8 | len << 16); off: payload offsets
 // within each field's base payload (which starts at out + 48 + 4 nblk).
 void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
-               const int64_t* off, hipStream_t st);
+               const int64_t* off, hipStream_t st, const T1Split* sp = nullptr);
 void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
                     const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
                     uint32_t* tail, void* sppf, hipStream_t st);
@@ -130,6 +136,7 @@ struct Tuning {
   int t1_wave_max;   // by work size: a wave per block up to this many blocks, lanes beyond
   int spiht;         // 0 LDS kernels by capacity class, 1 global-memory lists for every tile
   int t1_lanes;      // lanes-per-block kernels: blocks per wavefront (0 by work size, 1, 4, 16, 64)
+  int t1_split;      // percent of a lanes-per-block launch's blocks run concurrently by the wave kernel
 };
 Tuning tuning();
 

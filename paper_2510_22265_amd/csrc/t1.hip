@@ -723,17 +723,44 @@ static bool use_wave(int nblk, bool decode) {
   return v == 1 || (v == 0 && nblk <= t.t1_wave_max);
 }
 
+// Lanes-per-block launches can hand the first t1_split percent of their
+// blocks to the wave-per-block kernel on a second stream: that kernel runs on
+// the scalar unit, the lanes kernel on the vector unit, so the two overlap.
+static int split_count(int nblk, const T1Split* sp) {
+  if (!sp || !sp->aux) return 0;
+  const int pct = tuning().t1_split;
+  return pct <= 0 ? 0 : (int)((int64_t)nblk * (pct > 100 ? 100 : pct) / 100);
+}
+
 void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes, const void* signs,
                const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail, void* sppf,
-               hipStream_t st) {
+               hipStream_t st, const T1Split* sp) {
   if (nblk <= 0) return;
   if (use_wave(nblk, false)) {
     t1_encode_wave(F, blk, nblk, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st);
     return;
   }
+  const int s = split_count(nblk, sp);
+  if (s > 0) {
+    (void)hipEventRecord(sp->ev_fork, st);
+    (void)hipStreamWaitEvent(sp->aux, sp->ev_fork, 0);
+    t1_encode_wave(F, blk, s, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, sp->aux);
+    const size_t ms = cbw <= 32 ? 4 : 8;
+    blk += s; pb += s; cw += (size_t)s * kCwCap;
+    planes = (const char*)planes + (size_t)s * kQBits * cbh * ms;
+    signs = (const char*)signs + (size_t)s * cbh * ms;
+    sppf = (char*)sppf + (size_t)s * cbh * ms;
+    R += (size_t)s * kPassStride; D += (size_t)s * kPassStride;
+    bp += (size_t)s * kPassStride; tail += (size_t)s * kPassStride;
+    nblk -= s;
+  }
 #define ENC(MT, RW) launch_encode<MT, RW>(nblk, F, blk, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st)
   T1_DISPATCH(cbw, cbh, ENC);
 #undef ENC
+  if (s > 0) {
+    (void)hipEventRecord(sp->ev_join, sp->aux);
+    (void)hipStreamWaitEvent(st, sp->ev_join, 0);
+  }
 }
 
 void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,
@@ -747,15 +774,26 @@ void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
 }
 
 void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
-               const int64_t* off, hipStream_t st) {
+               const int64_t* off, hipStream_t st, const T1Split* sp) {
   if (nblk <= 0) return;
   if (use_wave(nblk, true)) {
     t1_decode_wave(F, blk, nblk, cbw, table, off, st);
     return;
   }
+  const int s = split_count(nblk, sp);
+  if (s > 0) {
+    (void)hipEventRecord(sp->ev_fork, st);
+    (void)hipStreamWaitEvent(sp->aux, sp->ev_fork, 0);
+    t1_decode_wave(F, blk, s, cbw, table, off, sp->aux);
+    blk += s; table += s; off += s; nblk -= s;
+  }
 #define DEC(MT, RW) launch_decode<MT, RW>(nblk, F, blk, table, off, st)
   T1_DISPATCH(cbw, cbh, DEC);
 #undef DEC
+  if (s > 0) {
+    (void)hipEventRecord(sp->ev_join, sp->aux);
+    (void)hipStreamWaitEvent(st, sp->ev_join, 0);
+  }
 }
 
 }  // namespace ebcc

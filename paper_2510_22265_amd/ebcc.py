@@ -32,7 +32,8 @@ class Params(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("t1_encoder", C.c_int32), ("t1_decoder", C.c_int32),
-                ("t1_wave_max", C.c_int32), ("spiht", C.c_int32), ("t1_lanes", C.c_int32)]
+                ("t1_wave_max", C.c_int32), ("spiht", C.c_int32), ("t1_lanes", C.c_int32),
+                ("t1_split", C.c_int32)]
 
 
 class EbccError(RuntimeError):
