@@ -117,10 +117,6 @@ template <typename M>
 __device__ __forceinline__ M wmask_of(int w) {
   return (w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << w) - 1);
 }
-template <typename M>
-__device__ __forceinline__ int sgn3(M s, M n, int x) {
-  return bt(s, x) ? (bt(n, x) ? -1 : 1) : 0;
-}
 
 // Lane y: the columns of row y with at least one significant neighbour among
 // the eight (rows y-1, y, y+1).  Significance does not change during a
@@ -154,6 +150,10 @@ template <typename M>
 __device__ __forceinline__ uint32_t f3(M m, int x) {
   return x > 0 ? (uint32_t)(m >> (x - 1)) & 7u : (uint32_t)(m << 1) & 7u;
 }
+template <>
+__device__ __forceinline__ uint32_t f3<uint32_t>(uint32_t m, int x) {
+  return (uint32_t)((((uint64_t)m) << 1) >> x) & 7u;
+}
 template <typename M>
 __device__ __forceinline__ int btu(M m, int x) { return (int)((m >> x) & 1); }   // 0 <= x < bits
 struct HVD { int h, v, d; bool any; };
@@ -164,6 +164,50 @@ __device__ __forceinline__ HVD hvd(uint32_t u3, uint32_t m3, uint32_t d3) {
   r.d = __builtin_popcount(u3 & 5u) + __builtin_popcount(d3 & 5u);
   r.any = ((u3 | d3 | (m3 & 5u)) != 0u);
   return r;
+}
+
+// Zero-coding contexts as a table in one vector register: the neighbourhood
+// pattern u3 | m3 << 3 | d3 << 6 (three f3 fields of the rows above, at and
+// below the sample) indexes 512 four-bit labels, eight per lane.
+__device__ __forceinline__ uint32_t zc_table(int orient, int lane) {
+  uint32_t t = 0;
+  for (int j = 0; j < 8; j++) {
+    const uint32_t pat = 8u * (uint32_t)lane + (uint32_t)j;
+    const HVD n = hvd(pat & 7u, (pat >> 3) & 7u, pat >> 6);
+    t |= (uint32_t)zc_ctx(orient, n.h, n.v, n.d) << (4 * j);
+  }
+  return t;
+}
+// Pattern of a sample whose own bit is 0: nonzero iff a neighbour is significant.
+__device__ __forceinline__ uint32_t zc_pat(uint32_t u3, uint32_t m3, uint32_t d3) { return u3 | (m3 << 3) | (d3 << 6); }
+__device__ __forceinline__ int zc_look(uint32_t zct, uint32_t pat) {
+  return (int)((rdl32(zct, (int)(pat >> 3)) >> (4u * (pat & 7u))) & 15u);
+}
+
+// Sign-coding contexts as a table: the pattern of the four neighbours'
+// (significant, negative) bits, left | right | above | below with
+// sl | nl << 1 | sr << 2 | nr << 3 | su << 4 | nu << 5 | sd << 6 | nd << 7,
+// indexes 256 entries of (label - 9) | XOR bit << 3, eight per lane.
+__device__ __forceinline__ uint32_t sc_table(int lane) {
+  uint32_t t = 0;
+  for (int j = 0; j < 8; j++) {
+    const uint32_t pat = 8u * (uint32_t)lane + (uint32_t)j;
+    auto c = [&](int sh) { return (pat >> sh) & 1u ? (((pat >> (sh + 1)) & 1u) ? -1 : 1) : 0; };
+    int hc = c(0) + c(2), vc = c(4) + c(6);
+    hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
+    vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
+    int xr;
+    const int cx = sc_ctx(hc, vc, &xr);
+    t |= (uint32_t)((cx - CX_SC) | (xr << 3)) << (4 * j);
+  }
+  return lane < 32 ? t : 0u;
+}
+// sm, nm: f3 fields of the sample's own row (significance, sign); su, nu,
+// sd, nd: the bits above and below.
+__device__ __forceinline__ uint32_t sc_look(uint32_t sct, uint32_t sm, uint32_t nm, uint32_t su, uint32_t nu,
+                                            uint32_t sd, uint32_t nd) {
+  const uint32_t pat = (sm & 5u) | ((nm & 5u) << 1) | (su << 4) | (nu << 5) | (sd << 6) | (nd << 7);
+  return (rdl32(sct, (int)(pat >> 3)) >> (4u * (pat & 7u))) & 15u;
 }
 
 // Row r' in [-1, 4] of the current stripe's significance / sign rows.
@@ -216,13 +260,13 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
   __syncthreads();
   uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
   uint32_t ctxv = lane == 0 ? 4u : (lane == CX_RL ? 3u : (lane == CX_UNI ? 46u : 0u));
+  const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
   M sig = 0, vis = 0, ref = 0, spp = 0, nsig = 0, mag = 0;
   M neg = lane < h ? signs[(size_t)b * cbh + lane] : (M)0;
   const M wm = wmask_of<M>(w);
   uint8_t* out = cw + (size_t)b * kCwCap;
   MQW e;
   e.C = 0; e.A = 0x8000; e.B = 0; e.CT = 12; e.BP = -1;
-  const int orient = k.orient;
   int npass = 3 * P - 2, kk = 0;
   bool stop = false;
   int64_t Dcum = 0;
@@ -253,19 +297,11 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
           nsB[r] = 0; spB[r] = 0;
         }
         if (ty != 1) { nA = rowv(neg, y0 - 1); nC = rowv(neg, y0 + 4); }
+        // r is a compile-time constant in every caller (unrolled loops)
         auto code_sign = [&](int r, int x) {
-          int hc = sgn3(SR(r), NR(r), x - 1) + sgn3(SR(r), NR(r), x + 1);
-          int vc = 0;
-          // r is a compile-time constant in every caller (unrolled loops)
-          if (r == 0) vc = sgn3(sA, nA, x) + sgn3(sB[1], nB[1], x);
-          else if (r == 1) vc = sgn3(sB[0], nB[0], x) + sgn3(sB[2], nB[2], x);
-          else if (r == 2) vc = sgn3(sB[1], nB[1], x) + sgn3(sB[3], nB[3], x);
-          else vc = sgn3(sB[2], nB[2], x) + sgn3(sC, nC, x);
-          hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
-          vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
-          int xr;
-          int cx = sc_ctx(hc, vc, &xr);
-          mqw_encode(e, ctxv, tabv, cx, btu(nB[r], x) ^ xr, out, lane);
+          const uint32_t sc = sc_look(sct, f3(SR(r), x), f3(NR(r), x), btu(SR(r - 1), x), btu(NR(r - 1), x),
+                                      btu(SR(r + 1), x), btu(NR(r + 1), x));
+          mqw_encode(e, ctxv, tabv, CX_SC + (int)(sc & 7u), btu(nB[r], x) ^ (int)(sc >> 3), out, lane);
         };
         if (ty == 0) {                                   // significance propagation
           // candidate columns at the stripe start; a sample that becomes
@@ -288,10 +324,10 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
               if (r >= rn) continue;
               M mid = sB[r];
               if (btu(mid, x)) continue;
-              const HVD n = hvd(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
-              if (!n.any) continue;
+              const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
+              if (!pat) continue;
               int bit = btu(gB[r], x);
-              mqw_encode(e, ctxv, tabv, zc_ctx(orient, n.h, n.v, n.d), bit, out, lane);
+              mqw_encode(e, ctxv, tabv, zc_look(zct, pat), bit, out, lane);
               vB[r] |= (M)1 << x;
               if (bit) {
                 code_sign(r, x);
@@ -360,9 +396,9 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
             for (int r = 0; r < 4; r++) {
               if (r < rstart || r >= rn) continue;
               if (btu(sB[r] | vB[r], x)) continue;
-              const HVD n = hvd(f3(SR(r - 1), x), f3(sB[r], x), f3(SR(r + 1), x));
+              const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(sB[r], x), f3(SR(r + 1), x));
               int bit = btu(gB[r], x);
-              mqw_encode(e, ctxv, tabv, zc_ctx(orient, n.h, n.v, n.d), bit, out, lane);
+              mqw_encode(e, ctxv, tabv, zc_look(zct, pat), bit, out, lane);
               if (bit) {
                 code_sign(r, x);
                 sB[r] |= (M)1 << x;
@@ -521,9 +557,9 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
   __syncthreads();
   uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
   uint32_t ctxv = lane == 0 ? 4u : (lane == CX_RL ? 3u : (lane == CX_UNI ? 46u : 0u));
+  const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
   M sig = 0, vis = 0, ref = 0, neg = 0, cur = 0, magp = 0;
   const M wm = wmask_of<M>(w);
-  const int orient = k.orient;
   MQWD d;
   mqwd_init(d, sec + o, len);
   auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
@@ -552,17 +588,9 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
           cB[r] = 0; mB[r] = 0;
         }
         auto dec_sign = [&](int r, int x) {
-          int hc = sgn3(SR(r), NR(r), x - 1) + sgn3(SR(r), NR(r), x + 1);
-          int vc = 0;
-          if (r == 0) vc = sgn3(sA, nA, x) + sgn3(sB[1], nB[1], x);
-          else if (r == 1) vc = sgn3(sB[0], nB[0], x) + sgn3(sB[2], nB[2], x);
-          else if (r == 2) vc = sgn3(sB[1], nB[1], x) + sgn3(sB[3], nB[3], x);
-          else vc = sgn3(sB[2], nB[2], x) + sgn3(sC, nC, x);
-          hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
-          vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
-          int xr;
-          int cx = sc_ctx(hc, vc, &xr);
-          int s = mqwd_decode(d, ctxv, tabv, cx, lane) ^ xr;
+          const uint32_t sc = sc_look(sct, f3(SR(r), x), f3(NR(r), x), btu(SR(r - 1), x), btu(NR(r - 1), x),
+                                      btu(SR(r + 1), x), btu(NR(r + 1), x));
+          int s = mqwd_decode(d, ctxv, tabv, CX_SC + (int)(sc & 7u), lane) ^ (int)(sc >> 3);
           if (s) nB[r] |= (M)1 << x;
         };
         if (ty == 0) {
@@ -586,9 +614,9 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
               if (r >= rn) continue;
               M mid = sB[r];
               if (btu(mid, x)) continue;
-              const HVD n = hvd(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
-              if (!n.any) continue;
-              int bit = mqwd_decode(d, ctxv, tabv, zc_ctx(orient, n.h, n.v, n.d), lane);
+              const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
+              if (!pat) continue;
+              int bit = mqwd_decode(d, ctxv, tabv, zc_look(zct, pat), lane);
               vB[r] |= (M)1 << x;
               if (bit) {
                 dec_sign(r, x);
@@ -656,8 +684,8 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
             for (int r = 0; r < 4; r++) {
               if (r < rstart || r >= rn) continue;
               if (btu(sB[r] | vB[r], x)) continue;
-              const HVD n = hvd(f3(SR(r - 1), x), f3(sB[r], x), f3(SR(r + 1), x));
-              int bit = mqwd_decode(d, ctxv, tabv, zc_ctx(orient, n.h, n.v, n.d), lane);
+              const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(sB[r], x), f3(SR(r + 1), x));
+              int bit = mqwd_decode(d, ctxv, tabv, zc_look(zct, pat), lane);
               if (bit) {
                 dec_sign(r, x);
                 sB[r] |= (M)1 << x;
