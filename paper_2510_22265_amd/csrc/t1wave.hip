@@ -281,7 +281,7 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
       for (int y0 = 0; y0 < h && !stop; y0 += 4) {
         const int rn = h - y0 < 4 ? h - y0 : 4;
         M sA = rowv(sig, y0 - 1), sC = rowv(sig, y0 + 4);
-        M sB[4], vB[4], fB[4], gB[4], nB[4], nsB[4], spB[4];
+        M sB[4], vB[4], fB[4], gB[4], nB[4];
         M nA = 0, nC = 0;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
@@ -294,7 +294,6 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
           // sign rows; in a refinement pass (no sign coding) the rows'
           // neighbour-significance masks instead
           nB[r] = in ? rdl<M>(ty == 1 ? nbm8 : neg, y) : (M)0;
-          nsB[r] = 0; spB[r] = 0;
         }
         if (ty != 1) { nA = rowv(neg, y0 - 1); nC = rowv(neg, y0 + 4); }
         // r is a compile-time constant in every caller (unrolled loops)
@@ -332,8 +331,6 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
               if (bit) {
                 code_sign(r, x);
                 sB[r] = mid | ((M)1 << x);
-                nsB[r] |= (M)1 << x;
-                spB[r] |= (M)1 << x;
                 grew = true;
               }
             }
@@ -387,7 +384,6 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
                   if (r == rr) {
                     code_sign(r, x);
                     sB[r] |= (M)1 << x;
-                    nsB[r] |= (M)1 << x;
                   }
                 rstart = rr + 1;
               }
@@ -402,19 +398,20 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
               if (bit) {
                 code_sign(r, x);
                 sB[r] |= (M)1 << x;
-                nsB[r] |= (M)1 << x;
               }
             }
           }
         }
-        // write the stripe's rows back to the row registers
+        // write the stripe's rows back to the row registers (samples that
+        // became significant: the bits new in the stripe's rows)
 #pragma unroll
         for (int r = 0; r < 4; r++)
           if (r < rn && lane == y0 + r) {
+            const M nw = sB[r] & ~sig;
+            nsig |= nw;
+            if (ty == 0) spp |= nw;
             sig = sB[r]; vis = vB[r];
             if (ty == 1) ref = fB[r];
-            nsig |= nsB[r];
-            spp |= spB[r];
           }
         if (e.BP >= 65536) stop = true;                  // every later pass exceeds the length limit
       }
@@ -499,29 +496,23 @@ __device__ __forceinline__ void mqwd_renorm(MQWD& d) {
 __device__ __forceinline__ int mqwd_decode(MQWD& d, uint32_t& ctxv, uint32_t tabv, int cx, int lane) {
   uint32_t cs = rdl32(ctxv, cx);
   uint32_t ent = rdl32(tabv, (int)(cs & 0x7f));
-  uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
-  uint32_t nm = (ent >> 16) & 0x3f, nl = (ent >> 22) & 0x3f, sw = ent >> 28;
-  int D;
-  uint32_t ncs = cs;
-  d.A -= qe;
-  if ((d.C >> 16) < qe) {
-    if (d.A < qe) { D = (int)mps; ncs = (mps << 7) | nm; }
-    else { D = (int)(mps ^ 1u); ncs = ((sw ? (mps ^ 1u) : mps) << 7) | nl; }
-    d.A = qe;
-    if (lane == cx) ctxv = ncs;
-    mqwd_renorm(d);
-  } else {
+  const uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
+  const uint32_t A = d.A - qe;
+  const bool chigh = (d.C >> 16) < qe;      // in the lower sub-interval of size Qe
+  if (__builtin_expect(!chigh && (A & 0x8000u), 1)) {
+    d.A = A;
     d.C -= qe << 16;
-    if ((d.A & 0x8000) == 0) {
-      if (d.A < qe) { D = (int)(mps ^ 1u); ncs = ((sw ? (mps ^ 1u) : mps) << 7) | nl; }
-      else { D = (int)mps; ncs = (mps << 7) | nm; }
-      if (lane == cx) ctxv = ncs;
-      mqwd_renorm(d);
-    } else {
-      D = (int)mps;
-    }
+    return (int)mps;
   }
-  return D;
+  // the MPS was decoded iff exactly one of: C below Qe, A below Qe
+  const bool is_mps = chigh == (A < qe);
+  d.A = chigh ? qe : A;
+  d.C -= chigh ? 0u : (qe << 16);
+  const uint32_t m = (!is_mps && (ent >> 28)) ? (mps ^ 1u) : mps;
+  const uint32_t ncs = (m << 7) | (is_mps ? ((ent >> 16) & 0x3f) : ((ent >> 22) & 0x3f));
+  if (lane == cx) ctxv = ncs;
+  mqwd_renorm(d);
+  return (int)(is_mps ? mps : (mps ^ 1u));
 }
 
 template <typename M>
@@ -574,7 +565,7 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
         const int rn = h - y0 < 4 ? h - y0 : 4;
         M sA = rowv(sig, y0 - 1), sC = rowv(sig, y0 + 4);
         M nA = rowv(neg, y0 - 1), nC = rowv(neg, y0 + 4);
-        M sB[4], vB[4], fB[4], nB[4], cB[4], mB[4];
+        M sB[4], vB[4], fB[4], nB[4], mB[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
           int y = y0 + r;
@@ -585,7 +576,7 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
           // decoded signs; in a refinement pass (no sign decoding) the
           // rows' neighbour-significance masks instead
           nB[r] = in ? rdl<M>(ty == 1 ? nbm8 : neg, y) : (M)0;
-          cB[r] = 0; mB[r] = 0;
+          mB[r] = 0;
         }
         auto dec_sign = [&](int r, int x) {
           const uint32_t sc = sc_look(sct, f3(SR(r), x), f3(NR(r), x), btu(SR(r - 1), x), btu(NR(r - 1), x),
@@ -621,8 +612,6 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
               if (bit) {
                 dec_sign(r, x);
                 sB[r] = mid | ((M)1 << x);
-                cB[r] |= (M)1 << x;
-                mB[r] |= (M)1 << x;
                 grew = true;
               }
             }
@@ -642,7 +631,6 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
               int bit = mqwd_decode(d, ctxv, tabv, cx, lane);
               if (bit) mB[r] |= (M)1 << x;
               fB[r] |= (M)1 << x;
-              cB[r] |= (M)1 << x;
             }
           }
         } else {
@@ -674,8 +662,6 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
                   if (r == rr) {
                     dec_sign(r, x);
                     sB[r] |= (M)1 << x;
-                    cB[r] |= (M)1 << x;
-                    mB[r] |= (M)1 << x;
                   }
                 rstart = rr + 1;
               }
@@ -689,20 +675,26 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
               if (bit) {
                 dec_sign(r, x);
                 sB[r] |= (M)1 << x;
-                cB[r] |= (M)1 << x;
-                mB[r] |= (M)1 << x;
               }
             }
           }
         }
+        // write back; the samples coded in this plane: those that became
+        // significant (their bit is 1) or were refined (bits in mB)
 #pragma unroll
         for (int r = 0; r < 4; r++)
           if (r < rn && lane == y0 + r) {
+            if (ty == 1) {
+              cur |= sB[r] & ~vB[r];
+              magp |= mB[r];
+              ref = fB[r];
+            } else {
+              const M nw = sB[r] & ~sig;
+              cur |= nw;
+              magp |= nw;
+              neg = nB[r];
+            }
             sig = sB[r]; vis = vB[r];
-            if (ty != 1) neg = nB[r];
-            if (ty == 1) ref = fB[r];
-            cur |= cB[r];
-            magp |= mB[r];
           }
       }
       if (ty == 2) vis = 0;
