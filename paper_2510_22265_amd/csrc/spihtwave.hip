@@ -24,6 +24,7 @@ namespace ebcc {
 
 struct TileGeom {
   int r0[kMaxBands], c0[kMaxBands], hr[kMaxBands], wr[kMaxBands], off[kMaxBands + 1];
+  uint64_t mg[kMaxBands];   // ceil(2^32 / wr): row of a rectangle index without a division
   int ncoef, nparents;
 };
 
@@ -47,7 +48,11 @@ __device__ void tile_geom(TileGeom& g, const Band* B, int nb, int L, const TileD
     g.wr[b] = c1 > c0 ? c1 - c0 : 0;
   }
   int o = 0;
-  for (int b = 0; b < nb; b++) { g.off[b] = o; o += g.hr[b] * g.wr[b]; }
+  for (int b = 0; b < nb; b++) {
+    g.off[b] = o;
+    o += g.hr[b] * g.wr[b];
+    g.mg[b] = g.wr[b] > 0 ? ((1ull << 32) + (uint64_t)g.wr[b] - 1) / (uint64_t)g.wr[b] : 0;
+  }
   g.off[nb] = o;
   g.ncoef = o;
   g.nparents = L >= 1 ? g.off[1 + 3 * (L - 1)] : 0;
@@ -64,7 +69,8 @@ __device__ __forceinline__ int offspring_local(const TileGeom& g, const Band* B,
                                                int* clevel) {
   int b = band_of(g, nb, loc);
   int rel = loc - g.off[b];
-  int li = rel / g.wr[b], lj = rel - li * g.wr[b];
+  // exact: rel * wr < 2^32 for tiles of up to 2^16 coefficients
+  int li = (int)(((uint64_t)rel * g.mg[b]) >> 32), lj = rel - li * g.wr[b];
   int i = g.r0[b] + li, j = g.c0[b] + lj;
   int k = 0;
   if (b == 0) {
@@ -387,6 +393,66 @@ struct BitRU {
   }
 };
 
+// Tile geometry held in vector registers, lane b for band b, so that the
+// wave-uniform decoder finds a node's band and offspring with a ballot and
+// readlanes instead of LDS round trips.
+struct GeomRegs {
+  int off, wr, r0, c0, h, w, level;
+  uint32_t mlo, mhi;
+  int nb;
+  __device__ void load(const TileGeom& g, const Band* B, int nb_, int lane) {
+    nb = nb_;
+    const bool in = lane < nb;
+    off = in ? g.off[lane] : 0x7FFFFFFF;
+    wr = in ? g.wr[lane] : 0;
+    r0 = in ? g.r0[lane] : 0;
+    c0 = in ? g.c0[lane] : 0;
+    h = in ? B[lane].h : 0;
+    w = in ? B[lane].w : 0;
+    level = in ? B[lane].level : 0;
+    const uint64_t m = in ? g.mg[lane] : 0;
+    mlo = (uint32_t)m;
+    mhi = (uint32_t)(m >> 32);
+  }
+};
+__device__ __forceinline__ int rl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint32_t rlu(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+
+// Offspring of node loc (the same in every lane); same results as
+// offspring_local.
+__device__ __forceinline__ int offspring_uniform(const GeomRegs& G, int L, int loc, int* ch, int* clevel) {
+  // bands are stored in order of offset: the node's band is the last one
+  // starting at or before it
+  const int b = __builtin_popcountll(__ballot(G.off <= loc)) - 1;
+  const int rel = loc - rl(G.off, b);
+  const uint64_t mg = (uint64_t)rlu(G.mlo, b) | ((uint64_t)rlu(G.mhi, b) << 32);
+  const int wrb = rl(G.wr, b);
+  const int li = (int)(((uint64_t)rel * mg) >> 32), lj = rel - li * wrb;
+  const int i = rl(G.r0, b) + li, j = rl(G.c0, b) + lj;
+  int k = 0;
+  if (b == 0) {
+    *clevel = L;
+    if (L == 0) return 0;
+#pragma unroll
+    for (int c = 1; c <= 3; c++)
+      if (i < rl(G.h, c) && j < rl(G.w, c)) ch[k++] = rl(G.off, c) + (i - rl(G.r0, c)) * rl(G.wr, c) + (j - rl(G.c0, c));
+    return k;
+  }
+  const int lev = rl(G.level, b);
+  *clevel = lev - 1;
+  if (lev == 1) return 0;
+  const int cb = b + 3;
+  const int hb = rl(G.h, b), wb = rl(G.w, b), hc = rl(G.h, cb), wc = rl(G.w, cb);
+  int r1 = (i == hb - 1) ? hc : 2 * i + 2;
+  int c1 = (j == wb - 1) ? wc : 2 * j + 2;
+  if (r1 > hc) r1 = hc;
+  if (c1 > wc) c1 = wc;
+  const int base = rl(G.off, cb) - rl(G.r0, cb) * rl(G.wr, cb) - rl(G.c0, cb), pitch = rl(G.wr, cb);
+  for (int r = 2 * i; r < r1; r++)
+    for (int c = 2 * j; c < c1; c++) ch[k++] = base + r * pitch + c;
+  return k;
+}
+
 template <int CAP>
 __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
                                                          const int* __restrict__ tix, const int64_t* __restrict__ toff,
@@ -439,14 +505,19 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
     nlis += tot;
   }
   __syncthreads();
+  GeomRegs G;
+  G.load(g, S.B, nb, lane);
   int nlip = nroots, nlsp = 0;
   BitRU rd;
   rd.init(pay, len);
   for (int pl = ntop; pl >= n_s; pl--) {
     const uint32_t thr = 1u << pl;
     const int lsp_prev = nlsp;
-    // LIP: runs of zeros leave entries in place; a one makes the entry significant
-    int k = 0, surv = 0;
+    // LIP: runs of zeros leave entries in place; a one makes the entry
+    // significant.  Entries are read through a 64-entry register window; the
+    // moves of survivors only write below the current position.
+    int k = 0, surv = 0, pbase = 0, pcnt = 0;
+    uint32_t pv = 0;
     while (k < nlip) {
       int z = rd.zeros();
       if (z > nlip - k) z = nlip - k;
@@ -467,25 +538,42 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
       // entry k: significant (its token is 1 and a sign bit)
       rd.get();
       int sg = rd.get();
-      int e = S.lip[k];
+      if (k - pbase >= pcnt || k < pbase) {
+        pbase = k;
+        pcnt = nlip - k < 64 ? nlip - k : 64;
+        pv = lane < pcnt ? (uint32_t)S.lip[k + lane] : 0u;
+      }
+      int e = rl((int)pv, k - pbase);
       if (lane == 0) { S.qv[e] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)e; }
-      __syncthreads();
       nlsp++;
       k++;
     }
     nlip = surv;
-    // LIS
-    int head = 0, kept = 0;
+    // LIS: entries are read 64 at a time into a vector register (lane i:
+    // entry base + i); a window never reaches past the list's end at the
+    // time it is read, so entries appended later are read by a later window.
+    // One wavefront runs the tile, so its LDS writes are seen by its later
+    // reads in program order.
+    int head = 0, kept = 0, wbase = 0, wcnt = 0;
+    uint32_t wv = 0;
     while (head < nlis) {
-      int e = S.lis[head];
-      int loc = e & 0x7FFF, typeB = e >> 15;
-      int ch[9], cl = 0;
-      int no = offspring_local(g, S.B, nb, L, loc, ch, &cl);
-      int s = rd.get();
+      if (head - wbase >= wcnt) {
+        wbase = head;
+        wcnt = nlis - head < 64 ? nlis - head : 64;
+        wv = lane < wcnt ? (uint32_t)S.lis[head + lane] : 0u;
+      }
+      const int e = (int)__builtin_amdgcn_readlane((int)wv, head - wbase);
+      const int s = rd.get();
       if (!s) {
         if (lane == 0) S.lis[kept] = (uint16_t)e;
         kept++;
-      } else if (!typeB) {
+        head++;
+        continue;
+      }
+      const int loc = e & 0x7FFF, typeB = e >> 15;
+      int ch[9], cl = 0;
+      const int no = offspring_uniform(G, L, loc, ch, &cl);
+      if (!typeB) {
         for (int c = 0; c < no; c++) {
           if (rd.get()) {
             int sg = rd.get();
@@ -506,23 +594,25 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
         }
         nlis += no;
       }
-      __syncthreads();
       head++;
     }
+    __syncthreads();
     nlis = kept;
-    // refinement: the next lsp_prev bits, read by all lanes
-    const int64_t p0 = rd.pos;
+    // refinement: the next lsp_prev bits, 64 at a time from the uniform
+    // reader, one per lane
     for (int h0 = 0; h0 < lsp_prev; h0 += 64) {
-      int kk = h0 + lane;
-      if (kk < lsp_prev) {
-        int64_t bp = p0 + kk;
-        int64_t by = bp >> 3;
-        uint32_t b = by < len ? (pay[by] >> (7 - (bp & 7))) & 1u : 0u;
+      const int n = lsp_prev - h0 < 64 ? lsp_prev - h0 : 64;
+      const uint32_t w0 = (uint32_t)(rd.win >> 32);
+      rd.skip(n < 32 ? n : 32);
+      const uint32_t w1 = (uint32_t)(rd.win >> 32);
+      if (n > 32) rd.skip(n - 32);
+      const int kk = h0 + lane;
+      if (lane < n) {
+        const uint32_t b = lane < 32 ? (w0 >> (31 - lane)) & 1u : (w1 >> (63 - lane)) & 1u;
         if (b) S.qv[S.lsp[kk]] |= thr;
       }
     }
     __syncthreads();
-    rd.seek(p0 + lsp_prev);
   }
   // dequantised significant coefficients
   for (int b = 0; b < nb; b++) {
