@@ -98,7 +98,10 @@ __device__ __forceinline__ int wscan_excl(int v, int lane, int* total) {
     int t = __shfl_up(x, o);
     if (lane >= o) x += t;
   }
-  *total = __shfl(x, 63);
+  // the total is the same in every lane: readfirstlane tells the compiler,
+  // which keeps the counters it feeds in scalar registers and the loops
+  // they bound wave-uniform
+  *total = __builtin_amdgcn_readfirstlane(__shfl(x, 63));
   return x - v;
 }
 
@@ -184,6 +187,7 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
     }
   }
   for (int o = 32; o > 0; o >>= 1) { uint32_t v = __shfl_xor(mx, o); mx = v > mx ? v : mx; }
+  mx = (uint32_t)__builtin_amdgcn_readfirstlane((int)mx);
   const int ntop = mx ? 31 - __builtin_clz(mx) : -1;
   if (ntop < n_s) {
     if (lane == 0) { tlen[t] = 0; tent[t] = 0; }
@@ -350,7 +354,9 @@ struct BitRU {
     if (i < 0 || i >= len) return 0u;
     uint64_t a = (uint64_t)(buf + i);
     uint64_t w = a & ~(uint64_t)3;
-    if (w != wa) { word = *reinterpret_cast<const uint32_t*>(w); wa = w; }
+    // uniform address; readfirstlane keeps the reader's state scalar (a load
+    // through a generic pointer is not known to be uniform)
+    if (w != wa) { word = (uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int*>(w)); wa = w; }
     return (word >> (8 * (uint32_t)(a & 3))) & 0xFFu;
   }
   __device__ void init(const uint8_t* b, int64_t n) {
@@ -476,8 +482,9 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
   }
   if (lane == 0) misfit[t] = 0;
   const TileGeom& g = S.g;
-  const uint32_t ent = (uint32_t)sec[4 * tl] | ((uint32_t)sec[4 * tl + 1] << 8) | ((uint32_t)sec[4 * tl + 2] << 16) |
-                       ((uint32_t)sec[4 * tl + 3] << 24);
+  const uint32_t ent = (uint32_t)__builtin_amdgcn_readfirstlane(
+      (int)((uint32_t)sec[4 * tl] | ((uint32_t)sec[4 * tl + 1] << 8) | ((uint32_t)sec[4 * tl + 2] << 16) |
+            ((uint32_t)sec[4 * tl + 3] << 24)));
   const int64_t len = ent & 0x3FFFFFF;
   const int ntop = (int)(ent >> 26) - 1;
   const int64_t pbase = 4 * (int64_t)f.ntiles;

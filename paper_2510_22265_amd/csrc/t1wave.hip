@@ -461,7 +461,9 @@ __device__ __forceinline__ uint32_t mqwd_rd(MQWD& d, int i) {
   uint64_t a = (uint64_t)(d.buf + i);
   uint64_t wa = a & ~(uint64_t)3;
   if (wa != d.wa) {
-    d.word = *reinterpret_cast<const uint32_t*>(wa);
+    // the address is wave-uniform; a load through a generic pointer is not
+    // known to be, so readfirstlane keeps the coder's state scalar
+    d.word = (uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int*>(wa));
     d.wa = wa;
   }
   return (d.word >> (8 * (uint32_t)(a & 3))) & 0xFFu;
