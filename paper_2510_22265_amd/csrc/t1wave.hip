@@ -15,6 +15,8 @@
 #include "common.h"
 #include "t1_common.h"
 
+#include <type_traits>
+
 namespace ebcc {
 
 template <typename M> __device__ __forceinline__ M rdl(M v, int l);
@@ -278,6 +280,10 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
       nsig = 0;
       M refd = sig & ~vis;          // MRP refines every sample significant before this plane
       const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
+      // one instance of the stripe loop per pass type, so that each keeps
+      // only the row masks its pass uses live
+      auto stripes = [&](auto tyc) {
+      constexpr int ty = decltype(tyc)::value;
       for (int y0 = 0; y0 < h && !stop; y0 += 4) {
         const int rn = h - y0 < 4 ? h - y0 : 4;
         M sA = rowv(sig, y0 - 1), sC = rowv(sig, y0 + 4);
@@ -415,6 +421,10 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
           }
         if (e.BP >= 65536) stop = true;                  // every later pass exceeds the length limit
       }
+      };
+      if (ty == 0) stripes(std::integral_constant<int, 0>{});
+      else if (ty == 1) stripes(std::integral_constant<int, 1>{});
+      else stripes(std::integral_constant<int, 2>{});
       if (stop) break;
       // distortion reduction of this pass, summed over rows in parallel
       M chg = (ty == 1) ? refd : nsig;
@@ -563,6 +573,8 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
     magp = 0;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < kb; ty++) {
       const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
+      auto stripes = [&](auto tyc) {
+      constexpr int ty = decltype(tyc)::value;
       for (int y0 = 0; y0 < h; y0 += 4) {
         const int rn = h - y0 < 4 ? h - y0 : 4;
         M sA = rowv(sig, y0 - 1), sC = rowv(sig, y0 + 4);
@@ -699,6 +711,10 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
             sig = sB[r]; vis = vB[r];
           }
       }
+      };
+      if (ty == 0) stripes(std::integral_constant<int, 0>{});
+      else if (ty == 1) stripes(std::integral_constant<int, 1>{});
+      else stripes(std::integral_constant<int, 2>{});
       if (ty == 2) vis = 0;
       done++;
     }
