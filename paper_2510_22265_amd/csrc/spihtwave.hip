@@ -341,61 +341,68 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
   }
 }
 
-// Uniform reader of a tile payload (bytes past its end read as 0).
+// Uniform reader of a tile payload (bytes past its end read as 0).  The
+// window holds the next 32..63 bits MSB first and takes 32 more bits, one
+// aligned word load, whenever fewer than 32 remain; the payload's byte
+// offset within its first aligned word is fixed, so each refill is a funnel
+// shift of two consecutive aligned words.
 struct BitRU {
-  const uint8_t* buf;
-  int64_t len, pos;        // pos: next bit to consume
-  uint64_t win;            // next bits, MSB first
-  int wn;                  // valid bits in win
-  int64_t bytepos;         // next byte to load into win
-  uint64_t wa;
-  uint32_t word;
-  __device__ uint32_t byte_at(int64_t i) {
-    if (i < 0 || i >= len) return 0u;
-    uint64_t a = (uint64_t)(buf + i);
-    uint64_t w = a & ~(uint64_t)3;
-    // uniform address; readfirstlane keeps the reader's state scalar (a load
-    // through a generic pointer is not known to be uniform)
-    if (w != wa) { word = (uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int*>(w)); wa = w; }
-    return (word >> (8 * (uint32_t)(a & 3))) & 0xFFu;
+  const uint32_t* wp;      // aligned word holding the payload's first byte
+  int len;                 // payload bytes
+  int bytepos;             // payload bytes already in the window
+  int sh;                  // 8 x (payload address mod 4)
+  int nwords;              // aligned words that hold payload bytes
+  int wi;                  // index of the next aligned word to load
+  uint32_t prev;           // aligned word wi - 1
+  uint64_t win;
+  int wn;
+  __device__ uint32_t word(int i) {
+    // i < nwords: the word holds at least one payload byte, so it lies in
+    // the payload's buffer; readfirstlane keeps the (uniform) value scalar
+    return i < nwords ? (uint32_t)__builtin_amdgcn_readfirstlane((int)wp[i]) : 0u;
   }
   __device__ void init(const uint8_t* b, int64_t n) {
-    buf = b; len = n; pos = 0; win = 0; wn = 0; bytepos = 0; wa = ~(uint64_t)0; word = 0;
+    const uint64_t a = (uint64_t)b;
+    wp = reinterpret_cast<const uint32_t*>(a & ~(uint64_t)3);
+    sh = 8 * (int)(a & 3);
+    len = (int)n;
+    nwords = (int)((a & 3) + (uint64_t)n + 3) >> 2;
+    bytepos = 0;
+    prev = word(0);
+    wi = 1;
+    win = 0;
+    wn = 0;
+    refill();
     refill();
   }
   __device__ void refill() {
-    while (wn <= 56) {
-      win |= (uint64_t)byte_at(bytepos) << (56 - wn);
-      bytepos++;
-      wn += 8;
-    }
+    const uint32_t nxt = word(wi);
+    uint32_t le = (uint32_t)(((((uint64_t)nxt) << 32) | prev) >> sh);   // next 4 bytes, first in the low byte
+    prev = nxt;
+    wi++;
+    const int avail = len - bytepos;
+    if (avail < 4) le &= avail <= 0 ? 0u : ((1u << (8 * avail)) - 1u);
+    bytepos += 4;
+    const uint32_t be = (le >> 24) | ((le >> 8) & 0xFF00u) | ((le << 8) & 0xFF0000u) | (le << 24);
+    win |= (uint64_t)be << (32 - wn);
+    wn += 32;
   }
   __device__ int get() {
-    int b = (int)(win >> 63);
-    win <<= 1; wn--; pos++;
-    if (wn <= 56) refill();
+    const int b = (int)(win >> 63);
+    win <<= 1;
+    if (--wn < 32) refill();
     return b;
   }
-  // leading zeros among the next bits (at most 57)
+  // leading zeros among the valid bits
   __device__ int zeros() {
-    int z = win ? __builtin_clzll(win) : 64;
+    const int z = win ? __builtin_clzll(win) : 64;
     return z < wn ? z : wn;
   }
+  // n <= wn
   __device__ void skip(int n) {
-    while (n > 0) {
-      int s = n < 32 ? n : 32;
-      win <<= s; wn -= s; pos += s; n -= s;
-      if (wn <= 56) refill();
-    }
-  }
-  // jump to an absolute bit position >= pos
-  __device__ void seek(int64_t p) {
-    pos = p; win = 0; wn = 0;
-    bytepos = p >> 3;
-    refill();
-    int drop = (int)(p & 7);
-    win <<= drop; wn -= drop;
-    if (wn <= 56) refill();
+    win = n < 64 ? win << n : 0;
+    wn -= n;
+    if (wn < 32) refill();
   }
 };
 
