@@ -503,7 +503,7 @@ struct Plan {
   int max_tile_coef = 0, max_tile_parents = 0;
   // tile indices grouped by SPIHT kernel class: LDS small, LDS big, global
   std::vector<int> tix;
-  int ncls[3] = {0, 0, 0};
+  int ncls[4] = {0, 0, 0, 0};   // small, big, global lists, huge
   int* d_tix = nullptr;
   ~Plan() {
     if (d_bands) (void)hipFree(d_bands);
@@ -572,7 +572,7 @@ static int build_plan(Plan& p) {
       p.max_tile_coef = std::max(p.max_tile_coef, (int)n);
       p.max_tile_parents = std::max(p.max_tile_parents, (int)(L > 0 ? n - n1 : 0));
       int64_t need = std::max<int64_t>(n, 2 * (L > 0 ? n - n1 : 0));
-      tcls.push_back(need <= kSpihtSmall ? 0 : (need <= kSpihtBig ? 1 : 2));
+      tcls.push_back(need <= kSpihtSmall ? 0 : (need <= kSpihtBig ? 1 : (need <= kSpihtHuge ? 3 : 2)));
       t.field = 0;
       off += n;
       soff += 12 * n + 16;
@@ -580,7 +580,7 @@ static int build_plan(Plan& p) {
       p.slot_off.push_back(soff);
     }
   p.ntiles = (int)p.tiles.size();
-  for (int k = 0; k < 3; k++)
+  for (int k = 0; k < 4; k++)
     for (int t = 0; t < p.ntiles; t++)
       if (tcls[t] == k) { p.tix.push_back(t); p.ncls[k]++; }
   if (off != (int64_t)ny * nx) return fail(EBCC_EINVAL, "internal: SPIHT trees do not cover the field");
@@ -790,7 +790,7 @@ struct Call {
   bool need_lists = false, forced_global = false;
   int cbw = 32, cbh = 32;
   const int* d_tix = nullptr;   // tile indices by class (see Plan::tix)
-  int ncls[3] = {0, 0, 0};
+  int ncls[4] = {0, 0, 0, 0};
   // per-item arrays
   void *planes, *signs, *sppf;
   uint8_t *pb, *kb, *hk, *nh, *cw, *slots;
@@ -953,7 +953,7 @@ static int upload_items(Call& c, const std::vector<int>& coded) {
     c.d_tiles = c.plans[0]->d_tiles;
     c.d_slot_off = c.plans[0]->d_slot_off;
     c.d_tix = c.plans[0]->d_tix;
-    for (int k = 0; k < 3; k++) c.ncls[k] = c.plans[0]->ncls[k];
+    for (int k = 0; k < 4; k++) c.ncls[k] = c.plans[0]->ncls[k];
     return EBCC_OK;
   }
   std::vector<Blk> blks;
@@ -979,7 +979,7 @@ static int upload_items(Call& c, const std::vector<int>& coded) {
   }
   std::vector<int> tix;
   tix.reserve(c.ntiles);
-  for (int k = 0; k < 3; k++) {
+  for (int k = 0; k < 4; k++) {
     c.ncls[k] = 0;
     for (int i : ci) {
       const Plan* p = c.plans[i];
@@ -1323,10 +1323,11 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
         spiht_encode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, st);
       } else {
         // the classes run concurrently: big and global tiles on the second stream
-        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1];
+        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
         hipStream_t sa = c.ws->aux;
         if ((rc = c.fork())) return rc;
         spiht_encode(c.F, c.d_tiles, t2, c.ncls[2], c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, sa);
+        spiht_encode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, sa);
         spiht_encode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, sa);
         spiht_encode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, st);
         if ((rc = c.join())) return rc;
@@ -1604,9 +1605,10 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
       if (c.forced_global) {
         spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, sa);
       } else {
-        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1];
-        spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sa);
+        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
         spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sa);
+        spiht_decode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.toff, c.misfit, sa);
+        spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sa);
         spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, sa);
       }
     }

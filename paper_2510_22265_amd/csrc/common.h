@@ -158,10 +158,14 @@ void spiht_encode(const FieldDev* F, const TileD* tiles, const int* tix, int nti
 // toff: payload offsets after each field's tile table.
 void spiht_decode(const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
                   uint64_t* lists, hipStream_t st);
-// spihtwave.hip: one wavefront per tile with the tile in LDS, in two capacity
-// classes (coefficients of the tile's trees, and twice its parents, must fit).
+// spihtwave.hip: one wavefront per tile with the tile in LDS, in three
+// capacity classes (coefficients of the tile's trees, and twice its parents,
+// must fit): small and big for the usual one-root tiles of 5 and 6 levels,
+// huge (one wavefront per compute unit) for the edge tiles that take the
+// extra row or column of odd-sized bands.
 constexpr int kSpihtSmall = 1280;
 constexpr int kSpihtBig = 4608;
+constexpr int kSpihtHuge = 12288;
 // Each SPIHT launch covers the tiles tix[0 .. ntix) of the call's tile array
 // (tiles are launched in capacity classes).
 void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint8_t* slots,

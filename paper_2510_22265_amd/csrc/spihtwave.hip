@@ -648,8 +648,10 @@ void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, const int*
   if (ntix <= 0) return;
   if (cap == kSpihtSmall)
     k_spiht_encode_lds<kSpihtSmall><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, misfit);
-  else
+  else if (cap == kSpihtBig)
     k_spiht_encode_lds<kSpihtBig><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, misfit);
+  else
+    k_spiht_encode_lds<kSpihtHuge><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, misfit);
 }
 
 void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
@@ -657,8 +659,10 @@ void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, const int*
   if (ntix <= 0) return;
   if (cap == kSpihtSmall)
     k_spiht_decode_lds<kSpihtSmall><<<ntix, 64, 0, st>>>(F, tiles, tix, toff, misfit);
-  else
+  else if (cap == kSpihtBig)
     k_spiht_decode_lds<kSpihtBig><<<ntix, 64, 0, st>>>(F, tiles, tix, toff, misfit);
+  else
+    k_spiht_decode_lds<kSpihtHuge><<<ntix, 64, 0, st>>>(F, tiles, tix, toff, misfit);
 }
 
 }  // namespace ebcc
