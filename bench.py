@@ -42,9 +42,9 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 # measured (checked by hash); otherwise traffic is reported as null.
 MEASURED_TRAFFIC = {
     "t1_encode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
-                  "sha256": "1bec147a73172eac890a04b479db0e0a424dfb03bff96a9bf01915babd006f9a",
+                  "sha256": "ff6617f2d28be1dcf87c9a91050f1e0f0a347c608b971dd7ebed57026cf7e073",
                   "ny": 721, "nx": 1440, "eps": 0.01,
-                  "bytes": (2.0 * (4530.3 + 4312.4) / 2 + 1.0 * (978.3 + 1231.4) / 2) * 1024},
+                  "bytes": (2.0 * (4510.7 + 4308.9) / 2 + 1.0 * (975.7 + 1230.8) / 2) * 1024},
 }
 
 
