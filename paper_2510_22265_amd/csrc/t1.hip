@@ -174,6 +174,18 @@ struct T1Shared {
   M sig[ROWS][LANES], vis[ROWS][LANES], ref[ROWS][LANES], neg[ROWS][LANES], mag[ROWS][LANES], aux[ROWS][LANES];
   uint8_t ctx[kNCtx][LANES];
   uint32_t mqt[47];
+  // context labels by neighbourhood pattern: zero coding for LL/LH, HL and
+  // HH blocks, and sign coding ((label - 9) | XOR bit << 3)
+  uint8_t zct[3][512];
+  uint8_t sct[256];
+  __device__ void fill_tables(int t, int n) {
+    for (int i = t; i < 47; i += n) mqt[i] = c_mqt[i];
+    for (int i = t; i < 3 * 512; i += n) {
+      const int c = i >> 9;
+      zct[c][i & 511] = (uint8_t)zc_entry(c == 0 ? ORI_LL : (c == 1 ? ORI_HL : ORI_HH), (uint32_t)(i & 511));
+    }
+    for (int i = t; i < 256; i += n) sct[i] = (uint8_t)sc_entry((uint32_t)i);
+  }
 };
 
 template <typename M, int ROWS, int LANES>
@@ -181,22 +193,17 @@ struct T1Lane {
   T1Shared<M, ROWS, LANES>& S;
   int lane, h, w, orient;
   __device__ M row(M (*a)[LANES], int y) const { return (y >= 0 && y < h) ? a[y][lane] : (M)0; }
-  __device__ void counts(int y, int x, int& H, int& V, int& D) const {
-    M up = row(S.sig, y - 1), mid = S.sig[y][lane], dn = row(S.sig, y + 1);
-    H = bt(mid, x - 1) + bt(mid, x + 1);
-    V = bt(up, x) + bt(dn, x);
-    D = bt(up, x - 1) + bt(up, x + 1) + bt(dn, x - 1) + bt(dn, x + 1);
+  // neighbourhood pattern of sample (y, x) (zc_pat)
+  __device__ uint32_t zpat(int y, int x) const {
+    return zc_pat(f3(row(S.sig, y - 1), x), f3(S.sig[y][lane], x), f3(row(S.sig, y + 1), x));
   }
-  __device__ int sgn(int y, int x) const {   // sign contribution of a neighbour
-    if (y < 0 || y >= h || !bt(S.sig[y][lane], x)) return 0;
-    return bt(S.neg[y][lane], x) ? -1 : 1;
-  }
+  __device__ const uint8_t* ztab() const { return S.zct[orient == ORI_HH ? 2 : (orient == ORI_HL ? 1 : 0)]; }
   __device__ int sign_ctx(int y, int x, int* xr) const {
-    int hc = sgn(y, x - 1) + sgn(y, x + 1);
-    int vc = sgn(y - 1, x) + sgn(y + 1, x);
-    hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
-    vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
-    return sc_ctx(hc, vc, xr);
+    const uint32_t e = S.sct[sc_pat(f3(S.sig[y][lane], x), f3(S.neg[y][lane], x), (uint32_t)bt(row(S.sig, y - 1), x),
+                                    (uint32_t)bt(row(S.neg, y - 1), x), (uint32_t)bt(row(S.sig, y + 1), x),
+                                    (uint32_t)bt(row(S.neg, y + 1), x))];
+    *xr = (int)(e >> 3);
+    return CX_SC + (int)(e & 7u);
   }
   // columns of stripe y0 (rn rows) holding a sample with sig = 0 and at
   // least one significant neighbour, restricted to columns >= x
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
                                                      uint32_t* __restrict__ tailt, M* __restrict__ sppf) {
   __shared__ T1Shared<M, ROWS, LANES> S;
   int lane = threadIdx.x;
-  for (int i = lane; i < 47; i += LANES) S.mqt[i] = c_mqt[i];
+  S.fill_tables(lane, LANES);
   __syncthreads();
   int b = blockIdx.x * LANES + lane;
   if (b >= nblk) return;
@@ -253,6 +260,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
     return;
   }
   T1Lane<M, ROWS, LANES> T{S, lane, k.h, k.w, k.orient};
+  const uint8_t* zt = T.ztab();
   for (int y = 0; y < k.h; y++) {
     S.sig[y][lane] = 0; S.vis[y][lane] = 0; S.ref[y][lane] = 0; S.aux[y][lane] = 0;
     S.neg[y][lane] = signs[(size_t)b * cbh + y];
@@ -290,11 +298,10 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
               int y = y0 + r;
               M mid = S.sig[y][lane];
               if (bt(mid, x)) continue;
-              int H, V, D;
-              T.counts(y, x, H, V, D);
-              if (H + V + D == 0) continue;
+              const uint32_t pat = T.zpat(y, x);
+              if (!pat) continue;
               int bit = bt(S.mag[y][lane], x);
-              mq_enc(&S.ctx[zc_ctx(k.orient, H, V, D)][lane], bit);
+              mq_enc(&S.ctx[zt[pat]][lane], bit);
               S.vis[y][lane] |= (M)1 << x;
               if (bit) {
                 code_sign(y, x);
@@ -316,7 +323,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
               if (!bt(S.sig[y][lane] & ~S.vis[y][lane], x)) continue;
               int cx;
               if (bt(S.ref[y][lane], x)) cx = CX_MR + 2;
-              else { int H, V, D; T.counts(y, x, H, V, D); cx = (H + V + D) ? CX_MR + 1 : CX_MR; }
+              else cx = (T.zpat(y, x) & ~0x10u) ? CX_MR + 1 : CX_MR;
               mq_enc(&S.ctx[cx][lane], bt(S.mag[y][lane], x));
               S.ref[y][lane] |= (M)1 << x;
               dd += ref_delta(qat(y, x), p);
@@ -348,10 +355,8 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
             for (; r < rn; r++) {
               int y = y0 + r;
               if (bt(S.sig[y][lane] | S.vis[y][lane], x)) continue;
-              int H, V, D;
-              T.counts(y, x, H, V, D);
               int bit = bt(S.mag[y][lane], x);
-              mq_enc(&S.ctx[zc_ctx(k.orient, H, V, D)][lane], bit);
+              mq_enc(&S.ctx[zt[T.zpat(y, x)]][lane], bit);
               if (bit) {
                 code_sign(y, x);
                 S.sig[y][lane] |= (M)1 << x;
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
                                                      const int64_t* __restrict__ off) {
   __shared__ T1Shared<M, ROWS, LANES> S;     // aux = coded in the current plane
   int lane = threadIdx.x;
-  for (int i = lane; i < 47; i += LANES) S.mqt[i] = c_mqt[i];
+  S.fill_tables(lane, LANES);
   __syncthreads();
   int b = blockIdx.x * LANES + lane;
   if (b >= nblk) return;
@@ -520,6 +525,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
     return;
   }
   T1Lane<M, ROWS, LANES> T{S, lane, k.h, k.w, k.orient};
+  const uint8_t* zt = T.ztab();
   for (int y = 0; y < k.h; y++) {
     S.sig[y][lane] = 0; S.vis[y][lane] = 0; S.ref[y][lane] = 0; S.neg[y][lane] = 0; S.aux[y][lane] = 0;
   }
@@ -551,10 +557,9 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
               int y = y0 + r;
               M mid = S.sig[y][lane];
               if (bt(mid, x)) continue;
-              int H, V, D;
-              T.counts(y, x, H, V, D);
-              if (H + V + D == 0) continue;
-              int bit = mq_dec(&S.ctx[zc_ctx(k.orient, H, V, D)][lane]);
+              const uint32_t pat = T.zpat(y, x);
+              if (!pat) continue;
+              int bit = mq_dec(&S.ctx[zt[pat]][lane]);
               S.vis[y][lane] |= (M)1 << x;
               if (bit) {
                 dec_sign(y, x);
@@ -576,7 +581,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
               if (!bt(S.sig[y][lane] & ~S.vis[y][lane], x)) continue;
               int cx;
               if (bt(S.ref[y][lane], x)) cx = CX_MR + 2;
-              else { int H, V, D; T.counts(y, x, H, V, D); cx = (H + V + D) ? CX_MR + 1 : CX_MR; }
+              else cx = (T.zpat(y, x) & ~0x10u) ? CX_MR + 1 : CX_MR;
               int bit = mq_dec(&S.ctx[cx][lane]);
               if (bit) mb[y * nx + x] |= 1u << p;
               S.ref[y][lane] |= (M)1 << x;
@@ -607,9 +612,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
             for (; r < rn; r++) {
               int y = y0 + r;
               if (bt(S.sig[y][lane] | S.vis[y][lane], x)) continue;
-              int H, V, D;
-              T.counts(y, x, H, V, D);
-              int bit = mq_dec(&S.ctx[zc_ctx(k.orient, H, V, D)][lane]);
+              int bit = mq_dec(&S.ctx[zt[T.zpat(y, x)]][lane]);
               if (bit) {
                 dec_sign(y, x);
                 S.sig[y][lane] |= (M)1 << x;

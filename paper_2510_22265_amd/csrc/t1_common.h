@@ -67,6 +67,56 @@ __device__ __forceinline__ M nb3(int x) {   // bits x-1, x, x+1
   return m;
 }
 
+// Bits x-1, x, x+1 of a row mask as bits 0, 1, 2 (0 outside the row), and
+// the neighbourhood counts of T.800 Table D.1 from three such fields.
+template <typename M>
+__device__ __forceinline__ uint32_t f3(M m, int x) {
+  return x > 0 ? (uint32_t)(m >> (x - 1)) & 7u : (uint32_t)(m << 1) & 7u;
+}
+template <>
+__device__ __forceinline__ uint32_t f3<uint32_t>(uint32_t m, int x) {
+  return (uint32_t)((((uint64_t)m) << 1) >> x) & 7u;
+}
+template <typename M>
+__device__ __forceinline__ int btu(M m, int x) { return (int)((m >> x) & 1); }   // 0 <= x < bits
+struct HVD { int h, v, d; bool any; };
+__device__ __forceinline__ HVD hvd(uint32_t u3, uint32_t m3, uint32_t d3) {
+  HVD r;
+  r.h = __builtin_popcount(m3 & 5u);
+  r.v = (int)((u3 >> 1) & 1u) + (int)((d3 >> 1) & 1u);
+  r.d = __builtin_popcount(u3 & 5u) + __builtin_popcount(d3 & 5u);
+  r.any = ((u3 | d3 | (m3 & 5u)) != 0u);
+  return r;
+}
+
+// Neighbourhood pattern of a sample: u3 | m3 << 3 | d3 << 6 (the f3 fields
+// of the rows above, at and below it); with the sample's own bit 0 it is
+// nonzero iff a neighbour is significant.
+__device__ __forceinline__ uint32_t zc_pat(uint32_t u3, uint32_t m3, uint32_t d3) { return u3 | (m3 << 3) | (d3 << 6); }
+// Zero-coding label of a pattern (T.800 Table D.1).
+__device__ __forceinline__ int zc_entry(int orient, uint32_t pat) {
+  const HVD n = hvd(pat & 7u, (pat >> 3) & 7u, pat >> 6);
+  return zc_ctx(orient, n.h, n.v, n.d);
+}
+// Sign-coding pattern: the four neighbours' (significant, negative) bits,
+// left | right | above | below as sl | nl << 1 | sr << 2 | nr << 3 | su << 4 |
+// nu << 5 | sd << 6 | nd << 7, from the f3 fields of the sample's own row
+// (sm significance, nm sign) and the bits above and below.
+__device__ __forceinline__ uint32_t sc_pat(uint32_t sm, uint32_t nm, uint32_t su, uint32_t nu, uint32_t sd,
+                                           uint32_t nd) {
+  return (sm & 5u) | ((nm & 5u) << 1) | (su << 4) | (nu << 5) | (sd << 6) | (nd << 7);
+}
+// (label - 9) | XOR bit << 3 of a sign-coding pattern (T.800 Table D.3).
+__device__ __forceinline__ uint32_t sc_entry(uint32_t pat) {
+  auto c = [&](int sh) { return (pat >> sh) & 1u ? (((pat >> (sh + 1)) & 1u) ? -1 : 1) : 0; };
+  int hc = c(0) + c(2), vc = c(4) + c(6);
+  hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
+  vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
+  int xr;
+  const int cx = sc_ctx(hc, vc, &xr);
+  return (uint32_t)((cx - CX_SC) | (xr << 3));
+}
+
 // Squared-error reductions (units of (step/2)^2) when a sample of magnitude q
 // becomes significant at plane p, or is refined at plane p.
 __device__ __forceinline__ int64_t sig_delta(uint32_t q, int p) {

@@ -146,42 +146,14 @@ __device__ __forceinline__ uint64_t lane_ptr(uint32_t pv, int i) {
   return (uint64_t)rdl32(pv, 2 * i) | ((uint64_t)rdl32(pv, 2 * i + 1) << 32);
 }
 
-// Bits x-1, x, x+1 of a row mask as bits 0, 1, 2 (0 outside the row), and
-// the neighbourhood counts of T.800 Table D.1 from three such fields.
-template <typename M>
-__device__ __forceinline__ uint32_t f3(M m, int x) {
-  return x > 0 ? (uint32_t)(m >> (x - 1)) & 7u : (uint32_t)(m << 1) & 7u;
-}
-template <>
-__device__ __forceinline__ uint32_t f3<uint32_t>(uint32_t m, int x) {
-  return (uint32_t)((((uint64_t)m) << 1) >> x) & 7u;
-}
-template <typename M>
-__device__ __forceinline__ int btu(M m, int x) { return (int)((m >> x) & 1); }   // 0 <= x < bits
-struct HVD { int h, v, d; bool any; };
-__device__ __forceinline__ HVD hvd(uint32_t u3, uint32_t m3, uint32_t d3) {
-  HVD r;
-  r.h = __builtin_popcount(m3 & 5u);
-  r.v = (int)((u3 >> 1) & 1u) + (int)((d3 >> 1) & 1u);
-  r.d = __builtin_popcount(u3 & 5u) + __builtin_popcount(d3 & 5u);
-  r.any = ((u3 | d3 | (m3 & 5u)) != 0u);
-  return r;
-}
-
 // Zero-coding contexts as a table in one vector register: the neighbourhood
 // pattern u3 | m3 << 3 | d3 << 6 (three f3 fields of the rows above, at and
 // below the sample) indexes 512 four-bit labels, eight per lane.
 __device__ __forceinline__ uint32_t zc_table(int orient, int lane) {
   uint32_t t = 0;
-  for (int j = 0; j < 8; j++) {
-    const uint32_t pat = 8u * (uint32_t)lane + (uint32_t)j;
-    const HVD n = hvd(pat & 7u, (pat >> 3) & 7u, pat >> 6);
-    t |= (uint32_t)zc_ctx(orient, n.h, n.v, n.d) << (4 * j);
-  }
+  for (int j = 0; j < 8; j++) t |= (uint32_t)zc_entry(orient, 8u * (uint32_t)lane + (uint32_t)j) << (4 * j);
   return t;
 }
-// Pattern of a sample whose own bit is 0: nonzero iff a neighbour is significant.
-__device__ __forceinline__ uint32_t zc_pat(uint32_t u3, uint32_t m3, uint32_t d3) { return u3 | (m3 << 3) | (d3 << 6); }
 __device__ __forceinline__ int zc_look(uint32_t zct, uint32_t pat) {
   return (int)((rdl32(zct, (int)(pat >> 3)) >> (4u * (pat & 7u))) & 15u);
 }
@@ -192,23 +164,14 @@ __device__ __forceinline__ int zc_look(uint32_t zct, uint32_t pat) {
 // indexes 256 entries of (label - 9) | XOR bit << 3, eight per lane.
 __device__ __forceinline__ uint32_t sc_table(int lane) {
   uint32_t t = 0;
-  for (int j = 0; j < 8; j++) {
-    const uint32_t pat = 8u * (uint32_t)lane + (uint32_t)j;
-    auto c = [&](int sh) { return (pat >> sh) & 1u ? (((pat >> (sh + 1)) & 1u) ? -1 : 1) : 0; };
-    int hc = c(0) + c(2), vc = c(4) + c(6);
-    hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
-    vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
-    int xr;
-    const int cx = sc_ctx(hc, vc, &xr);
-    t |= (uint32_t)((cx - CX_SC) | (xr << 3)) << (4 * j);
-  }
+  for (int j = 0; j < 8; j++) t |= sc_entry(8u * (uint32_t)lane + (uint32_t)j) << (4 * j);
   return lane < 32 ? t : 0u;
 }
 // sm, nm: f3 fields of the sample's own row (significance, sign); su, nu,
 // sd, nd: the bits above and below.
 __device__ __forceinline__ uint32_t sc_look(uint32_t sct, uint32_t sm, uint32_t nm, uint32_t su, uint32_t nu,
                                             uint32_t sd, uint32_t nd) {
-  const uint32_t pat = (sm & 5u) | ((nm & 5u) << 1) | (su << 4) | (nu << 5) | (sd << 6) | (nd << 7);
+  const uint32_t pat = sc_pat(sm, nm, su, nu, sd, nd);
   return (rdl32(sct, (int)(pat >> 3)) >> (4u * (pat & 7u))) & 15u;
 }
 
