@@ -228,6 +228,10 @@ struct T1Lane {
   }
 };
 
+// Row r' in [-1, 4] of the current stripe's significance / sign rows.
+#define SR(rr) ((rr) < 0 ? sA : ((rr) > 3 ? sC : sB[(rr)]))
+#define NR(rr) ((rr) < 0 ? nA : ((rr) > 3 ? nC : nB[(rr)]))
+
 // ------------------------------------------------------------------------
 // Tier-1 encoder: one lane per code-block.
 // ------------------------------------------------------------------------
@@ -273,102 +277,161 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
   const float* cb = coef + (size_t)k.y0 * nx + k.x0;
   auto qat = [&](int y, int x) { return quantq(cb[y * nx + x], sh); };
   auto mq_enc = [&](uint8_t* cs, int bit) { mq_encode(e, cs, bit, S.mqt); };
-  auto code_sign = [&](int y, int x) {
-    int xr;
-    int cx = T.sign_ctx(y, x, &xr);
-    mq_enc(&S.ctx[cx][lane], bt(S.neg[y][lane], x) ^ xr);
-  };
   int npass = 3 * P - 2, kk = 0;
   bool stop = false;
   int64_t Dcum = 0;
+  const int h = k.h, w = k.w;
+  const M wm = (w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << w) - 1);
+  auto rowm = [&](M (*a)[LANES], int y) -> M { return (y >= 0 && y < h) ? a[y][lane] : (M)0; };
   for (int p = P - 1; p >= 0 && !stop; p--) {
     const M* pl = planes + ((size_t)b * kQBits + p) * cbh;
-    for (int y = 0; y < k.h; y++) S.mag[y][lane] = pl[y];
+    for (int y = 0; y < h; y++) S.mag[y][lane] = pl[y];
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
       int64_t dd = 0;
-      for (int y0 = 0; y0 < k.h && !stop; y0 += 4) {
-        int rn = k.h - y0 < 4 ? k.h - y0 : 4;
-        if (ty == 0) {                         // significance propagation
-          int x = 0;
-          while (x < k.w) {
-            M c = T.spp_cands(y0, rn, x);
-            if (!c) break;
-            x = ctzm(c);
-            for (int r = 0; r < rn; r++) {
-              int y = y0 + r;
-              M mid = S.sig[y][lane];
-              if (bt(mid, x)) continue;
-              const uint32_t pat = T.zpat(y, x);
+      // the stripe's rows (and the rows above and below) are held in
+      // registers while the stripe is coded, then written back
+      for (int y0 = 0; y0 < h && !stop; y0 += 4) {
+        const int rn = h - y0 < 4 ? h - y0 : 4;
+        const M sA = rowm(S.sig, y0 - 1), sC = rowm(S.sig, y0 + 4);
+        const M nA = rowm(S.neg, y0 - 1), nC = rowm(S.neg, y0 + 4);
+        M sB[4], vB[4], fB[4], gB[4], nB[4], aB[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const bool in = r < rn;
+          sB[r] = in ? S.sig[y0 + r][lane] : (M)0;
+          vB[r] = in ? S.vis[y0 + r][lane] : (M)0;
+          fB[r] = (in && ty == 1) ? S.ref[y0 + r][lane] : (M)0;
+          gB[r] = in ? S.mag[y0 + r][lane] : (M)0;
+          nB[r] = in ? S.neg[y0 + r][lane] : (M)0;
+          aB[r] = 0;
+        }
+        // r is a compile-time constant in every caller (unrolled loops)
+        auto code_sign = [&](int r, int x) {
+          const uint32_t sc = S.sct[sc_pat(f3(SR(r), x), f3(NR(r), x), (uint32_t)btu(SR(r - 1), x),
+                                           (uint32_t)btu(NR(r - 1), x), (uint32_t)btu(SR(r + 1), x),
+                                           (uint32_t)btu(NR(r + 1), x))];
+          mq_enc(&S.ctx[CX_SC + (int)(sc & 7u)][lane], btu(nB[r], x) ^ (int)(sc >> 3));
+        };
+        if (ty == 0) {                                   // significance propagation
+          // candidate columns at the stripe start; a sample that becomes
+          // significant in column x can only add column x + 1
+          M c = 0;
+#pragma unroll
+          for (int r = 0; r < 4; r++)
+            if (r < rn) {
+              M nb = SR(r - 1) | SR(r) | SR(r + 1);
+              nb = nb | (nb << 1) | (nb >> 1);
+              c |= ~SR(r) & nb;
+            }
+          c &= wm;
+          while (c) {
+            const int x = ctzm(c);
+            c &= c - 1;
+            bool grew = false;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r >= rn) continue;
+              const M mid = sB[r];
+              if (btu(mid, x)) continue;
+              const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
               if (!pat) continue;
-              int bit = bt(S.mag[y][lane], x);
+              const int bit = btu(gB[r], x);
               mq_enc(&S.ctx[zt[pat]][lane], bit);
-              S.vis[y][lane] |= (M)1 << x;
+              vB[r] |= (M)1 << x;
               if (bit) {
-                code_sign(y, x);
-                S.sig[y][lane] = mid | ((M)1 << x);
-                S.aux[y][lane] |= (M)1 << x;
-                dd += sig_delta(qat(y, x), p);
+                code_sign(r, x);
+                sB[r] = mid | ((M)1 << x);
+                aB[r] |= (M)1 << x;
+                dd += sig_delta(qat(y0 + r, x), p);
+                grew = true;
               }
             }
-            x++;
+            if (grew && x + 1 < w) c |= (M)1 << (x + 1);
           }
-        } else if (ty == 1) {                  // magnitude refinement
+        } else if (ty == 1) {                            // magnitude refinement
+          M nbm[4];
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const M v = SR(r - 1) | SR(r + 1);
+            nbm[r] = (SR(r) << 1) | (SR(r) >> 1) | v | (v << 1) | (v >> 1);
+          }
           M mk = 0;
-          for (int r = 0; r < rn; r++) mk |= S.sig[y0 + r][lane] & ~S.vis[y0 + r][lane];
+#pragma unroll
+          for (int r = 0; r < 4; r++) mk |= sB[r] & ~vB[r];
           while (mk) {
-            int x = ctzm(mk);
+            const int x = ctzm(mk);
             mk &= mk - 1;
-            for (int r = 0; r < rn; r++) {
-              int y = y0 + r;
-              if (!bt(S.sig[y][lane] & ~S.vis[y][lane], x)) continue;
-              int cx;
-              if (bt(S.ref[y][lane], x)) cx = CX_MR + 2;
-              else cx = (T.zpat(y, x) & ~0x10u) ? CX_MR + 1 : CX_MR;
-              mq_enc(&S.ctx[cx][lane], bt(S.mag[y][lane], x));
-              S.ref[y][lane] |= (M)1 << x;
-              dd += ref_delta(qat(y, x), p);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r >= rn || !btu(sB[r] & ~vB[r], x)) continue;
+              const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nbm[r], x) ? CX_MR + 1 : CX_MR);
+              mq_enc(&S.ctx[cx][lane], btu(gB[r], x));
+              fB[r] |= (M)1 << x;
+              dd += ref_delta(qat(y0 + r, x), p);
             }
           }
-        } else {                               // cleanup
+        } else {                                         // cleanup
           M u = 0;
-          for (int r = 0; r < rn; r++) u |= ~(S.sig[y0 + r][lane] | S.vis[y0 + r][lane]);
-          M wm = (k.w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << k.w) - 1);
+#pragma unroll
+          for (int r = 0; r < 4; r++)
+            if (r < rn) u |= ~(sB[r] | vB[r]);
           u &= wm;
           while (u) {
-            int x = ctzm(u);
+            const int x = ctzm(u);
             u &= u - 1;
-            int r = 0;
-            if (rn == 4 && T.run_ok(y0, x)) {
-              int rr = -1;
-              for (int t = 0; t < 4; t++)
-                if (bt(S.mag[y0 + t][lane], x)) { rr = t; break; }
-              mq_enc(&S.ctx[CX_RL][lane], rr >= 0);
-              if (rr < 0) continue;
-              mq_enc(&S.ctx[CX_UNI][lane], (rr >> 1) & 1);
-              mq_enc(&S.ctx[CX_UNI][lane], rr & 1);
-              int y = y0 + rr;
-              code_sign(y, x);
-              S.sig[y][lane] |= (M)1 << x;
-              dd += sig_delta(qat(y, x), p);
-              r = rr + 1;
+            int rstart = 0;
+            if (rn == 4) {
+              bool run = true;
+#pragma unroll
+              for (int r = 0; r < 4; r++)
+                if (btu(sB[r] | vB[r], x)) run = false;
+              if (run && ((sA | sB[0] | sB[1] | sB[2] | sB[3] | sC) & nb3<M>(x))) run = false;
+              if (run) {
+                int rr = -1;
+#pragma unroll
+                for (int r = 3; r >= 0; r--)
+                  if (btu(gB[r], x)) rr = r;
+                mq_enc(&S.ctx[CX_RL][lane], rr >= 0);
+                if (rr < 0) continue;
+                mq_enc(&S.ctx[CX_UNI][lane], (rr >> 1) & 1);
+                mq_enc(&S.ctx[CX_UNI][lane], rr & 1);
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                  if (r == rr) {
+                    code_sign(r, x);
+                    sB[r] |= (M)1 << x;
+                    dd += sig_delta(qat(y0 + r, x), p);
+                  }
+                rstart = rr + 1;
+              }
             }
-            for (; r < rn; r++) {
-              int y = y0 + r;
-              if (bt(S.sig[y][lane] | S.vis[y][lane], x)) continue;
-              int bit = bt(S.mag[y][lane], x);
-              mq_enc(&S.ctx[zt[T.zpat(y, x)]][lane], bit);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r < rstart || r >= rn) continue;
+              if (btu(sB[r] | vB[r], x)) continue;
+              const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(sB[r], x), f3(SR(r + 1), x));
+              const int bit = btu(gB[r], x);
+              mq_enc(&S.ctx[zt[pat]][lane], bit);
               if (bit) {
-                code_sign(y, x);
-                S.sig[y][lane] |= (M)1 << x;
-                dd += sig_delta(qat(y, x), p);
+                code_sign(r, x);
+                sB[r] |= (M)1 << x;
+                dd += sig_delta(qat(y0 + r, x), p);
               }
             }
           }
         }
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          if (r < rn) {
+            S.sig[y0 + r][lane] = sB[r];
+            S.vis[y0 + r][lane] = vB[r];
+            if (ty == 1) S.ref[y0 + r][lane] = fB[r];
+            if (ty == 0) S.aux[y0 + r][lane] |= aB[r];
+          }
         if (e.BP >= 65536) stop = true;       // every later pass exceeds the length limit
       }
       if (ty == 2)
-        for (int y = 0; y < k.h; y++) S.vis[y][lane] = 0;
+        for (int y = 0; y < h; y++) S.vis[y][lane] = 0;
       if (stop) break;
       kk++;
       Dcum += dd;
