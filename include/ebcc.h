@@ -194,7 +194,7 @@ const char* ebcc_profile_stage_name(int i);
  *                           global-memory lists for every tile
  *   t1_lanes                lanes-per-block coders: code-blocks per
  *                           wavefront, 0 = by work size, or 1, 4, 16, 64
- *   t1_split                percent (0..100, default 20) of a lanes-per-block
+ *   t1_split                percent (0..100, default 10) of a lanes-per-block
  *                           encoder launch's code-blocks given to the
  *                           wave-per-block coder on a second stream (scalar
  *                           and vector units then work at the same time)

@@ -601,7 +601,7 @@ static int build_plan(Plan& p) {
 // global-memory lists; the environment variable EBCC_SPIHT_KERNEL=global
 // sends every tile to the global-memory kernels (to test both families).
 static std::mutex g_tune_mu;
-static Tuning g_tuning = {0, 0, 32768, 0, 0, 20};
+static Tuning g_tuning = {0, 0, 32768, 0, 0, 10};
 
 Tuning tuning() {
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -597,113 +597,177 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
   MQDec d;
   mq_dinit(d, sec + o, len);
   auto mq_dec = [&](uint8_t* cs) { return mq_decode(d, cs, S.mqt); };
-  auto dec_sign = [&](int y, int x) {
-    int xr;
-    int cx = T.sign_ctx(y, x, &xr);
-    int s = mq_dec(&S.ctx[cx][lane]) ^ xr;
-    if (s) S.neg[y][lane] |= (M)1 << x;
+  const int h = k.h, w = k.w;
+  const M wm = (w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << w) - 1);
+  auto rowm = [&](M (*a)[LANES], int y) -> M { return (y >= 0 && y < h) ? a[y][lane] : (M)0; };
+  // The magnitudes being decoded live in yhat's storage (as integers) until
+  // the block is finished.  Their bits are set with atomic ORs, which need
+  // no read back and so never wait.  Every access to that storage (the
+  // zeroing, the ORs, the final reads) is atomic, so they are ordered per
+  // location without fences.
+  for (int y = 0; y < h; y++)
+    for (int x = 0; x < w; x++) __hip_atomic_store(&mb[y * nx + x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  auto setbit = [&](int y, int x, int p) {
+    (void)__hip_atomic_fetch_or(&mb[y * nx + x], 1u << p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
   int done = 0, plast = P - 1;
   for (int p = P - 1; p >= 0 && done < kb; p--) {
     plast = p;
-    for (int y = 0; y < k.h; y++) S.aux[y][lane] = 0;
+    for (int y = 0; y < h; y++) S.aux[y][lane] = 0;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < kb; ty++) {
-      for (int y0 = 0; y0 < k.h; y0 += 4) {
-        int rn = k.h - y0 < 4 ? k.h - y0 : 4;
-        if (ty == 0) {
-          int x = 0;
-          while (x < k.w) {
-            M c = T.spp_cands(y0, rn, x);
-            if (!c) break;
-            x = ctzm(c);
-            for (int r = 0; r < rn; r++) {
-              int y = y0 + r;
-              M mid = S.sig[y][lane];
-              if (bt(mid, x)) continue;
-              const uint32_t pat = T.zpat(y, x);
+      for (int y0 = 0; y0 < h; y0 += 4) {
+        const int rn = h - y0 < 4 ? h - y0 : 4;
+        const M sA = rowm(S.sig, y0 - 1), sC = rowm(S.sig, y0 + 4);
+        const M nA = rowm(S.neg, y0 - 1), nC = rowm(S.neg, y0 + 4);
+        M sB[4], vB[4], fB[4], nB[4], aB[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const bool in = r < rn;
+          sB[r] = in ? S.sig[y0 + r][lane] : (M)0;
+          vB[r] = in ? S.vis[y0 + r][lane] : (M)0;
+          fB[r] = (in && ty == 1) ? S.ref[y0 + r][lane] : (M)0;
+          nB[r] = in ? S.neg[y0 + r][lane] : (M)0;
+          aB[r] = 0;
+        }
+        // r is a compile-time constant in every caller (unrolled loops)
+        auto dec_sign = [&](int r, int x) {
+          const uint32_t sc = S.sct[sc_pat(f3(SR(r), x), f3(NR(r), x), (uint32_t)btu(SR(r - 1), x),
+                                           (uint32_t)btu(NR(r - 1), x), (uint32_t)btu(SR(r + 1), x),
+                                           (uint32_t)btu(NR(r + 1), x))];
+          if (mq_dec(&S.ctx[CX_SC + (int)(sc & 7u)][lane]) ^ (int)(sc >> 3)) nB[r] |= (M)1 << x;
+        };
+        if (ty == 0) {                                   // significance propagation
+          M c = 0;
+#pragma unroll
+          for (int r = 0; r < 4; r++)
+            if (r < rn) {
+              M nb = SR(r - 1) | SR(r) | SR(r + 1);
+              nb = nb | (nb << 1) | (nb >> 1);
+              c |= ~SR(r) & nb;
+            }
+          c &= wm;
+          while (c) {
+            const int x = ctzm(c);
+            c &= c - 1;
+            bool grew = false;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r >= rn) continue;
+              const M mid = sB[r];
+              if (btu(mid, x)) continue;
+              const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
               if (!pat) continue;
-              int bit = mq_dec(&S.ctx[zt[pat]][lane]);
-              S.vis[y][lane] |= (M)1 << x;
+              const int bit = mq_dec(&S.ctx[zt[pat]][lane]);
+              vB[r] |= (M)1 << x;
               if (bit) {
-                dec_sign(y, x);
-                S.sig[y][lane] = mid | ((M)1 << x);
-                S.aux[y][lane] |= (M)1 << x;
-                mb[y * nx + x] = 1u << p;
+                dec_sign(r, x);
+                sB[r] = mid | ((M)1 << x);
+                aB[r] |= (M)1 << x;
+                setbit(y0 + r, x, p);
+                grew = true;
               }
             }
-            x++;
+            if (grew && x + 1 < w) c |= (M)1 << (x + 1);
           }
-        } else if (ty == 1) {
+        } else if (ty == 1) {                            // magnitude refinement
+          M nbm[4];
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const M v = SR(r - 1) | SR(r + 1);
+            nbm[r] = (SR(r) << 1) | (SR(r) >> 1) | v | (v << 1) | (v >> 1);
+          }
           M mk = 0;
-          for (int r = 0; r < rn; r++) mk |= S.sig[y0 + r][lane] & ~S.vis[y0 + r][lane];
+#pragma unroll
+          for (int r = 0; r < 4; r++) mk |= sB[r] & ~vB[r];
           while (mk) {
-            int x = ctzm(mk);
+            const int x = ctzm(mk);
             mk &= mk - 1;
-            for (int r = 0; r < rn; r++) {
-              int y = y0 + r;
-              if (!bt(S.sig[y][lane] & ~S.vis[y][lane], x)) continue;
-              int cx;
-              if (bt(S.ref[y][lane], x)) cx = CX_MR + 2;
-              else cx = (T.zpat(y, x) & ~0x10u) ? CX_MR + 1 : CX_MR;
-              int bit = mq_dec(&S.ctx[cx][lane]);
-              if (bit) mb[y * nx + x] |= 1u << p;
-              S.ref[y][lane] |= (M)1 << x;
-              S.aux[y][lane] |= (M)1 << x;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r >= rn || !btu(sB[r] & ~vB[r], x)) continue;
+              const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nbm[r], x) ? CX_MR + 1 : CX_MR);
+              if (mq_dec(&S.ctx[cx][lane])) setbit(y0 + r, x, p);
+              fB[r] |= (M)1 << x;
+              aB[r] |= (M)1 << x;
             }
           }
-        } else {
+        } else {                                         // cleanup
           M u = 0;
-          for (int r = 0; r < rn; r++) u |= ~(S.sig[y0 + r][lane] | S.vis[y0 + r][lane]);
-          M wm = (k.w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << k.w) - 1);
+#pragma unroll
+          for (int r = 0; r < 4; r++)
+            if (r < rn) u |= ~(sB[r] | vB[r]);
           u &= wm;
           while (u) {
-            int x = ctzm(u);
+            const int x = ctzm(u);
             u &= u - 1;
-            int r = 0;
-            if (rn == 4 && T.run_ok(y0, x)) {
-              if (!mq_dec(&S.ctx[CX_RL][lane])) continue;
-              int b1 = mq_dec(&S.ctx[CX_UNI][lane]);
-              int b0 = mq_dec(&S.ctx[CX_UNI][lane]);
-              int rr = 2 * b1 + b0;
-              int y = y0 + rr;
-              dec_sign(y, x);
-              S.sig[y][lane] |= (M)1 << x;
-              S.aux[y][lane] |= (M)1 << x;
-              mb[y * nx + x] = 1u << p;
-              r = rr + 1;
+            int rstart = 0;
+            if (rn == 4) {
+              bool run = true;
+#pragma unroll
+              for (int r = 0; r < 4; r++)
+                if (btu(sB[r] | vB[r], x)) run = false;
+              if (run && ((sA | sB[0] | sB[1] | sB[2] | sB[3] | sC) & nb3<M>(x))) run = false;
+              if (run) {
+                if (!mq_dec(&S.ctx[CX_RL][lane])) continue;
+                const int b1 = mq_dec(&S.ctx[CX_UNI][lane]);
+                const int b0 = mq_dec(&S.ctx[CX_UNI][lane]);
+                const int rr = 2 * b1 + b0;
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                  if (r == rr) {
+                    dec_sign(r, x);
+                    sB[r] |= (M)1 << x;
+                    aB[r] |= (M)1 << x;
+                    setbit(y0 + r, x, p);
+                  }
+                rstart = rr + 1;
+              }
             }
-            for (; r < rn; r++) {
-              int y = y0 + r;
-              if (bt(S.sig[y][lane] | S.vis[y][lane], x)) continue;
-              int bit = mq_dec(&S.ctx[zt[T.zpat(y, x)]][lane]);
-              if (bit) {
-                dec_sign(y, x);
-                S.sig[y][lane] |= (M)1 << x;
-                S.aux[y][lane] |= (M)1 << x;
-                mb[y * nx + x] = 1u << p;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              if (r < rstart || r >= rn) continue;
+              if (btu(sB[r] | vB[r], x)) continue;
+              const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(sB[r], x), f3(SR(r + 1), x));
+              if (mq_dec(&S.ctx[zt[pat]][lane])) {
+                dec_sign(r, x);
+                sB[r] |= (M)1 << x;
+                aB[r] |= (M)1 << x;
+                setbit(y0 + r, x, p);
               }
             }
           }
         }
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          if (r < rn) {
+            S.sig[y0 + r][lane] = sB[r];
+            S.vis[y0 + r][lane] = vB[r];
+            S.aux[y0 + r][lane] |= aB[r];
+            if (ty == 1) S.ref[y0 + r][lane] = fB[r];
+            else S.neg[y0 + r][lane] = nB[r];
+          }
       }
       if (ty == 2)
-        for (int y = 0; y < k.h; y++) S.vis[y][lane] = 0;
+        for (int y = 0; y < h; y++) S.vis[y][lane] = 0;
       done++;
     }
   }
   const int e = e0 - k.gain;
-  for (int y = 0; y < k.h; y++) {
+  for (int y = 0; y < h; y++) {
     M sg = S.sig[y][lane], cur = S.aux[y][lane], ng = S.neg[y][lane];
-    for (int x = 0; x < k.w; x++) {
+    for (int x = 0; x < w; x++) {
       float v = 0.0f;
       if (bt(sg, x)) {
         int pk = bt(cur, x) ? plast : plast + 1;
-        v = dequant(mb[y * nx + x], pk, bt(ng, x), e);
+        v = dequant(__hip_atomic_load(&mb[y * nx + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), pk, bt(ng, x), e);
       }
       yb[y * nx + x] = v;
     }
   }
 }
+
+#undef SR
+#undef NR
 
 // ------------------------------------------------------------------------
 // Launchers: mask width follows the code-block width, LDS rows its height,
