@@ -431,9 +431,17 @@ struct GeomRegs {
 __device__ __forceinline__ int rl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ uint32_t rlu(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
 
-// Offspring of node loc (the same in every lane); same results as
-// offspring_local.
-__device__ __forceinline__ int offspring_uniform(const GeomRegs& G, int L, int loc, int* ch, int* clevel) {
+// Offspring of node loc (the same in every lane), described without an
+// array: an LL root's (up to three) children k[0 .. n), or a detail node's
+// children base + r * pitch + c for r in [r0, r1), c in [c0, c1), row-major.
+// Same children, in the same order, as offspring_local.
+struct Kids {
+  int n, clevel;
+  bool ll;
+  int k0, k1, k2;
+  int base, pitch, r0, r1, c0, c1;
+};
+__device__ __forceinline__ void kids_uniform(const GeomRegs& G, int L, int loc, Kids& K) {
   // bands are stored in order of offset: the node's band is the last one
   // starting at or before it
   const int b = __builtin_popcountll(__ballot(G.off <= loc)) - 1;
@@ -442,28 +450,37 @@ __device__ __forceinline__ int offspring_uniform(const GeomRegs& G, int L, int l
   const int wrb = rl(G.wr, b);
   const int li = (int)(((uint64_t)rel * mg) >> 32), lj = rel - li * wrb;
   const int i = rl(G.r0, b) + li, j = rl(G.c0, b) + lj;
-  int k = 0;
+  K.n = 0;
+  K.k0 = K.k1 = K.k2 = 0;
   if (b == 0) {
-    *clevel = L;
-    if (L == 0) return 0;
+    K.ll = true;
+    K.clevel = L;
+    if (L == 0) return;
 #pragma unroll
     for (int c = 1; c <= 3; c++)
-      if (i < rl(G.h, c) && j < rl(G.w, c)) ch[k++] = rl(G.off, c) + (i - rl(G.r0, c)) * rl(G.wr, c) + (j - rl(G.c0, c));
-    return k;
+      if (i < rl(G.h, c) && j < rl(G.w, c)) {
+        const int v = rl(G.off, c) + (i - rl(G.r0, c)) * rl(G.wr, c) + (j - rl(G.c0, c));
+        if (K.n == 0) K.k0 = v;
+        else if (K.n == 1) K.k1 = v;
+        else K.k2 = v;
+        K.n++;
+      }
+    return;
   }
+  K.ll = false;
   const int lev = rl(G.level, b);
-  *clevel = lev - 1;
-  if (lev == 1) return 0;
+  K.clevel = lev - 1;
+  if (lev == 1) return;
   const int cb = b + 3;
   const int hb = rl(G.h, b), wb = rl(G.w, b), hc = rl(G.h, cb), wc = rl(G.w, cb);
   int r1 = (i == hb - 1) ? hc : 2 * i + 2;
   int c1 = (j == wb - 1) ? wc : 2 * j + 2;
   if (r1 > hc) r1 = hc;
   if (c1 > wc) c1 = wc;
-  const int base = rl(G.off, cb) - rl(G.r0, cb) * rl(G.wr, cb) - rl(G.c0, cb), pitch = rl(G.wr, cb);
-  for (int r = 2 * i; r < r1; r++)
-    for (int c = 2 * j; c < c1; c++) ch[k++] = base + r * pitch + c;
-  return k;
+  K.pitch = rl(G.wr, cb);
+  K.base = rl(G.off, cb) - rl(G.r0, cb) * K.pitch - rl(G.c0, cb);
+  K.r0 = 2 * i; K.r1 = r1; K.c0 = 2 * j; K.c1 = c1;
+  K.n = (r1 > 2 * i && c1 > 2 * j) ? (r1 - 2 * i) * (c1 - 2 * j) : 0;
 }
 
 template <int CAP>
@@ -585,28 +602,46 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
         continue;
       }
       const int loc = e & 0x7FFF, typeB = e >> 15;
-      int ch[9], cl = 0;
-      const int no = offspring_uniform(G, L, loc, ch, &cl);
+      Kids K;
+      kids_uniform(G, L, loc, K);
       if (!typeB) {
-        for (int c = 0; c < no; c++) {
+        // each child: its significance bit, and the sign when it is 1
+        const int nc = K.c1 - K.c0;
+        for (int l = 0; l < K.n; l++) {
+          int c;
+          if (K.ll) {
+            c = l == 0 ? K.k0 : (l == 1 ? K.k1 : K.k2);
+          } else {
+            const int r = nc == 1 ? l : (nc == 2 ? l >> 1 : (l * 11) >> 5);   // l / nc, l < 9
+            c = K.base + (K.r0 + r) * K.pitch + K.c0 + (l - r * nc);
+          }
           if (rd.get()) {
-            int sg = rd.get();
-            if (lane == 0) { S.qv[ch[c]] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)ch[c]; }
+            const int sg = rd.get();
+            if (lane == 0) { S.qv[c] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)c; }
             nlsp++;
           } else {
-            if (lane == 0) S.lip[nlip] = (uint16_t)ch[c];
+            if (lane == 0) S.lip[nlip] = (uint16_t)c;
             nlip++;
           }
         }
-        if (no > 0 && cl >= 2) {
+        if (K.n > 0 && K.clevel >= 2) {
           if (lane == 0) S.lis[nlis] = (uint16_t)(loc | 0x8000);
           nlis++;
         }
       } else {
-        for (int c = 0; c < no; c++) {
-          if (lane == 0) S.lis[nlis + c] = (uint16_t)ch[c];
+        // the children join the LIS as type-A entries, one per lane
+        if (lane < K.n) {
+          int v;
+          if (K.ll) {
+            v = lane == 0 ? K.k0 : (lane == 1 ? K.k1 : K.k2);
+          } else {
+            const int nc = K.c1 - K.c0;
+            const int r = nc == 1 ? lane : (nc == 2 ? lane >> 1 : (lane * 11) >> 5);   // lane / nc, lane < 9
+            v = K.base + (K.r0 + r) * K.pitch + K.c0 + (lane - r * nc);
+          }
+          S.lis[nlis + lane] = (uint16_t)v;
         }
-        nlis += no;
+        nlis += K.n;
       }
       head++;
     }
