@@ -42,9 +42,9 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 # measured (checked by hash); otherwise traffic is reported as null.
 MEASURED_TRAFFIC = {
     "t1_encode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
-                  "sha256": "ff6617f2d28be1dcf87c9a91050f1e0f0a347c608b971dd7ebed57026cf7e073",
+                  "sha256": "fb63dcce54237c138d529ec0791ba24af333bac965140f3301e312a09f887904",
                   "ny": 721, "nx": 1440, "eps": 0.01,
-                  "bytes": (2.0 * (4510.7 + 4308.9) / 2 + 1.0 * (975.7 + 1230.8) / 2) * 1024},
+                  "bytes": (2.0 * (4516.9 + 4308.9) / 2 + 1.0 * (976.1 + 1231.5) / 2) * 1024},
 }
 
 
