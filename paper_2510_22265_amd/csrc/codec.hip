@@ -649,18 +649,20 @@ struct WS {
   size_t pin_cap = 0;
   hipEvent_t ev = nullptr;
   bool ev_live = false;
-  // second stream for independent launches of one call (SPIHT tile
-  // classes), ordered against the caller's stream with two events
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // second and third streams for independent launches of one call (SPIHT
+  // tile classes), ordered against the caller's stream with events
+  hipStream_t aux = nullptr, aux2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
   ~WS() {
     if (ev_live) (void)hipEventSynchronize(ev);
     if (base) (void)hipFree(base);
     if (pin) (void)hipHostFree(pin);
     if (ev) (void)hipEventDestroy(ev);
     if (aux) (void)hipStreamDestroy(aux);
+    if (aux2) (void)hipStreamDestroy(aux2);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_join2) (void)hipEventDestroy(ev_join2);
   }
 };
 typedef std::pair<int, hipStream_t> WSKey;
@@ -687,7 +689,9 @@ static int get_ws(hipStream_t st, WS** out) {
     HIPCHK(hipEventCreateWithFlags(&w->ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&w->ev_join2, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&w->aux2, hipStreamNonBlocking));
   }
   // the previous call's staged copies must have left the pinned buffer
   if (w->ev_live) HIPCHK(hipEventSynchronize(w->ev));
@@ -836,16 +840,20 @@ struct Call {
     return EBCC_OK;
   }
   int upload() { return stage(F, Fh.data(), sizeof(FieldDev) * nf); }   // field table host -> device
-  // Work launched on ws->aux between fork() and join() runs concurrently with
-  // the caller's stream and is complete, for that stream, after join().
+  // Work launched on ws->aux and ws->aux2 between fork() and join() runs
+  // concurrently with the caller's stream and is complete, for that stream,
+  // after join().
   int fork() {
     HIPCHK(hipEventRecord(ws->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(ws->aux, ws->ev_fork, 0));
+    HIPCHK(hipStreamWaitEvent(ws->aux2, ws->ev_fork, 0));
     return EBCC_OK;
   }
   int join() {
     HIPCHK(hipEventRecord(ws->ev_join, ws->aux));
+    HIPCHK(hipEventRecord(ws->ev_join2, ws->aux2));
     HIPCHK(hipStreamWaitEvent(st, ws->ev_join, 0));
+    HIPCHK(hipStreamWaitEvent(st, ws->ev_join2, 0));
     return EBCC_OK;
   }
   int set_active(const std::vector<int>& act) {
@@ -1322,13 +1330,15 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
       if (c.forced_global) {
         spiht_encode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, st);
       } else {
-        // the classes run concurrently: big and global tiles on the second stream
+        // the classes run concurrently: global and huge tiles on the second
+        // stream, big tiles on the third, small ones on the caller's
         const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
         hipStream_t sa = c.ws->aux;
         if ((rc = c.fork())) return rc;
         spiht_encode(c.F, c.d_tiles, t2, c.ncls[2], c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, sa);
         spiht_encode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, sa);
-        spiht_encode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, sa);
+        spiht_encode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit,
+                         c.ws->aux2);
         spiht_encode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, st);
         if ((rc = c.join())) return rc;
       }
@@ -1596,7 +1606,7 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
     prof.mark(S_D_PARSE);
     if (anyres) {
       // The residual layer decodes independently of the base layer: SPIHT
-      // runs on the second stream while tier-1 decoding and the base
+      // runs on the second and third streams while tier-1 decoding and the base
       // inverse DWT run on the caller's (the SPIHT kernels skip fields
       // without a residual section).
       k_fill<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, BUF_CHAT, 0.0f);
@@ -1605,10 +1615,12 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
       if (c.forced_global) {
         spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, sa);
       } else {
+        // small tiles on one stream, the larger classes on another
         const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
-        spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sa);
-        spiht_decode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.toff, c.misfit, sa);
-        spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sa);
+        hipStream_t sb = c.ws->aux2;
+        spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sb);
+        spiht_decode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.toff, c.misfit, sb);
+        spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sb);
         spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, sa);
       }
     }
