@@ -268,8 +268,8 @@ def get_tuning():
 
 
 def set_tuning(**kw):
-    """Change kernel choices (t1_encoder, t1_decoder, t1_wave_max, spiht);
-    returns the previous ones."""
+    """Change kernel choices (fields of ebcc_tuning: t1_encoder, t1_decoder,
+    t1_wave_max, spiht, t1_lanes, t1_split); returns the previous ones."""
     old = get_tuning()
     t = Tuning()
     t.struct_size = C.sizeof(Tuning)

@@ -203,6 +203,21 @@ def test_batch_tuning_api(gpu, ref, tun):
         gpu.set_tuning(**old)
 
 
+@pytest.mark.parametrize("lanes", [4, 16, 64])
+@pytest.mark.parametrize("split", [0, 50])
+def test_batch_lanes_per_wavefront(gpu, ref, lanes, split):
+    """The lanes-per-block tier-1 coders with 4, 16 and 64 blocks per
+    wavefront (partly filled wavefronts, ragged and tiny blocks), with and
+    without half the encoder's blocks handed to the wavefront kernel: the
+    oracle's streams and decodes."""
+    old = gpu.set_tuning(t1_encoder=2, t1_decoder=2, t1_lanes=lanes, t1_split=split)
+    try:
+        xs, eps = _mixed_fields()
+        _check_batch(gpu, ref, xs, eps)
+    finally:
+        gpu.set_tuning(**old)
+
+
 def test_autotune_picks_a_measured_candidate(gpu):
     """The autotuner returns one of its measured candidates, respects the
     compression-ratio constraint, and leaves the tuning unchanged."""
