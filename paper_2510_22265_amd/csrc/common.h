@@ -129,7 +129,9 @@ void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
 void t1_decode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, const uint32_t* table,
                     const int64_t* off, hipStream_t st);
 // Kernel choices (process-wide, set through the C ABI; the environment
-// variables EBCC_T1_KERNEL=wave|lane and EBCC_SPIHT_KERNEL=global override).
+// variables EBCC_T1_KERNEL=wave|lane and EBCC_SPIHT_KERNEL=global override;
+// EBCC_T1_PIPE=0 replaces the pipelined wavefront encoder of 32x32 blocks
+// by the single-wavefront one).
 struct Tuning {
   int t1_encoder;    // 0 by work size, 1 wave per code-block, 2 lanes per code-block
   int t1_decoder;    // same

@@ -15,6 +15,7 @@
 #include "common.h"
 #include "t1_common.h"
 
+#include <cstdlib>
 #include <type_traits>
 
 namespace ebcc {
@@ -419,6 +420,300 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
 }
 
 // ------------------------------------------------------------------------
+// Tier-1 encoding with a pipeline of wavefronts per code-block (blocks of up
+// to 32x32).  The significance state at the start of every bit-plane is a
+// closed-form function of the magnitudes (significant before plane p iff
+// q >> (p + 1) != 0, refined before iff q >> (p + 2) != 0), so the context
+// modelling of different planes is independent: NM wavefronts each model
+// one plane's three passes at a time, writing the (context, decision)
+// pairs to LDS, while wavefront 0 runs the MQ coder over the previous
+// round's planes.  Only the MQ coder is sequential; the stream is the one
+// the single-wavefront coder writes.
+// ------------------------------------------------------------------------
+constexpr int kPipeSym = 2816 + 16;   // one 32x32 plane: 1024 decisions + 1024 signs + 256 RL + 512 UNI, padded
+
+template <int NM>
+__global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
+    const FieldDev* __restrict__ F, const Blk* __restrict__ blk, int nblk, int cbh, const uint32_t* __restrict__ planes,
+    const uint32_t* __restrict__ signs, const uint8_t* __restrict__ pbv, uint8_t* __restrict__ cw,
+    int32_t* __restrict__ Rt, int64_t* __restrict__ Dt, int32_t* __restrict__ bpt, uint32_t* __restrict__ tailt,
+    uint32_t* __restrict__ sppf) {
+  using M = uint32_t;
+  __shared__ uint32_t qs[32 * 32];             // quantised magnitudes [y][x], pitch 32
+  __shared__ __align__(16) uint8_t sym[2][NM][kPipeSym];
+  __shared__ int scnt[2][NM][3];
+  __shared__ int64_t sdd[2][NM][3];
+  __shared__ uint32_t sppm[32];
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x;
+  const Blk k = blk[b];
+  if (!F[k.field].active) return;
+  const float* coef = F[k.field].buf[BUF_COEF];
+  const int nx = F[k.field].nx, e0 = F[k.field].e0;
+  const int P = pbv[b];
+  const int h = k.h, w = k.w;
+  int32_t* R = Rt + (size_t)b * kPassStride;
+  int64_t* Dd = Dt + (size_t)b * kPassStride;
+  int32_t* BPk = bpt + (size_t)b * kPassStride;
+  uint32_t* TL = tailt + (size_t)b * kPassStride;
+  uint32_t* spo = sppf + (size_t)b * cbh;
+  if (wv == 0 && lane == 0) { R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0; }
+  if (P == 0) {
+    if (wv == 0 && lane < h) spo[lane] = 0;
+    return;
+  }
+  const int sh = k.gain - e0;
+  for (int i = threadIdx.x; i < w * h; i += 64 * (NM + 1)) {
+    const int y = i / w, x = i - y * w;
+    qs[y * 32 + x] = quantq(coef[(size_t)(k.y0 + y) * nx + k.x0 + x], sh);
+  }
+  if (threadIdx.x < 32) sppm[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
+  uint32_t ctxv = lane == 0 ? 4u : (lane == CX_RL ? 3u : (lane == CX_UNI ? 46u : 0u));
+  const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
+  const M wm = wmask_of<M>(w);
+  auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
+
+  // ---- one plane's context modelling (a modelling wavefront) ----
+  auto model_plane = [&](const int p, uint8_t* buf, int* cnt, int64_t* ddo) {
+    M sig = 0, ref = 0, mag = 0, vis = 0, spp = 0, nsig = 0;
+    if (lane < h)
+      for (int x = 0; x < w; x++) {
+        const uint32_t q = qs[lane * 32 + x];
+        sig |= (M)((q >> (p + 1)) != 0u) << x;
+        ref |= (M)((q >> (p + 2)) != 0u) << x;
+        mag |= (M)((q >> p) & 1u) << x;
+      }
+    const M neg = lane < h ? signs[(size_t)b * cbh + lane] : (M)0;
+    int n = 0;
+    auto emit = [&](int cx, int d) {
+      if (lane == 0 && n < kPipeSym - 4) buf[n] = (uint8_t)(cx | (d << 7));   // (the bound always holds)
+      n++;
+    };
+    for (int ty = (p == P - 1) ? 2 : 0; ty < 3; ty++) {
+      n = (n + 3) & ~3;                  // every pass starts on a 4-byte boundary
+      const int n0 = n;
+      nsig = 0;
+      M refd = sig & ~vis;
+      const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
+        auto stripes = [&](auto tyc) {
+        constexpr int ty = decltype(tyc)::value;
+        for (int y0 = 0; y0 < h; y0 += 4) {
+          const int rn = h - y0 < 4 ? h - y0 : 4;
+          M sA = rowv(sig, y0 - 1), sC = rowv(sig, y0 + 4);
+          M sB[4], vB[4], fB[4], gB[4], nB[4];
+          M nA = 0, nC = 0;
+  #pragma unroll
+          for (int r = 0; r < 4; r++) {
+            int y = y0 + r;
+            bool in = r < rn;
+            sB[r] = in ? rdl<M>(sig, y) : (M)0;
+            vB[r] = in ? rdl<M>(vis, y) : (M)0;
+            fB[r] = (in && ty == 1) ? rdl<M>(ref, y) : (M)0;
+            gB[r] = in ? rdl<M>(mag, y) : (M)0;
+            // sign rows; in a refinement pass (no sign coding) the rows'
+            // neighbour-significance masks instead
+            nB[r] = in ? rdl<M>(ty == 1 ? nbm8 : neg, y) : (M)0;
+          }
+          if (ty != 1) { nA = rowv(neg, y0 - 1); nC = rowv(neg, y0 + 4); }
+          // r is a compile-time constant in every caller (unrolled loops)
+          auto code_sign = [&](int r, int x) {
+            const uint32_t sc = sc_look(sct, f3(SR(r), x), f3(NR(r), x), btu(SR(r - 1), x), btu(NR(r - 1), x),
+                                        btu(SR(r + 1), x), btu(NR(r + 1), x));
+            emit(CX_SC + (int)(sc & 7u), btu(nB[r], x) ^ (int)(sc >> 3));
+          };
+          if (ty == 0) {                                   // significance propagation
+            // candidate columns at the stripe start; a sample that becomes
+            // significant in column x can only add column x + 1
+            M c = 0;
+  #pragma unroll
+            for (int r = 0; r < 4; r++)
+              if (r < rn) {
+                M nb = SR(r - 1) | SR(r) | SR(r + 1);
+                nb = nb | (nb << 1) | (nb >> 1);
+                c |= ~SR(r) & nb;
+              }
+            c &= wm;
+            while (c) {
+              const int x = ctzm(c);
+              c &= c - 1;
+              bool grew = false;
+  #pragma unroll
+              for (int r = 0; r < 4; r++) {
+                if (r >= rn) continue;
+                M mid = sB[r];
+                if (btu(mid, x)) continue;
+                const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
+                if (!pat) continue;
+                int bit = btu(gB[r], x);
+                emit(zc_look(zct, pat), bit);
+                vB[r] |= (M)1 << x;
+                if (bit) {
+                  code_sign(r, x);
+                  sB[r] = mid | ((M)1 << x);
+                  grew = true;
+                }
+              }
+              if (grew && x + 1 < w) c |= (M)1 << (x + 1);
+            }
+          } else if (ty == 1) {                            // magnitude refinement
+            M mk = 0;
+  #pragma unroll
+            for (int r = 0; r < 4; r++) mk |= sB[r] & ~vB[r];
+            while (mk) {
+              int x = ctzm(mk);
+              mk &= mk - 1;
+  #pragma unroll
+              for (int r = 0; r < 4; r++) {
+                if (r >= rn || !btu(sB[r] & ~vB[r], x)) continue;
+                const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nB[r], x) ? CX_MR + 1 : CX_MR);
+                emit(cx, btu(gB[r], x));
+                fB[r] |= (M)1 << x;
+              }
+            }
+          } else {                                         // cleanup
+            M u = 0;
+  #pragma unroll
+            for (int r = 0; r < 4; r++)
+              if (r < rn) u |= ~(sB[r] | vB[r]);
+            u &= wm;
+            while (u) {
+              int x = ctzm(u);
+              u &= u - 1;
+              int rstart = 0;
+              if (rn == 4) {
+                bool run = true;
+  #pragma unroll
+                for (int r = 0; r < 4; r++)
+                  if (btu(sB[r] | vB[r], x)) run = false;
+                if (run) {
+                  M nbm = nb3<M>(x);
+                  if ((sA | sB[0] | sB[1] | sB[2] | sB[3] | sC) & nbm) run = false;
+                }
+                if (run) {
+                  int rr = -1;
+  #pragma unroll
+                  for (int r = 3; r >= 0; r--)
+                    if (btu(gB[r], x)) rr = r;
+                  emit(CX_RL, rr >= 0);
+                  if (rr < 0) continue;
+                  emit(CX_UNI, (rr >> 1) & 1);
+                  emit(CX_UNI, rr & 1);
+  #pragma unroll
+                  for (int r = 0; r < 4; r++)
+                    if (r == rr) {
+                      code_sign(r, x);
+                      sB[r] |= (M)1 << x;
+                    }
+                  rstart = rr + 1;
+                }
+              }
+  #pragma unroll
+              for (int r = 0; r < 4; r++) {
+                if (r < rstart || r >= rn) continue;
+                if (btu(sB[r] | vB[r], x)) continue;
+                const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(sB[r], x), f3(SR(r + 1), x));
+                int bit = btu(gB[r], x);
+                emit(zc_look(zct, pat), bit);
+                if (bit) {
+                  code_sign(r, x);
+                  sB[r] |= (M)1 << x;
+                }
+              }
+            }
+          }
+          // write the stripe's rows back to the row registers (samples that
+          // became significant: the bits new in the stripe's rows)
+  #pragma unroll
+          for (int r = 0; r < 4; r++)
+            if (r < rn && lane == y0 + r) {
+              const M nw = sB[r] & ~sig;
+              nsig |= nw;
+              if (ty == 0) spp |= nw;
+              sig = sB[r]; vis = vB[r];
+              if (ty == 1) ref = fB[r];
+            }
+        }
+        };
+      if (ty == 0) stripes(std::integral_constant<int, 0>{});
+      else if (ty == 1) stripes(std::integral_constant<int, 1>{});
+      else stripes(std::integral_constant<int, 2>{});
+      M chg = (ty == 1) ? refd : nsig;
+      int64_t dd = 0;
+      while (chg) {
+        const int x = ctzm(chg);
+        chg &= chg - 1;
+        const uint32_t q = qs[lane * 32 + x];
+        dd += (ty == 1) ? ref_delta(q, p) : sig_delta(q, p);
+      }
+      for (int o = 32; o > 0; o >>= 1) dd += __shfl_xor(dd, o);
+      if (ty == 2) vis = 0;
+      if (lane == 0) { cnt[ty] = n - n0; ddo[ty] = dd; }
+    }
+    if (lane < h && spp) atomicOr(&sppm[lane], spp);
+  };
+
+  // ---- the MQ coder (wavefront 0) ----
+  uint8_t* out = cw + (size_t)b * kCwCap;
+  MQW e;
+  e.C = 0; e.A = 0x8000; e.B = 0; e.CT = 12; e.BP = -1;
+  int kk = 0;
+  bool stop = false;
+  int64_t Dcum = 0;
+  auto code_group = [&](const int s, const int g) {
+    for (int j = 0; j < NM; j++) {
+      const int p = P - 1 - g * NM - j;
+      if (p < 0) break;
+      const uint8_t* buf = sym[s][j];
+      int off = 0;
+      for (int ty = (p == P - 1) ? 2 : 0; ty < 3; ty++) {
+        const int n = scnt[s][j][ty];
+        if (!stop) {
+          for (int i = 0; i < n; i += 256) {
+            // 256 decisions at a time: lane l holds bytes 4l .. 4l + 3
+            const int m = n - i < 256 ? n - i : 256;
+            const bool in = 4 * lane < m && off + i + 4 * lane + 4 <= kPipeSym;
+            const uint32_t wv4 = in ? *reinterpret_cast<const uint32_t*>(buf + off + i + 4 * lane) : 0u;
+            for (int t = 0; t < m; t++) {
+              const uint32_t byte = (rdl32(wv4, t >> 2) >> (8 * (t & 3))) & 0xFFu;
+              mqw_encode(e, ctxv, tabv, (int)(byte & 0x1Fu), (int)(byte >> 7), out, lane);
+            }
+          }
+          if (e.BP >= 65536) {
+            stop = true;                 // every later pass exceeds the length limit
+          } else {
+            kk++;
+            Dcum += sdd[s][j][ty];
+            uint32_t tail;
+            const int rk = mqw_flush_copy(e, &tail);
+            if (lane == 0) { R[kk] = rk; Dd[kk] = Dcum; BPk[kk] = e.BP; TL[kk] = tail; }
+          }
+        }
+        off += (n + 3) & ~3;
+      }
+    }
+  };
+
+  const int G = (P + NM - 1) / NM;       // rounds of NM planes
+  for (int r = 0; r <= G; r++) {
+    if (wv >= 1 && r < G) {
+      const int j = wv - 1;
+      const int p = P - 1 - r * NM - j;
+      if (p >= 0) model_plane(p, sym[r & 1][j], scnt[r & 1][j], sdd[r & 1][j]);
+    }
+    if (wv == 0 && r >= 1) code_group((r - 1) & 1, r - 1);
+    __syncthreads();
+  }
+  if (wv == 0) {
+    if (lane == 0)
+      for (int jj = kk + 1; jj <= 3 * P - 2; jj++) { R[jj] = kRInf; Dd[jj] = Dcum; BPk[jj] = 0; TL[jj] = 0; }
+    if (lane < h) spo[lane] = sppm[lane];
+  }
+}
+
+// ------------------------------------------------------------------------
 // Wave-uniform MQ decoder: bytes are read through a uniform 4-byte window;
 // bytes past the codeword read as 0xFF.
 // ------------------------------------------------------------------------
@@ -710,7 +1005,12 @@ void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
                     const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
                     uint32_t* tail, void* sppf, hipStream_t st) {
   if (nblk <= 0) return;
-  if (cbw <= 32)
+  const char* pe = getenv("EBCC_T1_PIPE");
+  const bool pipe = !(pe && pe[0] == '0');
+  if (cbw <= 32 && cbh <= 32 && pipe)
+    k_t1_encode_pipe<2><<<nblk, 192, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes, (const uint32_t*)signs, pb,
+                                             cw, R, D, bp, tail, (uint32_t*)sppf);
+  else if (cbw <= 32)
     k_t1_encode_wave<uint32_t><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes, (const uint32_t*)signs,
                                                      pb, cw, R, D, bp, tail, (uint32_t*)sppf);
   else
