@@ -88,6 +88,32 @@ __device__ __forceinline__ void mqw_encode(MQW& e, uint32_t& ctxv, uint32_t tabv
     mqw_renorm(e, out, lane);
   }
 }
+// The same coding step with the common case (the MPS, A still >= 0x8000
+// after the subtraction) as the straight-line path and the rest out of line;
+// used by the pipelined coder, whose loop holds little else.
+__device__ __forceinline__ void mqw_encode_fast(MQW& e, uint32_t& ctxv, uint32_t tabv, int cx, int d, uint8_t* out,
+                                                int lane) {
+  const uint32_t cs = rdl32(ctxv, cx);
+  const uint32_t ent = rdl32(tabv, (int)(cs & 0x7f));
+  const uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
+  const uint32_t A = e.A - qe;
+  if (__builtin_expect(((uint32_t)d == mps) & ((A >> 15) & 1u), 1)) {
+    e.A = A;
+    e.C += qe;
+    return;
+  }
+  uint32_t ncs;
+  if ((uint32_t)d == mps) {
+    if (A < qe) e.A = qe; else { e.A = A; e.C += qe; }
+    ncs = (cs & 0x80) | ((ent >> 16) & 0x3f);
+  } else {
+    if (A < qe) { e.A = A; e.C += qe; } else e.A = qe;
+    const uint32_t m = (ent >> 28) ? (mps ^ 1u) : mps;
+    ncs = (m << 7) | ((ent >> 22) & 0x3f);
+  }
+  if (lane == cx) ctxv = ncs;
+  mqw_renorm(e, out, lane);
+}
 __device__ __forceinline__ int mqw_flush_copy(const MQW& e, uint32_t* tail) {
   uint32_t C = e.C, tempc = C + e.A;
   C |= 0xFFFF;
@@ -669,16 +695,18 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
       const uint8_t* buf = sym[s][j];
       int off = 0;
       for (int ty = (p == P - 1) ? 2 : 0; ty < 3; ty++) {
-        const int n = scnt[s][j][ty];
+        const int n = __builtin_amdgcn_readfirstlane(scnt[s][j][ty]);
         if (!stop) {
           for (int i = 0; i < n; i += 256) {
             // 256 decisions at a time: lane l holds bytes 4l .. 4l + 3
             const int m = n - i < 256 ? n - i : 256;
             const bool in = 4 * lane < m && off + i + 4 * lane + 4 <= kPipeSym;
             const uint32_t wv4 = in ? *reinterpret_cast<const uint32_t*>(buf + off + i + 4 * lane) : 0u;
-            for (int t = 0; t < m; t++) {
-              const uint32_t byte = (rdl32(wv4, t >> 2) >> (8 * (t & 3))) & 0xFFu;
-              mqw_encode(e, ctxv, tabv, (int)(byte & 0x1Fu), (int)(byte >> 7), out, lane);
+            for (int t = 0; t < m; t += 4) {
+              uint32_t word = rdl32(wv4, t >> 2);
+              const int tn = m - t < 4 ? m - t : 4;
+              for (int u = 0; u < tn; u++, word >>= 8)
+                mqw_encode_fast(e, ctxv, tabv, (int)(word & 0x1Fu), (int)((word >> 7) & 1u), out, lane);
             }
           }
           if (e.BP >= 65536) {
