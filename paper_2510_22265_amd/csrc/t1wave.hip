@@ -64,17 +64,31 @@ __device__ __forceinline__ void mqw_renorm(MQW& e, uint8_t* out, int lane) {
     if (e.CT == 0) mqw_byteout(e, out, lane);
   }
 }
-// ctxv: lane c holds context c's state (index | MPS << 7); tabv: lane i holds
-// table entry i.
+// Context states live one per lane: lane c holds context c's whole table
+// entry (Qe | NMPS << 16 | NLPS << 22 | SWITCH << 28) with its MPS in bit 31,
+// so a coding step that keeps its state reads it with a single cross-lane
+// read. tabv: lane i holds table entry i, read only when a state moves.
+__device__ __forceinline__ uint32_t mq_ctx_init(int lane) {
+  // T.800 Table D.7: all-zero neighbourhood context at index 4, run-length
+  // at index 3, uniform at index 46, every other context at index 0
+  const int idx = lane == 0 ? 4 : (lane == CX_RL ? 3 : (lane == CX_UNI ? 46 : 0));
+  return lane < kNCtx ? c_mqt[idx] : 0u;
+}
+__device__ __forceinline__ uint32_t mq_next_mps(uint32_t cs, uint32_t tabv) {
+  return rdl32(tabv, (int)((cs >> 16) & 0x3f)) | (cs & 0x80000000u);
+}
+__device__ __forceinline__ uint32_t mq_next_lps(uint32_t cs, uint32_t tabv) {
+  const uint32_t m = (cs >> 31) ^ ((cs >> 28) & 1u);
+  return rdl32(tabv, (int)((cs >> 22) & 0x3f)) | (m << 31);
+}
 __device__ __forceinline__ void mqw_encode(MQW& e, uint32_t& ctxv, uint32_t tabv, int cx, int d, uint8_t* out, int lane) {
-  uint32_t cs = rdl32(ctxv, cx);
-  uint32_t ent = rdl32(tabv, (int)(cs & 0x7f));
-  uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
+  const uint32_t cs = rdl32(ctxv, cx);
+  const uint32_t qe = cs & 0xFFFF, mps = cs >> 31;
   e.A -= qe;
   if ((uint32_t)d == mps) {
     if ((e.A & 0x8000) == 0) {
       if (e.A < qe) e.A = qe; else e.C += qe;
-      uint32_t ncs = (cs & 0x80) | ((ent >> 16) & 0x3f);
+      const uint32_t ncs = mq_next_mps(cs, tabv);
       if (lane == cx) ctxv = ncs;
       mqw_renorm(e, out, lane);
     } else {
@@ -82,8 +96,7 @@ __device__ __forceinline__ void mqw_encode(MQW& e, uint32_t& ctxv, uint32_t tabv
     }
   } else {
     if (e.A < qe) e.C += qe; else e.A = qe;
-    uint32_t m = (ent >> 28) ? (mps ^ 1u) : mps;
-    uint32_t ncs = (m << 7) | ((ent >> 22) & 0x3f);
+    const uint32_t ncs = mq_next_lps(cs, tabv);
     if (lane == cx) ctxv = ncs;
     mqw_renorm(e, out, lane);
   }
@@ -94,8 +107,7 @@ __device__ __forceinline__ void mqw_encode(MQW& e, uint32_t& ctxv, uint32_t tabv
 __device__ __forceinline__ void mqw_encode_fast(MQW& e, uint32_t& ctxv, uint32_t tabv, int cx, int d, uint8_t* out,
                                                 int lane) {
   const uint32_t cs = rdl32(ctxv, cx);
-  const uint32_t ent = rdl32(tabv, (int)(cs & 0x7f));
-  const uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
+  const uint32_t qe = cs & 0xFFFF, mps = cs >> 31;
   const uint32_t A = e.A - qe;
   if (__builtin_expect(((uint32_t)d == mps) & ((A >> 15) & 1u), 1)) {
     e.A = A;
@@ -105,11 +117,10 @@ __device__ __forceinline__ void mqw_encode_fast(MQW& e, uint32_t& ctxv, uint32_t
   uint32_t ncs;
   if ((uint32_t)d == mps) {
     if (A < qe) e.A = qe; else { e.A = A; e.C += qe; }
-    ncs = (cs & 0x80) | ((ent >> 16) & 0x3f);
+    ncs = mq_next_mps(cs, tabv);
   } else {
     if (A < qe) { e.A = A; e.C += qe; } else e.A = qe;
-    const uint32_t m = (ent >> 28) ? (mps ^ 1u) : mps;
-    ncs = (m << 7) | ((ent >> 22) & 0x3f);
+    ncs = mq_next_lps(cs, tabv);
   }
   if (lane == cx) ctxv = ncs;
   mqw_renorm(e, out, lane);
@@ -251,7 +262,7 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
   }
   __syncthreads();
   uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
-  uint32_t ctxv = lane == 0 ? 4u : (lane == CX_RL ? 3u : (lane == CX_UNI ? 46u : 0u));
+  uint32_t ctxv = mq_ctx_init(lane);
   const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
   M sig = 0, vis = 0, ref = 0, spp = 0, nsig = 0, mag = 0;
   M neg = lane < h ? signs[(size_t)b * cbh + lane] : (M)0;
@@ -497,7 +508,7 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
   if (threadIdx.x < 32) sppm[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
-  uint32_t ctxv = lane == 0 ? 4u : (lane == CX_RL ? 3u : (lane == CX_UNI ? 46u : 0u));
+  uint32_t ctxv = mq_ctx_init(lane);
   const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
   const M wm = wmask_of<M>(w);
   auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
@@ -792,9 +803,8 @@ __device__ __forceinline__ void mqwd_renorm(MQWD& d) {
   } while ((d.A & 0x8000) == 0);
 }
 __device__ __forceinline__ int mqwd_decode(MQWD& d, uint32_t& ctxv, uint32_t tabv, int cx, int lane) {
-  uint32_t cs = rdl32(ctxv, cx);
-  uint32_t ent = rdl32(tabv, (int)(cs & 0x7f));
-  const uint32_t qe = ent & 0xFFFF, mps = cs >> 7;
+  const uint32_t cs = rdl32(ctxv, cx);
+  const uint32_t qe = cs & 0xFFFF, mps = cs >> 31;
   const uint32_t A = d.A - qe;
   const bool chigh = (d.C >> 16) < qe;      // in the lower sub-interval of size Qe
   if (__builtin_expect(!chigh && (A & 0x8000u), 1)) {
@@ -806,8 +816,7 @@ __device__ __forceinline__ int mqwd_decode(MQWD& d, uint32_t& ctxv, uint32_t tab
   const bool is_mps = chigh == (A < qe);
   d.A = chigh ? qe : A;
   d.C -= chigh ? 0u : (qe << 16);
-  const uint32_t m = (!is_mps && (ent >> 28)) ? (mps ^ 1u) : mps;
-  const uint32_t ncs = (m << 7) | (is_mps ? ((ent >> 16) & 0x3f) : ((ent >> 22) & 0x3f));
+  const uint32_t ncs = is_mps ? mq_next_mps(cs, tabv) : mq_next_lps(cs, tabv);
   if (lane == cx) ctxv = ncs;
   mqwd_renorm(d);
   return (int)(is_mps ? mps : (mps ^ 1u));
@@ -845,7 +854,7 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
   for (int i = lane; i < 64 * 64; i += 64) qm[i] = 0;
   __syncthreads();
   uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
-  uint32_t ctxv = lane == 0 ? 4u : (lane == CX_RL ? 3u : (lane == CX_UNI ? 46u : 0u));
+  uint32_t ctxv = mq_ctx_init(lane);
   const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
   M sig = 0, vis = 0, ref = 0, neg = 0, cur = 0, magp = 0;
   const M wm = wmask_of<M>(w);
