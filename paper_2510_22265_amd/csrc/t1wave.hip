@@ -65,65 +65,54 @@ __device__ __forceinline__ void mqw_renorm(MQW& e, uint8_t* out, int lane) {
   }
 }
 // Context states live one per lane: lane c holds context c's whole table
-// entry (Qe | NMPS << 16 | NLPS << 22 | SWITCH << 28) with its MPS in bit 31,
-// so a coding step that keeps its state reads it with a single cross-lane
-// read. tabv: lane i holds table entry i, read only when a state moves.
+// entry with its MPS in bit 31 and, in place of Qe, T = Qe + 0x8000 in the
+// low half (NMPS << 16 | NLPS << 22 | SWITCH << 28 as in the table).  The
+// common step (the MPS, A staying >= 0x8000, i.e. A >= T beforehand) is then
+// one read and one compare.  tabv: lane i holds table entry i in the same
+// form, read only when a state moves.  Everything is written with integer
+// 0/1 values and masks: uniform booleans would otherwise become lane masks
+// and pull the coder's arithmetic into dependent vector instructions.
+__device__ __forceinline__ uint32_t mq_tab_init(int lane) { return lane < 47 ? c_mqt[lane] + 0x8000u : 0u; }
 __device__ __forceinline__ uint32_t mq_ctx_init(int lane) {
   // T.800 Table D.7: all-zero neighbourhood context at index 4, run-length
   // at index 3, uniform at index 46, every other context at index 0
   const int idx = lane == 0 ? 4 : (lane == CX_RL ? 3 : (lane == CX_UNI ? 46 : 0));
-  return lane < kNCtx ? c_mqt[idx] : 0u;
+  return lane < kNCtx ? c_mqt[idx] + 0x8000u : 0u;
 }
-__device__ __forceinline__ uint32_t mq_next_mps(uint32_t cs, uint32_t tabv) {
-  return rdl32(tabv, (int)((cs >> 16) & 0x3f)) | (cs & 0x80000000u);
-}
-__device__ __forceinline__ uint32_t mq_next_lps(uint32_t cs, uint32_t tabv) {
-  const uint32_t m = (cs >> 31) ^ ((cs >> 28) & 1u);
-  return rdl32(tabv, (int)((cs >> 22) & 0x3f)) | (m << 31);
+// State after coding with state cs; x = 1 for the LPS, 0 for the MPS (the
+// LPS moves to NLPS and flips the MPS when SWITCH is set).
+__device__ __forceinline__ uint32_t mq_next(uint32_t cs, uint32_t x, uint32_t tabv) {
+  const uint32_t m = (cs >> 31) ^ (x & (cs >> 28));
+  return rdl32(tabv, (int)((cs >> (16 + 6 * x)) & 0x3f)) | (m << 31);
 }
 __device__ __forceinline__ void mqw_encode(MQW& e, uint32_t& ctxv, uint32_t tabv, int cx, int d, uint8_t* out, int lane) {
   const uint32_t cs = rdl32(ctxv, cx);
-  const uint32_t qe = cs & 0xFFFF, mps = cs >> 31;
-  e.A -= qe;
-  if ((uint32_t)d == mps) {
-    if ((e.A & 0x8000) == 0) {
-      if (e.A < qe) e.A = qe; else e.C += qe;
-      const uint32_t ncs = mq_next_mps(cs, tabv);
-      if (lane == cx) ctxv = ncs;
-      mqw_renorm(e, out, lane);
-    } else {
-      e.C += qe;
-    }
-  } else {
-    if (e.A < qe) e.C += qe; else e.A = qe;
-    const uint32_t ncs = mq_next_lps(cs, tabv);
-    if (lane == cx) ctxv = ncs;
-    mqw_renorm(e, out, lane);
-  }
-}
-// The same coding step with the common case (the MPS, A still >= 0x8000
-// after the subtraction) as the straight-line path and the rest out of line;
-// used by the pipelined coder, whose loop holds little else.
-__device__ __forceinline__ void mqw_encode_fast(MQW& e, uint32_t& ctxv, uint32_t tabv, int cx, int d, uint8_t* out,
-                                                int lane) {
-  const uint32_t cs = rdl32(ctxv, cx);
-  const uint32_t qe = cs & 0xFFFF, mps = cs >> 31;
-  const uint32_t A = e.A - qe;
-  if (__builtin_expect(((uint32_t)d == mps) & ((A >> 15) & 1u), 1)) {
-    e.A = A;
-    e.C += qe;
+  const uint32_t key = (cs ^ ((uint32_t)d << 31)) & 0x8000FFFFu;   // T, plus bit 31 for the LPS
+  if (__builtin_expect(key <= e.A, 1)) {
+    const uint32_t q = key - 0x8000u;
+    e.A -= q;
+    e.C += q;
     return;
   }
-  uint32_t ncs;
-  if ((uint32_t)d == mps) {
-    if (A < qe) e.A = qe; else { e.A = A; e.C += qe; }
-    ncs = mq_next_mps(cs, tabv);
-  } else {
-    if (A < qe) { e.A = A; e.C += qe; } else e.A = qe;
-    ncs = mq_next_lps(cs, tabv);
-  }
+  const uint32_t q = (cs & 0xFFFFu) - 0x8000u;
+  const uint32_t Am = e.A - q;
+  const uint32_t x = key >> 31;
+  // the upper sub-interval (size A - Qe) goes to the MPS unless it is the
+  // smaller one (conditional exchange)
+  const uint32_t up = (x ^ 1u) ^ ((Am - q) >> 31);
+  const uint32_t mu = 0u - up;
+  e.A = q + ((Am - q) & mu);
+  e.C += q & mu;
+  const uint32_t ncs = mq_next(cs, x, tabv);
   if (lane == cx) ctxv = ncs;
-  mqw_renorm(e, out, lane);
+  const int n = __builtin_clz(e.A) - 16;
+  if (__builtin_expect(n < e.CT, 1)) {
+    e.A <<= n;
+    e.C <<= n;
+    e.CT -= n;
+  } else {
+    mqw_renorm(e, out, lane);
+  }
 }
 __device__ __forceinline__ int mqw_flush_copy(const MQW& e, uint32_t* tail) {
   uint32_t C = e.C, tempc = C + e.A;
@@ -261,7 +250,7 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
     qs[y * 64 + x] = quantq(coef[(size_t)(k.y0 + y) * nx + k.x0 + x], sh);
   }
   __syncthreads();
-  uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
+  uint32_t tabv = mq_tab_init(lane);
   uint32_t ctxv = mq_ctx_init(lane);
   const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
   M sig = 0, vis = 0, ref = 0, spp = 0, nsig = 0, mag = 0;
@@ -507,7 +496,7 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
   }
   if (threadIdx.x < 32) sppm[threadIdx.x] = 0;
   __syncthreads();
-  const uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
+  const uint32_t tabv = mq_tab_init(lane);
   uint32_t ctxv = mq_ctx_init(lane);
   const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
   const M wm = wmask_of<M>(w);
@@ -713,11 +702,18 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
             const int m = n - i < 256 ? n - i : 256;
             const bool in = 4 * lane < m && off + i + 4 * lane + 4 <= kPipeSym;
             const uint32_t wv4 = in ? *reinterpret_cast<const uint32_t*>(buf + off + i + 4 * lane) : 0u;
-            for (int t = 0; t < m; t += 4) {
-              uint32_t word = rdl32(wv4, t >> 2);
-              const int tn = m - t < 4 ? m - t : 4;
-              for (int u = 0; u < tn; u++, word >>= 8)
-                mqw_encode_fast(e, ctxv, tabv, (int)(word & 0x1Fu), (int)((word >> 7) & 1u), out, lane);
+            const int m4 = m & ~3;
+            for (int t = 0; t < m4; t += 4) {
+              const uint32_t w = rdl32(wv4, t >> 2);
+              mqw_encode(e, ctxv, tabv, (int)(w & 0x1Fu), (int)((w >> 7) & 1u), out, lane);
+              mqw_encode(e, ctxv, tabv, (int)((w >> 8) & 0x1Fu), (int)((w >> 15) & 1u), out, lane);
+              mqw_encode(e, ctxv, tabv, (int)((w >> 16) & 0x1Fu), (int)((w >> 23) & 1u), out, lane);
+              mqw_encode(e, ctxv, tabv, (int)((w >> 24) & 0x1Fu), (int)(w >> 31), out, lane);
+            }
+            if (m4 < m) {
+              uint32_t w = rdl32(wv4, m4 >> 2);
+              for (int t = m4; t < m; t++, w >>= 8)
+                mqw_encode(e, ctxv, tabv, (int)(w & 0x1Fu), (int)((w >> 7) & 1u), out, lane);
             }
           }
           if (e.BP >= 65536) {
@@ -804,22 +800,27 @@ __device__ __forceinline__ void mqwd_renorm(MQWD& d) {
 }
 __device__ __forceinline__ int mqwd_decode(MQWD& d, uint32_t& ctxv, uint32_t tabv, int cx, int lane) {
   const uint32_t cs = rdl32(ctxv, cx);
-  const uint32_t qe = cs & 0xFFFF, mps = cs >> 31;
-  const uint32_t A = d.A - qe;
-  const bool chigh = (d.C >> 16) < qe;      // in the lower sub-interval of size Qe
-  if (__builtin_expect(!chigh && (A & 0x8000u), 1)) {
-    d.A = A;
-    d.C -= qe << 16;
+  const uint32_t T = cs & 0xFFFFu, mps = cs >> 31;
+  // the MPS without renormalisation: C at or above Qe and A - Qe >= 0x8000
+  const uint32_t ch = (d.C >> 16) + 0x8000u;
+  if (__builtin_expect((d.A < ch ? d.A : ch) >= T, 1)) {
+    const uint32_t q = T - 0x8000u;
+    d.A -= q;
+    d.C -= q << 16;
     return (int)mps;
   }
+  const uint32_t q = T - 0x8000u;
+  const uint32_t A = d.A - q;
+  const uint32_t chigh = (ch - T) >> 31;         // C in the lower sub-interval of size Qe
   // the MPS was decoded iff exactly one of: C below Qe, A below Qe
-  const bool is_mps = chigh == (A < qe);
-  d.A = chigh ? qe : A;
-  d.C -= chigh ? 0u : (qe << 16);
-  const uint32_t ncs = is_mps ? mq_next_mps(cs, tabv) : mq_next_lps(cs, tabv);
+  const uint32_t x = chigh ^ ((A - q) >> 31);    // 1: the LPS
+  const uint32_t mc = 0u - chigh;
+  d.A = (A & ~mc) | (q & mc);
+  d.C -= (q << 16) & ~mc;
+  const uint32_t ncs = mq_next(cs, x, tabv);
   if (lane == cx) ctxv = ncs;
   mqwd_renorm(d);
-  return (int)(is_mps ? mps : (mps ^ 1u));
+  return (int)(mps ^ x);
 }
 
 template <typename M>
@@ -853,7 +854,7 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
   }
   for (int i = lane; i < 64 * 64; i += 64) qm[i] = 0;
   __syncthreads();
-  uint32_t tabv = lane < 47 ? c_mqt[lane] : 0u;
+  uint32_t tabv = mq_tab_init(lane);
   uint32_t ctxv = mq_ctx_init(lane);
   const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
   M sig = 0, vis = 0, ref = 0, neg = 0, cur = 0, magp = 0;
