@@ -823,11 +823,24 @@ __device__ __forceinline__ int mqwd_decode(MQWD& d, uint32_t& ctxv, uint32_t tab
   return (int)(mps ^ x);
 }
 
+// Set bits of m in the columns (lanes) below this lane, and bit `lane` of m.
+template <typename M> __device__ __forceinline__ int mbcnt_m(M m);
+template <> __device__ __forceinline__ int mbcnt_m<uint32_t>(uint32_t m) {
+  return (int)__builtin_amdgcn_mbcnt_lo(m, 0u);
+}
+template <> __device__ __forceinline__ int mbcnt_m<uint64_t>(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+template <typename M> __device__ __forceinline__ uint32_t col_bit(M m, int lane) {
+  return lane < (int)(8 * sizeof(M)) ? (uint32_t)(m >> lane) & 1u : 0u;
+}
+
 template <typename M>
 __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
                                                        int nblk, const uint32_t* __restrict__ table,
                                                        const int64_t* __restrict__ off) {
   __shared__ uint32_t qm[64 * 64];   // decoded magnitudes [y][x], pitch 64
+  __shared__ uint32_t rsym[64];      // a stripe's refinement contexts, one byte each
   const int lane = threadIdx.x;
   const int b = blockIdx.x;
   const Blk k = blk[b];
@@ -928,19 +941,64 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
             if (grew && x + 1 < w) c |= (M)1 << (x + 1);
           }
         } else if (ty == 1) {
-          M mk = 0;
+          // Refinement: each context is fixed before the pass (refined in an
+          // earlier plane, else the neighbourhood significance at the pass
+          // start), so the lanes (one per column) list the stripe's contexts
+          // in scan order, a tight loop decodes them, and the lanes take
+          // their bits back.
+          M Rr[4];
+          int tot = 0;
 #pragma unroll
-          for (int r = 0; r < 4; r++) mk |= sB[r] & ~vB[r];
-          while (mk) {
-            int x = ctzm(mk);
-            mk &= mk - 1;
+          for (int r = 0; r < 4; r++) {
+            Rr[r] = r < rn ? (sB[r] & ~vB[r]) : (M)0;
+            tot += __builtin_popcountll((uint64_t)Rr[r]);
+          }
+          tot = __builtin_amdgcn_readfirstlane(tot);
+          if (tot) {
+            uint8_t* const sb8 = reinterpret_cast<uint8_t*>(rsym);
+            int pos = 0;
+#pragma unroll
+            for (int r = 0; r < 4; r++) pos += mbcnt_m<M>(Rr[r]);
+            int pw = pos;
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+              if (col_bit<M>(Rr[r], lane)) {
+                const int c = col_bit<M>(fB[r], lane) ? 2 : (int)col_bit<M>(nB[r], lane);
+                sb8[pw++] = (uint8_t)(CX_MR + c);
+              }
+            const uint32_t wv4 = rsym[lane];
+            uint32_t dv = 0, acc = 0;
+            const int m4 = tot & ~3;
+            for (int t = 0; t < m4; t += 4) {
+              const uint32_t wd = rdl32(wv4, t >> 2);
+              uint32_t b4 = (uint32_t)mqwd_decode(d, ctxv, tabv, (int)(wd & 0x1Fu), lane);
+              b4 |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)((wd >> 8) & 0x1Fu), lane) << 1;
+              b4 |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)((wd >> 16) & 0x1Fu), lane) << 2;
+              b4 |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)((wd >> 24) & 0x1Fu), lane) << 3;
+              acc |= b4 << (t & 31);
+              if ((t & 31) == 28) {
+                if (lane == (t >> 5)) dv = acc;
+                acc = 0;
+              }
+            }
+            if (m4 < tot) {
+              uint32_t wd = rdl32(wv4, m4 >> 2);
+              for (int t = m4; t < tot; t++, wd >>= 8)
+                acc |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)(wd & 0x1Fu), lane) << (t & 31);
+            }
+            if (tot & 31) {
+              if (lane == (tot >> 5)) dv = acc;
+            }
+            // bits pos, pos+1, ... belong to this column's rows in order
+            const uint32_t lo = (uint32_t)__shfl((int)dv, pos >> 5), hi = (uint32_t)__shfl((int)dv, (pos >> 5) + 1);
+            uint32_t win = (uint32_t)(((((uint64_t)hi) << 32) | lo) >> (pos & 31));
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-              if (r >= rn || !btu(sB[r] & ~vB[r], x)) continue;
-              const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nB[r], x) ? CX_MR + 1 : CX_MR);
-              int bit = mqwd_decode(d, ctxv, tabv, cx, lane);
-              if (bit) mB[r] |= (M)1 << x;
-              fB[r] |= (M)1 << x;
+              const uint32_t has = col_bit<M>(Rr[r], lane);
+              const bool one = has && (win & 1u);
+              win >>= has;
+              mB[r] = (M)__ballot(one);
+              fB[r] |= Rr[r];
             }
           }
         } else {
