@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 
-# HBM bytes per launch of the headline path's dominant kernel on one
+# HBM bytes per launch of the headline path's tier-1 kernels on one
 # 721x1440 field at eps_rel 1%, from two rocprofv3 --pmc runs (FETCH_SIZE,
 # WRITE_SIZE; profiles/kernels_era5_721x1440_per_field.md), each scaled by
 # what the counter reads for a plain elementwise copy of 1 GiB (FETCH_SIZE
@@ -42,9 +42,13 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 # measured (checked by hash); otherwise traffic is reported as null.
 MEASURED_TRAFFIC = {
     "t1_encode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
-                  "sha256": "fb63dcce54237c138d529ec0791ba24af333bac965140f3301e312a09f887904",
+                  "sha256": "4d1937e6da2e20ebd3a70c1721ff41080530c8a3d029993ebab79d7c4cb0313b",
                   "ny": 721, "nx": 1440, "eps": 0.01,
-                  "bytes": (2.0 * (4516.9 + 4308.9) / 2 + 1.0 * (976.1 + 1231.5) / 2) * 1024},
+                  "bytes": (2.0 * (3883.4 + 3747.1) / 2 + 1.0 * (986.0 + 1229.9) / 2) * 1024},
+    "t1_decode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
+                  "sha256": "4d1937e6da2e20ebd3a70c1721ff41080530c8a3d029993ebab79d7c4cb0313b",
+                  "ny": 721, "nx": 1440, "eps": 0.01,
+                  "bytes": (2.0 * (593.8 + 558.4) / 2 + 1.0 * (4099.5 + 4099.5) / 2) * 1024},
 }
 
 
