@@ -69,19 +69,30 @@ __device__ __forceinline__ float prologue(const float* __restrict__ src, int idx
 }
 
 // Epilogue: reconstruction x_hat = xmin + ((abase + v + 0.5) * range).
+// Returns, for a bound check, whether this sample violates the bound; the
+// caller gathers the answers of its workgroup (report_violation).
 template <int EPI>
-__device__ __forceinline__ void epilogue(float* __restrict__ out, int idx, float v, const FieldDev& f, const Scal& sc) {
-  if (EPI == EPI_STORE) { out[idx] = v; return; }
+__device__ __forceinline__ bool epilogue(float* __restrict__ out, int idx, float v, const FieldDev& f, const Scal& sc) {
+  if (EPI == EPI_STORE) { out[idx] = v; return false; }
   float a = f.buf[BUF_ABASE][idx] + v;
   a = a + 0.5f;
   a = a * sc.range;
   float xh = sc.xmin + a;
-  if (EPI == EPI_FINAL) { f.buf[BUF_XOUT][idx] = xh; return; }
-  // one atomic per wavefront that sees a violation, skipped once the flag
-  // is known to be set
-  const bool bad = fabs((double)f.buf[BUF_X][idx] - (double)xh) > sc.eps;
-  const unsigned long long m = __ballot(bad);
-  if (bad && (int)__lane_id() == __builtin_ctzll(m) && *(volatile const int*)f.flags == 0) atomicOr(&f.flags[0], 1);
+  if (EPI == EPI_FINAL) { f.buf[BUF_XOUT][idx] = xh; return false; }
+  return fabs((double)f.buf[BUF_X][idx] - (double)xh) > sc.eps;
+}
+
+// One atomic per workgroup that saw a violation.  Every thread of the
+// workgroup calls it.  (Reading the flag first to skip the atomic costs
+// more than it saves: thousands of wavefronts reading one word at system
+// scope are served one after another.)
+__device__ __forceinline__ void report_violation(bool bad, const FieldDev& f) {
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  if (__ballot(bad) != 0ull && __lane_id() == 0) s_bad = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && s_bad) atomicOr(&f.flags[0], 1);
 }
 
 // One lifting step along the first LDS index (rows) of a column tile.
@@ -146,7 +157,7 @@ __global__ __launch_bounds__(256) void k_inv_cols(const FieldDev* __restrict__ F
   // thread reads it so that the whole workgroup takes the same branch.
   if (EPI == EPI_CHECK && l == 1) {
     __shared__ int s_done;
-    if (threadIdx.x == 0) s_done = *(volatile const int*)f.flags;
+    if (threadIdx.x == 0) s_done = __hip_atomic_load(f.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (s_done) return;
   }
@@ -177,13 +188,15 @@ __global__ __launch_bounds__(256) void k_inv_cols(const FieldDev* __restrict__ F
   lift_rows<true>(s, NR, 2, 1, L97_G, tx, ty);
   lift_rows<true>(s, NR, 3, 0, L97_B, tx, ty);
   lift_rows<true>(s, NR, 4, 1, L97_A, tx, ty);
+  bool bad = false;
   for (int r = kHalo + ty; r < kColTileR + kHalo; r += 4) {
     int g = r0 - kHalo + r;
     if (g < H && col < W) {
-      if (l == 1) epilogue<EPI>(dp, g * nx + col, s[r][tx], f, sc);
+      if (l == 1) bad |= epilogue<EPI>(dp, g * nx + col, s[r][tx], f, sc);
       else dp[g * nx + col] = s[r][tx];
     }
   }
+  if (EPI == EPI_CHECK && l == 1) report_violation(bad, f);
 }
 
 // One lifting step along the second LDS index (columns) of a row tile.
@@ -289,15 +302,16 @@ template <int PRO, int EPI>
 __global__ __launch_bounds__(256) void k_pointwise(const FieldDev* __restrict__ F, int src, int dst, int lzero) {
   const FieldDev& f = F[blockIdx.y];
   if (!f.active || (lzero && f.L != 0)) return;
-  if (EPI == EPI_CHECK && *(volatile const int*)f.flags) return;   // violation already found
   const int n = f.ny * f.nx;
   Scal sc = load_scal(f.fp);
   const float* sp = f.buf[src];
   float* dp = f.buf[dst];
+  bool bad = false;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     float v = (PRO == 3) ? 0.0f : prologue<(PRO == 3 ? 0 : PRO)>(sp, i, f, sc);
-    epilogue<EPI>(dp, i, v, f, sc);
+    bad |= epilogue<EPI>(dp, i, v, f, sc);
   }
+  if (EPI == EPI_CHECK) report_violation(bad, f);
 }
 
 struct Grid2 { int gx, gy; };
