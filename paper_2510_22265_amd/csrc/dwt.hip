@@ -82,6 +82,19 @@ __device__ __forceinline__ bool epilogue(float* __restrict__ out, int idx, float
   return fabs((double)f.buf[BUF_X][idx] - (double)xh) > sc.eps;
 }
 
+// The epilogue with its two loads (base reconstruction and, for a check,
+// the original sample) already done by the caller: the same arithmetic.
+template <int EPI>
+__device__ __forceinline__ bool epilogue_loaded(int idx, float v, float abase, float x, const FieldDev& f,
+                                                const Scal& sc) {
+  float a = abase + v;
+  a = a + 0.5f;
+  a = a * sc.range;
+  float xh = sc.xmin + a;
+  if (EPI == EPI_FINAL) { f.buf[BUF_XOUT][idx] = xh; return false; }
+  return fabs((double)x - (double)xh) > sc.eps;
+}
+
 // One atomic per workgroup that saw a violation.  Every thread of the
 // workgroup calls it.  (Reading the flag first to skip the atomic costs
 // more than it saves: thousands of wavefronts reading one word at system
@@ -125,10 +138,16 @@ __global__ __launch_bounds__(256) void k_fwd_cols(const FieldDev* __restrict__ F
   int col = c0 + tx;
   Scal sc = {};
   if (PRO != PRO_COPY) sc = load_scal(f.fp);
-  for (int r = ty; r < NR; r += 4) {
-    int g = mirror(r0 - kHalo + r, H);
-    s[r][tx] = (col < W) ? prologue<PRO>(sp, g * nx + col, f, sc) : 0.0f;
-  }
+  // every load of the thread first, then the LDS writes: the loads are
+  // independent, and issuing them together hides the memory latency (a
+  // generic pointer may alias LDS, so the compiler keeps the order written)
+  constexpr int NPT = (kColTileR + 2 * kHalo) / 4;
+  const int cl = col < W ? col : W - 1;   // in bounds; the value is dropped
+  float v[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; i++) v[i] = prologue<PRO>(sp, mirror(r0 - kHalo + ty + 4 * i, H) * nx + cl, f, sc);
+#pragma unroll
+  for (int i = 0; i < NPT; i++) s[ty + 4 * i][tx] = (col < W) ? v[i] : 0.0f;
   __syncthreads();
   lift_rows<false>(s, NR, 1, 1, L97_A, tx, ty);
   lift_rows<false>(s, NR, 2, 0, L97_B, tx, ty);
@@ -173,30 +192,50 @@ __global__ __launch_bounds__(256) void k_inv_cols(const FieldDev* __restrict__ F
   int nl = (H + 1) >> 1;
   Scal sc = {};
   if (EPI != EPI_STORE) sc = load_scal(f.fp);
-  for (int r = ty; r < NR; r += 4) {
-    int g = mirror(r0 - kHalo + r, H);
-    float v = 0.0f;
-    if (col < W) {
-      int srow = (g & 1) ? nl + (g >> 1) : (g >> 1);
-      v = sp[srow * nx + col];
-      v = (g & 1) ? v * L97_IK : v * L97_K;
-    }
-    s[r][tx] = v;
+  constexpr int NPT = (kColTileR + 2 * kHalo) / 4;
+  const int cl = col < W ? col : W - 1;
+  float v[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; i++) {
+    const int g = mirror(r0 - kHalo + ty + 4 * i, H);
+    v[i] = sp[((g & 1) ? nl + (g >> 1) : (g >> 1)) * nx + cl];
+  }
+#pragma unroll
+  for (int i = 0; i < NPT; i++) {
+    const int g = mirror(r0 - kHalo + ty + 4 * i, H);
+    s[ty + 4 * i][tx] = (col < W) ? ((g & 1) ? v[i] * L97_IK : v[i] * L97_K) : 0.0f;
   }
   __syncthreads();
   lift_rows<true>(s, NR, 1, 0, L97_D, tx, ty);
   lift_rows<true>(s, NR, 2, 1, L97_G, tx, ty);
   lift_rows<true>(s, NR, 3, 0, L97_B, tx, ty);
   lift_rows<true>(s, NR, 4, 1, L97_A, tx, ty);
-  bool bad = false;
-  for (int r = kHalo + ty; r < kColTileR + kHalo; r += 4) {
-    int g = r0 - kHalo + r;
-    if (g < H && col < W) {
-      if (l == 1) bad |= epilogue<EPI>(dp, g * nx + col, s[r][tx], f, sc);
-      else dp[g * nx + col] = s[r][tx];
+  constexpr int NO = kColTileR / 4;
+  if (EPI != EPI_STORE && l == 1) {
+    // the epilogue's loads for all of the thread's rows first
+    const float* ab = f.buf[BUF_ABASE];
+    const float* xs = f.buf[BUF_X];
+    float av[NO], xv[NO];
+#pragma unroll
+    for (int i = 0; i < NO; i++) {
+      const int g = r0 + ty + 4 * i;
+      const int idx = (g < H ? g : H - 1) * nx + cl;
+      av[i] = ab[idx];
+      xv[i] = EPI == EPI_CHECK ? xs[idx] : 0.0f;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < NO; i++) {
+      const int g = r0 + ty + 4 * i;
+      if (g < H && col < W) bad |= epilogue_loaded<EPI>(g * nx + col, s[kHalo + ty + 4 * i][tx], av[i], xv[i], f, sc);
+    }
+    if (EPI == EPI_CHECK) report_violation(bad, f);
+  } else {
+    for (int r = kHalo + ty; r < kColTileR + kHalo; r += 4) {
+      int g = r0 - kHalo + r;
+      if (g < H && col < W) dp[g * nx + col] = s[r][tx];
     }
   }
-  if (EPI == EPI_CHECK && l == 1) report_violation(bad, f);
 }
 
 // One lifting step along the second LDS index (columns) of a row tile.
@@ -226,11 +265,24 @@ __global__ __launch_bounds__(256) void k_fwd_rows(const FieldDev* __restrict__ F
   __shared__ float s[kRowTileR][kRowTileC + 2 * kHalo + 1];
   const int NC = kRowTileC + 2 * kHalo;
   int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int rr = 0; rr < kRowTileR; rr++) {
-    int row = r0 + rr;
-    for (int cc = threadIdx.x; cc < NC; cc += 256) {
-      int g = mirror(c0 - kHalo + cc, W);
-      s[rr][cc] = (row < H) ? src[row * nx + g] : 0.0f;
+  {
+    // loads first (see k_fwd_cols); each thread holds one column, and the
+    // first NC - 256 threads a second one
+    const int cc1 = threadIdx.x + 256;
+    const int g0 = mirror(c0 - kHalo + (int)threadIdx.x, W);
+    float v0[kRowTileR], v1[kRowTileR];
+#pragma unroll
+    for (int rr = 0; rr < kRowTileR; rr++) v0[rr] = src[(r0 + rr < H ? r0 + rr : H - 1) * nx + g0];
+    if (cc1 < NC) {
+      const int g1 = mirror(c0 - kHalo + cc1, W);
+#pragma unroll
+      for (int rr = 0; rr < kRowTileR; rr++) v1[rr] = src[(r0 + rr < H ? r0 + rr : H - 1) * nx + g1];
+    }
+#pragma unroll
+    for (int rr = 0; rr < kRowTileR; rr++) {
+      const bool in = r0 + rr < H;
+      s[rr][threadIdx.x] = in ? v0[rr] : 0.0f;
+      if (cc1 < NC) s[rr][cc1] = in ? v1[rr] : 0.0f;
     }
   }
   __syncthreads();
@@ -267,17 +319,26 @@ __global__ __launch_bounds__(256) void k_inv_rows(const FieldDev* __restrict__ F
   const int NC = kRowTileC + 2 * kHalo;
   int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   int nl = (W + 1) >> 1;
-  for (int rr = 0; rr < kRowTileR; rr++) {
-    int row = r0 + rr;
-    for (int cc = threadIdx.x; cc < NC; cc += 256) {
-      int g = mirror(c0 - kHalo + cc, W);
-      float v = 0.0f;
-      if (row < H) {
-        int scol = (g & 1) ? nl + (g >> 1) : (g >> 1);
-        v = src[row * nx + scol];
-        v = (g & 1) ? v * L97_IK : v * L97_K;
-      }
-      s[rr][cc] = v;
+  {
+    // loads first (see k_fwd_cols)
+    const int cc1 = threadIdx.x + 256;
+    const int g0 = mirror(c0 - kHalo + (int)threadIdx.x, W);
+    const int sc0 = (g0 & 1) ? nl + (g0 >> 1) : (g0 >> 1);
+    float v0[kRowTileR], v1[kRowTileR];
+#pragma unroll
+    for (int rr = 0; rr < kRowTileR; rr++) v0[rr] = src[(r0 + rr < H ? r0 + rr : H - 1) * nx + sc0];
+    int g1 = 0;
+    if (cc1 < NC) {
+      g1 = mirror(c0 - kHalo + cc1, W);
+      const int sc1 = (g1 & 1) ? nl + (g1 >> 1) : (g1 >> 1);
+#pragma unroll
+      for (int rr = 0; rr < kRowTileR; rr++) v1[rr] = src[(r0 + rr < H ? r0 + rr : H - 1) * nx + sc1];
+    }
+#pragma unroll
+    for (int rr = 0; rr < kRowTileR; rr++) {
+      const bool in = r0 + rr < H;
+      s[rr][threadIdx.x] = in ? ((g0 & 1) ? v0[rr] * L97_IK : v0[rr] * L97_K) : 0.0f;
+      if (cc1 < NC) s[rr][cc1] = in ? ((g1 & 1) ? v1[rr] * L97_IK : v1[rr] * L97_K) : 0.0f;
     }
   }
   __syncthreads();
