@@ -840,6 +840,11 @@ struct Call {
     return EBCC_OK;
   }
   int upload() { return stage(F, Fh.data(), sizeof(FieldDev) * nf); }   // field table host -> device
+  int max_nblk() const {   // code-blocks of the largest field of the call
+    int m = 0;
+    for (int i = 0; i < nf; i++) m = std::max(m, Fh[i].nblk);
+    return m;
+  }
   // Work launched on ws->aux and ws->aux2 between fork() and join() runs
   // concurrently with the caller's stream and is complete, for that stream,
   // after join().
@@ -1149,7 +1154,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
           int rc2;
           if ((rc2 = c.set_active(ev))) return rc2;
           k_zero_slot<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf, 2);
-          pcrd(c.F, nf, c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
+          pcrd(c.F, nf, c.max_nblk(), c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
           virtual_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.pb, c.kb, c.sppf, st);
           dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, st);
           k_count_within<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
@@ -1194,7 +1199,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
         if (act[i]) c.Fh[i].budget = base_budget(fieldN(i), c.Fh[i].nblk, r_use[i]);
       if ((rc = c.set_active(act))) return rc;
     }
-    pcrd(c.F, nf, c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
+    pcrd(c.F, nf, c.max_nblk(), c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
     prof.mark(S_PCRD);
     // ---- A_base = dec_base(e_base) (closed form), residual, its DWT ----
     virtual_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.pb, c.kb, c.sppf, st);
@@ -1373,7 +1378,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
           ebcc_total[i] = mode[i] == MODE_CODED ? col[8 * i + 4] + (int64_t)c.Fh[i].rb
                                                 : 4 * (int64_t)c.Fh[i].ny * c.Fh[i].nx;
       if ((rc = c.set_active(fbc))) return rc;
-      pcrd(c.F, nf, c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
+      pcrd(c.F, nf, c.max_nblk(), c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
       if ((rc = c.collect_host(col))) return rc;
       std::vector<int> sw(nf, 0), restore(nf, 0);
       bool anysw = false, anyrs = false;
@@ -1391,7 +1396,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
       }
       if (anyrs) {   // PCRD at the search's ratio again for the fields that keep it
         if ((rc = c.set_active(restore))) return rc;
-        pcrd(c.F, nf, c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
+        pcrd(c.F, nf, c.max_nblk(), c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
       }
       if (anysw) {   // block table and base size of the base-only streams
         if ((rc = c.set_active(sw))) return rc;

@@ -143,7 +143,7 @@ struct Tuning {
 Tuning tuning();
 
 // pcrd.hip: one workgroup per field; kb/len per block.
-void pcrd(const FieldDev* F, int nf, const uint8_t* pb, const int32_t* R, const int64_t* D, uint8_t* kb,
+void pcrd(const FieldDev* F, int nf, int max_nblk, const uint8_t* pb, const int32_t* R, const int64_t* D, uint8_t* kb,
           uint8_t* hk_scratch, uint64_t* key_scratch, int32_t* dr_scratch, uint8_t* nh_scratch, int32_t* len_out,
           hipStream_t st);
 

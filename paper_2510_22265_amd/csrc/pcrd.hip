@@ -2,10 +2,13 @@
 // optimisation (PCRD, Taubman 2000) meeting the base compression ratio r of
 // the paper's enc_base(A, r, eps) (Algorithm 1).
 //
-// One workgroup per field:
-//  1. one thread per code-block builds the upper convex hull of its
-//     (R_k, D_k) pass points (strictly decreasing slopes; passes that do not
-//     add distortion reduction or whose length exceeds 65535 are skipped);
+//  1. one thread per code-block (64-thread workgroups over all the fields'
+//     blocks) builds the upper convex hull of its (R_k, D_k) pass points
+//     (strictly decreasing slopes; passes that do not add distortion
+//     reduction or whose length exceeds 65535 are skipped); the block's pass
+//     table is first copied to LDS with its loads issued together, so the
+//     hull walk reads LDS, not a chain of dependent global loads;
+// then one workgroup per field:
 //  2. the segments are ordered by the composite key (slope descending,
 //     block ascending, segment ascending); segments are accepted in that
 //     order until the first one that would overflow the byte budget.  The
@@ -32,9 +35,69 @@ __device__ __forceinline__ u128 seg_key(uint64_t slope_bits, int b, int j) {
   return ((u128)slope_bits << 40) | ((u128)(0xFFFFFFFFu - (uint32_t)b) << 8) | (u128)(0xFFu - (uint32_t)j);
 }
 
-__global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restrict__ F, const uint8_t* __restrict__ pb_g,
-                                                       const int32_t* __restrict__ R_g, const int64_t* __restrict__ D_g,
-                                                       uint8_t* __restrict__ kb_g, uint8_t* __restrict__ hk_g,
+constexpr int kHullThreads = 64;
+
+__global__ __launch_bounds__(kHullThreads) void k_pcrd_hull(const FieldDev* __restrict__ F,
+                                                            const uint8_t* __restrict__ pb_g,
+                                                            const int32_t* __restrict__ R_g,
+                                                            const int64_t* __restrict__ D_g, uint8_t* __restrict__ hk_g,
+                                                            uint64_t* __restrict__ keys_g, int32_t* __restrict__ dr_g,
+                                                            uint8_t* __restrict__ nhv_g) {
+  __shared__ int64_t sd[kHullThreads][kPassStride];
+  __shared__ int32_t sr[kHullThreads][kPassStride];
+  __shared__ uint8_t sh[kHullThreads][kPassStride];
+  const FieldDev& f = F[blockIdx.y];
+  if (!f.active) return;
+  const int b = blockIdx.x * kHullThreads + (int)threadIdx.x;
+  if (b >= f.nblk) return;   // no barrier below
+  const size_t gb = (size_t)f.blk0 + (size_t)b;
+  const int P = pb_g[gb];
+  const int n = P ? 3 * P - 2 : 0;
+  const int32_t* r = R_g + gb * kPassStride;
+  const int64_t* d = D_g + gb * kPassStride;
+  int32_t* lr = sr[threadIdx.x];
+  int64_t* ld = sd[threadIdx.x];
+  uint8_t* h = sh[threadIdx.x];
+  for (int k0 = 0; k0 <= n; k0 += 8) {
+    int32_t rv[8];
+    int64_t dv[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+      if (k0 + u <= n) { rv[u] = r[k0 + u]; dv[u] = d[k0 + u]; }
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+      if (k0 + u <= n) { lr[k0 + u] = rv[u]; ld[k0 + u] = dv[u]; }
+  }
+  int nh = 0;
+  h[nh++] = 0;
+  for (int k = 1; k <= n; k++) {
+    const int32_t rk = lr[k];
+    if (rk > kSegRMax) continue;
+    const int64_t dk = ld[k];
+    if (dk <= ld[h[nh - 1]]) continue;
+    while (nh >= 2) {
+      const int a = h[nh - 2], c = h[nh - 1];
+      const double sac = seg_slope(ld[c] - ld[a], (int64_t)lr[c] - lr[a]);
+      const double sck = seg_slope(dk - ld[c], (int64_t)rk - lr[c]);
+      if (sck >= sac) nh--; else break;
+    }
+    h[nh++] = (uint8_t)k;
+  }
+  nhv_g[gb] = (uint8_t)nh;
+  uint8_t* hk = hk_g + gb * kPassStride;
+  uint64_t* keys = keys_g + gb * kPassStride;
+  int32_t* dr = dr_g + gb * kPassStride;
+  hk[0] = 0;
+  for (int j = 1; j < nh; j++) {
+    const int a = h[j - 1], c = h[j];
+    hk[j] = (uint8_t)c;
+    keys[j] = (uint64_t)__double_as_longlong(seg_slope(ld[c] - ld[a], (int64_t)lr[c] - lr[a]));
+    dr[j] = lr[c] - lr[a];
+  }
+}
+
+__global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restrict__ F,
+                                                       const int32_t* __restrict__ R_g, uint8_t* __restrict__ kb_g, uint8_t* __restrict__ hk_g,
                                                        uint64_t* __restrict__ keys_g, int32_t* __restrict__ dr_g,
                                                        uint8_t* __restrict__ nhv_g, int32_t* __restrict__ len_g) {
   __shared__ unsigned long long hist[256];
@@ -50,9 +113,7 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
   const size_t b0 = (size_t)f.blk0;
   const int nblk = f.nblk;
   const int64_t budget = f.budget < 0 ? 0 : f.budget;
-  const uint8_t* pb = pb_g + b0;
   const int32_t* R = R_g + b0 * kPassStride;
-  const int64_t* D = D_g + b0 * kPassStride;
   uint8_t* kb = kb_g + b0;
   uint8_t* hk = hk_g + b0 * kPassStride;
   uint64_t* keys = keys_g + b0 * kPassStride;
@@ -60,36 +121,6 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
   uint8_t* nhv = nhv_g + b0;
   int32_t* len_out = len_g + b0;
   int tid = threadIdx.x;
-  // 1. hulls
-  for (int b = tid; b < nblk; b += kPcrdThreads) {
-    int P = pb[b];
-    int n = P ? 3 * P - 2 : 0;
-    const int32_t* r = R + (size_t)b * kPassStride;
-    const int64_t* d = D + (size_t)b * kPassStride;
-    uint8_t* h = hk + (size_t)b * kPassStride;
-    int nh = 0;
-    h[nh++] = 0;
-    for (int k = 1; k <= n; k++) {
-      int32_t rk = r[k];
-      if (rk > kSegRMax) continue;
-      int64_t dk = d[k];
-      if (dk <= d[h[nh - 1]]) continue;
-      while (nh >= 2) {
-        int a = h[nh - 2], c = h[nh - 1];
-        double sac = seg_slope(d[c] - d[a], (int64_t)r[c] - r[a]);
-        double sck = seg_slope(dk - d[c], (int64_t)rk - r[c]);
-        if (sck >= sac) nh--; else break;
-      }
-      h[nh++] = (uint8_t)k;
-    }
-    nhv[b] = (uint8_t)nh;
-    for (int j = 1; j < nh; j++) {
-      int a = h[j - 1], c = h[j];
-      keys[(size_t)b * kPassStride + j] = (uint64_t)__double_as_longlong(seg_slope(d[c] - d[a], (int64_t)r[c] - r[a]));
-      dr[(size_t)b * kPassStride + j] = r[c] - r[a];
-    }
-  }
-  __syncthreads();
   // 2. radix select of the first segment that does not fit.  The first two
   // digits scan every segment in global memory; the segments that still
   // match the selected prefix are then copied to LDS (when they fit) and the
@@ -207,11 +238,14 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
   }
 }
 
-void pcrd(const FieldDev* F, int nf, const uint8_t* pb, const int32_t* R, const int64_t* D, uint8_t* kb,
+void pcrd(const FieldDev* F, int nf, int max_nblk, const uint8_t* pb, const int32_t* R, const int64_t* D, uint8_t* kb,
           uint8_t* hk_scratch, uint64_t* key_scratch, int32_t* dr_scratch, uint8_t* nh_scratch, int32_t* len_out,
           hipStream_t st) {
   if (nf <= 0) return;
-  k_pcrd<<<nf, kPcrdThreads, 0, st>>>(F, pb, R, D, kb, hk_scratch, key_scratch, dr_scratch, nh_scratch, len_out);
+  if (max_nblk > 0)
+    k_pcrd_hull<<<dim3((unsigned)((max_nblk + kHullThreads - 1) / kHullThreads), (unsigned)nf), kHullThreads, 0, st>>>(
+        F, pb, R, D, hk_scratch, key_scratch, dr_scratch, nh_scratch);
+  k_pcrd<<<nf, kPcrdThreads, 0, st>>>(F, R, kb, hk_scratch, key_scratch, dr_scratch, nh_scratch, len_out);
 }
 
 }  // namespace ebcc
