@@ -165,16 +165,37 @@ __global__ __launch_bounds__(kPcrdThreads) void k_pcrd(const FieldDev* __restric
       }
     }
     __syncthreads();
-    if (tid == 0) {
-      int choice = -1;
-      unsigned long long a = acc;
-      for (int t = 255; t >= 0; t--) {
-        if (a + hist[t] > (unsigned long long)budget) { choice = t; break; }
-        a += hist[t];
+    if (tid < 64) {
+      // digits from 255 down: the first whose segments would overflow the
+      // budget after all higher digits are accepted.  Lane q holds digits
+      // 255 - 4q .. 252 - 4q; a wave prefix sum gives each lane the total
+      // of the digits above its own.
+      unsigned long long v[4], sum = 0;
+#pragma unroll
+      for (int i = 0; i < 4; i++) { v[i] = hist[255 - 4 * tid - i]; sum += v[i]; }
+      unsigned long long inc = sum;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long t = __shfl_up(inc, o);
+        if (tid >= o) inc += t;
       }
-      s_choice = choice;
-      s_acc = a;
-      s_allfit = choice < 0;
+      unsigned long long a = acc + (inc - sum);   // accepted before this lane's digits
+      int hit = -1;
+      unsigned long long ahit = 0;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        if (hit < 0 && a + v[i] > (unsigned long long)budget) { hit = i; ahit = a; }
+        a += v[i];
+      }
+      const unsigned long long m = __ballot(hit >= 0);
+      const int first = m ? __builtin_ctzll(m) : -1;
+      if (first < 0) {
+        if (tid == 63) { s_choice = -1; s_acc = a; s_allfit = 1; }
+      } else if (tid == first) {
+        s_choice = 255 - 4 * tid - hit;
+        s_acc = ahit;
+        s_allfit = 0;
+      }
     }
     __syncthreads();
     if (s_allfit) { allfit = true; break; }
