@@ -171,19 +171,43 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
   if (lane == 0) misfit[t] = 0;
   const TileGeom& g = S.g;
   // coefficients and descendant maxima into LDS; the tile's top plane
+  // four samples per lane at a time, their global loads issued together
+  // (a generic pointer may alias LDS, so loads written between LDS stores
+  // would each wait for the one before)
   uint32_t mx = 0;
   for (int b = 0; b < nb; b++) {
-    int n = g.hr[b] * g.wr[b];
-    for (int r = lane; r < n; r += 64) {
-      int li = r / g.wr[b], lj = r - li * g.wr[b];
-      int p = (S.B[b].y0 + g.r0[b] + li) * nx + S.B[b].x0 + g.c0[b] + lj;
-      int loc = g.off[b] + r;
-      S.qv[loc] = qr[p];
-      if (loc < g.nparents) {
-        S.mdl[loc] = (uint8_t)blen(maxd[p]);
-        S.mll[loc] = (uint8_t)blen(maxl[p]);
+    const int n = g.hr[b] * g.wr[b], wr = g.wr[b];
+    const int y0 = S.B[b].y0 + g.r0[b], x0 = S.B[b].x0 + g.c0[b], off = g.off[b];
+    for (int r0 = 0; r0 < n; r0 += 256) {
+      int p[4];
+      uint32_t qv[4], md[4], ml[4], sv[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int r = r0 + 64 * u + lane;
+        const int rc = r < n ? r : n - 1;   // in bounds; the value is dropped
+        const int li = rc / wr, lj = rc - li * wr;
+        p[u] = (y0 + li) * nx + x0 + lj;
       }
-      if (b == 0) { uint32_t s = sub[p]; mx = s > mx ? s : mx; }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const bool par = off + r0 + 64 * u + lane < g.nparents;
+        qv[u] = qr[p[u]];
+        md[u] = par ? maxd[p[u]] : 0u;
+        ml[u] = par ? maxl[p[u]] : 0u;
+        sv[u] = b == 0 ? sub[p[u]] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int r = r0 + 64 * u + lane;
+        if (r >= n) continue;
+        const int loc = off + r;
+        S.qv[loc] = qv[u];
+        if (loc < g.nparents) {
+          S.mdl[loc] = (uint8_t)blen(md[u]);
+          S.mll[loc] = (uint8_t)blen(ml[u]);
+        }
+        if (b == 0) mx = sv[u] > mx ? sv[u] : mx;
+      }
     }
   }
   for (int o = 32; o > 0; o >>= 1) { uint32_t v = __shfl_xor(mx, o); mx = v > mx ? v : mx; }
