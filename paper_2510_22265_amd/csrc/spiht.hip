@@ -9,8 +9,9 @@
 // (column) than twice the coarser band, the parents of the last row (column)
 // also take that row (column); level-1 coefficients are leaves.
 //
-//  * k_maxima: per band, coarse-to-fine dependency order reversed (level 2
-//    first), one thread per node: the maximum magnitude over the node's
+//  * k_maxima: one launch per level, fine to coarse (level 2 first, the
+//    three orientations side by side), one thread per node: the maximum
+//    magnitude over the node's
 //    descendants (maxD), over its grand-descendants and below (maxL), and
 //    over its subtree including itself (sub).
 //  * k_spiht_encode / k_spiht_decode: one lane per tile; the three lists
@@ -64,8 +65,9 @@ __device__ __forceinline__ int child_level(const Band* B, int L, int band) { ret
 // denotes the LL roots.
 __device__ __forceinline__ int band_index(int L, int lvl, int o) { return lvl == 0 ? 0 : 1 + 3 * (L - lvl) + o; }
 
-__global__ __launch_bounds__(256) void k_maxima(const FieldDev* __restrict__ F, int lvl, int o) {
+__global__ __launch_bounds__(256) void k_maxima(const FieldDev* __restrict__ F, int lvl) {
   const FieldDev& f = F[blockIdx.y];
+  const int o = (int)blockIdx.z;   // the three orientations of a level are independent
   if (!f.active || lvl > f.L || (lvl == 1)) return;
   const int L = f.L, nx = f.nx;
   const Band* bands = f.bands;
@@ -120,16 +122,17 @@ void spiht_maxima(const FieldDev* F, const FieldDev* Fh, int nf, hipStream_t st)
   int Lm = 0;
   for (int i = 0; i < nf; i++)
     if (Fh[i].active) Lm = std::max(Lm, Fh[i].L);
-  // finer parents first: levels 2 .. L, then the LL roots
-  for (int l = 2; l <= Lm; l++)
-    for (int o = 0; o < 3; o++) {
-      int n = max_band_size(Fh, nf, l, o);
-      int g = std::min(2048, std::max(1, (n + 255) / 256));
-      if (n > 0) k_maxima<<<dim3(g, nf), 256, 0, st>>>(F, l, o);
-    }
+  // finer parents first: levels 2 .. L (one launch per level, blockIdx.z
+  // the orientation), then the LL roots
+  for (int l = 2; l <= Lm; l++) {
+    int n = 0;
+    for (int o = 0; o < 3; o++) n = std::max(n, max_band_size(Fh, nf, l, o));
+    int g = std::min(2048, std::max(1, (n + 255) / 256));
+    if (n > 0) k_maxima<<<dim3(g, nf, 3), 256, 0, st>>>(F, l);
+  }
   int n = max_band_size(Fh, nf, 0, 0);
   int g = std::min(2048, std::max(1, (n + 255) / 256));
-  k_maxima<<<dim3(g, nf), 256, 0, st>>>(F, 0, 0);
+  k_maxima<<<dim3(g, nf, 1), 256, 0, st>>>(F, 0);
 }
 
 // Tiles per wavefront: one per wavefront for a lone field (latency), up to

@@ -166,12 +166,14 @@ def test_full_size_era5_stack_fields(gpu, ref, var, eps):
     _roundtrip(gpu, ref, synth.field(var, 721, 1440, cfg=1, level=17), eps)
 
 
-@pytest.mark.parametrize("variant", ["lane", "wave"])
+@pytest.mark.parametrize("variant", ["lane", "wave", "wave-nopipe"])
 @pytest.mark.parametrize("cb", [(5, 5), (6, 6), (2, 3), (6, 4)])
 def test_tier1_kernel_variants(gpu, ref, variant, cb, monkeypatch):
     """Both tier-1 kernel families (wave per block for few blocks, lanes per
-    block for large batches) produce the oracle's stream and decode."""
-    monkeypatch.setenv("EBCC_T1_KERNEL", variant)
+    block for large batches), and the wave encoder with and without its
+    modelling/coding pipeline, produce the oracle's stream and decode."""
+    monkeypatch.setenv("EBCC_T1_KERNEL", variant.split("-")[0])
+    monkeypatch.setenv("EBCC_T1_PIPE", "0" if variant.endswith("nopipe") else "1")
     x = synth.field("u", 181, 360, cfg=1, level=11)
     _roundtrip(gpu, ref, x, 0.002, cbl2w=cb[0], cbl2h=cb[1])
 
