@@ -642,6 +642,34 @@ static int get_plan(int ny, int nx, int L, int cbl2w, int cbl2h, int T, Plan** o
 // Host-to-device copies of a call go through the workspace's pinned staging
 // buffer (the host source of an asynchronous copy must outlive it); the
 // event recorded at the end of each call guards the buffer's reuse.
+// Waits until everything queued on st has finished by polling an event.  A
+// blocking synchronisation wakes the host thread tens of microseconds after
+// the device is done, and a call makes several such round trips (header
+// reads, search rounds, size tables).  One event per device and host thread.
+static hipEvent_t sync_event() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  static thread_local std::map<int, hipEvent_t> evs;
+  auto it = evs.find(dev);
+  if (it != evs.end()) return it->second;
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  evs[dev] = e;
+  return e;
+}
+static int wait_stream(hipStream_t st) {
+  hipEvent_t ev = sync_event();
+  if (!ev || hipEventRecord(ev, st) != hipSuccess) {
+    HIPCHK(hipStreamSynchronize(st));
+    return EBCC_OK;
+  }
+  hipError_t e;
+  while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+  }
+  if (e != hipSuccess) return fail(EBCC_EHIP, std::string("waiting for the stream: ") + hipGetErrorString(e));
+  return EBCC_OK;
+}
+
 struct WS {
   void* base = nullptr;
   size_t cap = 0;
@@ -824,7 +852,7 @@ struct Call {
     if (!n) return EBCC_OK;
     size_t a = (pin_used + 255) & ~(size_t)255;
     if (a + n > ws->pin_cap) {
-      HIPCHK(hipStreamSynchronize(st));
+      if (int rc = wait_stream(st)) return rc;
       a = 0;
     }
     memcpy(ws->pin + a, src, n);
@@ -835,7 +863,7 @@ struct Call {
   // Device-to-host copy and synchronisation (the staging buffer is free again).
   template <typename T> int fetch(T* h, const T* d, size_t n) {
     HIPCHK(hipMemcpyAsync(h, d, sizeof(T) * n, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if (int rc = wait_stream(st)) return rc;
     pin_used = 0;
     return EBCC_OK;
   }
@@ -1469,7 +1497,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     }
     info[10] = checks[0];
     if (tr->info) memcpy(tr->info, info, sizeof(info));
-    HIPCHK(hipStreamSynchronize(st));
+    if (int rc2 = wait_stream(st)) return rc2;
   }
   return EBCC_OK;
 }
@@ -1496,7 +1524,7 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
     if (in[i].len >= (size_t)kHdr)
       HIPCHK(hipMemcpyAsync(hdr.data() + kHdr * (size_t)i, in[i].in, kHdr, hipMemcpyDeviceToHost, st));
   }
-  HIPCHK(hipStreamSynchronize(st));
+  if (int rc0 = wait_stream(st)) return rc0;
   Call c;
   c.nf = nf;
   c.st = st;
