@@ -1637,6 +1637,18 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
     k_scan<<<nf, 1024, 0, st>>>(c.F, c.tent, 1, 0, 0x3FFFFFFu, c.toff);
     k_check_tables<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
     prof.mark(S_D_PARSE);
+    // the residual's inverse DWT runs on the third stream with its own field
+    // table: the fields with a residual, scratch in BUF_CRES (unused when
+    // decoding) so that it does not meet the base transform's BUF_TMP
+    std::vector<FieldDev> Fr;
+    if (anyres) {
+      Fr = c.Fh;
+      for (int i = 0; i < nf; i++) {
+        Fr[i].active = cr[i];
+        Fr[i].buf[BUF_TMP] = Fr[i].buf[BUF_CRES];
+      }
+      if ((rc = c.stage(c.Fc, Fr.data(), sizeof(FieldDev) * nf))) return rc;
+    }
     if (anyres) {
       // The residual layer decodes independently of the base layer: SPIHT
       // runs on the second and third streams while tier-1 decoding and the base
@@ -1656,6 +1668,12 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
         spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sb);
         spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, sa);
       }
+      // all of the residual's inverse DWT but its last pass, in the shadow of
+      // tier-1 decoding, once both SPIHT streams are done
+      hipStream_t sb = c.ws->aux2;
+      HIPCHK(hipEventRecord(c.ws->ev_join, sa));
+      HIPCHK(hipStreamWaitEvent(sb, c.ws->ev_join, 0));
+      dwt_inverse_head(c.Fc, Fr.data(), nf, BUF_CHAT, sb);
     }
     // (no scalar/vector split here: the second stream is busy with SPIHT)
     t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, st);
@@ -1665,8 +1683,7 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
     if (anyres) {
       if ((rc = c.join())) return rc;
       prof.mark(S_D_SPIHT);
-      if ((rc = c.set_active(cr))) return rc;
-      dwt_inverse(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, EPI_FINAL, st);
+      dwt_inverse_tail(c.Fc, Fr.data(), nf, BUF_CHAT, BUF_CHAT, EPI_FINAL, st);
     }
     if (anynores) {
       if ((rc = c.set_active(cn))) return rc;

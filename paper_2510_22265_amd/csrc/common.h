@@ -100,6 +100,8 @@ void dwt_forward(const FieldDev* F, const FieldDev* Fh, int nf, int src, int dst
 // the epilogue into buf[out] (EPI_STORE), buf[BUF_XOUT] (EPI_FINAL), or only
 // checks the bound (EPI_CHECK, flags[0]).
 void dwt_inverse(const FieldDev* F, const FieldDev* Fh, int nf, int a, int out, int epilogue, hipStream_t st);
+void dwt_inverse_head(const FieldDev* F, const FieldDev* Fh, int nf, int a, hipStream_t st);
+void dwt_inverse_tail(const FieldDev* F, const FieldDev* Fh, int nf, int a, int out, int epilogue, hipStream_t st);
 // Elementwise prologue (PRO_*, or 3 = zero) and epilogue over whole fields.
 void pointwise(const FieldDev* F, const FieldDev* Fh, int nf, int src, int dst, int prologue, int epilogue,
                int lzero_only, hipStream_t st);

@@ -421,20 +421,35 @@ void dwt_forward(const FieldDev* F, const FieldDev* Fh, int nf, int src, int dst
   }
 }
 
-void dwt_inverse(const FieldDev* F, const FieldDev* Fh, int nf, int a, int out, int epi, hipStream_t st) {
-  if (any_lzero(Fh, nf)) pointwise(F, Fh, nf, a, out, PRO_COPY, epi, 1, st);
+// The passes of the inverse transform but the last (level 1's vertical pass,
+// the one with the epilogue), and that last pass with the fields of one
+// level (L = 0) done pointwise: split so that the first part can run on
+// another stream before the epilogue's inputs are ready.
+void dwt_inverse_head(const FieldDev* F, const FieldDev* Fh, int nf, int a, hipStream_t st) {
   int Lm = max_L(Fh, nf);
   for (int l = Lm; l >= 1; l--) {
     Grid2 r = level_grid(Fh, nf, l, kRowTileC, kRowTileR);
     if (r.gx == 0) continue;
     k_inv_rows<<<dim3(r.gx, r.gy, nf), 256, 0, st>>>(F, l, a);
+    if (l == 1) break;
     Grid2 c = level_grid(Fh, nf, l, kColTileC, kColTileR);
-    dim3 gc(c.gx, c.gy, nf);
-    int e = (l == 1) ? epi : EPI_STORE;
-    if (e == EPI_FINAL) k_inv_cols<EPI_FINAL><<<gc, 256, 0, st>>>(F, l, a, out);
-    else if (e == EPI_CHECK) k_inv_cols<EPI_CHECK><<<gc, 256, 0, st>>>(F, l, a, out);
-    else k_inv_cols<EPI_STORE><<<gc, 256, 0, st>>>(F, l, a, out);
+    k_inv_cols<EPI_STORE><<<dim3(c.gx, c.gy, nf), 256, 0, st>>>(F, l, a, a);
   }
+}
+
+void dwt_inverse_tail(const FieldDev* F, const FieldDev* Fh, int nf, int a, int out, int epi, hipStream_t st) {
+  if (any_lzero(Fh, nf)) pointwise(F, Fh, nf, a, out, PRO_COPY, epi, 1, st);
+  Grid2 c = level_grid(Fh, nf, 1, kColTileC, kColTileR);
+  if (c.gx == 0) return;
+  dim3 gc(c.gx, c.gy, nf);
+  if (epi == EPI_FINAL) k_inv_cols<EPI_FINAL><<<gc, 256, 0, st>>>(F, 1, a, out);
+  else if (epi == EPI_CHECK) k_inv_cols<EPI_CHECK><<<gc, 256, 0, st>>>(F, 1, a, out);
+  else k_inv_cols<EPI_STORE><<<gc, 256, 0, st>>>(F, 1, a, out);
+}
+
+void dwt_inverse(const FieldDev* F, const FieldDev* Fh, int nf, int a, int out, int epi, hipStream_t st) {
+  dwt_inverse_head(F, Fh, nf, a, st);
+  dwt_inverse_tail(F, Fh, nf, a, out, epi, st);
 }
 
 void pointwise(const FieldDev* F, const FieldDev* Fh, int nf, int src, int dst, int pro, int epi, int lzero,
