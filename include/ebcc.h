@@ -166,8 +166,10 @@ int ebcc_compress_trace(const float* d_x, size_t ny, size_t nx, const ebcc_param
 /* ---------------------------------------------------------------------------
  * Stage profiling.  When enabled, every call records HIP events on its
  * stream at stage boundaries (base DWT, tier-1 encode, rate allocation, ...)
- * and adds each stage's device time to process-wide accumulators; enabled
- * calls synchronise their stream once more before returning.
+ * and adds each stage's device time to process-wide accumulators.  A call
+ * only records its events; they are read once the device has passed them
+ * (at a later call, or in ebcc_profile_read / ebcc_profile_enable, which
+ * wait for the outstanding ones), so profiling adds no synchronisation.
  *   ebcc_profile_enable(on)   enable/disable and reset the accumulators
  *   ebcc_profile_read(ms, calls, n)  copy up to n stage totals (milliseconds,
  *                             number of timed occurrences); returns the

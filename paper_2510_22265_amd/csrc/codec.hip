@@ -39,8 +39,10 @@ static int fail(int code, const std::string& msg) {
 // ---------------------------------------------------------------------------
 // Stage profiling: HIP events recorded on the caller's stream at stage
 // boundaries; the time since the previous boundary is added to the stage
-// that just ended.  Off unless enabled (then every call synchronises once
-// more at its end to read the events).
+// that just ended.  Off unless enabled.  A call only records its events
+// (taken from a per-device pool) and queues them; they are read once the
+// stream has passed them — at a later call, or in ebcc_profile_read, which
+// waits for the outstanding ones — so profiling adds no synchronisation.
 // ---------------------------------------------------------------------------
 enum Stage {
   S_SCALARS, S_DWT, S_QUANT, S_T1ENC, S_PCRD, S_BASEREC, S_RESID, S_SEARCH, S_SPIHT, S_PACK,
@@ -53,31 +55,42 @@ static const char* kStageNames[S_COUNT] = {
 static int g_prof = 0;
 static double g_stage_ms[S_COUNT];
 static long g_stage_calls[S_COUNT];
-static std::mutex g_prof_mu;
+static std::mutex g_prof_mu;   // guards everything below and the accumulators
 
-struct Prof {
-  hipStream_t st;
-  bool on;
-  hipEvent_t prev = nullptr;
+struct ProfRec {
+  int dev;
+  hipEvent_t first;
   std::vector<std::pair<int, hipEvent_t>> marks;
-  hipEvent_t first = nullptr;
-  explicit Prof(hipStream_t s) : st(s), on(g_prof != 0) {
-    if (!on) return;
-    if (hipEventCreate(&first) != hipSuccess || hipEventRecord(first, st) != hipSuccess) on = false;
+};
+static std::vector<ProfRec> g_prof_pending;
+static std::map<int, std::vector<hipEvent_t>> g_ev_pool;
+
+static hipEvent_t pool_get(int dev) {
+  std::vector<hipEvent_t>& p = g_ev_pool[dev];
+  if (!p.empty()) {
+    hipEvent_t e = p.back();
+    p.pop_back();
+    return e;
   }
-  void mark(int stage) {
-    if (!on) return;
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
-    (void)hipEventRecord(e, st);
-    marks.push_back(std::make_pair(stage, e));
-  }
-  ~Prof() {
-    if (!on) return;
-    (void)hipStreamSynchronize(st);
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    hipEvent_t a = first;
-    for (auto& m : marks) {
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+// Adds the stage times of the queued calls the device has finished (all of
+// them, waiting, when wait is set) and returns their events to the pool.
+static void prof_resolve(bool wait) {
+  size_t keep = 0;
+  for (size_t i = 0; i < g_prof_pending.size(); i++) {
+    ProfRec& r = g_prof_pending[i];
+    hipEvent_t last = r.marks.empty() ? r.first : r.marks.back().second;
+    if (wait) (void)hipEventSynchronize(last);
+    else if (hipEventQuery(last) != hipSuccess) {
+      if (keep != i) g_prof_pending[keep] = std::move(r);
+      keep++;
+      continue;
+    }
+    hipEvent_t a = r.first;
+    for (auto& m : r.marks) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, a, m.second) == hipSuccess) {
         g_stage_ms[m.first] += ms;
@@ -85,8 +98,47 @@ struct Prof {
       }
       a = m.second;
     }
-    for (auto& m : marks) (void)hipEventDestroy(m.second);
-    (void)hipEventDestroy(first);
+    std::vector<hipEvent_t>& p = g_ev_pool[r.dev];
+    p.push_back(r.first);
+    for (auto& m : r.marks) p.push_back(m.second);
+  }
+  g_prof_pending.resize(keep);
+}
+
+struct Prof {
+  hipStream_t st;
+  bool on;
+  ProfRec rec;
+  explicit Prof(hipStream_t s) : st(s), on(g_prof != 0) {
+    if (!on) return;
+    rec.dev = 0;
+    (void)hipGetDevice(&rec.dev);
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      rec.first = pool_get(rec.dev);
+    }
+    if (!rec.first || hipEventRecord(rec.first, st) != hipSuccess) on = false;
+  }
+  void mark(int stage) {
+    if (!on) return;
+    hipEvent_t e;
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      e = pool_get(rec.dev);
+    }
+    if (!e) return;
+    if (hipEventRecord(e, st) != hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_ev_pool[rec.dev].push_back(e);
+      return;
+    }
+    rec.marks.push_back(std::make_pair(stage, e));
+  }
+  ~Prof() {
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(std::move(rec));
+    prof_resolve(false);
   }
 };
 
@@ -1858,12 +1910,14 @@ const char* ebcc_last_error(void) { return g_err.c_str(); }
 
 void ebcc_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_resolve(true);
   g_prof = on ? 1 : 0;
   for (int i = 0; i < S_COUNT; i++) { g_stage_ms[i] = 0.0; g_stage_calls[i] = 0; }
 }
 
 int ebcc_profile_read(double* ms, long* calls, int n) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_resolve(true);
   for (int i = 0; i < n && i < S_COUNT; i++) {
     if (ms) ms[i] = g_stage_ms[i];
     if (calls) calls[i] = g_stage_calls[i];
