@@ -894,7 +894,7 @@ struct Call {
   int spec_depth = 1;
   FieldDev* Fc = nullptr;
   int* cand_flags = nullptr;
-  std::vector<float*> cand_buf;   // per field: 6 planes (3 x CHAT, TMP) or none
+  std::vector<float*> cand_buf;   // per field: CHAT and TMP planes of the extra candidates, or none
 
   ~Call() {
     if (ws && hipEventRecord(ws->ev, st) == hipSuccess) ws->ev_live = true;
@@ -902,6 +902,7 @@ struct Call {
   // Asynchronous host-to-device copy through the pinned staging buffer.
   int stage(void* dst, const void* src, size_t n) {
     if (!n) return EBCC_OK;
+    if (n > ws->pin_cap) return fail(EBCC_ENOMEM, "staging buffer smaller than a table");
     size_t a = (pin_used + 255) & ~(size_t)255;
     if (a + n > ws->pin_cap) {
       if (int rc = wait_stream(st)) return rc;
@@ -992,11 +993,15 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
   c.tlen = cv.take<uint32_t>(nt); c.tent = cv.take<uint32_t>(nt); c.toff = cv.take<int64_t>(nt);
   c.misfit = cv.take<int>(nt);
   c.collect = cv.take<int64_t>(8 * (size_t)c.nf);
-  c.Fc = cv.take<FieldDev>(4 * (size_t)c.nf);
-  c.cand_flags = cv.take<int>(8 * 4 * (size_t)c.nf);
+  // candidates per field and search round: "all planes" and the nodes of
+  // spec_depth levels of the bisection tree
+  const size_t ncand = std::max<size_t>(4, (size_t)1 << c.spec_depth);
+  c.Fc = cv.take<FieldDev>(ncand * (size_t)c.nf);
+  c.cand_flags = cv.take<int>(8 * ncand * (size_t)c.nf);
   c.cand_buf.assign(c.nf, nullptr);
   for (int i = 0; i < c.nf; i++)
-    if (c.spec_depth > 1 && coded[i]) c.cand_buf[i] = cv.take<float>(6 * (size_t)c.Fh[i].ny * c.Fh[i].nx);
+    if (c.spec_depth > 1 && coded[i])
+      c.cand_buf[i] = cv.take<float>(2 * (ncand - 1) * (size_t)c.Fh[i].ny * c.Fh[i].nx);
   c.d_blk_own = cv.take<Blk>(nb);
   c.d_tiles_own = cv.take<TileD>(nt);
   c.d_slot_own = cv.take<int64_t>(nt + 1);
@@ -1012,7 +1017,9 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
 // Largest single staged copy of a call, doubled (the staging buffer then
 // holds at least two copies before it has to wait).
 static size_t pin_need(const Call& c) {
-  size_t m = sizeof(FieldDev) * (size_t)c.nf;
+  // the largest table staged at once: the search rounds' candidate fields
+  // (up to 2^spec_depth per field), block and tile tables
+  size_t m = sizeof(FieldDev) * (size_t)c.nf * std::max<size_t>(4, (size_t)1 << c.spec_depth);
   m = std::max(m, sizeof(Blk) * (size_t)c.nblk);
   m = std::max(m, sizeof(TileD) * (size_t)c.ntiles);
   m = std::max(m, sizeof(int64_t) * ((size_t)c.ntiles + 1));
@@ -1141,12 +1148,13 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   // every field is laid out as coded (the mode is known only on the device)
   std::vector<int> coded(nf, 1);
   build_items(c, coded);
-  // small calls evaluate two bisection levels per search round (fewer
-  // read-backs); large batches one (the device is busy anyway)
+  // small calls evaluate four bisection levels per search round (one round
+  // for up to 16 planes: one read-back), mid-sized ones two, large batches
+  // one (the device is busy anyway)
   {
     size_t tot = 0;
     for (auto& f : c.Fh) tot += (size_t)f.ny * f.nx;
-    c.spec_depth = tot <= ((size_t)1 << 24) ? 2 : 1;
+    c.spec_depth = tot <= ((size_t)1 << 22) ? 4 : (tot <= ((size_t)1 << 24) ? 2 : 1);
   }
   c.forced_global = spiht_forced_global();
   c.need_lists = c.forced_global;
