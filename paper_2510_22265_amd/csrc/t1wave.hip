@@ -1103,8 +1103,11 @@ void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
   if (nblk <= 0) return;
   const char* pe = getenv("EBCC_T1_PIPE");
   const bool pipe = !(pe && pe[0] == '0');
+  // three modelling wavefronts: with two the coder still waits for the
+  // next planes now and then (1.51 against 1.46 ms per 721x1440 field),
+  // with four or five they crowd the compute unit (1.59, 1.69 ms)
   if (cbw <= 32 && cbh <= 32 && pipe)
-    k_t1_encode_pipe<2><<<nblk, 192, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes, (const uint32_t*)signs, pb,
+    k_t1_encode_pipe<3><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes, (const uint32_t*)signs, pb,
                                              cw, R, D, bp, tail, (uint32_t*)sppf);
   else if (cbw <= 32)
     k_t1_encode_wave<uint32_t><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes, (const uint32_t*)signs,
