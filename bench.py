@@ -42,11 +42,11 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 # measured (checked by hash); otherwise traffic is reported as null.
 MEASURED_TRAFFIC = {
     "t1_encode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
-                  "sha256": "4d1937e6da2e20ebd3a70c1721ff41080530c8a3d029993ebab79d7c4cb0313b",
+                  "sha256": "ae2148ef88020237e02003971584fdb66d708c9add6b03aa4a1e1025b48d1a0e",
                   "ny": 721, "nx": 1440, "eps": 0.01,
-                  "bytes": (2.0 * (3883.4 + 3747.1) / 2 + 1.0 * (986.0 + 1229.9) / 2) * 1024},
+                  "bytes": (2.0 * (3869.4 + 3747.1) / 2 + 1.0 * (986.7 + 1230.2) / 2) * 1024},
     "t1_decode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
-                  "sha256": "4d1937e6da2e20ebd3a70c1721ff41080530c8a3d029993ebab79d7c4cb0313b",
+                  "sha256": "ae2148ef88020237e02003971584fdb66d708c9add6b03aa4a1e1025b48d1a0e",
                   "ny": 721, "nx": 1440, "eps": 0.01,
                   "bytes": (2.0 * (593.8 + 558.4) / 2 + 1.0 * (4099.5 + 4099.5) / 2) * 1024},
 }
