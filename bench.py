@@ -133,7 +133,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the path shards by field with no exchange between GPUs, "
-              "and multi-GPU runs are not part of this build (use --gpus 1).", file=sys.stderr)
+              "and it does not launch multi-GPU runs (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -44,7 +44,7 @@ typedef enum {
   EBCC_ECORRUPT = -3,  /* stream fails magic/version/length/checksum checks */
   EBCC_ENOMEM = -4,    /* device allocation failed */
   EBCC_EHIP = -5,      /* a HIP runtime call failed (see ebcc_last_error) */
-  EBCC_ENOTIMPL = -6   /* a parameter value this build does not implement */
+  EBCC_ENOTIMPL = -6   /* a parameter value the library does not implement */
 } ebcc_status;
 
 enum { EBCC_BOUND_REL = 0, EBCC_BOUND_ABS = 1 };
