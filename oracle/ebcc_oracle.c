@@ -1595,3 +1595,13 @@ EXPORT int ebcc_ref_levels(long ny, long nx, int L) { return levels_eff(ny, nx, 
 EXPORT void ebcc_ref_dwt_f32(float* a, long ny, long nx, int L, int inverse) { dwt2_f(a, ny, nx, L, inverse); }
 EXPORT void ebcc_ref_dwt_f64(double* a, long ny, long nx, int L, int inverse) { dwt2_d(a, ny, nx, L, inverse); }
 EXPORT uint32_t ebcc_ref_checksum(const uint8_t* p, long n) { return stream_checksum(p, n); }
+/* Entry i of the MQ probability-estimation table (for its pin against the
+ * standard's Table C.2); returns -1 for i outside 0..46. */
+EXPORT int ebcc_ref_mq_table(int i, int* qe, int* nmps, int* nlps, int* sw) {
+  if (i < 0 || i >= 47) return -1;
+  *qe = MQT[i].qe; *nmps = MQT[i].nmps; *nlps = MQT[i].nlps; *sw = MQT[i].sw;
+  return 0;
+}
+/* The base-layer quantiser of one coefficient at scale 2^sh (23-bit cap). */
+EXPORT uint32_t ebcc_ref_quant(float y, int sh) { return quant(y, sh, QMAX_BITS); }
+

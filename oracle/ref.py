@@ -72,6 +72,9 @@ def lib():
         L.ebcc_ref_spiht_decode.argtypes = [P, C.c_long, C.c_long, C.c_long, C.c_int, C.c_int, C.c_int, P, P]
         L.ebcc_ref_checksum.argtypes = [P, C.c_long]
         L.ebcc_ref_checksum.restype = C.c_uint32
+        L.ebcc_ref_mq_table.argtypes = [C.c_int] + [C.POINTER(C.c_int)] * 4
+        L.ebcc_ref_quant.argtypes = [C.c_float, C.c_int]
+        L.ebcc_ref_quant.restype = C.c_uint32
         _lib = L
     return _lib
 
@@ -291,3 +294,18 @@ def spiht_decode(sec, ny, nx, levels, tile, n_s):
 def checksum(b):
     buf = np.frombuffer(bytes(b) + b"\0", np.uint8).copy()
     return lib().ebcc_ref_checksum(_p(buf), len(b))
+
+
+def mq_table():
+    """The oracle's MQ probability table: list of (Qe, NMPS, NLPS, SWITCH)."""
+    rows = []
+    for i in range(47):
+        v = [C.c_int() for _ in range(4)]
+        assert lib().ebcc_ref_mq_table(i, *[C.byref(a) for a in v]) == 0
+        rows.append(tuple(a.value for a in v))
+    return rows
+
+
+def quant(y, sh):
+    """Base-layer quantised magnitude floor(|y| 2^sh) (capped at 2^23 - 1)."""
+    return lib().ebcc_ref_quant(float(y), int(sh))

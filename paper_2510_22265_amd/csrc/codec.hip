@@ -8,6 +8,7 @@
 #include "common.h"
 #include "ebcc.h"
 
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -17,6 +18,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -715,8 +717,16 @@ static int wait_stream(hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
     return EBCC_OK;
   }
+  // Poll for short waits (the common case: a few scalars after a short
+  // launch sequence), then give the core away: yield for a few
+  // milliseconds, sleep in 50 us steps beyond that.
   hipError_t e;
+  const auto t0 = std::chrono::steady_clock::now();
   while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    const auto dt = std::chrono::steady_clock::now() - t0;
+    if (dt < std::chrono::microseconds(200)) continue;
+    if (dt < std::chrono::milliseconds(5)) std::this_thread::yield();
+    else std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
   if (e != hipSuccess) return fail(EBCC_EHIP, std::string("waiting for the stream: ") + hipGetErrorString(e));
   return EBCC_OK;

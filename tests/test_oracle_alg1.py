@@ -110,3 +110,32 @@ def test_q_out_of_range_is_refused(ref):
     for q in (-0.1, 1.5, float("nan")):
         rc, _, _ = ref.compress_rc(x, 0.01, q=q)
         assert rc == ref.EINVAL
+
+
+@pytest.mark.parametrize("var,cfg", [("t", 1), ("u", 2), ("q", 3)])
+def test_base_quality_counts_errors_not_exceeding_eps(ref, var, cfg):
+    """q_A of enc_base is the proportion of samples whose base-layer error
+    does not exceed eps (Algorithm 1; inclusive, as the bound itself).  The
+    base reconstruction at r0 comes from a trace of the fixed-ratio run; the
+    bound is then set to one of the errors that reconstruction makes (in the
+    same power-of-two bracket, so the base quantiser is unchanged), where
+    the inclusive and the strict count differ.  The q_A the search logs for
+    r0 must equal the inclusive count made here from the definition."""
+    x = _field(var, (64, 96), cfg)
+    xmin = np.float32(x.min())
+    rng_d = float(x.max()) - float(x.min())
+    range_f = np.float32(rng_d)
+    _, tr = ref.compress(x, 0.01, trace=True)               # base at r0 = 30
+    xh = xmin + ((tr["abase"] + np.float32(0.5)) * range_f)  # decoder arithmetic, FP32
+    err = np.abs(x.astype(np.float64) - xh.astype(np.float64))
+    lo, hi = 2.0 ** -7 * rng_d, 2.0 ** -6 * rng_d           # floor(log2 0.01) = -7
+    cand = np.unique(err[(err >= lo) & (err < hi)])
+    assert cand.size, "no base error in the bracket of the 1% bound"
+    eps = float(cand[cand.size // 2])
+    _, log = ref.compress_logged(x, eps, 0.5, bound_mode=1)
+    r, qa, _, _ = log[0]
+    assert r == 30.0
+    incl = np.count_nonzero(err <= eps) / err.size
+    strict = np.count_nonzero(err < eps) / err.size
+    assert incl != strict
+    assert qa == incl

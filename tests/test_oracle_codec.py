@@ -171,3 +171,60 @@ def test_plane_search_bruteforce_8x8(ref, seed):
             lo = mid
     assert tr["n_s"] == tr["n_max"] - hi + 1
     assert feas[hi] and not feas[hi - 1]
+
+
+def test_base_quantiser_interval(ref):
+    """Dead-zone quantiser of the base layer: q = floor(|y| 2^sh), so that
+    q 2^-sh <= |y| < (q + 1) 2^-sh holds exactly (checked in rational
+    arithmetic), with the 23-bit cap; the scaling by 2^sh is exact."""
+    from fractions import Fraction
+    rng = np.random.default_rng(11)
+    ys = list((rng.standard_normal(400) * 10.0 ** rng.integers(-8, 4, 400)).astype(np.float32))
+    ys += [np.float32(v) for v in (0.0, -0.0, 1e-45, -3e-39, 0.5, -0.75, 1.0, 2.0 ** -20, 3 * 2.0 ** -7)]
+    for y in ys:
+        for sh in (-6, 0, 3, 7, 12, 20, 27):
+            q = ref.quant(y, sh)
+            v = abs(Fraction(float(y))) * Fraction(2) ** sh
+            if v >= 2 ** 23:
+                assert q == 2 ** 23 - 1, (y, sh)
+            else:
+                assert q <= v < q + 1, (y, sh, q)
+
+
+def _bands(ny, nx, L):
+    """(level, orientation, y0, x0, h, w) in stream order: LL_L, then HL_l,
+    LH_l, HH_l for l = L..1 (low half ceil(n/2) first)."""
+    h, w = [ny], [nx]
+    for _ in range(L):
+        h.append((h[-1] + 1) // 2)
+        w.append((w[-1] + 1) // 2)
+    out = [(L, 0, 0, 0, h[L], w[L])]
+    for l in range(L, 0, -1):
+        out += [(l, 1, 0, w[l], h[l], w[l - 1] - w[l]), (l, 2, h[l], 0, h[l - 1] - h[l], w[l]),
+                (l, 3, h[l], w[l], h[l - 1] - h[l], w[l - 1] - w[l])]
+    return out
+
+
+@pytest.mark.parametrize("shape,levels,cb,eps", [((61, 97), 4, (5, 5), 0.01), ((90, 45), 5, (4, 3), 0.001),
+                                                 ((33, 128), 3, (6, 2), 0.05)])
+def test_base_quantiser_planes_per_block(ref, shape, levels, cb, eps):
+    """Every band's coefficients quantised with step 2^(e0 - g_b) (the band's
+    synthesis gain g_b, the bound's e0), blocks tiled from each band's origin
+    in stream order: each block's magnitude bit-plane count P_b is the bit
+    length of its largest quantised magnitude, recomputed here in exact
+    arithmetic from the oracle's transform coefficients."""
+    x = synth.field("u", *shape, cfg=2, level=3)
+    _, tr = ref.compress(x, eps, levels=levels, cbl2w=cb[0], cbl2h=cb[1], trace=True)
+    coef = tr["coef"].astype(np.float64)
+    L, e0 = tr["L"], tr["e0"]
+    cw, ch = 1 << cb[0], 1 << cb[1]
+    pb = []
+    for (lev, ori, y0, x0, h, w) in _bands(*shape, L):
+        sh = ref.band_log2_gain(lev, ori) - e0
+        q = np.minimum(np.floor(np.ldexp(np.abs(coef[y0:y0 + h, x0:x0 + w]), sh)), 2 ** 23 - 1).astype(np.int64)
+        for by in range(0, h, ch):
+            for bx in range(0, w, cw):
+                m = int(q[by:by + ch, bx:bx + cw].max())
+                pb.append(m.bit_length())
+    assert tr["nblocks"] == len(pb)
+    assert list(tr["pb"]) == pb

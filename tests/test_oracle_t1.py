@@ -146,3 +146,60 @@ def test_t1_single_coefficient(ref):
     assert len(R) == 2 and D[1] == 9 - 0   # e^2: (2*1+1)^2 -> (3 - 3)^2
     m, ng, pk = ref.t1_decode(cw, 8, 8, 3, 1, 1)
     assert m[3, 5] == 1 and ng[3, 5] == 1 and m.sum() == 1
+
+
+MQ_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "t800_mq_table.txt")
+T88_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "t88_mq_test_sequence.txt")
+
+
+def _mq_golden():
+    rows = []
+    for line in open(MQ_GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            i, qe, nmps, nlps, sw = line.split()
+            rows.append((int(i), int(qe, 16), int(nmps), int(nlps), int(sw)))
+    return rows
+
+
+def test_mq_table_matches_t800(ref):
+    """The oracle's probability table equals T.800 Table C.2 entry by entry."""
+    gold = _mq_golden()
+    assert [r[0] for r in gold] == list(range(47))
+    assert ref.mq_table() == [r[1:] for r in gold]
+
+
+def test_mq_table_structure(ref):
+    """Properties of the state machine that any mistyped entry is likely to
+    break: the MPS switches only in the three 'fast attack' states 0, 6 and
+    14; state 46 is the non-adapting uniform state; every MPS chain ends in
+    the self-looping state 45; an MPS never raises Qe and an LPS never lowers
+    it outside the switching states."""
+    t = ref.mq_table()
+    assert [i for i, r in enumerate(t) if r[3]] == [0, 6, 14]
+    assert t[46] == (0x5601, 46, 46, 0)
+    for s in range(46):
+        seen, k = set(), s
+        while k != t[k][1]:
+            assert k not in seen
+            seen.add(k)
+            assert t[t[k][1]][0] <= t[k][0]
+            k = t[k][1]
+        assert k == 45
+        if not t[s][3]:
+            assert t[t[s][2]][0] >= t[s][0]
+    assert all(r[0] & 1 for r in t)          # every Qe in the table is odd
+
+
+def test_mq_matches_t88_test_sequence(ref):
+    """The standard's test sequence of the MQ coder (T.88 Annex H.2): one
+    context from state 0, MPS 0 (tier-1 context 1 starts there).  The
+    oracle's codeword equals the standard's encoded bytes up to its final
+    0xFF (T.800's FLUSH drops a trailing 0xFF; T.88 ends the sequence with
+    the 0xFF 0xAC marker), and decoding the standard's bytes gives the input."""
+    kv = dict(l.split() for l in open(T88_GOLDEN) if l.strip() and not l.startswith("#"))
+    bits = np.unpackbits(np.frombuffer(bytes.fromhex(kv["input"]), np.uint8))
+    enc = bytes.fromhex(kv["encoded"])
+    cx = np.ones(bits.size, np.uint8)
+    assert bits.size == 256 and enc[-2:] == b"\xff\xac"
+    assert ref.mq_encode(cx, bits) == enc[:-2]
+    assert (ref.mq_decode(enc, cx) == bits).all()
