@@ -117,23 +117,64 @@ int ebcc_decompress(const uint8_t* d_in, size_t in_len, float* d_x, size_t ny, s
  *                 back to back in field order.
  *   h_offsets, h_lengths  host [n]: byte offset in d_out and length of each
  *                 stream.
+ *   h_status      host [n] (may be NULL): each field's status.  A field
+ *                 whose arguments are invalid or whose input is not finite
+ *                 gets EBCC_EINVAL there and no stream (length 0); the other
+ *                 fields are still compressed and their streams are the same
+ *                 as without it.
+ * Returns the first error (EBCC_OK if every field was compressed).
  * out_cap >= sum of ebcc_compress_bound(ny[i], nx[i]) always suffices; a
  * smaller buffer may fail with EBCC_ENOSPC after earlier chunks were
- * written.  Errors of one field (non-finite input, bad size) fail the call.
- * Synchronises `stream`. */
+ * written.  Synchronises `stream`. */
 int ebcc_compress_batch(int n, const float* const* d_x, const size_t* ny, const size_t* nx,
                         const double* err_bounds, const ebcc_params* p, uint8_t* d_out,
-                        size_t out_cap, uint64_t* h_offsets, uint64_t* h_lengths, void* stream);
+                        size_t out_cap, uint64_t* h_offsets, uint64_t* h_lengths, int* h_status,
+                        void* stream);
 
 /* Decompress n streams: d_in[i] (device, in_len[i] bytes) into d_x[i]
  * [ny[i]][nx[i]] float32.  h_status (host [n], may be NULL) receives each
  * stream's status; a stream that is corrupt or does not match its size is
- * reported there and the others are still decoded.  Streams decoded in one
- * chunk must share the code-block size (EBCC_EINVAL for the odd ones
- * otherwise).  Returns the first error, or EBCC_OK.  Synchronises `stream`. */
+ * reported there and the others are still decoded.  Streams of different
+ * code-block sizes may be mixed: the library decodes each code-block size
+ * in its own launch sequence.  Returns the first error, or EBCC_OK.
+ * Synchronises `stream`. */
 int ebcc_decompress_batch(int n, const uint8_t* const* d_in, const size_t* in_len,
                           float* const* d_x, const size_t* ny, const size_t* nx, int* h_status,
                           void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Device memory.  The library keeps one workspace per (device, stream),
+ * grown on demand by a call and reused by the next calls on that stream, and
+ * small per-shape tables (plans).  These queries let a caller that budgets
+ * HBM (a serving loop) know and bound what the library takes.  No device
+ * memory is touched by the size queries.
+ * ------------------------------------------------------------------------- */
+
+/* Device bytes one ebcc_compress call of an ny x nx field with parameters p
+ * (NULL = defaults) allocates at most: its workspace (search candidates
+ * included) plus the shape's plan tables.  0 for invalid arguments.  A
+ * decompression of the stream takes no more. */
+size_t ebcc_workspace_size(size_t ny, size_t nx, const ebcc_params* p);
+
+/* Workspace bytes one batched call allocates at most (the largest over its
+ * internal chunks; plan tables not included):
+ *   h_hdrs == NULL: ebcc_compress_batch of n fields [ny[i]][nx[i]] with p;
+ *   h_hdrs != NULL: ebcc_decompress_batch of n streams whose first 48 bytes
+ *                   are h_hdrs[48*i .. 48*i+47] (host) and whose lengths are
+ *                   in_len[i], into fields [ny[i]][nx[i]] (p is not used).
+ * 0 for invalid arguments. */
+size_t ebcc_workspace_size_batch(int n, const size_t* ny, const size_t* nx, const ebcc_params* p,
+                                 const uint8_t* h_hdrs, const size_t* in_len);
+
+/* Make the workspace of `stream` on the current device exactly `bytes` now
+ * (0 frees it): calls whose workspace fits then allocate nothing, a call
+ * that needs more grows it again.  EBCC_ENOMEM if the allocation fails.
+ * Synchronises `stream` if an existing workspace is replaced. */
+int ebcc_workspace_reserve(size_t bytes, void* stream);
+
+/* Device bytes the library holds on the current device: every stream's
+ * workspace and the plan tables. */
+size_t ebcc_device_bytes(void);
 
 /* Header fields of a stream, read from host memory (the first 48 bytes). */
 int ebcc_stream_info(const uint8_t* h_hdr, size_t len, size_t* ny, size_t* nx, int* mode);

@@ -8,6 +8,7 @@
 #include "common.h"
 #include "ebcc.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -638,6 +639,17 @@ static int build_plan(Plan& p) {
     for (int t = 0; t < p.ntiles; t++)
       if (tcls[t] == k) { p.tix.push_back(t); p.ncls[k]++; }
   if (off != (int64_t)ny * nx) return fail(EBCC_EINVAL, "internal: SPIHT trees do not cover the field");
+  return EBCC_OK;
+}
+
+// Device bytes of a plan's tables.
+static size_t plan_table_bytes(const Plan& p) {
+  auto r = [](size_t n) { return (n + 255) & ~(size_t)255; };
+  return r(sizeof(Band) * p.bands.size()) + r(sizeof(Blk) * std::max<size_t>(1, p.blks.size())) +
+         r(sizeof(TileD) * p.tiles.size()) + r(sizeof(int) * p.tix.size()) + r(sizeof(int64_t) * p.slot_off.size());
+}
+
+static int upload_plan(Plan& p) {
   HIPCHK(hipMalloc(&p.d_bands, sizeof(Band) * p.bands.size()));
   HIPCHK(hipMemcpy(p.d_bands, p.bands.data(), sizeof(Band) * p.bands.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&p.d_blks, sizeof(Blk) * std::max<size_t>(1, p.blks.size())));
@@ -672,6 +684,23 @@ static std::mutex g_mu;
 typedef std::tuple<int, int, int, int, int, int, int> PlanKey;   // device, ny, nx, L, cbl2w, cbl2h, T
 static std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
+// Host-only plans (geometry without device tables) for the size queries.
+static std::map<PlanKey, std::unique_ptr<Plan>> g_hplans;
+static int host_plan(int ny, int nx, int L, int cbl2w, int cbl2h, int T, Plan** out) {
+  PlanKey key(-1, ny, nx, L, cbl2w, cbl2h, T);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_hplans.find(key);
+  if (it != g_hplans.end()) { *out = it->second.get(); return EBCC_OK; }
+  std::unique_ptr<Plan> p(new Plan());
+  p->ny = ny; p->nx = nx; p->L = L; p->cbl2w = cbl2w; p->cbl2h = cbl2h;
+  p->cbw = 1 << cbl2w; p->cbh = 1 << cbl2h; p->T = T;
+  if (int rc = build_plan(*p)) return rc;
+  *out = p.get();
+  if (g_hplans.size() > 4096) g_hplans.clear();
+  g_hplans[key] = std::move(p);
+  return EBCC_OK;
+}
+
 static int get_plan(int ny, int nx, int L, int cbl2w, int cbl2h, int T, Plan** out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -683,6 +712,7 @@ static int get_plan(int ny, int nx, int L, int cbl2w, int cbl2h, int T, Plan** o
   p->ny = ny; p->nx = nx; p->L = L; p->cbl2w = cbl2w; p->cbl2h = cbl2h;
   p->cbw = 1 << cbl2w; p->cbh = 1 << cbl2h; p->T = T;
   int rc = build_plan(*p);
+  if (!rc) rc = upload_plan(*p);
   if (rc) return rc;
   *out = p.get();
   g_plans[key] = std::move(p);
@@ -790,6 +820,9 @@ static int get_ws(hipStream_t st, WS** out) {
   return EBCC_OK;
 }
 
+// Device bytes grow_ws allocates for a workspace need (it keeps 1/8 slack).
+static size_t ws_alloc(size_t need) { return need + need / 8; }
+
 static int grow_ws(WS* w, size_t need, size_t pin_need, hipStream_t st, char** base) {
   if (w->pin_cap < pin_need) {
     if (w->pin) HIPCHK(hipHostFree(w->pin));
@@ -809,7 +842,7 @@ static int grow_ws(WS* w, size_t need, size_t pin_need, hipStream_t st, char** b
       w->base = nullptr;
       w->cap = 0;
     }
-    size_t alloc = need + need / 8;
+    size_t alloc = ws_alloc(need);
     hipError_t e = hipMalloc(&w->base, alloc);
     if (e != hipSuccess) { w->base = nullptr; return fail(EBCC_ENOMEM, "workspace allocation failed"); }
     w->cap = alloc;
@@ -1117,11 +1150,31 @@ struct FieldIn {
   double err;
 };
 
+// Geometry of a compress call whose fields' sizes and plans are set: every
+// field is laid out as coded (the mode is known only on the device).
+// Returns the workspace bytes the call needs.
+static size_t compress_need(Call& c, const std::vector<int>& coded) {
+  build_items(c, coded);
+  // small calls evaluate four bisection levels per search round (one round
+  // for up to 16 planes: one read-back), mid-sized ones two, large batches
+  // one (the device is busy anyway)
+  size_t tot = 0;
+  for (auto& f : c.Fh) tot += (size_t)f.ny * f.nx;
+  c.spec_depth = tot <= ((size_t)1 << 22) ? 4 : (tot <= ((size_t)1 << 24) ? 2 : 1);
+  c.forced_global = spiht_forced_global();
+  c.need_lists = c.forced_global;
+  for (int i = 0; i < c.nf; i++) c.need_lists |= c.plans[i]->ncls[2] > 0;
+  return layout_call(c, nullptr, coded);
+}
+
 // Compress nf fields; stream i goes to out + off[i] (compacted in field
 // order); lens[i] receives its length.  On ENOSPC *need holds the total.
+// With fstat, a field whose input is not finite gets EBCC_EINVAL there and
+// no stream (length 0), the others are still compressed and the call
+// returns EBCC_EINVAL; without it such a field fails the call.
 static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, uint8_t* out, size_t cap,
                          std::vector<uint64_t>& offs, std::vector<uint64_t>& lens, size_t* need, hipStream_t st,
-                         const Trace* tr) {
+                         const Trace* tr, std::vector<int>* fstat = nullptr) {
   ebcc_params dflt;
   if (!pp) { ebcc_params_default(&dflt); pp = &dflt; }
   const int nf = (int)in.size();
@@ -1155,21 +1208,8 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     f.bands = c.plans[i]->d_bands;
     f.nb = c.plans[i]->nb;
   }
-  // every field is laid out as coded (the mode is known only on the device)
   std::vector<int> coded(nf, 1);
-  build_items(c, coded);
-  // small calls evaluate four bisection levels per search round (one round
-  // for up to 16 planes: one read-back), mid-sized ones two, large batches
-  // one (the device is busy anyway)
-  {
-    size_t tot = 0;
-    for (auto& f : c.Fh) tot += (size_t)f.ny * f.nx;
-    c.spec_depth = tot <= ((size_t)1 << 22) ? 4 : (tot <= ((size_t)1 << 24) ? 2 : 1);
-  }
-  c.forced_global = spiht_forced_global();
-  c.need_lists = c.forced_global;
-  for (int i = 0; i < nf; i++) c.need_lists |= c.plans[i]->ncls[2] > 0;
-  size_t need_ws = layout_call(c, nullptr, coded);
+  size_t need_ws = compress_need(c, coded);
   char* base;
   if ((rc = get_ws(st, &c.ws))) return rc;
   if ((rc = grow_ws(c.ws, need_ws, pin_need(c), st, &base))) return rc;
@@ -1187,16 +1227,28 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   prof.mark(S_SCALARS);
   std::vector<FieldParams> fps(nf);
   if ((rc = c.fetch(fps.data(), c.d_fp, nf))) return rc;
-  std::vector<int> mode(nf);
+  std::vector<int> mode(nf), failed(nf, 0);
+  int first_bad = EBCC_OK;
+  std::string bad_msg;
+  if (fstat) fstat->assign(nf, EBCC_OK);
   for (int i = 0; i < nf; i++) {
-    if (fps[i].mode < 0) return fail(EBCC_EINVAL, "input field " + std::to_string(i) + " contains non-finite values");
+    if (fps[i].mode < 0) {
+      std::string msg = "input field " + std::to_string(i) + " contains non-finite values";
+      if (!fstat) return fail(EBCC_EINVAL, msg);
+      (*fstat)[i] = EBCC_EINVAL;
+      failed[i] = 1;
+      if (first_bad == EBCC_OK) { first_bad = EBCC_EINVAL; bad_msg = msg; }
+      mode[i] = MODE_CONST;   // no stream is written for it (below)
+      c.Fh[i].e0 = 0;
+      continue;
+    }
     mode[i] = fps[i].mode;
     c.Fh[i].e0 = fps[i].e0;
   }
   // coded fields take part in the pipeline
   std::vector<int> act(nf), resid(nf, 0), nmax(nf, -1), checks(nf, 0);
   for (int i = 0; i < nf; i++) {
-    act[i] = mode[i] == MODE_CODED;
+    act[i] = mode[i] == MODE_CODED && !failed[i];
     checks[i] = act[i];
     c.Fh[i].budget = base_budget((int64_t)in[i].ny * (int64_t)in[i].nx, c.plans[i]->nblk, pp->base_ratio);
     c.Fh[i].er = fps[i].elog - 6;
@@ -1518,7 +1570,8 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     FieldDev& f = c.Fh[i];
     size_t N = (size_t)f.ny * f.nx;
     f.mode = mode[i];
-    if (mode[i] == MODE_CONST) { f.len = kHdr; f.bb = 0; f.rb = 0; }
+    if (failed[i]) { f.len = 0; f.bb = 0; f.rb = 0; }
+    else if (mode[i] == MODE_CONST) { f.len = kHdr; f.bb = 0; f.rb = 0; }
     else if (mode[i] == MODE_RAW) { f.len = kHdr + 4 * (int64_t)N; f.bb = (uint32_t)(4 * N); f.rb = 0; }
     else f.len = kHdr + (int64_t)f.bb + f.rb;
     offs[i] = total;
@@ -1545,6 +1598,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     k_copy_raw<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, 1);
   }
   std::vector<int> all(nf, 1);
+  for (int i = 0; i < nf; i++) all[i] = !failed[i];
   if ((rc = c.set_active(all))) return rc;
   k_checksum<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
   k_header<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
@@ -1569,6 +1623,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     if (tr->info) memcpy(tr->info, info, sizeof(info));
     if (int rc2 = wait_stream(st)) return rc2;
   }
+  if (first_bad != EBCC_OK) return fail(first_bad, bad_msg);
   return EBCC_OK;
 }
 
@@ -1584,17 +1639,72 @@ struct StreamIn {
 // Decompress nf streams; status per stream in st_out (the first error is
 // returned).  A stream whose header cannot be used is reported and skipped;
 // the others are still decoded.
-static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st_out, hipStream_t st) {
+// Geometry of a decompress call whose coded streams' sizes and plans are
+// set; returns the workspace bytes the call needs.
+static size_t decompress_need(Call& c, const std::vector<int>& coded) {
+  build_items(c, coded);
+  c.forced_global = spiht_forced_global();
+  c.need_lists = false;
+  for (int i = 0; i < c.nf; i++)
+    if (coded[i]) c.need_lists |= c.forced_global || c.plans[i]->ncls[2] > 0;
+  return layout_call(c, nullptr, coded);
+}
+
+// Copies the first 48 bytes of each stream (device) to hdr (host); streams
+// shorter than a header leave zeros.
+static int read_headers(const std::vector<const uint8_t*>& d_in, const std::vector<size_t>& len,
+                        std::vector<uint8_t>& hdr, hipStream_t st) {
+  hdr.assign(kHdr * d_in.size(), 0);
+  for (size_t i = 0; i < d_in.size(); i++) {
+    if (!d_in[i]) return fail(EBCC_EINVAL, "NULL buffer");
+    if (len[i] >= (size_t)kHdr)
+      HIPCHK(hipMemcpyAsync(hdr.data() + kHdr * i, d_in[i], kHdr, hipMemcpyDeviceToHost, st));
+  }
+  return wait_stream(st);
+}
+
+// The decode calls of a batch: one launch sequence decodes streams of one
+// code-block size, so the coded streams are grouped by it (in order of first
+// appearance; the others join the first group), and each group is cut into
+// chunks of at most kChunkSamples samples or kChunkFields streams.
+static std::vector<std::vector<int>> decode_calls(int n, const uint8_t* hdrs, const size_t* len, const size_t* ny,
+                                                  const size_t* nx) {
+  std::vector<int> key(n, -1);
+  std::vector<int> order;
+  for (int i = 0; i < n; i++) {
+    const uint8_t* h = hdrs + kHdr * (size_t)i;
+    if (len[i] >= (size_t)kHdr && memcmp(h, "EBCC", 4) == 0 && h[5] == MODE_CODED) key[i] = h[7];
+    if (key[i] >= 0 && std::find(order.begin(), order.end(), key[i]) == order.end()) order.push_back(key[i]);
+  }
+  if (order.empty()) order.push_back(-1);
+  std::vector<std::vector<int>> calls;
+  for (size_t g = 0; g < order.size(); g++) {
+    std::vector<int> idx;
+    for (int i = 0; i < n; i++)
+      if (key[i] == order[g] || (g == 0 && key[i] < 0)) idx.push_back(i);
+    size_t k = 0;
+    while (k < idx.size()) {
+      std::vector<int> call;
+      size_t samples = 0;
+      while (k < idx.size() && (call.empty() || samples + ny[idx[k]] * nx[idx[k]] <= kChunkSamples) &&
+             (int)call.size() < kChunkFields) {
+        samples += ny[idx[k]] * nx[idx[k]];
+        call.push_back(idx[k++]);
+      }
+      calls.push_back(call);
+    }
+  }
+  return calls;
+}
+
+static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs, std::vector<int>& st_out,
+                           hipStream_t st) {
   const int nf = (int)in.size();
   st_out.assign(nf, EBCC_OK);
   if (nf == 0) return EBCC_OK;
-  std::vector<uint8_t> hdr(kHdr * (size_t)nf);
-  for (int i = 0; i < nf; i++) {
+  for (int i = 0; i < nf; i++)
     if (!in[i].in || !in[i].x) return fail(EBCC_EINVAL, "NULL buffer");
-    if (in[i].len >= (size_t)kHdr)
-      HIPCHK(hipMemcpyAsync(hdr.data() + kHdr * (size_t)i, in[i].in, kHdr, hipMemcpyDeviceToHost, st));
-  }
-  if (int rc0 = wait_stream(st)) return rc0;
+  std::vector<uint8_t> hdr(hdrs, hdrs + kHdr * (size_t)nf);
   Call c;
   c.nf = nf;
   c.st = st;
@@ -1638,7 +1748,7 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
         continue;
       }
       if (cbl2w >= 0 && (w2 != cbl2w || h2 != cbl2h)) {
-        bad(i, EBCC_EINVAL, "streams decoded together must share the code-block size");
+        bad(i, EBCC_EINVAL, "internal: streams decoded together must share the code-block size");
         continue;
       }
       f.L = L; f.T = T;
@@ -1656,12 +1766,9 @@ static int decompress_call(const std::vector<StreamIn>& in, std::vector<int>& st
     good[i] = 1;
   }
   if (cbl2w >= 0) { c.cbw = 1 << cbl2w; c.cbh = 1 << cbl2h; }
-  build_items(c, coded);
   bool anycoded = false;
-  c.forced_global = spiht_forced_global();
-  for (int i = 0; i < nf; i++)
-    if (coded[i]) { anycoded = true; c.need_lists |= c.forced_global || c.plans[i]->ncls[2] > 0; }
-  size_t need_ws = layout_call(c, nullptr, coded);
+  for (int i = 0; i < nf; i++) anycoded |= coded[i] != 0;
+  size_t need_ws = decompress_need(c, coded);
   char* base;
   if ((rc = get_ws(st, &c.ws))) return rc;
   if ((rc = grow_ws(c.ws, need_ws, pin_need(c), st, &base))) return rc;
@@ -1826,43 +1933,81 @@ int ebcc_compress_trace(const float* d_x, size_t ny, size_t nx, const ebcc_param
 
 int ebcc_compress_batch(int n, const float* const* d_x, const size_t* ny, const size_t* nx, const double* err_bounds,
                         const ebcc_params* p, uint8_t* d_out, size_t out_cap, uint64_t* h_offsets,
-                        uint64_t* h_lengths, void* stream) {
+                        uint64_t* h_lengths, int* h_status, void* stream) {
   g_err.clear();
   if (n < 0 || (n > 0 && (!d_x || !ny || !nx || !h_offsets || !h_lengths)))
     return fail(EBCC_EINVAL, "bad batch arguments");
-  for (int i = 0; i < n; i++) { h_offsets[i] = 0; h_lengths[i] = 0; }
+  ebcc_params dflt;
+  if (!p) { ebcc_params_default(&dflt); p = &dflt; }
+  std::vector<int> stv(n, EBCC_OK);
+  int first = EBCC_OK;
+  std::string first_msg;
+  auto note = [&](int rc) {
+    if (rc != EBCC_OK && first == EBCC_OK) { first = rc; first_msg = g_err; }
+  };
+  // fields with bad arguments get their own status and no stream
+  std::vector<int> ok;
+  for (int i = 0; i < n; i++) {
+    h_offsets[i] = 0; h_lengths[i] = 0;
+    const double e = err_bounds ? err_bounds[i] : p->err_bound;
+    int rc = check_params(ny[i], nx[i], p, e);
+    if (rc == EBCC_OK && !d_x[i]) rc = fail(EBCC_EINVAL, "NULL input buffer");
+    if (rc != EBCC_OK) { stv[i] = rc; note(rc); } else ok.push_back(i);
+  }
   size_t done = 0;
-  int i = 0;
-  while (i < n) {
+  size_t k = 0;
+  while (k < ok.size()) {
     // one chunk: consecutive fields up to kChunkSamples samples (at least one)
     std::vector<FieldIn> in;
+    std::vector<int> idx;
     size_t samples = 0;
-    int j = i;
-    while (j < n && (in.empty() || samples + ny[j] * nx[j] <= kChunkSamples) && (int)in.size() < kChunkFields) {
-      in.push_back(FieldIn{d_x[j], ny[j], nx[j], err_bounds ? err_bounds[j] : (p ? p->err_bound : 0.01)});
+    while (k < ok.size() && (in.empty() || samples + ny[ok[k]] * nx[ok[k]] <= kChunkSamples) &&
+           (int)in.size() < kChunkFields) {
+      const int j = ok[k++];
+      in.push_back(FieldIn{d_x[j], ny[j], nx[j], err_bounds ? err_bounds[j] : p->err_bound});
+      idx.push_back(j);
       samples += ny[j] * nx[j];
-      j++;
     }
     std::vector<uint64_t> offs, lens;
+    std::vector<int> fst;
     size_t need = 0;
-    if (done > out_cap) return fail(EBCC_ENOSPC, "output capacity too small");
-    int rc = compress_call(in, p, d_out + done, out_cap - done, offs, lens, &need, (hipStream_t)stream, nullptr);
-    if (rc) return rc;
-    for (int k = i; k < j; k++) {
-      h_offsets[k] = done + offs[k - i];
-      h_lengths[k] = lens[k - i];
+    if (done > out_cap) {
+      fail(EBCC_ENOSPC, "output capacity too small");
+      for (int j : idx) stv[j] = EBCC_ENOSPC;
+      note(EBCC_ENOSPC);
+      continue;
+    }
+    int rc = compress_call(in, p, d_out + done, out_cap - done, offs, lens, &need, (hipStream_t)stream, nullptr, &fst);
+    bool per_field = rc == EBCC_EINVAL && fst.size() == in.size();
+    if (rc != EBCC_OK && !per_field) {
+      for (int j : idx) stv[j] = rc;   // a failure of the whole chunk
+      note(rc);
+      if (rc != EBCC_ENOSPC) continue;
+      done += need;                    // the space the chunk would have taken
+      continue;
+    }
+    note(rc);
+    for (size_t m = 0; m < idx.size(); m++) {
+      stv[idx[m]] = per_field ? fst[m] : EBCC_OK;
+      h_offsets[idx[m]] = done + offs[m];
+      h_lengths[idx[m]] = lens[m];
     }
     done += need;
-    i = j;
   }
-  return EBCC_OK;
+  if (h_status)
+    for (int i = 0; i < n; i++) h_status[i] = stv[i];
+  if (first) g_err = first_msg;
+  return first;
 }
 
 int ebcc_decompress(const uint8_t* d_in, size_t in_len, float* d_x, size_t ny, size_t nx, void* stream) {
   g_err.clear();
+  if (!d_in || !d_x) return fail(EBCC_EINVAL, "NULL buffer");
   std::vector<StreamIn> in(1, StreamIn{d_in, in_len, d_x, ny, nx});
+  std::vector<uint8_t> hdr;
+  if (int rc = read_headers({d_in}, {in_len}, hdr, (hipStream_t)stream)) return rc;
   std::vector<int> st;
-  return decompress_call(in, st, (hipStream_t)stream);
+  return decompress_call(in, hdr.data(), st, (hipStream_t)stream);
 }
 
 int ebcc_decompress_batch(int n, const uint8_t* const* d_in, const size_t* in_len, float* const* d_x,
@@ -1870,27 +2015,30 @@ int ebcc_decompress_batch(int n, const uint8_t* const* d_in, const size_t* in_le
   g_err.clear();
   if (n < 0 || (n > 0 && (!d_in || !in_len || !d_x || !ny || !nx)))
     return fail(EBCC_EINVAL, "bad batch arguments");
+  if (n == 0) return EBCC_OK;
+  for (int i = 0; i < n; i++)
+    if (!d_in[i] || !d_x[i]) return fail(EBCC_EINVAL, "NULL buffer in the batch");
+  std::vector<uint8_t> hdr;
+  if (int rc = read_headers(std::vector<const uint8_t*>(d_in, d_in + n), std::vector<size_t>(in_len, in_len + n), hdr,
+                            (hipStream_t)stream))
+    return rc;
   int first = EBCC_OK;
   std::string first_msg;
-  int i = 0;
-  while (i < n) {
+  for (const std::vector<int>& call : decode_calls(n, hdr.data(), in_len, ny, nx)) {
     std::vector<StreamIn> in;
-    size_t samples = 0;
-    int j = i;
-    while (j < n && (in.empty() || samples + ny[j] * nx[j] <= kChunkSamples) && (int)in.size() < kChunkFields) {
-      in.push_back(StreamIn{d_in[j], in_len[j], d_x[j], ny[j], nx[j]});
-      samples += ny[j] * nx[j];
-      j++;
+    std::vector<uint8_t> h;
+    for (int k : call) {
+      in.push_back(StreamIn{d_in[k], in_len[k], d_x[k], ny[k], nx[k]});
+      h.insert(h.end(), hdr.begin() + kHdr * (size_t)k, hdr.begin() + kHdr * (size_t)(k + 1));
     }
     std::vector<int> st;
-    int rc = decompress_call(in, st, (hipStream_t)stream);
+    int rc = decompress_call(in, h.data(), st, (hipStream_t)stream);
     bool per_stream = false;
     for (int v : st) per_stream |= v != EBCC_OK;
-    if (rc && !per_stream) st.assign(j - i, rc);   // a failure of the whole chunk
-    for (int k = i; k < j; k++)
-      if (h_status) h_status[k] = st.empty() ? rc : st[k - i];
+    if (rc && !per_stream) st.assign(call.size(), rc);   // a failure of the whole call
+    for (size_t k = 0; k < call.size(); k++)
+      if (h_status) h_status[call[k]] = st.empty() ? rc : st[k];
     if (rc && first == EBCC_OK) { first = rc; first_msg = g_err; }
-    i = j;
   }
   if (first) g_err = first_msg;
   return first;
@@ -1969,5 +2117,138 @@ int ebcc_tuning_set(const ebcc_tuning* t) {
 }
 
 const char* ebcc_profile_stage_name(int i) { return (i >= 0 && i < S_COUNT) ? kStageNames[i] : ""; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Workspace sizes: the same geometry and layout code as the calls, on
+// host-only plans (no device memory is touched).
+// ---------------------------------------------------------------------------
+static size_t compress_ws(const std::vector<size_t>& ny, const std::vector<size_t>& nx, const ebcc_params* p) {
+  Call c;
+  c.nf = (int)ny.size();
+  c.Fh.assign(c.nf, FieldDev());
+  c.plans.assign(c.nf, nullptr);
+  c.cbw = 1 << p->cblk_log2w;
+  c.cbh = 1 << p->cblk_log2h;
+  for (int i = 0; i < c.nf; i++) {
+    FieldDev& f = c.Fh[i];
+    memset(&f, 0, sizeof(f));
+    f.ny = (int)ny[i]; f.nx = (int)nx[i];
+    f.L = levels_eff(f.ny, f.nx, (int)p->levels);
+    if (host_plan(f.ny, f.nx, f.L, p->cblk_log2w, p->cblk_log2h, (int)p->spiht_tile, &c.plans[i])) return 0;
+  }
+  std::vector<int> coded(c.nf, 1);
+  return ws_alloc(compress_need(c, coded));
+}
+
+static size_t decompress_ws(const std::vector<int>& call, const uint8_t* hdrs, const size_t* len, const size_t* ny,
+                            const size_t* nx) {
+  Call c;
+  c.nf = (int)call.size();
+  c.Fh.assign(c.nf, FieldDev());
+  c.plans.assign(c.nf, nullptr);
+  std::vector<int> coded(c.nf, 0);
+  for (int m = 0; m < c.nf; m++) {
+    const int i = call[m];
+    const uint8_t* h = hdrs + kHdr * (size_t)i;
+    FieldDev& f = c.Fh[m];
+    memset(&f, 0, sizeof(f));
+    f.ny = (int)ny[i]; f.nx = (int)nx[i];
+    size_t hny, hnx;
+    int mode;
+    if (len[i] < (size_t)kHdr || ebcc_stream_info(h, kHdr, &hny, &hnx, &mode) != EBCC_OK || mode != MODE_CODED ||
+        hny != ny[i] || hnx != nx[i] || hny * hnx > 0x7FFFFFFFull)
+      continue;
+    const int L = h[6], w2 = h[7] & 15, h2 = h[7] >> 4, T = h[32] | (h[33] << 8);
+    if (L != levels_eff(f.ny, f.nx, L) || w2 < 2 || w2 > 6 || h2 < 2 || h2 > 6 || T < 1 || T > 64) continue;
+    if (host_plan(f.ny, f.nx, L, w2, h2, T, &c.plans[m])) return 0;
+    c.cbw = 1 << w2; c.cbh = 1 << h2;
+    coded[m] = 1;
+  }
+  return ws_alloc(decompress_need(c, coded));
+}
+
+extern "C" {
+
+size_t ebcc_workspace_size(size_t ny, size_t nx, const ebcc_params* p) {
+  g_err.clear();
+  ebcc_params dflt;
+  if (!p) { ebcc_params_default(&dflt); p = &dflt; }
+  if (check_params(ny, nx, p, p->err_bound)) return 0;
+  const int L = levels_eff((int)ny, (int)nx, (int)p->levels);
+  Plan* pl = nullptr;
+  if (host_plan((int)ny, (int)nx, L, p->cblk_log2w, p->cblk_log2h, (int)p->spiht_tile, &pl)) return 0;
+  const size_t ws = compress_ws({ny}, {nx}, p);
+  return ws ? ws + plan_table_bytes(*pl) : 0;
+}
+
+size_t ebcc_workspace_size_batch(int n, const size_t* ny, const size_t* nx, const ebcc_params* p,
+                                 const uint8_t* h_hdrs, const size_t* in_len) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!ny || !nx)) || (h_hdrs && !in_len)) { fail(EBCC_EINVAL, "bad batch arguments"); return 0; }
+  ebcc_params dflt;
+  if (!p) { ebcc_params_default(&dflt); p = &dflt; }
+  size_t best = 0;
+  if (!h_hdrs) {
+    std::vector<size_t> cy, cx;
+    size_t samples = 0;
+    auto flush = [&]() {
+      if (cy.empty()) return true;
+      size_t w = compress_ws(cy, cx, p);
+      if (!w) return false;
+      best = std::max(best, w);
+      cy.clear(); cx.clear(); samples = 0;
+      return true;
+    };
+    for (int i = 0; i < n; i++) {
+      if (check_params(ny[i], nx[i], p, p->err_bound)) continue;   // such fields take no workspace
+      if (!cy.empty() && (samples + ny[i] * nx[i] > kChunkSamples || (int)cy.size() >= kChunkFields))
+        if (!flush()) return 0;
+      cy.push_back(ny[i]); cx.push_back(nx[i]);
+      samples += ny[i] * nx[i];
+    }
+    if (!flush()) return 0;
+    return best;
+  }
+  for (const std::vector<int>& call : decode_calls(n, h_hdrs, in_len, ny, nx)) {
+    size_t w = decompress_ws(call, h_hdrs, in_len, ny, nx);
+    if (!w) return 0;
+    best = std::max(best, w);
+  }
+  return best;
+}
+
+int ebcc_workspace_reserve(size_t bytes, void* stream) {
+  g_err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  WS* w = nullptr;
+  if (int rc = get_ws(st, &w)) return rc;
+  if (w->cap == bytes) return EBCC_OK;
+  if (w->base) {
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(w->base));
+    w->base = nullptr;
+    w->cap = 0;
+  }
+  if (bytes && hipMalloc(&w->base, bytes) != hipSuccess) {
+    w->base = nullptr;
+    return fail(EBCC_ENOMEM, "workspace allocation failed");
+  }
+  w->cap = bytes;
+  return EBCC_OK;
+}
+
+size_t ebcc_device_bytes(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  size_t t = 0;
+  for (auto& kv : g_ws)
+    if (kv.first.first == dev && kv.second) t += kv.second->cap;
+  for (auto& kv : g_plans)
+    if (std::get<0>(kv.first) == dev && kv.second) t += plan_table_bytes(*kv.second);
+  return t;
+}
 
 }  // extern "C"

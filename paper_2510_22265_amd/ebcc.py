@@ -21,7 +21,8 @@ HDR_BYTES = 48
 SYMBOLS = ("ebcc_params_default", "ebcc_compress_bound", "ebcc_compress", "ebcc_decompress", "ebcc_stream_info",
            "ebcc_release", "ebcc_status_str", "ebcc_last_error", "ebcc_compress_trace", "ebcc_profile_enable",
            "ebcc_profile_read", "ebcc_profile_stage_name", "ebcc_compress_batch", "ebcc_decompress_batch",
-           "ebcc_tuning_get", "ebcc_tuning_set")
+           "ebcc_tuning_get", "ebcc_tuning_set", "ebcc_workspace_size", "ebcc_workspace_size_batch",
+           "ebcc_workspace_reserve", "ebcc_device_bytes")
 
 
 class Params(C.Structure):
@@ -60,7 +61,14 @@ def lib():
         L.ebcc_compress.argtypes = [P, S, S, C.POINTER(Params), P, S, C.POINTER(S), P]
         L.ebcc_compress_trace.argtypes = [P, S, S, C.POINTER(Params), P, S, C.POINTER(S), P, P, P, P, P, P, P]
         L.ebcc_decompress.argtypes = [P, S, P, S, S, P]
-        L.ebcc_compress_batch.argtypes = [C.c_int, P, P, P, P, C.POINTER(Params), P, S, P, P, P]
+        L.ebcc_compress_batch.argtypes = [C.c_int, P, P, P, P, C.POINTER(Params), P, S, P, P, P, P]
+        L.ebcc_workspace_size.argtypes = [S, S, C.POINTER(Params)]
+        L.ebcc_workspace_size.restype = S
+        L.ebcc_workspace_size_batch.argtypes = [C.c_int, P, P, C.POINTER(Params), P, P]
+        L.ebcc_workspace_size_batch.restype = S
+        L.ebcc_workspace_reserve.argtypes = [S, P]
+        L.ebcc_device_bytes.argtypes = []
+        L.ebcc_device_bytes.restype = S
         L.ebcc_decompress_batch.argtypes = [C.c_int, P, P, P, P, P, P, P]
         L.ebcc_stream_info.argtypes = [P, S, C.POINTER(S), C.POINTER(S), C.POINTER(C.c_int)]
         L.ebcc_tuning_get.argtypes = [C.POINTER(Tuning)]
@@ -198,23 +206,31 @@ class BatchArgs:
 
 
 def compress_batch_into(args, out, p, stream=None):
-    """Compress args.xs into `out` (uint8 device tensor); returns rc.  Offsets
-    and lengths are left in args.offsets / args.lengths."""
+    """Compress args.xs into `out` (uint8 device tensor); returns rc.  Offsets,
+    lengths and per-field statuses are left in args.offsets / args.lengths /
+    args.status."""
     return lib().ebcc_compress_batch(args.n, args.d_x, args.ny, args.nx, args.err, C.byref(p),
                                      C.c_void_p(out.data_ptr()), out.numel(), args.offsets, args.lengths,
-                                     _stream_ptr(stream))
+                                     args.status, _stream_ptr(stream))
 
 
-def compress_batch(xs, err_bounds=None, err_bound=0.01, base_ratio=30.0, stream=None, **kw):
+def compress_batch(xs, err_bounds=None, err_bound=0.01, base_ratio=30.0, stream=None, check=True, **kw):
     """Compress a list of 2-D float32 CUDA tensors in one batched call;
-    returns a list of uint8 CUDA tensors (views of one buffer)."""
+    returns a list of uint8 CUDA tensors (views of one buffer).  With
+    check=False returns (streams, statuses) instead of raising on the first
+    bad field (a failed field's stream is None)."""
     xs = [_dev_f32(x) for x in xs]
     args = BatchArgs(xs, err_bounds=err_bounds)
     p = params(err_bound, base_ratio, **kw)
     dev = xs[0].device if xs else torch.device("cuda")
     out = torch.empty(max(1, args.bound()), dtype=torch.uint8, device=dev)
-    _check(compress_batch_into(args, out, p, stream))
-    return [out[args.offsets[i]: args.offsets[i] + args.lengths[i]] for i in range(args.n)]
+    rc = compress_batch_into(args, out, p, stream)
+    if check:
+        _check(rc)
+    st = [args.status[i] for i in range(args.n)]
+    streams = [out[args.offsets[i]: args.offsets[i] + args.lengths[i]] if st[i] == OK else None
+               for i in range(args.n)]
+    return streams if check else (streams, st)
 
 
 class DecodeArgs:
@@ -281,6 +297,38 @@ def set_tuning(**kw):
 
 def release():
     lib().ebcc_release()
+
+
+def workspace_size(ny, nx, p=None):
+    """Device bytes one compress call of an ny x nx field allocates at most
+    (workspace and plan tables); 0 for invalid arguments."""
+    return lib().ebcc_workspace_size(ny, nx, C.byref(p) if p is not None else None)
+
+
+def workspace_size_batch(shapes, p=None, headers=None, lengths=None):
+    """Workspace bytes of one batched compress (headers None) or decompress
+    (headers: the 48-byte header of each stream, host bytes; lengths: the
+    streams' lengths) call over fields of the given (ny, nx) shapes."""
+    n = len(shapes)
+    ny = _arr(C.c_size_t, [s[0] for s in shapes])
+    nx = _arr(C.c_size_t, [s[1] for s in shapes])
+    if headers is None:
+        return lib().ebcc_workspace_size_batch(n, ny, nx, C.byref(p) if p is not None else None, None, None)
+    h = b"".join(bytes(x)[:HDR_BYTES].ljust(HDR_BYTES, b"\0") for x in headers)
+    hb = (C.c_uint8 * max(1, len(h))).from_buffer_copy(h or b"\0")
+    ln = _arr(C.c_size_t, [int(v) for v in lengths])
+    return lib().ebcc_workspace_size_batch(n, ny, nx, None, hb, ln)
+
+
+def workspace_reserve(nbytes, stream=None):
+    """Make the stream's library workspace exactly nbytes now."""
+    _check(lib().ebcc_workspace_reserve(int(nbytes), _stream_ptr(stream)))
+
+
+def device_bytes():
+    """Device bytes the library holds on the current device (workspaces and
+    plan tables)."""
+    return lib().ebcc_device_bytes()
 
 
 def profile_enable(on=True):

@@ -1,18 +1,29 @@
 """Serving loop: continuous batching of compress / decompress requests.
 
 Requests of mixed sizes (device-resident fields to compress, device-resident
-streams to decompress) arrive at any time.  An admission controller keeps
-the device memory that admitted requests hold (inputs, outputs and the
-library's per-sample workspace) under an HBM budget; admitted requests wait
-in FIFO order for a lane.  Each lane is one host thread with its own HIP
-stream (the library keeps one workspace per stream): when a lane is free it
-takes every admitted request that is waiting (up to a batch cap) and runs
-them as one `ebcc_compress_batch` and one `ebcc_decompress_batch` call.
-Requests that arrive while the lanes are busy are admitted as memory frees
-up and go into the next batch of whichever lane frees first, so batches on
-different lanes overlap on the device.  Every result is byte-identical to
-what the request would produce alone (the batched entry points guarantee
-it; the GPU tests check it in the mix).
+streams to decompress) arrive at any time.  An admission controller bounds
+the device memory the server is responsible for by an HBM budget:
+
+  * every lane (one host thread with its own HIP stream) owns one library
+    workspace of a fixed size, reserved when the lane starts
+    (`ebcc_workspace_reserve`), and never runs a batch whose workspace
+    (`ebcc_workspace_size_batch`, the library's own sizing) exceeds it;
+  * every admitted request holds its input and output buffers until it
+    completes; requests are admitted first come, first served while these
+    fit what the lanes' workspaces leave of the budget.
+
+So device memory in use is at most lanes x lane workspace + the admitted
+requests' buffers <= budget (plus the library's small per-shape tables).
+Admitted requests wait in FIFO order for a lane: when a lane is free it
+takes every admitted request that is waiting (up to a batch cap and its
+workspace) and runs them as one `ebcc_compress_batch` and one
+`ebcc_decompress_batch` call.  Requests that arrive while the lanes are busy
+are admitted as memory frees up and go into the next batch of whichever lane
+frees first, so batches on different lanes overlap on the device.  Each
+request gets its own status: a field that cannot be compressed (non-finite
+values) or a stream that cannot be decoded fails alone, and every result is
+byte-identical to what the request produces alone (the batched entry points
+guarantee it; the GPU tests check it against the CPU oracle in the mix).
 
 The executor (what a lane runs for a batch) is a parameter, so the
 admission and batching logic can be exercised without a GPU.
@@ -22,11 +33,7 @@ import threading
 import time
 
 COMPRESS, DECOMPRESS = "compress", "decompress"
-
-# Device bytes the library's workspace takes per sample of a compressed field
-# (eight float planes, four u32 planes, per-code-block pass tables, codeword
-# slots and SPIHT slots, rounded up); decompression needs less.
-WS_BYTES_PER_SAMPLE = 128
+HDR_BYTES = 48
 
 
 class Request:
@@ -36,9 +43,9 @@ class Request:
     result = float32 field tensor."""
 
     __slots__ = ("kind", "data", "shape", "eps", "tag", "t_arrive", "t_admit", "t_start", "t_done", "result",
-                 "status", "cost", "done", "lane", "batch_id", "ready")
+                 "status", "cost", "ws", "done", "lane", "batch_id", "ready", "header", "on_done")
 
-    def __init__(self, kind, data, shape=None, eps=None, tag=None):
+    def __init__(self, kind, data, shape=None, eps=None, tag=None, header=None, on_done=None):
         self.kind = kind
         self.data = data
         self.shape = tuple(shape if shape is not None else data.shape)
@@ -48,10 +55,13 @@ class Request:
         self.result = None
         self.status = None
         self.cost = 0
+        self.ws = 0            # library workspace the request needs alone (bytes)
         self.done = threading.Event()
         self.lane = None
         self.batch_id = None
         self.ready = None      # executor's marker that the data is ready
+        self.header = header   # DECOMPRESS: the stream's first 48 bytes (host), read at submit if None
+        self.on_done = on_done  # called with the request in the lane thread when it completes
 
     @property
     def samples(self):
@@ -65,27 +75,36 @@ class Request:
 
 
 def request_cost(req):
-    """Device bytes an admitted request holds until it completes."""
+    """Device bytes an admitted request holds until it completes: its input
+    and its output (the library workspace is the lanes')."""
     n = req.samples
     if req.kind == COMPRESS:
-        return 4 * n + (48 + 4 * n) + WS_BYTES_PER_SAMPLE * n      # field, stream capacity, workspace
-    return req.data.numel() + 4 * n + (WS_BYTES_PER_SAMPLE // 2) * n  # stream, field, workspace
+        return 4 * n + (HDR_BYTES + 4 * n)          # field, stream capacity
+    return req.data.numel() + 4 * n                 # stream, field
 
 
 class Server:
     """Continuous-batching server.
 
-    hbm_budget   bytes that admitted requests may hold together (a request
-                 larger than the whole budget is refused with ValueError)
-    lanes        concurrent batches (one stream and host thread each)
-    max_batch    requests per batch
-    max_samples  samples per batch
-    executor     callable(lane, compress_reqs, decompress_reqs) that fills
-                 req.result / req.status; default: the GPU executor
+    hbm_budget      device bytes the server may hold: the lanes' workspaces
+                    plus the admitted requests' buffers
+    lanes           concurrent batches (one stream and host thread each)
+    lane_workspace  bytes of library workspace reserved per lane (default:
+                    a quarter of the budget shared by the lanes; 0 for an
+                    executor without workspaces)
+    max_batch       requests per batch
+    max_samples     samples per batch
+    executor        object with on_submit(req), start_lane(lane),
+                    run(lane, compress_reqs, decompress_reqs) (fills
+                    req.result / req.status) and close(); optionally
+                    workspace(req), batch_workspace(comp, dec) and
+                    reserve(lane, nbytes).  Default: the GPU executor.
+    A request whose buffers exceed what the workspaces leave of the budget,
+    or whose workspace exceeds a lane's, is refused with ValueError.
     """
 
     def __init__(self, hbm_budget=64 * 10**9, lanes=2, max_batch=256, max_samples=1 << 27, executor=None,
-                 params=None, base_ratio=30.0):
+                 params=None, base_ratio=30.0, lane_workspace=None):
         self.budget = int(hbm_budget)
         self.lanes = int(lanes)
         self.max_batch = int(max_batch)
@@ -93,10 +112,17 @@ class Server:
         self.params = params or {}
         self.base_ratio = base_ratio
         self.executor = executor or GpuExecutor(self.params, base_ratio)
+        has_ws = hasattr(self.executor, "workspace")
+        if lane_workspace is None:
+            lane_workspace = self.budget // (4 * self.lanes) if has_ws else 0
+        self.lane_ws = int(lane_workspace)
+        self.req_budget = self.budget - self.lanes * self.lane_ws
+        if self.req_budget <= 0:
+            raise ValueError("the lanes' workspaces take the whole budget")
         self._cv = threading.Condition()
         self._pending = collections.deque()    # arrived, not admitted
         self._ready = collections.deque()      # admitted, waiting for a lane
-        self.in_use = 0
+        self.in_use = 0                        # admitted requests' buffers
         self.peak_in_use = 0
         self._running = False
         self._threads = []
@@ -104,13 +130,23 @@ class Server:
         self.batch_sizes = []
         self.completed = []
 
+    @property
+    def reserved(self):
+        """Device bytes the lanes' workspaces take."""
+        return self.lanes * self.lane_ws
+
     # ---- client side ----
     def submit(self, req):
         req.cost = request_cost(req)
-        if req.cost > self.budget:
-            raise ValueError(f"request needs {req.cost} B, more than the whole budget {self.budget} B")
-        req.t_arrive = time.perf_counter()
+        if req.cost > self.req_budget:
+            raise ValueError(f"request needs {req.cost} B, more than the budget leaves for requests "
+                             f"({self.req_budget} B)")
         self.executor.on_submit(req)
+        if hasattr(self.executor, "workspace"):
+            req.ws = int(self.executor.workspace(req))
+            if req.ws > self.lane_ws:
+                raise ValueError(f"request needs {req.ws} B of workspace, more than a lane's {self.lane_ws} B")
+        req.t_arrive = time.perf_counter()
         with self._cv:
             self._pending.append(req)
             self._admit_locked()
@@ -119,7 +155,7 @@ class Server:
 
     # ---- admission: FIFO, as memory frees up ----
     def _admit_locked(self):
-        while self._pending and self.in_use + self._pending[0].cost <= self.budget:
+        while self._pending and self.in_use + self._pending[0].cost <= self.req_budget:
             r = self._pending.popleft()
             self.in_use += r.cost
             self.peak_in_use = max(self.peak_in_use, self.in_use)
@@ -127,17 +163,29 @@ class Server:
             self._ready.append(r)
 
     def _take_locked(self):
-        batch, samples = [], 0
+        batch, samples, ws = [], 0, 0
         while self._ready and len(batch) < self.max_batch:
             r = self._ready[0]
-            if batch and samples + r.samples > self.max_samples:
+            if batch and (samples + r.samples > self.max_samples or ws + r.ws > self.lane_ws):
                 break
             batch.append(self._ready.popleft())
             samples += r.samples
+            ws += r.ws
+        # the summed workspaces bound the batch's; the library's own sizing of
+        # the batch decides (requests that do not fit go back to the front)
+        fit = getattr(self.executor, "batch_workspace", None)
+        while fit is not None and len(batch) > 1:
+            comp = [r for r in batch if r.kind == COMPRESS]
+            dec = [r for r in batch if r.kind == DECOMPRESS]
+            if fit(comp, dec) <= self.lane_ws:
+                break
+            self._ready.appendleft(batch.pop())
         return batch
 
     def _lane(self, lane):
         self.executor.start_lane(lane)
+        if self.lane_ws and hasattr(self.executor, "reserve"):
+            self.executor.reserve(lane, self.lane_ws)
         while True:
             with self._cv:
                 while self._running and not self._ready:
@@ -162,9 +210,12 @@ class Server:
                     if r.status is None:
                         r.status = e
             t = time.perf_counter()
+            for r in batch:
+                r.t_done = t
+                if r.on_done is not None:
+                    r.on_done(r)
             with self._cv:
                 for r in batch:
-                    r.t_done = t
                     self.in_use -= r.cost
                     self.completed.append(r)
                 self._admit_locked()
@@ -219,6 +270,21 @@ class GpuExecutor:
         ev = self.torch.cuda.Event()
         ev.record(self.torch.cuda.current_stream(self.dev))
         req.ready = ev
+        if req.kind == DECOMPRESS and req.header is None:
+            req.header = bytes(req.data[:HDR_BYTES].cpu().numpy().tobytes())
+
+    def workspace(self, req):
+        """Library workspace of the request alone."""
+        return self.batch_workspace([req], []) if req.kind == COMPRESS else self.batch_workspace([], [req])
+
+    def batch_workspace(self, comp, dec):
+        """Library workspace of one lane batch: its compress call, then its
+        decompress call, on the same stream (the larger of the two)."""
+        ebcc = self.ebcc
+        a = ebcc.workspace_size_batch([r.shape for r in comp], self.p) if comp else 0
+        b = ebcc.workspace_size_batch([r.shape for r in dec], headers=[r.header for r in dec],
+                                      lengths=[r.data.numel() for r in dec]) if dec else 0
+        return max(a, b)
 
     def start_lane(self, lane):
         self.torch.cuda.set_device(self.dev)
@@ -226,6 +292,9 @@ class GpuExecutor:
         if key not in _LANE_STREAMS:
             _LANE_STREAMS[key] = self.torch.cuda.Stream(self.dev)
         self.streams[lane] = _LANE_STREAMS[key]
+
+    def reserve(self, lane, nbytes):
+        self.ebcc.workspace_reserve(nbytes, self.streams[lane])
 
     def run(self, lane, comp, dec):
         torch, ebcc = self.torch, self.ebcc
@@ -238,9 +307,10 @@ class GpuExecutor:
                 args = ebcc.BatchArgs([r.data for r in comp], err_bounds=[r.eps for r in comp])
                 out = torch.empty(max(1, args.bound()), dtype=torch.uint8, device=self.dev)
                 rc = ebcc.compress_batch_into(args, out, self.p, s)
+                per_field = rc in (ebcc.OK, ebcc.EINVAL)
                 for i, r in enumerate(comp):
-                    r.status = rc
-                    if rc == 0:
+                    r.status = args.status[i] if per_field else rc
+                    if r.status == 0:
                         r.result = out[args.offsets[i]: args.offsets[i] + args.lengths[i]]
             if dec:
                 outs = [torch.empty(r.shape, dtype=torch.float32, device=self.dev) for r in dec]

@@ -87,3 +87,42 @@ def test_tuning_struct_and_round_trip():
     finally:
         ebcc.set_tuning(**old)
     assert ebcc.get_tuning() == old
+
+
+def _hdr(ny, nx, L=5, cbl=(5, 5), T=1, mode=2):
+    h = bytearray(48)
+    h[:4] = b"EBCC"
+    h[4], h[5], h[6], h[7] = 1, mode, L, cbl[0] | (cbl[1] << 4)
+    h[8:12] = ny.to_bytes(4, "little")
+    h[12:16] = nx.to_bytes(4, "little")
+    h[32:34] = T.to_bytes(2, "little")
+    return bytes(h)
+
+
+def test_workspace_size_queries():
+    """The workspace-size queries are host-only (plan geometry and the calls'
+    own layout code): positive for valid shapes, 0 for invalid arguments,
+    growing with the field, a batch needs no more than its fields alone, and
+    a decompression no more than the compression of the same shape."""
+    ebcc = _lib()
+    shapes = [(91, 180), (181, 360), (361, 720), (721, 1440)]
+    single = [ebcc.workspace_size(*s) for s in shapes]
+    assert all(a > 0 for a in single) and single == sorted(single)
+    assert single[-1] > 4 * 721 * 1440
+    assert ebcc.workspace_size(0, 5) == 0 and ebcc.workspace_size(1 << 25, 2) == 0
+    p = ebcc.params(cblk_log2w=2)           # 4x32 code-blocks: more blocks, more tables
+    assert ebcc.workspace_size(721, 1440, p) > single[-1]
+    mix = [shapes[i % 4] for i in range(37)]
+    batch = ebcc.workspace_size_batch(mix)
+    assert 0 < batch <= sum(single[i % 4] for i in range(37))
+    assert ebcc.workspace_size_batch([shapes[3]]) <= single[3]
+    dec = ebcc.workspace_size_batch([shapes[3]], headers=[_hdr(721, 1440)], lengths=[100000])
+    assert 0 < dec <= ebcc.workspace_size_batch([shapes[3]])
+    # two code-block sizes decode in two calls: the workspace is the larger one
+    both = ebcc.workspace_size_batch([shapes[3], shapes[3]], headers=[_hdr(721, 1440), _hdr(721, 1440, cbl=(2, 2))],
+                                     lengths=[100000, 100000])
+    small = ebcc.workspace_size_batch([shapes[3]], headers=[_hdr(721, 1440, cbl=(2, 2))], lengths=[100000])
+    assert both == max(dec, small)
+    # constant and raw streams need no field buffers
+    const = ebcc.workspace_size_batch([shapes[3]], headers=[_hdr(721, 1440, mode=0)], lengths=[48])
+    assert const < dec

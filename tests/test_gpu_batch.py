@@ -99,23 +99,22 @@ def test_batch_kernel_variants(gpu, ref, t1, spiht, monkeypatch):
     _check_batch(gpu, ref, xs, eps)
 
 
-def test_batch_uneven_mix_equals_solo(gpu):
+def test_batch_uneven_mix_matches_oracle(gpu, ref):
     """The uneven mix of grids from 91x180 to 721x1440 with log-uniform
-    bounds: batched streams equal the single-field calls' streams, and every
-    decoded point meets its bound."""
+    bounds: every batched stream is the oracle's stream of that field alone,
+    every batched decode the oracle's decode, and every decoded point meets
+    its bound."""
     specs = synth.batch_specs(n=24)
     xs = [synth.batch_field(s) for s in specs]
     eps = [s[3] for s in specs]
-    dx = [_dev(x) for x in xs]
-    streams = gpu.compress_batch(dx, err_bounds=eps)
-    for i, x in enumerate(dx):
-        solo = _host(gpu.compress(x, eps[i])).tobytes()
-        assert _host(streams[i]).tobytes() == solo, f"field {i} {tuple(x.shape)}"
+    streams = gpu.compress_batch([_dev(x) for x in xs], err_bounds=eps)
+    refs = [ref.compress(x, e) for x, e in zip(xs, eps)]
+    for i, x in enumerate(xs):
+        assert _host(streams[i]).tobytes() == refs[i], f"field {i} {x.shape}"
     ys = gpu.decompress_batch(streams, [x.shape for x in xs])
     for i, x in enumerate(xs):
         y = _host(ys[i])
-        solo = _host(gpu.decompress(streams[i], *x.shape))
-        assert np.array_equal(y.view(np.uint32), solo.view(np.uint32))
+        assert np.array_equal(y.view(np.uint32), ref.decompress(refs[i], *x.shape).view(np.uint32)), f"field {i}"
         rng_ = float(x.max()) - float(x.min())
         assert np.abs(x.astype(np.float64) - y.astype(np.float64)).max() <= eps[i] * rng_
 
@@ -153,20 +152,21 @@ def test_batch_bad_stream_isolated(gpu):
         assert torch.equal(outs[i].view(torch.int32), good[i].view(torch.int32))
 
 
-def test_batch_mixed_code_block_sizes_decode(gpu):
-    """Streams with another code-block size than the first coded stream of a
-    decode batch are refused one by one; the rest decode."""
+def test_batch_mixed_code_block_sizes_decode(gpu, ref):
+    """Streams of different code-block sizes in one decode batch: the library
+    decodes each size in its own launch sequence; every decode is the
+    oracle's."""
     xs, eps = _mixed_fields()
-    a = gpu.compress(_dev(xs[0]), eps[0])
-    b = gpu.compress(_dev(xs[2]), eps[2], cblk_log2w=6, cblk_log2h=6)
-    c = gpu.compress(_dev(xs[8]), eps[8])
-    outs, st = gpu.decompress_batch([a, b, c], [xs[0].shape, xs[2].shape, xs[8].shape], check=False)
-    assert st == [gpu.OK, gpu.EINVAL, gpu.OK]
-    assert np.array_equal(_host(outs[0]), _host(gpu.decompress(a, *xs[0].shape)))
-    assert np.array_equal(_host(outs[2]), _host(gpu.decompress(c, *xs[8].shape)))
+    cases = [(0, 5, 5), (2, 6, 6), (8, 5, 5), (4, 2, 3), (10, 6, 6), (7, 5, 5)]
+    refs = [ref.compress(xs[i], eps[i], cbl2w=w, cbl2h=h) for i, w, h in cases]
+    outs, st = gpu.decompress_batch([_dev(np.frombuffer(s, np.uint8).copy()) for s in refs],
+                                    [xs[i].shape for i, _, _ in cases], check=False)
+    assert st == [gpu.OK] * len(cases)
+    for (i, _, _), s, y in zip(cases, refs, outs):
+        assert np.array_equal(_host(y).view(np.uint32), ref.decompress(s, *xs[i].shape).view(np.uint32))
 
 
-def test_batch_errors(gpu):
+def test_batch_errors(gpu, ref):
     import torch
     xs, eps = _mixed_fields()
     dx = [_dev(x) for x in xs]
@@ -175,6 +175,16 @@ def test_batch_errors(gpu):
     with pytest.raises(gpu.EbccError) as e:
         gpu.compress_batch(dx, err_bounds=eps)
     assert e.value.code == gpu.EINVAL
+    # the bad field fails alone: the others are the oracle's streams
+    streams, st = gpu.compress_batch(dx, err_bounds=eps, check=False)
+    assert st[3] == gpu.EINVAL and streams[3] is None
+    for i, x in enumerate(xs):
+        if i != 3:
+            assert st[i] == gpu.OK and _host(streams[i]).tobytes() == ref.compress(x, eps[i]), i
+    # a field with invalid dimensions or bound fails alone too
+    streams, st = gpu.compress_batch(dx[:3] + [dx[4]], err_bounds=[eps[0], -1.0, eps[2], eps[4]], check=False)
+    assert st == [gpu.OK, gpu.EINVAL, gpu.OK, gpu.OK]
+    assert _host(streams[3]).tobytes() == ref.compress(xs[4], eps[4])
     args = gpu.BatchArgs([_dev(x) for x in xs], err_bounds=eps)
     small = torch.empty(100, dtype=torch.uint8, device="cuda")
     assert gpu.compress_batch_into(args, small, gpu.params()) == gpu.ENOSPC
@@ -238,11 +248,11 @@ def test_autotune_picks_a_measured_candidate(gpu):
         assert np.abs(xh - y).max() <= eps[i] * (xh.max() - xh.min())
 
 
-def test_nd_chunks_round_trip(gpu):
+def test_nd_chunks_round_trip(gpu, ref):
     """A (T, P, H, W) array in chunks: every chunk is a field of one batched
-    call (its stream equals the flattened chunk compressed alone) and the
-    decoded array meets each chunk's range-relative bound."""
-    import torch
+    call whose stream is the oracle's stream of the flattened chunk, the
+    decoded array is the oracle's decode of each chunk, and every chunk meets
+    its range-relative bound."""
     from paper_2510_22265_amd import nd
     T, P, H, W = 3, 4, 46, 90
     x = np.stack([np.stack([synth.field(v, H, W, cfg=7, level=4 * t + p) for p, v in enumerate("tuvq")])
@@ -254,9 +264,11 @@ def test_nd_chunks_round_trip(gpu):
     assert shape == x.shape and ch == chunk
     for (origin, ext), (o, n) in zip(nd.chunk_grid(x.shape, chunk), table):
         sl = tuple(slice(a, a + e) for a, e in zip(origin, ext))
-        xc = x[sl].reshape(nd.flat_shape(ext))
-        solo = _host(gpu.compress(_dev(xc), 0.005)).tobytes()
-        assert blob[start + o: start + o + n] == solo
+        xc = np.ascontiguousarray(x[sl].reshape(nd.flat_shape(ext)))
+        s_ref = ref.compress(xc, 0.005)
+        assert blob[start + o: start + o + n] == s_ref
+        y_ref = ref.decompress(s_ref, *xc.shape)
+        assert np.array_equal(np.ascontiguousarray(y[sl]).reshape(xc.shape).view(np.uint32), y_ref.view(np.uint32))
         err = np.abs(x[sl].astype(np.float64) - y[sl].astype(np.float64)).max()
         assert err <= 0.005 * (float(xc.max()) - float(xc.min()))
 

@@ -140,3 +140,82 @@ def test_executor_failure_is_reported_per_batch():
     srv.stop()
     assert isinstance(reqs[7].status, RuntimeError)
     _check_results(reqs[:7] + reqs[8:])
+
+
+class WsExecutor(FakeExecutor):
+    """A stand-in with a library workspace: a request needs one byte per
+    sample, a batch the sum plus a fixed overhead per call."""
+
+    def __init__(self, overhead=0, **kw):
+        super().__init__(**kw)
+        self.overhead = overhead
+        self.reserved = {}
+        self.batch_ws = []
+
+    def workspace(self, req):
+        return req.samples + self.overhead
+
+    def batch_workspace(self, comp, dec):
+        return max(sum(r.samples for r in comp) + (self.overhead if comp else 0),
+                   sum(r.samples for r in dec) + (self.overhead if dec else 0))
+
+    def reserve(self, lane, nbytes):
+        self.reserved[lane] = nbytes
+
+    def run(self, lane, comp, dec):
+        self.batch_ws.append(self.batch_workspace(comp, dec))
+        super().run(lane, comp, dec)
+
+
+def test_lane_workspaces_bound_batches():
+    """Each lane reserves its workspace at start; no batch needs more than
+    that; the requests share what the workspaces leave of the budget."""
+    ex = WsExecutor(overhead=1000)
+    n = 361 * 720
+    one = serve.request_cost(serve.Request(serve.COMPRESS, FakeData((361, 720), 0)))
+    lane_ws = 3 * (n + 1000)               # three requests by their own sizes
+    srv = serve.Server(hbm_budget=2 * lane_ws + 8 * one, lanes=2, lane_workspace=lane_ws, executor=ex).start()
+    assert srv.req_budget == 8 * one and srv.reserved == 2 * lane_ws
+    reqs = [srv.submit(serve.Request(serve.COMPRESS, FakeData((361, 720), i), eps=0.01, tag=i)) for i in range(24)]
+    for r in reqs:
+        r.wait(5)
+    srv.stop()
+    _check_results(reqs)
+    assert ex.reserved == {0: lane_ws, 1: lane_ws}
+    assert max(ex.batch_ws) <= lane_ws and max(srv.batch_sizes) == 3
+    assert srv.peak_in_use <= srv.req_budget
+    with pytest.raises(ValueError):     # more workspace than a lane has
+        serve.Server(hbm_budget=10**9, lanes=1, lane_workspace=100, executor=WsExecutor()).submit(
+            serve.Request(serve.COMPRESS, FakeData((91, 180), 0), eps=0.01))
+    with pytest.raises(ValueError):     # the workspaces take the whole budget
+        serve.Server(hbm_budget=100, lanes=2, lane_workspace=50, executor=WsExecutor())
+
+
+def test_batch_workspace_decides_over_the_sum():
+    """When the library's sizing of a batch exceeds the lane's workspace
+    although the requests' own sizes fit, the last requests go back to the
+    front of the queue (FIFO is kept)."""
+    ex = WsExecutor(overhead=1000)
+    ex.workspace = lambda req: req.samples             # understates each request's need
+    n = 181 * 360
+    srv = serve.Server(hbm_budget=10**9, lanes=1, lane_workspace=2 * n + 1000, executor=ex).start()
+    reqs = [srv.submit(serve.Request(serve.COMPRESS, FakeData((181, 360), i), eps=0.01, tag=i)) for i in range(9)]
+    for r in reqs:
+        r.wait(5)
+    srv.stop()
+    _check_results(reqs)
+    assert max(ex.batch_ws) <= 2 * n + 1000
+    starts = [r.t_start for r in reqs]
+    assert starts == sorted(starts)
+
+
+def test_on_done_runs_before_completion_is_signalled():
+    seen = []
+    srv = serve.Server(lanes=1, executor=FakeExecutor()).start()
+    reqs = [srv.submit(serve.Request(serve.COMPRESS, FakeData((91, 180), i), eps=0.01, tag=i,
+                                     on_done=lambda r: seen.append((r.tag, r.done.is_set(), r.status))))
+            for i in range(5)]
+    for r in reqs:
+        r.wait(5)
+    srv.stop()
+    assert sorted(seen) == [(i, False, 0) for i in range(5)]
