@@ -142,6 +142,29 @@ int ebcc_decompress_batch(int n, const uint8_t* const* d_in, const size_t* in_le
                           float* const* d_x, const size_t* ny, const size_t* nx, int* h_status,
                           void* stream);
 
+/* Compress one float32 field without allocating: for callers that cannot
+ * allocate memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and stream
+ * bytes as ebcc_compress; the call's workspace is a static device array of
+ * the library, 256 MiB on each device the library runs on (held until the
+ * process ends), instead of an allocated one.  It calls no device or pinned
+ * host allocation: host tables reach the device as kernel arguments (no
+ * staging buffer), every stage runs on `stream` (no extra streams or
+ * events), and the per-shape tables are written into the scratch by each
+ * call.
+ *   - A field whose workspace does not fit in the array fails with
+ *     EBCC_EINVAL before any work is queued (fields up to 721 x 1440 at the
+ *     default parameters fit; the truncation search then evaluates fewer
+ *     bisection levels per round, with the same result).
+ *   - Every call on a device shares that device's array and leaves its
+ *     contents behind; a call rewrites everything it reads.  Calls are
+ *     serialised by a host lock per device and each returns only after its
+ *     stream has drained, so they do not overlap.  A caller that touches
+ *     the array by other means while a call runs would race with it.
+ * Synchronises `stream`. */
+int ebcc_compress_noalloc(const float* d_x, size_t ny, size_t nx, const ebcc_params* p,
+                          uint8_t* d_out, size_t out_cap, size_t* out_len, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Device memory.  The library keeps one workspace per (device, stream),
  * grown on demand by a call and reused by the next calls on that stream, and

@@ -112,7 +112,7 @@ struct Prof {
   hipStream_t st;
   bool on;
   ProfRec rec;
-  explicit Prof(hipStream_t s) : st(s), on(g_prof != 0) {
+  explicit Prof(hipStream_t s, bool allowed = true) : st(s), on(allowed && g_prof != 0) {
     if (!on) return;
     rec.dev = 0;
     (void)hipGetDevice(&rec.dev);
@@ -156,6 +156,16 @@ __device__ __forceinline__ unsigned f2o(float f) {
 }
 __device__ __forceinline__ float o2f(unsigned u) {
   return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
+// Host-to-device copy through kernel arguments (the no-allocation entry
+// point has no staging buffer): up to kArgChunk bytes per launch.
+constexpr int kArgChunk = 2048;
+struct ArgChunk {
+  uint8_t b[kArgChunk];
+};
+__global__ __launch_bounds__(256) void k_put_bytes(uint8_t* __restrict__ dst, const ArgChunk c, int n) {
+  for (int i = threadIdx.x; i < n; i += 256) dst[i] = c.b[i];
 }
 
 __global__ void k_init_fields(const FieldDev* __restrict__ F, int nf) {
@@ -765,6 +775,9 @@ static int wait_stream(hipStream_t st) {
 struct WS {
   void* base = nullptr;
   size_t cap = 0;
+  // a workspace over the static scratch array: no pinned staging buffer, no
+  // events, no extra streams; every wait is a stream synchronisation
+  bool fixed = false;
   uint8_t* pin = nullptr;
   size_t pin_cap = 0;
   hipEvent_t ev = nullptr;
@@ -774,6 +787,7 @@ struct WS {
   hipStream_t aux = nullptr, aux2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
   ~WS() {
+    if (fixed) return;
     if (ev_live) (void)hipEventSynchronize(ev);
     if (base) (void)hipFree(base);
     if (pin) (void)hipHostFree(pin);
@@ -938,17 +952,40 @@ struct Call {
   FieldDev* Fc = nullptr;
   int* cand_flags = nullptr;
   std::vector<float*> cand_buf;   // per field: CHAT and TMP planes of the extra candidates, or none
+  // plans without device tables (the no-allocation entry point): the
+  // fields' subband tables are carved from the workspace and staged
+  bool own_bands = false;
+  Band* d_bands_own = nullptr;
 
   ~Call() {
-    if (ws && hipEventRecord(ws->ev, st) == hipSuccess) ws->ev_live = true;
+    if (ws && ws->ev && hipEventRecord(ws->ev, st) == hipSuccess) ws->ev_live = true;
   }
-  // Asynchronous host-to-device copy through the pinned staging buffer.
+  int wait() {
+    if (ws && ws->fixed) {
+      HIPCHK(hipStreamSynchronize(st));
+      return EBCC_OK;
+    }
+    return wait_stream(st);
+  }
+  // Asynchronous host-to-device copy through the pinned staging buffer.  A
+  // fixed workspace has none: the bytes travel as kernel arguments, which
+  // the launch copies, so the host source is free again when it returns.
   int stage(void* dst, const void* src, size_t n) {
     if (!n) return EBCC_OK;
+    if (ws->fixed) {
+      ArgChunk ch;
+      for (size_t o = 0; o < n; o += kArgChunk) {
+        const int m = (int)std::min<size_t>(kArgChunk, n - o);
+        memcpy(ch.b, (const uint8_t*)src + o, m);
+        k_put_bytes<<<1, 256, 0, st>>>((uint8_t*)dst + o, ch, m);
+      }
+      HIPCHK(hipGetLastError());
+      return EBCC_OK;
+    }
     if (n > ws->pin_cap) return fail(EBCC_ENOMEM, "staging buffer smaller than a table");
     size_t a = (pin_used + 255) & ~(size_t)255;
     if (a + n > ws->pin_cap) {
-      if (int rc = wait_stream(st)) return rc;
+      if (int rc = wait()) return rc;
       a = 0;
     }
     memcpy(ws->pin + a, src, n);
@@ -959,7 +996,7 @@ struct Call {
   // Device-to-host copy and synchronisation (the staging buffer is free again).
   template <typename T> int fetch(T* h, const T* d, size_t n) {
     HIPCHK(hipMemcpyAsync(h, d, sizeof(T) * n, hipMemcpyDeviceToHost, st));
-    if (int rc = wait_stream(st)) return rc;
+    if (int rc = wait()) return rc;
     pin_used = 0;
     return EBCC_OK;
   }
@@ -972,13 +1009,17 @@ struct Call {
   // Work launched on ws->aux and ws->aux2 between fork() and join() runs
   // concurrently with the caller's stream and is complete, for that stream,
   // after join().
+  // Without extra streams (fixed workspace) everything runs on the caller's.
+  hipStream_t aux_or(hipStream_t s) const { return ws->aux ? s : st; }
   int fork() {
+    if (!ws->aux) return EBCC_OK;
     HIPCHK(hipEventRecord(ws->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(ws->aux, ws->ev_fork, 0));
     HIPCHK(hipStreamWaitEvent(ws->aux2, ws->ev_fork, 0));
     return EBCC_OK;
   }
   int join() {
+    if (!ws->aux) return EBCC_OK;
     HIPCHK(hipEventRecord(ws->ev_join, ws->aux));
     HIPCHK(hipEventRecord(ws->ev_join2, ws->aux2));
     HIPCHK(hipStreamWaitEvent(st, ws->ev_join, 0));
@@ -1045,6 +1086,16 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
   for (int i = 0; i < c.nf; i++)
     if (c.spec_depth > 1 && coded[i])
       c.cand_buf[i] = cv.take<float>(2 * (ncand - 1) * (size_t)c.Fh[i].ny * c.Fh[i].nx);
+  if (c.own_bands) {
+    size_t nbands = 0;
+    for (int i = 0; i < c.nf; i++) nbands += c.plans[i]->bands.size();
+    c.d_bands_own = cv.take<Band>(nbands);
+    nbands = 0;
+    for (int i = 0; i < c.nf; i++) {
+      c.Fh[i].bands = c.d_bands_own ? c.d_bands_own + nbands : nullptr;
+      nbands += c.plans[i]->bands.size();
+    }
+  }
   c.d_blk_own = cv.take<Blk>(nb);
   c.d_tiles_own = cv.take<TileD>(nt);
   c.d_slot_own = cv.take<int64_t>(nt + 1);
@@ -1091,7 +1142,14 @@ static int upload_items(Call& c, const std::vector<int>& coded) {
   std::vector<int> ci;
   for (int i = 0; i < c.nf; i++)
     if (coded[i]) ci.push_back(i);
-  if (ci.size() == 1 && ci[0] == 0) {
+  if (c.own_bands) {   // plans without device tables: stage the subband tables
+    for (int i = 0; i < c.nf; i++) {
+      const Plan* p = c.plans[i];
+      if (int rc = c.stage(const_cast<Band*>(c.Fh[i].bands), p->bands.data(), sizeof(Band) * p->bands.size()))
+        return rc;
+    }
+  }
+  if (ci.size() == 1 && ci[0] == 0 && c.plans[0]->d_blks) {
     c.d_blk = c.plans[0]->d_blks;
     c.d_tiles = c.plans[0]->d_tiles;
     c.d_slot_off = c.plans[0]->d_slot_off;
@@ -1172,9 +1230,13 @@ static size_t compress_need(Call& c, const std::vector<int>& coded) {
 // With fstat, a field whose input is not finite gets EBCC_EINVAL there and
 // no stream (length 0), the others are still compressed and the call
 // returns EBCC_EINVAL; without it such a field fails the call.
+// With fixed_ws (the no-allocation entry point) the call runs in that
+// workspace alone: plans are built for the call without device tables, the
+// search depth is the largest that fits, and a call that does not fit fails
+// before any launch.
 static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, uint8_t* out, size_t cap,
                          std::vector<uint64_t>& offs, std::vector<uint64_t>& lens, size_t* need, hipStream_t st,
-                         const Trace* tr, std::vector<int>* fstat = nullptr) {
+                         const Trace* tr, std::vector<int>* fstat = nullptr, WS* fixed_ws = nullptr) {
   ebcc_params dflt;
   if (!pp) { ebcc_params_default(&dflt); pp = &dflt; }
   const int nf = (int)in.size();
@@ -1196,6 +1258,8 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   c.cbw = 1 << pp->cblk_log2w;
   c.cbh = 1 << pp->cblk_log2h;
   const int cbl = (int)(pp->cblk_log2w | (pp->cblk_log2h << 4)), T = (int)pp->spiht_tile;
+  std::vector<std::unique_ptr<Plan>> own_plans;
+  c.own_bands = fixed_ws != nullptr;
   for (int i = 0; i < nf; i++) {
     FieldDev& f = c.Fh[i];
     memset(&f, 0, sizeof(f));
@@ -1204,17 +1268,39 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     f.buf[BUF_X] = const_cast<float*>(in[i].x);
     f.err = in[i].err; f.bound_mode = (int)pp->bound_mode;
     f.cbl = cbl; f.T = T; f.active = 1;
-    if ((rc = get_plan(f.ny, f.nx, f.L, pp->cblk_log2w, pp->cblk_log2h, T, &c.plans[i]))) return rc;
+    if (fixed_ws) {
+      std::unique_ptr<Plan> p(new Plan());
+      p->ny = f.ny; p->nx = f.nx; p->L = f.L; p->cbl2w = (int)pp->cblk_log2w; p->cbl2h = (int)pp->cblk_log2h;
+      p->cbw = 1 << p->cbl2w; p->cbh = 1 << p->cbl2h; p->T = T;
+      if ((rc = build_plan(*p))) return rc;
+      c.plans[i] = p.get();
+      own_plans.push_back(std::move(p));
+    } else if ((rc = get_plan(f.ny, f.nx, f.L, pp->cblk_log2w, pp->cblk_log2h, T, &c.plans[i]))) {
+      return rc;
+    }
     f.bands = c.plans[i]->d_bands;
     f.nb = c.plans[i]->nb;
   }
   std::vector<int> coded(nf, 1);
   size_t need_ws = compress_need(c, coded);
   char* base;
-  if ((rc = get_ws(st, &c.ws))) return rc;
-  if ((rc = grow_ws(c.ws, need_ws, pin_need(c), st, &base))) return rc;
+  if (fixed_ws) {
+    // fewer bisection levels per search round take fewer candidate planes
+    while (need_ws > fixed_ws->cap && c.spec_depth > 1) {
+      c.spec_depth = c.spec_depth > 2 ? 2 : 1;
+      need_ws = layout_call(c, nullptr, coded);
+    }
+    if (need_ws > fixed_ws->cap)
+      return fail(EBCC_EINVAL, "the field needs " + std::to_string(need_ws) + " bytes of scratch; the static scratch "
+                  "array holds " + std::to_string(fixed_ws->cap));
+    c.ws = fixed_ws;
+    base = (char*)fixed_ws->base;
+  } else {
+    if ((rc = get_ws(st, &c.ws))) return rc;
+    if ((rc = grow_ws(c.ws, need_ws, pin_need(c), st, &base))) return rc;
+  }
   layout_call(c, base, coded);
-  Prof prof(st);
+  Prof prof(st, fixed_ws == nullptr);
 
   // ---- scalars of every field: min, max, range, eps, exponents ----
   if ((rc = c.upload())) return rc;
@@ -1488,12 +1574,12 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
         // the classes run concurrently: global and huge tiles on the second
         // stream, big tiles on the third, small ones on the caller's
         const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
-        hipStream_t sa = c.ws->aux;
+        hipStream_t sa = c.aux_or(c.ws->aux);
         if ((rc = c.fork())) return rc;
         spiht_encode(c.F, c.d_tiles, t2, c.ncls[2], c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, sa);
         spiht_encode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, sa);
         spiht_encode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit,
-                         c.ws->aux2);
+                         c.aux_or(c.ws->aux2));
         spiht_encode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, st);
         if ((rc = c.join())) return rc;
       }
@@ -1621,7 +1707,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     }
     info[10] = checks[0];
     if (tr->info) memcpy(tr->info, info, sizeof(info));
-    if (int rc2 = wait_stream(st)) return rc2;
+    if (int rc2 = c.wait()) return rc2;
   }
   if (first_bad != EBCC_OK) return fail(first_bad, bad_msg);
   return EBCC_OK;
@@ -1881,6 +1967,44 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
   return first;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch for callers that cannot allocate (ebcc_compress_noalloc).
+// The array is a device symbol: host code reaches its memory only through
+// the address hipGetSymbolAddress returns for the current device, taken once
+// per device.  One host mutex per device serialises the calls that use it,
+// and a call waits for its stream before releasing it, so the contents a
+// call leaves are never read by the next one's kernels before they rewrite
+// them.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+struct FixedScratch {
+  std::mutex mu;
+  WS ws;
+};
+static std::mutex g_fixed_mu;
+static std::map<int, std::unique_ptr<FixedScratch>> g_fixed;
+
+static int fixed_scratch(FixedScratch** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  auto it = g_fixed.find(dev);
+  if (it != g_fixed.end()) { *out = it->second.get(); return EBCC_OK; }
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(EBCC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  std::unique_ptr<FixedScratch> f(new FixedScratch());
+  f->ws.fixed = true;
+  f->ws.base = ptr;
+  f->ws.cap = kScratchBytes;
+  *out = f.get();
+  g_fixed[dev] = std::move(f);
+  return EBCC_OK;
+}
+
 }  // namespace ebcc
 
 using namespace ebcc;
@@ -1912,6 +2036,26 @@ int ebcc_compress(const float* d_x, size_t ny, size_t nx, const ebcc_params* p, 
   std::vector<uint64_t> offs, lens;
   size_t need = 0;
   int rc = compress_call(in, p, d_out, out_cap, offs, lens, &need, (hipStream_t)stream, nullptr);
+  *out_len = rc == EBCC_ENOSPC ? need : (rc == EBCC_OK ? (size_t)lens[0] : 0);
+  return rc;
+}
+
+int ebcc_compress_noalloc(const float* d_x, size_t ny, size_t nx, const ebcc_params* p, uint8_t* d_out,
+                          size_t out_cap, size_t* out_len, void* stream) {
+  g_err.clear();
+  if (!out_len) return fail(EBCC_EINVAL, "out_len is NULL");
+  *out_len = 0;
+  FixedScratch* fs = nullptr;
+  if (int rc = fixed_scratch(&fs)) return rc;
+  std::lock_guard<std::mutex> lk(fs->mu);
+  std::vector<FieldIn> in(1, FieldIn{d_x, ny, nx, p ? p->err_bound : 0.01});
+  std::vector<uint64_t> offs, lens;
+  size_t need = 0;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = compress_call(in, p, d_out, out_cap, offs, lens, &need, st, nullptr, nullptr, &fs->ws);
+  // the scratch is free for the next call only once this call's kernels are done
+  hipError_t e = hipStreamSynchronize(st);
+  if (rc == EBCC_OK && e != hipSuccess) rc = fail(EBCC_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
   *out_len = rc == EBCC_ENOSPC ? need : (rc == EBCC_OK ? (size_t)lens[0] : 0);
   return rc;
 }

@@ -22,7 +22,7 @@ SYMBOLS = ("ebcc_params_default", "ebcc_compress_bound", "ebcc_compress", "ebcc_
            "ebcc_release", "ebcc_status_str", "ebcc_last_error", "ebcc_compress_trace", "ebcc_profile_enable",
            "ebcc_profile_read", "ebcc_profile_stage_name", "ebcc_compress_batch", "ebcc_decompress_batch",
            "ebcc_tuning_get", "ebcc_tuning_set", "ebcc_workspace_size", "ebcc_workspace_size_batch",
-           "ebcc_workspace_reserve", "ebcc_device_bytes")
+           "ebcc_workspace_reserve", "ebcc_device_bytes", "ebcc_compress_noalloc")
 
 
 class Params(C.Structure):
@@ -59,6 +59,7 @@ def lib():
         L.ebcc_compress_bound.argtypes = [S, S]
         L.ebcc_compress_bound.restype = S
         L.ebcc_compress.argtypes = [P, S, S, C.POINTER(Params), P, S, C.POINTER(S), P]
+        L.ebcc_compress_noalloc.argtypes = [P, S, S, C.POINTER(Params), P, S, C.POINTER(S), P]
         L.ebcc_compress_trace.argtypes = [P, S, S, C.POINTER(Params), P, S, C.POINTER(S), P, P, P, P, P, P, P]
         L.ebcc_decompress.argtypes = [P, S, P, S, S, P]
         L.ebcc_compress_batch.argtypes = [C.c_int, P, P, P, P, C.POINTER(Params), P, S, P, P, P, P]
@@ -122,6 +123,15 @@ def compress_into(x, out, p, stream=None):
     n = C.c_size_t(0)
     rc = lib().ebcc_compress(C.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], C.byref(p), C.c_void_p(out.data_ptr()),
                              out.numel(), C.byref(n), _stream_ptr(stream))
+    return rc, n.value
+
+
+def compress_noalloc_into(x, out, p, stream=None):
+    """ebcc_compress_noalloc: like compress_into, with the library's static
+    scratch array instead of an allocated workspace; returns (rc, length)."""
+    n = C.c_size_t(0)
+    rc = lib().ebcc_compress_noalloc(C.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], C.byref(p),
+                                     C.c_void_p(out.data_ptr()), out.numel(), C.byref(n), _stream_ptr(stream))
     return rc, n.value
 
 
