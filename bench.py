@@ -44,6 +44,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
+# Plain-ALU ceiling of MQ decisions: 256 compute units issuing one 64-lane
+# vector instruction per cycle at 2.4 GHz (39.3 T lane-operations/s), at
+# about 25 lane-operations per decision (context formation, interval update,
+# renormalisation).  The coders are chains of dependent decisions per
+# code-block, so this is a bound on decisions over all blocks at once.
+T1_ALU_CEILING = 256 * 64 * 2.4e9 / 25
 
 # Per-launch figures of the headline path's tier-1 kernels on one 721x1440
 # field at eps_rel 1%, measured with rocprofv3 (profiles/
@@ -710,7 +716,7 @@ def main():
         log(f"km-scale: {km}")
 
     # ---------------- CPU oracle baselines ----------------
-    cpu = cpu_single = cpu_legs = None
+    cpu = cpu_single = cpu_legs = tier1 = None
     if not args.no_cpu:
         from oracle import ref
         ref.lib()
@@ -724,16 +730,42 @@ def main():
                "cpu_model": model}
         log(f"oracle all cores: {cpu}")
         # one thread (the paper's protocol)
+        # (the oracle's work counters give the MQ decisions of these fields:
+        # what the tier-1 kernels execute, for a decisions/s figure)
         t0 = time.perf_counter()
         done = sb = 0
+        enc_c, dec_c = [], []
         while done < len(stack_h) and time.perf_counter() - t0 < args.cpu_seconds:
+            ref.mq_counts(reset=True)
             s = ref.compress(stack_h[done], args.eps, base_ratio=args.ratio)
+            enc_c.append(ref.mq_counts(reset=True))
             ref.decompress(s, args.ny, args.nx)
+            dec_c.append(ref.mq_counts(reset=True))
             sb += stack_h[done].nbytes
             done += 1
         el = time.perf_counter() - t0
         cpu_single = {"value": sb / el / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
                       "sample": f"{done} of {len(stack_h)} fields, single thread, {el:.1f} s", "cpu_model": model}
+        if done and "t1_encode" in stages and "t1_decode" in stages:
+            enc = float(np.mean([c["enc"] for c in enc_c]))
+            dec = float(np.mean([c["dec"] for c in dec_c]))
+            emax = float(np.mean([c["enc_max_block"] for c in enc_c]))
+            dmax = float(np.mean([c["dec_max_block"] for c in dec_c]))
+            t_enc = stages["t1_encode"][0] / stages["t1_encode"][1] / 1e3    # s per launch (one field)
+            t_dec = stages["t1_decode"][0] / stages["t1_decode"][1] / 1e3
+            tier1 = {"fields": done, "samples_per_field": args.ny * args.nx,
+                     "enc_decisions_per_field": enc, "enc_decisions_per_sample": enc / (args.ny * args.nx),
+                     "enc_max_block_decisions": emax,
+                     "dec_decisions_per_field": dec, "dec_decisions_per_sample": dec / (args.ny * args.nx),
+                     "dec_max_block_decisions": dmax,
+                     "t1_encode_ms": t_enc * 1e3, "t1_decode_ms": t_dec * 1e3,
+                     "enc_decisions_per_s": enc / t_enc, "dec_decisions_per_s": dec / t_dec,
+                     "enc_ns_per_decision_heaviest_block": t_enc / emax * 1e9,
+                     "dec_ns_per_decision_heaviest_block": t_dec / dmax * 1e9,
+                     "alu_ceiling_decisions_per_s": T1_ALU_CEILING,
+                     "enc_frac_of_alu_ceiling": enc / t_enc / T1_ALU_CEILING,
+                     "dec_frac_of_alu_ceiling": dec / t_dec / T1_ALU_CEILING}
+            log(f"tier-1 decisions: {tier1}")
         cpu_legs = {}
         if batch_h:
             rb = oracle_all_cores(batch_h, beps, threads, args.cpu_seconds, base_ratio=args.ratio)
@@ -768,6 +800,7 @@ def main():
         "ratio_search": ratio_search,
         "q_ablation": q_ablation,
         "km_scale": km,
+        "tier1_decisions": tier1,
         "roofline": roof, "cpu_baseline": cpu, "cpu_single_thread": cpu_single, "cpu_legs": cpu_legs,
     }
     print(json.dumps(out), flush=True)

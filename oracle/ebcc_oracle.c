@@ -341,9 +341,22 @@ static void mqe_renorm(mqe_t* e) {
     if (e->CT == 0) mqe_byteout(e);
   } while ((e->A & 0x8000) == 0);
 }
+/* Work counters (measurement only; they do not change any result): MQ
+ * decisions coded and decoded on the calling thread since the last reset,
+ * the code-blocks coded / decoded, and the most decisions in one block. */
+static _Thread_local long g_mq_enc, g_mq_dec, g_mq_enc_blocks, g_mq_dec_blocks, g_mq_enc_max, g_mq_dec_max;
+EXPORT void ebcc_ref_mq_counts(long* out, int reset) {
+  if (out) {
+    out[0] = g_mq_enc; out[1] = g_mq_enc_blocks; out[2] = g_mq_enc_max;
+    out[3] = g_mq_dec; out[4] = g_mq_dec_blocks; out[5] = g_mq_dec_max;
+  }
+  if (reset) g_mq_enc = g_mq_dec = g_mq_enc_blocks = g_mq_dec_blocks = g_mq_enc_max = g_mq_dec_max = 0;
+}
+
 /* ENCODE: MPS takes the upper sub-interval, LPS the lower one of size Qe,
  * with conditional exchange when the MPS part would be the smaller. */
 static void mqe_encode(mqe_t* e, int cx, int d) {
+  g_mq_enc++;
   int s = e->I[cx];
   uint32_t qe = MQT[s].qe;
   e->A -= qe;
@@ -429,6 +442,7 @@ static void mqd_renorm(mqd_t* d) {
   } while ((d->A & 0x8000) == 0);
 }
 static int mqd_decode(mqd_t* d, int cx) {
+  g_mq_dec++;
   int s = d->I[cx];
   uint32_t qe = MQT[s].qe;
   int D;
@@ -664,6 +678,7 @@ static void t1_encode_block(const uint32_t* q, const uint8_t* neg, int w, int h,
   t.m = (uint32_t*)calloc((size_t)n, 4); t.pk = (int8_t*)calloc((size_t)n, 1);
   t.e = &out->e;
   int k = 0;
+  const long dec0 = g_mq_enc;
   for (int p = out->P - 1; p >= 0; p--) {
     for (int ty = (p == out->P - 1) ? 2 : 0; ty < 3; ty++) {
       t.dd = 0;
@@ -673,6 +688,8 @@ static void t1_encode_block(const uint32_t* q, const uint8_t* neg, int w, int h,
       out->R[k] = (int32_t)mqe_flush_copy(&out->e, out->tail[k], &out->bp[k]);
     }
   }
+  g_mq_enc_blocks++;
+  if (g_mq_enc - dec0 > g_mq_enc_max) g_mq_enc_max = g_mq_enc - dec0;
   free(t.sig); free(t.vis); free(t.ref); free(t.neg); free(t.m); free(t.pk);
 }
 /* Codeword terminated after k passes: the bytes emitted before the byte the
@@ -696,11 +713,14 @@ static void t1_decode_block(const uint8_t* cw, long len, int w, int h, int orien
   t.sig = (uint8_t*)calloc((size_t)n, 1); t.vis = (uint8_t*)calloc((size_t)n, 1);
   t.ref = (uint8_t*)calloc((size_t)n, 1); t.neg = neg; t.m = m; t.pk = pk;
   int done = 0;
+  const long dec0 = g_mq_dec;
   for (int p = P - 1; p >= 0 && done < k; p--)
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < k; ty++) {
       if (ty == 0) t1_spp(&t, p); else if (ty == 1) t1_mrp(&t, p); else t1_cp(&t, p);
       done++;
     }
+  g_mq_dec_blocks++;
+  if (g_mq_dec - dec0 > g_mq_dec_max) g_mq_dec_max = g_mq_dec - dec0;
   free(t.sig); free(t.vis); free(t.ref);
 }
 

@@ -73,6 +73,7 @@ def lib():
         L.ebcc_ref_checksum.argtypes = [P, C.c_long]
         L.ebcc_ref_checksum.restype = C.c_uint32
         L.ebcc_ref_mq_table.argtypes = [C.c_int] + [C.POINTER(C.c_int)] * 4
+        L.ebcc_ref_mq_counts.argtypes = [P, C.c_int]
         L.ebcc_ref_quant.argtypes = [C.c_float, C.c_int]
         L.ebcc_ref_quant.restype = C.c_uint32
         _lib = L
@@ -309,3 +310,13 @@ def mq_table():
 def quant(y, sh):
     """Base-layer quantised magnitude floor(|y| 2^sh) (capped at 2^23 - 1)."""
     return lib().ebcc_ref_quant(float(y), int(sh))
+
+
+def mq_counts(reset=False):
+    """MQ decisions made by the oracle on the calling thread since the last
+    reset: coded (encoder) and decoded (decoder) totals, the code-blocks
+    each ran over, and the most decisions in one block (measurement only)."""
+    v = np.zeros(6, dtype=np.int64)
+    lib().ebcc_ref_mq_counts(v.ctypes.data, 1 if reset else 0)
+    return {"enc": int(v[0]), "enc_blocks": int(v[1]), "enc_max_block": int(v[2]),
+            "dec": int(v[3]), "dec_blocks": int(v[4]), "dec_max_block": int(v[5])}

@@ -203,3 +203,26 @@ def test_mq_matches_t88_test_sequence(ref):
     assert bits.size == 256 and enc[-2:] == b"\xff\xac"
     assert ref.mq_encode(cx, bits) == enc[:-2]
     assert (ref.mq_decode(enc, cx) == bits).all()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_mq_decision_counters(ref, seed):
+    """The work counters (measurement only): decoding every pass of a block
+    makes exactly the decisions its encoder made, one block each; the
+    cleanup pass of the top plane codes every sample at least through its
+    run-length or zero-coding decision (one per 4-row column at least)."""
+    rng = np.random.default_rng(900 + seed)
+    h, w = [(32, 32), (16, 64), (7, 13), (64, 64), (5, 4), (32, 8)][seed]
+    q, neg = _block(rng, h, w)
+    ref.mq_counts(reset=True)
+    cw, R, D = ref.t1_encode(q, neg, seed % 4)
+    P = int(q.max()).bit_length()
+    m, ng, pk = ref.t1_decode(cw, h, w, seed % 4, P, len(R) - 1)
+    c = ref.mq_counts(reset=True)
+    if P == 0:      # an all-zero block codes nothing
+        assert c == {k: 0 for k in c}
+        return
+    assert c["enc_blocks"] == 1 and c["dec_blocks"] == 1
+    assert c["enc"] == c["dec"] == c["enc_max_block"] == c["dec_max_block"]
+    assert c["enc"] >= w * ((h + 3) // 4)
+    assert ref.mq_counts() == {k: 0 for k in c}
