@@ -139,3 +139,25 @@ def test_base_quality_counts_errors_not_exceeding_eps(ref, var, cfg):
     strict = np.count_nonzero(err < eps) / err.size
     assert incl != strict
     assert qa == incl
+
+
+ABL_QS = [1 - 1e-3, 1 - 1e-4, 1 - 1e-5, 1 - 1e-6]
+
+
+@pytest.mark.parametrize("eps", [0.001, 0.01, 0.1])
+def test_q_ablation_relative_cr_at_least_one(ref, eps):
+    """Ablation Study: over q in [1 - 1e-3, 1] and range-relative bounds 0.1%
+    to 10%, the compression ratio relative to q = 1 (base layer alone) is at
+    least 1 for every field, because Algorithm 1 falls back to the base-only
+    stream whenever it is the smaller; every stream meets the bound."""
+    rels = []
+    for k, (var, shape) in enumerate([("t", (45, 90)), ("u", (64, 96)), ("v", (48, 80)), ("q", (40, 72))]):
+        x = synth.field(var, *shape, cfg=2, level=k)
+        rng_ = float(x.max()) - float(x.min())
+        base_only = len(ref.compress(x, eps, q=1.0))
+        for q in ABL_QS:
+            s = ref.compress(x, eps, q=q)
+            y = ref.decompress(s, *shape)
+            assert np.abs(x.astype(np.float64) - y.astype(np.float64)).max() <= eps * rng_
+            rels.append(base_only / len(s))
+    assert min(rels) >= 1.0
