@@ -26,9 +26,11 @@
  *   - Said & Pearlman 1996 (SPIHT), cited by the paper for the residual layer.
  *
  * Readings where the paper is silent (the full list is kept with the design
- * notes): fixed base ratio r (no q-feedback), truncation of the residual at
- * bit-plane ends, power-of-two quantiser steps tied to eps, midpoint
- * reconstruction, FP32 lifting in a fixed operation order with contraction off.
+ * notes): a fixed base ratio r or Algorithm 1's q-feedback search, truncation
+ * of the residual at bit-plane ends or (trunc = 1) at a byte position of the
+ * tiles' codes read as one embedded sequence, power-of-two quantiser steps
+ * tied to eps, midpoint reconstruction, FP32 lifting in a fixed operation
+ * order with contraction off.
  *
  * Build: gcc -std=c11 -O2 -ffp-contract=off -fno-fast-math -shared -fPIC
  */
@@ -902,7 +904,9 @@ static void bw_put(bitw_t* w, int bit) {
   if (bit) w->buf[w->nbits >> 3] |= (uint8_t)(0x80 >> (w->nbits & 7));
   w->nbits++;
 }
-typedef struct { const uint8_t* buf; long nbytes, pos; } bitr_t;
+/* Bit reader; bits at positions >= limit are not part of the stream (a
+ * residual cut inside a tile's code), the decoder stops before the first. */
+typedef struct { const uint8_t* buf; long nbytes, pos, limit; } bitr_t;
 static int br_get(bitr_t* r) {
   long by = r->pos >> 3;
   int bit = (by < r->nbytes) ? (r->buf[by] >> (7 - (r->pos & 7))) & 1 : 0;
@@ -914,12 +918,16 @@ typedef struct { node_t n; uint8_t typeB, alive; } lis_t;
 typedef struct { node_t n; uint8_t alive; } lip_t;
 
 /* SPIHT on one tile (Said & Pearlman 1996 list algorithm).  Encoder when
- * dec == 0 (bits from q/neg), decoder otherwise (fills m/neg).  Codes the
+ * dec == 0 (bits from q/neg), decoder otherwise (fills m/neg, and pk, the
+ * lowest bit-plane known of each significant coefficient).  Codes the
  * planes n_top .. n_bot; plane_end_bits[n] (if given) receives the bit count
- * after plane n. */
+ * after plane n.  The decoder stops at the first bit its reader does not
+ * hold (r->limit): a coefficient whose sign is not read stays
+ * insignificant, a refinement bit not read leaves its plane unknown. */
 static void spiht_tile(const sgeom_t* g, long ty, long tx, int n_top, int n_bot, int dec,
                        const uint32_t* q, const smax_t* sm, bitw_t* w, bitr_t* r,
-                       uint32_t* m, uint8_t* neg, long* plane_end_bits) {
+                       uint32_t* m, uint8_t* neg, int8_t* pk, long* plane_end_bits, long* refine_start_bits,
+                       int sort_only_last) {
   long i0 = ty * g->T, j0 = tx * g->T;
   long i1 = i0 + g->T < g->hL ? i0 + g->T : g->hL, j1 = j0 + g->T < g->wL ? j0 + g->T : g->wL;
   /* capacity: every coefficient of the tile's trees */
@@ -938,6 +946,7 @@ static void spiht_tile(const sgeom_t* g, long ty, long tx, int n_top, int n_bot,
       if (offspring(g, n, o) > 0) lis[nlis++] = (lis_t){n, 0, 1};
     }
 #define EMIT(bitv) (dec ? br_get(r) : (bw_put(w, (bitv)), (bitv)))
+#define CUT (dec && r->pos > r->limit)      /* the bit just read lies past the cut */
   for (int pl = n_top; pl >= n_bot; pl--) {
     uint64_t thr = (uint64_t)1 << pl;
     long lsp_prev = nlsp;
@@ -945,9 +954,11 @@ static void spiht_tile(const sgeom_t* g, long ty, long tx, int n_top, int n_bot,
       if (!lip[k].alive) continue;
       long p = node_pos(g, lip[k].n);
       int s = EMIT(dec ? 0 : (q[p] >= thr));
+      if (CUT) goto out;
       if (s) {
         int sg = EMIT(dec ? 0 : neg[p]);
-        if (dec) { neg[p] = (uint8_t)sg; m[p] = (uint32_t)thr; }
+        if (CUT) goto out;
+        if (dec) { neg[p] = (uint8_t)sg; m[p] = (uint32_t)thr; pk[p] = (int8_t)pl; }
         lsp[nlsp++] = lip[k].n;
         lip[k].alive = 0;
       }
@@ -959,14 +970,17 @@ static void spiht_tile(const sgeom_t* g, long ty, long tx, int n_top, int n_bot,
       int no = offspring(g, n, o);
       if (!lis[k].typeB) {
         int s = EMIT(dec ? 0 : (sm->maxD[p] >= thr));
+        if (CUT) goto out;
         if (!s) continue;
         int hasL = 0;
         for (int c = 0; c < no; c++) {
           long pc = node_pos(g, o[c]);
           int sc = EMIT(dec ? 0 : (q[pc] >= thr));
+          if (CUT) goto out;
           if (sc) {
             int sg = EMIT(dec ? 0 : neg[pc]);
-            if (dec) { neg[pc] = (uint8_t)sg; m[pc] = (uint32_t)thr; }
+            if (CUT) goto out;
+            if (dec) { neg[pc] = (uint8_t)sg; m[pc] = (uint32_t)thr; pk[pc] = (int8_t)pl; }
             lsp[nlsp++] = o[c];
           } else {
             lip[nlip++] = (lip_t){o[c], 1};
@@ -977,19 +991,25 @@ static void spiht_tile(const sgeom_t* g, long ty, long tx, int n_top, int n_bot,
         if (hasL) lis[nlis++] = (lis_t){n, 1, 1};
       } else {
         int s = EMIT(dec ? 0 : (sm->maxL[p] >= thr));
+        if (CUT) goto out;
         if (!s) continue;
         for (int c = 0; c < no; c++)
           if (offspring(g, o[c], oo) > 0) lis[nlis++] = (lis_t){o[c], 0, 1};
         lis[k].alive = 0;
       }
     }
+    if (refine_start_bits) refine_start_bits[pl] = dec ? r->pos : w->nbits;
+    if (pl == n_bot && sort_only_last) break;
     for (long k = 0; k < lsp_prev; k++) {
       long p = node_pos(g, lsp[k]);
       int b = EMIT(dec ? 0 : (int)((q[p] >> pl) & 1u));
-      if (dec && b) m[p] |= (uint32_t)thr;
+      if (CUT) goto out;
+      if (dec) { if (b) m[p] |= (uint32_t)thr; pk[p] = (int8_t)pl; }
     }
     if (plane_end_bits) plane_end_bits[pl] = dec ? r->pos : w->nbits;
   }
+out:
+#undef CUT
 #undef EMIT
   free(lip); free(lis); free(lsp);
 }
@@ -1008,24 +1028,26 @@ static int tile_top_plane(const sgeom_t* g, const smax_t* sm, long ty, long tx) 
 
 /* Full SPIHT code of every tile (planes n_t .. 0) with the bit position at
  * the end of each plane, so that any plane-end truncation can be cut out. */
-typedef struct { long ntiles; int* ntop; bitw_t* w; long (*pend)[32]; } scode_t;
+typedef struct { long ntiles; int* ntop; bitw_t* w; long (*pend)[32]; long (*rs)[32]; } scode_t;
 static void spiht_encode_all(const sgeom_t* g, const uint32_t* q, const uint8_t* neg, scode_t* sc) {
   smax_t sm; smax_build(g, q, &sm);
   sc->ntiles = g->tiles_y * g->tiles_x;
   sc->ntop = (int*)malloc(sizeof(int) * (size_t)sc->ntiles);
   sc->w = (bitw_t*)calloc((size_t)sc->ntiles, sizeof(bitw_t));
   sc->pend = (long(*)[32])calloc((size_t)sc->ntiles, sizeof(long[32]));
+  sc->rs = (long(*)[32])calloc((size_t)sc->ntiles, sizeof(long[32]));
   for (long t = 0; t < sc->ntiles; t++) {
     long ty = t / g->tiles_x, tx = t % g->tiles_x;
     sc->ntop[t] = tile_top_plane(g, &sm, ty, tx);
     if (sc->ntop[t] >= 0)
-      spiht_tile(g, ty, tx, sc->ntop[t], 0, 0, q, &sm, &sc->w[t], NULL, NULL, (uint8_t*)neg, sc->pend[t]);
+      spiht_tile(g, ty, tx, sc->ntop[t], 0, 0, q, &sm, &sc->w[t], NULL, NULL, (uint8_t*)neg, NULL, sc->pend[t],
+                 sc->rs[t], 0);
   }
   smax_free(&sm);
 }
 static void scode_free(scode_t* sc) {
   for (long t = 0; t < sc->ntiles; t++) free(sc->w[t].buf);
-  free(sc->w); free(sc->ntop); free(sc->pend);
+  free(sc->w); free(sc->ntop); free(sc->pend); free(sc->rs);
 }
 /* Residual section for truncation at the end of plane n_s: tile table
  * (u32: byte length | (n_t + 1) << 26, or 0 for a tile with no plane >= n_s),
@@ -1051,18 +1073,88 @@ static void resid_section_write(const scode_t* sc, int n_s, uint8_t* out) {
     pay += by;
   }
 }
-/* Decode a residual section: magnitudes m (bits >= n_s) and signs. */
-static int resid_section_decode(const sgeom_t* g, const uint8_t* in, long len, int n_s, uint32_t* m, uint8_t* neg) {
+/* Byte-granular truncation (Algorithm 1's second binary search over a
+ * byte position t of one embedded code).  The tiles' codes are read as one
+ * embedded sequence ordered like a single SPIHT code: plane by plane, and
+ * within a plane the sorting passes of every tile (in tile order), then
+ * the refinement passes of every tile.  A prefix that ends inside plane n_s
+ * keeps every plane above n_s, and of plane n_s either (kind 0) the sorting
+ * passes of the tiles before the cut tile J and the first lJ bits of J's
+ * code, or (kind 1) every sorting pass, the refinement passes of the tiles
+ * before J and the first lJ bits of J's code.  Each tile's code is then
+ * still a prefix of itself.  Section: u32 J | kind << 31, u32 lJ, then the
+ * tile table and payloads as above.
+ * Bits of tile t's code through plane n, and before plane n's refinement
+ * pass (0 if the tile has no plane >= n). */
+static long tile_bits(const scode_t* sc, long t, int n) { return sc->ntop[t] >= n ? sc->pend[t][n] : 0; }
+static long tile_sort_bits(const scode_t* sc, long t, int n) { return sc->ntop[t] >= n ? sc->rs[t][n] : 0; }
+/* Sequence position t (bits) with lo < t <= hi (lo, hi: bits through plane
+ * n_s + 1, through n_s) -> the cut: kind, tile J and its code length lJ. */
+static void byte_cut(const scode_t* sc, int n_s, long t, int* kind, long* J, long* lJ) {
+  long u = t;
+  for (long j = 0; j < sc->ntiles; j++) u -= tile_bits(sc, j, n_s + 1);
+  for (int k = 0; k < 2; k++)
+    for (long j = 0; j < sc->ntiles; j++) {
+      long a = k ? tile_sort_bits(sc, j, n_s) : tile_bits(sc, j, n_s + 1);
+      long len = (k ? tile_bits(sc, j, n_s) : tile_sort_bits(sc, j, n_s)) - a;
+      if (len > 0 && u <= len) { *kind = k; *J = j; *lJ = a + u; return; }
+      u -= len;
+    }
+  *kind = 1; *J = sc->ntiles - 1; *lJ = tile_bits(sc, sc->ntiles - 1, n_s);   /* not reached for t in range */
+}
+static long cut_tile_bits(const scode_t* sc, int n_s, int kind, long J, long lJ, long t) {
+  if (t == J) return lJ;
+  if (kind == 0) return t < J ? tile_sort_bits(sc, t, n_s) : tile_bits(sc, t, n_s + 1);
+  return t < J ? tile_bits(sc, t, n_s) : tile_sort_bits(sc, t, n_s);
+}
+static long resid_section_size_bt(const scode_t* sc, int n_s, int kind, long J, long lJ) {
+  long sz = 8 + 4 * sc->ntiles;
+  for (long t = 0; t < sc->ntiles; t++) sz += (cut_tile_bits(sc, n_s, kind, J, lJ, t) + 7) >> 3;
+  return sz;
+}
+static void resid_section_write_bt(const scode_t* sc, int n_s, int kind, long J, long lJ, uint8_t* out) {
+  put_u32(out, (uint32_t)J | ((uint32_t)kind << 31)); put_u32(out + 4, (uint32_t)lJ);
+  out += 8;
+  uint8_t* pay = out + 4 * sc->ntiles;
+  for (long t = 0; t < sc->ntiles; t++) {
+    long bits = cut_tile_bits(sc, n_s, kind, J, lJ, t), by = (bits + 7) >> 3;
+    if (bits == 0) { put_u32(out + 4 * t, 0); continue; }
+    put_u32(out + 4 * t, (uint32_t)by | ((uint32_t)(sc->ntop[t] + 1) << 26));
+    memcpy(pay, sc->w[t].buf, (size_t)by);
+    if (bits & 7) pay[by - 1] &= (uint8_t)(0xFF << (8 - (bits & 7)));
+    pay += by;
+  }
+}
+/* Decode a residual section: magnitudes m (known bits), signs, and the
+ * lowest known plane of each significant coefficient.  bt: the section is
+ * cut at a byte position (the two words above lead it). */
+static int resid_section_decode(const sgeom_t* g, const uint8_t* in, long len, int n_s, int bt,
+                                uint32_t* m, uint8_t* neg, int8_t* pk) {
   long nt = g->tiles_y * g->tiles_x;
+  long J = nt, lJ = 0;
+  int kind = 1;
+  if (bt) {
+    if (len < 8) return REF_ECORRUPT;
+    J = get_u32(in) & 0x7FFFFFFF; kind = (int)(get_u32(in) >> 31); lJ = get_u32(in + 4);
+    if (J >= nt) return REF_ECORRUPT;
+    in += 8; len -= 8;
+  }
   if (len < 4 * nt) return REF_ECORRUPT;
   long off = 4 * nt;
   for (long t = 0; t < nt; t++) {
     uint32_t e = get_u32(in + 4 * t);
     long by = e & 0x3FFFFFF; int ntop = (int)(e >> 26) - 1;
     if (off + by > len) return REF_ECORRUPT;
-    if (ntop >= n_s) {
-      bitr_t r = {in + off, by, 0};
-      spiht_tile(g, t / g->tiles_x, t % g->tiles_x, ntop, n_s, 1, NULL, NULL, NULL, &r, m, neg, NULL);
+    /* kind 0: tiles before J stop after plane n_s's sorting pass, tiles
+     * after it at the end of plane n_s + 1; kind 1: tiles after J stop after
+     * plane n_s's sorting pass */
+    int nb = (kind == 0 && t > J) ? n_s + 1 : n_s;
+    int sort_only = (kind == 0 && t < J) || (kind == 1 && t > J);
+    if (t == J && (lJ > 8 * by || lJ <= 8 * (by - 1))) return REF_ECORRUPT;
+    if (ntop >= nb) {
+      bitr_t r = {in + off, by, 0, t == J ? lJ : 8 * by};
+      spiht_tile(g, t / g->tiles_x, t % g->tiles_x, ntop, nb, 1, NULL, NULL, NULL, &r, m, neg, pk, NULL, NULL,
+                 sort_only);
     }
     off += by;
   }
@@ -1083,7 +1175,37 @@ EXPORT int ebcc_ref_spiht_decode(const uint8_t* in, long len, long ny, long nx, 
   sgeom_t g; sgeom_init(&g, ny, nx, L, T);
   memset(m, 0, sizeof(uint32_t) * (size_t)(ny * nx));
   memset(neg, 0, (size_t)(ny * nx));
-  return resid_section_decode(&g, in, len, n_s, m, neg);
+  int8_t* pk = (int8_t*)calloc((size_t)(ny * nx), 1);
+  int rc = resid_section_decode(&g, in, len, n_s, 0, m, neg, pk);
+  free(pk);
+  return rc;
+}
+/* Test hooks of the byte-granular cut: the residual section of q/neg cut at
+ * embedded position t (bits within plane n_s), and one tile's code decoded
+ * from its first `limit` bits (magnitudes, signs, lowest known planes). */
+EXPORT long ebcc_ref_spiht_encode_cut(const uint32_t* q, const uint8_t* neg, long ny, long nx, int L, int T, int n_s,
+                                      long t, uint8_t* out, long cap, long* span) {
+  sgeom_t g; sgeom_init(&g, ny, nx, L, T);
+  scode_t sc; spiht_encode_all(&g, q, neg, &sc);
+  long lo = 0, hi = 0;
+  for (long j = 0; j < sc.ntiles; j++) { lo += tile_bits(&sc, j, n_s + 1); hi += tile_bits(&sc, j, n_s); }
+  if (span) { span[0] = lo; span[1] = hi; }
+  long sz = -1;
+  if (t > lo && t <= hi) {
+    int kind; long J, lJ; byte_cut(&sc, n_s, t, &kind, &J, &lJ);
+    sz = resid_section_size_bt(&sc, n_s, kind, J, lJ);
+    if (sz <= cap) resid_section_write_bt(&sc, n_s, kind, J, lJ, out); else sz = -sz;
+  }
+  scode_free(&sc);
+  return sz;
+}
+EXPORT int ebcc_ref_spiht_decode_cut(const uint8_t* in, long len, long ny, long nx, int L, int T, int n_s,
+                                     uint32_t* m, uint8_t* neg, int8_t* pk) {
+  sgeom_t g; sgeom_init(&g, ny, nx, L, T);
+  memset(m, 0, sizeof(uint32_t) * (size_t)(ny * nx));
+  memset(neg, 0, (size_t)(ny * nx));
+  memset(pk, 0, (size_t)(ny * nx));
+  return resid_section_decode(&g, in, len, n_s, 1, m, neg, pk);
 }
 
 /* ======================================================================== */
@@ -1184,14 +1306,17 @@ static void base_decode(const layout_t* ly, int e0, const uint8_t* pbv, const ui
   dwt2_f(out, ly->ny, ly->nx, ly->L, 1);
 }
 
-/* Residual reconstruction of a residual section at truncation plane n_s. */
-static int resid_decode(const layout_t* ly, const uint8_t* sec, long len, int er, int ns, float* out) {
+/* Residual reconstruction of a residual section at truncation plane n_s
+ * (bt: cut at a byte position inside plane n_s): midpoint of each
+ * coefficient's remaining interval, below its lowest known plane. */
+static int resid_decode(const layout_t* ly, const uint8_t* sec, long len, int er, int ns, int bt, float* out) {
   long N = ly->ny * ly->nx;
   sgeom_t g; sgeom_init(&g, ly->ny, ly->nx, ly->L, ly->T);
   uint32_t* m = (uint32_t*)calloc((size_t)N, 4); uint8_t* ng = (uint8_t*)calloc((size_t)N, 1);
-  int rc = resid_section_decode(&g, sec, len, ns, m, ng);
-  for (long i = 0; i < N; i++) out[i] = dequant(m[i], ns, ng[i], er);
-  free(m); free(ng);
+  int8_t* pk = (int8_t*)calloc((size_t)N, 1);
+  int rc = resid_section_decode(&g, sec, len, ns, bt, m, ng, pk);
+  for (long i = 0; i < N; i++) out[i] = dequant(m[i], pk[i], ng[i], er);
+  free(m); free(ng); free(pk);
   dwt2_f(out, ly->ny, ly->nx, ly->L, 1);
   return rc;
 }
@@ -1343,13 +1468,14 @@ EXPORT long ebcc_ref_base_budget(long N, long nblk, double r) { return base_budg
  * Returns 0 and the stream length, or a negative status. */
 EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, double err_bound, int bound_mode,
                                    double base_ratio, double q, int levels, int cbl2w, int cbl2h, int tile,
-                                   uint8_t* out, size_t cap, size_t* out_len, ebcc_ref_trace* tr) {
+                                   int trunc, uint8_t* out, size_t cap, size_t* out_len, ebcc_ref_trace* tr) {
   long ny = (long)ny_, nx = (long)nx_;
   if (out_len) *out_len = 0;
   if (ny < 1 || nx < 1 || ny > (1L << 24) || nx > (1L << 24) || ny * nx > (1L << 31) - 1) return REF_EINVAL;
   if (!(err_bound > 0) || !isfinite(err_bound) || !(base_ratio >= 1.0) || !isfinite(base_ratio)) return REF_EINVAL;
   if (!(q >= 0.0 && q <= 1.0)) return REF_EINVAL;
-  if (levels < 0 || levels > MAX_LEVELS || cbl2w < 2 || cbl2h < 2 || cbl2w > 6 || cbl2h > 6 || tile < 1 || tile > 64)
+  if (levels < 0 || levels > MAX_LEVELS || cbl2w < 2 || cbl2h < 2 || cbl2w > 6 || cbl2h > 6 || tile < 1 || tile > 64 ||
+      trunc < 0 || trunc > 1)
     return REF_EINVAL;
   long N = ny * nx;
   float xmin = x[0], xmax = x[0];
@@ -1388,7 +1514,7 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
   /* normalise: a = ((x - min) * (1/range)) - 0.5 */
   for (long i = 0; i < N; i++) { float t = x[i] - xmin; t = t * inv_f; a[i] = t - 0.5f; }
   int e0 = elog - 2; if (e0 < -20) e0 = -20; if (e0 > 0) e0 = 0;
-  int er_final = 0, nmax_final = -1, ns_final = 0, checks = 0;
+  int er_final = 0, nmax_final = -1, ns_final = 0, checks = 0, bt_final = 0;
   uint8_t* pbv = (uint8_t*)calloc((size_t)ly.nblk, 1);
   uint8_t* kbv = (uint8_t*)calloc((size_t)ly.nblk, 1);
   uint8_t** cw = (uint8_t**)calloc((size_t)ly.nblk, sizeof(uint8_t*));
@@ -1471,7 +1597,7 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
         #define FEASIBLE(kk, res) do { \
             int ns_ = nmax - (kk) + 1; long sz_ = resid_section_size(&sc, ns_); \
             uint8_t* sec_ = (uint8_t*)malloc((size_t)sz_ + 1); resid_section_write(&sc, ns_, sec_); \
-            resid_decode(&ly, sec_, sz_, er, ns_, rrec); free(sec_); checks++; \
+            resid_decode(&ly, sec_, sz_, er, ns_, 0, rrec); free(sec_); checks++; \
             res = within_bound(x, abase, rrec, N, xmin, range_f, eps); } while (0)
         int okK; FEASIBLE(K, okK);
         if (okK) {
@@ -1484,9 +1610,40 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
           #undef FEASIBLE
           found = 1;
           er_final = er; nmax_final = nmax; ns_final = nmax - hi + 1;
-          resid_bytes = resid_section_size(&sc, ns_final);
-          resid = (uint8_t*)malloc((size_t)resid_bytes + 1);
-          resid_section_write(&sc, ns_final, resid);
+          if (!trunc) {
+            resid_bytes = resid_section_size(&sc, ns_final);
+            resid = (uint8_t*)malloc((size_t)resid_bytes + 1);
+            resid_section_write(&sc, ns_final, resid);
+          } else {
+            /* Algorithm 1's second binary search at byte granularity, over
+             * the embedded sequence from the end of plane n_s + 1 (known to
+             * miss the bound) to the end of plane n_s (known to meet it):
+             * t = 8 b bits, b integer; the end of plane n_s when 8 b passes it. */
+            long vlo = 0, vhi = 0;
+            for (long j = 0; j < sc.ntiles; j++) { vlo += tile_bits(&sc, j, ns_final + 1); vhi += tile_bits(&sc, j, ns_final); }
+            long blo = vlo / 8, bhi = (vhi + 7) / 8;
+            #define CUTAT(b) (8 * (b) < vhi ? 8 * (b) : vhi)
+            while (bhi - blo > 1) {
+              long bm = (blo + bhi) / 2, J, lJ;
+              int kind;
+              byte_cut(&sc, ns_final, CUTAT(bm), &kind, &J, &lJ);
+              long sz = resid_section_size_bt(&sc, ns_final, kind, J, lJ);
+              uint8_t* sec = (uint8_t*)malloc((size_t)sz + 1);
+              resid_section_write_bt(&sc, ns_final, kind, J, lJ, sec);
+              resid_decode(&ly, sec, sz, er, ns_final, 1, rrec);
+              free(sec);
+              checks++;
+              if (within_bound(x, abase, rrec, N, xmin, range_f, eps)) bhi = bm; else blo = bm;
+            }
+            long J, lJ;
+            int kind;
+            byte_cut(&sc, ns_final, CUTAT(bhi), &kind, &J, &lJ);
+            #undef CUTAT
+            resid_bytes = resid_section_size_bt(&sc, ns_final, kind, J, lJ);
+            resid = (uint8_t*)malloc((size_t)resid_bytes + 1);
+            resid_section_write_bt(&sc, ns_final, kind, J, lJ, resid);
+            bt_final = 1;
+          }
         }
         scode_free(&sc);
       }
@@ -1503,7 +1660,7 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
       if (pay1 < ebcc_total) {
         base_payload = base_at(&bc, r_only, NULL, NULL);
         mode = MODE_CODED;
-        er_final = 0; nmax_final = -1; ns_final = 0; resid_bytes = 0;
+        er_final = 0; nmax_final = -1; ns_final = 0; resid_bytes = 0; bt_final = 0;
         free(resid); resid = NULL;
         if (tr && tr->kb) memcpy(tr->kb, kbv, (size_t)ly.nblk);
         if (tr && tr->abase) memcpy(tr->abase, abase, sizeof(float) * (size_t)N);
@@ -1527,6 +1684,7 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
     uint32_t bb = (uint32_t)(4 * ly.nblk + base_payload);
     write_header(out, MODE_CODED, ly.L, cbl, ny, nx, xmin, range_f, inv_f, e0, er_final, nmax_final, ns_final,
                  tile, bb, (uint32_t)resid_bytes);
+    if (bt_final) out[34] |= 1;                            /* residual cut at a byte position */
     uint8_t* p = out + HDR_BYTES;
     for (long b = 0; b < ly.nblk; b++) {
       p[4 * b] = pbv[b]; p[4 * b + 1] = kbv[b]; put_u16(p + 4 * b + 2, (uint32_t)cwlen[b]);
@@ -1553,10 +1711,10 @@ done:
 }
 
 EXPORT int ebcc_ref_compress(const float* x, size_t ny, size_t nx, double err_bound, int bound_mode,
-                             double base_ratio, double q, int levels, int cbl2w, int cbl2h, int tile,
+                             double base_ratio, double q, int levels, int cbl2w, int cbl2h, int tile, int trunc,
                              uint8_t* out, size_t cap, size_t* out_len) {
   return ebcc_ref_compress_trace(x, ny, nx, err_bound, bound_mode, base_ratio, q, levels, cbl2w, cbl2h, tile,
-                                 out, cap, out_len, NULL);
+                                 trunc, out, cap, out_len, NULL);
 }
 
 /* Header fields of a stream (no payload validation). */
@@ -1582,7 +1740,7 @@ EXPORT int ebcc_ref_decompress(const uint8_t* in, size_t len, float* x, size_t n
   if (mode == MODE_CONST) { for (long i = 0; i < N; i++) x[i] = xmin; return REF_OK; }
   if (mode == MODE_RAW) { if (bb != 4 * (uint32_t)N) return REF_ECORRUPT; memcpy(x, in + HDR_BYTES, 4 * (size_t)N); return REF_OK; }
   int L = in[6], cbl2w = in[7] & 15, cbl2h = in[7] >> 4, T = (int)get_u16(in + 32);
-  int e0 = (int8_t)in[28], er = (int8_t)in[29], ns = (int8_t)in[31];
+  int e0 = (int8_t)in[28], er = (int8_t)in[29], ns = (int8_t)in[31], bt = in[34] & 1;
   if (L != levels_eff(ny, nx, L) || cbl2w < 2 || cbl2h < 2 || cbl2w > 6 || cbl2h > 6 || T < 1) return REF_ECORRUPT;
   layout_t ly; layout_init(&ly, ny, nx, L, cbl2w, cbl2h, T);
   int rc = REF_OK;
@@ -1602,7 +1760,7 @@ EXPORT int ebcc_ref_decompress(const uint8_t* in, size_t len, float* x, size_t n
   float* r = (float*)calloc((size_t)N, sizeof(float));
   if (rc == REF_OK) {
     base_decode(&ly, e0, pbv, kbv, cw, cwlen, abase);
-    if (rb) rc = resid_decode(&ly, in + HDR_BYTES + bb, rb, er, ns, r);
+    if (rb) rc = resid_decode(&ly, in + HDR_BYTES + bb, rb, er, ns, bt, r);
   }
   if (rc == REF_OK)
     for (long i = 0; i < N; i++) x[i] = denorm(abase[i], r[i], xmin, range_f);

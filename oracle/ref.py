@@ -41,8 +41,12 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.ebcc_ref_compress_trace.argtypes = [P, C.c_size_t, C.c_size_t, C.c_double, C.c_int, C.c_double,
-                                              C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, P, C.c_size_t,
-                                              C.POINTER(C.c_size_t), P]
+                                              C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P,
+                                              C.c_size_t, C.POINTER(C.c_size_t), P]
+        L.ebcc_ref_spiht_encode_cut.argtypes = [P, P, C.c_long, C.c_long, C.c_int, C.c_int, C.c_int, C.c_long, P,
+                                                C.c_long, P]
+        L.ebcc_ref_spiht_encode_cut.restype = C.c_long
+        L.ebcc_ref_spiht_decode_cut.argtypes = [P, C.c_long, C.c_long, C.c_long, C.c_int, C.c_int, C.c_int, P, P, P]
         L.ebcc_ref_base_budget.argtypes = [C.c_long, C.c_long, C.c_double]
         L.ebcc_ref_base_budget.restype = C.c_long
         L.ebcc_ref_alg1_log.argtypes = [P, P, P, P, C.c_int]
@@ -104,9 +108,11 @@ def n_blocks(ny, nx, levels=5, cbl2w=5, cbl2h=5):
     return n
 
 
-def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, trace=False, q=0.0):
+def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, trace=False, q=0.0,
+             trunc=0):
     """Compress a 2-D float32 field.  Returns bytes (and a dict of
-    intermediate results when ``trace`` is true)."""
+    intermediate results when ``trace`` is true).  trunc=1 cuts the residual
+    at a byte position instead of a bit-plane end."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     ny, nx = x.shape
     L = lib()
@@ -122,8 +128,8 @@ def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl
                     info=np.zeros(11, np.int32))
         tr = Trace(*[_p(bufs[k]).value for k in ("coef", "abase", "cres", "kb", "pb", "info")])
     rc = L.ebcc_ref_compress_trace(_p(x), ny, nx, float(err_bound), int(bound_mode), float(base_ratio), float(q),
-                                   int(levels), int(cbl2w), int(cbl2h), int(tile), _p(out), cap, C.byref(n),
-                                   C.byref(tr) if tr is not None else None)
+                                   int(levels), int(cbl2w), int(cbl2h), int(tile), int(trunc), _p(out), cap,
+                                   C.byref(n), C.byref(tr) if tr is not None else None)
     if rc != OK:
         raise RuntimeError(f"ebcc_ref_compress failed: {rc}")
     s = out[: n.value].tobytes()
@@ -136,7 +142,8 @@ def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl
     return s
 
 
-def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, cap=None, q=0.0):
+def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, cap=None, q=0.0,
+                trunc=0):
     """Raw status-code form for error-path tests: returns (rc, bytes or None, out_len)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     ny, nx = x.shape if x.ndim == 2 else (x.size, 1)
@@ -146,7 +153,8 @@ def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, 
     out = np.zeros(max(cap, 1), dtype=np.uint8)
     n = C.c_size_t(0)
     rc = L.ebcc_ref_compress_trace(_p(x), ny, nx, float(err_bound), int(bound_mode), float(base_ratio), float(q),
-                                   int(levels), int(cbl2w), int(cbl2h), int(tile), _p(out), cap, C.byref(n), None)
+                                   int(levels), int(cbl2w), int(cbl2h), int(tile), int(trunc), _p(out), cap,
+                                   C.byref(n), None)
     return rc, (out[: n.value].tobytes() if rc == OK else None), n.value
 
 
@@ -290,6 +298,32 @@ def spiht_decode(sec, ny, nx, levels, tile, n_s):
     neg = np.zeros((ny, nx), np.uint8)
     rc = lib().ebcc_ref_spiht_decode(_p(buf), len(sec), ny, nx, levels, tile, n_s, _p(m), _p(neg))
     return rc, m, neg
+
+
+def spiht_encode_cut(q, neg, levels, tile, n_s, t):
+    """Residual section of q/neg cut at position t of the embedded sequence
+    (tiles' codes ordered by plane, then tile), where lo < t <= hi with lo,
+    hi the sequence's bits through plane n_s + 1 and through plane n_s.
+    Returns (section bytes, or None when t is outside (lo, hi]; (lo, hi))."""
+    q = np.ascontiguousarray(q, np.uint32)
+    neg = np.ascontiguousarray(neg, np.uint8)
+    ny, nx = q.shape
+    cap = 16 * q.size + 4096
+    out = np.zeros(cap, np.uint8)
+    span = np.zeros(2, np.int64)
+    n = lib().ebcc_ref_spiht_encode_cut(_p(q), _p(neg), ny, nx, levels, tile, n_s, int(t), _p(out), cap, _p(span))
+    return (out[:n].tobytes() if n >= 0 else None), (int(span[0]), int(span[1]))
+
+
+def spiht_decode_cut(sec, ny, nx, levels, tile, n_s):
+    """Decode a byte-cut residual section: (rc, magnitudes, signs, lowest
+    known plane per coefficient)."""
+    buf = np.frombuffer(bytes(sec) + b"\0", np.uint8).copy()
+    m = np.zeros((ny, nx), np.uint32)
+    neg = np.zeros((ny, nx), np.uint8)
+    pk = np.zeros((ny, nx), np.int8)
+    rc = lib().ebcc_ref_spiht_decode_cut(_p(buf), len(sec), ny, nx, levels, tile, n_s, _p(m), _p(neg), _p(pk))
+    return rc, m, neg, pk
 
 
 def checksum(b):
