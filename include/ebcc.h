@@ -66,10 +66,15 @@ typedef struct {
   uint32_t cblk_log2w;    /* code-block width  = 2^cblk_log2w, 2..6 (default 5) */
   uint32_t cblk_log2h;    /* code-block height = 2^cblk_log2h, 2..6 (default 5); w*h <= 4096 */
   uint32_t spiht_tile;    /* SPIHT tile side in coarsest-LL roots, 1..64 (default 1) */
+  uint32_t trunc;         /* residual truncation (Algorithm 1's second binary search): 0 = at the
+                             end of a bit-plane (default); 1 = at a byte position of the tiles'
+                             codes read as one embedded sequence (plane by plane, the sorting
+                             passes of every tile before their refinement passes), searched
+                             within the last plane the plane search keeps */
 } ebcc_params;
 
 /* Fill p with the defaults: range-relative 1% bound, r = 30, 5 levels,
- * 32x32 code-blocks, one-root SPIHT tiles, q = 0. */
+ * 32x32 code-blocks, one-root SPIHT tiles, q = 0, truncation at plane ends. */
 void ebcc_params_default(ebcc_params* p);
 
 /* Largest stream ebcc_compress can produce for an ny x nx field (a coded

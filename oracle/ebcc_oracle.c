@@ -1082,8 +1082,8 @@ static void resid_section_write(const scode_t* sc, int n_s, uint8_t* out) {
  * passes of the tiles before the cut tile J and the first lJ bits of J's
  * code, or (kind 1) every sorting pass, the refinement passes of the tiles
  * before J and the first lJ bits of J's code.  Each tile's code is then
- * still a prefix of itself.  Section: u32 J | kind << 31, u32 lJ, then the
- * tile table and payloads as above.
+ * still a prefix of itself.  Section: the tile table and payloads as above,
+ * then a trailer u32 J | kind << 31, u32 lJ.
  * Bits of tile t's code through plane n, and before plane n's refinement
  * pass (0 if the tile has no plane >= n). */
 static long tile_bits(const scode_t* sc, long t, int n) { return sc->ntop[t] >= n ? sc->pend[t][n] : 0; }
@@ -1113,8 +1113,6 @@ static long resid_section_size_bt(const scode_t* sc, int n_s, int kind, long J, 
   return sz;
 }
 static void resid_section_write_bt(const scode_t* sc, int n_s, int kind, long J, long lJ, uint8_t* out) {
-  put_u32(out, (uint32_t)J | ((uint32_t)kind << 31)); put_u32(out + 4, (uint32_t)lJ);
-  out += 8;
   uint8_t* pay = out + 4 * sc->ntiles;
   for (long t = 0; t < sc->ntiles; t++) {
     long bits = cut_tile_bits(sc, n_s, kind, J, lJ, t), by = (bits + 7) >> 3;
@@ -1124,6 +1122,7 @@ static void resid_section_write_bt(const scode_t* sc, int n_s, int kind, long J,
     if (bits & 7) pay[by - 1] &= (uint8_t)(0xFF << (8 - (bits & 7)));
     pay += by;
   }
+  put_u32(pay, (uint32_t)J | ((uint32_t)kind << 31)); put_u32(pay + 4, (uint32_t)lJ);
 }
 /* Decode a residual section: magnitudes m (known bits), signs, and the
  * lowest known plane of each significant coefficient.  bt: the section is
@@ -1133,11 +1132,11 @@ static int resid_section_decode(const sgeom_t* g, const uint8_t* in, long len, i
   long nt = g->tiles_y * g->tiles_x;
   long J = nt, lJ = 0;
   int kind = 1;
-  if (bt) {
+  if (bt) {   /* the trailer */
     if (len < 8) return REF_ECORRUPT;
-    J = get_u32(in) & 0x7FFFFFFF; kind = (int)(get_u32(in) >> 31); lJ = get_u32(in + 4);
+    len -= 8;
+    J = get_u32(in + len) & 0x7FFFFFFF; kind = (int)(get_u32(in + len) >> 31); lJ = get_u32(in + len + 4);
     if (J >= nt) return REF_ECORRUPT;
-    in += 8; len -= 8;
   }
   if (len < 4 * nt) return REF_ECORRUPT;
   long off = 4 * nt;

@@ -450,12 +450,18 @@ __global__ __launch_bounds__(256) void k_put_tiles(const FieldDev* __restrict__ 
     const FieldDev& f = F[tiles[t].field];
     if (!f.active || f.rb == 0) continue;
     put32(f.out + kHdr + f.bb + 4 * (size_t)(t - f.tile0), tent[t]);
+    if (f.bt && t == f.tile0) {   // a byte-cut residual ends with its cut
+      uint8_t* tr = f.out + kHdr + f.bb + f.rb - 8;
+      put32(tr, (uint32_t)f.cut_tile | ((uint32_t)f.cut_kind << 31));
+      put32(tr + 4, f.cut_bits);
+    }
   }
 }
 __global__ __launch_bounds__(256) void k_gather_tiles(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
                                                       const uint8_t* __restrict__ slots,
                                                       const int64_t* __restrict__ slot_off,
                                                       const uint32_t* __restrict__ tlen,
+                                                      const uint32_t* __restrict__ tbits,
                                                       const int64_t* __restrict__ off, int nt) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int t = blockIdx.x * 4 + wave; t < nt; t += gridDim.x * 4) {
@@ -465,7 +471,13 @@ __global__ __launch_bounds__(256) void k_gather_tiles(const FieldDev* __restrict
     int n = (int)((int64_t)tlen[t] < cap ? (int64_t)tlen[t] : cap);
     const uint8_t* src = slots + slot_off[t];
     uint8_t* dst = f.out + kHdr + f.bb + 4 * (size_t)f.ntiles + off[t];
-    for (int j = lane; j < n; j += 64) dst[j] = src[j];
+    // a code cut inside a byte keeps that byte's leading bits only
+    const int tail = f.bt ? (int)(tbits[t] & 7u) : 0;
+    for (int j = lane; j < n; j += 64) {
+      uint8_t v = src[j];
+      if (tail && j == n - 1) v &= (uint8_t)(0xFFu << (8 - tail));
+      dst[j] = v;
+    }
   }
 }
 
@@ -522,6 +534,7 @@ __global__ void k_header(const FieldDev* __restrict__ F, int nfields) {
   o[30] = (uint8_t)(int8_t)(mode == MODE_CODED && f.rb ? f.nmax : -1);
   o[31] = (uint8_t)(int8_t)(mode == MODE_CODED && f.rb ? f.ns : 0);
   o[32] = (uint8_t)f.T; o[33] = (uint8_t)(f.T >> 8);
+  o[34] = (uint8_t)(mode == MODE_CODED && f.rb && f.bt ? 1 : 0);   // residual cut at a byte position
   put32(o + 36, f.bb);
   put32(o + 40, f.rb);
   put32(o + 44, f.u32s[1]);
@@ -547,7 +560,7 @@ __global__ void k_check_tables(const FieldDev* __restrict__ F, int nfields) {
   if (i >= nfields || !F[i].active) return;
   const FieldDev& f = F[i];
   if (f.totals[0] != (int64_t)f.bb - 4 * (int64_t)f.nblk) f.flags[1] = 1;
-  if (f.rb && f.totals[1] != (int64_t)f.rb - 4 * (int64_t)f.ntiles) f.flags[1] = 1;
+  if (f.rb && f.totals[1] != (int64_t)f.rb - 4 * (int64_t)f.ntiles - (f.bt ? 8 : 0)) f.flags[1] = 1;
 }
 
 
@@ -902,6 +915,7 @@ static int check_params(size_t ny, size_t nx, const ebcc_params* p, double err) 
     return fail(EBCC_EINVAL, "code-block size out of range");
   if (p->spiht_tile < 1 || p->spiht_tile > 64) return fail(EBCC_EINVAL, "spiht_tile out of range");
   if (!(p->q >= 0.0 && p->q <= 1.0)) return fail(EBCC_EINVAL, "q must be 0 (fixed base ratio) or in (0, 1]");
+  if (p->trunc > 1) return fail(EBCC_EINVAL, "trunc must be 0 (bit-plane ends) or 1 (byte positions)");
   return EBCC_OK;
 }
 
@@ -939,6 +953,8 @@ struct Call {
   int64_t *D, *boff, *toff, *collect;
   uint64_t *keys, *lists;
   uint32_t *tail, *tlen, *tent, *bent;
+  uint32_t *tcut, *tbits;   // byte-cut residuals: per tile bit counts around plane ns, final code bits
+  bool want_cpos = false;   // compression with byte-cut residuals: every coded field gets a cpos plane
   int* misfit;
   Blk* d_blk_own;
   TileD* d_tiles_own;
@@ -1057,6 +1073,7 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
     size_t nbuf = coded[i] ? N : 0;
     for (int b = BUF_COEF; b <= BUF_CHAT; b++) f.buf[b] = cv.take<float>(nbuf);
     f.qr = cv.take<uint32_t>(nbuf);
+    f.cpos = (c.want_cpos && nbuf) ? cv.take<uint32_t>(nbuf) : nullptr;
     f.sub = cv.take<uint32_t>(nbuf);
     f.maxd = cv.take<uint32_t>(nbuf);
     f.maxl = cv.take<uint32_t>(nbuf);
@@ -1076,6 +1093,8 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
   c.cw = cv.take<uint8_t>(nb * (size_t)kCwCap);
   c.tlen = cv.take<uint32_t>(nt); c.tent = cv.take<uint32_t>(nt); c.toff = cv.take<int64_t>(nt);
   c.misfit = cv.take<int>(nt);
+  c.tcut = cv.take<uint32_t>(3 * nt);
+  c.tbits = cv.take<uint32_t>(nt);
   c.collect = cv.take<int64_t>(8 * (size_t)c.nf);
   // candidates per field and search round: "all planes" and the nodes of
   // spec_depth levels of the bisection tree
@@ -1225,6 +1244,131 @@ static size_t compress_need(Call& c, const std::vector<int>& coded) {
   return layout_call(c, nullptr, coded);
 }
 
+// Algorithm 1's second binary search at byte granularity, for the fields
+// sp marks (their residual planes n_max .. ns are SPIHT coded, with cpos and
+// the tiles' bit counts tcut): the tiles' codes are read as one embedded
+// sequence (plane by plane; sorting passes of every tile, then refinement
+// passes), and the search bisects a position t = 8 b (bits, b integer; the
+// end of plane ns when 8 b passes it) between the end of plane ns + 1,
+// which misses the bound, and the end of plane ns, which meets it.  Every
+// field advances in lockstep, spec_depth levels of its bisection per round
+// (one launch sequence and one read-back); a candidate's coefficients come
+// from spiht_cut_recon, its check from the inverse DWT's epilogue.  The
+// chosen cut goes to each field's table entry and the tiles' final lengths
+// to tlen/tent/tbits.
+struct CutTables {
+  std::vector<uint32_t> lo, rs, hi;        // per tile of the field: bits through ns + 1, before ns's refinement, through ns
+  std::vector<int64_t> ps, pr;             // inclusive prefix sums of the sorting / refinement lengths of plane ns
+  int64_t vlo = 0, vhi = 0;
+  // position t (vlo < t <= vhi) of the embedded sequence -> the cut
+  void cut(int64_t t, int* kind, int* J, uint32_t* lJ) const {
+    int64_t u = t - vlo;
+    const int64_t stot = ps.empty() ? 0 : ps.back();
+    const std::vector<int64_t>& pre = u <= stot ? ps : pr;
+    const std::vector<uint32_t>& base = u <= stot ? lo : rs;
+    if (u > stot) u -= stot;
+    const int j = (int)(std::lower_bound(pre.begin(), pre.end(), u) - pre.begin());
+    const int jj = j < (int)pre.size() ? j : (int)pre.size() - 1;
+    *kind = stot >= t - vlo ? 0 : 1;
+    *J = jj;
+    *lJ = (uint32_t)((int64_t)base[jj] + u - (jj ? pre[jj - 1] : 0));
+  }
+};
+
+static int byte_search(Call& c, const std::vector<int>& sp, std::vector<int>& checks) {
+  const int nf = c.nf;
+  hipStream_t st = c.st;
+  std::vector<uint32_t> tc(3 * (size_t)std::max(c.ntiles, 1));
+  if (int rc = c.fetch(tc.data(), c.tcut, 3 * (size_t)c.ntiles)) return rc;
+  std::vector<CutTables> ct(nf);
+  std::vector<int64_t> blo(nf, 0), bhi(nf, 0);
+  std::vector<int> on(nf, 0);
+  int max_tiles = 0;
+  for (int i = 0; i < nf; i++) {
+    if (!sp[i] || !c.Fh[i].bt) continue;
+    const FieldDev& f = c.Fh[i];
+    CutTables& T = ct[i];
+    int64_t s = 0, r = 0;
+    for (int j = 0; j < f.ntiles; j++) {
+      const uint32_t* e = &tc[3 * (size_t)(f.tile0 + j)];
+      T.lo.push_back(e[0]); T.rs.push_back(e[1]); T.hi.push_back(e[2]);
+      T.vlo += e[0]; T.vhi += e[2];
+      s += (int64_t)e[1] - e[0]; r += (int64_t)e[2] - e[1];
+      T.ps.push_back(s); T.pr.push_back(r);
+    }
+    blo[i] = T.vlo / 8; bhi[i] = (T.vhi + 7) / 8;
+    on[i] = 1;
+    max_tiles = std::max(max_tiles, f.ntiles);
+  }
+  auto at = [&](int i, int64_t b) { return std::min<int64_t>(8 * b, ct[i].vhi); };
+  struct Cand { int field; int64_t b; int slot; };
+  std::vector<FieldDev> Fch;
+  for (int round = 0; round < 64; round++) {
+    std::vector<Cand> cands;
+    std::vector<int> nslot(nf, 0);
+    std::function<void(int, int64_t, int64_t, int)> tree = [&](int i, int64_t l, int64_t h, int depth) {
+      if (depth == 0 || h - l <= 1) return;
+      const int64_t m = (l + h) >> 1;
+      cands.push_back(Cand{i, m, nslot[i]++});
+      tree(i, l, m, depth - 1);
+      tree(i, m, h, depth - 1);
+    };
+    for (int i = 0; i < nf; i++)
+      if (on[i]) tree(i, blo[i], bhi[i], c.spec_depth);
+    if (cands.empty()) break;
+    const int nc = (int)cands.size();
+    Fch.resize(nc);
+    size_t cmax = 0;
+    for (int j = 0; j < nc; j++) {
+      const Cand& q = cands[j];
+      FieldDev f = c.Fh[q.field];
+      f.active = 1;
+      ct[q.field].cut(at(q.field, q.b), &f.cut_kind, &f.cut_tile, &f.cut_bits);
+      f.flags = c.cand_flags + 8 * j;
+      if (q.slot > 0) {
+        size_t N = (size_t)f.ny * f.nx;
+        f.buf[BUF_CHAT] = c.cand_buf[q.field] + (size_t)(2 * (q.slot - 1)) * N;
+        f.buf[BUF_TMP] = c.cand_buf[q.field] + (size_t)(2 * (q.slot - 1) + 1) * N;
+      }
+      Fch[j] = f;
+      cmax = std::max(cmax, (size_t)f.ny * f.nx);
+    }
+    if (int rc = c.stage(c.Fc, Fch.data(), sizeof(FieldDev) * nc)) return rc;
+    k_zero_slot<<<(nc + 63) / 64, 64, 0, st>>>(c.Fc, nc, 0);
+    spiht_cut_recon(c.Fc, nc, max_tiles, c.d_tiles, c.tcut, st);
+    dwt_inverse(c.Fc, Fch.data(), nc, BUF_CHAT, BUF_CHAT, EPI_CHECK, st);
+    HIPCHK(hipGetLastError());
+    std::vector<int> cf(8 * (size_t)nc);
+    if (int rc = c.fetch(cf.data(), c.cand_flags, 8 * (size_t)nc)) return rc;
+    std::vector<std::map<int64_t, bool>> res(nf);
+    for (int j = 0; j < nc; j++) {
+      res[cands[j].field][cands[j].b] = cf[8 * j] == 0;
+      checks[cands[j].field]++;
+    }
+    for (int i = 0; i < nf; i++) {
+      if (!on[i]) continue;
+      while (bhi[i] - blo[i] > 1) {
+        const int64_t m = (blo[i] + bhi[i]) >> 1;
+        auto it = res[i].find(m);
+        if (it == res[i].end()) break;
+        if (it->second) bhi[i] = m; else blo[i] = m;
+      }
+      if (bhi[i] - blo[i] <= 1) on[i] = 0;
+    }
+  }
+  std::vector<int> btf(nf, 0);
+  for (int i = 0; i < nf; i++) {
+    if (!sp[i] || !c.Fh[i].bt) continue;
+    FieldDev& f = c.Fh[i];
+    ct[i].cut(at(i, bhi[i]), &f.cut_kind, &f.cut_tile, &f.cut_bits);
+    btf[i] = 1;
+  }
+  if (int rc = c.set_active(btf)) return rc;
+  spiht_cut_tiles(c.F, c.d_tiles, c.ntiles, c.tcut, c.tlen, c.tent, c.tbits, st);
+  HIPCHK(hipGetLastError());
+  return c.set_active(sp);
+}
+
 // Compress nf fields; stream i goes to out + off[i] (compacted in field
 // order); lens[i] receives its length.  On ENOSPC *need holds the total.
 // With fstat, a field whose input is not finite gets EBCC_EINVAL there and
@@ -1282,6 +1426,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     f.nb = c.plans[i]->nb;
   }
   std::vector<int> coded(nf, 1);
+  c.want_cpos = pp->trunc != 0;
   size_t need_ws = compress_need(c, coded);
   char* base;
   if (fixed_ws) {
@@ -1566,23 +1711,27 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
       if (state[i] != FOUND) resid[i] = 0;
     }
     if (anysp) {
+      for (int i = 0; i < nf; i++) c.Fh[i].bt = (pp->trunc && sp[i]) ? 1 : 0;
       if ((rc = c.set_active(sp))) return rc;
       spiht_maxima(c.F, c.Fh.data(), nf, st);
       if (c.forced_global) {
-        spiht_encode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, st);
+        spiht_encode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut, st);
       } else {
         // the classes run concurrently: global and huge tiles on the second
         // stream, big tiles on the third, small ones on the caller's
         const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
         hipStream_t sa = c.aux_or(c.ws->aux);
         if ((rc = c.fork())) return rc;
-        spiht_encode(c.F, c.d_tiles, t2, c.ncls[2], c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, sa);
-        spiht_encode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, sa);
-        spiht_encode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit,
-                         c.aux_or(c.ws->aux2));
-        spiht_encode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.slots, c.d_slot_off, c.tlen, c.tent, c.misfit, st);
+        spiht_encode(c.F, c.d_tiles, t2, c.ncls[2], c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut, sa);
+        spiht_encode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut,
+                         c.misfit, sa);
+        spiht_encode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut,
+                         c.misfit, c.aux_or(c.ws->aux2));
+        spiht_encode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut,
+                         c.misfit, st);
         if ((rc = c.join())) return rc;
       }
+      if (pp->trunc && (rc = byte_search(c, sp, checks))) return rc;
       k_scan<<<nf, 1024, 0, st>>>(c.F, c.tlen, 1, 0, 0xFFFFFFFFu, c.toff);
     }
     prof.mark(S_SPIHT);
@@ -1596,7 +1745,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
       if (!act[i]) continue;
       FieldDev& f = c.Fh[i];
       f.bb = (uint32_t)(4 * (int64_t)f.nblk + col[8 * i + 4]);
-      f.rb = resid[i] ? (uint32_t)(4 * (int64_t)f.ntiles + col[8 * i + 5]) : 0u;
+      f.rb = resid[i] ? (uint32_t)(4 * (int64_t)f.ntiles + col[8 * i + 5] + (f.bt ? 8 : 0)) : 0u;
     }
     // ---- fallback (end of Algorithm 1): the base alone at its own ratio
     // when that stream is smaller ----
@@ -1673,7 +1822,8 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     k_put_blocks<<<grid_for(c.nblk), 256, 0, st>>>(c.F, c.d_blk, c.bent, c.nblk);
     k_gather_cw<<<std::max(1, (c.nblk + 3) / 4), 256, 0, st>>>(c.F, c.d_blk, c.cw, c.kb, c.len, c.bpt, c.tail, c.boff, c.nblk);
     k_put_tiles<<<grid_for(c.ntiles), 256, 0, st>>>(c.F, c.d_tiles, c.tent, c.ntiles);
-    k_gather_tiles<<<std::max(1, (c.ntiles + 3) / 4), 256, 0, st>>>(c.F, c.d_tiles, c.slots, c.d_slot_off, c.tlen, c.toff, c.ntiles);
+    k_gather_tiles<<<std::max(1, (c.ntiles + 3) / 4), 256, 0, st>>>(c.F, c.d_tiles, c.slots, c.d_slot_off, c.tlen,
+                                                                     c.tbits, c.toff, c.ntiles);
   }
   std::vector<int> rawm(nf, 0);
   bool anyraw = false;
@@ -1731,8 +1881,8 @@ static size_t decompress_need(Call& c, const std::vector<int>& coded) {
   build_items(c, coded);
   c.forced_global = spiht_forced_global();
   c.need_lists = false;
-  for (int i = 0; i < c.nf; i++)
-    if (coded[i]) c.need_lists |= c.forced_global || c.plans[i]->ncls[2] > 0;
+  for (int i = 0; i < c.nf; i++)   // (the cut tile of a byte-cut residual decodes with global-memory lists)
+    if (coded[i]) c.need_lists |= c.forced_global || c.plans[i]->ncls[2] > 0 || c.Fh[i].bt;
   return layout_call(c, nullptr, coded);
 }
 
@@ -1838,9 +1988,10 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
         continue;
       }
       f.L = L; f.T = T;
+      f.bt = f.rb ? (h[34] & 1) : 0;
       if ((rc = get_plan(f.ny, f.nx, L, w2, h2, T, &c.plans[i]))) return rc;
       if ((int64_t)f.bb < 4 * (int64_t)c.plans[i]->nblk) { bad(i, EBCC_ECORRUPT, "base section shorter than its table"); continue; }
-      if (f.rb && (int64_t)f.rb < 4 * (int64_t)c.plans[i]->ntiles) {
+      if (f.rb && (int64_t)f.rb < 4 * (int64_t)c.plans[i]->ntiles + (f.bt ? 8 : 0)) {
         bad(i, EBCC_ECORRUPT, "residual section shorter than its table");
         continue;
       }
@@ -1920,6 +2071,9 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
       k_fill<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, BUF_CHAT, 0.0f);
       hipStream_t sa = c.ws->aux;
       if ((rc = c.fork())) return rc;
+      bool anybt = false;
+      for (int i = 0; i < nf; i++) anybt |= cr[i] && c.Fh[i].bt;
+      if (anybt) spiht_decode_cut(c.F, nf, c.d_tiles, c.toff, c.lists, sa);
       if (c.forced_global) {
         spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, sa);
       } else {
@@ -2023,6 +2177,7 @@ void ebcc_params_default(ebcc_params* p) {
   p->cblk_log2w = 5;
   p->cblk_log2h = 5;
   p->spiht_tile = 1;
+  p->trunc = 0;
 }
 
 size_t ebcc_compress_bound(size_t ny, size_t nx) { return (size_t)kHdr + 4 * ny * nx; }
@@ -2283,6 +2438,7 @@ static size_t compress_ws(const std::vector<size_t>& ny, const std::vector<size_
     if (host_plan(f.ny, f.nx, f.L, p->cblk_log2w, p->cblk_log2h, (int)p->spiht_tile, &c.plans[i])) return 0;
   }
   std::vector<int> coded(c.nf, 1);
+  c.want_cpos = p->trunc != 0;
   return ws_alloc(compress_need(c, coded));
 }
 
@@ -2308,6 +2464,7 @@ static size_t decompress_ws(const std::vector<int>& call, const uint8_t* hdrs, c
     if (L != levels_eff(f.ny, f.nx, L) || w2 < 2 || w2 > 6 || h2 < 2 || h2 > 6 || T < 1 || T > 64) continue;
     if (host_plan(f.ny, f.nx, L, w2, h2, T, &c.plans[m])) return 0;
     c.cbw = 1 << w2; c.cbh = 1 << h2;
+    f.bt = h[34] & 1;
     coded[m] = 1;
   }
   return ws_alloc(decompress_need(c, coded));

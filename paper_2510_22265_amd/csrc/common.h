@@ -86,7 +86,36 @@ struct FieldDev {
   int bound_mode, mode, nmax, cbl, T;
   uint32_t bb, rb;     // base and residual section bytes (header fields)
   int64_t len;         // stream length
+  // Byte-granular truncation of the residual (Algorithm 1's second binary
+  // search over one embedded code, the tiles' codes read plane by plane,
+  // sorting passes of every tile before refinement passes): bt set; the cut
+  // of plane ns is in the sorting (kind 0) or refinement (kind 1) passes, in
+  // tile cut_tile (field-local index) after cut_bits bits of its code.
+  // cpos[p] (compression): stream position, within its tile's code, of the
+  // bit of plane ns that coefficient p needs (its sign bit when it becomes
+  // significant in plane ns, its refinement bit when it was significant
+  // before); null unless bt.
+  uint32_t* cpos;
+  int bt, cut_kind, cut_tile;
+  uint32_t cut_bits;
 };
+
+// Byte-cut residual: code length (bits) of tile tl (field-local) of a cut
+// field, from the tile's bit counts through plane ns + 1 (lo), before plane
+// ns's refinement pass (rs) and through plane ns (hi).
+__host__ __device__ __forceinline__ uint32_t cut_tile_bits(int kind, int J, uint32_t lJ, int tl, uint32_t lo,
+                                                           uint32_t rs, uint32_t hi) {
+  if (tl == J) return lJ;
+  if (kind == 0) return tl < J ? rs : lo;
+  return tl < J ? hi : rs;
+}
+// Decoding a tile of a cut field: the lowest plane it reaches and whether it
+// stops before that plane's refinement pass (the cut tile itself stops at
+// its bit count).
+__host__ __device__ __forceinline__ void cut_tile_mode(int kind, int J, int tl, int ns, int* nbot, int* sort_only) {
+  *nbot = (kind == 0 && tl > J) ? ns + 1 : ns;
+  *sort_only = (kind == 0 && tl < J) || (kind == 1 && tl > J) || (kind == 0 && tl == J);
+}
 
 // Device kernels' launch wrappers (all asynchronous on `st`).
 // dwt.hip
@@ -155,13 +184,19 @@ void spiht_maxima(const FieldDev* F, const FieldDev* Fh, int nf, hipStream_t st)
 // Encode every tile for planes n_t .. F.ns into its slot of `slots`
 // (slot_off[t] ..); tlen[t] receives the byte length and tent[t] the tile
 // table entry.
+// tcut (byte-cut fields; may be null otherwise): per tile the bits through
+// plane ns + 1, before plane ns's refinement pass and through plane ns.
 void spiht_encode(const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint64_t* lists, uint8_t* slots,
-                  const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st);
+                  const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, uint32_t* tcut, hipStream_t st);
 // Decode residual sections (each field's starts at out + 48 + bb): writes the
 // dequantised significant coefficients into buf[BUF_CHAT] (zero elsewhere);
 // toff: payload offsets after each field's tile table.
 void spiht_decode(const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
                   uint64_t* lists, hipStream_t st);
+// The cut tile of every byte-cut field (one lane per field; the other
+// decoders skip it): decoded to its bit count.
+void spiht_decode_cut(const FieldDev* F, int nf, const TileD* tiles, const int64_t* toff, uint64_t* lists,
+                      hipStream_t st);
 // spihtwave.hip: one wavefront per tile with the tile in LDS, in three
 // capacity classes (coefficients of the tile's trees, and twice its parents,
 // must fit): small and big for the usual one-root tiles of 5 and 6 levels,
@@ -173,7 +208,19 @@ constexpr int kSpihtHuge = 12288;
 // Each SPIHT launch covers the tiles tix[0 .. ntix) of the call's tile array
 // (tiles are launched in capacity classes).
 void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint8_t* slots,
-                      const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit, hipStream_t st);
+                      const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, uint32_t* tcut, int* misfit,
+                      hipStream_t st);
+// Byte-cut candidates (Fc[0 .. ncand), each a field with its cut): the
+// residual coefficients the decoder of that cut would reconstruct, into each
+// candidate's buf[BUF_CHAT], from the field's magnitudes (qr), cpos and the
+// tiles' tcut; max_tiles: the most tiles of a candidate's field.
+void spiht_cut_recon(const FieldDev* Fc, int ncand, int max_tiles, const TileD* tiles, const uint32_t* tcut,
+                     hipStream_t st);
+// Final tile lengths of the byte-cut fields: tbits[t] = the tile's code bits,
+// tlen[t] its bytes and tent[t] its table entry (tent holds the encoder's
+// entry on input, for the tile's top plane).
+void spiht_cut_tiles(const FieldDev* F, const TileD* tiles, int nt, const uint32_t* tcut, uint32_t* tlen,
+                     uint32_t* tent, uint32_t* tbits, hipStream_t st);
 void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
                       int* misfit, hipStream_t st);
 

@@ -156,6 +156,7 @@ struct BitW {
       acc = 0; n = 0;
     }
   }
+  __device__ int64_t bits() const { return 8 * pos + n; }
   __device__ void flush() {
     if (n) {
       if (pos < cap) out[pos] = (uint8_t)(acc << (8 - n));
@@ -171,7 +172,8 @@ __global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restri
                                                         uint64_t* __restrict__ lists,
                                                         uint8_t* __restrict__ slots,
                                                         const int64_t* __restrict__ slot_off,
-                                                        uint32_t* __restrict__ tlen, uint32_t* __restrict__ tent) {
+                                                        uint32_t* __restrict__ tlen, uint32_t* __restrict__ tent,
+                                                        uint32_t* __restrict__ tcut) {
   const int q = blockIdx.x * LANES + threadIdx.x;
   if (q >= ntix) return;
   const int t = tix[q];
@@ -181,6 +183,8 @@ __global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restri
   const Band* B = f.bands;
   const int nx = f.nx, L = f.L, n_s = f.ns;
   const uint32_t *qr = f.qr, *sub = f.sub, *maxd = f.maxd, *maxl = f.maxl;
+  // byte-cut fields: positions of the last plane's bits, bit counts around it
+  uint32_t* const cpos = f.cpos;
   uint32_t mx = 0;
   for (int i = td.i0; i < td.i1; i++)
     for (int j = td.j0; j < td.j1; j++) {
@@ -188,7 +192,11 @@ __global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restri
       mx = s > mx ? s : mx;
     }
   int ntop = mx ? 31 - __builtin_clz(mx) : -1;
-  if (ntop < n_s) { tlen[t] = 0; tent[t] = 0; return; }
+  if (ntop < n_s) {
+    tlen[t] = 0; tent[t] = 0;
+    if (cpos) { tcut[3 * t] = 0; tcut[3 * t + 1] = 0; tcut[3 * t + 2] = 0; }
+    return;
+  }
   int nc = td.ncoef;
   uint64_t* lip = lists + 4 * td.off;
   uint64_t* lsp = lip + nc;
@@ -206,6 +214,8 @@ __global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restri
   for (int pl = ntop; pl >= n_s; pl--) {
     uint32_t thr = 1u << pl;
     int lsp_prev = nlsp;
+    const bool last = cpos && pl == n_s;
+    if (last) tcut[3 * t] = (uint32_t)w.bits();
     for (int k = 0; k < nlip; k++) {
       uint64_t e = lip[k];
       if (!(e & kAlive)) continue;
@@ -213,6 +223,7 @@ __global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restri
       int s = (v & 0x7FFFFFu) >= thr;
       w.put(s);
       if (s) {
+        if (last) cpos[nd_pos(B, nx, e)] = (uint32_t)w.bits();   // its sign bit
         w.put((int)(v >> 31));
         lsp[nlsp++] = e & ~kAlive;
         lip[k] = e & ~kAlive;
@@ -233,6 +244,7 @@ __global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restri
           int sc = (v & 0x7FFFFFu) >= thr;
           w.put(sc);
           if (sc) {
+            if (last) cpos[nd_pos(B, nx, o[c])] = (uint32_t)w.bits();
             w.put((int)(v >> 31));
             lsp[nlsp++] = o[c];
           } else {
@@ -249,30 +261,36 @@ __global__ __launch_bounds__(LANES) void k_spiht_encode(const FieldDev* __restri
         lis[k] = e & ~kAlive;
       }
     }
+    if (last) tcut[3 * t + 1] = (uint32_t)w.bits();
     for (int k = 0; k < lsp_prev; k++) {
       uint32_t v = qr[nd_pos(B, nx, lsp[k])];
+      if (last) cpos[nd_pos(B, nx, lsp[k])] = (uint32_t)w.bits();
       w.put((int)((v >> pl) & 1u));
     }
   }
+  if (cpos) tcut[3 * t + 2] = (uint32_t)w.bits();
   w.flush();
   tlen[t] = (uint32_t)w.pos;
   tent[t] = (uint32_t)w.pos | ((uint32_t)(ntop + 1) << 26);
 }
 
 void spiht_encode(const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint64_t* lists, uint8_t* slots,
-                  const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, hipStream_t st) {
+                  const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, uint32_t* tcut, hipStream_t st) {
   if (ntix <= 0) return;
   int ln = pick_tile_lanes(ntix);
 #define ENC_L(LN) k_spiht_encode<LN><<<(ntix + LN - 1) / LN, LN, 0, st>>>(F, tiles, tix, ntix, lists, slots, slot_off, \
-                                                                      tlen, tent)
+                                                                      tlen, tent, tcut)
   if (ln == 1) ENC_L(1); else if (ln == 4) ENC_L(4); else if (ln == 16) ENC_L(16); else ENC_L(64);
 #undef ENC_L
 }
 
+// Bit reader; a read at or past `limit` (the cut of a byte-cut tile) returns
+// -1 and decoding of the tile stops there.
 struct BitR {
   const uint8_t* in;
-  int64_t len, pos;
+  int64_t len, pos, limit;
   __device__ int get() {
+    if (pos >= limit) return -1;
     int64_t by = pos >> 3;
     int b = (by < len) ? (in[by] >> (7 - (pos & 7))) & 1 : 0;
     pos++;
@@ -281,15 +299,29 @@ struct BitR {
 };
 
 // sec: residual section (tile table then payloads); toff[t]: offset of tile
-// t's payload after the table.  mags: N-sized scratch (magnitude | sign << 31).
-template <int LANES>
+// t's payload after the table.  mags: N-sized scratch (magnitude | lowest
+// known plane << 24 | sign << 31).  CUT: one lane per field, decoding the
+// cut tile of a byte-cut field (tix unused); otherwise one lane per listed
+// tile, the cut tiles skipped.
+template <int LANES, bool CUT>
 __global__ __launch_bounds__(LANES) void k_spiht_decode(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
                                                         const int* __restrict__ tix, int ntix,
                                                         const int64_t* __restrict__ toff,
                                                         uint64_t* __restrict__ lists) {
   const int q = blockIdx.x * LANES + threadIdx.x;
   if (q >= ntix) return;
-  const int t = tix[q];
+  int t;
+  if (CUT) {
+    const FieldDev& ff = F[q];
+    if (!ff.active || ff.rb == 0 || !ff.bt) return;
+    const uint8_t* tr = ff.out + kHdr + ff.bb + ff.rb - 8;
+    const uint32_t w0 = (uint32_t)tr[0] | ((uint32_t)tr[1] << 8) | ((uint32_t)tr[2] << 16) | ((uint32_t)tr[3] << 24);
+    const uint32_t J = w0 & 0x7FFFFFFFu;
+    if (J >= (uint32_t)ff.ntiles) { atomicOr(&ff.flags[1], 1); return; }   // names no tile of the field
+    t = ff.tile0 + (int)J;
+  } else {
+    t = tix[q];
+  }
   TileD td = tiles[t];
   const FieldDev& f = F[td.field];
   if (!f.active || f.rb == 0) return;
@@ -307,8 +339,25 @@ __global__ __launch_bounds__(LANES) void k_spiht_decode(const FieldDev* __restri
   int ntop = (int)(ent >> 26) - 1;
   int64_t pbase = 4 * (int64_t)f.ntiles;      // payloads follow the tile table
   int64_t o0 = toff[t];
-  if (o0 < 0 || pbase + o0 + len > sec_len || (ntop >= kQBits)) { atomicOr(flag, 1); return; }
-  if (ntop < n_s) return;
+  // byte-cut fields: the trailer names the cut tile J (its code ends after
+  // lJ bits) and where the other tiles stop
+  int n_bot = n_s, sort_only = 0;
+  int64_t pay_end = sec_len, limit = 8 * len;
+  if (f.bt) {
+    pay_end = sec_len - 8;
+    const uint8_t* tr = sec + pay_end;
+    const uint32_t w0 = (uint32_t)tr[0] | ((uint32_t)tr[1] << 8) | ((uint32_t)tr[2] << 16) | ((uint32_t)tr[3] << 24);
+    const uint32_t lJ = (uint32_t)tr[4] | ((uint32_t)tr[5] << 8) | ((uint32_t)tr[6] << 16) | ((uint32_t)tr[7] << 24);
+    const int J = (int)(w0 & 0x7FFFFFFFu), kind = (int)(w0 >> 31);
+    if (!CUT && tl == J) return;
+    cut_tile_mode(kind, J, tl, n_s, &n_bot, &sort_only);
+    if (tl == J) {
+      if ((int64_t)lJ > 8 * len || (int64_t)lJ <= 8 * (len - 1)) { atomicOr(flag, 1); return; }
+      limit = lJ;
+    }
+  }
+  if (o0 < 0 || pbase + o0 + len > pay_end || (ntop >= kQBits)) { atomicOr(flag, 1); return; }
+  if (ntop < n_bot) return;
   int nc = td.ncoef;
   uint64_t* lip = lists + 4 * td.off;
   uint64_t* lsp = lip + nc;
@@ -321,16 +370,20 @@ __global__ __launch_bounds__(LANES) void k_spiht_decode(const FieldDev* __restri
       lip[nlip++] = n | kAlive;
       if (offspring(B, L, 0, i, j, o) > 0) lis[nlis++] = n | kAlive;
     }
-  BitR r{sec + pbase + o0, len, 0};
-  for (int pl = ntop; pl >= n_s; pl--) {
+  BitR r{sec + pbase + o0, len, 0, limit};
+  constexpr uint32_t kPkMask = 0x1Fu << 24;
+  for (int pl = ntop; pl >= n_bot; pl--) {
     uint32_t thr = 1u << pl;
     int lsp_prev = nlsp;
     for (int k = 0; k < nlip; k++) {
       uint64_t e = lip[k];
       if (!(e & kAlive)) continue;
-      if (r.get()) {
-        int sg = r.get();
-        mags[nd_pos(B, nx, e)] = thr | ((uint32_t)sg << 31);
+      const int s = r.get();
+      if (s < 0) goto done;
+      if (s) {
+        const int sg = r.get();
+        if (sg < 0) goto done;
+        mags[nd_pos(B, nx, e)] = thr | ((uint32_t)pl << 24) | ((uint32_t)sg << 31);
         lsp[nlsp++] = e & ~kAlive;
         lip[k] = e & ~kAlive;
       }
@@ -340,12 +393,17 @@ __global__ __launch_bounds__(LANES) void k_spiht_decode(const FieldDev* __restri
       if (!(e & kAlive)) continue;
       int band = nd_band(e), i = nd_i(e), j = nd_j(e);
       int no = offspring(B, L, band, i, j, o);
+      const int s = r.get();
+      if (s < 0) goto done;
       if (!(e & kTypeB)) {
-        if (!r.get()) continue;
+        if (!s) continue;
         for (int c = 0; c < no; c++) {
-          if (r.get()) {
-            int sg = r.get();
-            mags[nd_pos(B, nx, o[c])] = thr | ((uint32_t)sg << 31);
+          const int sc = r.get();
+          if (sc < 0) goto done;
+          if (sc) {
+            const int sg = r.get();
+            if (sg < 0) goto done;
+            mags[nd_pos(B, nx, o[c])] = thr | ((uint32_t)pl << 24) | ((uint32_t)sg << 31);
             lsp[nlsp++] = o[c];
           } else {
             lip[nlip++] = o[c] | kAlive;
@@ -354,21 +412,26 @@ __global__ __launch_bounds__(LANES) void k_spiht_decode(const FieldDev* __restri
         lis[k] = e & ~kAlive;
         if (no > 0 && child_level(B, L, band) >= 2) lis[nlis++] = (e & ~kAlive) | kTypeB | kAlive;
       } else {
-        if (!r.get()) continue;
+        if (!s) continue;
         for (int c = 0; c < no; c++) lis[nlis++] = o[c] | kAlive;
         lis[k] = e & ~kAlive;
       }
     }
+    if (pl == n_bot && sort_only) break;
     for (int k = 0; k < lsp_prev; k++) {
       int p = nd_pos(B, nx, lsp[k]);
-      if (r.get()) mags[p] |= thr;
+      const int b = r.get();
+      if (b < 0) goto done;
+      mags[p] = (mags[p] & ~kPkMask) | ((uint32_t)pl << 24) | (b ? thr : 0u);
     }
   }
+done:
   for (int k = 0; k < nlsp; k++) {
     int p = nd_pos(B, nx, lsp[k]);
     uint32_t v = mags[p];
     uint32_t m = v & 0x7FFFFFu;
-    float f = ldexpf((float)(2u * m + (1u << n_s)), e_r - 1);
+    const int pk = (int)((v >> 24) & 0x1Fu);
+    float f = ldexpf((float)(2u * m + (1u << pk)), e_r - 1);
     chat[p] = (v >> 31) ? -f : f;
   }
 }
@@ -377,9 +440,15 @@ void spiht_decode(const FieldDev* F, const TileD* tiles, const int* tix, int nti
                   uint64_t* lists, hipStream_t st) {
   if (ntix <= 0) return;
   int ln = pick_tile_lanes(ntix);
-#define DEC_L(LN) k_spiht_decode<LN><<<(ntix + LN - 1) / LN, LN, 0, st>>>(F, tiles, tix, ntix, toff, lists)
+#define DEC_L(LN) k_spiht_decode<LN, false><<<(ntix + LN - 1) / LN, LN, 0, st>>>(F, tiles, tix, ntix, toff, lists)
   if (ln == 1) DEC_L(1); else if (ln == 4) DEC_L(4); else if (ln == 16) DEC_L(16); else DEC_L(64);
 #undef DEC_L
+}
+
+void spiht_decode_cut(const FieldDev* F, int nf, const TileD* tiles, const int64_t* toff, uint64_t* lists,
+                      hipStream_t st) {
+  if (nf <= 0) return;
+  k_spiht_decode<64, true><<<(nf + 63) / 64, 64, 0, st>>>(F, tiles, nullptr, nf, toff, lists);
 }
 
 }  // namespace ebcc

@@ -64,6 +64,14 @@ __device__ __forceinline__ int band_of(const TileGeom& g, int nb, int local) {
   return b;
 }
 
+// Position in the field (Mallat layout) of the tile coefficient `loc`.
+__device__ __forceinline__ int loc_to_pos(const TileGeom& g, const Band* B, int nb, int nx, int loc) {
+  const int b = band_of(g, nb, loc);
+  const int rel = loc - g.off[b];
+  const int li = (int)(((uint64_t)rel * g.mg[b]) >> 32), lj = rel - li * g.wr[b];
+  return (B[b].y0 + g.r0[b] + li) * nx + B[b].x0 + g.c0[b] + lj;
+}
+
 // Offspring (local indices, row-major) of the node with local index `loc`.
 __device__ __forceinline__ int offspring_local(const TileGeom& g, const Band* B, int nb, int L, int loc, int* ch,
                                                int* clevel) {
@@ -154,7 +162,7 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
                                                          const int* __restrict__ tix, uint8_t* __restrict__ slots,
                                                          const int64_t* __restrict__ slot_off,
                                                          uint32_t* __restrict__ tlen, uint32_t* __restrict__ tent,
-                                                         int* __restrict__ misfit) {
+                                                         uint32_t* __restrict__ tcut, int* __restrict__ misfit) {
   __shared__ SpihtLds<CAP> S;
   const int lane = threadIdx.x;
   const int t = tix[blockIdx.x];
@@ -162,6 +170,10 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
   const FieldDev& f = F[td.field];
   if (!f.active) return;
   const uint32_t *qr = f.qr, *sub = f.sub, *maxd = f.maxd, *maxl = f.maxl;
+  // byte-cut fields: the positions of the last plane's bits and the tile's
+  // bit counts around that plane
+  uint32_t* const cpos = f.cpos;
+  const bool cut = cpos != nullptr;
   const Band* bands_g = f.bands;
   const int nx = f.nx, nb = f.nb, L = f.L, n_s = f.ns;
   if (!spiht_setup<CAP>(S, bands_g, nb, L, td, lane)) {
@@ -214,7 +226,10 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
   mx = (uint32_t)__builtin_amdgcn_readfirstlane((int)mx);
   const int ntop = mx ? 31 - __builtin_clz(mx) : -1;
   if (ntop < n_s) {
-    if (lane == 0) { tlen[t] = 0; tent[t] = 0; }
+    if (lane == 0) {
+      tlen[t] = 0; tent[t] = 0;
+      if (cut) { tcut[3 * t] = 0; tcut[3 * t + 1] = 0; tcut[3 * t + 2] = 0; }
+    }
     return;
   }
   // initial lists: LIP = roots, LIS = roots with offspring (type A)
@@ -257,6 +272,8 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
   for (int pl = ntop; pl >= n_s; pl--) {
     const uint32_t thr = 1u << pl;
     const int lsp_prev = nlsp;
+    const bool last = cut && pl == n_s;   // wave-uniform
+    if (last && lane == 0) tcut[3 * t] = (uint32_t)bitpos;
     // sorting pass, LIP
     int surv = 0;
     for (int h0 = 0; h0 < nlip; h0 += 64) {
@@ -275,6 +292,7 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
       put_bits(S.bw, (int)(bitpos - wbase) + pb, nbits, v);
       if (s) S.lsp[nlsp + ps] = (uint16_t)e;
       if (act && !s) S.lip[surv + pk] = (uint16_t)e;
+      if (last && s) cpos[loc_to_pos(g, S.B, nb, nx, e)] = (uint32_t)(bitpos + pb + 1);   // its sign bit
       bitpos += tb; nlsp += ts; surv += tl;
       flush(false);
     }
@@ -325,12 +343,19 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
       if (act && s) {
         if (!typeB) {
           int a = 0, b = 0;
+          int64_t bp = bitpos + pb + 1;   // the first child's significance bit
 #pragma unroll
           for (int c = 0; c < 9; c++)
             if (c < no) {
               int sc = (S.qv[ch[c]] & 0x7FFFFFu) >= thr;
-              if (sc) S.lsp[nlsp + psp + (a++)] = (uint16_t)ch[c];
-              else S.lip[nlip + pip + (b++)] = (uint16_t)ch[c];
+              if (sc) {
+                S.lsp[nlsp + psp + (a++)] = (uint16_t)ch[c];
+                if (last) cpos[loc_to_pos(g, S.B, nb, nx, ch[c])] = (uint32_t)(bp + 1);
+                bp += 2;
+              } else {
+                S.lip[nlip + pip + (b++)] = (uint16_t)ch[c];
+                bp += 1;
+              }
             }
           if (nlis_a) S.lis[nlis + pis] = (uint16_t)(loc | 0x8000);
         } else {
@@ -346,11 +371,13 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
     }
     nlis = kept;
     // refinement pass
+    if (last && lane == 0) tcut[3 * t + 1] = (uint32_t)bitpos;
     for (int h0 = 0; h0 < lsp_prev; h0 += 64) {
       int k = h0 + lane;
       bool act = k < lsp_prev;
       int n = lsp_prev - h0 < 64 ? lsp_prev - h0 : 64;
       uint32_t bit = act ? (S.qv[S.lsp[k]] >> pl) & 1u : 0u;
+      if (last && act) cpos[loc_to_pos(g, S.B, nb, nx, S.lsp[k])] = (uint32_t)(bitpos + lane);
       __syncthreads();
       if (act) put_bits(S.bw, (int)(bitpos - wbase) + lane, 1, bit);
       bitpos += n;
@@ -362,6 +389,7 @@ __global__ __launch_bounds__(64) void k_spiht_encode_lds(const FieldDev* __restr
     uint32_t bytes = (uint32_t)((bitpos + 7) >> 3);
     tlen[t] = bytes;
     tent[t] = bytes | ((uint32_t)(ntop + 1) << 26);
+    if (cut) tcut[3 * t + 2] = (uint32_t)bitpos;
   }
 }
 
@@ -537,11 +565,25 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
   const int ntop = (int)(ent >> 26) - 1;
   const int64_t pbase = 4 * (int64_t)f.ntiles;
   const int64_t o0 = toff[t];
-  if (o0 < 0 || pbase + o0 + len > sec_len || ntop >= kQBits) {
+  // byte-cut fields: the trailer after the payloads names the cut; the cut
+  // tile is decoded by its own launch, the others stop at a plane end or
+  // before a refinement pass
+  int n_bot = n_s, sort_only = 0;
+  int64_t pay_end = sec_len;
+  if (f.bt) {
+    pay_end = sec_len - 8;
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)((uint32_t)sec[pay_end] | ((uint32_t)sec[pay_end + 1] << 8) | ((uint32_t)sec[pay_end + 2] << 16) |
+              ((uint32_t)sec[pay_end + 3] << 24)));
+    const int J = (int)(w0 & 0x7FFFFFFFu), kind = (int)(w0 >> 31);
+    if (tl == J) return;
+    cut_tile_mode(kind, J, tl, n_s, &n_bot, &sort_only);
+  }
+  if (o0 < 0 || pbase + o0 + len > pay_end || ntop >= kQBits) {
     if (lane == 0) atomicOr(flag, 1);
     return;
   }
-  if (ntop < n_s) return;
+  if (ntop < n_bot) return;
   const uint8_t* pay = sec + pbase + o0;
   for (int i = lane; i < g.ncoef; i += 64) S.qv[i] = 0;
   const int nroots = g.hr[0] * g.wr[0];
@@ -565,7 +607,7 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
   int nlip = nroots, nlsp = 0;
   BitRU rd;
   rd.init(pay, len);
-  for (int pl = ntop; pl >= n_s; pl--) {
+  for (int pl = ntop; pl >= n_bot; pl--) {
     const uint32_t thr = 1u << pl;
     const int lsp_prev = nlsp;
     // LIP: runs of zeros leave entries in place; a one makes the entry
@@ -671,6 +713,7 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
     }
     __syncthreads();
     nlis = kept;
+    if (pl == n_bot && sort_only) break;   // a byte-cut field's tile that stops before this refinement pass
     // refinement: the next lsp_prev bits, 64 at a time from the uniform
     // reader, one per lane
     for (int h0 = 0; h0 < lsp_prev; h0 += 64) {
@@ -696,21 +739,108 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
       int li = r / g.wr[b], lj = r - li * g.wr[b];
       int p = (S.B[b].y0 + g.r0[b] + li) * nx + S.B[b].x0 + g.c0[b] + lj;
       uint32_t m = v & 0x7FFFFFu;
-      float f = ldexpf((float)(2u * m + (1u << n_s)), e_r - 1);
+      // lowest known plane: n_bot, or above it for coefficients significant
+      // before a last plane whose refinement pass was not decoded
+      const int pk = (sort_only && m >= (2u << n_s)) ? n_s + 1 : n_bot;
+      float f = ldexpf((float)(2u * m + (1u << pk)), e_r - 1);
       chat[p] = (v >> 31) ? -f : f;
     }
   }
 }
 
+// Byte-cut candidates: the residual coefficients the decoder of each cut
+// would reconstruct, one wavefront per tile of the candidate's field.  A
+// coefficient known above plane ns + 1 is known there whatever the cut; of
+// plane ns it needs one bit, at cpos in its tile's code: its sign bit (it
+// becomes significant in plane ns) or its refinement bit.
+struct CutGeomLds {
+  Band B[kMaxBands];
+  TileGeom g;
+};
+__global__ __launch_bounds__(64) void k_spiht_cut_recon(const FieldDev* __restrict__ Fc, const TileD* __restrict__ tiles,
+                                                        const uint32_t* __restrict__ tcut) {
+  __shared__ CutGeomLds S;
+  const FieldDev& f = Fc[blockIdx.y];
+  const int tl = (int)blockIdx.x;
+  if (!f.active || tl >= f.ntiles) return;
+  const int lane = threadIdx.x;
+  const int t = f.tile0 + tl;
+  const TileD td = tiles[t];
+  const int nb = f.nb, nx = f.nx, ns = f.ns, er = f.er;
+  for (int i = lane; i < nb; i += 64) S.B[i] = f.bands[i];
+  __syncthreads();
+  if (lane == 0) tile_geom(S.g, S.B, nb, f.L, td);
+  __syncthreads();
+  const TileGeom& g = S.g;
+  const uint32_t ell = cut_tile_bits(f.cut_kind, f.cut_tile, f.cut_bits, tl, tcut[3 * t], tcut[3 * t + 1],
+                                     tcut[3 * t + 2]);
+  const uint32_t* __restrict__ qr = f.qr;
+  const uint32_t* __restrict__ cpos = f.cpos;
+  float* __restrict__ chat = f.buf[BUF_CHAT];
+  const uint32_t lo = 1u << ns, hi = 2u << ns;
+  for (int b = 0; b < nb; b++) {
+    const int n = g.hr[b] * g.wr[b], wr = g.wr[b];
+    if (n == 0) continue;
+    const int y0 = S.B[b].y0 + g.r0[b], x0 = S.B[b].x0 + g.c0[b];
+    for (int r = lane; r < n; r += 64) {
+      const int li = r / wr, lj = r - li * wr;
+      const int p = (y0 + li) * nx + x0 + lj;
+      const uint32_t w = qr[p], m = w & 0x7FFFFFu;
+      float v = 0.0f;
+      if (m >= lo) {
+        const bool known = cpos[p] < ell;
+        if (m >= hi) {
+          const int pk = known ? ns : ns + 1;
+          v = dequant((m >> pk) << pk, pk, (int)(w >> 31), er);
+        } else if (known) {
+          v = dequant(lo, ns, (int)(w >> 31), er);
+        }
+      }
+      chat[p] = v;
+    }
+  }
+}
+
+// Final tile lengths of the byte-cut fields.
+__global__ __launch_bounds__(256) void k_spiht_cut_tiles(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
+                                                         int nt, const uint32_t* __restrict__ tcut,
+                                                         uint32_t* __restrict__ tlen, uint32_t* __restrict__ tent,
+                                                         uint32_t* __restrict__ tbits) {
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < nt; t += gridDim.x * 256) {
+    const FieldDev& f = F[tiles[t].field];
+    if (!f.active) continue;
+    const uint32_t ell = cut_tile_bits(f.cut_kind, f.cut_tile, f.cut_bits, t - f.tile0, tcut[3 * t],
+                                       tcut[3 * t + 1], tcut[3 * t + 2]);
+    const uint32_t by = (ell + 7) >> 3;
+    tbits[t] = ell;
+    tlen[t] = by;
+    tent[t] = ell ? (by | (tent[t] & 0xFC000000u)) : 0u;
+  }
+}
+
+void spiht_cut_recon(const FieldDev* Fc, int ncand, int max_tiles, const TileD* tiles, const uint32_t* tcut,
+                     hipStream_t st) {
+  if (ncand <= 0 || max_tiles <= 0) return;
+  k_spiht_cut_recon<<<dim3(max_tiles, ncand), 64, 0, st>>>(Fc, tiles, tcut);
+}
+
+void spiht_cut_tiles(const FieldDev* F, const TileD* tiles, int nt, const uint32_t* tcut, uint32_t* tlen,
+                     uint32_t* tent, uint32_t* tbits, hipStream_t st) {
+  if (nt <= 0) return;
+  int g = (nt + 255) / 256;
+  k_spiht_cut_tiles<<<g < 2048 ? g : 2048, 256, 0, st>>>(F, tiles, nt, tcut, tlen, tent, tbits);
+}
+
 void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint8_t* slots,
-                      const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, int* misfit, hipStream_t st) {
+                      const int64_t* slot_off, uint32_t* tlen, uint32_t* tent, uint32_t* tcut, int* misfit,
+                      hipStream_t st) {
   if (ntix <= 0) return;
   if (cap == kSpihtSmall)
-    k_spiht_encode_lds<kSpihtSmall><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, misfit);
+    k_spiht_encode_lds<kSpihtSmall><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, tcut, misfit);
   else if (cap == kSpihtBig)
-    k_spiht_encode_lds<kSpihtBig><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, misfit);
+    k_spiht_encode_lds<kSpihtBig><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, tcut, misfit);
   else
-    k_spiht_encode_lds<kSpihtHuge><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, misfit);
+    k_spiht_encode_lds<kSpihtHuge><<<ntix, 64, 0, st>>>(F, tiles, tix, slots, slot_off, tlen, tent, tcut, misfit);
 }
 
 void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
