@@ -182,6 +182,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per arrival rate")
     ap.add_argument("--q", type=float, default=1 - 1e-5, help="proportion q of the ratio-search run (0: skip)")
     ap.add_argument("--ablation-fields", type=int, default=256, help="fields of the q ablation (0: skip)")
+    ap.add_argument("--byte-cut", type=int, default=1, help="measure the byte-granular residual cut (0: skip)")
     ap.add_argument("--km-fields", type=int, default=16, help="km-scale 1801x3600 vortex fields (0: skip)")
     ap.add_argument("--batch-fields", type=int, default=256, help="fields of the uneven batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of each oracle baseline leg")
@@ -630,6 +631,44 @@ def main():
                         "max_err_rel": qmax}
         log(f"ratio search: {ratio_search}")
 
+    # ---------------- byte-granular residual truncation (trunc = 1) ----------------
+    byte_cut = None
+    if args.byte_cut:
+        bcargs = ebcc.BatchArgs(xs, err_bounds=[args.eps] * len(xs))
+        bcout = torch.empty(bcargs.bound(), dtype=torch.uint8, device=dev)
+        byte_cut = {"workload": f"the stack through the batched entry points, residual cut at byte positions "
+                                f"(trunc = 1), eps_rel {args.eps}, r {args.ratio}"}
+        for qv in ([0.0, args.q] if args.q > 0 else [0.0]):
+            pb = ebcc.params(args.eps, args.ratio, q=qv, trunc=1, **fmt)
+            assert ebcc.compress_batch_into(bcargs, bcout, pb, stream) == 0
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            assert ebcc.compress_batch_into(bcargs, bcout, pb, stream) == 0
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            bcs = [bcout[bcargs.offsets[i]: bcargs.offsets[i] + bcargs.lengths[i]] for i in range(bcargs.n)]
+            assert ebcc.decompress_batch_into(ebcc.DecodeArgs(bcs, recs), stream) == 0
+            torch.cuda.synchronize()
+            c = time.perf_counter()
+            bv, bm = verify(stack_h, recs, [args.eps] * len(xs))
+            bsb = sum(bcargs.lengths[i] for i in range(bcargs.n))
+            key = "fixed_ratio" if qv == 0 else f"q_{qv:g}"
+            byte_cut[key] = {"CR": nbytes / bsb, "CR_plane_ends": cr_stack if qv == 0 else None,
+                             "compress_GBps": nbytes / (b - a) / 1e9, "decompress_GBps": nbytes / (c - b) / 1e9,
+                             "violations": bv, "max_err_rel": bm}
+        # per-call latency of the per-field path with the byte search
+        pl1 = ebcc.params(args.eps, args.ratio, trunc=1, **fmt)
+        lc = []
+        for i in range(min(16, len(xs))):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            rc, _ = ebcc.compress_into(xs[i], outs[i], pl1, stream)
+            lc.append(time.perf_counter() - a)
+            assert rc == 0
+        byte_cut["per_field_compress_ms_p50"] = pct(lc, 50) * 1e3
+        byte_cut["per_field_fields"] = len(lc)
+        log(f"byte cut: {byte_cut}")
+
     # ---------------- ablation of q (relative CR against q = 1) ----------------
     q_ablation = None
     if args.ablation_fields and bx:
@@ -798,6 +837,7 @@ def main():
         "batched": batched,
         "serving": serving,
         "ratio_search": ratio_search,
+        "byte_cut": byte_cut,
         "q_ablation": q_ablation,
         "km_scale": km,
         "tier1_decisions": tier1,
