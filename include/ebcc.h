@@ -268,7 +268,14 @@ const char* ebcc_profile_stage_name(int i);
  *   t1_split                percent (0..100, default 10) of a lanes-per-block
  *                           encoder launch's code-blocks given to the
  *                           wave-per-block coder on a second stream (scalar
- *                           and vector units then work at the same time)
+ *                           and vector units then work at the same time);
+ *                           not used by persistent launches
+ *   t1_persist              1 (default) = lanes-per-block coders as one
+ *                           persistent launch: code-blocks ordered by the
+ *                           bit-planes they code (most first), workgroups the
+ *                           device keeps resident taking groups of them from
+ *                           a work counter until none is left; 0 = one
+ *                           workgroup per group of blocks in block order
  * ebcc_tuning_set returns EBCC_EINVAL for out-of-range values.
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -279,6 +286,7 @@ typedef struct {
   int32_t spiht;
   int32_t t1_lanes;
   int32_t t1_split;
+  int32_t t1_persist;
 } ebcc_tuning;
 int ebcc_tuning_get(ebcc_tuning* t);
 int ebcc_tuning_set(const ebcc_tuning* t);

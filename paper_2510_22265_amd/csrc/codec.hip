@@ -690,7 +690,7 @@ static int upload_plan(Plan& p) {
 // global-memory lists; the environment variable EBCC_SPIHT_KERNEL=global
 // sends every tile to the global-memory kernels (to test both families).
 static std::mutex g_tune_mu;
-static Tuning g_tuning = {0, 0, 32768, 0, 0, 10};
+static Tuning g_tuning = {0, 0, 32768, 0, 0, 10, 1};
 
 Tuning tuning() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -799,6 +799,9 @@ struct WS {
   // tile classes), ordered against the caller's stream with events
   hipStream_t aux = nullptr, aux2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
+  // stream on which launch sequences are recorded into graphs (recording
+  // runs nothing; the graph is then launched on the caller's stream)
+  hipStream_t capst = nullptr;
   ~WS() {
     if (fixed) return;
     if (ev_live) (void)hipEventSynchronize(ev);
@@ -807,6 +810,7 @@ struct WS {
     if (ev) (void)hipEventDestroy(ev);
     if (aux) (void)hipStreamDestroy(aux);
     if (aux2) (void)hipStreamDestroy(aux2);
+    if (capst) (void)hipStreamDestroy(capst);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_join2) (void)hipEventDestroy(ev_join2);
@@ -839,6 +843,7 @@ static int get_ws(hipStream_t st, WS** out) {
     HIPCHK(hipEventCreateWithFlags(&w->ev_join2, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&w->aux2, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&w->capst, hipStreamNonBlocking));
   }
   // the previous call's staged copies must have left the pinned buffer
   if (w->ev_live) HIPCHK(hipEventSynchronize(w->ev));
@@ -954,6 +959,7 @@ struct Call {
   uint64_t *keys, *lists;
   uint32_t *tail, *tlen, *tent, *bent;
   uint32_t *tcut, *tbits;   // byte-cut residuals: per tile bit counts around plane ns, final code bits
+  int *border, *qctr;       // persistent tier-1 launches: block order and work counter
   bool want_cpos = false;   // compression with byte-cut residuals: every coded field gets a cpos plane
   int* misfit;
   Blk* d_blk_own;
@@ -1027,19 +1033,23 @@ struct Call {
   // after join().
   // Without extra streams (fixed workspace) everything runs on the caller's.
   hipStream_t aux_or(hipStream_t s) const { return ws->aux ? s : st; }
-  int fork() {
+  int fork() { return fork_from(st); }
+  int join() { return join_to(st); }
+  // main: the stream the launches of the sequence go to (the caller's, or
+  // the workspace's capture stream while a graph is recorded)
+  int fork_from(hipStream_t main) {
     if (!ws->aux) return EBCC_OK;
-    HIPCHK(hipEventRecord(ws->ev_fork, st));
+    HIPCHK(hipEventRecord(ws->ev_fork, main));
     HIPCHK(hipStreamWaitEvent(ws->aux, ws->ev_fork, 0));
     HIPCHK(hipStreamWaitEvent(ws->aux2, ws->ev_fork, 0));
     return EBCC_OK;
   }
-  int join() {
+  int join_to(hipStream_t main) {
     if (!ws->aux) return EBCC_OK;
     HIPCHK(hipEventRecord(ws->ev_join, ws->aux));
     HIPCHK(hipEventRecord(ws->ev_join2, ws->aux2));
-    HIPCHK(hipStreamWaitEvent(st, ws->ev_join, 0));
-    HIPCHK(hipStreamWaitEvent(st, ws->ev_join2, 0));
+    HIPCHK(hipStreamWaitEvent(main, ws->ev_join, 0));
+    HIPCHK(hipStreamWaitEvent(main, ws->ev_join2, 0));
     return EBCC_OK;
   }
   int set_active(const std::vector<int>& act) {
@@ -1053,6 +1063,93 @@ struct Call {
     return fetch(v.data(), collect, v.size());
   }
 };
+
+// ---------------------------------------------------------------------------
+// Launch sequences as HIP graphs.  A sequence of kernel launches (on the
+// caller's stream and the workspace's two extra streams, joined by events)
+// that depends on nothing the host decides while it runs is recorded once on
+// the workspace's capture stream and kept under a key of everything its
+// launches take (workspace and table addresses, the fields' geometry and
+// roles, kernel choices); a later call with the same key launches the graph
+// on its stream instead of issuing the launches one by one.  Not used with
+// stage profiling (its events would be recorded), by the static-scratch
+// entry point, or when EBCC_GRAPHS=0.  The sequences stage nothing and set
+// no memory with hipMemset: every table is uploaded before them, and
+// buffers are cleared by kernels.
+// ---------------------------------------------------------------------------
+struct GraphKey {
+  std::string b;
+  template <typename T> void add(const T& v) { b.append(reinterpret_cast<const char*>(&v), sizeof(T)); }
+  GraphKey(const char* what, const Call& c) {
+    b = what;
+    b.push_back('\0');
+    add(c.ws); add(c.ws->base); add(c.nf); add(c.nblk); add(c.ntiles); add(c.cbw); add(c.cbh);
+    add(c.forced_global); add(c.d_blk); add(c.d_tiles); add(c.d_tix); add(c.d_slot_off); add(c.F); add(c.Fc);
+    add(c.spec_depth); add(c.want_cpos); add(c.need_lists);
+    for (int k = 0; k < 4; k++) add(c.ncls[k]);
+    const Tuning t = tuning();
+    add(t);
+    for (const char* v : {"EBCC_T1_KERNEL", "EBCC_T1_PIPE", "EBCC_T1_PERSIST", "EBCC_SPIHT_KERNEL"}) {
+      const char* e = getenv(v);
+      b += e ? e : "-";
+      b.push_back('\0');
+    }
+    for (int i = 0; i < c.nf; i++) {
+      const FieldDev& f = c.Fh[i];
+      add(f.ny); add(f.nx); add(f.L); add(f.nb); add(f.blk0); add(f.nblk); add(f.tile0); add(f.ntiles);
+      add(f.active); add(f.mode); add(f.bt); add(c.plans[i]);
+    }
+  }
+};
+
+constexpr size_t kMaxGraphs = 512;
+static std::mutex g_graph_mu;
+static std::map<std::string, hipGraphExec_t> g_graphs;
+
+static bool graphs_usable(const Call& c, const Prof& prof) {
+  const char* e = getenv("EBCC_GRAPHS");
+  if (e && e[0] == '0') return false;
+  return !prof.on && c.ws && !c.ws->fixed && c.ws->capst && c.ws->aux;
+}
+
+// Runs seq(stream): from the graph cached under key, recording it first if
+// there is none (when the cache is full the launches are issued directly).
+template <typename Seq>
+static int run_graph(const GraphKey& key, Call& c, Seq& seq) {
+  hipGraphExec_t ex = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key.b);
+    if (it != g_graphs.end()) ex = it->second;
+    else if (g_graphs.size() >= kMaxGraphs) return seq(c.st);
+  }
+  if (!ex) {
+    hipStream_t cs = c.ws->capst;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const int rc = seq(cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc != EBCC_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess || !g) return fail(EBCC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(EBCC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    g_graphs[key.b] = ex;
+  }
+  HIPCHK(hipGraphLaunch(ex, c.st));
+  return EBCC_OK;
+}
+
+// Drops every cached graph (their tables and workspaces are being freed).
+static void graphs_clear() {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+  g_graphs.clear();
+}
 
 // Lay out (base == nullptr: measure) the workspace of a call; every coded
 // field gets its buffers, items get their tables.
@@ -1095,6 +1192,8 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
   c.misfit = cv.take<int>(nt);
   c.tcut = cv.take<uint32_t>(3 * nt);
   c.tbits = cv.take<uint32_t>(nt);
+  c.border = cv.take<int>(nb);
+  c.qctr = cv.take<int>(1);
   c.collect = cv.take<int64_t>(8 * (size_t)c.nf);
   // candidates per field and search round: "all planes" and the nodes of
   // spec_depth levels of the bisection tree
@@ -1490,17 +1589,32 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   std::vector<int64_t> col;             // per-field results read back (k_collect)
   bool any = false;
   for (int v : act) any |= v != 0;
+  // launch sequences without host decisions inside run from cached graphs
+  const bool use_graphs = graphs_usable(c, prof);
+  size_t maxN_all = 0;
+  for (auto& f : c.Fh) maxN_all = std::max(maxN_all, (size_t)f.ny * f.nx);
+  auto run_seq = [&](const char* name, auto& seq) -> int {
+    if (!use_graphs) return seq(st);
+    GraphKey key(name, c);
+    key.add(maxN_all);
+    return run_graph(key, c, seq);
+  };
   if (any) {
     if ((rc = c.set_active(act))) return rc;
     // ---- base layer: DWT of the normalised field, tier-1, PCRD at ratio r ----
-    dwt_forward(c.F, c.Fh.data(), nf, BUF_X, BUF_COEF, PRO_NORM, st);
-    prof.mark(S_DWT);
-    quant_planes(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, st);
-    prof.mark(S_QUANT);
-    const T1Split t1s{c.ws->aux, c.ws->ev_fork, c.ws->ev_join};
-    t1_encode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, c.cw, c.R, c.D, c.bpt, c.tail, c.sppf, st,
-              &t1s);
-    prof.mark(S_T1ENC);
+    auto seq_base = [&](hipStream_t s) -> int {
+      dwt_forward(c.F, c.Fh.data(), nf, BUF_X, BUF_COEF, PRO_NORM, s);
+      prof.mark(S_DWT);
+      quant_planes(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, s);
+      prof.mark(S_QUANT);
+      const T1Split t1s{c.ws->aux, c.ws->ev_fork, c.ws->ev_join};
+      t1_encode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, c.cw, c.R, c.D, c.bpt, c.tail, c.sppf,
+                s, &t1s, c.border, c.qctr);
+      prof.mark(S_T1ENC);
+      HIPCHK(hipGetLastError());
+      return EBCC_OK;
+    };
+    if ((rc = run_seq("enc_base", seq_base))) return rc;
     // ---- base ratio: the given r, or Algorithm 1's feedback search ----
     if (pp->q > 0.0) {
       auto fieldN = [&](int i) { return (int64_t)c.Fh[i].ny * c.Fh[i].nx; };
@@ -1580,17 +1694,21 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
         if (act[i]) c.Fh[i].budget = base_budget(fieldN(i), c.Fh[i].nblk, r_use[i]);
       if ((rc = c.set_active(act))) return rc;
     }
-    pcrd(c.F, nf, c.max_nblk(), c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, st);
-    prof.mark(S_PCRD);
-    // ---- A_base = dec_base(e_base) (closed form), residual, its DWT ----
-    virtual_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.pb, c.kb, c.sppf, st);
-    dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, st);
-    pointwise(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, 3, EPI_CHECK, 0, st);   // does the base alone meet the bound?
-    prof.mark(S_BASEREC);
-    dwt_forward(c.F, c.Fh.data(), nf, BUF_X, BUF_CRES, PRO_NORM_MINUS, st);
-    k_quant_res<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
-    HIPCHK(hipGetLastError());
-    prof.mark(S_RESID);
+    auto seq_resid = [&](hipStream_t s) -> int {
+      pcrd(c.F, nf, c.max_nblk(), c.pb, c.R, c.D, c.kb, c.hk, c.keys, c.dr, c.nh, c.len, s);
+      prof.mark(S_PCRD);
+      // ---- A_base = dec_base(e_base) (closed form), residual, its DWT ----
+      virtual_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.pb, c.kb, c.sppf, s);
+      dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, s);
+      pointwise(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, 3, EPI_CHECK, 0, s);   // does the base alone meet the bound?
+      prof.mark(S_BASEREC);
+      dwt_forward(c.F, c.Fh.data(), nf, BUF_X, BUF_CRES, PRO_NORM_MINUS, s);
+      k_quant_res<<<dim3(grid_sweep(maxN), nf), 256, 0, s>>>(c.F);
+      HIPCHK(hipGetLastError());
+      prof.mark(S_RESID);
+      return EBCC_OK;
+    };
+    if ((rc = run_seq("enc_resid", seq_resid))) return rc;
     if ((rc = c.collect_host(col))) return rc;
     // ---- truncation search, all fields in lockstep: one launch + one sync per round ----
     enum { NONE = 0, CHECK_ALL, BISECT, REQUANT, FOUND, FAIL };
@@ -1713,24 +1831,29 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     if (anysp) {
       for (int i = 0; i < nf; i++) c.Fh[i].bt = (pp->trunc && sp[i]) ? 1 : 0;
       if ((rc = c.set_active(sp))) return rc;
-      spiht_maxima(c.F, c.Fh.data(), nf, st);
-      if (c.forced_global) {
-        spiht_encode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut, st);
-      } else {
-        // the classes run concurrently: global and huge tiles on the second
-        // stream, big tiles on the third, small ones on the caller's
-        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
-        hipStream_t sa = c.aux_or(c.ws->aux);
-        if ((rc = c.fork())) return rc;
-        spiht_encode(c.F, c.d_tiles, t2, c.ncls[2], c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut, sa);
-        spiht_encode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut,
-                         c.misfit, sa);
-        spiht_encode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut,
-                         c.misfit, c.aux_or(c.ws->aux2));
-        spiht_encode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut,
-                         c.misfit, st);
-        if ((rc = c.join())) return rc;
-      }
+      auto seq_spiht = [&](hipStream_t s) -> int {
+        spiht_maxima(c.F, c.Fh.data(), nf, s);
+        if (c.forced_global) {
+          spiht_encode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut, s);
+        } else {
+          // the classes run concurrently: global and huge tiles on the second
+          // stream, big tiles on the third, small ones on the caller's
+          const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
+          hipStream_t sa = c.ws->aux ? c.ws->aux : s, sb = c.ws->aux2 ? c.ws->aux2 : s;
+          if (int rc2 = c.fork_from(s)) return rc2;
+          spiht_encode(c.F, c.d_tiles, t2, c.ncls[2], c.lists, c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut, sa);
+          spiht_encode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut,
+                           c.misfit, sa);
+          spiht_encode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut,
+                           c.misfit, sb);
+          spiht_encode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.slots, c.d_slot_off, c.tlen, c.tent, c.tcut,
+                           c.misfit, s);
+          if (int rc2 = c.join_to(s)) return rc2;
+        }
+        HIPCHK(hipGetLastError());
+        return EBCC_OK;
+      };
+      if ((rc = run_seq("enc_spiht", seq_spiht))) return rc;
       if (pp->trunc && (rc = byte_search(c, sp, checks))) return rc;
       k_scan<<<nf, 1024, 0, st>>>(c.F, c.tlen, 1, 0, 0xFFFFFFFFu, c.toff);
     }
@@ -1817,28 +1940,45 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   if (total > cap) return fail(EBCC_ENOSPC, "output capacity too small");
   for (int i = 0; i < nf; i++) c.Fh[i].out = out + offs[i];
   // ---- pack: tables, codewords, tile tables and payloads, raw data, checksum, header ----
+  // (the tables of the three roles are staged first: the coded fields in
+  // c.F, the raw ones at c.Fc, every field with a stream at c.Fc + nf)
   if ((rc = c.set_active(act))) return rc;
-  if (any) {
-    k_put_blocks<<<grid_for(c.nblk), 256, 0, st>>>(c.F, c.d_blk, c.bent, c.nblk);
-    k_gather_cw<<<std::max(1, (c.nblk + 3) / 4), 256, 0, st>>>(c.F, c.d_blk, c.cw, c.kb, c.len, c.bpt, c.tail, c.boff, c.nblk);
-    k_put_tiles<<<grid_for(c.ntiles), 256, 0, st>>>(c.F, c.d_tiles, c.tent, c.ntiles);
-    k_gather_tiles<<<std::max(1, (c.ntiles + 3) / 4), 256, 0, st>>>(c.F, c.d_tiles, c.slots, c.d_slot_off, c.tlen,
-                                                                     c.tbits, c.toff, c.ntiles);
-  }
-  std::vector<int> rawm(nf, 0);
+  std::vector<int> rawm(nf, 0), all(nf, 1);
   bool anyraw = false;
-  for (int i = 0; i < nf; i++)
+  for (int i = 0; i < nf; i++) {
     if (mode[i] == MODE_RAW) { rawm[i] = 1; anyraw = true; }
-  if (anyraw) {
-    if ((rc = c.set_active(rawm))) return rc;
-    k_copy_raw<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, 1);
+    all[i] = !failed[i];
   }
-  std::vector<int> all(nf, 1);
-  for (int i = 0; i < nf; i++) all[i] = !failed[i];
-  if ((rc = c.set_active(all))) return rc;
-  k_checksum<<<dim3(grid_sweep(maxN), nf), 256, 0, st>>>(c.F);
-  k_header<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
-  HIPCHK(hipGetLastError());
+  std::vector<FieldDev> Fraw(c.Fh), Fall(c.Fh);
+  for (int i = 0; i < nf; i++) { Fraw[i].active = rawm[i]; Fall[i].active = all[i]; }
+  FieldDev *const Frd = c.Fc, *const Fad = c.Fc + nf;
+  if (anyraw && (rc = c.stage(Frd, Fraw.data(), sizeof(FieldDev) * nf))) return rc;
+  if ((rc = c.stage(Fad, Fall.data(), sizeof(FieldDev) * nf))) return rc;
+  auto seq_pack = [&](hipStream_t s) -> int {
+    if (any) {
+      k_put_blocks<<<grid_for(c.nblk), 256, 0, s>>>(c.F, c.d_blk, c.bent, c.nblk);
+      k_gather_cw<<<std::max(1, (c.nblk + 3) / 4), 256, 0, s>>>(c.F, c.d_blk, c.cw, c.kb, c.len, c.bpt, c.tail, c.boff,
+                                                               c.nblk);
+      k_put_tiles<<<grid_for(c.ntiles), 256, 0, s>>>(c.F, c.d_tiles, c.tent, c.ntiles);
+      k_gather_tiles<<<std::max(1, (c.ntiles + 3) / 4), 256, 0, s>>>(c.F, c.d_tiles, c.slots, c.d_slot_off, c.tlen,
+                                                                      c.tbits, c.toff, c.ntiles);
+    }
+    if (anyraw) k_copy_raw<<<dim3(grid_for(maxN), nf), 256, 0, s>>>(Frd, 1);
+    k_checksum<<<dim3(grid_sweep(maxN), nf), 256, 0, s>>>(Fad);
+    k_header<<<(nf + 63) / 64, 64, 0, s>>>(Fad, nf);
+    HIPCHK(hipGetLastError());
+    return EBCC_OK;
+  };
+  {
+    auto run_pack = [&]() -> int {
+      if (!use_graphs) return seq_pack(st);
+      GraphKey key("enc_pack", c);
+      key.add(maxN_all); key.add(any); key.add(anyraw);
+      for (int i = 0; i < nf; i++) { key.add(rawm[i]); key.add(all[i]); }
+      return run_graph(key, c, seq_pack);
+    };
+    if ((rc = run_pack())) return rc;
+  }
   prof.mark(S_PACK);
   if (tr && nf == 1) {
     const FieldDev& f = c.Fh[0];
@@ -2044,17 +2184,14 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
     k_copy_raw<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, 0);
   }
   if (anycoded) {
+    // Tables of the launch sequence, all staged before it: the coded fields
+    // (c.F), the fields with a residual whose inverse DWT runs on the third
+    // stream, scratch in BUF_CRES (unused when decoding) so that it does not
+    // meet the base transform's BUF_TMP (c.Fc), the fields without one
+    // (c.Fc + nf).  The sequence itself is only launches, so it runs from a
+    // cached HIP graph when one matches the call.
     if ((rc = c.set_active(cd))) return rc;
-    k_read_blocks<<<grid_for(c.nblk), 256, 0, st>>>(c.F, c.d_blk, c.nblk, c.bent);
-    k_scan<<<nf, 1024, 0, st>>>(c.F, c.bent, 0, 16, 0xFFFFu, c.boff);
-    k_read_tiles<<<grid_for(c.ntiles), 256, 0, st>>>(c.F, c.d_tiles, c.ntiles, c.tent);
-    k_scan<<<nf, 1024, 0, st>>>(c.F, c.tent, 1, 0, 0x3FFFFFFu, c.toff);
-    k_check_tables<<<(nf + 63) / 64, 64, 0, st>>>(c.F, nf);
-    prof.mark(S_D_PARSE);
-    // the residual's inverse DWT runs on the third stream with its own field
-    // table: the fields with a residual, scratch in BUF_CRES (unused when
-    // decoding) so that it does not meet the base transform's BUF_TMP
-    std::vector<FieldDev> Fr;
+    std::vector<FieldDev> Fr, Fn;
     if (anyres) {
       Fr = c.Fh;
       for (int i = 0; i < nf; i++) {
@@ -2063,50 +2200,71 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
       }
       if ((rc = c.stage(c.Fc, Fr.data(), sizeof(FieldDev) * nf))) return rc;
     }
-    if (anyres) {
-      // The residual layer decodes independently of the base layer: SPIHT
-      // runs on the second and third streams while tier-1 decoding and the base
-      // inverse DWT run on the caller's (the SPIHT kernels skip fields
-      // without a residual section).
-      k_fill<<<dim3(grid_for(maxN), nf), 256, 0, st>>>(c.F, BUF_CHAT, 0.0f);
-      hipStream_t sa = c.ws->aux;
-      if ((rc = c.fork())) return rc;
-      bool anybt = false;
-      for (int i = 0; i < nf; i++) anybt |= cr[i] && c.Fh[i].bt;
-      if (anybt) spiht_decode_cut(c.F, nf, c.d_tiles, c.toff, c.lists, sa);
-      if (c.forced_global) {
-        spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, sa);
-      } else {
-        // small tiles on one stream, the larger classes on another
-        const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
-        hipStream_t sb = c.ws->aux2;
-        spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sb);
-        spiht_decode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.toff, c.misfit, sb);
-        spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sb);
-        spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, sa);
-      }
-      // all of the residual's inverse DWT but its last pass, in the shadow of
-      // tier-1 decoding, once both SPIHT streams are done
-      hipStream_t sb = c.ws->aux2;
-      HIPCHK(hipEventRecord(c.ws->ev_join, sa));
-      HIPCHK(hipStreamWaitEvent(sb, c.ws->ev_join, 0));
-      dwt_inverse_head(c.Fc, Fr.data(), nf, BUF_CHAT, sb);
-    }
-    // (no scalar/vector split here: the second stream is busy with SPIHT)
-    t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, st);
-    prof.mark(S_D_T1);
-    dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, st);
-    prof.mark(S_D_IDWT_BASE);
-    if (anyres) {
-      if ((rc = c.join())) return rc;
-      prof.mark(S_D_SPIHT);
-      dwt_inverse_tail(c.Fc, Fr.data(), nf, BUF_CHAT, BUF_CHAT, EPI_FINAL, st);
-    }
+    FieldDev* const Fnd = c.Fc + nf;
     if (anynores) {
-      if ((rc = c.set_active(cn))) return rc;
-      pointwise(c.F, c.Fh.data(), nf, BUF_CHAT, BUF_CHAT, 3, EPI_FINAL, 0, st);
+      Fn = c.Fh;
+      for (int i = 0; i < nf; i++) Fn[i].active = cn[i];
+      if ((rc = c.stage(Fnd, Fn.data(), sizeof(FieldDev) * nf))) return rc;
     }
-    prof.mark(S_D_FINAL);
+    bool anybt = false;
+    for (int i = 0; i < nf; i++) anybt |= cr[i] && c.Fh[i].bt;
+    auto seq = [&](hipStream_t s) -> int {
+      k_read_blocks<<<grid_for(c.nblk), 256, 0, s>>>(c.F, c.d_blk, c.nblk, c.bent);
+      k_scan<<<nf, 1024, 0, s>>>(c.F, c.bent, 0, 16, 0xFFFFu, c.boff);
+      k_read_tiles<<<grid_for(c.ntiles), 256, 0, s>>>(c.F, c.d_tiles, c.ntiles, c.tent);
+      k_scan<<<nf, 1024, 0, s>>>(c.F, c.tent, 1, 0, 0x3FFFFFFu, c.toff);
+      k_check_tables<<<(nf + 63) / 64, 64, 0, s>>>(c.F, nf);
+      prof.mark(S_D_PARSE);
+      if (anyres) {
+        // The residual layer decodes independently of the base layer: SPIHT
+        // runs on the second and third streams while tier-1 decoding and the
+        // base inverse DWT run on the caller's (the SPIHT kernels skip
+        // fields without a residual section).
+        k_fill<<<dim3(grid_for(maxN), nf), 256, 0, s>>>(c.F, BUF_CHAT, 0.0f);
+        hipStream_t sa = c.ws->aux;
+        if (int rc2 = c.fork_from(s)) return rc2;
+        if (anybt) spiht_decode_cut(c.F, nf, c.d_tiles, c.toff, c.lists, sa);
+        if (c.forced_global) {
+          spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, sa);
+        } else {
+          // small tiles on one stream, the larger classes on another
+          const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
+          hipStream_t sb = c.ws->aux2;
+          spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sb);
+          spiht_decode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.toff, c.misfit, sb);
+          spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sb);
+          spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, sa);
+        }
+        // all of the residual's inverse DWT but its last pass, in the shadow
+        // of tier-1 decoding, once both SPIHT streams are done
+        hipStream_t sb = c.ws->aux2;
+        HIPCHK(hipEventRecord(c.ws->ev_join, sa));
+        HIPCHK(hipStreamWaitEvent(sb, c.ws->ev_join, 0));
+        dwt_inverse_head(c.Fc, Fr.data(), nf, BUF_CHAT, sb);
+      }
+      // (no scalar/vector split here: the second stream is busy with SPIHT)
+      t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, s, nullptr, c.border, c.qctr);
+      prof.mark(S_D_T1);
+      dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, s);
+      prof.mark(S_D_IDWT_BASE);
+      if (anyres) {
+        if (int rc2 = c.join_to(s)) return rc2;
+        prof.mark(S_D_SPIHT);
+        dwt_inverse_tail(c.Fc, Fr.data(), nf, BUF_CHAT, BUF_CHAT, EPI_FINAL, s);
+      }
+      if (anynores) pointwise(Fnd, Fn.data(), nf, BUF_CHAT, BUF_CHAT, 3, EPI_FINAL, 0, s);
+      prof.mark(S_D_FINAL);
+      HIPCHK(hipGetLastError());
+      return EBCC_OK;
+    };
+    if (graphs_usable(c, prof)) {
+      GraphKey key("decode", c);
+      key.add(anyres); key.add(anynores); key.add(anybt); key.add(maxN);
+      for (int i = 0; i < nf; i++) { key.add(cd[i]); key.add(cr[i]); key.add(cn[i]); }
+      if ((rc = run_graph(key, c, seq))) return rc;
+    } else if ((rc = seq(st))) {
+      return rc;
+    }
   }
   HIPCHK(hipGetLastError());
   if ((rc = c.set_active(all))) return rc;
@@ -2354,6 +2512,7 @@ int ebcc_stream_info(const uint8_t* h, size_t len, size_t* ny, size_t* nx, int* 
 void ebcc_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   (void)hipDeviceSynchronize();
+  graphs_clear();
   g_ws.clear();
   g_plans.clear();
 }
@@ -2400,6 +2559,7 @@ int ebcc_tuning_get(ebcc_tuning* t) {
   t->spiht = v.spiht;
   t->t1_lanes = v.t1_lanes;
   t->t1_split = v.t1_split;
+  t->t1_persist = v.t1_persist;
   return EBCC_OK;
 }
 
@@ -2408,10 +2568,11 @@ int ebcc_tuning_set(const ebcc_tuning* t) {
   if (t->t1_encoder < 0 || t->t1_encoder > 2 || t->t1_decoder < 0 || t->t1_decoder > 2 || t->t1_wave_max < 0 ||
       t->spiht < 0 || t->spiht > 1 ||
       !(t->t1_lanes == 0 || t->t1_lanes == 1 || t->t1_lanes == 4 || t->t1_lanes == 16 || t->t1_lanes == 64) ||
-      t->t1_split < 0 || t->t1_split > 100)
+      t->t1_split < 0 || t->t1_split > 100 || t->t1_persist < 0 || t->t1_persist > 1)
     return fail(EBCC_EINVAL, "tuning value out of range");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuning = Tuning{t->t1_encoder, t->t1_decoder, t->t1_wave_max, t->spiht, t->t1_lanes, t->t1_split};
+  g_tuning = Tuning{t->t1_encoder, t->t1_decoder, t->t1_wave_max, t->spiht, t->t1_lanes, t->t1_split,
+                    t->t1_persist};
   return EBCC_OK;
 }
 

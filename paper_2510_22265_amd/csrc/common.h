@@ -145,15 +145,19 @@ struct T1Split {
   hipStream_t aux;
   hipEvent_t ev_fork, ev_join;
 };
+// order (nblk ints) and qctr (one int): scratch of the persistent
+// lanes-per-block launch, used when that launch is chosen (may be null).
 void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
                const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
-               uint32_t* tail, void* sppf, hipStream_t st, const T1Split* sp = nullptr);
+               uint32_t* tail, void* sppf, hipStream_t st, const T1Split* sp = nullptr, int* order = nullptr,
+               int* qctr = nullptr);
 void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,
                     const uint8_t* kb, const void* sppf, hipStream_t st);
 // table: per-block entries (P | k << 8 | len << 16); off: payload offsets
 // within each field's base payload (which starts at out + 48 + 4 nblk).
 void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
-               const int64_t* off, hipStream_t st, const T1Split* sp = nullptr);
+               const int64_t* off, hipStream_t st, const T1Split* sp = nullptr, int* order = nullptr,
+               int* qctr = nullptr);
 void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
                     const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
                     uint32_t* tail, void* sppf, hipStream_t st);
@@ -170,6 +174,7 @@ struct Tuning {
   int spiht;         // 0 LDS kernels by capacity class, 1 global-memory lists for every tile
   int t1_lanes;      // lanes-per-block kernels: blocks per wavefront (0 by work size, 1, 4, 16, 64)
   int t1_split;      // percent of a lanes-per-block launch's blocks run concurrently by the wave kernel
+  int t1_persist;    // lanes-per-block encoding as one persistent launch over a work counter (0 off, 1 on)
 };
 Tuning tuning();
 

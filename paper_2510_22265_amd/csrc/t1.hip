@@ -19,6 +19,8 @@
 //    significance-propagation pass" bit recorded by the encoder.
 //  * k_t1_decode: one lane per block; the decoder for decompression.
 #include "common.h"
+
+#include <algorithm>
 #include "t1_common.h"
 
 #include <cstdlib>
@@ -236,17 +238,13 @@ struct T1Lane {
 // Tier-1 encoder: one lane per code-block.
 // ------------------------------------------------------------------------
 template <typename M, int ROWS, int LANES>
-__global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
-                                                     int nblk, int cbh, const M* __restrict__ planes,
-                                                     const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
-                                                     uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
-                                                     int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
-                                                     uint32_t* __restrict__ tailt, M* __restrict__ sppf) {
-  __shared__ T1Shared<M, ROWS, LANES> S;
-  int lane = threadIdx.x;
-  S.fill_tables(lane, LANES);
-  __syncthreads();
-  int b = blockIdx.x * LANES + lane;
+__device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES>& S, int lane, int b, const FieldDev* __restrict__ F,
+                                             const Blk* __restrict__ blk, int nblk, int cbh,
+                                             const M* __restrict__ planes, const M* __restrict__ signs,
+                                             const uint8_t* __restrict__ pbv, uint8_t* __restrict__ cw,
+                                             int32_t* __restrict__ Rt, int64_t* __restrict__ Dt,
+                                             int32_t* __restrict__ bpt, uint32_t* __restrict__ tailt,
+                                             M* __restrict__ sppf) {
   if (b >= nblk) return;
   Blk k = blk[b];
   if (!F[k.field].active) return;
@@ -446,6 +444,88 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
   for (int y = 0; y < k.h; y++) spo[y] = S.aux[y][lane];
 }
 
+// One lane per code-block.  Without `order`, lane i of workgroup g codes
+// block g * LANES + i.  With it (persistent launch: a grid the chip keeps
+// resident), each workgroup takes the next group of LANES entries of
+// `order` from the counter *qctr (zero at launch) until none is left; the
+// order puts blocks with more bit-planes first, so the longest blocks start
+// early and a workgroup's lanes hold blocks of similar length.
+template <typename M, int ROWS, int LANES>
+__global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                     int nblk, int cbh, const M* __restrict__ planes,
+                                                     const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
+                                                     uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
+                                                     int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
+                                                     uint32_t* __restrict__ tailt, M* __restrict__ sppf,
+                                                     const int* __restrict__ order, int* __restrict__ qctr) {
+  __shared__ T1Shared<M, ROWS, LANES> S;
+  const int lane = threadIdx.x;
+  S.fill_tables(lane, LANES);
+  __syncthreads();
+  if (!order) {
+    t1_enc_block<M, ROWS, LANES>(S, lane, blockIdx.x * LANES + lane, F, blk, nblk, cbh, planes, signs, pbv, cw, Rt,
+                                 Dt, bpt, tailt, sppf);
+    return;
+  }
+  const int ngroups = (nblk + LANES - 1) / LANES;
+  for (;;) {
+    int g = 0;
+    if (lane == 0) g = atomicAdd(qctr, 1);
+    g = __shfl(g, 0);   // one wavefront per workgroup (LANES <= 64)
+    if (g >= ngroups) break;
+    const int i = g * LANES + lane;
+    if (i < nblk)
+      t1_enc_block<M, ROWS, LANES>(S, lane, order[i], F, blk, nblk, cbh, planes, signs, pbv, cw, Rt, Dt, bpt, tailt,
+                                   sppf);
+  }
+}
+
+// Block order of the persistent launches: by number of bit-planes P_b,
+// largest first, stable within a P_b (one workgroup: per-thread counts of
+// a contiguous share of the blocks, a scan over (P_b, thread), a scatter);
+// also zeroes the work counter.
+template <typename KeyF>
+__device__ __forceinline__ void order_by_key(int nblk, KeyF key, int* __restrict__ order, int* __restrict__ qctr) {
+  __shared__ int cnt[kQBits + 1][256];
+  __shared__ int base[kQBits + 1];
+  const int t = threadIdx.x;
+  const int per = (nblk + 255) / 256;
+  const int b0 = t * per < nblk ? t * per : nblk;
+  const int b1 = b0 + per < nblk ? b0 + per : nblk;
+  for (int k = 0; k <= kQBits; k++) cnt[k][t] = 0;
+  for (int b = b0; b < b1; b++) cnt[key(b)][t]++;
+  __syncthreads();
+  if (t <= kQBits) {   // exclusive scan of row t
+    int sum = 0;
+    for (int u = 0; u < 256; u++) { const int v = cnt[t][u]; cnt[t][u] = sum; sum += v; }
+    base[t] = sum;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int sum = 0;
+    for (int k = 0; k <= kQBits; k++) { const int v = base[k]; base[k] = sum; sum += v; }
+    *qctr = 0;
+  }
+  __syncthreads();
+  for (int b = b0; b < b1; b++) {
+    const int k = key(b);
+    order[base[k] + cnt[k][t]] = b;
+    cnt[k][t]++;
+  }
+}
+__global__ __launch_bounds__(256) void k_t1_order(const uint8_t* __restrict__ pb, int nblk, int* __restrict__ order,
+                                                  int* __restrict__ qctr) {
+  order_by_key(nblk, [&](int b) { const int P = pb[b]; return kQBits - (P < kQBits ? P : kQBits); }, order, qctr);
+}
+// decoding: by the planes its kept passes reach, k_b / 3 (k_b <= 3 * 23 - 2)
+__global__ __launch_bounds__(256) void k_t1_order_dec(const uint32_t* __restrict__ table, int nblk,
+                                                      int* __restrict__ order, int* __restrict__ qctr) {
+  order_by_key(nblk, [&](int b) {
+    const int kp = (int)((table[b] >> 8) & 0xFFu) / 3;
+    return kQBits - (kp < kQBits ? kp : kQBits);
+  }, order, qctr);
+}
+
 // ------------------------------------------------------------------------
 // Closed-form base reconstruction for the kept passes (one wave per block).
 // ------------------------------------------------------------------------
@@ -558,14 +638,10 @@ __device__ __forceinline__ int mq_decode(MQDec& d, uint8_t* cs_ptr, const uint32
 // in yhat's storage as integers until the block is finished.
 // ------------------------------------------------------------------------
 template <typename M, int ROWS, int LANES>
-__global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
-                                                     int nblk, const uint32_t* __restrict__ table,
-                                                     const int64_t* __restrict__ off) {
-  __shared__ T1Shared<M, ROWS, LANES> S;     // aux = coded in the current plane
-  int lane = threadIdx.x;
-  S.fill_tables(lane, LANES);
-  __syncthreads();
-  int b = blockIdx.x * LANES + lane;
+__device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES>& S, int lane, int b,
+                                             const FieldDev* __restrict__ F, const Blk* __restrict__ blk, int nblk,
+                                             const uint32_t* __restrict__ table, const int64_t* __restrict__ off) {
+  // S.aux = coded in the current plane
   if (b >= nblk) return;
   Blk k = blk[b];
   const FieldDev& f = F[k.field];
@@ -766,6 +842,32 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
   }
 }
 
+// One lane per code-block; with `order`, a persistent launch as for the
+// encoder (blocks ordered by coding passes kept, most first).
+template <typename M, int ROWS, int LANES>
+__global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                     int nblk, const uint32_t* __restrict__ table,
+                                                     const int64_t* __restrict__ off, const int* __restrict__ order,
+                                                     int* __restrict__ qctr) {
+  __shared__ T1Shared<M, ROWS, LANES> S;
+  const int lane = threadIdx.x;
+  S.fill_tables(lane, LANES);
+  __syncthreads();
+  if (!order) {
+    t1_dec_block<M, ROWS, LANES>(S, lane, blockIdx.x * LANES + lane, F, blk, nblk, table, off);
+    return;
+  }
+  const int ngroups = (nblk + LANES - 1) / LANES;
+  for (;;) {
+    int g = 0;
+    if (lane == 0) g = atomicAdd(qctr, 1);
+    g = __shfl(g, 0);   // one wavefront per workgroup (LANES <= 64)
+    if (g >= ngroups) break;
+    const int i = g * LANES + lane;
+    if (i < nblk) t1_dec_block<M, ROWS, LANES>(S, lane, order[i], F, blk, nblk, table, off);
+  }
+}
+
 #undef SR
 #undef NR
 
@@ -801,15 +903,31 @@ constexpr int t1_lanes_max() {
     }                                                              \
   } while (0)
 
+// Workgroups of `threads` threads the device keeps resident at once.
+template <typename K>
+static int resident_groups(K kernel, int threads) {
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
+  return (cus > 0 ? cus : 1) * (per > 0 ? per : 1);
+}
+
+// order/qctr non-null: persistent launch (order filled by k_t1_order first).
 template <typename M, int ROWS>
 static void launch_encode(int nblk, const FieldDev* F, const Blk* blk, int cbh, const void* planes, const void* signs,
                           const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail,
-                          void* sppf, hipStream_t st) {
+                          void* sppf, hipStream_t st, int* order, int* qctr) {
   constexpr int LM = t1_lanes_max<M, ROWS>();
   int ln = pick_lanes(nblk, LM);
+  if (order) k_t1_order<<<1, 256, 0, st>>>(pb, nblk, order, qctr);
 #define ENC_L(LN)                                                                                                  \
-  k_t1_encode<M, ROWS, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(F, blk, nblk, cbh, (const M*)planes,               \
-                                                               (const M*)signs, pb, cw, R, D, bp, tail, (M*)sppf)
+  do {                                                                                                             \
+    const int groups = (nblk + LN - 1) / LN;                                                                       \
+    const int grid = order ? std::min(groups, resident_groups(k_t1_encode<M, ROWS, LN>, LN)) : groups;             \
+    k_t1_encode<M, ROWS, LN><<<grid, LN, 0, st>>>(F, blk, nblk, cbh, (const M*)planes, (const M*)signs, pb, cw, R, \
+                                                  D, bp, tail, (M*)sppf, order, qctr);                             \
+  } while (0)
   if (ln == 1) ENC_L(1);
   else if (ln == 4) ENC_L(4);
   else if (ln == 16 || LM == 16) ENC_L((LM >= 16 ? 16 : 4));
@@ -819,10 +937,16 @@ static void launch_encode(int nblk, const FieldDev* F, const Blk* blk, int cbh, 
 
 template <typename M, int ROWS>
 static void launch_decode(int nblk, const FieldDev* F, const Blk* blk, const uint32_t* table, const int64_t* off,
-                          hipStream_t st) {
+                          hipStream_t st, int* order, int* qctr) {
   constexpr int LM = t1_lanes_max<M, ROWS>();
   int ln = pick_lanes(nblk, LM);
-#define DEC_L(LN) k_t1_decode<M, ROWS, LN><<<(nblk + LN - 1) / LN, LN, 0, st>>>(F, blk, nblk, table, off)
+  if (order) k_t1_order_dec<<<1, 256, 0, st>>>(table, nblk, order, qctr);
+#define DEC_L(LN)                                                                                                  \
+  do {                                                                                                             \
+    const int groups = (nblk + LN - 1) / LN;                                                                       \
+    const int grid = order ? std::min(groups, resident_groups(k_t1_decode<M, ROWS, LN>, LN)) : groups;             \
+    k_t1_decode<M, ROWS, LN><<<grid, LN, 0, st>>>(F, blk, nblk, table, off, order, qctr);                          \
+  } while (0)
   if (ln == 1) DEC_L(1);
   else if (ln == 4) DEC_L(4);
   else if (ln == 16 || LM == 16) DEC_L((LM >= 16 ? 16 : 4));
@@ -862,15 +986,24 @@ static int split_count(int nblk, const T1Split* sp) {
   return pct <= 0 ? 0 : (int)((int64_t)nblk * (pct > 100 ? 100 : pct) / 100);
 }
 
+// Persistent lanes-per-block launches (block order by bit-planes, work
+// counter): tuning t1_persist, or EBCC_T1_PERSIST=0/1.
+static bool use_persist() {
+  const char* e = getenv("EBCC_T1_PERSIST");
+  if (e && e[0]) return e[0] == '1';
+  return tuning().t1_persist != 0;
+}
+
 void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes, const void* signs,
                const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail, void* sppf,
-               hipStream_t st, const T1Split* sp) {
+               hipStream_t st, const T1Split* sp, int* order, int* qctr) {
   if (nblk <= 0) return;
   if (use_wave(nblk, false)) {
     t1_encode_wave(F, blk, nblk, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st);
     return;
   }
-  const int s = split_count(nblk, sp);
+  if (!(order && qctr && use_persist())) order = nullptr, qctr = nullptr;
+  const int s = order ? 0 : split_count(nblk, sp);
   if (s > 0) {
     (void)hipEventRecord(sp->ev_fork, st);
     (void)hipStreamWaitEvent(sp->aux, sp->ev_fork, 0);
@@ -884,7 +1017,7 @@ void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, co
     bp += (size_t)s * kPassStride; tail += (size_t)s * kPassStride;
     nblk -= s;
   }
-#define ENC(MT, RW) launch_encode<MT, RW>(nblk, F, blk, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st)
+#define ENC(MT, RW) launch_encode<MT, RW>(nblk, F, blk, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st, order, qctr)
   T1_DISPATCH(cbw, cbh, ENC);
 #undef ENC
   if (s > 0) {
@@ -904,20 +1037,21 @@ void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
 }
 
 void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
-               const int64_t* off, hipStream_t st, const T1Split* sp) {
+               const int64_t* off, hipStream_t st, const T1Split* sp, int* order, int* qctr) {
   if (nblk <= 0) return;
   if (use_wave(nblk, true)) {
     t1_decode_wave(F, blk, nblk, cbw, table, off, st);
     return;
   }
-  const int s = split_count(nblk, sp);
+  if (!(order && qctr && use_persist())) order = nullptr, qctr = nullptr;
+  const int s = order ? 0 : split_count(nblk, sp);
   if (s > 0) {
     (void)hipEventRecord(sp->ev_fork, st);
     (void)hipStreamWaitEvent(sp->aux, sp->ev_fork, 0);
     t1_decode_wave(F, blk, s, cbw, table, off, sp->aux);
     blk += s; table += s; off += s; nblk -= s;
   }
-#define DEC(MT, RW) launch_decode<MT, RW>(nblk, F, blk, table, off, st)
+#define DEC(MT, RW) launch_decode<MT, RW>(nblk, F, blk, table, off, st, order, qctr)
   T1_DISPATCH(cbw, cbh, DEC);
 #undef DEC
   if (s > 0) {

@@ -34,7 +34,7 @@ class Params(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("t1_encoder", C.c_int32), ("t1_decoder", C.c_int32),
                 ("t1_wave_max", C.c_int32), ("spiht", C.c_int32), ("t1_lanes", C.c_int32),
-                ("t1_split", C.c_int32)]
+                ("t1_split", C.c_int32), ("t1_persist", C.c_int32)]
 
 
 class EbccError(RuntimeError):
@@ -296,7 +296,8 @@ def get_tuning():
 
 def set_tuning(**kw):
     """Change kernel choices (fields of ebcc_tuning: t1_encoder, t1_decoder,
-    t1_wave_max, spiht, t1_lanes, t1_split); returns the previous ones."""
+    t1_wave_max, spiht, t1_lanes, t1_split, t1_persist); returns the previous
+    ones."""
     old = get_tuning()
     t = Tuning()
     t.struct_size = C.sizeof(Tuning)

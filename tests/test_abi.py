@@ -73,12 +73,13 @@ def test_tuning_struct_and_round_trip():
     ebcc = _lib()
     assert fields == [f for f, _ in ebcc.Tuning._fields_]
     old = ebcc.get_tuning()
-    assert old == {"t1_encoder": 0, "t1_decoder": 0, "t1_wave_max": 32768, "spiht": 0, "t1_lanes": 0, "t1_split": 10}
+    assert old == {"t1_encoder": 0, "t1_decoder": 0, "t1_wave_max": 32768, "spiht": 0, "t1_lanes": 0, "t1_split": 10,
+                   "t1_persist": 1}
     try:
-        ebcc.set_tuning(t1_encoder=2, t1_wave_max=100, spiht=1, t1_lanes=64, t1_split=30)
+        ebcc.set_tuning(t1_encoder=2, t1_wave_max=100, spiht=1, t1_lanes=64, t1_split=30, t1_persist=0)
         assert ebcc.get_tuning() == {"t1_encoder": 2, "t1_decoder": 0, "t1_wave_max": 100, "spiht": 1, "t1_lanes": 64,
-                                     "t1_split": 30}
-        for bad in (dict(spiht=5), dict(t1_lanes=8), dict(t1_split=101)):
+                                     "t1_split": 30, "t1_persist": 0}
+        for bad in (dict(spiht=5), dict(t1_lanes=8), dict(t1_split=101), dict(t1_persist=2)):
             try:
                 ebcc.set_tuning(**bad)
                 assert False

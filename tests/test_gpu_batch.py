@@ -214,13 +214,14 @@ def test_batch_tuning_api(gpu, ref, tun):
 
 
 @pytest.mark.parametrize("lanes", [4, 16, 64])
-@pytest.mark.parametrize("split", [0, 50])
-def test_batch_lanes_per_wavefront(gpu, ref, lanes, split):
+@pytest.mark.parametrize("split,persist", [(0, 0), (50, 0), (0, 1)])
+def test_batch_lanes_per_wavefront(gpu, ref, lanes, split, persist):
     """The lanes-per-block tier-1 coders with 4, 16 and 64 blocks per
-    wavefront (partly filled wavefronts, ragged and tiny blocks), with and
-    without half the encoder's blocks handed to the wavefront kernel: the
-    oracle's streams and decodes."""
-    old = gpu.set_tuning(t1_encoder=2, t1_decoder=2, t1_lanes=lanes, t1_split=split)
+    wavefront (partly filled wavefronts, ragged and tiny blocks), one
+    workgroup per group of blocks with and without half the encoder's blocks
+    handed to the wavefront kernel, and as persistent launches over a work
+    counter: the oracle's streams and decodes."""
+    old = gpu.set_tuning(t1_encoder=2, t1_decoder=2, t1_lanes=lanes, t1_split=split, t1_persist=persist)
     try:
         xs, eps = _mixed_fields()
         _check_batch(gpu, ref, xs, eps)
