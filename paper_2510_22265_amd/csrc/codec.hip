@@ -960,6 +960,7 @@ struct Call {
   uint32_t *tail, *tlen, *tent, *bent;
   uint32_t *tcut, *tbits;   // byte-cut residuals: per tile bit counts around plane ns, final code bits
   int *border, *qctr;       // persistent tier-1 launches: block order and work counter
+  int* tix_sorted;          // decoding: the LDS classes' tiles, longest payload first
   bool want_cpos = false;   // compression with byte-cut residuals: every coded field gets a cpos plane
   int* misfit;
   Blk* d_blk_own;
@@ -1194,6 +1195,7 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
   c.tbits = cv.take<uint32_t>(nt);
   c.border = cv.take<int>(nb);
   c.qctr = cv.take<int>(1);
+  c.tix_sorted = cv.take<int>(nt);
   c.collect = cv.take<int64_t>(8 * (size_t)c.nf);
   // candidates per field and search round: "all planes" and the nodes of
   // spec_depth levels of the bisection tree
@@ -2230,10 +2232,15 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
           // small tiles on one stream, the larger classes on another
           const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
           hipStream_t sb = c.ws->aux2;
+          // the LDS classes' tiles longest payload first (batches: the
+          // longest decodes start first)
+          int *o0 = c.tix_sorted, *o1 = o0 + c.ncls[0];
+          spiht_tiles_longest_first(t0, c.ncls[0], c.tent, o0, sa);
+          spiht_tiles_longest_first(t1, c.ncls[1], c.tent, o1, sb);
           spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sb);
           spiht_decode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.toff, c.misfit, sb);
-          spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, t1, c.ncls[1], c.toff, c.misfit, sb);
-          spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, t0, c.ncls[0], c.toff, c.misfit, sa);
+          spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, o1, c.ncls[1], c.toff, c.misfit, sb);
+          spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, o0, c.ncls[0], c.toff, c.misfit, sa);
         }
         // all of the residual's inverse DWT but its last pass, in the shadow
         // of tier-1 decoding, once both SPIHT streams are done

@@ -117,6 +117,42 @@ __host__ __device__ __forceinline__ void cut_tile_mode(int kind, int J, int tl, 
   *sort_only = (kind == 0 && tl < J) || (kind == 1 && tl > J) || (kind == 0 && tl == J);
 }
 
+// Order of n work items by a key in [0, kQBits] (0 first), stable within a
+// key, for the persistent and longest-first launches.  One workgroup of 256
+// threads: per-thread counts over a contiguous share of the items, a scan
+// over (key, thread), a scatter.  order[i] receives map[item] (the item
+// itself when map is null); *qctr, when given, is zeroed (a work counter).
+template <typename KeyF>
+__device__ __forceinline__ void order_by_key(int n, KeyF key, const int* __restrict__ map, int* __restrict__ order,
+                                             int* __restrict__ qctr) {
+  __shared__ int cnt[kQBits + 1][256];
+  __shared__ int base[kQBits + 1];
+  const int t = threadIdx.x;
+  const int per = (n + 255) / 256;
+  const int b0 = t * per < n ? t * per : n;
+  const int b1 = b0 + per < n ? b0 + per : n;
+  for (int k = 0; k <= kQBits; k++) cnt[k][t] = 0;
+  for (int b = b0; b < b1; b++) cnt[key(b)][t]++;
+  __syncthreads();
+  if (t <= kQBits) {   // exclusive scan of row t
+    int sum = 0;
+    for (int u = 0; u < 256; u++) { const int v = cnt[t][u]; cnt[t][u] = sum; sum += v; }
+    base[t] = sum;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int sum = 0;
+    for (int k = 0; k <= kQBits; k++) { const int v = base[k]; base[k] = sum; sum += v; }
+    if (qctr) *qctr = 0;
+  }
+  __syncthreads();
+  for (int b = b0; b < b1; b++) {
+    const int k = key(b);
+    order[base[k] + cnt[k][t]] = map ? map[b] : b;
+    cnt[k][t]++;
+  }
+}
+
 // Device kernels' launch wrappers (all asynchronous on `st`).
 // dwt.hip
 enum { PRO_COPY = 0, PRO_NORM = 1, PRO_NORM_MINUS = 2 };
@@ -228,5 +264,9 @@ void spiht_cut_tiles(const FieldDev* F, const TileD* tiles, int nt, const uint32
                      uint32_t* tent, uint32_t* tbits, hipStream_t st);
 void spiht_decode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, const int64_t* toff,
                       int* misfit, hipStream_t st);
+// The tiles tix[0 .. n) in order of their payload length (from their table
+// entries tent), longest first, into out: a launch over them starts the
+// longest decodes first.
+void spiht_tiles_longest_first(const int* tix, int n, const uint32_t* tent, int* out, hipStream_t st);
 
 }  // namespace ebcc

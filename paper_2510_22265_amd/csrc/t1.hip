@@ -480,42 +480,11 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
   }
 }
 
-// Block order of the persistent launches: by number of bit-planes P_b,
-// largest first, stable within a P_b (one workgroup: per-thread counts of
-// a contiguous share of the blocks, a scan over (P_b, thread), a scatter);
-// also zeroes the work counter.
-template <typename KeyF>
-__device__ __forceinline__ void order_by_key(int nblk, KeyF key, int* __restrict__ order, int* __restrict__ qctr) {
-  __shared__ int cnt[kQBits + 1][256];
-  __shared__ int base[kQBits + 1];
-  const int t = threadIdx.x;
-  const int per = (nblk + 255) / 256;
-  const int b0 = t * per < nblk ? t * per : nblk;
-  const int b1 = b0 + per < nblk ? b0 + per : nblk;
-  for (int k = 0; k <= kQBits; k++) cnt[k][t] = 0;
-  for (int b = b0; b < b1; b++) cnt[key(b)][t]++;
-  __syncthreads();
-  if (t <= kQBits) {   // exclusive scan of row t
-    int sum = 0;
-    for (int u = 0; u < 256; u++) { const int v = cnt[t][u]; cnt[t][u] = sum; sum += v; }
-    base[t] = sum;
-  }
-  __syncthreads();
-  if (t == 0) {
-    int sum = 0;
-    for (int k = 0; k <= kQBits; k++) { const int v = base[k]; base[k] = sum; sum += v; }
-    *qctr = 0;
-  }
-  __syncthreads();
-  for (int b = b0; b < b1; b++) {
-    const int k = key(b);
-    order[base[k] + cnt[k][t]] = b;
-    cnt[k][t]++;
-  }
-}
+// Block orders of the persistent launches (order_by_key, common.h).
 __global__ __launch_bounds__(256) void k_t1_order(const uint8_t* __restrict__ pb, int nblk, int* __restrict__ order,
                                                   int* __restrict__ qctr) {
-  order_by_key(nblk, [&](int b) { const int P = pb[b]; return kQBits - (P < kQBits ? P : kQBits); }, order, qctr);
+  order_by_key(nblk, [&](int b) { const int P = pb[b]; return kQBits - (P < kQBits ? P : kQBits); }, nullptr, order,
+               qctr);
 }
 // decoding: by the planes its kept passes reach, k_b / 3 (k_b <= 3 * 23 - 2)
 __global__ __launch_bounds__(256) void k_t1_order_dec(const uint32_t* __restrict__ table, int nblk,
@@ -523,7 +492,7 @@ __global__ __launch_bounds__(256) void k_t1_order_dec(const uint32_t* __restrict
   order_by_key(nblk, [&](int b) {
     const int kp = (int)((table[b] >> 8) & 0xFFu) / 3;
     return kQBits - (kp < kQBits ? kp : kQBits);
-  }, order, qctr);
+  }, nullptr, order, qctr);
 }
 
 // ------------------------------------------------------------------------
