@@ -513,6 +513,27 @@ EXPORT int ebcc_ref_sc_ctx(int hc, int vc, int* xorbit) {
   return ctx[hc + 1][vc + 1];
 }
 
+/* Raw (uncoded) bits of the bypassed passes: written and read MSB-first;
+ * reading past the end gives 0. */
+typedef struct { uint8_t* buf; long nbits, cap; } rawbits_t;
+static void raw_put(rawbits_t* r, int bit) {
+  if ((r->nbits >> 3) >= r->cap) {
+    long nc = r->cap * 2 + 256;
+    r->buf = (uint8_t*)realloc(r->buf, (size_t)nc);
+    memset(r->buf + r->cap, 0, (size_t)(nc - r->cap));
+    r->cap = nc;
+  }
+  if (bit) r->buf[r->nbits >> 3] |= (uint8_t)(0x80 >> (r->nbits & 7));
+  r->nbits++;
+}
+typedef struct { const uint8_t* buf; long nbytes, pos; } rawrd_t;
+static int raw_get(rawrd_t* r) {
+  long by = r->pos >> 3;
+  int bit = by < r->nbytes ? (r->buf[by] >> (7 - (r->pos & 7))) & 1 : 0;
+  r->pos++;
+  return bit;
+}
+
 typedef struct {
   int w, h, orient, dec;
   const uint32_t* q;      /* encoder: magnitudes */
@@ -522,9 +543,17 @@ typedef struct {
   mqe_t* e;
   mqd_t* d;
   int64_t dd;             /* distortion reduction of the current pass */
+  int rawpass;            /* the current pass is bypassed: its decisions are raw bits */
+  rawbits_t* rw;          /* encoder: raw bits */
+  rawrd_t* rr;            /* decoder: raw bits */
 } t1_t;
 
 static int t1_code(t1_t* t, int cx, int bit) {
+  if (t->rawpass) {
+    if (t->dec) return raw_get(t->rr);
+    raw_put(t->rw, bit);
+    return bit;
+  }
   if (t->dec) return mqd_decode(t->d, cx);
   mqe_encode(t->e, cx, bit);
   return bit;
@@ -554,6 +583,7 @@ static void t1_code_sign(t1_t* t, int y, int x) {
   hc = hc > 1 ? 1 : (hc < -1 ? -1 : hc);
   vc = vc > 1 ? 1 : (vc < -1 ? -1 : vc);
   int xr, cx = ebcc_ref_sc_ctx(hc, vc, &xr);
+  if (t->rawpass) xr = 0;                      /* a bypassed pass sends the sign itself */
   int i = y * t->w + x;
   int b = t1_code(t, cx, t->dec ? 0 : (t->neg[i] ^ xr));
   if (t->dec) t->neg[i] = (uint8_t)(b ^ xr);
@@ -650,27 +680,48 @@ static void t1_cp(t1_t* t, int p) {
 
 static int bitlen32(uint32_t v) { int n = 0; while (v) { n++; v >>= 1; } return n; }
 
+/* Selective arithmetic-coding bypass (T.800 D.6, the "lazy" mode; a
+ * stream option): the significance propagation and magnitude refinement
+ * passes after the first ten (bit-planes below the fourth from the top) send
+ * their decisions as raw bits, sign bits included; cleanup passes stay
+ * arithmetic coded.  One codeword per block still: after k > 10 passes it is
+ * u16 (little-endian) the raw byte count, the MQ codeword terminated after
+ * the last arithmetic-coded pass <= k, then the raw bits of the bypassed
+ * passes <= k (MSB-first, zero padded).  The MQ coder's state runs on across
+ * the bypassed passes.  A pass whose MQ part exceeds BYP_MQ_MAX bytes or
+ * whose raw part exceeds BYP_RAW_MAX bytes is never kept. */
+#define BYP_FIRST 11
+#define BYP_MQ_MAX 49000
+#define BYP_RAW_MAX 16000
+static int t1_raw_pass(int bypass, int k, int ty) { return bypass && k >= BYP_FIRST && ty < 2; }
+
 /* Result of encoding one code-block with all of its coding passes. */
 typedef struct {
-  int P, npass;
+  int P, npass, bypass;
   int32_t R[3 * QMAX_BITS];        /* R[k]: codeword length terminated after k passes */
   int64_t D[3 * QMAX_BITS];        /* D[k]: cumulative distortion reduction */
-  long bp[3 * QMAX_BITS];
+  long bp[3 * QMAX_BITS];          /* MQ termination of the last arithmetic-coded pass <= k */
   uint8_t tail[3 * QMAX_BITS][3];
+  int32_t Rmq[3 * QMAX_BITS];      /* its length */
+  long rawb[3 * QMAX_BITS];        /* raw bits of the passes <= k */
   mqe_t e;
+  rawbits_t raw;
 } t1enc_t;
 
 /* Pass k (0-based) of a block with P magnitude planes: pass 0 is the cleanup
  * pass of plane P-1; plane p < P-1 has SPP, MRP, CP as passes
  * 3(P-2-p)+1, +2, +3.  Total 3P-2 passes. */
-static void t1_encode_block(const uint32_t* q, const uint8_t* neg, int w, int h, int orient, t1enc_t* out) {
+static void t1_encode_block(const uint32_t* q, const uint8_t* neg, int w, int h, int orient, int bypass,
+                            t1enc_t* out) {
   int n = w * h;
   uint32_t mx = 0;
   for (int i = 0; i < n; i++) if (q[i] > mx) mx = q[i];
   out->P = bitlen32(mx);
   out->npass = out->P ? 3 * out->P - 2 : 0;
+  out->bypass = bypass;
   mqe_init(&out->e);
-  out->R[0] = 0; out->D[0] = 0;
+  out->R[0] = 0; out->D[0] = 0; out->Rmq[0] = 0; out->rawb[0] = 0; out->bp[0] = -1;
+  out->raw.buf = NULL; out->raw.nbits = 0; out->raw.cap = 0;
   if (!out->P) return;
   t1_t t = {0};
   t.w = w; t.h = h; t.orient = orient; t.dec = 0; t.q = q;
@@ -679,15 +730,30 @@ static void t1_encode_block(const uint32_t* q, const uint8_t* neg, int w, int h,
   memcpy(t.neg, neg, (size_t)n);
   t.m = (uint32_t*)calloc((size_t)n, 4); t.pk = (int8_t*)calloc((size_t)n, 1);
   t.e = &out->e;
+  t.rw = &out->raw;
   int k = 0;
   const long dec0 = g_mq_enc;
   for (int p = out->P - 1; p >= 0; p--) {
     for (int ty = (p == out->P - 1) ? 2 : 0; ty < 3; ty++) {
       t.dd = 0;
+      t.rawpass = t1_raw_pass(bypass, k + 1, ty);
       if (ty == 0) t1_spp(&t, p); else if (ty == 1) t1_mrp(&t, p); else t1_cp(&t, p);
       k++;
       out->D[k] = out->D[k - 1] + t.dd;
-      out->R[k] = (int32_t)mqe_flush_copy(&out->e, out->tail[k], &out->bp[k]);
+      if (t.rawpass) {           /* the MQ part is the last arithmetic-coded pass's */
+        out->Rmq[k] = out->Rmq[k - 1]; out->bp[k] = out->bp[k - 1];
+        memcpy(out->tail[k], out->tail[k - 1], 3);
+      } else {
+        out->Rmq[k] = (int32_t)mqe_flush_copy(&out->e, out->tail[k], &out->bp[k]);
+      }
+      out->rawb[k] = out->raw.nbits;
+      const long rby = (out->rawb[k] + 7) >> 3;
+      if (bypass && k >= BYP_FIRST) {
+        out->R[k] = (int32_t)(2 + out->Rmq[k] + rby);
+        if (out->Rmq[k] > BYP_MQ_MAX || rby > BYP_RAW_MAX) out->R[k] = SEG_RMAX + 1;
+      } else {
+        out->R[k] = out->Rmq[k];
+      }
     }
   }
   g_mq_enc_blocks++;
@@ -698,50 +764,77 @@ static void t1_encode_block(const uint32_t* q, const uint8_t* neg, int w, int h,
  * termination touches, then the termination bytes of pass k. */
 static void t1_codeword(const t1enc_t* te, int k, uint8_t* out) {
   if (k == 0) return;
-  long R = te->R[k], bp0 = te->bp[k];
+  long R = te->Rmq[k], bp0 = te->bp[k];
+  const int byp = te->bypass && k >= BYP_FIRST;
+  const long rby = byp ? (te->rawb[k] + 7) >> 3 : 0;
+  if (byp) { out[0] = (uint8_t)rby; out[1] = (uint8_t)(rby >> 8); out += 2; }
   for (long j = 0; j < R; j++) out[j] = (j < bp0) ? mqe_get(&te->e, j) : te->tail[k][j - bp0];
+  if (byp) {
+    for (long j = 0; j < rby; j++) out[R + j] = te->raw.buf[j];
+    if (te->rawb[k] & 7) out[R + rby - 1] &= (uint8_t)(0xFF << (8 - (te->rawb[k] & 7)));
+  }
 }
 /* Decode k passes of a codeword: magnitudes m, signs, lowest known plane. */
-static void t1_decode_block(const uint8_t* cw, long len, int w, int h, int orient, int P, int k,
-                            uint32_t* m, uint8_t* neg, int8_t* pk) {
+static int t1_decode_block(const uint8_t* cw, long len, int w, int h, int orient, int P, int k, int bypass,
+                           uint32_t* m, uint8_t* neg, int8_t* pk) {
   int n = w * h;
   memset(m, 0, sizeof(uint32_t) * (size_t)n);
   memset(neg, 0, (size_t)n);
   memset(pk, 0, (size_t)n);
-  if (P == 0 || k == 0) return;
+  if (P == 0 || k == 0) return REF_OK;
+  rawrd_t rr = {NULL, 0, 0};
+  if (bypass && k >= BYP_FIRST) {            /* u16 raw bytes, MQ codeword, raw bits */
+    if (len < 2) return REF_ECORRUPT;
+    long rby = cw[0] | ((long)cw[1] << 8);
+    if (2 + rby > len) return REF_ECORRUPT;
+    rr.buf = cw + len - rby; rr.nbytes = rby;
+    cw += 2; len -= 2 + rby;
+  }
   mqd_t d; mqd_init(&d, cw, len);
   t1_t t = {0};
-  t.w = w; t.h = h; t.orient = orient; t.dec = 1; t.d = &d;
+  t.w = w; t.h = h; t.orient = orient; t.dec = 1; t.d = &d; t.rr = &rr;
   t.sig = (uint8_t*)calloc((size_t)n, 1); t.vis = (uint8_t*)calloc((size_t)n, 1);
   t.ref = (uint8_t*)calloc((size_t)n, 1); t.neg = neg; t.m = m; t.pk = pk;
   int done = 0;
   const long dec0 = g_mq_dec;
   for (int p = P - 1; p >= 0 && done < k; p--)
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < k; ty++) {
+      t.rawpass = t1_raw_pass(bypass, done + 1, ty);
       if (ty == 0) t1_spp(&t, p); else if (ty == 1) t1_mrp(&t, p); else t1_cp(&t, p);
       done++;
     }
   g_mq_dec_blocks++;
   if (g_mq_dec - dec0 > g_mq_dec_max) g_mq_dec_max = g_mq_dec - dec0;
   free(t.sig); free(t.vis); free(t.ref);
+  return REF_OK;
 }
 
 /* Test hooks for one block. */
-EXPORT int ebcc_ref_t1_encode(const uint32_t* q, const uint8_t* neg, int w, int h, int orient, int keep,
+EXPORT int ebcc_ref_t1_encode(const uint32_t* q, const uint8_t* neg, int w, int h, int orient, int bypass, int keep,
                               int32_t* R, int64_t* D, uint8_t* out, long cap, long* len) {
   t1enc_t* te = (t1enc_t*)calloc(1, sizeof(t1enc_t));
-  t1_encode_block(q, neg, w, h, orient, te);
+  t1_encode_block(q, neg, w, h, orient, bypass, te);
   for (int k = 0; k <= te->npass; k++) { if (R) R[k] = te->R[k]; if (D) D[k] = te->D[k]; }
   if (keep < 0 || keep > te->npass) keep = te->npass;
   int rc = te->npass;
   *len = te->R[keep];
   if (*len > cap) rc = REF_ENOSPC; else t1_codeword(te, keep, out);
-  free(te->e.raw); free(te);
+  free(te->e.raw); free(te->raw.buf); free(te);
   return rc;
 }
-EXPORT void ebcc_ref_t1_decode(const uint8_t* cw, long len, int w, int h, int orient, int P, int k,
-                               uint32_t* m, uint8_t* neg, int8_t* pk) {
-  t1_decode_block(cw, len, w, h, orient, P, k, m, neg, pk);
+/* Raw bit counts rawb[0 .. npass] of a block encoded with the bypass
+ * (test hook); returns npass. */
+EXPORT int ebcc_ref_t1_rawbits(const uint32_t* q, const uint8_t* neg, int w, int h, int orient, long* rawb) {
+  t1enc_t* te = (t1enc_t*)calloc(1, sizeof(t1enc_t));
+  t1_encode_block(q, neg, w, h, orient, 1, te);
+  for (int k = 0; k <= te->npass; k++) rawb[k] = te->rawb[k];
+  int n = te->npass;
+  free(te->e.raw); free(te->raw.buf); free(te);
+  return n;
+}
+EXPORT int ebcc_ref_t1_decode(const uint8_t* cw, long len, int w, int h, int orient, int bypass, int P, int k,
+                              uint32_t* m, uint8_t* neg, int8_t* pk) {
+  return t1_decode_block(cw, len, w, h, orient, P, k, bypass, m, neg, pk);
 }
 
 /* ======================================================================== */
@@ -1285,15 +1378,17 @@ static int band_gain(const band_t* b) { return ebcc_ref_band_log2_gain(b->level,
 
 /* Base-layer reconstruction from the block table and codewords:
  * dec_base of Algorithm 1 (tier-1 decode, dequantise, inverse DWT). */
-static void base_decode(const layout_t* ly, int e0, const uint8_t* pbv, const uint8_t* kbv,
-                        const uint8_t* const* cw, const long* cwlen, float* out) {
+static int base_decode(const layout_t* ly, int e0, int bypass, const uint8_t* pbv, const uint8_t* kbv,
+                       const uint8_t* const* cw, const long* cwlen, float* out) {
+  int rc = REF_OK;
   long N = ly->ny * ly->nx;
   memset(out, 0, sizeof(float) * (size_t)N);
   uint32_t* m = (uint32_t*)malloc(4 * 4096); uint8_t* ng = (uint8_t*)malloc(4096); int8_t* pk = (int8_t*)malloc(4096);
   for (long b = 0; b < ly->nblk; b++) {
     const blk_t* k = &ly->blk[b];
     const band_t* bd = &ly->bands[k->band];
-    t1_decode_block(cw[b], cwlen[b], k->w, k->h, bd->orient, pbv[b], kbv[b], m, ng, pk);
+    if (t1_decode_block(cw[b], cwlen[b], k->w, k->h, bd->orient, pbv[b], kbv[b], bypass, m, ng, pk) != REF_OK)
+      rc = REF_ECORRUPT;
     int e = e0 - band_gain(bd);
     for (int y = 0; y < k->h; y++)
       for (int x = 0; x < k->w; x++) {
@@ -1303,6 +1398,7 @@ static void base_decode(const layout_t* ly, int e0, const uint8_t* pbv, const ui
   }
   free(m); free(ng); free(pk);
   dwt2_f(out, ly->ny, ly->nx, ly->L, 1);
+  return rc;
 }
 
 /* Residual reconstruction of a residual section at truncation plane n_s
@@ -1354,8 +1450,8 @@ EXPORT size_t ebcc_ref_compress_bound(size_t ny, size_t nx) { return HDR_BYTES +
 typedef struct {
   const layout_t* ly;
   const int* np; const int32_t* R; const int64_t* D; int stride;
-  mqe_t* saved; long (*sbp)[3 * QMAX_BITS]; uint8_t (*stail)[3 * QMAX_BITS][3];
-  const uint8_t* pbv; int e0;
+  t1enc_t* tes;                    /* every block's encoding with all of its passes */
+  const uint8_t* pbv; int e0, bypass;
   const float* x; float xmin, range_f; double eps; long N;
   uint8_t* kb; uint8_t** cw; long* cwlen; float* abase;
   int evals;
@@ -1386,15 +1482,12 @@ static long base_at(basectx_t* c, double r, int* allfit, long* budget) {
   if (budget) *budget = bud;
   long used = pcrd_af((int)nblk, c->np, c->R, c->D, c->stride, bud, c->kb, allfit);
   for (long b = 0; b < nblk; b++) {
-    t1enc_t tmp; tmp.e = c->saved[b];
-    memcpy(tmp.bp, c->sbp[b], sizeof(tmp.bp)); memcpy(tmp.tail, c->stail[b], sizeof(tmp.tail));
-    for (int j = 0; j <= c->np[b]; j++) tmp.R[j] = c->R[b * c->stride + j];
     free(c->cw[b]);
     c->cwlen[b] = c->kb[b] ? c->R[b * c->stride + c->kb[b]] : 0;
     c->cw[b] = (uint8_t*)malloc((size_t)c->cwlen[b] + 1);
-    t1_codeword(&tmp, c->kb[b], c->cw[b]);
+    t1_codeword(&c->tes[b], c->kb[b], c->cw[b]);
   }
-  base_decode(c->ly, c->e0, c->pbv, c->kb, (const uint8_t* const*)c->cw, c->cwlen, c->abase);
+  base_decode(c->ly, c->e0, c->bypass, c->pbv, c->kb, (const uint8_t* const*)c->cw, c->cwlen, c->abase);
   c->evals++;
   if (g_log_n < g_log_cap) {
     int allfit_v = 0;
@@ -1467,14 +1560,15 @@ EXPORT long ebcc_ref_base_budget(long N, long nblk, double r) { return base_budg
  * Returns 0 and the stream length, or a negative status. */
 EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, double err_bound, int bound_mode,
                                    double base_ratio, double q, int levels, int cbl2w, int cbl2h, int tile,
-                                   int trunc, uint8_t* out, size_t cap, size_t* out_len, ebcc_ref_trace* tr) {
+                                   int trunc, int bypass, uint8_t* out, size_t cap, size_t* out_len,
+                                   ebcc_ref_trace* tr) {
   long ny = (long)ny_, nx = (long)nx_;
   if (out_len) *out_len = 0;
   if (ny < 1 || nx < 1 || ny > (1L << 24) || nx > (1L << 24) || ny * nx > (1L << 31) - 1) return REF_EINVAL;
   if (!(err_bound > 0) || !isfinite(err_bound) || !(base_ratio >= 1.0) || !isfinite(base_ratio)) return REF_EINVAL;
   if (!(q >= 0.0 && q <= 1.0)) return REF_EINVAL;
   if (levels < 0 || levels > MAX_LEVELS || cbl2w < 2 || cbl2h < 2 || cbl2w > 6 || cbl2h > 6 || tile < 1 || tile > 64 ||
-      trunc < 0 || trunc > 1)
+      trunc < 0 || trunc > 1 || bypass < 0 || bypass > 1)
     return REF_EINVAL;
   long N = ny * nx;
   float xmin = x[0], xmax = x[0];
@@ -1531,11 +1625,8 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
     int32_t* R = (int32_t*)calloc((size_t)(ly.nblk * stride), 4);
     int64_t* D = (int64_t*)calloc((size_t)(ly.nblk * stride), 8);
     int* np = (int*)calloc((size_t)ly.nblk, sizeof(int));
-    t1enc_t* te = (t1enc_t*)calloc(1, sizeof(t1enc_t));
+    t1enc_t* tes = (t1enc_t*)calloc((size_t)ly.nblk, sizeof(t1enc_t));
     uint32_t* qb = (uint32_t*)malloc(4 * 4096); uint8_t* nb = (uint8_t*)malloc(4096);
-    mqe_t* saved = (mqe_t*)calloc((size_t)ly.nblk, sizeof(mqe_t));
-    long (*sbp)[3 * QMAX_BITS] = calloc((size_t)ly.nblk, sizeof(long[3 * QMAX_BITS]));
-    uint8_t (*stail)[3 * QMAX_BITS][3] = calloc((size_t)ly.nblk, sizeof(uint8_t[3 * QMAX_BITS][3]));
     for (long b = 0; b < ly.nblk; b++) {
       const blk_t* k = &ly.blk[b];
       const band_t* bd = &ly.bands[k->band];
@@ -1546,12 +1637,12 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
           qb[y * k->w + xx] = quant(c, sh, QMAX_BITS);
           nb[y * k->w + xx] = (uint8_t)(c < 0.0f);
         }
-      t1_encode_block(qb, nb, k->w, k->h, bd->orient, te);
+      t1enc_t* te = &tes[b];
+      t1_encode_block(qb, nb, k->w, k->h, bd->orient, bypass, te);
       pbv[b] = (uint8_t)te->P; np[b] = te->npass;
       for (int j = 0; j <= te->npass; j++) { R[b * stride + j] = te->R[j]; D[b * stride + j] = te->D[j]; }
-      saved[b] = te->e; memcpy(sbp[b], te->bp, sizeof(te->bp)); memcpy(stail[b], te->tail, sizeof(te->tail));
     }
-    basectx_t bc = {&ly, np, R, D, stride, saved, sbp, stail, pbv, e0, x, xmin, range_f, eps, N,
+    basectx_t bc = {&ly, np, R, D, stride, tes, pbv, e0, bypass, x, xmin, range_f, eps, N,
                     kbv, cw, cwlen, abase, 0};
     /* base ratio: the given r (q = 0), or Algorithm 1's feedback search for
      * proportion q from r0 = r, plus the base-only search (q = 1) for the
@@ -1665,8 +1756,8 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
         if (tr && tr->abase) memcpy(tr->abase, abase, sizeof(float) * (size_t)N);
       }
     }
-    for (long b = 0; b < ly.nblk; b++) free(saved[b].raw);
-    free(saved); free(sbp); free(stail); free(te); free(qb); free(nb); free(R); free(D); free(np);
+    for (long b = 0; b < ly.nblk; b++) { free(tes[b].e.raw); free(tes[b].raw.buf); }
+    free(tes); free(qb); free(nb); free(R); free(D); free(np);
   }
 
   size_t total;
@@ -1684,6 +1775,7 @@ EXPORT int ebcc_ref_compress_trace(const float* x, size_t ny_, size_t nx_, doubl
     write_header(out, MODE_CODED, ly.L, cbl, ny, nx, xmin, range_f, inv_f, e0, er_final, nmax_final, ns_final,
                  tile, bb, (uint32_t)resid_bytes);
     if (bt_final) out[34] |= 1;                            /* residual cut at a byte position */
+    if (bypass) out[35] |= 1;                              /* tier-1 passes with the arithmetic-coding bypass */
     uint8_t* p = out + HDR_BYTES;
     for (long b = 0; b < ly.nblk; b++) {
       p[4 * b] = pbv[b]; p[4 * b + 1] = kbv[b]; put_u16(p + 4 * b + 2, (uint32_t)cwlen[b]);
@@ -1711,9 +1803,9 @@ done:
 
 EXPORT int ebcc_ref_compress(const float* x, size_t ny, size_t nx, double err_bound, int bound_mode,
                              double base_ratio, double q, int levels, int cbl2w, int cbl2h, int tile, int trunc,
-                             uint8_t* out, size_t cap, size_t* out_len) {
+                             int bypass, uint8_t* out, size_t cap, size_t* out_len) {
   return ebcc_ref_compress_trace(x, ny, nx, err_bound, bound_mode, base_ratio, q, levels, cbl2w, cbl2h, tile,
-                                 trunc, out, cap, out_len, NULL);
+                                 trunc, bypass, out, cap, out_len, NULL);
 }
 
 /* Header fields of a stream (no payload validation). */
@@ -1739,7 +1831,7 @@ EXPORT int ebcc_ref_decompress(const uint8_t* in, size_t len, float* x, size_t n
   if (mode == MODE_CONST) { for (long i = 0; i < N; i++) x[i] = xmin; return REF_OK; }
   if (mode == MODE_RAW) { if (bb != 4 * (uint32_t)N) return REF_ECORRUPT; memcpy(x, in + HDR_BYTES, 4 * (size_t)N); return REF_OK; }
   int L = in[6], cbl2w = in[7] & 15, cbl2h = in[7] >> 4, T = (int)get_u16(in + 32);
-  int e0 = (int8_t)in[28], er = (int8_t)in[29], ns = (int8_t)in[31], bt = in[34] & 1;
+  int e0 = (int8_t)in[28], er = (int8_t)in[29], ns = (int8_t)in[31], bt = in[34] & 1, bypass = in[35] & 1;
   if (L != levels_eff(ny, nx, L) || cbl2w < 2 || cbl2h < 2 || cbl2w > 6 || cbl2h > 6 || T < 1) return REF_ECORRUPT;
   layout_t ly; layout_init(&ly, ny, nx, L, cbl2w, cbl2h, T);
   int rc = REF_OK;
@@ -1758,8 +1850,8 @@ EXPORT int ebcc_ref_decompress(const uint8_t* in, size_t len, float* x, size_t n
   float* abase = (float*)malloc(sizeof(float) * (size_t)N);
   float* r = (float*)calloc((size_t)N, sizeof(float));
   if (rc == REF_OK) {
-    base_decode(&ly, e0, pbv, kbv, cw, cwlen, abase);
-    if (rb) rc = resid_decode(&ly, in + HDR_BYTES + bb, rb, er, ns, bt, r);
+    rc = base_decode(&ly, e0, bypass, pbv, kbv, cw, cwlen, abase);
+    if (rc == REF_OK && rb) rc = resid_decode(&ly, in + HDR_BYTES + bb, rb, er, ns, bt, r);
   }
   if (rc == REF_OK)
     for (long i = 0; i < N; i++) x[i] = denorm(abase[i], r[i], xmin, range_f);

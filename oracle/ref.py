@@ -41,8 +41,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.ebcc_ref_compress_trace.argtypes = [P, C.c_size_t, C.c_size_t, C.c_double, C.c_int, C.c_double,
-                                              C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P,
-                                              C.c_size_t, C.POINTER(C.c_size_t), P]
+                                              C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                              P, C.c_size_t, C.POINTER(C.c_size_t), P]
         L.ebcc_ref_spiht_encode_cut.argtypes = [P, P, C.c_long, C.c_long, C.c_int, C.c_int, C.c_int, C.c_long, P,
                                                 C.c_long, P]
         L.ebcc_ref_spiht_encode_cut.restype = C.c_long
@@ -66,9 +66,11 @@ def lib():
         L.ebcc_ref_mq_decode.argtypes = [P, C.c_long, P, C.c_long, P]
         L.ebcc_ref_zc_ctx.argtypes = [C.c_int] * 4
         L.ebcc_ref_sc_ctx.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int)]
-        L.ebcc_ref_t1_encode.argtypes = [P, P, C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, C.c_long,
+        L.ebcc_ref_t1_encode.argtypes = [P, P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, C.c_long,
                                          C.POINTER(C.c_long)]
-        L.ebcc_ref_t1_decode.argtypes = [P, C.c_long, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P, P, P]
+        L.ebcc_ref_t1_decode.argtypes = [P, C.c_long, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P, P,
+                                         P]
+        L.ebcc_ref_t1_rawbits.argtypes = [P, P, C.c_int, C.c_int, C.c_int, P]
         L.ebcc_ref_pcrd.argtypes = [C.c_int, P, P, P, C.c_int, C.c_long, P]
         L.ebcc_ref_pcrd.restype = C.c_long
         L.ebcc_ref_spiht_encode.argtypes = [P, P, C.c_long, C.c_long, C.c_int, C.c_int, C.c_int, P, C.c_long]
@@ -109,10 +111,12 @@ def n_blocks(ny, nx, levels=5, cbl2w=5, cbl2h=5):
 
 
 def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, trace=False, q=0.0,
-             trunc=0):
+             trunc=0, bypass=0):
     """Compress a 2-D float32 field.  Returns bytes (and a dict of
     intermediate results when ``trace`` is true).  trunc=1 cuts the residual
-    at a byte position instead of a bit-plane end."""
+    at a byte position instead of a bit-plane end; bypass=1 sends the
+    significance-propagation and refinement passes below the fourth
+    bit-plane as raw bits."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     ny, nx = x.shape
     L = lib()
@@ -128,8 +132,8 @@ def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl
                     info=np.zeros(11, np.int32))
         tr = Trace(*[_p(bufs[k]).value for k in ("coef", "abase", "cres", "kb", "pb", "info")])
     rc = L.ebcc_ref_compress_trace(_p(x), ny, nx, float(err_bound), int(bound_mode), float(base_ratio), float(q),
-                                   int(levels), int(cbl2w), int(cbl2h), int(tile), int(trunc), _p(out), cap,
-                                   C.byref(n), C.byref(tr) if tr is not None else None)
+                                   int(levels), int(cbl2w), int(cbl2h), int(tile), int(trunc), int(bypass), _p(out),
+                                   cap, C.byref(n), C.byref(tr) if tr is not None else None)
     if rc != OK:
         raise RuntimeError(f"ebcc_ref_compress failed: {rc}")
     s = out[: n.value].tobytes()
@@ -143,7 +147,7 @@ def compress(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl
 
 
 def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, cbl2h=5, tile=1, cap=None, q=0.0,
-                trunc=0):
+                trunc=0, bypass=0):
     """Raw status-code form for error-path tests: returns (rc, bytes or None, out_len)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     ny, nx = x.shape if x.ndim == 2 else (x.size, 1)
@@ -153,8 +157,8 @@ def compress_rc(x, err_bound, bound_mode=0, base_ratio=30.0, levels=5, cbl2w=5, 
     out = np.zeros(max(cap, 1), dtype=np.uint8)
     n = C.c_size_t(0)
     rc = L.ebcc_ref_compress_trace(_p(x), ny, nx, float(err_bound), int(bound_mode), float(base_ratio), float(q),
-                                   int(levels), int(cbl2w), int(cbl2h), int(tile), int(trunc), _p(out), cap,
-                                   C.byref(n), None)
+                                   int(levels), int(cbl2w), int(cbl2h), int(tile), int(trunc), int(bypass), _p(out),
+                                   cap, C.byref(n), None)
     return rc, (out[: n.value].tobytes() if rc == OK else None), n.value
 
 
@@ -246,7 +250,7 @@ def mq_decode(stream, cx):
     return bits
 
 
-def t1_encode(q, neg, orient, keep=-1):
+def t1_encode(q, neg, orient, keep=-1, bypass=0):
     """Encode one code-block (q: magnitudes h x w, neg: sign flags).
     Returns (codeword terminated after `keep` passes, R[0..n], D[0..n])."""
     q = np.ascontiguousarray(q, np.uint32)
@@ -257,18 +261,30 @@ def t1_encode(q, neg, orient, keep=-1):
     cap = 2 * 24 * 3 * q.size + 64
     out = np.zeros(cap, np.uint8)
     ln = C.c_long(0)
-    npass = lib().ebcc_ref_t1_encode(_p(q), _p(neg), w, h, orient, keep, _p(R), _p(D), _p(out), cap, C.byref(ln))
+    npass = lib().ebcc_ref_t1_encode(_p(q), _p(neg), w, h, orient, bypass, keep, _p(R), _p(D), _p(out), cap,
+                                     C.byref(ln))
     assert npass >= 0
     return out[: ln.value].tobytes(), R[: npass + 1].copy(), D[: npass + 1].copy()
 
 
-def t1_decode(cw, h, w, orient, P, k):
+def t1_decode(cw, h, w, orient, P, k, bypass=0):
     buf = np.frombuffer(bytes(cw) + b"\0", np.uint8).copy()
     m = np.zeros((h, w), np.uint32)
     neg = np.zeros((h, w), np.uint8)
     pk = np.zeros((h, w), np.int8)
-    lib().ebcc_ref_t1_decode(_p(buf), len(cw), w, h, orient, P, k, _p(m), _p(neg), _p(pk))
+    rc = lib().ebcc_ref_t1_decode(_p(buf), len(cw), w, h, orient, bypass, P, k, _p(m), _p(neg), _p(pk))
+    assert rc == 0
     return m, neg, pk
+
+
+def t1_rawbits(q, neg, orient):
+    """Raw bits after each pass of a block coded with the bypass."""
+    q = np.ascontiguousarray(q, np.uint32)
+    neg = np.ascontiguousarray(neg, np.uint8)
+    h, w = q.shape
+    rb = np.zeros(70, np.int64)
+    n = lib().ebcc_ref_t1_rawbits(_p(q), _p(neg), w, h, orient, _p(rb))
+    return rb[: n + 1].copy()
 
 
 def pcrd(npass, R, D, budget):

@@ -228,3 +228,20 @@ def test_base_quantiser_planes_per_block(ref, shape, levels, cb, eps):
                 pb.append(m.bit_length())
     assert tr["nblocks"] == len(pb)
     assert list(tr["pb"]) == pb
+
+
+@pytest.mark.parametrize("var,shape,eps", [("t", (181, 360), 0.01), ("u", (91, 180), 0.001), ("q", (64, 96), 0.01)])
+def test_bypass_streams(ref, var, shape, eps):
+    """Streams with the tier-1 bypass: flagged in the header, decoded within
+    the bound; the base layer's choice of passes may differ (other lengths),
+    the compression ratio stays close to the arithmetic-coded stream's."""
+    import numpy as np
+    from paper_2510_22265_amd import synth
+    x = synth.field(var, *shape, cfg=1, level=4)
+    s0 = ref.compress(x, eps)
+    s1 = ref.compress(x, eps, bypass=1)
+    assert s1[35] & 1 and not s0[35] & 1
+    y = ref.decompress(s1, *shape)
+    rng_ = float(x.max()) - float(x.min())
+    assert np.abs(x.astype(np.float64) - y.astype(np.float64)).max() <= eps * rng_
+    assert abs(len(s1) / len(s0) - 1) < 0.05

@@ -226,3 +226,67 @@ def test_mq_decision_counters(ref, seed):
     assert c["enc"] == c["dec"] == c["enc_max_block"] == c["dec_max_block"]
     assert c["enc"] >= w * ((h + 3) // 4)
     assert ref.mq_counts() == {k: 0 for k in c}
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_t1_bypass_block_properties(ref, seed):
+    """The arithmetic-coding bypass (T.800 D.6): every pass kept is lossless;
+    each truncated codeword has the length R_k and decodes to q's known bits;
+    distortion reductions are those of the arithmetic-coded block (the coding
+    of a decision does not change what it tells); the first ten passes give
+    the same bytes as without the bypass."""
+    rng = np.random.default_rng(700 + seed)
+    h, w = [(32, 32), (64, 64), (16, 32), (13, 9), (32, 7), (4, 64), (1, 1), (32, 32)][seed % 8]
+    orient = seed % 4
+    q, neg = _block(rng, h, w)
+    if seed % 3 == 0:
+        q = np.minimum(q << np.uint32(10), (1 << 23) - 1).astype(np.uint32)   # many planes: raw passes present
+    cw, R, D = ref.t1_encode(q, neg, orient, bypass=1)
+    cw0, R0, D0 = ref.t1_encode(q, neg, orient, bypass=0)
+    P = int(q.max()).bit_length()
+    n = len(R) - 1
+    assert n == len(R0) - 1 == (3 * P - 2 if P else 0)
+    assert (D == D0).all()
+    m, ng, pk = ref.t1_decode(cw, h, w, orient, P, n, bypass=1)
+    assert (m == q).all() and ((ng == neg) | (q == 0)).all()
+    ks = range(n + 1) if n <= 30 else sorted(set(rng.integers(0, n + 1, 14)) | {0, 1, 10, 11, 12, 13, n})
+    for k in ks:
+        cwk, _, _ = ref.t1_encode(q, neg, orient, keep=k, bypass=1)
+        assert len(cwk) == R[k]
+        if k <= 10:
+            cwk0, _, _ = ref.t1_encode(q, neg, orient, keep=k, bypass=0)
+            assert cwk == cwk0
+        mk, ngk, pkk = ref.t1_decode(cwk, h, w, orient, P, k, bypass=1)
+        mk0, _, pkk0 = ref.t1_decode(ref.t1_encode(q, neg, orient, keep=k)[0], h, w, orient, P, k)
+        assert (mk == mk0).all() and (pkk[mk > 0] == pkk0[mk > 0]).all()
+        sig = mk > 0
+        assert ((ngk == neg) | ~sig).all()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_t1_bypass_raw_refinement_bits(ref, seed):
+    """The raw bits of the first bypassed refinement pass (pass 12: plane
+    P - 5) are bit P - 5 of every sample significant before that plane, in
+    the stripe scan order (stripes of four rows, columns left to right, rows
+    top to bottom), read from the end of the codeword kept after 12 passes."""
+    rng = np.random.default_rng(7100 + seed)
+    h, w = [(32, 32), (16, 16), (9, 13), (64, 32), (32, 5), (8, 64)][seed]
+    q, neg = _block(rng, h, w)
+    q = np.maximum(q, 1).astype(np.uint32) << np.uint32(14)
+    q = np.minimum(q, (1 << 23) - 1).astype(np.uint32)
+    P = int(q.max()).bit_length()
+    assert 3 * P - 2 >= 12
+    rb = ref.t1_rawbits(q, neg, seed % 4)
+    cw, R, _ = ref.t1_encode(q, neg, seed % 4, keep=12, bypass=1)
+    rby = cw[0] | (cw[1] << 8)
+    assert rby == (rb[12] + 7) // 8
+    raw = np.unpackbits(np.frombuffer(cw[len(cw) - rby:], np.uint8))
+    got = raw[rb[11]: rb[12]]
+    p = P - 5
+    want = []
+    for y0 in range(0, h, 4):
+        for x in range(w):
+            for y in range(y0, min(y0 + 4, h)):
+                if q[y, x] >> (p + 1):
+                    want.append((int(q[y, x]) >> p) & 1)
+    assert got.tolist() == want
