@@ -71,10 +71,17 @@ typedef struct {
                              codes read as one embedded sequence (plane by plane, the sorting
                              passes of every tile before their refinement passes), searched
                              within the last plane the plane search keeps */
+  uint32_t bypass;        /* tier-1 arithmetic-coding bypass (JPEG2000 Part 1, D.6, the "lazy"
+                             mode): 0 = every coding pass MQ coded (default); 1 = the
+                             significance-propagation and refinement passes after a block's
+                             first ten send their decisions as raw bits (cleanup passes stay MQ
+                             coded); a block's codeword after k > 10 passes is then u16 raw byte
+                             count, MQ codeword, raw bits.  Any other value: EINVAL */
 } ebcc_params;
 
 /* Fill p with the defaults: range-relative 1% bound, r = 30, 5 levels,
- * 32x32 code-blocks, one-root SPIHT tiles, q = 0, truncation at plane ends. */
+ * 32x32 code-blocks, one-root SPIHT tiles, q = 0, truncation at plane ends,
+ * no tier-1 bypass. */
 void ebcc_params_default(ebcc_params* p);
 
 /* Largest stream ebcc_compress can produce for an ny x nx field (a coded

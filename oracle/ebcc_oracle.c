@@ -688,8 +688,9 @@ static int bitlen32(uint32_t v) { int n = 0; while (v) { n++; v >>= 1; } return 
  * u16 (little-endian) the raw byte count, the MQ codeword terminated after
  * the last arithmetic-coded pass <= k, then the raw bits of the bypassed
  * passes <= k (MSB-first, zero padded).  The MQ coder's state runs on across
- * the bypassed passes.  A pass whose MQ part exceeds BYP_MQ_MAX bytes or
- * whose raw part exceeds BYP_RAW_MAX bytes is never kept. */
+ * the bypassed passes.  In a stream with the bypass, a pass (any pass, the
+ * first ten included) whose MQ part exceeds BYP_MQ_MAX bytes or whose raw
+ * part exceeds BYP_RAW_MAX bytes is never kept. */
 #define BYP_FIRST 11
 #define BYP_MQ_MAX 49000
 #define BYP_RAW_MAX 16000
@@ -748,12 +749,10 @@ static void t1_encode_block(const uint32_t* q, const uint8_t* neg, int w, int h,
       }
       out->rawb[k] = out->raw.nbits;
       const long rby = (out->rawb[k] + 7) >> 3;
-      if (bypass && k >= BYP_FIRST) {
-        out->R[k] = (int32_t)(2 + out->Rmq[k] + rby);
-        if (out->Rmq[k] > BYP_MQ_MAX || rby > BYP_RAW_MAX) out->R[k] = SEG_RMAX + 1;
-      } else {
-        out->R[k] = out->Rmq[k];
-      }
+      out->R[k] = (bypass && k >= BYP_FIRST) ? (int32_t)(2 + out->Rmq[k] + rby) : out->Rmq[k];
+      /* with the bypass, every pass of the block: the MQ part and the raw
+       * part share one fixed-size coder buffer */
+      if (bypass && (out->Rmq[k] > BYP_MQ_MAX || rby > BYP_RAW_MAX)) out->R[k] = SEG_RMAX + 1;
     }
   }
   g_mq_enc_blocks++;

@@ -424,11 +424,15 @@ __global__ __launch_bounds__(256) void k_put_blocks(const FieldDev* __restrict__
 }
 
 // Terminated codewords: bytes before the termination point from the
-// encoder's buffer, then the bytes the termination of pass k_b writes.
+// encoder's buffer, then the bytes the termination of pass k_b writes.  With
+// the tier-1 bypass and k_b > 10: the raw byte count (u16), that MQ
+// codeword (terminated after the last MQ-coded pass), then the raw bits of
+// the bypassed passes from the buffer's raw area, the last byte's unused
+// bits cleared.
 __global__ __launch_bounds__(256) void k_gather_cw(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
                                                    const uint8_t* __restrict__ cw, const uint8_t* __restrict__ kb,
                                                    const int32_t* __restrict__ len, const int32_t* __restrict__ bpt,
-                                                   const uint32_t* __restrict__ tailt,
+                                                   const uint32_t* __restrict__ tailt, const int32_t* __restrict__ rbt,
                                                    const int64_t* __restrict__ off, int nblk) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int b = blockIdx.x * 4 + wave; b < nblk; b += gridDim.x * 4) {
@@ -439,6 +443,18 @@ __global__ __launch_bounds__(256) void k_gather_cw(const FieldDev* __restrict__ 
     uint32_t tl = tailt[(size_t)b * kPassStride + k];
     const uint8_t* src = cw + (size_t)b * kCwCap;
     uint8_t* dst = f.out + kHdr + 4 * (size_t)f.nblk + off[b];
+    if (f.byp && k >= kBypFirst) {
+      const int rbits = rbt[(size_t)b * kPassStride + k], rby = (rbits + 7) >> 3, nmq = n - 2 - rby;
+      const uint8_t lastm = (uint8_t)(0xFF << ((8 - (rbits & 7)) & 7));
+      for (int j = lane; j < n; j += 64) {
+        uint8_t v;
+        if (j < 2) v = (uint8_t)(rby >> (8 * j));
+        else if (j < 2 + nmq) v = j - 2 < bp ? src[j - 2] : (uint8_t)(tl >> (8 * (j - 2 - bp)));
+        else v = src[kRawOff + (j - 2 - nmq)] & (j == n - 1 ? lastm : (uint8_t)0xFF);
+        dst[j] = v;
+      }
+      continue;
+    }
     for (int j = lane; j < n; j += 64) dst[j] = j < bp ? src[j] : (uint8_t)(tl >> (8 * (j - bp)));
   }
 }
@@ -535,6 +551,7 @@ __global__ void k_header(const FieldDev* __restrict__ F, int nfields) {
   o[31] = (uint8_t)(int8_t)(mode == MODE_CODED && f.rb ? f.ns : 0);
   o[32] = (uint8_t)f.T; o[33] = (uint8_t)(f.T >> 8);
   o[34] = (uint8_t)(mode == MODE_CODED && f.rb && f.bt ? 1 : 0);   // residual cut at a byte position
+  o[35] = (uint8_t)(mode == MODE_CODED && f.byp ? 1 : 0);           // tier-1 arithmetic-coding bypass
   put32(o + 36, f.bb);
   put32(o + 40, f.rb);
   put32(o + 44, f.u32s[1]);
@@ -921,6 +938,7 @@ static int check_params(size_t ny, size_t nx, const ebcc_params* p, double err) 
   if (p->spiht_tile < 1 || p->spiht_tile > 64) return fail(EBCC_EINVAL, "spiht_tile out of range");
   if (!(p->q >= 0.0 && p->q <= 1.0)) return fail(EBCC_EINVAL, "q must be 0 (fixed base ratio) or in (0, 1]");
   if (p->trunc > 1) return fail(EBCC_EINVAL, "trunc must be 0 (bit-plane ends) or 1 (byte positions)");
+  if (p->bypass > 1) return fail(EBCC_EINVAL, "bypass must be 0 (every pass MQ coded) or 1 (raw passes after ten)");
   return EBCC_OK;
 }
 
@@ -962,6 +980,8 @@ struct Call {
   int *border, *qctr;       // persistent tier-1 launches: block order and work counter
   int* tix_sorted;          // decoding: the LDS classes' tiles, longest payload first
   bool want_cpos = false;   // compression with byte-cut residuals: every coded field gets a cpos plane
+  bool any_byp = false;     // some field's tier-1 passes use the arithmetic-coding bypass
+  int32_t* rbt = nullptr;   // compression with the bypass: raw bits per block and pass
   int* misfit;
   Blk* d_blk_own;
   TileD* d_tiles_own;
@@ -1086,7 +1106,7 @@ struct GraphKey {
     b.push_back('\0');
     add(c.ws); add(c.ws->base); add(c.nf); add(c.nblk); add(c.ntiles); add(c.cbw); add(c.cbh);
     add(c.forced_global); add(c.d_blk); add(c.d_tiles); add(c.d_tix); add(c.d_slot_off); add(c.F); add(c.Fc);
-    add(c.spec_depth); add(c.want_cpos); add(c.need_lists);
+    add(c.spec_depth); add(c.want_cpos); add(c.need_lists); add(c.any_byp);
     for (int k = 0; k < 4; k++) add(c.ncls[k]);
     const Tuning t = tuning();
     add(t);
@@ -1098,7 +1118,7 @@ struct GraphKey {
     for (int i = 0; i < c.nf; i++) {
       const FieldDev& f = c.Fh[i];
       add(f.ny); add(f.nx); add(f.L); add(f.nb); add(f.blk0); add(f.nblk); add(f.tile0); add(f.ntiles);
-      add(f.active); add(f.mode); add(f.bt); add(c.plans[i]);
+      add(f.active); add(f.mode); add(f.bt); add(f.byp); add(c.plans[i]);
     }
   }
 };
@@ -1187,6 +1207,7 @@ static size_t layout_call(Call& c, char* base, const std::vector<int>& coded) {
   c.dr = cv.take<int32_t>(nb * kPassStride); c.len = cv.take<int32_t>(nb);
   c.D = cv.take<int64_t>(nb * kPassStride); c.keys = cv.take<uint64_t>(nb * kPassStride);
   c.tail = cv.take<uint32_t>(nb * kPassStride);
+  c.rbt = cv.take<int32_t>(c.any_byp ? nb * kPassStride : 0);
   c.boff = cv.take<int64_t>(nb); c.bent = cv.take<uint32_t>(nb);
   c.cw = cv.take<uint8_t>(nb * (size_t)kCwCap);
   c.tlen = cv.take<uint32_t>(nt); c.tent = cv.take<uint32_t>(nt); c.toff = cv.take<int64_t>(nt);
@@ -1512,7 +1533,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
     f.L = levels_eff(f.ny, f.nx, (int)pp->levels);
     f.buf[BUF_X] = const_cast<float*>(in[i].x);
     f.err = in[i].err; f.bound_mode = (int)pp->bound_mode;
-    f.cbl = cbl; f.T = T; f.active = 1;
+    f.cbl = cbl; f.T = T; f.active = 1; f.byp = (int)pp->bypass;
     if (fixed_ws) {
       std::unique_ptr<Plan> p(new Plan());
       p->ny = f.ny; p->nx = f.nx; p->L = f.L; p->cbl2w = (int)pp->cblk_log2w; p->cbl2h = (int)pp->cblk_log2h;
@@ -1528,6 +1549,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   }
   std::vector<int> coded(nf, 1);
   c.want_cpos = pp->trunc != 0;
+  c.any_byp = pp->bypass != 0;
   size_t need_ws = compress_need(c, coded);
   char* base;
   if (fixed_ws) {
@@ -1611,7 +1633,7 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
       prof.mark(S_QUANT);
       const T1Split t1s{c.ws->aux, c.ws->ev_fork, c.ws->ev_join};
       t1_encode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.planes, c.signs, c.pb, c.cw, c.R, c.D, c.bpt, c.tail, c.sppf,
-                s, &t1s, c.border, c.qctr);
+                s, &t1s, c.border, c.qctr, c.any_byp ? c.rbt : nullptr);
       prof.mark(S_T1ENC);
       HIPCHK(hipGetLastError());
       return EBCC_OK;
@@ -1959,8 +1981,8 @@ static int compress_call(const std::vector<FieldIn>& in, const ebcc_params* pp, 
   auto seq_pack = [&](hipStream_t s) -> int {
     if (any) {
       k_put_blocks<<<grid_for(c.nblk), 256, 0, s>>>(c.F, c.d_blk, c.bent, c.nblk);
-      k_gather_cw<<<std::max(1, (c.nblk + 3) / 4), 256, 0, s>>>(c.F, c.d_blk, c.cw, c.kb, c.len, c.bpt, c.tail, c.boff,
-                                                               c.nblk);
+      k_gather_cw<<<std::max(1, (c.nblk + 3) / 4), 256, 0, s>>>(c.F, c.d_blk, c.cw, c.kb, c.len, c.bpt, c.tail,
+                                                               c.rbt, c.boff, c.nblk);
       k_put_tiles<<<grid_for(c.ntiles), 256, 0, s>>>(c.F, c.d_tiles, c.tent, c.ntiles);
       k_gather_tiles<<<std::max(1, (c.ntiles + 3) / 4), 256, 0, s>>>(c.F, c.d_tiles, c.slots, c.d_slot_off, c.tlen,
                                                                       c.tbits, c.toff, c.ntiles);
@@ -2131,6 +2153,8 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
       }
       f.L = L; f.T = T;
       f.bt = f.rb ? (h[34] & 1) : 0;
+      f.byp = h[35] & 1;
+      c.any_byp |= f.byp != 0;
       if ((rc = get_plan(f.ny, f.nx, L, w2, h2, T, &c.plans[i]))) return rc;
       if ((int64_t)f.bb < 4 * (int64_t)c.plans[i]->nblk) { bad(i, EBCC_ECORRUPT, "base section shorter than its table"); continue; }
       if (f.rb && (int64_t)f.rb < 4 * (int64_t)c.plans[i]->ntiles + (f.bt ? 8 : 0)) {
@@ -2250,7 +2274,7 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
         dwt_inverse_head(c.Fc, Fr.data(), nf, BUF_CHAT, sb);
       }
       // (no scalar/vector split here: the second stream is busy with SPIHT)
-      t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, s, nullptr, c.border, c.qctr);
+      t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, s, nullptr, c.border, c.qctr, c.any_byp);
       prof.mark(S_D_T1);
       dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, s);
       prof.mark(S_D_IDWT_BASE);
@@ -2343,6 +2367,7 @@ void ebcc_params_default(ebcc_params* p) {
   p->cblk_log2h = 5;
   p->spiht_tile = 1;
   p->trunc = 0;
+  p->bypass = 0;
 }
 
 size_t ebcc_compress_bound(size_t ny, size_t nx) { return (size_t)kHdr + 4 * ny * nx; }
@@ -2607,6 +2632,7 @@ static size_t compress_ws(const std::vector<size_t>& ny, const std::vector<size_
   }
   std::vector<int> coded(c.nf, 1);
   c.want_cpos = p->trunc != 0;
+  c.any_byp = p->bypass != 0;
   return ws_alloc(compress_need(c, coded));
 }
 

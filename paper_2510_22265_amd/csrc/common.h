@@ -14,6 +14,17 @@ constexpr int kCwCap = 65536 + 64;   // codeword slot per block (longer passes a
 constexpr int kMaxLevels = 16;
 constexpr int kMaxBands = 3 * kMaxLevels + 1;
 constexpr int kRInf = 0x7fffffff;    // length of a pass that can never be kept
+// Tier-1 arithmetic-coding bypass (a stream option): passes kBypFirst and
+// later (1-based) of the significance-propagation and refinement kinds are
+// raw.  A block's coder buffer then holds the MQ bytes below kRawOff and the
+// raw bits from kRawOff on; a pass whose MQ codeword exceeds kBypMqMax bytes
+// or whose raw bits exceed kBypRawMax bytes is never kept.
+constexpr int kBypFirst = 11;
+constexpr int kBypMqMax = 49000;
+constexpr int kBypRawMax = 16000;
+constexpr int kRawOff = kCwCap - 16064;
+constexpr int kRawCap = kCwCap - kRawOff;
+static_assert(kRawOff % 4 == 0 && kRawCap >= kBypRawMax + 64 && kRawOff >= kBypMqMax + 512, "coder buffer layout");
 
 enum { ORI_LL = 0, ORI_HL = 1, ORI_LH = 2, ORI_HH = 3 };
 enum { MODE_CONST = 0, MODE_RAW = 1, MODE_CODED = 2 };
@@ -98,6 +109,7 @@ struct FieldDev {
   uint32_t* cpos;
   int bt, cut_kind, cut_tile;
   uint32_t cut_bits;
+  int byp;             // tier-1 passes with the arithmetic-coding bypass
 };
 
 // Byte-cut residual: code length (bits) of tile tl (field-local) of a cut
@@ -183,22 +195,25 @@ struct T1Split {
 };
 // order (nblk ints) and qctr (one int): scratch of the persistent
 // lanes-per-block launch, used when that launch is chosen (may be null).
+// rbt (nblk * kPassStride): raw bits per block and pass when some field uses
+// the bypass (then the wavefront-per-block coders run), else null.
 void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
                const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
                uint32_t* tail, void* sppf, hipStream_t st, const T1Split* sp = nullptr, int* order = nullptr,
-               int* qctr = nullptr);
+               int* qctr = nullptr, int32_t* rbt = nullptr);
 void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,
                     const uint8_t* kb, const void* sppf, hipStream_t st);
 // table: per-block entries (P | k << 8 | len << 16); off: payload offsets
 // within each field's base payload (which starts at out + 48 + 4 nblk).
+// byp: some field uses the bypass (then the wavefront-per-block decoder runs).
 void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
                const int64_t* off, hipStream_t st, const T1Split* sp = nullptr, int* order = nullptr,
-               int* qctr = nullptr);
+               int* qctr = nullptr, bool byp = false);
 void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
                     const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
-                    uint32_t* tail, void* sppf, hipStream_t st);
+                    uint32_t* tail, void* sppf, hipStream_t st, int32_t* rbt = nullptr);
 void t1_decode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, const uint32_t* table,
-                    const int64_t* off, hipStream_t st);
+                    const int64_t* off, hipStream_t st, bool byp = false);
 // Kernel choices (process-wide, set through the C ABI; the environment
 // variables EBCC_T1_KERNEL=wave|lane and EBCC_SPIHT_KERNEL=global override;
 // EBCC_T1_PIPE=0 replaces the pipelined wavefront encoder of 32x32 blocks

@@ -965,10 +965,10 @@ static bool use_persist() {
 
 void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes, const void* signs,
                const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail, void* sppf,
-               hipStream_t st, const T1Split* sp, int* order, int* qctr) {
+               hipStream_t st, const T1Split* sp, int* order, int* qctr, int32_t* rbt) {
   if (nblk <= 0) return;
-  if (use_wave(nblk, false)) {
-    t1_encode_wave(F, blk, nblk, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st);
+  if (rbt || use_wave(nblk, false)) {
+    t1_encode_wave(F, blk, nblk, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st, rbt);
     return;
   }
   if (!(order && qctr && use_persist())) order = nullptr, qctr = nullptr;
@@ -1006,10 +1006,10 @@ void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
 }
 
 void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
-               const int64_t* off, hipStream_t st, const T1Split* sp, int* order, int* qctr) {
+               const int64_t* off, hipStream_t st, const T1Split* sp, int* order, int* qctr, bool byp) {
   if (nblk <= 0) return;
-  if (use_wave(nblk, true)) {
-    t1_decode_wave(F, blk, nblk, cbw, table, off, st);
+  if (byp || use_wave(nblk, true)) {
+    t1_decode_wave(F, blk, nblk, cbw, table, off, st, byp);
     return;
   }
   if (!(order && qctr && use_persist())) order = nullptr, qctr = nullptr;

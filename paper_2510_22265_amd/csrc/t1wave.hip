@@ -31,13 +31,14 @@ template <> __device__ __forceinline__ uint64_t rdl<uint64_t>(uint64_t v, int l)
 }
 __device__ __forceinline__ uint32_t rdl32(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
 
-// Wave-uniform MQ encoder; lane 0 stores the finished bytes.
+// Wave-uniform MQ encoder; lane 0 stores the finished bytes below cap (the
+// block's coder buffer, or its MQ area when the buffer also holds raw bits).
 struct MQW {
   uint32_t C, A, B;
-  int CT, BP;
+  int CT, BP, cap;
 };
 __device__ __forceinline__ void mqw_emit(MQW& e, uint32_t nb, uint8_t* out, int lane) {
-  if (lane == 0 && e.BP >= 0 && e.BP < kCwCap) out[e.BP] = (uint8_t)e.B;
+  if (lane == 0 && e.BP >= 0 && e.BP < e.cap) out[e.BP] = (uint8_t)e.B;
   e.BP++;
   e.B = nb;
 }
@@ -142,6 +143,23 @@ __device__ __forceinline__ int mqw_flush_copy(const MQW& e, uint32_t* tail) {
   return e.BP + 3 - (t2 == 0xFF ? 1 : 0);
 }
 
+// Raw bits of the bypassed passes (arithmetic-coding bypass), wave-uniform:
+// n bits pending in acc (first bit in bit 31), W words stored.  Lane 0
+// stores each full word MSB-first (big-endian bytes) into the raw area.
+struct RawW {
+  uint32_t acc;
+  int n, W;
+};
+__device__ __forceinline__ void raww_put(RawW& r, int d, uint8_t* raw, int lane) {
+  r.acc |= (uint32_t)d << (31 - r.n);
+  if (++r.n == 32) {
+    if (lane == 0 && r.W < kRawCap / 4) reinterpret_cast<uint32_t*>(raw)[r.W] = __builtin_bswap32(r.acc);
+    r.W++;
+    r.acc = 0;
+    r.n = 0;
+  }
+}
+
 template <typename M>
 __device__ __forceinline__ M wmask_of(int w) {
   return (w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << w) - 1);
@@ -206,18 +224,23 @@ __device__ __forceinline__ uint32_t sc_look(uint32_t sct, uint32_t sm, uint32_t 
 #define SR(rr) ((rr) < 0 ? sA : ((rr) > 3 ? sC : sB[(rr)]))
 #define NR(rr) ((rr) < 0 ? nA : ((rr) > 3 ? nC : nB[(rr)]))
 
-template <typename M>
+// BYP: the launch may hold fields with the arithmetic-coding bypass (their
+// significance-propagation and refinement passes after the tenth write raw
+// bits; rbt receives the raw bit count of every pass).
+template <typename M, bool BYP>
 __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
                                                        int nblk, int cbh, const M* __restrict__ planes,
                                                        const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
                                                        uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
                                                        int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
-                                                       uint32_t* __restrict__ tailt, M* __restrict__ sppf) {
+                                                       uint32_t* __restrict__ tailt, M* __restrict__ sppf,
+                                                       int32_t* __restrict__ rbt) {
   __shared__ uint32_t qs[64 * 64];   // quantised magnitudes [y][x], pitch 64
   const int lane = threadIdx.x;
   const int b = blockIdx.x;
   const Blk k = blk[b];
   if (!F[k.field].active) return;
+  const bool byp = BYP && F[k.field].byp;
   const float* coef = F[k.field].buf[BUF_COEF];
   const int nx = F[k.field].nx, e0 = F[k.field].e0;
   const int P = pbv[b];
@@ -227,19 +250,26 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
   int32_t* BPk = bpt + (size_t)b * kPassStride;
   uint32_t* TL = tailt + (size_t)b * kPassStride;
   M* spo = sppf + (size_t)b * cbh;
+  int32_t* RB = BYP ? rbt + (size_t)b * kPassStride : nullptr;
   // per-block table pointers used once per pass live in lanes of one vector
-  // register (lane 2i / 2i+1: low / high half of pointer i)
+  // register (lane 2i / 2i+1: low / high half of pointer i).  They are read
+  // back (readlane) only in wave-uniform control flow: inside a branch on the
+  // lane index the compiler may fold the lane selects that built the
+  // register by that branch's condition and read a lane before it was set.
   uint32_t pv = 0;
   {
-    const uint64_t pp[5] = {(uint64_t)R, (uint64_t)Dd, (uint64_t)BPk, (uint64_t)TL,
-                            (uint64_t)(planes + (size_t)b * kQBits * cbh)};
+    const uint64_t pp[6] = {(uint64_t)R, (uint64_t)Dd, (uint64_t)BPk, (uint64_t)TL,
+                            (uint64_t)(planes + (size_t)b * kQBits * cbh), (uint64_t)RB};
 #pragma unroll
-    for (int i = 0; i < 5; i++) {
+    for (int i = 0; i < 6; i++) {
       if (lane == 2 * i) pv = (uint32_t)pp[i];
       if (lane == 2 * i + 1) pv = (uint32_t)(pp[i] >> 32);
     }
   }
-  if (lane == 0) { R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0; }
+  if (lane == 0) {
+    R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0;
+    if (byp) RB[0] = 0;
+  }
   if (P == 0) {
     if (lane < h) spo[lane] = 0;
     return;
@@ -257,16 +287,26 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
   M neg = lane < h ? signs[(size_t)b * cbh + lane] : (M)0;
   const M wm = wmask_of<M>(w);
   uint8_t* out = cw + (size_t)b * kCwCap;
+  uint8_t* const rawp = out + kRawOff;
   MQW e;
-  e.C = 0; e.A = 0x8000; e.B = 0; e.CT = 12; e.BP = -1;
+  e.C = 0; e.A = 0x8000; e.B = 0; e.CT = 12; e.BP = -1; e.cap = byp ? kRawOff : kCwCap;
+  RawW rw;
+  rw.acc = 0; rw.n = 0; rw.W = 0;
+  // lengths past these are never kept: stop coding once one is reached
+  const int mq_stop = byp ? kBypMqMax : 65536;
   int npass = 3 * P - 2, kk = 0;
   bool stop = false;
   int64_t Dcum = 0;
+  int lrk = 0, lbp = -1;              // the last MQ-coded pass's termination
+  uint32_t ltail = 0;
   auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
 
   for (int p = P - 1; p >= 0 && !stop; p--) {
-    mag = lane < h ? ((const M*)lane_ptr(pv, 4))[(size_t)p * cbh + lane] : (M)0;
+    const M* const pl = (const M*)lane_ptr(pv, 4);
+    mag = lane < h ? pl[(size_t)p * cbh + lane] : (M)0;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
+      // pass numbers 11 and later of planes p <= P - 5 (SPP, MRP) are raw
+      const bool raw = byp && ty < 2 && p <= P - 5;
       nsig = 0;
       M refd = sig & ~vis;          // MRP refines every sample significant before this plane
       const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
@@ -294,6 +334,10 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
         if (ty != 1) { nA = rowv(neg, y0 - 1); nC = rowv(neg, y0 + 4); }
         // r is a compile-time constant in every caller (unrolled loops)
         auto code_sign = [&](int r, int x) {
+          if (ty == 0 && raw) {                          // a raw pass sends the sign itself
+            raww_put(rw, btu(nB[r], x), rawp, lane);
+            return;
+          }
           const uint32_t sc = sc_look(sct, f3(SR(r), x), f3(NR(r), x), btu(SR(r - 1), x), btu(NR(r - 1), x),
                                       btu(SR(r + 1), x), btu(NR(r + 1), x));
           mqw_encode(e, ctxv, tabv, CX_SC + (int)(sc & 7u), btu(nB[r], x) ^ (int)(sc >> 3), out, lane);
@@ -322,7 +366,8 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
               const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
               if (!pat) continue;
               int bit = btu(gB[r], x);
-              mqw_encode(e, ctxv, tabv, zc_look(zct, pat), bit, out, lane);
+              if (raw) raww_put(rw, bit, rawp, lane);
+              else mqw_encode(e, ctxv, tabv, zc_look(zct, pat), bit, out, lane);
               vB[r] |= (M)1 << x;
               if (bit) {
                 code_sign(r, x);
@@ -342,8 +387,12 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
 #pragma unroll
             for (int r = 0; r < 4; r++) {
               if (r >= rn || !btu(sB[r] & ~vB[r], x)) continue;
-              const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nB[r], x) ? CX_MR + 1 : CX_MR);
-              mqw_encode(e, ctxv, tabv, cx, btu(gB[r], x), out, lane);
+              if (raw) {
+                raww_put(rw, btu(gB[r], x), rawp, lane);
+              } else {
+                const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nB[r], x) ? CX_MR + 1 : CX_MR);
+                mqw_encode(e, ctxv, tabv, cx, btu(gB[r], x), out, lane);
+              }
               fB[r] |= (M)1 << x;
             }
           }
@@ -409,7 +458,8 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
             sig = sB[r]; vis = vB[r];
             if (ty == 1) ref = fB[r];
           }
-        if (e.BP >= 65536) stop = true;                  // every later pass exceeds the length limit
+        // every later pass exceeds a length limit
+        if (e.BP >= mq_stop || (byp && 32 * rw.W + rw.n > 8 * kBypRawMax)) stop = true;
       }
       };
       if (ty == 0) stripes(std::integral_constant<int, 0>{});
@@ -429,19 +479,30 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
       if (ty == 2) vis = 0;
       kk++;
       Dcum += dd;
-      uint32_t tail;
-      int rk = mqw_flush_copy(e, &tail);
+      // a raw pass's MQ part is the last MQ-coded pass's codeword
+      if (!raw) { lrk = mqw_flush_copy(e, &ltail); lbp = e.BP; }
+      int rk = lrk, rbits = 0;
+      if (byp) {
+        rbits = 32 * rw.W + rw.n;
+        const int rby = (rbits + 7) >> 3;
+        if (kk >= kBypFirst) rk = 2 + lrk + rby;
+        if (lrk > kBypMqMax || rby > kBypRawMax) rk = kRInf;
+      }
+      int32_t* const Rp = (int32_t*)lane_ptr(pv, 0);
+      int64_t* const Dp = (int64_t*)lane_ptr(pv, 1);
+      int32_t* const Bp = (int32_t*)lane_ptr(pv, 2);
+      uint32_t* const Tp = (uint32_t*)lane_ptr(pv, 3);
+      int32_t* const RBp = BYP ? (int32_t*)lane_ptr(pv, 5) : nullptr;
       if (lane == 0) {
-        int32_t* Rp = (int32_t*)lane_ptr(pv, 0);
-        int64_t* Dp = (int64_t*)lane_ptr(pv, 1);
-        int32_t* Bp = (int32_t*)lane_ptr(pv, 2);
-        uint32_t* Tp = (uint32_t*)lane_ptr(pv, 3);
-        Rp[kk] = rk; Dp[kk] = Dcum; Bp[kk] = e.BP; Tp[kk] = tail;
+        Rp[kk] = rk; Dp[kk] = Dcum; Bp[kk] = lbp; Tp[kk] = ltail;
+        if (byp) RBp[kk] = rbits;
       }
     }
   }
   if (lane == 0)
     for (int j = kk + 1; j <= npass; j++) { R[j] = kRInf; Dd[j] = Dcum; BPk[j] = 0; TL[j] = 0; }
+  // the raw area's last, partial word
+  if (byp && lane == 0 && rw.n && rw.W < kRawCap / 4) reinterpret_cast<uint32_t*>(rawp)[rw.W] = __builtin_bswap32(rw.acc);
   if (lane < h) spo[lane] = spp;
 }
 
@@ -458,12 +519,15 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
 // ------------------------------------------------------------------------
 constexpr int kPipeSym = 2816 + 16;   // one 32x32 plane: 1024 decisions + 1024 signs + 256 RL + 512 UNI, padded
 
-template <int NM>
+// With the arithmetic-coding bypass (BYP, a field's byp) the raw passes'
+// records carry the plain decisions (signs uncoded), and wavefront 0 packs
+// them into the raw area 256 at a time instead of MQ coding them.
+template <int NM, bool BYP>
 __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
     const FieldDev* __restrict__ F, const Blk* __restrict__ blk, int nblk, int cbh, const uint32_t* __restrict__ planes,
     const uint32_t* __restrict__ signs, const uint8_t* __restrict__ pbv, uint8_t* __restrict__ cw,
     int32_t* __restrict__ Rt, int64_t* __restrict__ Dt, int32_t* __restrict__ bpt, uint32_t* __restrict__ tailt,
-    uint32_t* __restrict__ sppf) {
+    uint32_t* __restrict__ sppf, int32_t* __restrict__ rbt) {
   using M = uint32_t;
   __shared__ uint32_t qs[32 * 32];             // quantised magnitudes [y][x], pitch 32
   __shared__ __align__(16) uint8_t sym[2][NM][kPipeSym];
@@ -475,6 +539,7 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
   const int b = blockIdx.x;
   const Blk k = blk[b];
   if (!F[k.field].active) return;
+  const bool byp = BYP && F[k.field].byp;
   const float* coef = F[k.field].buf[BUF_COEF];
   const int nx = F[k.field].nx, e0 = F[k.field].e0;
   const int P = pbv[b];
@@ -483,8 +548,12 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
   int64_t* Dd = Dt + (size_t)b * kPassStride;
   int32_t* BPk = bpt + (size_t)b * kPassStride;
   uint32_t* TL = tailt + (size_t)b * kPassStride;
+  int32_t* RB = BYP ? rbt + (size_t)b * kPassStride : nullptr;
   uint32_t* spo = sppf + (size_t)b * cbh;
-  if (wv == 0 && lane == 0) { R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0; }
+  if (wv == 0 && lane == 0) {
+    R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0;
+    if (byp) RB[0] = 0;
+  }
   if (P == 0) {
     if (wv == 0 && lane < h) spo[lane] = 0;
     return;
@@ -521,6 +590,7 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3; ty++) {
       n = (n + 3) & ~3;                  // every pass starts on a 4-byte boundary
       const int n0 = n;
+      const bool raw = byp && ty < 2 && p <= P - 5;   // passes 11 and later, SPP and MRP
       nsig = 0;
       M refd = sig & ~vis;
       const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
@@ -546,6 +616,10 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
           if (ty != 1) { nA = rowv(neg, y0 - 1); nC = rowv(neg, y0 + 4); }
           // r is a compile-time constant in every caller (unrolled loops)
           auto code_sign = [&](int r, int x) {
+            if (ty == 0 && raw) {                        // a raw pass sends the sign itself
+              emit(0, btu(nB[r], x));
+              return;
+            }
             const uint32_t sc = sc_look(sct, f3(SR(r), x), f3(NR(r), x), btu(SR(r - 1), x), btu(NR(r - 1), x),
                                         btu(SR(r + 1), x), btu(NR(r + 1), x));
             emit(CX_SC + (int)(sc & 7u), btu(nB[r], x) ^ (int)(sc >> 3));
@@ -683,11 +757,41 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
 
   // ---- the MQ coder (wavefront 0) ----
   uint8_t* out = cw + (size_t)b * kCwCap;
+  uint8_t* const rawp = out + kRawOff;
   MQW e;
-  e.C = 0; e.A = 0x8000; e.B = 0; e.CT = 12; e.BP = -1;
+  e.C = 0; e.A = 0x8000; e.B = 0; e.CT = 12; e.BP = -1; e.cap = byp ? kRawOff : kCwCap;
+  const int mq_stop = byp ? kBypMqMax : 65536;   // lengths past these are never kept
   int kk = 0;
   bool stop = false;
   int64_t Dcum = 0;
+  int lrk = 0, lbp = -1;             // the last MQ-coded pass's termination
+  uint32_t ltail = 0;
+  int rbits = 0;                     // raw bits so far; racc: the pending partial word
+  uint32_t racc = 0;
+  // m <= 256 raw decisions (bit 7 of each record), lane l holding records
+  // 4l .. 4l + 3 in wv4, appended MSB-first at bit rbits of the raw area
+  auto raw_append = [&](uint32_t wv4, int m) {
+    uint32_t nib = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+      if (4 * lane + j < m) nib |= ((wv4 >> (8 * j + 7)) & 1u) << (3 - j);
+    // lane 8t: the chunk's word t (decisions 32t .. 32t + 31, first in bit 31)
+    uint32_t part = nib << (28 - 4 * (lane & 7));
+    part |= (uint32_t)__shfl_xor((int)part, 1);
+    part |= (uint32_t)__shfl_xor((int)part, 2);
+    part |= (uint32_t)__shfl_xor((int)part, 4);
+    const int o = rbits & 31, W = rbits >> 5, T = (m + 31) >> 5;
+    const uint32_t a = (uint32_t)__shfl((int)part, lane < 8 ? 8 * lane : 0);
+    const uint32_t pa = (uint32_t)__shfl((int)part, (lane >= 1 && lane <= 8) ? 8 * (lane - 1) : 0);
+    // lane t (t <= T): raw word W + t
+    uint32_t dw = lane < T ? a >> o : 0u;
+    if (lane == 0) dw |= racc;
+    else if (o && lane <= T) dw |= pa << (32 - o);
+    const int nfull = (o + m) >> 5;
+    if (lane < nfull && W + lane < kRawCap / 4) reinterpret_cast<uint32_t*>(rawp)[W + lane] = __builtin_bswap32(dw);
+    racc = rdl32(dw, nfull);
+    rbits += m;
+  };
   auto code_group = [&](const int s, const int g) {
     for (int j = 0; j < NM; j++) {
       const int p = P - 1 - g * NM - j;
@@ -696,7 +800,14 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
       int off = 0;
       for (int ty = (p == P - 1) ? 2 : 0; ty < 3; ty++) {
         const int n = __builtin_amdgcn_readfirstlane(scnt[s][j][ty]);
-        if (!stop) {
+        const bool raw = byp && ty < 2 && p <= P - 5;
+        if (!stop && raw) {
+          for (int i = 0; i < n; i += 256) {
+            const int m = n - i < 256 ? n - i : 256;
+            const bool in = 4 * lane < m && off + i + 4 * lane + 4 <= kPipeSym;
+            raw_append(in ? *reinterpret_cast<const uint32_t*>(buf + off + i + 4 * lane) : 0u, m);
+          }
+        } else if (!stop) {
           for (int i = 0; i < n; i += 256) {
             // 256 decisions at a time: lane l holds bytes 4l .. 4l + 3
             const int m = n - i < 256 ? n - i : 256;
@@ -716,14 +827,25 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
                 mqw_encode(e, ctxv, tabv, (int)(w & 0x1Fu), (int)((w >> 7) & 1u), out, lane);
             }
           }
-          if (e.BP >= 65536) {
-            stop = true;                 // every later pass exceeds the length limit
+        }
+        if (!stop) {
+          if (e.BP >= mq_stop || (byp && rbits > 8 * kBypRawMax)) {
+            stop = true;                 // every later pass exceeds a length limit
           } else {
             kk++;
             Dcum += sdd[s][j][ty];
-            uint32_t tail;
-            const int rk = mqw_flush_copy(e, &tail);
-            if (lane == 0) { R[kk] = rk; Dd[kk] = Dcum; BPk[kk] = e.BP; TL[kk] = tail; }
+            // a raw pass's MQ part is the last MQ-coded pass's codeword
+            if (!raw) { lrk = mqw_flush_copy(e, &ltail); lbp = e.BP; }
+            int rk = lrk;
+            if (byp) {
+              const int rby = (rbits + 7) >> 3;
+              if (kk >= kBypFirst) rk = 2 + lrk + rby;
+              if (lrk > kBypMqMax || rby > kBypRawMax) rk = kRInf;
+            }
+            if (lane == 0) {
+              R[kk] = rk; Dd[kk] = Dcum; BPk[kk] = lbp; TL[kk] = ltail;
+              if (byp) RB[kk] = rbits;
+            }
           }
         }
         off += (n + 3) & ~3;
@@ -744,6 +866,9 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
   if (wv == 0) {
     if (lane == 0)
       for (int jj = kk + 1; jj <= 3 * P - 2; jj++) { R[jj] = kRInf; Dd[jj] = Dcum; BPk[jj] = 0; TL[jj] = 0; }
+    // the raw area's last, partial word
+    if (byp && lane == 0 && (rbits & 31) && (rbits >> 5) < kRawCap / 4)
+      reinterpret_cast<uint32_t*>(rawp)[rbits >> 5] = __builtin_bswap32(racc);
     if (lane < h) spo[lane] = sppm[lane];
   }
 }
@@ -823,6 +948,39 @@ __device__ __forceinline__ int mqwd_decode(MQWD& d, uint32_t& ctxv, uint32_t tab
   return (int)(mps ^ x);
 }
 
+// Raw bits of the bypassed passes, read MSB-first through a wave-uniform
+// 4-byte window like the MQ decoder's; bits past the end read as 0.
+struct RawD {
+  const uint8_t* buf;
+  int nbytes, pos;
+  uint64_t wa;
+  uint32_t word;
+};
+__device__ __forceinline__ int rawd_get(RawD& r) {
+  const int i = r.pos >> 3;
+  uint32_t v = 0;
+  if (i < r.nbytes) {
+    const uint64_t a = (uint64_t)(r.buf + i), wa = a & ~(uint64_t)3;
+    if (wa != r.wa) {
+      r.word = (uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int*>(wa));
+      r.wa = wa;
+    }
+    v = r.word >> (8 * (uint32_t)(a & 3));
+  }
+  const int bit = (int)((v >> (7 - (r.pos & 7))) & 1u);
+  r.pos++;
+  return bit;
+}
+// Lane j: raw bits pos + 32j .. pos + 32j + 31, the first in bit 0 (the
+// layout of a refinement stripe's decoded bits).
+__device__ __forceinline__ uint32_t rawd_words(const RawD& r, int lane) {
+  const int s0 = r.pos + 32 * lane, i0 = s0 >> 3;
+  uint64_t win = 0;
+#pragma unroll
+  for (int q = 0; q < 5; q++) win = (win << 8) | (i0 + q < r.nbytes ? r.buf[i0 + q] : 0u);
+  return __builtin_bitreverse32((uint32_t)(win >> (8 - (s0 & 7))));
+}
+
 // Set bits of m in the columns (lanes) below this lane, and bit `lane` of m.
 template <typename M> __device__ __forceinline__ int mbcnt_m(M m);
 template <> __device__ __forceinline__ int mbcnt_m<uint32_t>(uint32_t m) {
@@ -835,7 +993,8 @@ template <typename M> __device__ __forceinline__ uint32_t col_bit(M m, int lane)
   return lane < (int)(8 * sizeof(M)) ? (uint32_t)(m >> lane) & 1u : 0u;
 }
 
-template <typename M>
+// BYP: the launch may hold streams with the arithmetic-coding bypass.
+template <typename M, bool BYP>
 __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
                                                        int nblk, const uint32_t* __restrict__ table,
                                                        const int64_t* __restrict__ off) {
@@ -856,7 +1015,19 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
   const int P = ent & 0xFF, kb = (ent >> 8) & 0xFF, len = (int)(ent >> 16);
   const int64_t o = off[b];
   float* yb = yhat + (size_t)k.y0 * nx + k.x0;
-  const bool bad = P > kQBits || kb > (P ? 3 * P - 2 : 0) || o < 0 || o + len > sec_len;
+  bool bad = P > kQBits || kb > (P ? 3 * P - 2 : 0) || o < 0 || o + len > sec_len;
+  // bypass codeword after more than ten passes: u16 raw byte count, the MQ
+  // codeword, the raw bytes
+  const bool rawcw = BYP && f.byp && kb >= kBypFirst;
+  int rby = 0;
+  if (rawcw && !bad) {
+    if (len < 2) {
+      bad = true;
+    } else {
+      rby = __builtin_amdgcn_readfirstlane((int)sec[o] | ((int)sec[o + 1] << 8));
+      if (2 + rby > len) bad = true;
+    }
+  }
   if (bad && lane == 0) atomicOr(flag, 1);
   if (bad || P == 0 || kb == 0) {
     for (int i = lane; i < w * h; i += 64) {
@@ -873,7 +1044,9 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
   M sig = 0, vis = 0, ref = 0, neg = 0, cur = 0, magp = 0;
   const M wm = wmask_of<M>(w);
   MQWD d;
-  mqwd_init(d, sec + o, len);
+  mqwd_init(d, sec + o + (rawcw ? 2 : 0), rawcw ? len - 2 - rby : len);
+  RawD rr;
+  rr.buf = sec + o + len - rby; rr.nbytes = rby; rr.pos = 0; rr.wa = ~(uint64_t)0; rr.word = 0;
   auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
   int done = 0, plast = P - 1;
   for (int p = P - 1; p >= 0 && done < kb; p--) {
@@ -881,6 +1054,8 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
     cur = 0;
     magp = 0;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < kb; ty++) {
+      // pass numbers 11 and later of planes p <= P - 5 (SPP, MRP) are raw
+      const bool raw = rawcw && ty < 2 && p <= P - 5;
       const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
       auto stripes = [&](auto tyc) {
       constexpr int ty = decltype(tyc)::value;
@@ -902,9 +1077,14 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
           mB[r] = 0;
         }
         auto dec_sign = [&](int r, int x) {
-          const uint32_t sc = sc_look(sct, f3(SR(r), x), f3(NR(r), x), btu(SR(r - 1), x), btu(NR(r - 1), x),
-                                      btu(SR(r + 1), x), btu(NR(r + 1), x));
-          int s = mqwd_decode(d, ctxv, tabv, CX_SC + (int)(sc & 7u), lane) ^ (int)(sc >> 3);
+          int s;
+          if (ty == 0 && raw) {
+            s = rawd_get(rr);                            // a raw pass sends the sign itself
+          } else {
+            const uint32_t sc = sc_look(sct, f3(SR(r), x), f3(NR(r), x), btu(SR(r - 1), x), btu(NR(r - 1), x),
+                                        btu(SR(r + 1), x), btu(NR(r + 1), x));
+            s = mqwd_decode(d, ctxv, tabv, CX_SC + (int)(sc & 7u), lane) ^ (int)(sc >> 3);
+          }
           if (s) nB[r] |= (M)1 << x;
         };
         if (ty == 0) {
@@ -930,7 +1110,7 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
               if (btu(mid, x)) continue;
               const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
               if (!pat) continue;
-              int bit = mqwd_decode(d, ctxv, tabv, zc_look(zct, pat), lane);
+              const int bit = raw ? rawd_get(rr) : mqwd_decode(d, ctxv, tabv, zc_look(zct, pat), lane);
               vB[r] |= (M)1 << x;
               if (bit) {
                 dec_sign(r, x);
@@ -959,35 +1139,42 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
             int pos = 0;
 #pragma unroll
             for (int r = 0; r < 4; r++) pos += mbcnt_m<M>(Rr[r]);
-            int pw = pos;
+            uint32_t dv = 0;
+            if (raw) {
+              // a raw refinement pass: the stripe's bits are the next tot raw bits
+              if (lane < ((tot + 31) >> 5)) dv = rawd_words(rr, lane);
+              rr.pos += tot;
+            } else {
+              int pw = pos;
 #pragma unroll
-            for (int r = 0; r < 4; r++)
-              if (col_bit<M>(Rr[r], lane)) {
-                const int c = col_bit<M>(fB[r], lane) ? 2 : (int)col_bit<M>(nB[r], lane);
-                sb8[pw++] = (uint8_t)(CX_MR + c);
+              for (int r = 0; r < 4; r++)
+                if (col_bit<M>(Rr[r], lane)) {
+                  const int c = col_bit<M>(fB[r], lane) ? 2 : (int)col_bit<M>(nB[r], lane);
+                  sb8[pw++] = (uint8_t)(CX_MR + c);
+                }
+              const uint32_t wv4 = rsym[lane];
+              uint32_t acc = 0;
+              const int m4 = tot & ~3;
+              for (int t = 0; t < m4; t += 4) {
+                const uint32_t wd = rdl32(wv4, t >> 2);
+                uint32_t b4 = (uint32_t)mqwd_decode(d, ctxv, tabv, (int)(wd & 0x1Fu), lane);
+                b4 |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)((wd >> 8) & 0x1Fu), lane) << 1;
+                b4 |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)((wd >> 16) & 0x1Fu), lane) << 2;
+                b4 |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)((wd >> 24) & 0x1Fu), lane) << 3;
+                acc |= b4 << (t & 31);
+                if ((t & 31) == 28) {
+                  if (lane == (t >> 5)) dv = acc;
+                  acc = 0;
+                }
               }
-            const uint32_t wv4 = rsym[lane];
-            uint32_t dv = 0, acc = 0;
-            const int m4 = tot & ~3;
-            for (int t = 0; t < m4; t += 4) {
-              const uint32_t wd = rdl32(wv4, t >> 2);
-              uint32_t b4 = (uint32_t)mqwd_decode(d, ctxv, tabv, (int)(wd & 0x1Fu), lane);
-              b4 |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)((wd >> 8) & 0x1Fu), lane) << 1;
-              b4 |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)((wd >> 16) & 0x1Fu), lane) << 2;
-              b4 |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)((wd >> 24) & 0x1Fu), lane) << 3;
-              acc |= b4 << (t & 31);
-              if ((t & 31) == 28) {
-                if (lane == (t >> 5)) dv = acc;
-                acc = 0;
+              if (m4 < tot) {
+                uint32_t wd = rdl32(wv4, m4 >> 2);
+                for (int t = m4; t < tot; t++, wd >>= 8)
+                  acc |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)(wd & 0x1Fu), lane) << (t & 31);
               }
-            }
-            if (m4 < tot) {
-              uint32_t wd = rdl32(wv4, m4 >> 2);
-              for (int t = m4; t < tot; t++, wd >>= 8)
-                acc |= (uint32_t)mqwd_decode(d, ctxv, tabv, (int)(wd & 0x1Fu), lane) << (t & 31);
-            }
-            if (tot & 31) {
-              if (lane == (tot >> 5)) dv = acc;
+              if (tot & 31) {
+                if (lane == (tot >> 5)) dv = acc;
+              }
             }
             // bits pos, pos+1, ... belong to this column's rows in order
             const uint32_t lo = (uint32_t)__shfl((int)dv, pos >> 5), hi = (uint32_t)__shfl((int)dv, (pos >> 5) + 1);
@@ -1099,31 +1286,43 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
 
 void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
                     const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
-                    uint32_t* tail, void* sppf, hipStream_t st) {
+                    uint32_t* tail, void* sppf, hipStream_t st, int32_t* rbt) {
   if (nblk <= 0) return;
   const char* pe = getenv("EBCC_T1_PIPE");
   const bool pipe = !(pe && pe[0] == '0');
   // three modelling wavefronts: with two the coder still waits for the
   // next planes now and then (1.51 against 1.46 ms per 721x1440 field),
   // with four or five they crowd the compute unit (1.59, 1.69 ms)
-  if (cbw <= 32 && cbh <= 32 && pipe)
-    k_t1_encode_pipe<3><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes, (const uint32_t*)signs, pb,
-                                             cw, R, D, bp, tail, (uint32_t*)sppf);
-  else if (cbw <= 32)
-    k_t1_encode_wave<uint32_t><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes, (const uint32_t*)signs,
-                                                     pb, cw, R, D, bp, tail, (uint32_t*)sppf);
-  else
-    k_t1_encode_wave<uint64_t><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint64_t*)planes, (const uint64_t*)signs,
-                                                     pb, cw, R, D, bp, tail, (uint64_t*)sppf);
+#define ENC_W(BYP)                                                                                                  \
+  do {                                                                                                             \
+    if (cbw <= 32 && cbh <= 32 && pipe)                                                                            \
+      k_t1_encode_pipe<3, BYP><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes,                    \
+                                                    (const uint32_t*)signs, pb, cw, R, D, bp, tail,                 \
+                                                    (uint32_t*)sppf, rbt);                                          \
+    else if (cbw <= 32)                                                                                            \
+      k_t1_encode_wave<uint32_t, BYP><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes,              \
+                                                          (const uint32_t*)signs, pb, cw, R, D, bp, tail,           \
+                                                          (uint32_t*)sppf, rbt);                                    \
+    else                                                                                                           \
+      k_t1_encode_wave<uint64_t, BYP><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint64_t*)planes,              \
+                                                          (const uint64_t*)signs, pb, cw, R, D, bp, tail,           \
+                                                          (uint64_t*)sppf, rbt);                                    \
+  } while (0)
+  if (rbt) ENC_W(true);
+  else ENC_W(false);
+#undef ENC_W
 }
 
 void t1_decode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, const uint32_t* table, const int64_t* off,
-                    hipStream_t st) {
+                    hipStream_t st, bool byp) {
   if (nblk <= 0) return;
-  if (cbw <= 32)
-    k_t1_decode_wave<uint32_t><<<nblk, 64, 0, st>>>(F, blk, nblk, table, off);
-  else
-    k_t1_decode_wave<uint64_t><<<nblk, 64, 0, st>>>(F, blk, nblk, table, off);
+  if (cbw <= 32) {
+    if (byp) k_t1_decode_wave<uint32_t, true><<<nblk, 64, 0, st>>>(F, blk, nblk, table, off);
+    else k_t1_decode_wave<uint32_t, false><<<nblk, 64, 0, st>>>(F, blk, nblk, table, off);
+  } else {
+    if (byp) k_t1_decode_wave<uint64_t, true><<<nblk, 64, 0, st>>>(F, blk, nblk, table, off);
+    else k_t1_decode_wave<uint64_t, false><<<nblk, 64, 0, st>>>(F, blk, nblk, table, off);
+  }
 }
 
 }  // namespace ebcc

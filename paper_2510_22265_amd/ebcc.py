@@ -28,7 +28,8 @@ SYMBOLS = ("ebcc_params_default", "ebcc_compress_bound", "ebcc_compress", "ebcc_
 class Params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("bound_mode", C.c_uint32), ("err_bound", C.c_double),
                 ("base_ratio", C.c_double), ("q", C.c_double), ("levels", C.c_uint32), ("cblk_log2w", C.c_uint32),
-                ("cblk_log2h", C.c_uint32), ("spiht_tile", C.c_uint32), ("trunc", C.c_uint32)]
+                ("cblk_log2h", C.c_uint32), ("spiht_tile", C.c_uint32), ("trunc", C.c_uint32),
+                ("bypass", C.c_uint32)]
 
 
 class Tuning(C.Structure):
@@ -90,12 +91,13 @@ def lib():
 
 
 def params(err_bound=0.01, base_ratio=30.0, bound_mode=BOUND_REL, levels=5, cblk_log2w=5, cblk_log2h=5,
-           spiht_tile=1, q=0.0, trunc=0):
+           spiht_tile=1, q=0.0, trunc=0, bypass=0):
     p = Params()
     lib().ebcc_params_default(C.byref(p))
     p.err_bound, p.base_ratio, p.bound_mode = float(err_bound), float(base_ratio), int(bound_mode)
     p.levels, p.cblk_log2w, p.cblk_log2h, p.spiht_tile, p.q = levels, cblk_log2w, cblk_log2h, spiht_tile, float(q)
     p.trunc = int(trunc)
+    p.bypass = int(bypass)
     return p
 
 

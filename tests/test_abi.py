@@ -38,6 +38,7 @@ def test_host_only_entry_points():
     L.ebcc_params_default(ctypes.byref(p))
     assert p.struct_size == ctypes.sizeof(ebcc.Params)
     assert (p.err_bound, p.base_ratio, p.levels, p.cblk_log2w, p.cblk_log2h, p.spiht_tile) == (0.01, 30.0, 5, 5, 5, 1)
+    assert (p.q, p.trunc, p.bypass) == (0.0, 0, 0)
     assert L.ebcc_compress_bound(181, 360) == 48 + 4 * 181 * 360
     assert L.ebcc_status_str(-3) == b"corrupt stream"
     hdr = bytearray(48)
@@ -113,6 +114,10 @@ def test_workspace_size_queries():
     assert ebcc.workspace_size(0, 5) == 0 and ebcc.workspace_size(1 << 25, 2) == 0
     p = ebcc.params(cblk_log2w=2)           # 4x32 code-blocks: more blocks, more tables
     assert ebcc.workspace_size(721, 1440, p) > single[-1]
+    # the tier-1 bypass adds a raw-bit table per block and pass; other values are refused
+    assert ebcc.workspace_size(721, 1440, ebcc.params(bypass=1)) > single[-1]
+    assert ebcc.workspace_size(721, 1440, ebcc.params(bypass=2)) == 0
+    assert ebcc.workspace_size(721, 1440, ebcc.params(trunc=2)) == 0
     mix = [shapes[i % 4] for i in range(37)]
     batch = ebcc.workspace_size_batch(mix)
     assert 0 < batch <= sum(single[i % 4] for i in range(37))
