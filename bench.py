@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--q", type=float, default=1 - 1e-5, help="proportion q of the ratio-search run (0: skip)")
     ap.add_argument("--ablation-fields", type=int, default=256, help="fields of the q ablation (0: skip)")
     ap.add_argument("--byte-cut", type=int, default=1, help="measure the byte-granular residual cut (0: skip)")
+    ap.add_argument("--bypass", type=int, default=1,
+                    help="measure the tier-1 arithmetic-coding bypass against MQ-only streams (0: skip)")
     ap.add_argument("--km-fields", type=int, default=16, help="km-scale 1801x3600 vortex fields (0: skip)")
     ap.add_argument("--batch-fields", type=int, default=256, help="fields of the uneven batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of each oracle baseline leg")
@@ -669,6 +671,51 @@ def main():
         byte_cut["per_field_fields"] = len(lc)
         log(f"byte cut: {byte_cut}")
 
+    # ---------------- tier-1 arithmetic-coding bypass (bypass = 1) ----------------
+    bypass = None
+    if args.bypass:
+        bypass = {"workload": f"the stack ({len(xs)} fields of {args.ny}x{args.nx}), per-field and batched entry "
+                              f"points, r {args.ratio}, with and without the arithmetic-coding bypass "
+                              f"(raw SPP/MRP passes after the tenth)"}
+        yout = None
+        for e in (args.eps, 0.001):
+            row = {}
+            bargs_y = ebcc.BatchArgs(xs, err_bounds=[e] * len(xs))
+            if yout is None:
+                yout = torch.empty(bargs_y.bound(), dtype=torch.uint8, device=dev)
+            for byp in (0, 1):
+                pl = [ebcc.params(e, args.ratio, bypass=byp, **fmt)] * len(xs)
+                per_field_step(xs, outs, recs, lens, pl)             # warm-up (graphs, workspace)
+                lc, ld = [], []
+                ebcc.profile_enable(True)
+                torch.cuda.synchronize()
+                tcy, tdy = per_field_step(xs, outs, recs, lens, pl, lc, ld)
+                prof_y = ebcc.profile_read()
+                ebcc.profile_enable(False)
+                vy, my = verify(stack_h, recs, [e] * len(xs))
+                st = {k: v for k, v in prof_y.items() if k.startswith("t1") and v[1] > 0}
+                pb = ebcc.params(e, args.ratio, bypass=byp, **fmt)
+                assert ebcc.compress_batch_into(bargs_y, yout, pb, stream) == 0
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                assert ebcc.compress_batch_into(bargs_y, yout, pb, stream) == 0
+                torch.cuda.synchronize()
+                b = time.perf_counter()
+                ys_ = [yout[bargs_y.offsets[i]: bargs_y.offsets[i] + bargs_y.lengths[i]] for i in range(bargs_y.n)]
+                assert ebcc.decompress_batch_into(ebcc.DecodeArgs(ys_, recs), stream) == 0
+                torch.cuda.synchronize()
+                c = time.perf_counter()
+                vb, _ = verify(stack_h, recs, [e] * len(xs))
+                row["bypass" if byp else "mq_only"] = {
+                    "CR": nbytes / sum(lens), "per_field_compress_ms_p50": pct(lc, 50) * 1e3,
+                    "per_field_decompress_ms_p50": pct(ld, 50) * 1e3, "per_field_GBps": nbytes / (tcy + tdy) / 1e9,
+                    "tier1_stage_ms_per_call": {k: v[0] / v[1] for k, v in st.items()},
+                    "batched_compress_GBps": nbytes / (b - a) / 1e9, "batched_decompress_GBps": nbytes / (c - b) / 1e9,
+                    "violations": vy + vb, "max_err_rel": my}
+            row["CR_cost_pct"] = 100.0 * (1.0 - row["bypass"]["CR"] / row["mq_only"]["CR"])
+            bypass[f"eps_{e:g}"] = row
+        log(f"bypass: {bypass}")
+
     # ---------------- ablation of q (relative CR against q = 1) ----------------
     q_ablation = None
     if args.ablation_fields and bx:
@@ -838,6 +885,7 @@ def main():
         "serving": serving,
         "ratio_search": ratio_search,
         "byte_cut": byte_cut,
+        "bypass": bypass,
         "q_ablation": q_ablation,
         "km_scale": km,
         "tier1_decisions": tier1,
