@@ -462,7 +462,7 @@ struct BitRU {
 // wave-uniform decoder finds a node's band and offspring with a ballot and
 // readlanes instead of LDS round trips.
 struct GeomRegs {
-  int off, wr, r0, c0, h, w, level;
+  int off, wr, r0, c0, h, w, level, hr, y0, x0;
   uint32_t mlo, mhi;
   int nb;
   __device__ void load(const TileGeom& g, const Band* B, int nb_, int lane) {
@@ -475,6 +475,9 @@ struct GeomRegs {
     h = in ? B[lane].h : 0;
     w = in ? B[lane].w : 0;
     level = in ? B[lane].level : 0;
+    hr = in ? g.hr[lane] : 0;
+    y0 = in ? B[lane].y0 : 0;
+    x0 = in ? B[lane].x0 : 0;
     const uint64_t m = in ? g.mg[lane] : 0;
     mlo = (uint32_t)m;
     mhi = (uint32_t)(m >> 32);
@@ -535,11 +538,29 @@ __device__ __forceinline__ void kids_uniform(const GeomRegs& G, int L, int loc, 
   K.n = (r1 > 2 * i && c1 > 2 * j) ? (r1 - 2 * i) * (c1 - 2 * j) : 0;
 }
 
+// The decoder's LDS: the band table and the tile's geometry are needed only
+// until the lists are set up and the geometry is in registers, so the
+// decoded magnitudes reuse their space (more tiles resident per CU).
+template <int CAP>
+struct SpihtDecLds {
+  union {
+    struct {
+      Band B[kMaxBands];
+      TileGeom g;
+    } s;
+    uint32_t qv[CAP];        // decoded magnitude | sign << 31
+  } u;
+  uint16_t lip[CAP], lsp[CAP];
+  uint16_t lis[CAP];         // local index | typeB << 15
+  int ok;
+};
+
 template <int CAP>
 __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restrict__ F, const TileD* __restrict__ tiles,
                                                          const int* __restrict__ tix, const int64_t* __restrict__ toff,
                                                          int* __restrict__ misfit) {
-  __shared__ SpihtLds<CAP> S;
+  static_assert(sizeof(Band) * kMaxBands + sizeof(TileGeom) <= sizeof(uint32_t) * CAP, "decoder LDS union");
+  __shared__ SpihtDecLds<CAP> S;
   const int lane = threadIdx.x;
   const int t = tix[blockIdx.x];
   const TileD td = tiles[t];
@@ -552,12 +573,19 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
   float* chat = f.buf[BUF_CHAT];
   int* flag = &f.flags[1];
   const int tl = t - f.tile0;
-  if (!spiht_setup<CAP>(S, bands_g, nb, L, td, lane)) {
+  for (int i = lane; i < nb; i += 64) S.u.s.B[i] = bands_g[i];
+  __syncthreads();
+  if (lane == 0) {
+    tile_geom(S.u.s.g, S.u.s.B, nb, L, td);
+    S.ok = S.u.s.g.ncoef <= CAP && 2 * S.u.s.g.nparents <= CAP;
+  }
+  __syncthreads();
+  if (!S.ok) {
     if (lane == 0) misfit[t] = 1;
     return;
   }
   if (lane == 0) misfit[t] = 0;
-  const TileGeom& g = S.g;
+  const TileGeom& g = S.u.s.g;
   const uint32_t ent = (uint32_t)__builtin_amdgcn_readfirstlane(
       (int)((uint32_t)sec[4 * tl] | ((uint32_t)sec[4 * tl + 1] << 8) | ((uint32_t)sec[4 * tl + 2] << 16) |
             ((uint32_t)sec[4 * tl + 3] << 24)));
@@ -585,8 +613,7 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
   }
   if (ntop < n_bot) return;
   const uint8_t* pay = sec + pbase + o0;
-  for (int i = lane; i < g.ncoef; i += 64) S.qv[i] = 0;
-  const int nroots = g.hr[0] * g.wr[0];
+  const int nroots = g.hr[0] * g.wr[0], ncoef = g.ncoef;
   int nlis = 0;
   for (int r0 = 0; r0 < nroots; r0 += 64) {
     int r = r0 + lane;
@@ -594,16 +621,20 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
     int has = 0;
     if (r < nroots) {
       S.lip[r] = (uint16_t)r;
-      has = offspring_local(g, S.B, nb, L, r, ch, &cl) > 0;
+      has = offspring_local(g, S.u.s.B, nb, L, r, ch, &cl) > 0;
     }
     int tot;
     int pre = wscan_excl(has, lane, &tot);
     if (has) S.lis[nlis + pre] = (uint16_t)r;
     nlis += tot;
   }
-  __syncthreads();
   GeomRegs G;
-  G.load(g, S.B, nb, lane);
+  G.load(g, S.u.s.B, nb, lane);
+  // the band table and geometry are in registers now: their LDS becomes
+  // the decoded magnitudes
+  __syncthreads();
+  for (int i = lane; i < ncoef; i += 64) S.u.qv[i] = 0;
+  __syncthreads();
   int nlip = nroots, nlsp = 0;
   BitRU rd;
   rd.init(pay, len);
@@ -641,7 +672,7 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
         pv = lane < pcnt ? (uint32_t)S.lip[k + lane] : 0u;
       }
       int e = rl((int)pv, k - pbase);
-      if (lane == 0) { S.qv[e] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)e; }
+      if (lane == 0) { S.u.qv[e] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)e; }
       nlsp++;
       k++;
     }
@@ -683,7 +714,7 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
           }
           if (rd.get()) {
             const int sg = rd.get();
-            if (lane == 0) { S.qv[c] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)c; }
+            if (lane == 0) { S.u.qv[c] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)c; }
             nlsp++;
           } else {
             if (lane == 0) S.lip[nlip] = (uint16_t)c;
@@ -725,19 +756,21 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
       const int kk = h0 + lane;
       if (lane < n) {
         const uint32_t b = lane < 32 ? (w0 >> (31 - lane)) & 1u : (w1 >> (63 - lane)) & 1u;
-        if (b) S.qv[S.lsp[kk]] |= thr;
+        if (b) S.u.qv[S.lsp[kk]] |= thr;
       }
     }
     __syncthreads();
   }
-  // dequantised significant coefficients
+  // dequantised significant coefficients (band geometry from the lanes of
+  // G, read in wave-uniform code)
   for (int b = 0; b < nb; b++) {
-    int n = g.hr[b] * g.wr[b];
+    const int wrb = rl(G.wr, b), n = rl(G.hr, b) * wrb, offb = rl(G.off, b);
+    const int yb = rl(G.y0, b) + rl(G.r0, b), xb = rl(G.x0, b) + rl(G.c0, b);
     for (int r = lane; r < n; r += 64) {
-      uint32_t v = S.qv[g.off[b] + r];
+      uint32_t v = S.u.qv[offb + r];
       if (!v) continue;
-      int li = r / g.wr[b], lj = r - li * g.wr[b];
-      int p = (S.B[b].y0 + g.r0[b] + li) * nx + S.B[b].x0 + g.c0[b] + lj;
+      int li = r / wrb, lj = r - li * wrb;
+      int p = (yb + li) * nx + xb + lj;
       uint32_t m = v & 0x7FFFFFu;
       // lowest known plane: n_bot, or above it for coefficients significant
       // before a last plane whose refinement pass was not decoded
