@@ -168,6 +168,20 @@ __global__ __launch_bounds__(256) void k_put_bytes(uint8_t* __restrict__ dst, co
   for (int i = threadIdx.x; i < n; i += 256) dst[i] = c.b[i];
 }
 
+// Stream headers of a decode batch gathered in one launch per kHdrArgs
+// streams (their addresses travel as kernel arguments): workgroup i copies
+// the 48 header bytes of stream i, or zeros for a stream shorter than a
+// header, to out[48 i ..].
+constexpr int kHdrArgs = 64;
+struct HdrArgs {
+  const uint8_t* p[kHdrArgs];
+  int ok[kHdrArgs];
+};
+__global__ __launch_bounds__(64) void k_read_headers(const HdrArgs a, int n, uint8_t* __restrict__ out) {
+  const int i = blockIdx.x, j = threadIdx.x;
+  if (i < n && j < kHdr) out[kHdr * i + j] = a.ok[i] ? a.p[i][j] : (uint8_t)0;
+}
+
 __global__ void k_init_fields(const FieldDev* __restrict__ F, int nf) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nf) return;
@@ -2051,16 +2065,35 @@ static size_t decompress_need(Call& c, const std::vector<int>& coded) {
 }
 
 // Copies the first 48 bytes of each stream (device) to hdr (host); streams
-// shorter than a header leave zeros.
+// shorter than a header leave zeros.  The headers are gathered by kernels
+// into the stream's pinned staging buffer (mapped host memory), then read
+// after one wait: no copy per stream.
 static int read_headers(const std::vector<const uint8_t*>& d_in, const std::vector<size_t>& len,
                         std::vector<uint8_t>& hdr, hipStream_t st) {
-  hdr.assign(kHdr * d_in.size(), 0);
-  for (size_t i = 0; i < d_in.size(); i++) {
+  const size_t n = d_in.size();
+  hdr.assign(kHdr * n, 0);
+  for (size_t i = 0; i < n; i++)
     if (!d_in[i]) return fail(EBCC_EINVAL, "NULL buffer");
-    if (len[i] >= (size_t)kHdr)
-      HIPCHK(hipMemcpyAsync(hdr.data() + kHdr * i, d_in[i], kHdr, hipMemcpyDeviceToHost, st));
+  WS* ws = nullptr;
+  if (int rc = get_ws(st, &ws)) return rc;
+  char* base = nullptr;
+  if (int rc = grow_ws(ws, 0, kHdr * n, st, &base)) return rc;
+  uint8_t* d_pin = nullptr;
+  HIPCHK(hipHostGetDevicePointer((void**)&d_pin, ws->pin, 0));
+  for (size_t i0 = 0; i0 < n; i0 += kHdrArgs) {
+    const int m = (int)std::min<size_t>(kHdrArgs, n - i0);
+    HdrArgs a;
+    for (int k = 0; k < kHdrArgs; k++) {
+      const bool in = k < m && len[i0 + k] >= (size_t)kHdr;
+      a.p[k] = in ? d_in[i0 + k] : nullptr;
+      a.ok[k] = in ? 1 : 0;
+    }
+    k_read_headers<<<m, 64, 0, st>>>(a, m, d_pin + kHdr * i0);
   }
-  return wait_stream(st);
+  HIPCHK(hipGetLastError());
+  if (int rc = wait_stream(st)) return rc;
+  memcpy(hdr.data(), ws->pin, kHdr * n);
+  return EBCC_OK;
 }
 
 // The decode calls of a batch: one launch sequence decodes streams of one
