@@ -171,9 +171,14 @@ __device__ __forceinline__ int mq_flush_copy(const MQEnc& e, uint32_t* tail) {
   return e.BP + 3 - (tb[2] == 0xFF ? 1 : 0);
 }
 
-template <typename M, int ROWS, int LANES>
+// Coding-pass state of a workgroup's blocks, one bit mask per block row.
+// The encoder reads its signs and magnitude bits from the bit-plane masks in
+// global memory (read-only, cached), so it keeps four row arrays (more
+// workgroups per compute unit); the decoder also keeps the decoded signs.
+template <typename M, int ROWS, int LANES, bool ENC>
 struct T1Shared {
-  M sig[ROWS][LANES], vis[ROWS][LANES], ref[ROWS][LANES], neg[ROWS][LANES], mag[ROWS][LANES], aux[ROWS][LANES];
+  M sig[ROWS][LANES], vis[ROWS][LANES], ref[ROWS][LANES], aux[ROWS][LANES];
+  M neg[ENC ? 1 : ROWS][LANES];
   uint8_t ctx[kNCtx][LANES];
   uint32_t mqt[47];
   // context labels by neighbourhood pattern: zero coding for LL/LH, HL and
@@ -190,45 +195,11 @@ struct T1Shared {
   }
 };
 
-template <typename M, int ROWS, int LANES>
-struct T1Lane {
-  T1Shared<M, ROWS, LANES>& S;
-  int lane, h, w, orient;
-  __device__ M row(M (*a)[LANES], int y) const { return (y >= 0 && y < h) ? a[y][lane] : (M)0; }
-  // neighbourhood pattern of sample (y, x) (zc_pat)
-  __device__ uint32_t zpat(int y, int x) const {
-    return zc_pat(f3(row(S.sig, y - 1), x), f3(S.sig[y][lane], x), f3(row(S.sig, y + 1), x));
-  }
-  __device__ const uint8_t* ztab() const { return S.zct[orient == ORI_HH ? 2 : (orient == ORI_HL ? 1 : 0)]; }
-  __device__ int sign_ctx(int y, int x, int* xr) const {
-    const uint32_t e = S.sct[sc_pat(f3(S.sig[y][lane], x), f3(S.neg[y][lane], x), (uint32_t)bt(row(S.sig, y - 1), x),
-                                    (uint32_t)bt(row(S.neg, y - 1), x), (uint32_t)bt(row(S.sig, y + 1), x),
-                                    (uint32_t)bt(row(S.neg, y + 1), x))];
-    *xr = (int)(e >> 3);
-    return CX_SC + (int)(e & 7u);
-  }
-  // columns of stripe y0 (rn rows) holding a sample with sig = 0 and at
-  // least one significant neighbour, restricted to columns >= x
-  __device__ M spp_cands(int y0, int rn, int x) const {
-    M c = 0;
-    for (int r = 0; r < rn; r++) {
-      M mid = S.sig[y0 + r][lane];
-      M nb = row(S.sig, y0 + r - 1) | mid | row(S.sig, y0 + r + 1);
-      nb = nb | (nb << 1) | (nb >> 1);
-      c |= ~mid & nb;
-    }
-    M wm = (w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << w) - 1);
-    return c & wm & (~(M)0 << x);
-  }
-  __device__ bool run_ok(int y0, int x) const {
-    for (int r = 0; r < 4; r++)
-      if (bt(S.sig[y0 + r][lane] | S.vis[y0 + r][lane], x)) return false;
-    M nbm = nb3<M>(x);
-    for (int y = y0 - 1; y <= y0 + 4; y++)
-      if (row(S.sig, y) & nbm) return false;
-    return true;
-  }
-};
+// Zero-coding label table of a block of orientation `orient`.
+template <typename S_>
+__device__ __forceinline__ const uint8_t* ztab_of(const S_& S, int orient) {
+  return S.zct[orient == ORI_HH ? 2 : (orient == ORI_HL ? 1 : 0)];
+}
 
 // Row r' in [-1, 4] of the current stripe's significance / sign rows.
 #define SR(rr) ((rr) < 0 ? sA : ((rr) > 3 ? sC : sB[(rr)]))
@@ -238,7 +209,7 @@ struct T1Lane {
 // Tier-1 encoder: one lane per code-block.
 // ------------------------------------------------------------------------
 template <typename M, int ROWS, int LANES>
-__device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES>& S, int lane, int b, const FieldDev* __restrict__ F,
+__device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, int lane, int b, const FieldDev* __restrict__ F,
                                              const Blk* __restrict__ blk, int nblk, int cbh,
                                              const M* __restrict__ planes, const M* __restrict__ signs,
                                              const uint8_t* __restrict__ pbv, uint8_t* __restrict__ cw,
@@ -261,11 +232,10 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES>& S, int la
     for (int y = 0; y < k.h; y++) spo[y] = 0;
     return;
   }
-  T1Lane<M, ROWS, LANES> T{S, lane, k.h, k.w, k.orient};
-  const uint8_t* zt = T.ztab();
+  const uint8_t* zt = ztab_of(S, k.orient);
+  const M* sg = signs + (size_t)b * cbh;
   for (int y = 0; y < k.h; y++) {
     S.sig[y][lane] = 0; S.vis[y][lane] = 0; S.ref[y][lane] = 0; S.aux[y][lane] = 0;
-    S.neg[y][lane] = signs[(size_t)b * cbh + y];
   }
   for (int c = 0; c < kNCtx; c++) S.ctx[c][lane] = 0;
   S.ctx[0][lane] = 4; S.ctx[CX_RL][lane] = 3; S.ctx[CX_UNI][lane] = 46;
@@ -283,15 +253,17 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES>& S, int la
   auto rowm = [&](M (*a)[LANES], int y) -> M { return (y >= 0 && y < h) ? a[y][lane] : (M)0; };
   for (int p = P - 1; p >= 0 && !stop; p--) {
     const M* pl = planes + ((size_t)b * kQBits + p) * cbh;
-    for (int y = 0; y < h; y++) S.mag[y][lane] = pl[y];
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
       int64_t dd = 0;
       // the stripe's rows (and the rows above and below) are held in
-      // registers while the stripe is coded, then written back
+      // registers while the stripe is coded, then written back; magnitude
+      // bits and signs come from global memory (no sign coding in a
+      // refinement pass)
+      const bool sgn = ty != 1;
       for (int y0 = 0; y0 < h && !stop; y0 += 4) {
         const int rn = h - y0 < 4 ? h - y0 : 4;
         const M sA = rowm(S.sig, y0 - 1), sC = rowm(S.sig, y0 + 4);
-        const M nA = rowm(S.neg, y0 - 1), nC = rowm(S.neg, y0 + 4);
+        const M nA = (sgn && y0 > 0) ? sg[y0 - 1] : (M)0, nC = (sgn && y0 + 4 < h) ? sg[y0 + 4] : (M)0;
         M sB[4], vB[4], fB[4], gB[4], nB[4], aB[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
@@ -299,8 +271,8 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES>& S, int la
           sB[r] = in ? S.sig[y0 + r][lane] : (M)0;
           vB[r] = in ? S.vis[y0 + r][lane] : (M)0;
           fB[r] = (in && ty == 1) ? S.ref[y0 + r][lane] : (M)0;
-          gB[r] = in ? S.mag[y0 + r][lane] : (M)0;
-          nB[r] = in ? S.neg[y0 + r][lane] : (M)0;
+          gB[r] = in ? pl[y0 + r] : (M)0;
+          nB[r] = (in && sgn) ? sg[y0 + r] : (M)0;
           aB[r] = 0;
         }
         // r is a compile-time constant in every caller (unrolled loops)
@@ -458,7 +430,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
                                                      int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
                                                      uint32_t* __restrict__ tailt, M* __restrict__ sppf,
                                                      const int* __restrict__ order, int* __restrict__ qctr) {
-  __shared__ T1Shared<M, ROWS, LANES> S;
+  __shared__ T1Shared<M, ROWS, LANES, true> S;
   const int lane = threadIdx.x;
   S.fill_tables(lane, LANES);
   __syncthreads();
@@ -607,7 +579,7 @@ __device__ __forceinline__ int mq_decode(MQDec& d, uint8_t* cs_ptr, const uint32
 // in yhat's storage as integers until the block is finished.
 // ------------------------------------------------------------------------
 template <typename M, int ROWS, int LANES>
-__device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES>& S, int lane, int b,
+__device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S, int lane, int b,
                                              const FieldDev* __restrict__ F, const Blk* __restrict__ blk, int nblk,
                                              const uint32_t* __restrict__ table, const int64_t* __restrict__ off) {
   // S.aux = coded in the current plane
@@ -632,8 +604,7 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES>& S, int la
       for (int x = 0; x < k.w; x++) yb[y * nx + x] = 0.0f;
     return;
   }
-  T1Lane<M, ROWS, LANES> T{S, lane, k.h, k.w, k.orient};
-  const uint8_t* zt = T.ztab();
+  const uint8_t* zt = ztab_of(S, k.orient);
   for (int y = 0; y < k.h; y++) {
     S.sig[y][lane] = 0; S.vis[y][lane] = 0; S.ref[y][lane] = 0; S.neg[y][lane] = 0; S.aux[y][lane] = 0;
   }
@@ -818,7 +789,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
                                                      int nblk, const uint32_t* __restrict__ table,
                                                      const int64_t* __restrict__ off, const int* __restrict__ order,
                                                      int* __restrict__ qctr) {
-  __shared__ T1Shared<M, ROWS, LANES> S;
+  __shared__ T1Shared<M, ROWS, LANES, false> S;
   const int lane = threadIdx.x;
   S.fill_tables(lane, LANES);
   __syncthreads();
