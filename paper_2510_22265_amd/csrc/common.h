@@ -196,7 +196,8 @@ struct T1Split {
 // order (nblk ints) and qctr (one int): scratch of the persistent
 // lanes-per-block launch, used when that launch is chosen (may be null).
 // rbt (nblk * kPassStride): raw bits per block and pass when some field uses
-// the bypass (then the wavefront-per-block coders run), else null.
+// the bypass (the coders are then instantiated with the raw passes), else
+// null.
 void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
                const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
                uint32_t* tail, void* sppf, hipStream_t st, const T1Split* sp = nullptr, int* order = nullptr,
@@ -205,7 +206,8 @@ void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
                     const uint8_t* kb, const void* sppf, hipStream_t st);
 // table: per-block entries (P | k << 8 | len << 16); off: payload offsets
 // within each field's base payload (which starts at out + 48 + 4 nblk).
-// byp: some field uses the bypass (then the wavefront-per-block decoder runs).
+// byp: some field uses the bypass (the decoders are then instantiated with
+// the raw passes).
 void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
                const int64_t* off, hipStream_t st, const T1Split* sp = nullptr, int* order = nullptr,
                int* qctr = nullptr, bool byp = false);

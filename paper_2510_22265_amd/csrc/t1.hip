@@ -87,13 +87,15 @@ __global__ __launch_bounds__(256) void k_quant_planes(const FieldDev* __restrict
 // MQ encoder in registers.  B is the byte at index BP (not yet written: it
 // may still receive a carry); BP = -1 is the dummy byte before the output.
 // ------------------------------------------------------------------------
+// Bytes are stored below cap: the block's coder buffer, or its MQ area when
+// the buffer also holds raw bits (arithmetic-coding bypass).
 struct MQEnc {
   uint32_t C, A, B;
-  int CT, BP;
+  int CT, BP, cap;
   uint8_t* out;
 };
 __device__ __forceinline__ void mq_emit(MQEnc& e, uint32_t nb) {
-  if (e.BP >= 0 && e.BP < kCwCap) e.out[e.BP] = (uint8_t)e.B;
+  if (e.BP >= 0 && e.BP < e.cap) e.out[e.BP] = (uint8_t)e.B;
   e.BP++;
   e.B = nb;
 }
@@ -208,17 +210,21 @@ __device__ __forceinline__ const uint8_t* ztab_of(const S_& S, int orient) {
 // ------------------------------------------------------------------------
 // Tier-1 encoder: one lane per code-block.
 // ------------------------------------------------------------------------
-template <typename M, int ROWS, int LANES>
+// BYP: the launch may hold fields with the arithmetic-coding bypass (their
+// significance-propagation and refinement passes after the tenth write raw
+// bits into the buffer's raw area; rbt receives each pass's raw bit count).
+template <typename M, int ROWS, int LANES, bool BYP>
 __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, int lane, int b, const FieldDev* __restrict__ F,
                                              const Blk* __restrict__ blk, int nblk, int cbh,
                                              const M* __restrict__ planes, const M* __restrict__ signs,
                                              const uint8_t* __restrict__ pbv, uint8_t* __restrict__ cw,
                                              int32_t* __restrict__ Rt, int64_t* __restrict__ Dt,
                                              int32_t* __restrict__ bpt, uint32_t* __restrict__ tailt,
-                                             M* __restrict__ sppf) {
+                                             M* __restrict__ sppf, int32_t* __restrict__ rbt) {
   if (b >= nblk) return;
   Blk k = blk[b];
   if (!F[k.field].active) return;
+  const bool byp = BYP && F[k.field].byp;
   const float* coef = F[k.field].buf[BUF_COEF];
   const int nx = F[k.field].nx, e0 = F[k.field].e0;
   int P = pbv[b];
@@ -227,6 +233,8 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
   int32_t* BPk = bpt + (size_t)b * kPassStride;
   uint32_t* TL = tailt + (size_t)b * kPassStride;
   R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0;
+  int32_t* RB = BYP ? rbt + (size_t)b * kPassStride : nullptr;
+  if (byp) RB[0] = 0;
   M* spo = sppf + (size_t)b * cbh;
   if (P == 0) {
     for (int y = 0; y < k.h; y++) spo[y] = 0;
@@ -241,6 +249,24 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
   S.ctx[0][lane] = 4; S.ctx[CX_RL][lane] = 3; S.ctx[CX_UNI][lane] = 46;
   MQEnc e;
   e.C = 0; e.A = 0x8000; e.B = 0; e.CT = 12; e.BP = -1; e.out = cw + (size_t)b * kCwCap;
+  e.cap = byp ? kRawOff : kCwCap;
+  // raw bits: racc holds rnb pending bits (first in bit 31), rwi words stored
+  uint32_t racc = 0;
+  int rnb = 0, rwi = 0;
+  uint32_t* const rawp = reinterpret_cast<uint32_t*>(e.out + kRawOff);
+  auto rawput = [&](int d) {
+    racc |= (uint32_t)d << (31 - rnb);
+    if (++rnb == 32) {
+      if (rwi < kRawCap / 4) rawp[rwi] = __builtin_bswap32(racc);
+      rwi++;
+      racc = 0;
+      rnb = 0;
+    }
+  };
+  // lengths past these are never kept: stop coding once one is reached
+  const int mq_stop = byp ? kBypMqMax : 65536;
+  int lrk = 0, lbp = -1;              // the last MQ-coded pass's termination
+  uint32_t ltail = 0;
   const int sh = k.gain - e0;
   const float* cb = coef + (size_t)k.y0 * nx + k.x0;
   auto qat = [&](int y, int x) { return quantq(cb[y * nx + x], sh); };
@@ -255,6 +281,8 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
     const M* pl = planes + ((size_t)b * kQBits + p) * cbh;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
       int64_t dd = 0;
+      // pass numbers 11 and later of planes p <= P - 5 (SPP, MRP) are raw
+      const bool raw = byp && ty < 2 && p <= P - 5;
       // the stripe's rows (and the rows above and below) are held in
       // registers while the stripe is coded, then written back; magnitude
       // bits and signs come from global memory (no sign coding in a
@@ -277,6 +305,10 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
         }
         // r is a compile-time constant in every caller (unrolled loops)
         auto code_sign = [&](int r, int x) {
+          if (raw) {                                     // a raw pass sends the sign itself
+            rawput(btu(nB[r], x));
+            return;
+          }
           const uint32_t sc = S.sct[sc_pat(f3(SR(r), x), f3(NR(r), x), (uint32_t)btu(SR(r - 1), x),
                                            (uint32_t)btu(NR(r - 1), x), (uint32_t)btu(SR(r + 1), x),
                                            (uint32_t)btu(NR(r + 1), x))];
@@ -306,7 +338,8 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
               const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
               if (!pat) continue;
               const int bit = btu(gB[r], x);
-              mq_enc(&S.ctx[zt[pat]][lane], bit);
+              if (raw) rawput(bit);
+              else mq_enc(&S.ctx[zt[pat]][lane], bit);
               vB[r] |= (M)1 << x;
               if (bit) {
                 code_sign(r, x);
@@ -334,8 +367,12 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
 #pragma unroll
             for (int r = 0; r < 4; r++) {
               if (r >= rn || !btu(sB[r] & ~vB[r], x)) continue;
-              const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nbm[r], x) ? CX_MR + 1 : CX_MR);
-              mq_enc(&S.ctx[cx][lane], btu(gB[r], x));
+              if (raw) {
+                rawput(btu(gB[r], x));
+              } else {
+                const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nbm[r], x) ? CX_MR + 1 : CX_MR);
+                mq_enc(&S.ctx[cx][lane], btu(gB[r], x));
+              }
               fB[r] |= (M)1 << x;
               dd += ref_delta(qat(y0 + r, x), p);
             }
@@ -398,21 +435,31 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
             if (ty == 1) S.ref[y0 + r][lane] = fB[r];
             if (ty == 0) S.aux[y0 + r][lane] |= aB[r];
           }
-        if (e.BP >= 65536) stop = true;       // every later pass exceeds the length limit
+        // every later pass exceeds a length limit
+        if (e.BP >= mq_stop || (byp && 32 * rwi + rnb > 8 * kBypRawMax)) stop = true;
       }
       if (ty == 2)
         for (int y = 0; y < h; y++) S.vis[y][lane] = 0;
       if (stop) break;
       kk++;
       Dcum += dd;
-      uint32_t tail;
-      R[kk] = mq_flush_copy(e, &tail);
+      // a raw pass's MQ part is the last MQ-coded pass's codeword
+      if (!raw) { lrk = mq_flush_copy(e, &ltail); lbp = e.BP; }
+      int rk = lrk;
+      if (byp) {
+        const int rbits = 32 * rwi + rnb, rby = (rbits + 7) >> 3;
+        if (kk >= kBypFirst) rk = 2 + lrk + rby;
+        if (lrk > kBypMqMax || rby > kBypRawMax) rk = kRInf;
+        RB[kk] = rbits;
+      }
+      R[kk] = rk;
       Dd[kk] = Dcum;
-      BPk[kk] = e.BP;
-      TL[kk] = tail;
+      BPk[kk] = lbp;
+      TL[kk] = ltail;
     }
   }
   for (int j = kk + 1; j <= npass; j++) { R[j] = kRInf; Dd[j] = Dcum; BPk[j] = 0; TL[j] = 0; }
+  if (byp && rnb && rwi < kRawCap / 4) rawp[rwi] = __builtin_bswap32(racc);   // the last, partial word
   for (int y = 0; y < k.h; y++) spo[y] = S.aux[y][lane];
 }
 
@@ -422,21 +469,22 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
 // `order` from the counter *qctr (zero at launch) until none is left; the
 // order puts blocks with more bit-planes first, so the longest blocks start
 // early and a workgroup's lanes hold blocks of similar length.
-template <typename M, int ROWS, int LANES>
+template <typename M, int ROWS, int LANES, bool BYP>
 __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
                                                      int nblk, int cbh, const M* __restrict__ planes,
                                                      const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
                                                      uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
                                                      int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
                                                      uint32_t* __restrict__ tailt, M* __restrict__ sppf,
-                                                     const int* __restrict__ order, int* __restrict__ qctr) {
+                                                     const int* __restrict__ order, int* __restrict__ qctr,
+                                                     int32_t* __restrict__ rbt) {
   __shared__ T1Shared<M, ROWS, LANES, true> S;
   const int lane = threadIdx.x;
   S.fill_tables(lane, LANES);
   __syncthreads();
   if (!order) {
-    t1_enc_block<M, ROWS, LANES>(S, lane, blockIdx.x * LANES + lane, F, blk, nblk, cbh, planes, signs, pbv, cw, Rt,
-                                 Dt, bpt, tailt, sppf);
+    t1_enc_block<M, ROWS, LANES, BYP>(S, lane, blockIdx.x * LANES + lane, F, blk, nblk, cbh, planes, signs, pbv, cw,
+                                      Rt, Dt, bpt, tailt, sppf, rbt);
     return;
   }
   const int ngroups = (nblk + LANES - 1) / LANES;
@@ -447,8 +495,8 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
     if (g >= ngroups) break;
     const int i = g * LANES + lane;
     if (i < nblk)
-      t1_enc_block<M, ROWS, LANES>(S, lane, order[i], F, blk, nblk, cbh, planes, signs, pbv, cw, Rt, Dt, bpt, tailt,
-                                   sppf);
+      t1_enc_block<M, ROWS, LANES, BYP>(S, lane, order[i], F, blk, nblk, cbh, planes, signs, pbv, cw, Rt, Dt, bpt,
+                                        tailt, sppf, rbt);
   }
 }
 
@@ -578,7 +626,8 @@ __device__ __forceinline__ int mq_decode(MQDec& d, uint8_t* cs_ptr, const uint32
 // every sample of the block into yhat; the magnitudes being decoded are kept
 // in yhat's storage as integers until the block is finished.
 // ------------------------------------------------------------------------
-template <typename M, int ROWS, int LANES>
+// BYP: the launch may hold streams with the arithmetic-coding bypass.
+template <typename M, int ROWS, int LANES, bool BYP>
 __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S, int lane, int b,
                                              const FieldDev* __restrict__ F, const Blk* __restrict__ blk, int nblk,
                                              const uint32_t* __restrict__ table, const int64_t* __restrict__ off) {
@@ -598,6 +647,18 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
   float* yb = yhat + (size_t)k.y0 * nx + k.x0;
   uint32_t* mb = reinterpret_cast<uint32_t*>(yb);
   bool bad = P > kQBits || kb > (P ? 3 * P - 2 : 0) || o < 0 || o + len > sec_len;
+  // bypass codeword after more than ten passes: u16 raw byte count, the MQ
+  // codeword, the raw bytes
+  const bool rawcw = BYP && f.byp && kb >= kBypFirst;
+  int rby = 0;
+  if (rawcw && !bad) {
+    if (len < 2) {
+      bad = true;
+    } else {
+      rby = (int)sec[o] | ((int)sec[o + 1] << 8);
+      if (2 + rby > len) bad = true;
+    }
+  }
   if (bad) atomicOr(flag, 1);
   if (bad || P == 0 || kb == 0) {
     for (int y = 0; y < k.h; y++)
@@ -611,8 +672,22 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
   for (int c = 0; c < kNCtx; c++) S.ctx[c][lane] = 0;
   S.ctx[0][lane] = 4; S.ctx[CX_RL][lane] = 3; S.ctx[CX_UNI][lane] = 46;
   MQDec d;
-  mq_dinit(d, sec + o, len);
+  mq_dinit(d, sec + o + (rawcw ? 2 : 0), rawcw ? len - 2 - rby : len);
   auto mq_dec = [&](uint8_t* cs) { return mq_decode(d, cs, S.mqt); };
+  // raw bits, MSB-first, bits past the end read as 0; the current byte and
+  // the next one are held in registers (the next load is issued a byte early)
+  const uint8_t* const rbuf = sec + o + len - rby;
+  int rpos = 0;
+  uint32_t rcur = (BYP && rby > 0) ? rbuf[0] : 0u, rnxt = (BYP && rby > 1) ? rbuf[1] : 0u;
+  auto rawget = [&]() -> int {
+    const int bit = (int)((rcur >> (7 - (rpos & 7))) & 1u);
+    if ((++rpos & 7) == 0) {
+      const int i = (rpos >> 3) + 1;
+      rcur = rnxt;
+      rnxt = i < rby ? rbuf[i] : 0u;
+    }
+    return bit;
+  };
   const int h = k.h, w = k.w;
   const M wm = (w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << w) - 1);
   auto rowm = [&](M (*a)[LANES], int y) -> M { return (y >= 0 && y < h) ? a[y][lane] : (M)0; };
@@ -631,6 +706,8 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
     plast = p;
     for (int y = 0; y < h; y++) S.aux[y][lane] = 0;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < kb; ty++) {
+      // pass numbers 11 and later of planes p <= P - 5 (SPP, MRP) are raw
+      const bool raw = rawcw && ty < 2 && p <= P - 5;
       for (int y0 = 0; y0 < h; y0 += 4) {
         const int rn = h - y0 < 4 ? h - y0 : 4;
         const M sA = rowm(S.sig, y0 - 1), sC = rowm(S.sig, y0 + 4);
@@ -647,6 +724,10 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
         }
         // r is a compile-time constant in every caller (unrolled loops)
         auto dec_sign = [&](int r, int x) {
+          if (raw) {                                     // a raw pass sends the sign itself
+            if (rawget()) nB[r] |= (M)1 << x;
+            return;
+          }
           const uint32_t sc = S.sct[sc_pat(f3(SR(r), x), f3(NR(r), x), (uint32_t)btu(SR(r - 1), x),
                                            (uint32_t)btu(NR(r - 1), x), (uint32_t)btu(SR(r + 1), x),
                                            (uint32_t)btu(NR(r + 1), x))];
@@ -673,7 +754,7 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
               if (btu(mid, x)) continue;
               const uint32_t pat = zc_pat(f3(SR(r - 1), x), f3(mid, x), f3(SR(r + 1), x));
               if (!pat) continue;
-              const int bit = mq_dec(&S.ctx[zt[pat]][lane]);
+              const int bit = raw ? rawget() : mq_dec(&S.ctx[zt[pat]][lane]);
               vB[r] |= (M)1 << x;
               if (bit) {
                 dec_sign(r, x);
@@ -702,7 +783,7 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
             for (int r = 0; r < 4; r++) {
               if (r >= rn || !btu(sB[r] & ~vB[r], x)) continue;
               const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nbm[r], x) ? CX_MR + 1 : CX_MR);
-              if (mq_dec(&S.ctx[cx][lane])) setbit(y0 + r, x, p);
+              if (raw ? rawget() : mq_dec(&S.ctx[cx][lane])) setbit(y0 + r, x, p);
               fB[r] |= (M)1 << x;
               aB[r] |= (M)1 << x;
             }
@@ -784,7 +865,7 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
 
 // One lane per code-block; with `order`, a persistent launch as for the
 // encoder (blocks ordered by coding passes kept, most first).
-template <typename M, int ROWS, int LANES>
+template <typename M, int ROWS, int LANES, bool BYP>
 __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
                                                      int nblk, const uint32_t* __restrict__ table,
                                                      const int64_t* __restrict__ off, const int* __restrict__ order,
@@ -794,7 +875,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
   S.fill_tables(lane, LANES);
   __syncthreads();
   if (!order) {
-    t1_dec_block<M, ROWS, LANES>(S, lane, blockIdx.x * LANES + lane, F, blk, nblk, table, off);
+    t1_dec_block<M, ROWS, LANES, BYP>(S, lane, blockIdx.x * LANES + lane, F, blk, nblk, table, off);
     return;
   }
   const int ngroups = (nblk + LANES - 1) / LANES;
@@ -804,7 +885,7 @@ __global__ __launch_bounds__(LANES) void k_t1_decode(const FieldDev* __restrict_
     g = __shfl(g, 0);   // one wavefront per workgroup (LANES <= 64)
     if (g >= ngroups) break;
     const int i = g * LANES + lane;
-    if (i < nblk) t1_dec_block<M, ROWS, LANES>(S, lane, order[i], F, blk, nblk, table, off);
+    if (i < nblk) t1_dec_block<M, ROWS, LANES, BYP>(S, lane, order[i], F, blk, nblk, table, off);
   }
 }
 
@@ -854,19 +935,19 @@ static int resident_groups(K kernel, int threads) {
 }
 
 // order/qctr non-null: persistent launch (order filled by k_t1_order first).
-template <typename M, int ROWS>
+template <typename M, int ROWS, bool BYP>
 static void launch_encode(int nblk, const FieldDev* F, const Blk* blk, int cbh, const void* planes, const void* signs,
                           const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail,
-                          void* sppf, hipStream_t st, int* order, int* qctr) {
+                          void* sppf, hipStream_t st, int* order, int* qctr, int32_t* rbt) {
   constexpr int LM = t1_lanes_max<M, ROWS>();
   int ln = pick_lanes(nblk, LM);
   if (order) k_t1_order<<<1, 256, 0, st>>>(pb, nblk, order, qctr);
 #define ENC_L(LN)                                                                                                  \
   do {                                                                                                             \
     const int groups = (nblk + LN - 1) / LN;                                                                       \
-    const int grid = order ? std::min(groups, resident_groups(k_t1_encode<M, ROWS, LN>, LN)) : groups;             \
-    k_t1_encode<M, ROWS, LN><<<grid, LN, 0, st>>>(F, blk, nblk, cbh, (const M*)planes, (const M*)signs, pb, cw, R, \
-                                                  D, bp, tail, (M*)sppf, order, qctr);                             \
+    const int grid = order ? std::min(groups, resident_groups(k_t1_encode<M, ROWS, LN, BYP>, LN)) : groups;        \
+    k_t1_encode<M, ROWS, LN, BYP><<<grid, LN, 0, st>>>(F, blk, nblk, cbh, (const M*)planes, (const M*)signs, pb,    \
+                                                       cw, R, D, bp, tail, (M*)sppf, order, qctr, rbt);             \
   } while (0)
   if (ln == 1) ENC_L(1);
   else if (ln == 4) ENC_L(4);
@@ -875,7 +956,7 @@ static void launch_encode(int nblk, const FieldDev* F, const Blk* blk, int cbh, 
 #undef ENC_L
 }
 
-template <typename M, int ROWS>
+template <typename M, int ROWS, bool BYP>
 static void launch_decode(int nblk, const FieldDev* F, const Blk* blk, const uint32_t* table, const int64_t* off,
                           hipStream_t st, int* order, int* qctr) {
   constexpr int LM = t1_lanes_max<M, ROWS>();
@@ -884,8 +965,8 @@ static void launch_decode(int nblk, const FieldDev* F, const Blk* blk, const uin
 #define DEC_L(LN)                                                                                                  \
   do {                                                                                                             \
     const int groups = (nblk + LN - 1) / LN;                                                                       \
-    const int grid = order ? std::min(groups, resident_groups(k_t1_decode<M, ROWS, LN>, LN)) : groups;             \
-    k_t1_decode<M, ROWS, LN><<<grid, LN, 0, st>>>(F, blk, nblk, table, off, order, qctr);                          \
+    const int grid = order ? std::min(groups, resident_groups(k_t1_decode<M, ROWS, LN, BYP>, LN)) : groups;        \
+    k_t1_decode<M, ROWS, LN, BYP><<<grid, LN, 0, st>>>(F, blk, nblk, table, off, order, qctr);                     \
   } while (0)
   if (ln == 1) DEC_L(1);
   else if (ln == 4) DEC_L(4);
@@ -938,7 +1019,7 @@ void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, co
                const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail, void* sppf,
                hipStream_t st, const T1Split* sp, int* order, int* qctr, int32_t* rbt) {
   if (nblk <= 0) return;
-  if (rbt || use_wave(nblk, false)) {
+  if (use_wave(nblk, false)) {
     t1_encode_wave(F, blk, nblk, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st, rbt);
     return;
   }
@@ -947,7 +1028,7 @@ void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, co
   if (s > 0) {
     (void)hipEventRecord(sp->ev_fork, st);
     (void)hipStreamWaitEvent(sp->aux, sp->ev_fork, 0);
-    t1_encode_wave(F, blk, s, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, sp->aux);
+    t1_encode_wave(F, blk, s, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, sp->aux, rbt);
     const size_t ms = cbw <= 32 ? 4 : 8;
     blk += s; pb += s; cw += (size_t)s * kCwCap;
     planes = (const char*)planes + (size_t)s * kQBits * cbh * ms;
@@ -955,9 +1036,16 @@ void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, co
     sppf = (char*)sppf + (size_t)s * cbh * ms;
     R += (size_t)s * kPassStride; D += (size_t)s * kPassStride;
     bp += (size_t)s * kPassStride; tail += (size_t)s * kPassStride;
+    if (rbt) rbt += (size_t)s * kPassStride;
     nblk -= s;
   }
-#define ENC(MT, RW) launch_encode<MT, RW>(nblk, F, blk, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st, order, qctr)
+#define ENC(MT, RW)                                                                                        \
+  do {                                                                                                     \
+    if (rbt) launch_encode<MT, RW, true>(nblk, F, blk, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st, \
+                                         order, qctr, rbt);                                                \
+    else launch_encode<MT, RW, false>(nblk, F, blk, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st,    \
+                                      order, qctr, nullptr);                                               \
+  } while (0)
   T1_DISPATCH(cbw, cbh, ENC);
 #undef ENC
   if (s > 0) {
@@ -979,7 +1067,7 @@ void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
 void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint32_t* table,
                const int64_t* off, hipStream_t st, const T1Split* sp, int* order, int* qctr, bool byp) {
   if (nblk <= 0) return;
-  if (byp || use_wave(nblk, true)) {
+  if (use_wave(nblk, true)) {
     t1_decode_wave(F, blk, nblk, cbw, table, off, st, byp);
     return;
   }
@@ -988,10 +1076,14 @@ void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, co
   if (s > 0) {
     (void)hipEventRecord(sp->ev_fork, st);
     (void)hipStreamWaitEvent(sp->aux, sp->ev_fork, 0);
-    t1_decode_wave(F, blk, s, cbw, table, off, sp->aux);
+    t1_decode_wave(F, blk, s, cbw, table, off, sp->aux, byp);
     blk += s; table += s; off += s; nblk -= s;
   }
-#define DEC(MT, RW) launch_decode<MT, RW>(nblk, F, blk, table, off, st, order, qctr)
+#define DEC(MT, RW)                                                               \
+  do {                                                                            \
+    if (byp) launch_decode<MT, RW, true>(nblk, F, blk, table, off, st, order, qctr);  \
+    else launch_decode<MT, RW, false>(nblk, F, blk, table, off, st, order, qctr);     \
+  } while (0)
   T1_DISPATCH(cbw, cbh, DEC);
 #undef DEC
   if (s > 0) {

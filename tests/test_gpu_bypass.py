@@ -124,6 +124,30 @@ def test_bypass_batch_and_mixed_decode(gpu, ref):
         assert np.array_equal(_host(ys[i]).view(np.uint32), y_ref.view(np.uint32)), f"stream {i}"
 
 
+@pytest.mark.parametrize("lanes,persist", [(1, 0), (4, 1), (16, 1), (16, 0), (64, 1)])
+def test_bypass_lanes_per_block_coders(gpu, ref, lanes, persist):
+    """The lanes-per-block coders (the batch path's, forced here) with the
+    bypass: every stream the oracle's, every decode bit-identical; without
+    persistent launches a share of the blocks goes to the wavefront coders on
+    a second stream."""
+    xs = [synth.field(v, *sh, cfg=12, level=k) for k, (v, sh) in
+          enumerate([("u", (181, 360)), ("t", (91, 180)), ("v", (129, 255)), ("q", (64, 96))])]
+    eps = [0.001, 0.0005, 0.002, 0.001]
+    old = gpu.set_tuning(t1_encoder=2, t1_decoder=2, t1_lanes=lanes, t1_persist=persist)
+    try:
+        print(f"bypass lanes {lanes} persist {persist}", flush=True)
+        streams = gpu.compress_batch([_dev(x) for x in xs], err_bounds=eps, base_ratio=5.0, bypass=1)
+        refs = [ref.compress(x, e, base_ratio=5.0, bypass=1) for x, e in zip(xs, eps)]
+        for i, s_ref in enumerate(refs):
+            _same(_host(streams[i]).tobytes(), s_ref, f"field {i}")
+        assert sum(_raw_blocks(ref, s, x.shape) for s, x in zip(refs, xs)) > 0
+        ys = gpu.decompress_batch([_dev(np.frombuffer(s, np.uint8).copy()) for s in refs], [x.shape for x in xs])
+        for i, (s, x) in enumerate(zip(refs, xs)):
+            assert np.array_equal(_host(ys[i]).view(np.uint32), ref.decompress(s, *x.shape).view(np.uint32)), i
+    finally:
+        gpu.set_tuning(**old)
+
+
 @pytest.mark.parametrize("var,eps,r", [("u", 0.01, 30.0), ("v", 0.001, 6.0), ("q", 0.0005, 4.0)])
 def test_bypass_full_size_fields(gpu, ref, var, eps, r):
     """721x1440 fields: the bypass stream is the oracle's."""
