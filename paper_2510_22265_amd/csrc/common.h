@@ -212,8 +212,13 @@ void t1_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, co
                const int64_t* off, hipStream_t st, const T1Split* sp = nullptr, int* order = nullptr,
                int* qctr = nullptr, bool byp = false);
 void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
-                    const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
+                    const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int32_t* bp,
                     uint32_t* tail, void* sppf, hipStream_t st, int32_t* rbt = nullptr);
+// Running distortion reductions D[b][0 .. 3P_b - 2] of every block's coding
+// passes (closed form from the magnitudes and the encoder's sppf masks);
+// t1_encode runs it after the coders.
+void t1_distortion(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,
+                   const void* sppf, int64_t* D, hipStream_t st);
 void t1_decode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, const uint32_t* table,
                     const int64_t* off, hipStream_t st, bool byp = false);
 // Kernel choices (process-wide, set through the C ABI; the environment

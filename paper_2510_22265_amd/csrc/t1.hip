@@ -218,21 +218,17 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
                                              const Blk* __restrict__ blk, int nblk, int cbh,
                                              const M* __restrict__ planes, const M* __restrict__ signs,
                                              const uint8_t* __restrict__ pbv, uint8_t* __restrict__ cw,
-                                             int32_t* __restrict__ Rt, int64_t* __restrict__ Dt,
-                                             int32_t* __restrict__ bpt, uint32_t* __restrict__ tailt,
+                                             int32_t* __restrict__ Rt, int32_t* __restrict__ bpt, uint32_t* __restrict__ tailt,
                                              M* __restrict__ sppf, int32_t* __restrict__ rbt) {
   if (b >= nblk) return;
   Blk k = blk[b];
   if (!F[k.field].active) return;
   const bool byp = BYP && F[k.field].byp;
-  const float* coef = F[k.field].buf[BUF_COEF];
-  const int nx = F[k.field].nx, e0 = F[k.field].e0;
   int P = pbv[b];
   int32_t* R = Rt + (size_t)b * kPassStride;
-  int64_t* Dd = Dt + (size_t)b * kPassStride;
   int32_t* BPk = bpt + (size_t)b * kPassStride;
   uint32_t* TL = tailt + (size_t)b * kPassStride;
-  R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0;
+  R[0] = 0; BPk[0] = -1; TL[0] = 0;
   int32_t* RB = BYP ? rbt + (size_t)b * kPassStride : nullptr;
   if (byp) RB[0] = 0;
   M* spo = sppf + (size_t)b * cbh;
@@ -267,20 +263,15 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
   const int mq_stop = byp ? kBypMqMax : 65536;
   int lrk = 0, lbp = -1;              // the last MQ-coded pass's termination
   uint32_t ltail = 0;
-  const int sh = k.gain - e0;
-  const float* cb = coef + (size_t)k.y0 * nx + k.x0;
-  auto qat = [&](int y, int x) { return quantq(cb[y * nx + x], sh); };
   auto mq_enc = [&](uint8_t* cs, int bit) { mq_encode(e, cs, bit, S.mqt); };
   int npass = 3 * P - 2, kk = 0;
   bool stop = false;
-  int64_t Dcum = 0;
   const int h = k.h, w = k.w;
   const M wm = (w >= MaskBits<M>::value) ? ~(M)0 : (((M)1 << w) - 1);
   auto rowm = [&](M (*a)[LANES], int y) -> M { return (y >= 0 && y < h) ? a[y][lane] : (M)0; };
   for (int p = P - 1; p >= 0 && !stop; p--) {
     const M* pl = planes + ((size_t)b * kQBits + p) * cbh;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
-      int64_t dd = 0;
       // pass numbers 11 and later of planes p <= P - 5 (SPP, MRP) are raw
       const bool raw = byp && ty < 2 && p <= P - 5;
       // the stripe's rows (and the rows above and below) are held in
@@ -345,7 +336,6 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
                 code_sign(r, x);
                 sB[r] = mid | ((M)1 << x);
                 aB[r] |= (M)1 << x;
-                dd += sig_delta(qat(y0 + r, x), p);
                 grew = true;
               }
             }
@@ -374,7 +364,6 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
                 mq_enc(&S.ctx[cx][lane], btu(gB[r], x));
               }
               fB[r] |= (M)1 << x;
-              dd += ref_delta(qat(y0 + r, x), p);
             }
           }
         } else {                                         // cleanup
@@ -407,7 +396,6 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
                   if (r == rr) {
                     code_sign(r, x);
                     sB[r] |= (M)1 << x;
-                    dd += sig_delta(qat(y0 + r, x), p);
                   }
                 rstart = rr + 1;
               }
@@ -422,7 +410,6 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
               if (bit) {
                 code_sign(r, x);
                 sB[r] |= (M)1 << x;
-                dd += sig_delta(qat(y0 + r, x), p);
               }
             }
           }
@@ -442,7 +429,6 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
         for (int y = 0; y < h; y++) S.vis[y][lane] = 0;
       if (stop) break;
       kk++;
-      Dcum += dd;
       // a raw pass's MQ part is the last MQ-coded pass's codeword
       if (!raw) { lrk = mq_flush_copy(e, &ltail); lbp = e.BP; }
       int rk = lrk;
@@ -453,12 +439,11 @@ __device__ __forceinline__ void t1_enc_block(T1Shared<M, ROWS, LANES, true>& S, 
         RB[kk] = rbits;
       }
       R[kk] = rk;
-      Dd[kk] = Dcum;
       BPk[kk] = lbp;
       TL[kk] = ltail;
     }
   }
-  for (int j = kk + 1; j <= npass; j++) { R[j] = kRInf; Dd[j] = Dcum; BPk[j] = 0; TL[j] = 0; }
+  for (int j = kk + 1; j <= npass; j++) { R[j] = kRInf; BPk[j] = 0; TL[j] = 0; }
   if (byp && rnb && rwi < kRawCap / 4) rawp[rwi] = __builtin_bswap32(racc);   // the last, partial word
   for (int y = 0; y < k.h; y++) spo[y] = S.aux[y][lane];
 }
@@ -474,7 +459,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
                                                      int nblk, int cbh, const M* __restrict__ planes,
                                                      const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
                                                      uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
-                                                     int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
+                                                     int32_t* __restrict__ bpt,
                                                      uint32_t* __restrict__ tailt, M* __restrict__ sppf,
                                                      const int* __restrict__ order, int* __restrict__ qctr,
                                                      int32_t* __restrict__ rbt) {
@@ -484,7 +469,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
   __syncthreads();
   if (!order) {
     t1_enc_block<M, ROWS, LANES, BYP>(S, lane, blockIdx.x * LANES + lane, F, blk, nblk, cbh, planes, signs, pbv, cw,
-                                      Rt, Dt, bpt, tailt, sppf, rbt);
+                                      Rt, bpt, tailt, sppf, rbt);
     return;
   }
   const int ngroups = (nblk + LANES - 1) / LANES;
@@ -495,7 +480,7 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
     if (g >= ngroups) break;
     const int i = g * LANES + lane;
     if (i < nblk)
-      t1_enc_block<M, ROWS, LANES, BYP>(S, lane, order[i], F, blk, nblk, cbh, planes, signs, pbv, cw, Rt, Dt, bpt,
+      t1_enc_block<M, ROWS, LANES, BYP>(S, lane, order[i], F, blk, nblk, cbh, planes, signs, pbv, cw, Rt, bpt,
                                         tailt, sppf, rbt);
   }
 }
@@ -552,6 +537,101 @@ __global__ __launch_bounds__(256) void k_virtual_decode(const FieldDev* __restri
     }
     yhat[idx] = v;
   }
+}
+
+// ------------------------------------------------------------------------
+// Distortion reductions of every coding pass (the ΔD the rate allocation
+// needs), from the magnitudes in closed form: a sample with top bit ps
+// becomes significant at plane ps — in the cleanup pass of the block's top
+// plane (ps = P-1), else in the significance-propagation pass of plane ps if
+// the encoder recorded it there (sppf), in its cleanup pass otherwise — and
+// is refined in the refinement pass of every plane below ps.  Pass numbers
+// (1-based): 1 for the top plane's cleanup; 3(P-2-p)+2, +3, +4 for plane
+// p < P-1's three passes.  One workgroup per block; per plane, each
+// wavefront sums its samples' reductions and adds them to the block's
+// per-pass totals in LDS; the table holds running sums D[k] (D[0] = 0).
+// Integer sums: the same values in any order.
+// ------------------------------------------------------------------------
+template <typename M>
+__global__ __launch_bounds__(256) void k_t1_dist(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                 int nblk, int cbh, const uint8_t* __restrict__ pbv,
+                                                 const M* __restrict__ sppf, int64_t* __restrict__ Dt) {
+  constexpr int kPer = 4096 / 256;   // samples per thread of the largest block
+  __shared__ unsigned long long acc[kPassStride];
+  const int b = blockIdx.x;
+  const Blk k = blk[b];
+  if (!F[k.field].active) return;
+  const int P = pbv[b], npass = P ? 3 * P - 2 : 0;
+  const int t = threadIdx.x, lane = t & 63;
+  for (int i = t; i < kPassStride; i += 256) acc[i] = 0;
+  __syncthreads();
+  if (P > 0) {
+    const float* coef = F[k.field].buf[BUF_COEF];
+    const int nx = F[k.field].nx, sh = k.gain - F[k.field].e0;
+    const int n = k.w * k.h;
+    uint32_t qv[kPer];
+    uint32_t spb = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const int i = t + 256 * j;
+      qv[j] = 0;
+      if (i < n) {
+        const int y = i / k.w, x = i - y * k.w;
+        qv[j] = quantq(coef[(size_t)(k.y0 + y) * nx + k.x0 + x], sh);
+        spb |= (uint32_t)bt(sppf[(size_t)b * cbh + y], x) << j;
+      }
+    }
+    for (int p = P - 1; p >= 0; p--) {
+      int64_t dspp = 0, dcp = 0, dref = 0;
+#pragma unroll
+      for (int j = 0; j < kPer; j++) {
+        const uint32_t q = qv[j];
+        if (!q) continue;
+        const int ps = 31 - __builtin_clz(q);
+        if (ps == p) {
+          const int64_t d = sig_delta(q, p);
+          if (p < P - 1 && ((spb >> j) & 1u)) dspp += d;
+          else dcp += d;
+        } else if (ps > p) {
+          dref += ref_delta(q, p);
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        dspp += __shfl_xor(dspp, o);
+        dcp += __shfl_xor(dcp, o);
+        dref += __shfl_xor(dref, o);
+      }
+      if (lane == 0) {
+        if (p == P - 1) {
+          atomicAdd(&acc[1], (unsigned long long)dcp);
+        } else {
+          const int k0 = 3 * (P - 2 - p) + 2;
+          atomicAdd(&acc[k0], (unsigned long long)dspp);
+          atomicAdd(&acc[k0 + 1], (unsigned long long)dref);
+          atomicAdd(&acc[k0 + 2], (unsigned long long)dcp);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    int64_t* Dd = Dt + (size_t)b * kPassStride;
+    int64_t c = 0;
+    Dd[0] = 0;
+    for (int j = 1; j <= npass; j++) {
+      c += (int64_t)acc[j];
+      Dd[j] = c;
+    }
+  }
+}
+
+void t1_distortion(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,
+                   const void* sppf, int64_t* D, hipStream_t st) {
+  if (nblk <= 0) return;
+  if (cbw <= 32)
+    k_t1_dist<uint32_t><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, pb, (const uint32_t*)sppf, D);
+  else
+    k_t1_dist<uint64_t><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, pb, (const uint64_t*)sppf, D);
 }
 
 // ------------------------------------------------------------------------
@@ -937,7 +1017,7 @@ static int resident_groups(K kernel, int threads) {
 // order/qctr non-null: persistent launch (order filled by k_t1_order first).
 template <typename M, int ROWS, bool BYP>
 static void launch_encode(int nblk, const FieldDev* F, const Blk* blk, int cbh, const void* planes, const void* signs,
-                          const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp, uint32_t* tail,
+                          const uint8_t* pb, uint8_t* cw, int32_t* R, int32_t* bp, uint32_t* tail,
                           void* sppf, hipStream_t st, int* order, int* qctr, int32_t* rbt) {
   constexpr int LM = t1_lanes_max<M, ROWS>();
   int ln = pick_lanes(nblk, LM);
@@ -947,7 +1027,7 @@ static void launch_encode(int nblk, const FieldDev* F, const Blk* blk, int cbh, 
     const int groups = (nblk + LN - 1) / LN;                                                                       \
     const int grid = order ? std::min(groups, resident_groups(k_t1_encode<M, ROWS, LN, BYP>, LN)) : groups;        \
     k_t1_encode<M, ROWS, LN, BYP><<<grid, LN, 0, st>>>(F, blk, nblk, cbh, (const M*)planes, (const M*)signs, pb,    \
-                                                       cw, R, D, bp, tail, (M*)sppf, order, qctr, rbt);             \
+                                                       cw, R, bp, tail, (M*)sppf, order, qctr, rbt);                \
   } while (0)
   if (ln == 1) ENC_L(1);
   else if (ln == 4) ENC_L(4);
@@ -1020,30 +1100,35 @@ void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, co
                hipStream_t st, const T1Split* sp, int* order, int* qctr, int32_t* rbt) {
   if (nblk <= 0) return;
   if (use_wave(nblk, false)) {
-    t1_encode_wave(F, blk, nblk, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st, rbt);
+    t1_encode_wave(F, blk, nblk, cbw, cbh, planes, signs, pb, cw, R, bp, tail, sppf, st, rbt);
+    t1_distortion(F, blk, nblk, cbw, cbh, pb, sppf, D, st);
     return;
   }
   if (!(order && qctr && use_persist())) order = nullptr, qctr = nullptr;
+  const Blk* const blk0 = blk;
+  const uint8_t* const pb0 = pb;
+  void* const sppf0 = sppf;
+  const int nblk0 = nblk;
   const int s = order ? 0 : split_count(nblk, sp);
   if (s > 0) {
     (void)hipEventRecord(sp->ev_fork, st);
     (void)hipStreamWaitEvent(sp->aux, sp->ev_fork, 0);
-    t1_encode_wave(F, blk, s, cbw, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, sp->aux, rbt);
+    t1_encode_wave(F, blk, s, cbw, cbh, planes, signs, pb, cw, R, bp, tail, sppf, sp->aux, rbt);
     const size_t ms = cbw <= 32 ? 4 : 8;
     blk += s; pb += s; cw += (size_t)s * kCwCap;
     planes = (const char*)planes + (size_t)s * kQBits * cbh * ms;
     signs = (const char*)signs + (size_t)s * cbh * ms;
     sppf = (char*)sppf + (size_t)s * cbh * ms;
-    R += (size_t)s * kPassStride; D += (size_t)s * kPassStride;
+    R += (size_t)s * kPassStride;
     bp += (size_t)s * kPassStride; tail += (size_t)s * kPassStride;
     if (rbt) rbt += (size_t)s * kPassStride;
     nblk -= s;
   }
 #define ENC(MT, RW)                                                                                        \
   do {                                                                                                     \
-    if (rbt) launch_encode<MT, RW, true>(nblk, F, blk, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st, \
+    if (rbt) launch_encode<MT, RW, true>(nblk, F, blk, cbh, planes, signs, pb, cw, R, bp, tail, sppf, st,    \
                                          order, qctr, rbt);                                                \
-    else launch_encode<MT, RW, false>(nblk, F, blk, cbh, planes, signs, pb, cw, R, D, bp, tail, sppf, st,    \
+    else launch_encode<MT, RW, false>(nblk, F, blk, cbh, planes, signs, pb, cw, R, bp, tail, sppf, st,       \
                                       order, qctr, nullptr);                                               \
   } while (0)
   T1_DISPATCH(cbw, cbh, ENC);
@@ -1052,6 +1137,7 @@ void t1_encode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, co
     (void)hipEventRecord(sp->ev_join, sp->aux);
     (void)hipStreamWaitEvent(st, sp->ev_join, 0);
   }
+  t1_distortion(F, blk0, nblk0, cbw, cbh, pb0, sppf0, D, st);
 }
 
 void virtual_decode(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,

@@ -11,7 +11,8 @@
 // the stripe starts and written back when it ends.  The 19 context states
 // live in one VGPR (lane = context) and the 47-entry probability table in
 // another (lane = state), both read with readlane.  The per-pass distortion
-// reductions are summed in parallel across rows at the pass end.
+// reductions are not computed here (k_t1_dist derives them from the
+// magnitudes in closed form).
 #include "common.h"
 #include "t1_common.h"
 
@@ -232,21 +233,17 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
                                                        int nblk, int cbh, const M* __restrict__ planes,
                                                        const M* __restrict__ signs, const uint8_t* __restrict__ pbv,
                                                        uint8_t* __restrict__ cw, int32_t* __restrict__ Rt,
-                                                       int64_t* __restrict__ Dt, int32_t* __restrict__ bpt,
+                                                       int32_t* __restrict__ bpt,
                                                        uint32_t* __restrict__ tailt, M* __restrict__ sppf,
                                                        int32_t* __restrict__ rbt) {
-  __shared__ uint32_t qs[64 * 64];   // quantised magnitudes [y][x], pitch 64
   const int lane = threadIdx.x;
   const int b = blockIdx.x;
   const Blk k = blk[b];
   if (!F[k.field].active) return;
   const bool byp = BYP && F[k.field].byp;
-  const float* coef = F[k.field].buf[BUF_COEF];
-  const int nx = F[k.field].nx, e0 = F[k.field].e0;
   const int P = pbv[b];
   const int h = k.h, w = k.w;
   int32_t* R = Rt + (size_t)b * kPassStride;
-  int64_t* Dd = Dt + (size_t)b * kPassStride;
   int32_t* BPk = bpt + (size_t)b * kPassStride;
   uint32_t* TL = tailt + (size_t)b * kPassStride;
   M* spo = sppf + (size_t)b * cbh;
@@ -258,32 +255,26 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
   // register by that branch's condition and read a lane before it was set.
   uint32_t pv = 0;
   {
-    const uint64_t pp[6] = {(uint64_t)R, (uint64_t)Dd, (uint64_t)BPk, (uint64_t)TL,
+    const uint64_t pp[5] = {(uint64_t)R, (uint64_t)BPk, (uint64_t)TL,
                             (uint64_t)(planes + (size_t)b * kQBits * cbh), (uint64_t)RB};
 #pragma unroll
-    for (int i = 0; i < 6; i++) {
+    for (int i = 0; i < 5; i++) {
       if (lane == 2 * i) pv = (uint32_t)pp[i];
       if (lane == 2 * i + 1) pv = (uint32_t)(pp[i] >> 32);
     }
   }
   if (lane == 0) {
-    R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0;
+    R[0] = 0; BPk[0] = -1; TL[0] = 0;
     if (byp) RB[0] = 0;
   }
   if (P == 0) {
     if (lane < h) spo[lane] = 0;
     return;
   }
-  const int sh = k.gain - e0;
-  for (int i = lane; i < w * h; i += 64) {
-    int y = i / w, x = i - y * w;
-    qs[y * 64 + x] = quantq(coef[(size_t)(k.y0 + y) * nx + k.x0 + x], sh);
-  }
-  __syncthreads();
   uint32_t tabv = mq_tab_init(lane);
   uint32_t ctxv = mq_ctx_init(lane);
   const uint32_t zct = zc_table(k.orient, lane), sct = sc_table(lane);
-  M sig = 0, vis = 0, ref = 0, spp = 0, nsig = 0, mag = 0;
+  M sig = 0, vis = 0, ref = 0, spp = 0, mag = 0;
   M neg = lane < h ? signs[(size_t)b * cbh + lane] : (M)0;
   const M wm = wmask_of<M>(w);
   uint8_t* out = cw + (size_t)b * kCwCap;
@@ -296,19 +287,16 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
   const int mq_stop = byp ? kBypMqMax : 65536;
   int npass = 3 * P - 2, kk = 0;
   bool stop = false;
-  int64_t Dcum = 0;
   int lrk = 0, lbp = -1;              // the last MQ-coded pass's termination
   uint32_t ltail = 0;
   auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
 
   for (int p = P - 1; p >= 0 && !stop; p--) {
-    const M* const pl = (const M*)lane_ptr(pv, 4);
+    const M* const pl = (const M*)lane_ptr(pv, 3);
     mag = lane < h ? pl[(size_t)p * cbh + lane] : (M)0;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && !stop; ty++) {
       // pass numbers 11 and later of planes p <= P - 5 (SPP, MRP) are raw
       const bool raw = byp && ty < 2 && p <= P - 5;
-      nsig = 0;
-      M refd = sig & ~vis;          // MRP refines every sample significant before this plane
       const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
       // one instance of the stripe loop per pass type, so that each keeps
       // only the row masks its pass uses live
@@ -452,9 +440,7 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
 #pragma unroll
         for (int r = 0; r < 4; r++)
           if (r < rn && lane == y0 + r) {
-            const M nw = sB[r] & ~sig;
-            nsig |= nw;
-            if (ty == 0) spp |= nw;
+            if (ty == 0) spp |= sB[r] & ~sig;
             sig = sB[r]; vis = vB[r];
             if (ty == 1) ref = fB[r];
           }
@@ -466,19 +452,8 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
       else if (ty == 1) stripes(std::integral_constant<int, 1>{});
       else stripes(std::integral_constant<int, 2>{});
       if (stop) break;
-      // distortion reduction of this pass, summed over rows in parallel
-      M chg = (ty == 1) ? refd : nsig;
-      int64_t dd = 0;
-      while (chg) {
-        int x = ctzm(chg);
-        chg &= chg - 1;
-        uint32_t q = qs[lane * 64 + x];
-        dd += (ty == 1) ? ref_delta(q, p) : sig_delta(q, p);
-      }
-      for (int o = 32; o > 0; o >>= 1) dd += __shfl_xor(dd, o);
       if (ty == 2) vis = 0;
       kk++;
-      Dcum += dd;
       // a raw pass's MQ part is the last MQ-coded pass's codeword
       if (!raw) { lrk = mqw_flush_copy(e, &ltail); lbp = e.BP; }
       int rk = lrk, rbits = 0;
@@ -489,18 +464,17 @@ __global__ __launch_bounds__(64) void k_t1_encode_wave(const FieldDev* __restric
         if (lrk > kBypMqMax || rby > kBypRawMax) rk = kRInf;
       }
       int32_t* const Rp = (int32_t*)lane_ptr(pv, 0);
-      int64_t* const Dp = (int64_t*)lane_ptr(pv, 1);
-      int32_t* const Bp = (int32_t*)lane_ptr(pv, 2);
-      uint32_t* const Tp = (uint32_t*)lane_ptr(pv, 3);
-      int32_t* const RBp = BYP ? (int32_t*)lane_ptr(pv, 5) : nullptr;
+      int32_t* const Bp = (int32_t*)lane_ptr(pv, 1);
+      uint32_t* const Tp = (uint32_t*)lane_ptr(pv, 2);
+      int32_t* const RBp = BYP ? (int32_t*)lane_ptr(pv, 4) : nullptr;
       if (lane == 0) {
-        Rp[kk] = rk; Dp[kk] = Dcum; Bp[kk] = lbp; Tp[kk] = ltail;
+        Rp[kk] = rk; Bp[kk] = lbp; Tp[kk] = ltail;
         if (byp) RBp[kk] = rbits;
       }
     }
   }
   if (lane == 0)
-    for (int j = kk + 1; j <= npass; j++) { R[j] = kRInf; Dd[j] = Dcum; BPk[j] = 0; TL[j] = 0; }
+    for (int j = kk + 1; j <= npass; j++) { R[j] = kRInf; BPk[j] = 0; TL[j] = 0; }
   // the raw area's last, partial word
   if (byp && lane == 0 && rw.n && rw.W < kRawCap / 4) reinterpret_cast<uint32_t*>(rawp)[rw.W] = __builtin_bswap32(rw.acc);
   if (lane < h) spo[lane] = spp;
@@ -526,13 +500,11 @@ template <int NM, bool BYP>
 __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
     const FieldDev* __restrict__ F, const Blk* __restrict__ blk, int nblk, int cbh, const uint32_t* __restrict__ planes,
     const uint32_t* __restrict__ signs, const uint8_t* __restrict__ pbv, uint8_t* __restrict__ cw,
-    int32_t* __restrict__ Rt, int64_t* __restrict__ Dt, int32_t* __restrict__ bpt, uint32_t* __restrict__ tailt,
+    int32_t* __restrict__ Rt, int32_t* __restrict__ bpt, uint32_t* __restrict__ tailt,
     uint32_t* __restrict__ sppf, int32_t* __restrict__ rbt) {
   using M = uint32_t;
-  __shared__ uint32_t qs[32 * 32];             // quantised magnitudes [y][x], pitch 32
   __shared__ __align__(16) uint8_t sym[2][NM][kPipeSym];
   __shared__ int scnt[2][NM][3];
-  __shared__ int64_t sdd[2][NM][3];
   __shared__ uint32_t sppm[32];
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
@@ -540,28 +512,21 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
   const Blk k = blk[b];
   if (!F[k.field].active) return;
   const bool byp = BYP && F[k.field].byp;
-  const float* coef = F[k.field].buf[BUF_COEF];
-  const int nx = F[k.field].nx, e0 = F[k.field].e0;
   const int P = pbv[b];
   const int h = k.h, w = k.w;
   int32_t* R = Rt + (size_t)b * kPassStride;
-  int64_t* Dd = Dt + (size_t)b * kPassStride;
   int32_t* BPk = bpt + (size_t)b * kPassStride;
   uint32_t* TL = tailt + (size_t)b * kPassStride;
   int32_t* RB = BYP ? rbt + (size_t)b * kPassStride : nullptr;
   uint32_t* spo = sppf + (size_t)b * cbh;
+  const uint32_t* const pl = planes + (size_t)b * kQBits * cbh;   // [plane][row] magnitude-bit masks
   if (wv == 0 && lane == 0) {
-    R[0] = 0; Dd[0] = 0; BPk[0] = -1; TL[0] = 0;
+    R[0] = 0; BPk[0] = -1; TL[0] = 0;
     if (byp) RB[0] = 0;
   }
   if (P == 0) {
     if (wv == 0 && lane < h) spo[lane] = 0;
     return;
-  }
-  const int sh = k.gain - e0;
-  for (int i = threadIdx.x; i < w * h; i += 64 * (NM + 1)) {
-    const int y = i / w, x = i - y * w;
-    qs[y * 32 + x] = quantq(coef[(size_t)(k.y0 + y) * nx + k.x0 + x], sh);
   }
   if (threadIdx.x < 32) sppm[threadIdx.x] = 0;
   __syncthreads();
@@ -572,15 +537,15 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
   auto rowv = [&](M v, int y) -> M { return (y >= 0 && y < h) ? rdl<M>(v, y) : (M)0; };
 
   // ---- one plane's context modelling (a modelling wavefront) ----
-  auto model_plane = [&](const int p, uint8_t* buf, int* cnt, int64_t* ddo) {
-    M sig = 0, ref = 0, mag = 0, vis = 0, spp = 0, nsig = 0;
-    if (lane < h)
-      for (int x = 0; x < w; x++) {
-        const uint32_t q = qs[lane * 32 + x];
-        sig |= (M)((q >> (p + 1)) != 0u) << x;
-        ref |= (M)((q >> (p + 2)) != 0u) << x;
-        mag |= (M)((q >> p) & 1u) << x;
-      }
+  auto model_plane = [&](const int p, uint8_t* buf, int* cnt) {
+    // the row's state at the plane's start from the magnitude-bit masks:
+    // significant iff a bit above p is set, refined iff one above p + 1 is
+    M sig = 0, ref = 0, mag = 0, vis = 0, spp = 0;
+    if (lane < h) {
+      for (int pp = P - 1; pp >= p + 2; pp--) ref |= pl[(size_t)pp * cbh + lane];
+      sig = ref | (p + 1 < P ? pl[(size_t)(p + 1) * cbh + lane] : (M)0);
+      mag = pl[(size_t)p * cbh + lane];
+    }
     const M neg = lane < h ? signs[(size_t)b * cbh + lane] : (M)0;
     int n = 0;
     auto emit = [&](int cx, int d) {
@@ -591,8 +556,6 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
       n = (n + 3) & ~3;                  // every pass starts on a 4-byte boundary
       const int n0 = n;
       const bool raw = byp && ty < 2 && p <= P - 5;   // passes 11 and later, SPP and MRP
-      nsig = 0;
-      M refd = sig & ~vis;
       const M nbm8 = (ty == 1) ? neighbour_mask<M>(sig, lane) : (M)0;
         auto stripes = [&](auto tyc) {
         constexpr int ty = decltype(tyc)::value;
@@ -729,9 +692,7 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
   #pragma unroll
           for (int r = 0; r < 4; r++)
             if (r < rn && lane == y0 + r) {
-              const M nw = sB[r] & ~sig;
-              nsig |= nw;
-              if (ty == 0) spp |= nw;
+              if (ty == 0) spp |= sB[r] & ~sig;
               sig = sB[r]; vis = vB[r];
               if (ty == 1) ref = fB[r];
             }
@@ -740,17 +701,8 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
       if (ty == 0) stripes(std::integral_constant<int, 0>{});
       else if (ty == 1) stripes(std::integral_constant<int, 1>{});
       else stripes(std::integral_constant<int, 2>{});
-      M chg = (ty == 1) ? refd : nsig;
-      int64_t dd = 0;
-      while (chg) {
-        const int x = ctzm(chg);
-        chg &= chg - 1;
-        const uint32_t q = qs[lane * 32 + x];
-        dd += (ty == 1) ? ref_delta(q, p) : sig_delta(q, p);
-      }
-      for (int o = 32; o > 0; o >>= 1) dd += __shfl_xor(dd, o);
       if (ty == 2) vis = 0;
-      if (lane == 0) { cnt[ty] = n - n0; ddo[ty] = dd; }
+      if (lane == 0) cnt[ty] = n - n0;
     }
     if (lane < h && spp) atomicOr(&sppm[lane], spp);
   };
@@ -763,7 +715,6 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
   const int mq_stop = byp ? kBypMqMax : 65536;   // lengths past these are never kept
   int kk = 0;
   bool stop = false;
-  int64_t Dcum = 0;
   int lrk = 0, lbp = -1;             // the last MQ-coded pass's termination
   uint32_t ltail = 0;
   int rbits = 0;                     // raw bits so far; racc: the pending partial word
@@ -833,7 +784,6 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
             stop = true;                 // every later pass exceeds a length limit
           } else {
             kk++;
-            Dcum += sdd[s][j][ty];
             // a raw pass's MQ part is the last MQ-coded pass's codeword
             if (!raw) { lrk = mqw_flush_copy(e, &ltail); lbp = e.BP; }
             int rk = lrk;
@@ -843,7 +793,7 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
               if (lrk > kBypMqMax || rby > kBypRawMax) rk = kRInf;
             }
             if (lane == 0) {
-              R[kk] = rk; Dd[kk] = Dcum; BPk[kk] = lbp; TL[kk] = ltail;
+              R[kk] = rk; BPk[kk] = lbp; TL[kk] = ltail;
               if (byp) RB[kk] = rbits;
             }
           }
@@ -858,14 +808,14 @@ __global__ __launch_bounds__(64 * (NM + 1)) void k_t1_encode_pipe(
     if (wv >= 1 && r < G) {
       const int j = wv - 1;
       const int p = P - 1 - r * NM - j;
-      if (p >= 0) model_plane(p, sym[r & 1][j], scnt[r & 1][j], sdd[r & 1][j]);
+      if (p >= 0) model_plane(p, sym[r & 1][j], scnt[r & 1][j]);
     }
     if (wv == 0 && r >= 1) code_group((r - 1) & 1, r - 1);
     __syncthreads();
   }
   if (wv == 0) {
     if (lane == 0)
-      for (int jj = kk + 1; jj <= 3 * P - 2; jj++) { R[jj] = kRInf; Dd[jj] = Dcum; BPk[jj] = 0; TL[jj] = 0; }
+      for (int jj = kk + 1; jj <= 3 * P - 2; jj++) { R[jj] = kRInf; BPk[jj] = 0; TL[jj] = 0; }
     // the raw area's last, partial word
     if (byp && lane == 0 && (rbits & 31) && (rbits >> 5) < kRawCap / 4)
       reinterpret_cast<uint32_t*>(rawp)[rbits >> 5] = __builtin_bswap32(racc);
@@ -1285,7 +1235,7 @@ __global__ __launch_bounds__(64) void k_t1_decode_wave(const FieldDev* __restric
 #undef NR
 
 void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const void* planes,
-                    const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int64_t* D, int32_t* bp,
+                    const void* signs, const uint8_t* pb, uint8_t* cw, int32_t* R, int32_t* bp,
                     uint32_t* tail, void* sppf, hipStream_t st, int32_t* rbt) {
   if (nblk <= 0) return;
   const char* pe = getenv("EBCC_T1_PIPE");
@@ -1297,15 +1247,15 @@ void t1_encode_wave(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cb
   do {                                                                                                             \
     if (cbw <= 32 && cbh <= 32 && pipe)                                                                            \
       k_t1_encode_pipe<3, BYP><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes,                    \
-                                                    (const uint32_t*)signs, pb, cw, R, D, bp, tail,                 \
+                                                    (const uint32_t*)signs, pb, cw, R, bp, tail,                    \
                                                     (uint32_t*)sppf, rbt);                                          \
     else if (cbw <= 32)                                                                                            \
       k_t1_encode_wave<uint32_t, BYP><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint32_t*)planes,              \
-                                                          (const uint32_t*)signs, pb, cw, R, D, bp, tail,           \
+                                                          (const uint32_t*)signs, pb, cw, R, bp, tail,              \
                                                           (uint32_t*)sppf, rbt);                                    \
     else                                                                                                           \
       k_t1_encode_wave<uint64_t, BYP><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, (const uint64_t*)planes,              \
-                                                          (const uint64_t*)signs, pb, cw, R, D, bp, tail,           \
+                                                          (const uint64_t*)signs, pb, cw, R, bp, tail,              \
                                                           (uint64_t*)sppf, rbt);                                    \
   } while (0)
   if (rbt) ENC_W(true);
