@@ -290,3 +290,56 @@ def test_t1_bypass_raw_refinement_bits(ref, seed):
                 if q[y, x] >> (p + 1):
                     want.append((int(q[y, x]) >> p) & 1)
     assert got.tolist() == want
+
+
+def _sig_delta(q, p):
+    e0 = 2 * q + 1
+    m = (q >> p) << p
+    e1 = e0 - (2 * m + (1 << p))
+    return e0 * e0 - e1 * e1
+
+
+def _ref_delta(q, p):
+    e = 2 * q + 1
+    a = e - (2 * ((q >> (p + 1)) << (p + 1)) + (1 << (p + 1)))
+    b = e - (2 * ((q >> p) << p) + (1 << p))
+    return a * a - b * b
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_t1_distortion_closed_form(ref, seed):
+    """The per-pass distortion reductions in closed form (what the GPU's
+    distortion kernel computes after the coders): a sample with top bit ps
+    becomes significant in pass 1 when ps = P - 1, else in the
+    significance-propagation (pass 3(P-2-ps)+2) or cleanup (+4) pass of
+    plane ps, and is refined in pass 3(P-2-p)+3 of every plane p < ps; D_k
+    is the sum of those reductions up to pass k.  The significance pass of
+    every sample is read from the oracle's decoder (first k at which it
+    decodes significant), and the sums equal the oracle encoder's D."""
+    rng = np.random.default_rng(300 + seed)
+    h, w = [(32, 32), (4, 4), (3, 17), (16, 16), (13, 9), (8, 32)][seed % 6]
+    q, neg = _block(rng, h, w)
+    cw, R, D = ref.t1_encode(q, neg, seed % 4)
+    P = int(q.max()).bit_length()
+    n = len(R) - 1
+    if P == 0:
+        return
+    sigk = np.zeros((h, w), np.int64)
+    for k in range(n, 0, -1):                 # first pass after which a sample is significant
+        mk, _, _ = ref.t1_decode(cw, h, w, seed % 4, P, k)
+        sigk[mk > 0] = k
+    dk = np.zeros(n + 1, np.int64)
+    for (y, x), qv in np.ndenumerate(q):
+        qv = int(qv)
+        if not qv:
+            continue
+        ps = qv.bit_length() - 1
+        k = int(sigk[y, x])
+        if ps == P - 1:
+            assert k == 1
+        else:
+            assert k in (3 * (P - 2 - ps) + 2, 3 * (P - 2 - ps) + 4)
+        dk[k] += _sig_delta(qv, ps)
+        for p in range(ps):
+            dk[3 * (P - 2 - p) + 3] += _ref_delta(qv, p)
+    assert (np.cumsum(dk) == D).all()
