@@ -130,25 +130,35 @@ __host__ __device__ __forceinline__ void cut_tile_mode(int kind, int J, int tl, 
 }
 
 // Order of n work items by a key in [0, kQBits] (0 first), stable within a
-// key, for the persistent and longest-first launches.  One workgroup of 256
-// threads: per-thread counts over a contiguous share of the items, a scan
+// key, for the persistent and longest-first launches.  One workgroup of
+// kOrderThreads threads: per-thread counts over a contiguous share of the
+// items (keys read eight at a time, their loads issued together), a scan
 // over (key, thread), a scatter.  order[i] receives map[item] (the item
 // itself when map is null); *qctr, when given, is zeroed (a work counter).
+constexpr int kOrderThreads = 1024;
 template <typename KeyF>
 __device__ __forceinline__ void order_by_key(int n, KeyF key, const int* __restrict__ map, int* __restrict__ order,
                                              int* __restrict__ qctr) {
-  __shared__ int cnt[kQBits + 1][256];
+  constexpr int T = kOrderThreads;
+  __shared__ int cnt[kQBits + 1][T];
   __shared__ int base[kQBits + 1];
   const int t = threadIdx.x;
-  const int per = (n + 255) / 256;
+  const int per = (n + T - 1) / T;
   const int b0 = t * per < n ? t * per : n;
   const int b1 = b0 + per < n ? b0 + per : n;
   for (int k = 0; k <= kQBits; k++) cnt[k][t] = 0;
-  for (int b = b0; b < b1; b++) cnt[key(b)][t]++;
+  for (int b = b0; b < b1; b += 8) {
+    int kk[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) kk[u] = b + u < b1 ? key(b + u) : -1;
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+      if (kk[u] >= 0) cnt[kk[u]][t]++;
+  }
   __syncthreads();
   if (t <= kQBits) {   // exclusive scan of row t
     int sum = 0;
-    for (int u = 0; u < 256; u++) { const int v = cnt[t][u]; cnt[t][u] = sum; sum += v; }
+    for (int u = 0; u < T; u++) { const int v = cnt[t][u]; cnt[t][u] = sum; sum += v; }
     base[t] = sum;
   }
   __syncthreads();
@@ -158,10 +168,16 @@ __device__ __forceinline__ void order_by_key(int n, KeyF key, const int* __restr
     if (qctr) *qctr = 0;
   }
   __syncthreads();
-  for (int b = b0; b < b1; b++) {
-    const int k = key(b);
-    order[base[k] + cnt[k][t]] = map ? map[b] : b;
-    cnt[k][t]++;
+  for (int b = b0; b < b1; b += 8) {
+    int kk[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) kk[u] = b + u < b1 ? key(b + u) : -1;
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+      if (kk[u] >= 0) {
+        order[base[kk[u]] + cnt[kk[u]][t]] = map ? map[b + u] : b + u;
+        cnt[kk[u]][t]++;
+      }
   }
 }
 

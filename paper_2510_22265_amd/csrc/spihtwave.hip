@@ -852,7 +852,7 @@ __global__ __launch_bounds__(256) void k_spiht_cut_tiles(const FieldDev* __restr
 }
 
 // key: bit length of the payload's byte length, longest first
-__global__ __launch_bounds__(256) void k_tile_order(const int* __restrict__ tix, int n, const uint32_t* __restrict__ tent,
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const int* __restrict__ tix, int n, const uint32_t* __restrict__ tent,
                                                     int* __restrict__ out) {
   order_by_key(n, [&](int i) {
     const int bl = blen(tent[tix[i]] & 0x3FFFFFFu);
@@ -862,7 +862,7 @@ __global__ __launch_bounds__(256) void k_tile_order(const int* __restrict__ tix,
 
 void spiht_tiles_longest_first(const int* tix, int n, const uint32_t* tent, int* out, hipStream_t st) {
   if (n <= 0) return;
-  k_tile_order<<<1, 256, 0, st>>>(tix, n, tent, out);
+  k_tile_order<<<1, kOrderThreads, 0, st>>>(tix, n, tent, out);
 }
 
 void spiht_cut_recon(const FieldDev* Fc, int ncand, int max_tiles, const TileD* tiles, const uint32_t* tcut,

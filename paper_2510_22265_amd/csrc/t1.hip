@@ -486,13 +486,13 @@ __global__ __launch_bounds__(LANES) void k_t1_encode(const FieldDev* __restrict_
 }
 
 // Block orders of the persistent launches (order_by_key, common.h).
-__global__ __launch_bounds__(256) void k_t1_order(const uint8_t* __restrict__ pb, int nblk, int* __restrict__ order,
+__global__ __launch_bounds__(kOrderThreads) void k_t1_order(const uint8_t* __restrict__ pb, int nblk, int* __restrict__ order,
                                                   int* __restrict__ qctr) {
   order_by_key(nblk, [&](int b) { const int P = pb[b]; return kQBits - (P < kQBits ? P : kQBits); }, nullptr, order,
                qctr);
 }
 // decoding: by the planes its kept passes reach, k_b / 3 (k_b <= 3 * 23 - 2)
-__global__ __launch_bounds__(256) void k_t1_order_dec(const uint32_t* __restrict__ table, int nblk,
+__global__ __launch_bounds__(kOrderThreads) void k_t1_order_dec(const uint32_t* __restrict__ table, int nblk,
                                                       int* __restrict__ order, int* __restrict__ qctr) {
   order_by_key(nblk, [&](int b) {
     const int kp = (int)((table[b] >> 8) & 0xFFu) / 3;
@@ -547,23 +547,24 @@ __global__ __launch_bounds__(256) void k_virtual_decode(const FieldDev* __restri
 // the encoder recorded it there (sppf), in its cleanup pass otherwise — and
 // is refined in the refinement pass of every plane below ps.  Pass numbers
 // (1-based): 1 for the top plane's cleanup; 3(P-2-p)+2, +3, +4 for plane
-// p < P-1's three passes.  One workgroup per block; per plane, each
-// wavefront sums its samples' reductions and adds them to the block's
-// per-pass totals in LDS; the table holds running sums D[k] (D[0] = 0).
-// Integer sums: the same values in any order.
+// p < P-1's three passes.  One workgroup per block (one or four
+// wavefronts); per plane, each wavefront sums its samples' reductions and
+// adds them to the block's per-pass totals in LDS; the table holds running
+// sums D[k] (D[0] = 0).  Integer sums: the same values in any order.
 // ------------------------------------------------------------------------
-template <typename M>
-__global__ __launch_bounds__(256) void k_t1_dist(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
-                                                 int nblk, int cbh, const uint8_t* __restrict__ pbv,
-                                                 const M* __restrict__ sppf, int64_t* __restrict__ Dt) {
-  constexpr int kPer = 4096 / 256;   // samples per thread of the largest block
+template <typename M, int TH>
+__global__ __launch_bounds__(TH) void k_t1_dist(const FieldDev* __restrict__ F, const Blk* __restrict__ blk,
+                                                int nblk, int cbh, const uint8_t* __restrict__ pbv,
+                                                const M* __restrict__ sppf, int64_t* __restrict__ Dt) {
+  // samples per thread of the largest block (64 rows of 32 or 64 columns)
+  constexpr int kPer = 64 * 8 * (int)sizeof(M) / TH;
   __shared__ unsigned long long acc[kPassStride];
   const int b = blockIdx.x;
   const Blk k = blk[b];
   if (!F[k.field].active) return;
   const int P = pbv[b], npass = P ? 3 * P - 2 : 0;
   const int t = threadIdx.x, lane = t & 63;
-  for (int i = t; i < kPassStride; i += 256) acc[i] = 0;
+  for (int i = t; i < kPassStride; i += TH) acc[i] = 0;
   __syncthreads();
   if (P > 0) {
     const float* coef = F[k.field].buf[BUF_COEF];
@@ -571,9 +572,10 @@ __global__ __launch_bounds__(256) void k_t1_dist(const FieldDev* __restrict__ F,
     const int n = k.w * k.h;
     uint32_t qv[kPer];
     uint32_t spb = 0;
+    static_assert(kPer <= 32, "one sppf bit per sample of the thread");
 #pragma unroll
     for (int j = 0; j < kPer; j++) {
-      const int i = t + 256 * j;
+      const int i = t + TH * j;
       qv[j] = 0;
       if (i < n) {
         const int y = i / k.w, x = i - y * k.w;
@@ -628,10 +630,14 @@ __global__ __launch_bounds__(256) void k_t1_dist(const FieldDev* __restrict__ F,
 void t1_distortion(const FieldDev* F, const Blk* blk, int nblk, int cbw, int cbh, const uint8_t* pb,
                    const void* sppf, int64_t* D, hipStream_t st) {
   if (nblk <= 0) return;
-  if (cbw <= 32)
-    k_t1_dist<uint32_t><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, pb, (const uint32_t*)sppf, D);
+  // few blocks (one field): four wavefronts per block shorten the launch;
+  // many: one wavefront per block does the least work
+  if (cbw > 32)
+    k_t1_dist<uint64_t, 256><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, pb, (const uint64_t*)sppf, D);
+  else if (nblk <= 8192)
+    k_t1_dist<uint32_t, 256><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, pb, (const uint32_t*)sppf, D);
   else
-    k_t1_dist<uint64_t><<<nblk, 256, 0, st>>>(F, blk, nblk, cbh, pb, (const uint64_t*)sppf, D);
+    k_t1_dist<uint32_t, 64><<<nblk, 64, 0, st>>>(F, blk, nblk, cbh, pb, (const uint32_t*)sppf, D);
 }
 
 // ------------------------------------------------------------------------
@@ -1021,7 +1027,7 @@ static void launch_encode(int nblk, const FieldDev* F, const Blk* blk, int cbh, 
                           void* sppf, hipStream_t st, int* order, int* qctr, int32_t* rbt) {
   constexpr int LM = t1_lanes_max<M, ROWS>();
   int ln = pick_lanes(nblk, LM);
-  if (order) k_t1_order<<<1, 256, 0, st>>>(pb, nblk, order, qctr);
+  if (order) k_t1_order<<<1, kOrderThreads, 0, st>>>(pb, nblk, order, qctr);
 #define ENC_L(LN)                                                                                                  \
   do {                                                                                                             \
     const int groups = (nblk + LN - 1) / LN;                                                                       \
@@ -1041,7 +1047,7 @@ static void launch_decode(int nblk, const FieldDev* F, const Blk* blk, const uin
                           hipStream_t st, int* order, int* qctr) {
   constexpr int LM = t1_lanes_max<M, ROWS>();
   int ln = pick_lanes(nblk, LM);
-  if (order) k_t1_order_dec<<<1, 256, 0, st>>>(table, nblk, order, qctr);
+  if (order) k_t1_order_dec<<<1, kOrderThreads, 0, st>>>(table, nblk, order, qctr);
 #define DEC_L(LN)                                                                                                  \
   do {                                                                                                             \
     const int groups = (nblk + LN - 1) / LN;                                                                       \

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 KQBITS = 23
-THREADS = 256
+THREADS = 1024
 
 
 def model_order(pb):
