@@ -16,6 +16,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -1140,6 +1141,11 @@ struct GraphKey {
 constexpr size_t kMaxGraphs = 512;
 static std::mutex g_graph_mu;
 static std::map<std::string, hipGraphExec_t> g_graphs;
+// Keys met once: a sequence is recorded the second time its key comes up,
+// so one-off shapes (a serving loop's ever-changing batches) pay no
+// recording.  Forgotten when full.
+constexpr size_t kMaxSeen = 4096;
+static std::set<std::string> g_graph_seen;
 
 static bool graphs_usable(const Call& c, const Prof& prof) {
   const char* e = getenv("EBCC_GRAPHS");
@@ -1147,16 +1153,26 @@ static bool graphs_usable(const Call& c, const Prof& prof) {
   return !prof.on && c.ws && !c.ws->fixed && c.ws->capst && c.ws->aux;
 }
 
-// Runs seq(stream): from the graph cached under key, recording it first if
-// there is none (when the cache is full the launches are issued directly).
+// Runs seq(stream): from the graph cached under key; the first time a key
+// comes up the launches are issued directly, the second time the sequence is
+// recorded (when the cache is full the launches are always issued directly).
 template <typename Seq>
 static int run_graph(const GraphKey& key, Call& c, Seq& seq) {
   hipGraphExec_t ex = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key.b);
-    if (it != g_graphs.end()) ex = it->second;
-    else if (g_graphs.size() >= kMaxGraphs) return seq(c.st);
+    if (it != g_graphs.end()) {
+      ex = it->second;
+    } else if (g_graphs.size() >= kMaxGraphs) {
+      return seq(c.st);
+    } else if (!g_graph_seen.count(key.b)) {
+      if (g_graph_seen.size() >= kMaxSeen) g_graph_seen.clear();
+      g_graph_seen.insert(key.b);
+      return seq(c.st);
+    } else {
+      g_graph_seen.erase(key.b);
+    }
   }
   if (!ex) {
     hipStream_t cs = c.ws->capst;
@@ -1184,6 +1200,7 @@ static void graphs_clear() {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
   g_graphs.clear();
+  g_graph_seen.clear();
 }
 
 // Lay out (base == nullptr: measure) the workspace of a call; every coded

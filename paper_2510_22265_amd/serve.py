@@ -163,23 +163,37 @@ class Server:
             self._ready.append(r)
 
     def _take_locked(self):
+        # FIFO candidates up to the batch limits; with the library's sizing
+        # of a batch (batch_workspace), the longest prefix that fits the
+        # lane's workspace is kept (a batch shares its search candidates'
+        # planes, so it needs less than its requests alone), found by
+        # bisection, and the rest go back to the front of the queue; without
+        # it, the requests' own workspaces must fit together.
+        fit = getattr(self.executor, "batch_workspace", None)
         batch, samples, ws = [], 0, 0
         while self._ready and len(batch) < self.max_batch:
             r = self._ready[0]
-            if batch and (samples + r.samples > self.max_samples or ws + r.ws > self.lane_ws):
+            if batch and (samples + r.samples > self.max_samples or (fit is None and ws + r.ws > self.lane_ws)):
                 break
             batch.append(self._ready.popleft())
             samples += r.samples
             ws += r.ws
-        # the summed workspaces bound the batch's; the library's own sizing of
-        # the batch decides (requests that do not fit go back to the front)
-        fit = getattr(self.executor, "batch_workspace", None)
-        while fit is not None and len(batch) > 1:
-            comp = [r for r in batch if r.kind == COMPRESS]
-            dec = [r for r in batch if r.kind == DECOMPRESS]
-            if fit(comp, dec) <= self.lane_ws:
-                break
-            self._ready.appendleft(batch.pop())
+        if fit is not None and len(batch) > 1:
+            def fits(m):
+                part = batch[:m]
+                return fit([r for r in part if r.kind == COMPRESS],
+                           [r for r in part if r.kind == DECOMPRESS]) <= self.lane_ws
+            if not fits(len(batch)):
+                lo, hi = 1, len(batch)          # a request alone fits (checked at submit)
+                while hi - lo > 1:
+                    mid = (lo + hi) // 2
+                    if fits(mid):
+                        lo = mid
+                    else:
+                        hi = mid
+                for r in reversed(batch[lo:]):
+                    self._ready.appendleft(r)
+                del batch[lo:]
         return batch
 
     def _lane(self, lane):

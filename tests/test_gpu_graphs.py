@@ -1,5 +1,5 @@
 """Launch sequences from cached HIP graphs: calls of one shape replay the
-graph recorded by the first, with the program's own eager work and
+graph recorded by an earlier one (the second), with the program's own eager work and
 synchronisations between the replays.  Every replay's stream must be the
 oracle's, byte for byte, and every decode the oracle's, bit for bit; the
 same calls with graphs switched off (EBCC_GRAPHS=0) give the same bytes."""

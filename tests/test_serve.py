@@ -209,6 +209,32 @@ def test_batch_workspace_decides_over_the_sum():
     assert starts == sorted(starts)
 
 
+def test_batch_is_the_longest_prefix_that_fits():
+    """A batch shares workspace (the library sizes it below the sum of its
+    requests alone): the lane takes the longest FIFO prefix whose batch
+    sizing fits its workspace, more requests than their own sizes would
+    allow, and never one that does not fit."""
+    ex = WsExecutor(per_sample=1e-6)
+    n = 181 * 360
+    ex.workspace = lambda req: req.samples
+    ex.batch_workspace = lambda comp, dec: max(sum(r.samples for r in comp) // 2 + 1000,
+                                               sum(r.samples for r in dec) // 2 + 1000)
+    lane_ws = 3 * n                         # own sizes: 3 per batch; batch sizing: 5
+    srv = serve.Server(hbm_budget=10**9, lanes=1, lane_workspace=lane_ws, executor=ex)
+    blocker = srv.submit(serve.Request(serve.COMPRESS, FakeData((181, 360), 99), eps=0.01, tag=99))
+    srv.start()
+    time.sleep(0.01)                        # the lane is busy with the first request (65 ms)
+    reqs = [srv.submit(serve.Request(serve.COMPRESS, FakeData((181, 360), i), eps=0.01, tag=i)) for i in range(12)]
+    for r in [blocker] + reqs:
+        r.wait(10)
+    srv.stop()
+    _check_results(reqs)
+    assert max(ex.batch_ws) <= lane_ws
+    assert max(srv.batch_sizes) == 5
+    starts = [r.t_start for r in reqs]
+    assert starts == sorted(starts)
+
+
 def test_on_done_runs_before_completion_is_signalled():
     seen = []
     srv = serve.Server(lanes=1, executor=FakeExecutor()).start()
