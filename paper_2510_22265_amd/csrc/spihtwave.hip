@@ -685,6 +685,25 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
     int head = 0, kept = 0, wbase = 0, wcnt = 0;
     uint32_t wv = 0;
     while (head < nlis) {
+      // a run of zero bits (sets that stay insignificant) leaves its entries
+      // in the list: they move down to the kept ones 64 at a time (only
+      // below the current position, which the window never reads again)
+      int z = rd.zeros();
+      if (z > nlis - head) z = nlis - head;
+      if (z > 0) {
+        if (kept != head)
+          for (int c = 0; c < z; c += 64) {
+            const int i = c + lane;
+            const uint16_t v = i < z ? S.lis[head + i] : (uint16_t)0;
+            __syncthreads();
+            if (i < z) S.lis[kept + i] = v;
+            __syncthreads();
+          }
+        rd.skip(z);
+        head += z;
+        kept += z;
+        continue;
+      }
       if (head - wbase >= wcnt) {
         wbase = head;
         wcnt = nlis - head < 64 ? nlis - head : 64;
