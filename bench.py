@@ -127,7 +127,9 @@ def cpu_model():
 def verify(xs_h, recs, eps):
     """Count bound violations (FP64) and the largest range-relative error."""
     viol, max_rel = 0, 0.0
-    for x, y, e in zip(xs_h, recs, eps):
+    for i, (x, y, e) in enumerate(zip(xs_h, recs, eps)):
+        if i and i % 128 == 0:
+            log(f"verified {i} of {len(xs_h)} fields")
         rng_ = float(x.max()) - float(x.min())
         yh = y if isinstance(y, np.ndarray) else y.cpu().numpy()
         err = float(np.abs(x.astype(np.float64) - yh.astype(np.float64)).max())
@@ -763,7 +765,9 @@ def main():
         c = time.perf_counter()
         kviol, kmax = verify(km_h, krec, [0.001] * len(kx))
         ext_err = 0.0
-        for f, y in zip(km_h, krec):   # error at the vortex cores (top 0.01% of |x|)
+        for i, (f, y) in enumerate(zip(km_h, krec)):   # error at the vortex cores (top 0.01% of |x|)
+            if i and i % 128 == 0:
+                log(f"vortex-core errors of {i} of {len(km_h)} fields")
             a64 = np.abs(f.astype(np.float64))
             m = a64 >= np.quantile(a64, 0.9999)
             e = np.abs(f.astype(np.float64) - y.cpu().numpy().astype(np.float64))[m].max()
