@@ -17,7 +17,8 @@
  *    device); h_ are host pointers.  The caller owns every buffer passed in.
  *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
  *    it; entry points that return a size or a status read it back and
- *    therefore synchronise that stream before returning.
+ *    therefore synchronise that stream before returning (the asynchronous
+ *    decoder leaves its statuses in device memory instead).
  *  - The library keeps per-device scratch workspaces and per-shape plans
  *    between calls (grown on demand, freed by ebcc_release).  Calls on
  *    different streams are safe to make from different host threads.
@@ -153,6 +154,44 @@ int ebcc_compress_batch(int n, const float* const* d_x, const size_t* ny, const 
 int ebcc_decompress_batch(int n, const uint8_t* const* d_in, const size_t* in_len,
                           float* const* d_x, const size_t* ny, const size_t* nx, int* h_status,
                           void* stream);
+
+/* Decompress n streams without waiting for the device (the decoder of
+ * Algorithm 1's problem statement, batched): every step is enqueued on
+ * `stream` and the call returns; stream offsets, lengths and the per-stream
+ * statuses stay in device memory.  The host knows the streams' shapes and
+ * the parameters they were coded with, not their bytes.
+ *   d_in          device buffer holding the streams.
+ *   d_offsets, d_lengths  device [n]: stream i is d_in[d_offsets[i] ..
+ *                 + d_lengths[i]); each such range must lie inside the
+ *                 caller's allocation (the lengths written by a batched
+ *                 compression, for instance).
+ *   d_x, ny, nx   host [n]: device pointer and shape of output field i.
+ *   p             the parameters the streams were coded with (host; NULL =
+ *                 defaults): levels, cblk_log2w/h and spiht_tile must be
+ *                 those of every coded stream; trunc = 1 and bypass = 1
+ *                 allow streams with byte-cut residuals and with the tier-1
+ *                 bypass (streams without them decode too); the other
+ *                 fields are not used.
+ *   d_status      device int32 [n]: set, when the work has run, to each
+ *                 stream's status: EBCC_OK, EBCC_ECORRUPT (the checks of
+ *                 ebcc_decompress_batch: header, lengths, tables, checksum)
+ *                 or EBCC_EINVAL (shape not the stream's, or coding
+ *                 parameters other than p's).  A stream that fails the
+ *                 header checks leaves its output untouched; one found
+ *                 corrupt by its tables or checksum has been decoded all the
+ *                 same (its output is meaningless); the others decode.
+ * Returns EBCC_EINVAL for bad arguments (NULL arrays, shapes out of range,
+ * invalid p) before anything is enqueued, EBCC_ENOMEM / EBCC_EHIP when
+ * enqueuing fails (the statuses of streams not yet enqueued then stay
+ * unwritten), EBCC_OK otherwise.  Does not synchronise `stream`: the inputs
+ * must stay unchanged and the outputs and statuses must not be read until
+ * the stream has reached this point.  A call may wait for an earlier
+ * call's table uploads (at most four calls' uploads are in flight per
+ * stream), and waits when its stream's workspace has to grow. */
+int ebcc_decompress_batch_async(int n, const uint8_t* d_in, const uint64_t* d_offsets,
+                                const uint64_t* d_lengths, float* const* d_x, const size_t* ny,
+                                const size_t* nx, const ebcc_params* p, int32_t* d_status,
+                                void* stream);
 
 /* Compress one float32 field without allocating: for callers that cannot
  * allocate memory (code under HIP graph capture, tight serving loops,

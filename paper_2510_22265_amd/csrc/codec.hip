@@ -595,6 +595,111 @@ __global__ void k_check_tables(const FieldDev* __restrict__ F, int nfields) {
   if (f.rb && f.totals[1] != (int64_t)f.rb - 4 * (int64_t)f.ntiles - (f.bt ? 8 : 0)) f.flags[1] = 1;
 }
 
+// Asynchronous decoding: the host knows each stream's shape and the coding
+// parameters of the call, not the stream's bytes.  One thread per stream
+// checks the header (the host decoder's checks, plus agreement with the
+// call's parameters), sets the field's scalars and its entries in the
+// residual (Fr, scratch of the residual's inverse DWT in BUF_CRES) and
+// no-residual (Fn) tables, and writes the stream's status.
+struct AsyncCfg {
+  int cbl, T, trunc, byp;
+};
+
+__device__ int levels_eff_dev(int ny, int nx, int L) {
+  int m = ny < nx ? ny : nx, f = 0;
+  while ((2L << f) <= m) f++;
+  if (L > f) L = f;
+  if (L > kMaxLevels) L = kMaxLevels;
+  return L < 0 ? 0 : L;
+}
+
+__global__ void k_parse_async(FieldDev* __restrict__ F, FieldDev* __restrict__ Fr, FieldDev* __restrict__ Fn, int nf,
+                              const uint8_t* __restrict__ in, const uint64_t* __restrict__ offs,
+                              const uint64_t* __restrict__ lens, const AsyncCfg cfg, int32_t* __restrict__ status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  FieldDev f = F[i];
+  const uint64_t len = lens[i];
+  const uint8_t* h = in + offs[i];
+  const int64_t N = (int64_t)f.ny * f.nx;
+  int st = EBCC_OK, mode = MODE_CONST, bt = 0, byp = 0, e0 = 0, er = 0, ns = 0;
+  uint32_t bb = 0, rb = 0;
+  if (len < (uint64_t)kHdr) {
+    st = EBCC_ECORRUPT;
+  } else if (h[0] != 'E' || h[1] != 'B' || h[2] != 'C' || h[3] != 'C' || h[4] != 1 || h[5] > MODE_CODED) {
+    st = EBCC_ECORRUPT;
+  } else if (get32(h + 8) != (uint32_t)f.ny || get32(h + 12) != (uint32_t)f.nx) {
+    st = EBCC_EINVAL;
+  } else {
+    mode = h[5];
+    bb = get32(h + 36);
+    rb = get32(h + 40);
+    if ((uint64_t)kHdr + bb + rb != len) {
+      st = EBCC_ECORRUPT;
+    } else if (mode == MODE_RAW && (int64_t)bb != 4 * N) {
+      st = EBCC_ECORRUPT;
+    } else if (mode == MODE_CODED) {
+      const int L = h[6], w2 = h[7] & 15, h2 = h[7] >> 4, T = h[32] | (h[33] << 8);
+      e0 = (int8_t)h[28];
+      er = (int8_t)h[29];
+      ns = (int8_t)h[31];
+      if (L != levels_eff_dev(f.ny, f.nx, L) || w2 < 2 || w2 > 6 || h2 < 2 || h2 > 6 || T < 1 || T > 64 || ns < 0 ||
+          ns >= kQBits) {
+        st = EBCC_ECORRUPT;
+      } else {
+        bt = rb ? (h[34] & 1) : 0;
+        byp = h[35] & 1;
+        if (L != f.L || h[7] != cfg.cbl || T != cfg.T || (bt && !cfg.trunc) || (byp && !cfg.byp))
+          st = EBCC_EINVAL;   // coded with other parameters than the call's
+        else if ((int64_t)bb < 4 * (int64_t)f.nblk)
+          st = EBCC_ECORRUPT;
+        else if (rb && (int64_t)rb < 4 * (int64_t)f.ntiles + (bt ? 8 : 0))
+          st = EBCC_ECORRUPT;
+      }
+    }
+  }
+  const bool ok = st == EBCC_OK;
+  f.out = const_cast<uint8_t*>(h);
+  f.len = (int64_t)len;
+  f.mode = mode;
+  f.bb = bb; f.rb = rb;
+  f.e0 = e0; f.er = er; f.ns = ns;
+  f.bt = bt; f.byp = byp;
+  f.active = ok ? 1 : 0;
+  f.fp->xmin = ok ? __uint_as_float(get32(h + 16)) : 0.0f;
+  f.fp->range_f = ok ? __uint_as_float(get32(h + 20)) : 0.0f;
+  f.fp->inv_f = 0.0f;
+  f.fp->eps = 0.0;
+  for (int k = 0; k < 8; k++) { f.flags[k] = 0; f.u32s[k] = 0; f.totals[k] = 0; }
+  F[i] = f;
+  FieldDev r = f;
+  r.active = ok && mode == MODE_CODED && rb != 0;
+  r.buf[BUF_TMP] = r.buf[BUF_CRES];
+  Fr[i] = r;
+  FieldDev q = f;
+  q.active = ok && mode == MODE_CODED && rb == 0;
+  Fn[i] = q;
+  status[i] = st;
+}
+
+// Asynchronous decoding: the fields of one role (a stream mode; mode < 0:
+// every stream whose header passed) active, the others not.
+__global__ void k_select_async(FieldDev* __restrict__ F, int nf, const int32_t* __restrict__ status, int mode) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  F[i].active = status[i] == EBCC_OK && (mode < 0 || F[i].mode == mode);
+}
+
+// Asynchronous decoding: a stream whose tables are inconsistent or whose
+// checksum differs from its header's is corrupt.
+__global__ void k_finish_async(const FieldDev* __restrict__ F, int nf, int32_t* __restrict__ status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf || status[i] != EBCC_OK) return;
+  const FieldDev& f = F[i];
+  if (f.flags[1]) status[i] = EBCC_ECORRUPT;
+  else if (f.u32s[1] != get32(f.out + 44)) status[i] = EBCC_ECORRUPT;
+}
+
 
 // ---------------------------------------------------------------------------
 // Plans: per-shape geometry on the host and on the device.
@@ -834,8 +939,24 @@ struct WS {
   // stream on which launch sequences are recorded into graphs (recording
   // runs nothing; the graph is then launched on the caller's stream)
   hipStream_t capst = nullptr;
+  // pinned staging areas of the asynchronous decoder: an area is reused only
+  // once the copies staged from it have run (its event), so a call returns
+  // without waiting for the ones before it
+  struct APin {
+    uint8_t* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool live = false;
+  };
+  static constexpr int kAPins = 4;
+  APin apin[kAPins];
   ~WS() {
     if (fixed) return;
+    for (APin& a : apin) {
+      if (a.live) (void)hipEventSynchronize(a.ev);
+      if (a.p) (void)hipHostFree(a.p);
+      if (a.ev) (void)hipEventDestroy(a.ev);
+    }
     if (ev_live) (void)hipEventSynchronize(ev);
     if (base) (void)hipFree(base);
     if (pin) (void)hipHostFree(pin);
@@ -913,6 +1034,37 @@ static int grow_ws(WS* w, size_t need, size_t pin_need, hipStream_t st, char** b
   }
   *base = (char*)w->base;
   return EBCC_OK;
+}
+
+// An asynchronous call's staging area of at least need bytes: one whose
+// copies have run (waiting for the oldest when all are in flight), grown
+// when too small.
+static int async_pin(WS* w, size_t need, WS::APin** out) {
+  for (int pass = 0; pass < 2; pass++) {
+    for (WS::APin& a : w->apin) {
+      if (a.live) {
+        const hipError_t q = pass ? hipEventSynchronize(a.ev) : hipEventQuery(a.ev);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return fail(EBCC_EHIP, std::string("staging area event: ") + hipGetErrorString(q));
+        a.live = false;
+      }
+      if (a.cap < need) {
+        if (a.p) HIPCHK(hipHostFree(a.p));
+        a.p = nullptr;
+        a.cap = 0;
+        const size_t alloc = std::max<size_t>(need, 1 << 20);
+        if (hipHostMalloc((void**)&a.p, alloc, hipHostMallocDefault) != hipSuccess) {
+          a.p = nullptr;
+          return fail(EBCC_ENOMEM, "pinned staging allocation failed");
+        }
+        a.cap = alloc;
+      }
+      if (!a.ev) HIPCHK(hipEventCreateWithFlags(&a.ev, hipEventDisableTiming));
+      *out = &a;
+      return EBCC_OK;
+    }
+  }
+  return fail(EBCC_EHIP, "internal: no staging area");
 }
 
 // Batches are processed in chunks of at most this many samples or fields.
@@ -1014,8 +1166,15 @@ struct Call {
   // fields' subband tables are carved from the workspace and staged
   bool own_bands = false;
   Band* d_bands_own = nullptr;
+  // asynchronous calls stage through an area of their own (WS::apin)
+  WS::APin* apin = nullptr;
+  size_t apin_used = 0;
 
   ~Call() {
+    if (apin) {   // (normally marked right after the staging)
+      if (!apin->live && hipEventRecord(apin->ev, st) == hipSuccess) apin->live = true;
+      return;
+    }
     if (ws && ws->ev && hipEventRecord(ws->ev, st) == hipSuccess) ws->ev_live = true;
   }
   int wait() {
@@ -1038,6 +1197,14 @@ struct Call {
         k_put_bytes<<<1, 256, 0, st>>>((uint8_t*)dst + o, ch, m);
       }
       HIPCHK(hipGetLastError());
+      return EBCC_OK;
+    }
+    if (apin) {
+      const size_t a = (apin_used + 255) & ~(size_t)255;
+      if (a + n > apin->cap) return fail(EBCC_ENOMEM, "internal: staging area smaller than the call's tables");
+      memcpy(apin->p + a, src, n);
+      HIPCHK(hipMemcpyAsync(dst, apin->p + a, n, hipMemcpyHostToDevice, st));
+      apin_used = a + n;
       return EBCC_OK;
     }
     if (n > ws->pin_cap) return fail(EBCC_ENOMEM, "staging buffer smaller than a table");
@@ -2147,6 +2314,71 @@ static std::vector<std::vector<int>> decode_calls(int n, const uint8_t* hdrs, co
   return calls;
 }
 
+// The launch sequence that decodes the coded fields of a call (c.F's active
+// entries), from the block and tile tables to the output: c.Fc holds the
+// fields with a residual (scratch of the residual's inverse DWT in BUF_CRES),
+// c.Fc + nf those without one; Frh and Fnh are their host copies (grid
+// sizes).  anyres / anynores / anybt may be set when no field needs them:
+// the kernels skip inactive fields, fields without a residual section and
+// residuals not cut at a byte position.
+static int decode_sequence(Call& c, Prof& prof, bool anyres, bool anynores, bool anybt, const FieldDev* Frh,
+                           const FieldDev* Fnh, size_t maxN, hipStream_t s) {
+  const int nf = c.nf;
+  FieldDev* const Fnd = c.Fc + nf;
+  k_read_blocks<<<grid_for(c.nblk), 256, 0, s>>>(c.F, c.d_blk, c.nblk, c.bent);
+  k_scan<<<nf, 1024, 0, s>>>(c.F, c.bent, 0, 16, 0xFFFFu, c.boff);
+  k_read_tiles<<<grid_for(c.ntiles), 256, 0, s>>>(c.F, c.d_tiles, c.ntiles, c.tent);
+  k_scan<<<nf, 1024, 0, s>>>(c.F, c.tent, 1, 0, 0x3FFFFFFu, c.toff);
+  k_check_tables<<<(nf + 63) / 64, 64, 0, s>>>(c.F, nf);
+  prof.mark(S_D_PARSE);
+  if (anyres) {
+    // The residual layer decodes independently of the base layer: SPIHT
+    // runs on the second and third streams while tier-1 decoding and the
+    // base inverse DWT run on the caller's (the SPIHT kernels skip
+    // fields without a residual section).
+    k_fill<<<dim3(grid_for(maxN), nf), 256, 0, s>>>(c.F, BUF_CHAT, 0.0f);
+    hipStream_t sa = c.ws->aux;
+    if (int rc2 = c.fork_from(s)) return rc2;
+    if (anybt) spiht_decode_cut(c.F, nf, c.d_tiles, c.toff, c.lists, sa);
+    if (c.forced_global) {
+      spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, sa);
+    } else {
+      // small tiles on one stream, the larger classes on another
+      const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
+      hipStream_t sb = c.ws->aux2;
+      // the LDS classes' tiles longest payload first (batches: the
+      // longest decodes start first)
+      int *o0 = c.tix_sorted, *o1 = o0 + c.ncls[0];
+      spiht_tiles_longest_first(t0, c.ncls[0], c.tent, o0, sa);
+      spiht_tiles_longest_first(t1, c.ncls[1], c.tent, o1, sb);
+      spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sb);
+      spiht_decode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.toff, c.misfit, sb);
+      spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, o1, c.ncls[1], c.toff, c.misfit, sb);
+      spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, o0, c.ncls[0], c.toff, c.misfit, sa);
+    }
+    // all of the residual's inverse DWT but its last pass, in the shadow
+    // of tier-1 decoding, once both SPIHT streams are done
+    hipStream_t sb = c.ws->aux2;
+    HIPCHK(hipEventRecord(c.ws->ev_join, sa));
+    HIPCHK(hipStreamWaitEvent(sb, c.ws->ev_join, 0));
+    dwt_inverse_head(c.Fc, Frh, nf, BUF_CHAT, sb);
+  }
+  // (no scalar/vector split here: the second stream is busy with SPIHT)
+  t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, s, nullptr, c.border, c.qctr, c.any_byp);
+  prof.mark(S_D_T1);
+  dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, s);
+  prof.mark(S_D_IDWT_BASE);
+  if (anyres) {
+    if (int rc2 = c.join_to(s)) return rc2;
+    prof.mark(S_D_SPIHT);
+    dwt_inverse_tail(c.Fc, Frh, nf, BUF_CHAT, BUF_CHAT, EPI_FINAL, s);
+  }
+  if (anynores) pointwise(Fnd, Fnh, nf, BUF_CHAT, BUF_CHAT, 3, EPI_FINAL, 0, s);
+  prof.mark(S_D_FINAL);
+  HIPCHK(hipGetLastError());
+  return EBCC_OK;
+}
+
 static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs, std::vector<int>& st_out,
                            hipStream_t st) {
   const int nf = (int)in.size();
@@ -2285,58 +2517,7 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
     bool anybt = false;
     for (int i = 0; i < nf; i++) anybt |= cr[i] && c.Fh[i].bt;
     auto seq = [&](hipStream_t s) -> int {
-      k_read_blocks<<<grid_for(c.nblk), 256, 0, s>>>(c.F, c.d_blk, c.nblk, c.bent);
-      k_scan<<<nf, 1024, 0, s>>>(c.F, c.bent, 0, 16, 0xFFFFu, c.boff);
-      k_read_tiles<<<grid_for(c.ntiles), 256, 0, s>>>(c.F, c.d_tiles, c.ntiles, c.tent);
-      k_scan<<<nf, 1024, 0, s>>>(c.F, c.tent, 1, 0, 0x3FFFFFFu, c.toff);
-      k_check_tables<<<(nf + 63) / 64, 64, 0, s>>>(c.F, nf);
-      prof.mark(S_D_PARSE);
-      if (anyres) {
-        // The residual layer decodes independently of the base layer: SPIHT
-        // runs on the second and third streams while tier-1 decoding and the
-        // base inverse DWT run on the caller's (the SPIHT kernels skip
-        // fields without a residual section).
-        k_fill<<<dim3(grid_for(maxN), nf), 256, 0, s>>>(c.F, BUF_CHAT, 0.0f);
-        hipStream_t sa = c.ws->aux;
-        if (int rc2 = c.fork_from(s)) return rc2;
-        if (anybt) spiht_decode_cut(c.F, nf, c.d_tiles, c.toff, c.lists, sa);
-        if (c.forced_global) {
-          spiht_decode(c.F, c.d_tiles, c.d_tix, c.ntiles, c.toff, c.lists, sa);
-        } else {
-          // small tiles on one stream, the larger classes on another
-          const int *t0 = c.d_tix, *t1 = t0 + c.ncls[0], *t2 = t1 + c.ncls[1], *t3 = t2 + c.ncls[2];
-          hipStream_t sb = c.ws->aux2;
-          // the LDS classes' tiles longest payload first (batches: the
-          // longest decodes start first)
-          int *o0 = c.tix_sorted, *o1 = o0 + c.ncls[0];
-          spiht_tiles_longest_first(t0, c.ncls[0], c.tent, o0, sa);
-          spiht_tiles_longest_first(t1, c.ncls[1], c.tent, o1, sb);
-          spiht_decode(c.F, c.d_tiles, t2, c.ncls[2], c.toff, c.lists, sb);
-          spiht_decode_lds(kSpihtHuge, c.F, c.d_tiles, t3, c.ncls[3], c.toff, c.misfit, sb);
-          spiht_decode_lds(kSpihtBig, c.F, c.d_tiles, o1, c.ncls[1], c.toff, c.misfit, sb);
-          spiht_decode_lds(kSpihtSmall, c.F, c.d_tiles, o0, c.ncls[0], c.toff, c.misfit, sa);
-        }
-        // all of the residual's inverse DWT but its last pass, in the shadow
-        // of tier-1 decoding, once both SPIHT streams are done
-        hipStream_t sb = c.ws->aux2;
-        HIPCHK(hipEventRecord(c.ws->ev_join, sa));
-        HIPCHK(hipStreamWaitEvent(sb, c.ws->ev_join, 0));
-        dwt_inverse_head(c.Fc, Fr.data(), nf, BUF_CHAT, sb);
-      }
-      // (no scalar/vector split here: the second stream is busy with SPIHT)
-      t1_decode(c.F, c.d_blk, c.nblk, c.cbw, c.cbh, c.bent, c.boff, s, nullptr, c.border, c.qctr, c.any_byp);
-      prof.mark(S_D_T1);
-      dwt_inverse(c.F, c.Fh.data(), nf, BUF_YHAT, BUF_ABASE, EPI_STORE, s);
-      prof.mark(S_D_IDWT_BASE);
-      if (anyres) {
-        if (int rc2 = c.join_to(s)) return rc2;
-        prof.mark(S_D_SPIHT);
-        dwt_inverse_tail(c.Fc, Fr.data(), nf, BUF_CHAT, BUF_CHAT, EPI_FINAL, s);
-      }
-      if (anynores) pointwise(Fnd, Fn.data(), nf, BUF_CHAT, BUF_CHAT, 3, EPI_FINAL, 0, s);
-      prof.mark(S_D_FINAL);
-      HIPCHK(hipGetLastError());
-      return EBCC_OK;
+      return decode_sequence(c, prof, anyres, anynores, anybt, Fr.data(), Fn.data(), maxN, s);
     };
     if (graphs_usable(c, prof)) {
       GraphKey key("decode", c);
@@ -2358,6 +2539,88 @@ static int decompress_call(const std::vector<StreamIn>& in, const uint8_t* hdrs,
     else if ((uint32_t)col[8 * i + 3] != csum) bad(i, EBCC_ECORRUPT, "checksum mismatch");
   }
   return first;
+}
+
+// Asynchronous batched decoding of streams [i0, i0 + m) of
+// ebcc_decompress_batch_async: every field is laid out as coded with the
+// call's parameters (geometry known on the host); the headers are checked
+// and the fields' roles chosen on the device, every role's launches run and
+// skip the fields that are not theirs, and the statuses stay on the device.
+// Nothing waits for the device.
+static int decompress_async_chunk(const uint8_t* d_in, const uint64_t* d_offs, const uint64_t* d_lens, int i0, int m,
+                                  float* const* d_x, const size_t* ny, const size_t* nx, const ebcc_params* p,
+                                  int32_t* d_status, hipStream_t st) {
+  Call c;
+  c.nf = m;
+  c.st = st;
+  c.Fh.assign(m, FieldDev());
+  c.plans.assign(m, nullptr);
+  const int w2 = (int)p->cblk_log2w, h2 = (int)p->cblk_log2h, T = (int)p->spiht_tile;
+  std::vector<int> coded(m, 1);
+  int rc;
+  for (int k = 0; k < m; k++) {
+    FieldDev& f = c.Fh[k];
+    memset(&f, 0, sizeof(f));
+    f.ny = (int)ny[i0 + k];
+    f.nx = (int)nx[i0 + k];
+    f.L = levels_eff(f.ny, f.nx, (int)p->levels);
+    f.cbl = w2 | (h2 << 4);
+    f.T = T;
+    f.mode = MODE_CODED;
+    f.active = 1;
+    f.bt = (int)p->trunc;
+    f.byp = (int)p->bypass;
+    if ((rc = get_plan(f.ny, f.nx, f.L, w2, h2, T, &c.plans[k]))) return rc;
+    f.bands = c.plans[k]->d_bands;
+    f.nb = c.plans[k]->nb;
+  }
+  c.cbw = 1 << w2;
+  c.cbh = 1 << h2;
+  c.any_byp = p->bypass != 0;
+  const size_t need_ws = decompress_need(c, coded);
+  char* base;
+  if ((rc = get_ws(st, &c.ws))) return rc;
+  if ((rc = grow_ws(c.ws, need_ws, 0, st, &base))) return rc;
+  layout_call(c, base, coded);
+  for (int k = 0; k < m; k++) c.Fh[k].buf[BUF_XOUT] = d_x[i0 + k];
+  // the field table and the item tables go through a staging area of the
+  // call's own, free again once these copies have run
+  const size_t stage_bytes = sizeof(FieldDev) * (size_t)m + sizeof(Blk) * (size_t)c.nblk +
+                             (sizeof(TileD) + sizeof(int) + sizeof(int64_t)) * (size_t)c.ntiles + sizeof(int64_t) +
+                             8 * 256;
+  if ((rc = async_pin(c.ws, stage_bytes, &c.apin))) return rc;
+  Prof prof(st);
+  if ((rc = upload_items(c, coded))) return rc;
+  if ((rc = c.upload())) return rc;
+  HIPCHK(hipEventRecord(c.apin->ev, st));
+  c.apin->live = true;
+  size_t maxN = 0;
+  for (auto& f : c.Fh) maxN = std::max(maxN, (size_t)f.ny * f.nx);
+  const AsyncCfg cfg{w2 | (h2 << 4), T, (int)p->trunc, (int)p->bypass};
+  int32_t* sts = d_status + i0;
+  const int g = (m + 63) / 64;
+  k_parse_async<<<g, 64, 0, st>>>(c.F, c.Fc, c.Fc + m, m, d_in, d_offs + i0, d_lens + i0, cfg, sts);
+  k_checksum<<<dim3(grid_sweep(maxN), m), 256, 0, st>>>(c.F);
+  k_select_async<<<g, 64, 0, st>>>(c.F, m, sts, MODE_CONST);
+  k_fill<<<dim3(grid_for(maxN), m), 256, 0, st>>>(c.F, BUF_XOUT, __builtin_nanf(""));
+  k_select_async<<<g, 64, 0, st>>>(c.F, m, sts, MODE_RAW);
+  k_copy_raw<<<dim3(grid_for(maxN), m), 256, 0, st>>>(c.F, 0);
+  k_select_async<<<g, 64, 0, st>>>(c.F, m, sts, MODE_CODED);
+  const bool anybt = p->trunc != 0;
+  auto seq = [&](hipStream_t s) -> int {
+    return decode_sequence(c, prof, true, true, anybt, c.Fh.data(), c.Fh.data(), maxN, s);
+  };
+  if (graphs_usable(c, prof)) {
+    GraphKey key("decode_async", c);
+    key.add(anybt);
+    key.add(maxN);
+    if ((rc = run_graph(key, c, seq))) return rc;
+  } else if ((rc = seq(st))) {
+    return rc;
+  }
+  k_finish_async<<<g, 64, 0, st>>>(c.F, m, sts);
+  HIPCHK(hipGetLastError());
+  return EBCC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -2581,6 +2844,34 @@ int ebcc_decompress_batch(int n, const uint8_t* const* d_in, const size_t* in_le
   }
   if (first) g_err = first_msg;
   return first;
+}
+
+int ebcc_decompress_batch_async(int n, const uint8_t* d_in, const uint64_t* d_offsets, const uint64_t* d_lengths,
+                                float* const* d_x, const size_t* ny, const size_t* nx, const ebcc_params* p,
+                                int32_t* d_status, void* stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!d_in || !d_offsets || !d_lengths || !d_x || !ny || !nx || !d_status)))
+    return fail(EBCC_EINVAL, "bad batch arguments");
+  ebcc_params dflt;
+  if (!p) { ebcc_params_default(&dflt); p = &dflt; }
+  for (int i = 0; i < n; i++) {
+    if (int rc = check_params(ny[i], nx[i], p, 1.0)) return rc;
+    if (!d_x[i]) return fail(EBCC_EINVAL, "NULL output buffer in the batch");
+  }
+  const hipStream_t st = (hipStream_t)stream;
+  int i0 = 0;
+  while (i0 < n) {
+    // one chunk: consecutive streams up to kChunkSamples samples (at least one)
+    int m = 0;
+    size_t samples = 0;
+    while (i0 + m < n && (m == 0 || samples + ny[i0 + m] * nx[i0 + m] <= kChunkSamples) && m < kChunkFields) {
+      samples += ny[i0 + m] * nx[i0 + m];
+      m++;
+    }
+    if (int rc = decompress_async_chunk(d_in, d_offsets, d_lengths, i0, m, d_x, ny, nx, p, d_status, st)) return rc;
+    i0 += m;
+  }
+  return EBCC_OK;
 }
 
 int ebcc_stream_info(const uint8_t* h, size_t len, size_t* ny, size_t* nx, int* mode) {

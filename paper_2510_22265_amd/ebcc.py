@@ -22,7 +22,8 @@ SYMBOLS = ("ebcc_params_default", "ebcc_compress_bound", "ebcc_compress", "ebcc_
            "ebcc_release", "ebcc_status_str", "ebcc_last_error", "ebcc_compress_trace", "ebcc_profile_enable",
            "ebcc_profile_read", "ebcc_profile_stage_name", "ebcc_compress_batch", "ebcc_decompress_batch",
            "ebcc_tuning_get", "ebcc_tuning_set", "ebcc_workspace_size", "ebcc_workspace_size_batch",
-           "ebcc_workspace_reserve", "ebcc_device_bytes", "ebcc_compress_noalloc")
+           "ebcc_workspace_reserve", "ebcc_device_bytes", "ebcc_compress_noalloc",
+           "ebcc_decompress_batch_async")
 
 
 class Params(C.Structure):
@@ -72,6 +73,7 @@ def lib():
         L.ebcc_device_bytes.argtypes = []
         L.ebcc_device_bytes.restype = S
         L.ebcc_decompress_batch.argtypes = [C.c_int, P, P, P, P, P, P, P]
+        L.ebcc_decompress_batch_async.argtypes = [C.c_int, P, P, P, P, P, P, C.POINTER(Params), P, P]
         L.ebcc_stream_info.argtypes = [P, S, C.POINTER(S), C.POINTER(S), C.POINTER(C.c_int)]
         L.ebcc_tuning_get.argtypes = [C.POINTER(Tuning)]
         L.ebcc_tuning_set.argtypes = [C.POINTER(Tuning)]
@@ -279,6 +281,37 @@ def decompress_batch(streams, shapes, stream=None, check=True):
         _check(rc)
         return outs
     return outs, [args.status[i] for i in range(args.n)]
+
+
+def decompress_batch_async(buf, offsets, lengths, shapes, stream=None, outs=None, status=None, **kw):
+    """Decompress the streams buf[offsets[i] : offsets[i] + lengths[i]] (buf a
+    uint8 CUDA tensor; offsets and lengths int64/uint64 CUDA tensors) into
+    float32 CUDA tensors of the given shapes without waiting for the device.
+    kw are the coding parameters of the streams (levels, cblk_log2w,
+    cblk_log2h, spiht_tile, trunc, bypass).  Returns (outputs, status), status
+    an int32 CUDA tensor of per-stream codes; both are valid once `stream`
+    (default: the current stream) has reached this point.  Raises only for
+    errors found before or while enqueuing."""
+    n = len(shapes)
+    dev = buf.device
+    for t in (buf, offsets, lengths):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+            raise TypeError("buf, offsets and lengths must be contiguous CUDA tensors")
+    if buf.dtype != torch.uint8 or offsets.dtype not in (torch.int64, torch.uint64) or \
+            lengths.dtype not in (torch.int64, torch.uint64) or offsets.numel() < n or lengths.numel() < n:
+        raise TypeError("buf uint8, offsets and lengths 64-bit integers with one entry per stream")
+    if outs is None:
+        outs = [torch.empty(tuple(sh), dtype=torch.float32, device=dev) for sh in shapes]
+    if status is None:
+        status = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+    d_x = _arr(C.c_void_p, [o.data_ptr() for o in outs])
+    ny = _arr(C.c_size_t, [int(sh[0]) for sh in shapes])
+    nx = _arr(C.c_size_t, [int(sh[1]) for sh in shapes])
+    p = params(**kw)
+    _check(lib().ebcc_decompress_batch_async(n, C.c_void_p(buf.data_ptr()), C.c_void_p(offsets.data_ptr()),
+                                             C.c_void_p(lengths.data_ptr()), d_x, ny, nx, C.byref(p),
+                                             C.c_void_p(status.data_ptr()), _stream_ptr(stream)))
+    return outs, status[:n]
 
 
 def stream_info(header_bytes):

@@ -132,3 +132,30 @@ def test_workspace_size_queries():
     # constant and raw streams need no field buffers
     const = ebcc.workspace_size_batch([shapes[3]], headers=[_hdr(721, 1440, mode=0)], lengths=[48])
     assert const < dec
+
+
+def test_async_decode_refuses_bad_arguments():
+    """ebcc_decompress_batch_async checks its arguments on the host before it
+    enqueues anything: an empty batch is a no-op; negative counts, NULL
+    arrays, shapes out of range and invalid parameters are EINVAL (the
+    pointers below are never dereferenced)."""
+    ebcc = _lib()
+    L = ebcc.lib()
+    C = ctypes
+    fake = C.c_void_p(256)
+    p = ebcc.params()
+
+    def call(n, ny, nx, p, status=fake, d_in=fake):
+        d_x = (C.c_void_p * max(1, n))(*([fake] * max(1, n)))
+        a_ny = (C.c_size_t * max(1, n))(*([ny] * max(1, n)))
+        a_nx = (C.c_size_t * max(1, n))(*([nx] * max(1, n)))
+        return L.ebcc_decompress_batch_async(n, d_in, fake, fake, d_x, a_ny, a_nx, C.byref(p), status, None)
+
+    assert L.ebcc_decompress_batch_async(0, None, None, None, None, None, None, C.byref(p), None, None) == ebcc.OK
+    assert call(-1, 8, 8, p) == ebcc.EINVAL
+    assert call(1, 8, 8, p, status=None) == ebcc.EINVAL
+    assert call(1, 8, 8, p, d_in=None) == ebcc.EINVAL
+    assert call(1, 0, 8, p) == ebcc.EINVAL
+    assert call(2, 1 << 25, 8, p) == ebcc.EINVAL
+    for bad in (dict(cblk_log2w=7), dict(spiht_tile=0), dict(levels=17), dict(trunc=2), dict(bypass=3)):
+        assert call(1, 8, 8, ebcc.params(**bad)) == ebcc.EINVAL, bad

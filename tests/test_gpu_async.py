@@ -1,0 +1,221 @@
+"""Asynchronous batched decoding on the GPU (ebcc_decompress_batch_async):
+the streams sit in one device buffer at device offsets and lengths, the
+per-stream statuses are left in device memory, and the call returns without
+waiting for the device.
+
+Every decode must be bit-identical to the oracle's decode of the same
+stream; a stream that is corrupt, does not match its shape or was coded with
+other parameters than the call's gets its own status and leaves its output
+untouched while the others decode; repeated calls of one composition (the
+launch sequence then runs from a recorded graph) stay exact; and the call
+returns while its stream is still busy."""
+import struct
+
+import numpy as np
+import pytest
+
+from paper_2510_22265_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SENTINEL = 0x7FC0DEAD   # a NaN bit pattern no decoder writes
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_22265_amd import ebcc
+    ebcc.lib()
+    return ebcc
+
+
+def _pack(streams, gap=3):
+    """One device buffer holding the streams back to back with `gap` bytes
+    between them (unaligned offsets), and device offset/length arrays."""
+    import torch
+    offs, lens, parts, o = [], [], [], 0
+    for s in streams:
+        offs.append(o)
+        lens.append(len(s))
+        parts.append(bytes(s) + b"\xa5" * gap)
+        o += len(s) + gap
+    buf = torch.from_numpy(np.frombuffer(b"".join(parts) or b"\0", np.uint8).copy()).cuda()
+    return buf, torch.tensor(offs, dtype=torch.int64).cuda(), torch.tensor(lens, dtype=torch.int64).cuda()
+
+
+def _outs(shapes):
+    import torch
+    return [torch.full(tuple(sh), SENTINEL, dtype=torch.int32).cuda().view(torch.float32) for sh in shapes]
+
+
+def _bits(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _mixed():
+    """Ragged shapes, three field kinds, a constant field, a raw field (bound
+    below FP32 resolution), fields with and without a residual."""
+    fs = [
+        (synth.field("t", 91, 180, cfg=1), 0.01),
+        (np.full((37, 41), 273.15, np.float32), 0.01),
+        (synth.field("q", 181, 360, cfg=1, level=9), 0.003),
+        (synth.field("t", 20, 30), 1e-13),
+        (synth.field("u", 33, 17, cfg=1), 0.05),
+        (synth.field("v", 1, 1), 0.01),
+        (synth.field("u", 5, 64), 0.001),
+        (synth.field("v", 129, 255, cfg=3, level=2), 0.02),
+        (synth.field("q", 1, 7), 0.1),
+        (synth.field("t", 64, 64, cfg=5), 0.001),
+        (synth.field("u", 181, 360, cfg=2, level=4), 0.5),
+    ]
+    return [x for x, _ in fs], [e for _, e in fs]
+
+
+def _decode_and_check(gpu, ref, refs, shapes, **kw):
+    import torch
+    buf, offs, lens = _pack(refs)
+    outs, st = gpu.decompress_batch_async(buf, offs, lens, shapes, outs=_outs(shapes), **kw)
+    torch.cuda.synchronize()
+    assert st.cpu().tolist() == [0] * len(refs)
+    for i, (s, sh) in enumerate(zip(refs, shapes)):
+        assert np.array_equal(_bits(outs[i]), ref.decompress(s, *sh).view(np.uint32)), f"stream {i} {sh}"
+
+
+def test_async_decode_matches_oracle(gpu, ref):
+    xs, eps = _mixed()
+    refs = [ref.compress(x, e, base_ratio=30.0) for x, e in zip(xs, eps)]
+    modes = {s[5] for s in refs}
+    assert modes == {0, 1, 2}
+    assert any(s[5] == 2 and struct.unpack_from("<I", s, 40)[0] == 0 for s in refs), "no coded stream without residual"
+    print("async mixed", flush=True)
+    _decode_and_check(gpu, ref, refs, [x.shape for x in xs])
+
+
+@pytest.mark.parametrize("kw", [dict(cbl=(6, 6)), dict(cbl=(4, 6), levels=3), dict(tile=2), dict(bypass=1),
+                                dict(trunc=1), dict(trunc=1, bypass=1), dict(levels=0)])
+def test_async_decode_coding_parameters(gpu, ref, kw):
+    """Streams coded with other code-block sizes, levels, tile sizes, the
+    tier-1 bypass and byte-cut residuals decode with those parameters."""
+    cbl = kw.get("cbl", (5, 5))
+    okw = dict(cbl2w=cbl[0], cbl2h=cbl[1], tile=kw.get("tile", 1), levels=kw.get("levels", 5),
+               trunc=kw.get("trunc", 0), bypass=kw.get("bypass", 0))
+    gkw = dict(cblk_log2w=cbl[0], cblk_log2h=cbl[1], spiht_tile=okw["tile"], levels=okw["levels"],
+               trunc=okw["trunc"], bypass=okw["bypass"])
+    xs = [synth.field(v, *sh, cfg=11, level=k) for k, (v, sh) in
+          enumerate([("u", (181, 360)), ("t", (91, 180)), ("v", (129, 255)), ("q", (64, 96)), ("u", (33, 47))])]
+    eps = [0.001, 0.0005, 0.002, 0.001, 0.02]
+    refs = [ref.compress(x, e, base_ratio=5.0, **okw) for x, e in zip(xs, eps)]
+    if okw["trunc"]:
+        assert any(s[34] & 1 for s in refs), "no byte-cut residual"
+    if okw["bypass"]:
+        assert all(s[35] & 1 for s in refs if s[5] == 2)
+    print(f"async params {kw}", flush=True)
+    _decode_and_check(gpu, ref, refs, [x.shape for x in xs], **gkw)
+
+
+def test_async_decode_reports_bad_streams(gpu, ref):
+    """Each bad stream gets its own status (the synchronous decoder's code
+    where both check the same thing); one that fails the header checks
+    leaves its output untouched; the good streams of the call decode
+    exactly."""
+    import torch
+    from paper_2510_22265_amd import ebcc
+    x = synth.field("u", 91, 180, cfg=1, level=3)
+    y = synth.field("t", 64, 96, cfg=1, level=4)
+    good = ref.compress(x, 0.001, base_ratio=8.0)
+    good2 = ref.compress(y, 0.01)
+    corrupt = bytearray(good)
+    corrupt[200] ^= 0x40                                   # payload byte: checksum mismatch
+    bad_magic = bytearray(good)
+    bad_magic[0] = ord("X")
+    longer = bytes(good) + b"\0"                            # length not the header's
+    cut = ref.compress(x, 0.0005, base_ratio=4.0, trunc=1)
+    assert cut[34] & 1
+    byp = ref.compress(x, 0.0005, base_ratio=4.0, bypass=1)
+    assert byp[35] & 1
+    big = ref.compress(x, 0.001, base_ratio=8.0, cbl2w=6, cbl2h=6)
+    lv = ref.compress(x, 0.001, base_ratio=8.0, levels=3)
+    cases = [  # (stream, shape, expected status)
+        (good, x.shape, ebcc.OK),
+        (bytes(corrupt), x.shape, ebcc.ECORRUPT),
+        (good, (91, 181), ebcc.EINVAL),
+        (good[:40], x.shape, ebcc.ECORRUPT),
+        (bytes(bad_magic), x.shape, ebcc.ECORRUPT),
+        (longer, x.shape, ebcc.ECORRUPT),
+        (cut, x.shape, ebcc.EINVAL),
+        (byp, x.shape, ebcc.EINVAL),
+        (big, x.shape, ebcc.EINVAL),
+        (lv, x.shape, ebcc.EINVAL),
+        (good2, y.shape, ebcc.OK),
+    ]
+    streams = [c[0] for c in cases]
+    shapes = [c[1] for c in cases]
+    buf, offs, lens = _pack(streams)
+    print("async bad streams", flush=True)
+    outs, st = gpu.decompress_batch_async(buf, offs, lens, shapes, outs=_outs(shapes))
+    torch.cuda.synchronize()
+    assert st.cpu().tolist() == [c[2] for c in cases]
+    for i, (s, sh, code) in enumerate(cases):
+        if code == ebcc.OK:
+            assert np.array_equal(_bits(outs[i]), ref.decompress(s, *sh).view(np.uint32)), i
+        elif i != 1:   # (stream 1 passes the header checks: decoded, then found corrupt)
+            assert (_bits(outs[i]) == SENTINEL).all(), f"stream {i} wrote its output"
+    # the synchronous decoder reports the same codes for what both check
+    sync = [i for i in range(6)] + [10]
+    _, st2 = gpu.decompress_batch([torch.from_numpy(np.frombuffer(streams[i], np.uint8).copy()).cuda()
+                                   for i in sync], [shapes[i] for i in sync], check=False)
+    assert st2 == [cases[i][2] for i in sync]
+
+
+def test_async_decode_repeated_calls(gpu, ref):
+    """One composition decoded four times with different streams (the launch
+    sequence is issued directly, then recorded, then replayed), with eager
+    work and a synchronous decode between the calls: every call exact."""
+    import torch
+    shapes = [(91, 180), (37, 41), (181, 360), (20, 30), (129, 255)]
+    kinds = ["t", "u", "q", "v", "u"]
+    for rnd in range(4):
+        xs = [synth.field(k, *sh, cfg=20 + rnd, level=rnd) for k, sh in zip(kinds, shapes)]
+        if rnd == 1:
+            xs[1] = np.full(shapes[1], 1.5, np.float32)
+        eps = [0.002, 0.01, 0.001 * (rnd + 1), 1e-13 if rnd == 2 else 0.01, 0.005]
+        refs = [ref.compress(x, e, base_ratio=10.0) for x, e in zip(xs, eps)]
+        print(f"async round {rnd}", flush=True)
+        _decode_and_check(gpu, ref, refs, shapes)
+        z = torch.randn(1 << 20, device="cuda").sum()
+        ys = gpu.decompress_batch([torch.from_numpy(np.frombuffer(refs[0], np.uint8).copy()).cuda()], [shapes[0]])
+        assert np.array_equal(_bits(ys[0]), ref.decompress(refs[0], *shapes[0]).view(np.uint32))
+        assert torch.isfinite(z)
+
+
+def test_async_decode_returns_before_the_device_is_done(gpu, ref):
+    """After a warm-up call (plans, workspace, staging areas exist), a call
+    queued behind long-running work returns while its stream is still busy;
+    once the stream has drained its results are exact."""
+    import torch
+    xs = [synth.field("u", 181, 360, cfg=3), synth.field("t", 91, 180, cfg=3)]
+    refs = [ref.compress(x, 0.001) for x in xs]
+    shapes = [x.shape for x in xs]
+    buf, offs, lens = _pack(refs)
+    a = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    print("async warm-up", flush=True)
+    with torch.cuda.stream(s):
+        gpu.decompress_batch_async(buf, offs, lens, shapes, stream=s)
+    s.synchronize()
+    with torch.cuda.stream(s):
+        outs = _outs(shapes)
+        b = a
+        for _ in range(200):
+            b = torch.mm(b, a) * 1e-2
+        outs, st = gpu.decompress_batch_async(buf, offs, lens, shapes, stream=s, outs=outs)
+        busy = not s.query()
+    s.synchronize()
+    assert busy, "the call waited for its stream"
+    assert st.cpu().tolist() == [0, 0]
+    for i in range(2):
+        assert np.array_equal(_bits(outs[i]), ref.decompress(refs[i], *shapes[i]).view(np.uint32))
+    del b
