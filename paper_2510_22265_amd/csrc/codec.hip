@@ -786,7 +786,7 @@ static int build_plan(Plan& p) {
       t.ncoef = (int)n;
       p.max_tile_coef = std::max(p.max_tile_coef, (int)n);
       p.max_tile_parents = std::max(p.max_tile_parents, (int)(L > 0 ? n - n1 : 0));
-      int64_t need = std::max<int64_t>(n, 2 * (L > 0 ? n - n1 : 0));
+      int64_t need = std::max<int64_t>(n, 4 * (L > 0 ? n - n1 : 0));
       tcls.push_back(need <= kSpihtSmall ? 0 : (need <= kSpihtBig ? 1 : (need <= kSpihtHuge ? 3 : 2)));
       t.field = 0;
       off += n;

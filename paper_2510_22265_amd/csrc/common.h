@@ -277,13 +277,16 @@ void spiht_decode(const FieldDev* F, const TileD* tiles, const int* tix, int nti
 void spiht_decode_cut(const FieldDev* F, int nf, const TileD* tiles, const int64_t* toff, uint64_t* lists,
                       hipStream_t st);
 // spihtwave.hip: one wavefront per tile with the tile in LDS, in three
-// capacity classes (coefficients of the tile's trees, and twice its parents,
-// must fit): small and big for the usual one-root tiles of 5 and 6 levels,
-// huge (one wavefront per compute unit) for the edge tiles that take the
-// extra row or column of odd-sized bands.
-constexpr int kSpihtSmall = 1280;
-constexpr int kSpihtBig = 4608;
-constexpr int kSpihtHuge = 12288;
+// capacity classes (the coefficients of the tile's trees, and four times
+// its parents, must fit: the decoder's set list holds up to twice the
+// parents in half the capacity): small and big for the usual one-root tiles
+// of 5 and 6 levels with the edge tiles that take the extra row or column
+// of odd-sized bands, huge for larger edge tiles; larger tiles decode with
+// lists in global memory.  The decoder's LDS is 9 bytes per unit of
+// capacity: 15, 4 and 2 wavefronts per compute unit (160 KB).
+constexpr int kSpihtSmall = 1192;
+constexpr int kSpihtBig = 4352;
+constexpr int kSpihtHuge = 8704;
 // Each SPIHT launch covers the tiles tix[0 .. ntix) of the call's tile array
 // (tiles are launched in capacity classes).
 void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint8_t* slots,

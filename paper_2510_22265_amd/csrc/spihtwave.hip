@@ -551,7 +551,7 @@ struct SpihtDecLds {
     uint32_t qv[CAP];        // decoded magnitude | sign << 31
   } u;
   uint16_t lip[CAP], lsp[CAP];
-  uint16_t lis[CAP];         // local index | typeB << 15
+  uint16_t lis[CAP / 2];     // local index | typeB << 15 (at most twice the parents)
   int ok;
 };
 
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
   __syncthreads();
   if (lane == 0) {
     tile_geom(S.u.s.g, S.u.s.B, nb, L, td);
-    S.ok = S.u.s.g.ncoef <= CAP && 2 * S.u.s.g.nparents <= CAP;
+    S.ok = S.u.s.g.ncoef <= CAP && 4 * S.u.s.g.nparents <= CAP;
   }
   __syncthreads();
   if (!S.ok) {
