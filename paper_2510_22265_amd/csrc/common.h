@@ -281,12 +281,13 @@ void spiht_decode_cut(const FieldDev* F, int nf, const TileD* tiles, const int64
 // its parents, must fit: the decoder's set list holds up to twice the
 // parents in half the capacity): small and big for the usual one-root tiles
 // of 5 and 6 levels with the edge tiles that take the extra row or column
-// of odd-sized bands, huge for larger edge tiles; larger tiles decode with
-// lists in global memory.  The decoder's LDS is 9 bytes per unit of
-// capacity: 15, 4 and 2 wavefronts per compute unit (160 KB).
+// of odd-sized bands, huge for larger edge tiles; larger tiles are coded
+// with lists in global memory.  LDS per unit of capacity: 9 bytes in the
+// decoder (15, 4 and 2 wavefronts per compute unit of 160 KB), 9.5 bytes
+// plus the band table in the encoder (11, 3 and 2).
 constexpr int kSpihtSmall = 1192;
 constexpr int kSpihtBig = 4352;
-constexpr int kSpihtHuge = 8704;
+constexpr int kSpihtHuge = 8192;
 // Each SPIHT launch covers the tiles tix[0 .. ntix) of the call's tile array
 // (tiles are launched in capacity classes).
 void spiht_encode_lds(int cap, const FieldDev* F, const TileD* tiles, const int* tix, int ntix, uint8_t* slots,

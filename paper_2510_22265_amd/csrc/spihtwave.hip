@@ -136,10 +136,10 @@ struct SpihtLds {
   Band B[kMaxBands];
   TileGeom g;
   uint32_t qv[CAP];          // magnitude | sign << 31 (decoder: decoded magnitude)
-  uint8_t mdl[CAP / 2];      // bit length of the max over descendants
-  uint8_t mll[CAP / 2];      // bit length of the max over grand-descendants
+  uint8_t mdl[CAP / 4];      // bit length of the max over descendants (per parent)
+  uint8_t mll[CAP / 4];      // bit length of the max over grand-descendants
   uint16_t lip[CAP], lsp[CAP];
-  uint16_t lis[CAP];         // local index | typeB << 15
+  uint16_t lis[CAP / 2];     // local index | typeB << 15 (at most twice the parents)
   uint32_t bw[72];           // encoder output window (2048 bits + slack)
   int ntop, ok;
 };
@@ -151,7 +151,7 @@ __device__ bool spiht_setup(SpihtLds<CAP>& S, const Band* bands_g, int nb, int L
   __syncthreads();
   if (lane == 0) {
     tile_geom(S.g, S.B, nb, L, td);
-    S.ok = S.g.ncoef <= CAP && 2 * S.g.nparents <= CAP;
+    S.ok = S.g.ncoef <= CAP && 4 * S.g.nparents <= CAP;
   }
   __syncthreads();
   return S.ok;
