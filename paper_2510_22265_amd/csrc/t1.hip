@@ -179,7 +179,8 @@ __device__ __forceinline__ int mq_flush_copy(const MQEnc& e, uint32_t* tail) {
 // workgroups per compute unit); the decoder also keeps the decoded signs.
 template <typename M, int ROWS, int LANES, bool ENC>
 struct T1Shared {
-  M sig[ROWS][LANES], vis[ROWS][LANES], ref[ROWS][LANES], aux[ROWS][LANES];
+  M sig[ROWS][LANES], vis[ROWS][LANES], ref[ROWS][LANES];
+  M aux[ENC ? ROWS : 1][LANES];   // encoder: the significance-propagation masks
   M neg[ENC ? 1 : ROWS][LANES];
   uint8_t ctx[kNCtx][LANES];
   uint32_t mqt[47];
@@ -717,7 +718,6 @@ template <typename M, int ROWS, int LANES, bool BYP>
 __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S, int lane, int b,
                                              const FieldDev* __restrict__ F, const Blk* __restrict__ blk, int nblk,
                                              const uint32_t* __restrict__ table, const int64_t* __restrict__ off) {
-  // S.aux = coded in the current plane
   if (b >= nblk) return;
   Blk k = blk[b];
   const FieldDev& f = F[k.field];
@@ -753,7 +753,7 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
   }
   const uint8_t* zt = ztab_of(S, k.orient);
   for (int y = 0; y < k.h; y++) {
-    S.sig[y][lane] = 0; S.vis[y][lane] = 0; S.ref[y][lane] = 0; S.neg[y][lane] = 0; S.aux[y][lane] = 0;
+    S.sig[y][lane] = 0; S.vis[y][lane] = 0; S.ref[y][lane] = 0; S.neg[y][lane] = 0;
   }
   for (int c = 0; c < kNCtx; c++) S.ctx[c][lane] = 0;
   S.ctx[0][lane] = 4; S.ctx[CX_RL][lane] = 3; S.ctx[CX_UNI][lane] = 46;
@@ -787,10 +787,14 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
   auto setbit = [&](int y, int x, int p) {
     (void)__hip_atomic_fetch_or(&mb[y * nx + x], 1u << p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
-  int done = 0, plast = P - 1;
+  // The samples whose bit of the last decoded plane is known: after its
+  // significance-propagation pass, those that pass made significant (the
+  // significant samples it visited); after its refinement or cleanup pass,
+  // every significant sample (refinement codes the bit of each sample
+  // significant before the plane).
+  int done = 0, plast = P - 1, lastty = 2;
   for (int p = P - 1; p >= 0 && done < kb; p--) {
     plast = p;
-    for (int y = 0; y < h; y++) S.aux[y][lane] = 0;
     for (int ty = (p == P - 1) ? 2 : 0; ty < 3 && done < kb; ty++) {
       // pass numbers 11 and later of planes p <= P - 5 (SPP, MRP) are raw
       const bool raw = rawcw && ty < 2 && p <= P - 5;
@@ -798,7 +802,7 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
         const int rn = h - y0 < 4 ? h - y0 : 4;
         const M sA = rowm(S.sig, y0 - 1), sC = rowm(S.sig, y0 + 4);
         const M nA = rowm(S.neg, y0 - 1), nC = rowm(S.neg, y0 + 4);
-        M sB[4], vB[4], fB[4], nB[4], aB[4];
+        M sB[4], vB[4], fB[4], nB[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
           const bool in = r < rn;
@@ -806,7 +810,6 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
           vB[r] = in ? S.vis[y0 + r][lane] : (M)0;
           fB[r] = (in && ty == 1) ? S.ref[y0 + r][lane] : (M)0;
           nB[r] = in ? S.neg[y0 + r][lane] : (M)0;
-          aB[r] = 0;
         }
         // r is a compile-time constant in every caller (unrolled loops)
         auto dec_sign = [&](int r, int x) {
@@ -845,7 +848,6 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
               if (bit) {
                 dec_sign(r, x);
                 sB[r] = mid | ((M)1 << x);
-                aB[r] |= (M)1 << x;
                 setbit(y0 + r, x, p);
                 grew = true;
               }
@@ -871,7 +873,6 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
               const int cx = btu(fB[r], x) ? CX_MR + 2 : (btu(nbm[r], x) ? CX_MR + 1 : CX_MR);
               if (raw ? rawget() : mq_dec(&S.ctx[cx][lane])) setbit(y0 + r, x, p);
               fB[r] |= (M)1 << x;
-              aB[r] |= (M)1 << x;
             }
           }
         } else {                                         // cleanup
@@ -900,7 +901,6 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
                   if (r == rr) {
                     dec_sign(r, x);
                     sB[r] |= (M)1 << x;
-                    aB[r] |= (M)1 << x;
                     setbit(y0 + r, x, p);
                   }
                 rstart = rr + 1;
@@ -914,7 +914,6 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
               if (mq_dec(&S.ctx[zt[pat]][lane])) {
                 dec_sign(r, x);
                 sB[r] |= (M)1 << x;
-                aB[r] |= (M)1 << x;
                 setbit(y0 + r, x, p);
               }
             }
@@ -925,7 +924,6 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
           if (r < rn) {
             S.sig[y0 + r][lane] = sB[r];
             S.vis[y0 + r][lane] = vB[r];
-            S.aux[y0 + r][lane] |= aB[r];
             if (ty == 1) S.ref[y0 + r][lane] = fB[r];
             else S.neg[y0 + r][lane] = nB[r];
           }
@@ -933,11 +931,13 @@ __device__ __forceinline__ void t1_dec_block(T1Shared<M, ROWS, LANES, false>& S,
       if (ty == 2)
         for (int y = 0; y < h; y++) S.vis[y][lane] = 0;
       done++;
+      lastty = ty;
     }
   }
   const int e = e0 - k.gain;
   for (int y = 0; y < h; y++) {
-    M sg = S.sig[y][lane], cur = S.aux[y][lane], ng = S.neg[y][lane];
+    const M sg = S.sig[y][lane], ng = S.neg[y][lane];
+    const M cur = lastty == 0 ? (sg & S.vis[y][lane]) : sg;
     for (int x = 0; x < w; x++) {
       float v = 0.0f;
       if (bt(sg, x)) {
