@@ -219,3 +219,28 @@ def test_async_decode_returns_before_the_device_is_done(gpu, ref):
     for i in range(2):
         assert np.array_equal(_bits(outs[i]), ref.decompress(refs[i], *shapes[i]).view(np.uint32))
     del b
+
+
+def test_async_decode_more_streams_than_a_chunk(gpu, ref):
+    """4100 streams (more than one chunk of 4096) in one call, a bad one in
+    each chunk: the second chunk's statuses and outputs are right too."""
+    import torch
+    from paper_2510_22265_amd import ebcc
+    g = np.random.default_rng(11)
+    xs = [g.standard_normal((3 + i % 5, 2 + i % 7)).astype(np.float32) for i in range(4100)]
+    streams = [ref.compress(x, 0.01) for x in xs]
+    shapes = [x.shape for x in xs]
+    shapes[100] = (shapes[100][0] + 1, shapes[100][1])   # first chunk: wrong shape
+    bad = bytearray(streams[4098])
+    bad[1] = ord("X")
+    streams[4098] = bytes(bad)                           # second chunk: bad magic
+    buf, offs, lens = _pack(streams, gap=1)
+    print("async 4100 streams", flush=True)
+    outs, st = gpu.decompress_batch_async(buf, offs, lens, shapes, outs=_outs(shapes))
+    torch.cuda.synchronize()
+    st = st.cpu().tolist()
+    assert st[100] == ebcc.EINVAL and st[4098] == ebcc.ECORRUPT
+    assert all(v == 0 for i, v in enumerate(st) if i not in (100, 4098))
+    for i in list(range(0, 4100, 97)) + [4095, 4096, 4099]:
+        assert np.array_equal(_bits(outs[i]), ref.decompress(streams[i], *shapes[i]).view(np.uint32)), i
+    assert (_bits(outs[100]) == SENTINEL).all() and (_bits(outs[4098]) == SENTINEL).all()
