@@ -159,3 +159,20 @@ def test_async_decode_refuses_bad_arguments():
     assert call(2, 1 << 25, 8, p) == ebcc.EINVAL
     for bad in (dict(cblk_log2w=7), dict(spiht_tile=0), dict(levels=17), dict(trunc=2), dict(bypass=3)):
         assert call(1, 8, 8, ebcc.params(**bad)) == ebcc.EINVAL, bad
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No CPU fallback: without libebcc.so every entry point of the binding
+    raises, and host tensors are refused rather than compressed another way."""
+    import numpy as np
+    import pytest
+    import torch
+    from paper_2510_22265_amd import ebcc
+    monkeypatch.setattr(ebcc, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libebcc.so"))
+    monkeypatch.setattr(ebcc, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        ebcc.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        ebcc.params()
+    with pytest.raises((TypeError, RuntimeError)):
+        ebcc.compress(torch.from_numpy(np.zeros((8, 8), np.float32)), 0.01)
