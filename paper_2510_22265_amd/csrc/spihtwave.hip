@@ -538,6 +538,36 @@ __device__ __forceinline__ void kids_uniform(const GeomRegs& G, int L, int loc, 
   K.n = (r1 > 2 * i && c1 > 2 * j) ? (r1 - 2 * i) * (c1 - 2 * j) : 0;
 }
 
+// Significance and sign bits of up to four children of a significant set,
+// read from the next eight bits of the code (first bit in bit 7 of the
+// index): for n children, entry [n - 1][byte] holds the children found
+// significant (bits 0-3), their signs (bits 4-7) and the bits the n
+// children take (bits 8-11).  Each child takes its significance bit, and a
+// sign bit after a 1.
+struct KidsTab {
+  uint32_t v[4][256];
+};
+constexpr KidsTab make_kids_tab() {
+  KidsTab t{};
+  for (int n = 1; n <= 4; n++)
+    for (int b = 0; b < 256; b++) {
+      int pos = 0;
+      uint32_t sg = 0, sn = 0;
+      for (int l = 0; l < n; l++) {
+        const uint32_t bit = ((uint32_t)b >> (7 - pos)) & 1u;
+        pos++;
+        if (bit) {
+          sn |= (((uint32_t)b >> (7 - pos)) & 1u) << l;
+          pos++;
+          sg |= 1u << l;
+        }
+      }
+      t.v[n - 1][b] = sg | (sn << 4) | ((uint32_t)pos << 8);
+    }
+  return t;
+}
+__constant__ KidsTab c_kids_tab = make_kids_tab();
+
 // The decoder's LDS: the band table and the tile's geometry are needed only
 // until the lists are set up and the geometry is in registers, so the
 // decoded magnitudes reuse their space (more tiles resident per CU).
@@ -720,8 +750,41 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
       const int loc = e & 0x7FFF, typeB = e >> 15;
       Kids K;
       kids_uniform(G, L, loc, K);
-      if (!typeB) {
-        // each child: its significance bit, and the sign when it is 1
+      if (!typeB && K.n <= 4) {
+        // each child: its significance bit, and the sign when it is 1; up
+        // to four children read at once (at most 8 bits) through a table of
+        // the next byte, then placed by the lanes (one per child)
+        const int n = K.n;
+        const uint32_t te = n ? c_kids_tab.v[n - 1][(uint32_t)(rd.win >> 56)] : 0u;
+        const uint32_t sigm = te & 15u, sgnm = (te >> 4) & 15u;
+        if (n) rd.skip((int)(te >> 8));
+        if (lane < n) {
+          int c;
+          if (K.ll) {
+            c = lane == 0 ? K.k0 : (lane == 1 ? K.k1 : K.k2);
+          } else {
+            const int nc = K.c1 - K.c0;
+            const int r = nc == 1 ? lane : (nc == 2 ? lane >> 1 : (lane * 11) >> 5);   // lane / nc, lane < 9
+            c = K.base + (K.r0 + r) * K.pitch + K.c0 + (lane - r * nc);
+          }
+          const uint32_t below = (1u << lane) - 1u;
+          if ((sigm >> lane) & 1u) {
+            S.u.qv[c] = thr | (((sgnm >> lane) & 1u) << 31);
+            S.lsp[nlsp + __builtin_popcount(sigm & below)] = (uint16_t)c;
+          } else {
+            S.lip[nlip + lane - __builtin_popcount(sigm & below)] = (uint16_t)c;
+          }
+        }
+        const int ns1 = __builtin_popcount(sigm);
+        nlsp += ns1;
+        nlip += n - ns1;
+        if (n > 0 && K.clevel >= 2) {
+          if (lane == 0) S.lis[nlis] = (uint16_t)(loc | 0x8000);
+          nlis++;
+        }
+      } else if (!typeB) {
+        // more than four children (the extra row or column of odd-sized
+        // bands): one at a time
         const int nc = K.c1 - K.c0;
         for (int l = 0; l < K.n; l++) {
           int c;
