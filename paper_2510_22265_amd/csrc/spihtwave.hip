@@ -693,9 +693,10 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
         k += z; surv += z;
         continue;
       }
-      // entry k: significant (its token is 1 and a sign bit)
-      rd.get();
-      int sg = rd.get();
+      // entry k: significant (its token is 1, as no zero run starts here,
+      // and a sign bit)
+      const int sg = (int)((rd.win >> 62) & 1u);
+      rd.skip(2);
       if (k - pbase >= pcnt || k < pbase) {
         pbase = k;
         pcnt = nlip - k < 64 ? nlip - k : 64;
@@ -740,13 +741,9 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
         wv = lane < wcnt ? (uint32_t)S.lis[head + lane] : 0u;
       }
       const int e = (int)__builtin_amdgcn_readlane((int)wv, head - wbase);
-      const int s = rd.get();
-      if (!s) {
-        if (lane == 0) S.lis[kept] = (uint16_t)e;
-        kept++;
-        head++;
-        continue;
-      }
+      // no zero run starts here (the window always holds at least 32 valid
+      // bits), so the set's significance bit is 1
+      rd.skip(1);
       const int loc = e & 0x7FFF, typeB = e >> 15;
       Kids K;
       kids_uniform(G, L, loc, K);
