@@ -538,6 +538,40 @@ __device__ __forceinline__ void kids_uniform(const GeomRegs& G, int L, int loc, 
   K.n = (r1 > 2 * i && c1 > 2 * j) ? (r1 - 2 * i) * (c1 - 2 * j) : 0;
 }
 
+// Children of a node loc of the detail band b > 0 (both the same in every
+// lane), as kids_uniform finds them, with the arithmetic on the vector unit
+// (the decoder's wave-uniform chain is bound by the compute unit's scalar
+// issue): K.n, K.clevel and K.ll (false) are set, the other fields of K are
+// not; child l < K.n is returned in lane l.
+__device__ __forceinline__ int kids_lanes(const GeomRegs& G, int loc, int b, int lane, Kids& K) {
+  K.ll = false;
+  const int lev = rl(G.level, b);
+  K.clevel = lev - 1;
+  K.n = 0;
+  if (lev == 1) return 0;
+  // zero in every lane, but not known to be uniform: what depends on it is
+  // computed by vector instructions
+  const int vz = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
+  const uint32_t rel = (uint32_t)(loc + vz - rl(G.off, b));
+  const uint64_t mg = (uint64_t)rlu(G.mlo, b) | ((uint64_t)rlu(G.mhi, b) << 32);
+  const int wrb = rl(G.wr, b);
+  const int li = (int)(((uint64_t)rel * mg) >> 32), lj = (int)rel - li * wrb;
+  const int i = rl(G.r0, b) + li, j = rl(G.c0, b) + lj;
+  const int cb = b + 3;
+  const int hb = rl(G.h, b), wb = rl(G.w, b), hc = rl(G.h, cb), wc = rl(G.w, cb);
+  int r1 = (i == hb - 1) ? hc : 2 * i + 2;
+  int c1 = (j == wb - 1) ? wc : 2 * j + 2;
+  r1 = r1 < hc ? r1 : hc;
+  c1 = c1 < wc ? c1 : wc;
+  const int nr = r1 > 2 * i ? r1 - 2 * i : 0, ncv = c1 > 2 * j ? c1 - 2 * j : 0;
+  K.n = __builtin_amdgcn_readfirstlane(nr * ncv);
+  const int nc = __builtin_amdgcn_readfirstlane(ncv);
+  const int pitch = rl(G.wr, cb);
+  const int base = rl(G.off, cb) - rl(G.r0, cb) * pitch - rl(G.c0, cb);
+  const int r = nc == 1 ? lane : (nc == 2 ? lane >> 1 : (lane * 11) >> 5);   // lane / nc, lane < 9
+  return base + (2 * i + r) * pitch + 2 * j + (lane - r * nc);
+}
+
 // Significance and sign bits of up to four children of a significant set,
 // read from the next eight bits of the code (first bit in bit 7 of the
 // index): for n children, entry [n - 1][byte] holds the children found
@@ -745,8 +779,11 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
       // bits), so the set's significance bit is 1
       rd.skip(1);
       const int loc = e & 0x7FFF, typeB = e >> 15;
+      const int bnd = __builtin_popcountll(__ballot(G.off <= loc)) - 1;
       Kids K;
-      kids_uniform(G, L, loc, K);
+      int cl = 0;   // a detail node's child K.n > lane in this lane
+      if (bnd == 0) kids_uniform(G, L, loc, K);
+      else cl = kids_lanes(G, loc, bnd, lane, K);
       if (!typeB && K.n <= 4) {
         // each child: its significance bit, and the sign when it is 1; up
         // to four children read at once (at most 8 bits) through a table of
@@ -756,14 +793,7 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
         const uint32_t sigm = te & 15u, sgnm = (te >> 4) & 15u;
         if (n) rd.skip((int)(te >> 8));
         if (lane < n) {
-          int c;
-          if (K.ll) {
-            c = lane == 0 ? K.k0 : (lane == 1 ? K.k1 : K.k2);
-          } else {
-            const int nc = K.c1 - K.c0;
-            const int r = nc == 1 ? lane : (nc == 2 ? lane >> 1 : (lane * 11) >> 5);   // lane / nc, lane < 9
-            c = K.base + (K.r0 + r) * K.pitch + K.c0 + (lane - r * nc);
-          }
+          const int c = K.ll ? (lane == 0 ? K.k0 : (lane == 1 ? K.k1 : K.k2)) : cl;
           const uint32_t below = (1u << lane) - 1u;
           if ((sigm >> lane) & 1u) {
             S.u.qv[c] = thr | (((sgnm >> lane) & 1u) << 31);
@@ -781,16 +811,9 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
         }
       } else if (!typeB) {
         // more than four children (the extra row or column of odd-sized
-        // bands): one at a time
-        const int nc = K.c1 - K.c0;
+        // bands; never an LL root's): one at a time
         for (int l = 0; l < K.n; l++) {
-          int c;
-          if (K.ll) {
-            c = l == 0 ? K.k0 : (l == 1 ? K.k1 : K.k2);
-          } else {
-            const int r = nc == 1 ? l : (nc == 2 ? l >> 1 : (l * 11) >> 5);   // l / nc, l < 9
-            c = K.base + (K.r0 + r) * K.pitch + K.c0 + (l - r * nc);
-          }
+          const int c = rl(cl, l);
           if (rd.get()) {
             const int sg = rd.get();
             if (lane == 0) { S.u.qv[c] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)c; }
@@ -807,14 +830,7 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
       } else {
         // the children join the LIS as type-A entries, one per lane
         if (lane < K.n) {
-          int v;
-          if (K.ll) {
-            v = lane == 0 ? K.k0 : (lane == 1 ? K.k1 : K.k2);
-          } else {
-            const int nc = K.c1 - K.c0;
-            const int r = nc == 1 ? lane : (nc == 2 ? lane >> 1 : (lane * 11) >> 5);   // lane / nc, lane < 9
-            v = K.base + (K.r0 + r) * K.pitch + K.c0 + (lane - r * nc);
-          }
+          const int v = K.ll ? (lane == 0 ? K.k0 : (lane == 1 ? K.k1 : K.k2)) : cl;
           S.lis[nlis + lane] = (uint16_t)v;
         }
         nlis += K.n;
