@@ -602,6 +602,37 @@ constexpr KidsTab make_kids_tab() {
 }
 __constant__ KidsTab c_kids_tab = make_kids_tab();
 
+// LIP tokens in the next eight bits of the code (first bit in bit 7 of the
+// index): each entry takes a 0 (it stays insignificant) or a 1 and its sign
+// bit; entry [byte] holds the number of tokens that fit whole (bits 0-3,
+// 1 to 8 when the byte holds a 1), which of them are 1 (bits 4-11) and
+// their signs (bits 12-19).
+struct LipTab {
+  uint32_t v[256];
+};
+constexpr LipTab make_lip_tab() {
+  LipTab t{};
+  for (int b = 0; b < 256; b++) {
+    int pos = 0, m = 0;
+    uint32_t sg = 0, sn = 0;
+    while (pos < 8) {
+      if ((((uint32_t)b >> (7 - pos)) & 1u) == 0) {
+        pos++;
+        m++;
+        continue;
+      }
+      if (pos + 1 >= 8) break;
+      sn |= (((uint32_t)b >> (6 - pos)) & 1u) << m;
+      sg |= 1u << m;
+      pos += 2;
+      m++;
+    }
+    t.v[b] = (uint32_t)m | (sg << 4) | (sn << 12);
+  }
+  return t;
+}
+__constant__ LipTab c_lip_tab = make_lip_tab();
+
 // The decoder's LDS: the band table and the tile's geometry are needed only
 // until the lists are set up and the geometry is in registers, so the
 // decoded magnitudes reuse their space (more tiles resident per CU).
@@ -705,15 +736,18 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
   for (int pl = ntop; pl >= n_bot; pl--) {
     const uint32_t thr = 1u << pl;
     const int lsp_prev = nlsp;
-    // LIP: runs of zeros leave entries in place; a one makes the entry
-    // significant.  Entries are read through a 64-entry register window; the
-    // moves of survivors only write below the current position.
+    // LIP: each entry's token is a 0 (it stays) or a 1 and its sign bit (it
+    // becomes significant).  Runs of eight zeros or more (or up to the list's
+    // end) are skipped with one count of leading zeros; otherwise the tokens
+    // that fit in the next byte come from a table, the lanes (one per entry)
+    // placing them.  Entries are read through a 64-entry register window;
+    // survivors only move below the current position.
     int k = 0, surv = 0, pbase = 0, pcnt = 0;
     uint32_t pv = 0;
     while (k < nlip) {
       int z = rd.zeros();
       if (z > nlip - k) z = nlip - k;
-      if (z > 0) {
+      if (z > 0 && (z >= 8 || z == nlip - k)) {
         // survivors k .. k+z-1 move down to surv .. (ascending chunks are safe)
         if (surv != k)
           for (int c = 0; c < z; c += 64) {
@@ -727,19 +761,35 @@ __global__ __launch_bounds__(64) void k_spiht_decode_lds(const FieldDev* __restr
         k += z; surv += z;
         continue;
       }
-      // entry k: significant (its token is 1, as no zero run starts here,
-      // and a sign bit)
-      const int sg = (int)((rd.win >> 62) & 1u);
-      rd.skip(2);
-      if (k - pbase >= pcnt || k < pbase) {
+      // entries k .. k + m - 1: the tokens that fit in the next byte
+      const uint32_t te = c_lip_tab.v[(uint32_t)(rd.win >> 56)];
+      int m = (int)(te & 15u);
+      uint32_t sigm = (te >> 4) & 255u, sgnm = (te >> 12) & 255u;
+      if (m > nlip - k) {
+        m = nlip - k;
+        sigm &= (1u << m) - 1u;
+        sgnm &= (1u << m) - 1u;
+      }
+      const int nsig = __builtin_popcount(sigm);
+      rd.skip(m + nsig);
+      if (k < pbase || k + m > pbase + pcnt) {
         pbase = k;
         pcnt = nlip - k < 64 ? nlip - k : 64;
         pv = lane < pcnt ? (uint32_t)S.lip[k + lane] : 0u;
       }
-      int e = rl((int)pv, k - pbase);
-      if (lane == 0) { S.u.qv[e] = thr | ((uint32_t)sg << 31); S.lsp[nlsp] = (uint16_t)e; }
-      nlsp++;
-      k++;
+      const int e = __shfl((int)pv, k - pbase + lane);   // lane < m: entry k + lane
+      if (lane < m) {
+        const int r1 = __builtin_popcount(sigm & ((1u << lane) - 1u));
+        if ((sigm >> lane) & 1u) {
+          S.u.qv[e] = thr | (((sgnm >> lane) & 1u) << 31);
+          S.lsp[nlsp + r1] = (uint16_t)e;
+        } else {
+          S.lip[surv + lane - r1] = (uint16_t)e;
+        }
+      }
+      nlsp += nsig;
+      surv += m - nsig;
+      k += m;
     }
     nlip = surv;
     // LIS: entries are read 64 at a time into a vector register (lane i:
