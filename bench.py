@@ -61,11 +61,11 @@ T1_ALU_CEILING = 256 * 64 * 2.4e9 / 25
 MEASURED = {
     "t1_encode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
                   "sha256": "6bccb9e1a87ceff9e73ad4faa539c8c8181f3f2979f9b4cca93cbfaed0f07907",
-                  "ny": 721, "nx": 1440, "eps": 0.01, "kernel": "k_t1_encode_pipe<3>", "avg_ms": 1.4474,
+                  "ny": 721, "nx": 1440, "eps": 0.01, "kernel": "k_t1_encode_pipe<3>", "avg_ms": 1.4465,
                   "bytes": (2.0 * (734.1 + 680.8) / 2 + 1.0 * (868.2 + 1078.6) / 2) * 1024},
     "t1_decode": {"source": "paper_2510_22265_amd/csrc/t1wave.hip",
                   "sha256": "6bccb9e1a87ceff9e73ad4faa539c8c8181f3f2979f9b4cca93cbfaed0f07907",
-                  "ny": 721, "nx": 1440, "eps": 0.01, "kernel": "k_t1_decode_wave<u32>", "avg_ms": 1.5640,
+                  "ny": 721, "nx": 1440, "eps": 0.01, "kernel": "k_t1_decode_wave<u32>", "avg_ms": 1.5401,
                   "bytes": (2.0 * (593.8 + 558.4) / 2 + 1.0 * (4099.5 + 4099.5) / 2) * 1024},
 }
 
